@@ -1,0 +1,194 @@
+/*
+ * ephw.h - C ABI of libephw, Wannier-to-Bloch interpolation of electron-phonon
+ * matrix elements on AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates Eq. (7) of arXiv:2603.10295,
+ *
+ *   g_{mn nu}(k,q) = sum_{m'n' kappa alpha} sum_{Re,Rp} g_{m'n' kappa alpha}(Re,Rp)
+ *                    U_{mm'}(k+q) U*_{nn'}(k) u_{kappa alpha, nu}(q) e^{i(q.Rp + k.Re)},
+ *
+ * through the nested loop of Eqs. (9)-(10): per batch of q points the Rp phase
+ * sum (Eq. (9)) is one complex GEMM, the mode vectors u(q) are applied once per
+ * q, the Re phase sum (Eq. (10)) is one complex GEMM over all k, and the band
+ * rotations are applied per (k, q) pair.  U(k) and u(q) come from Hermitian
+ * eigensolves of the interpolated H(k) and D(q), done on the GPU in FP64.
+ *
+ * Conventions
+ *   - k, q are fractional coordinates (reciprocal-lattice units); lattice
+ *     vectors R are integer triples.  Every phase is w_R * exp(+2 pi i p.R)
+ *     with the argument p.R reduced to (-1/2, 1/2] in FP64 before the sine and
+ *     cosine; w_R are optional Wigner-Seitz degeneracy weights (NULL = 1).
+ *   - H(k) = sum_R w_R e^{2 pi i k.R} H(R), H(R)_{ab} = <w_a(0)|H|w_b(R)>.  Its
+ *     eigenvector columns V(k) fix the gauge of Eq. (5) as U(k) = V(k)^dagger,
+ *     so the band factors of Eq. (7) are V(k+q)^dagger g V(k).
+ *   - D(q) = sum_R w_R e^{2 pi i q.R} C(R) / sqrt(M_kappa M_kappa');
+ *     u_{kappa alpha, nu}(q) = e_{kappa alpha, nu}(q) / sqrt(M_kappa) (mode
+ *     index kappa alpha = 3 kappa + alpha); omega = sqrt(|lambda|).
+ *   - Eigenvalues are ascending; each eigenvector column is scaled so that its
+ *     largest-magnitude component is real and positive.
+ *
+ * Memory
+ *   - ephw_system_load copies the Wannier-space tensors from HOST memory into
+ *     library-owned device memory, where they stay until ephw_system_free (the
+ *     e-ph matrix g(Re,Rp) is uploaded once and reused for every k and q).
+ *   - Every other pointer argument is DEVICE memory owned by the caller
+ *     (k/q lists, index tables, outputs).  The library keeps no pointer to
+ *     caller memory after a call returns.
+ *   - Complex numbers are interleaved (re, im) pairs: "c128" is two doubles,
+ *     "c64" two floats.  All arrays are dense row-major in the index order
+ *     given at each argument.
+ *
+ * Streams and errors
+ *   - Compute calls take `stream` (a hipStream_t; NULL = the null stream),
+ *     enqueue their work on it and return; the caller synchronises.
+ *   - Every function returns an ephw_status.  Argument errors are detected on
+ *     the host before anything is enqueued (EPHW_EINVAL, EPHW_EUNSUPPORTED);
+ *     ephw_last_error() gives a description (thread-local).  Errors raised by
+ *     kernels (an eigensolve that did not converge, an out-of-range index in a
+ *     k+q table) are recorded in a device status word of the context and read
+ *     by ephw_ctx_check().
+ *   - Calls that share a system or k-set use that object's workspace and must
+ *     be issued on one stream (or be externally ordered).
+ */
+#ifndef EPHW_H
+#define EPHW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ephw_status;
+#define EPHW_OK            0
+#define EPHW_EINVAL        1  /* invalid argument (shape, NULL pointer, range) */
+#define EPHW_ENOMEM        2  /* device allocation failed */
+#define EPHW_EDEVICE       3  /* HIP runtime error */
+#define EPHW_ENOCONV       4  /* a Jacobi eigensolve hit its sweep limit */
+#define EPHW_EUNSUPPORTED  5  /* valid request this build does not handle */
+#define EPHW_EINDEX        6  /* a k+q index table entry was out of range */
+
+/* arithmetic of the phase sums and rotations; eigensolves are always FP64 */
+#define EPHW_FP64        0  /* complex128 GEMMs on FP64 MFMA, g stored c128 */
+#define EPHW_FP32        1  /* complex64 GEMMs on FP32 MFMA, g stored c64 */
+#define EPHW_FP32_SPLIT  2  /* FP32 with phases split hi+lo (compensated phase products) */
+
+/* storage type of g(Re,Rp) */
+#define EPHW_C128 0
+#define EPHW_C64  1
+
+/* output selection for ephw_interpolate (bit flags) */
+#define EPHW_OUT_G          1u  /* store g_{mn nu}(k,q) */
+#define EPHW_OUT_BAND_SUM   2u  /* store T_nu(k,q) = sum_mn |g_{mn nu}|^2 (gauge free) */
+#define EPHW_OUT_LOSS       4u  /* accumulate L += sum w_{mn nu}(k,q) |g_{mn nu}|^2 */
+#define EPHW_OUT_WANNIER    8u  /* skip the band and mode rotations: store the
+                                   Re/Rp phase sums g_{m'n' kappa alpha}(k,q) */
+
+typedef struct ephw_ctx ephw_ctx;
+typedef struct ephw_system ephw_system;
+typedef struct ephw_kset ephw_kset;
+
+/* Create a context on HIP device `device`.  Allocates the device status word. */
+ephw_status ephw_ctx_create(int device, ephw_ctx** out);
+ephw_status ephw_ctx_destroy(ephw_ctx* ctx);
+
+/* Synchronise `stream`, read and clear the context's device status word.
+   Returns EPHW_OK, EPHW_ENOCONV or EPHW_EINDEX. */
+ephw_status ephw_ctx_check(ephw_ctx* ctx, void* stream);
+
+/* Wannier-space description of one material (Eqs. (3)-(5) inputs).  All
+   pointers are HOST memory.  nm = 3*na.
+     r_e [ne][3], r_p [np][3], r_h [nh][3], r_c [nc][3]   int32 lattice vectors
+     w_e [ne], w_p [np], w_h [nh], w_c [nc]               f64 weights or NULL (= 1)
+     h_r  [nh][nw][nw]            c128, H(R)
+     c_r  [nc][nm][nm]            f64, force constants C(R) (real)
+     mass [na]                    f64, atomic masses (> 0)
+     g    [np][ne][nm][nw][nw]    e-ph matrix g_{m'n' kappa alpha}(Re,Rp) of
+                                  Eq. (3), element type given by g_dtype      */
+typedef struct ephw_system_desc {
+  int32_t nw, na;
+  int64_t ne, np, nh, nc;
+  const int32_t *r_e, *r_p, *r_h, *r_c;
+  const double *w_e, *w_p, *w_h, *w_c;
+  const void* h_r;
+  const double* c_r;
+  const double* mass;
+  const void* g;
+  int32_t g_dtype;              /* EPHW_C128 or EPHW_C64 */
+} ephw_system_desc;
+
+/* Copy a system to the device (blocking).  Limits: 1 <= nw <= 256,
+   1 <= na <= 86 (nm <= 258), every n >= 1. */
+ephw_status ephw_system_load(ephw_ctx* ctx, const ephw_system_desc* desc, ephw_system** out);
+ephw_status ephw_system_free(ephw_system* sys);
+/* bytes of library-owned device memory held by the system (tensors + workspace) */
+ephw_status ephw_system_bytes(const ephw_system* sys, int64_t* bytes);
+
+/* Electron bands on a k list (H(k) interpolation + FP64 eigensolve).
+     k    [nk][3] f64 (device)
+     eps  [nk][nw] f64 (device) or NULL
+     vecs [nk][nw][nw] c128 (device) or NULL; column j is the eigenvector of eps[j] */
+ephw_status ephw_bands(ephw_system* sys, const double* k, int64_t nk, double* eps, void* vecs,
+                       void* stream);
+
+/* Phonons on a q list (D(q) interpolation + FP64 eigensolve).
+     q     [nq][3] f64 (device)
+     lam   [nq][nm] f64 eigenvalues of D(q), or NULL
+     omega [nq][nm] f64 sqrt(|lam|), or NULL
+     evecs [nq][nm][nm] c128 eigenvectors e (columns), or NULL  (u = e/sqrt(M)) */
+ephw_status ephw_phonons(ephw_system* sys, const double* q, int64_t nq, double* lam,
+                         double* omega, void* evecs, void* stream);
+
+/* Eq. (9) alone: g(Re,q) = sum_Rp w_Rp e^{2 pi i q.Rp} g(Re,Rp).
+     q   [nq][3] f64 (device)
+     out [nq][ne][nm][nw][nw] c128 (EPHW_FP64) or c64 (EPHW_FP32*) (device)
+   The precision must match the stored g (FP64 <-> c128, FP32 <-> c64). */
+ephw_status ephw_phase_sum_rp(ephw_system* sys, const double* q, int64_t nq, int32_t prec,
+                              void* out, void* stream);
+
+/* A prepared set of fine k points: their phases e^{2 pi i k.Re}, bands eps(k)
+   and eigenvectors V(k), kept on the device and reused by every
+   ephw_interpolate call on that set (the k loop of Eq. (10)).
+     k [nk][3] f64 (device), copied. */
+ephw_status ephw_kset_create(ephw_system* sys, const double* k, int64_t nk, int32_t prec,
+                             void* stream, ephw_kset** out);
+ephw_status ephw_kset_free(ephw_kset* ks);
+/* copy eps(k) [nk][nw] f64 and/or V(k) [nk][nw][nw] c128 (device) out of the set */
+ephw_status ephw_kset_bands(ephw_kset* ks, double* eps, void* vecs, void* stream);
+
+/* Eq. (7) on every pair of the k-set's points with the q list.
+     q        [nq][3] f64 (device)
+     kq_index [nq][nk] int32 (device) or NULL.  If given, V(k_i + q_j) is taken as
+              V(k_{kq_index[j][i]}) of the k-set (k+q on the k grid); otherwise
+              H(k+q) is interpolated and diagonalised for every pair.
+     q_offset index of q[0] in the caller's full q list (enters the loss weights)
+     prec     EPHW_FP64 / EPHW_FP32 / EPHW_FP32_SPLIT; must match the k-set's
+     flags    EPHW_OUT_* bits
+     g_out    [nq][nk][nm][nw][nw] c128 (FP64) or c64 (FP32*), if EPHW_OUT_G;
+              with EPHW_OUT_WANNIER the same shape holds the unrotated sums
+              (index order [q][k][kappa alpha][m'][n'])
+     band_sum [nq][nk][nm] f64, if EPHW_OUT_BAND_SUM
+     loss     one f64, if EPHW_OUT_LOSS: L += sum w |g|^2 with
+              w = 0.5 + (x >> 40) 2^-24, x the i-th SplitMix64 output for seed
+              loss_seed and i = ((((q_offset+iq)*nk + ik)*nm + nu)*nw + m)*nw + n
+     eps_kq   [nq][nk][nw] f64 or NULL: bands at k+q
+     omega    [nq][nm] f64 or NULL
+   Returns EPHW_EINVAL for inconsistent arguments before enqueuing anything. */
+ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index,
+                             int64_t q_offset, int32_t prec, uint32_t flags, void* g_out,
+                             double* band_sum, double* loss, uint64_t loss_seed, double* eps_kq,
+                             double* omega, void* stream);
+
+/* Tuning knobs (0 = automatic).  q_batch: q points per Rp/Re GEMM sweep. */
+ephw_status ephw_set_q_batch(ephw_system* sys, int32_t q_batch);
+
+const char* ephw_status_string(ephw_status s);
+const char* ephw_last_error(void);
+/* library version as MAJOR*10000 + MINOR*100 + PATCH */
+int32_t ephw_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EPHW_H */

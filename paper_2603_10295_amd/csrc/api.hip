@@ -1,0 +1,694 @@
+// Host side of the libephw C ABI: validation, ownership, workspaces and the
+// sequencing of the interpolation (Eqs. (7), (9), (10)) on a HIP stream.
+#include <math.h>
+#include <string.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "gemm.h"
+#include "kernels.h"
+
+namespace ephw {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
+// grow-only device buffer; reallocation waits for the device to go idle
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+ephw_status dev_alloc(void** p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    *p = nullptr;
+    return EPHW_ENOMEM;
+  }
+  return EPHW_OK;
+}
+
+ephw_status grow(DevBuf& b, size_t bytes, int64_t* owner_bytes) {
+  if (b.bytes >= bytes && b.p) return EPHW_OK;
+  if (b.p) {
+    EPHW_HIP(hipDeviceSynchronize());
+    EPHW_HIP(hipFree(b.p));
+    *owner_bytes -= (int64_t)b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  EPHW_TRY(dev_alloc(&b.p, bytes));
+  b.bytes = bytes;
+  *owner_bytes += (int64_t)bytes;
+  return EPHW_OK;
+}
+
+template <typename X>
+ephw_status upload(X** dst, const X* src, size_t count, int64_t* owner_bytes) {
+  void* p = nullptr;
+  EPHW_TRY(dev_alloc(&p, count * sizeof(X)));
+  *owner_bytes += (int64_t)(count * sizeof(X));
+  EPHW_HIP(hipMemcpy(p, src, count * sizeof(X), hipMemcpyHostToDevice));
+  *dst = static_cast<X*>(p);
+  return EPHW_OK;
+}
+
+int prec_kind(int32_t prec) { return prec == EPHW_FP64 ? 0 : 1; }
+size_t csize(int kind) { return kind == 0 ? 16 : 8; }
+
+}  // namespace
+}  // namespace ephw
+
+using namespace ephw;
+
+struct ephw_ctx {
+  int device = 0;
+  uint32_t* status = nullptr;
+};
+
+enum WsSlot {
+  WS_PQ, WS_PQ_LO, WS_PQH, WS_PQC, WS_D, WS_LAM, WS_E, WS_U, WS_G, WS_GNU, WS_W, WS_BQ, WS_HKQ,
+  WS_EKQ, WS_VKQ64, WS_VKQ, WS_JWORK, WS_LOSS, WS_PH, WS_HK, WS_EPS, WS_V64, WS_COUNT
+};
+
+struct ephw_system {
+  ephw_ctx* ctx = nullptr;
+  int nw = 0, na = 0, nm = 0;
+  int64_t ne = 0, np = 0, nh = 0, nc = 0;
+  int g_kind = 0;  // 0 = c128, 1 = c64
+  int32_t *r_e = nullptr, *r_p = nullptr, *r_h = nullptr, *r_c = nullptr;
+  double *w_e = nullptr, *w_p = nullptr, *w_h = nullptr, *w_c = nullptr;
+  double* h_r = nullptr;      // c128 [nh][nw][nw]
+  double* c_scaled = nullptr; // c128 [nc][nm][nm] = C / sqrt(M M')
+  double* ism = nullptr;      // [nm] 1/sqrt(M_kappa) per mode index
+  void* g = nullptr;
+  int32_t q_batch = 0;
+  int64_t bytes = 0;
+  DevBuf ws[WS_COUNT];
+};
+
+struct ephw_kset {
+  ephw_system* sys = nullptr;
+  int64_t nk = 0;
+  int32_t prec = 0;
+  int64_t bytes = 0;
+  double* k = nullptr;      // [nk][3]
+  void* pk = nullptr;       // T [nk][ne]
+  void* pk_lo = nullptr;    // float [nk][ne] (split)
+  double* pkh = nullptr;    // c128 [nk][nh]
+  double* eps = nullptr;    // [nk][nw]
+  double* v64 = nullptr;    // c128 [nk][nw][nw]
+  void* vt = nullptr;       // T [nk][nw][nw]
+};
+
+namespace {
+
+void* wsp(ephw_system* s, WsSlot slot) { return s->ws[slot].p; }
+
+ephw_status ws_need(ephw_system* s, WsSlot slot, size_t bytes) {
+  return grow(s->ws[slot], bytes, &s->bytes);
+}
+
+hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+
+// FP64 interpolation + eigensolve: out_eps [n][dim], out_v c128 [n][dim][dim]
+// from A = phases [n][nr] (c128) and B = R-space matrices [nr][dim*dim] (c128).
+ephw_status interp_eigh(ephw_system* s, const double* phase, int64_t n, int64_t nr, const double* mats,
+                        int dim, double* out_eps, double* out_v, hipStream_t st) {
+  const int64_t d2 = (int64_t)dim * dim;
+  EPHW_TRY(ws_need(s, WS_HK, (size_t)n * d2 * 16));
+  GemmParams p;
+  p.M = n;
+  p.N = d2;
+  p.K = nr;
+  p.A = phase;
+  p.lda = nr;
+  p.B = mats;
+  p.ldb = d2;
+  p.C = wsp(s, WS_HK);
+  p.ldc = d2;
+  EPHW_TRY(cgemm(0, p, st));
+  const int64_t jw = jacobi_work_doubles(dim, n);
+  if (jw > 0) EPHW_TRY(ws_need(s, WS_JWORK, (size_t)jw * 8));
+  return jacobi_eigh(static_cast<const double*>(wsp(s, WS_HK)), n, dim, out_eps, out_v,
+                     jw > 0 ? static_cast<double*>(wsp(s, WS_JWORK)) : nullptr, s->ctx->status, st);
+}
+
+int32_t pick_q_batch(const ephw_system* s, int64_t nk, int64_t nq, int kind) {
+  if (s->q_batch > 0) return (int32_t)(s->q_batch < nq ? s->q_batch : nq);
+  const int64_t E = (int64_t)s->nm * s->nw * s->nw;
+  const double per_q = (double)csize(kind) * E * ((double)nk + 2.0 * (double)s->ne);
+  int64_t qb = (int64_t)((4.0 * 1024 * 1024 * 1024) / per_q);
+  if (qb > 256) qb = 256;
+  if (qb >= 128) qb = 128;
+  else if (qb >= 64) qb = 64;
+  if (qb < 1) qb = 1;
+  if (qb > nq) qb = nq;
+  if (qb > 65535) qb = 65535;
+  return (int32_t)qb;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ephw_status_string(ephw_status s) {
+  switch (s) {
+    case EPHW_OK: return "ok";
+    case EPHW_EINVAL: return "invalid argument";
+    case EPHW_ENOMEM: return "out of device memory";
+    case EPHW_EDEVICE: return "HIP runtime error";
+    case EPHW_ENOCONV: return "eigensolver did not converge";
+    case EPHW_EUNSUPPORTED: return "unsupported request";
+    case EPHW_EINDEX: return "k+q index out of range";
+    default: return "unknown status";
+  }
+}
+
+const char* ephw_last_error(void) { return g_last_error.c_str(); }
+
+int32_t ephw_version(void) { return 100; }
+
+ephw_status ephw_ctx_create(int device, ephw_ctx** out) {
+  if (!out) {
+    set_error("ephw_ctx_create: out is NULL");
+    return EPHW_EINVAL;
+  }
+  *out = nullptr;
+  int count = 0;
+  EPHW_HIP(hipGetDeviceCount(&count));
+  if (device < 0 || device >= count) {
+    set_error("ephw_ctx_create: no such device");
+    return EPHW_EINVAL;
+  }
+  EPHW_HIP(hipSetDevice(device));
+  ephw_ctx* c = new ephw_ctx();
+  c->device = device;
+  void* p = nullptr;
+  ephw_status st = dev_alloc(&p, sizeof(uint32_t));
+  if (st != EPHW_OK) {
+    delete c;
+    return st;
+  }
+  c->status = static_cast<uint32_t*>(p);
+  EPHW_HIP(hipMemset(c->status, 0, sizeof(uint32_t)));
+  *out = c;
+  return EPHW_OK;
+}
+
+ephw_status ephw_ctx_destroy(ephw_ctx* ctx) {
+  if (!ctx) return EPHW_OK;
+  if (ctx->status) (void)hipFree(ctx->status);
+  delete ctx;
+  return EPHW_OK;
+}
+
+ephw_status ephw_ctx_check(ephw_ctx* ctx, void* stream) {
+  if (!ctx) {
+    set_error("ephw_ctx_check: ctx is NULL");
+    return EPHW_EINVAL;
+  }
+  EPHW_HIP(hipStreamSynchronize(as_stream(stream)));
+  uint32_t v = 0;
+  EPHW_HIP(hipMemcpy(&v, ctx->status, sizeof(v), hipMemcpyDeviceToHost));
+  EPHW_HIP(hipMemset(ctx->status, 0, sizeof(uint32_t)));
+  if (v & kStatusIndex) {
+    set_error("a k+q index table entry was outside [0, nk)");
+    return EPHW_EINDEX;
+  }
+  if (v & kStatusNoConv) {
+    set_error("a Jacobi eigensolve reached its sweep limit");
+    return EPHW_ENOCONV;
+  }
+  return EPHW_OK;
+}
+
+ephw_status ephw_system_free(ephw_system* s) {
+  if (!s) return EPHW_OK;
+  (void)hipDeviceSynchronize();
+  void* ptrs[] = {s->r_e, s->r_p, s->r_h, s->r_c, s->w_e, s->w_p, s->w_h, s->w_c,
+                  s->h_r, s->c_scaled, s->ism, s->g};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  for (auto& b : s->ws)
+    if (b.p) (void)hipFree(b.p);
+  delete s;
+  return EPHW_OK;
+}
+
+ephw_status ephw_system_load(ephw_ctx* ctx, const ephw_system_desc* d, ephw_system** out) {
+  if (!ctx || !d || !out) {
+    set_error("ephw_system_load: NULL argument");
+    return EPHW_EINVAL;
+  }
+  *out = nullptr;
+  if (d->nw < 1 || d->nw > 256 || d->na < 1 || d->na > 86 || d->ne < 1 || d->np < 1 || d->nh < 1 ||
+      d->nc < 1) {
+    set_error("ephw_system_load: sizes out of range (1<=nw<=256, 1<=na<=86, counts >= 1)");
+    return EPHW_EINVAL;
+  }
+  if (!d->r_e || !d->r_p || !d->r_h || !d->r_c || !d->h_r || !d->c_r || !d->mass || !d->g) {
+    set_error("ephw_system_load: a required array is NULL");
+    return EPHW_EINVAL;
+  }
+  if (d->g_dtype != EPHW_C128 && d->g_dtype != EPHW_C64) {
+    set_error("ephw_system_load: g_dtype must be EPHW_C128 or EPHW_C64");
+    return EPHW_EINVAL;
+  }
+  for (int a = 0; a < d->na; ++a)
+    if (!(d->mass[a] > 0.0)) {
+      set_error("ephw_system_load: masses must be positive");
+      return EPHW_EINVAL;
+    }
+  EPHW_HIP(hipSetDevice(ctx->device));
+  ephw_system* s = new ephw_system();
+  s->ctx = ctx;
+  s->nw = d->nw;
+  s->na = d->na;
+  s->nm = 3 * d->na;
+  s->ne = d->ne;
+  s->np = d->np;
+  s->nh = d->nh;
+  s->nc = d->nc;
+  s->g_kind = d->g_dtype == EPHW_C128 ? 0 : 1;
+  const int nm = s->nm;
+  ephw_status st = EPHW_OK;
+  auto fail = [&](ephw_status e) {
+    ephw_system_free(s);
+    return e;
+  };
+  if ((st = upload(&s->r_e, d->r_e, 3 * d->ne, &s->bytes)) != EPHW_OK) return fail(st);
+  if ((st = upload(&s->r_p, d->r_p, 3 * d->np, &s->bytes)) != EPHW_OK) return fail(st);
+  if ((st = upload(&s->r_h, d->r_h, 3 * d->nh, &s->bytes)) != EPHW_OK) return fail(st);
+  if ((st = upload(&s->r_c, d->r_c, 3 * d->nc, &s->bytes)) != EPHW_OK) return fail(st);
+  auto weights = [&](double** dst, const double* w, int64_t n) {
+    std::vector<double> ones;
+    if (!w) {
+      ones.assign((size_t)n, 1.0);
+      w = ones.data();
+    }
+    return upload(dst, w, (size_t)n, &s->bytes);
+  };
+  if ((st = weights(&s->w_e, d->w_e, d->ne)) != EPHW_OK) return fail(st);
+  if ((st = weights(&s->w_p, d->w_p, d->np)) != EPHW_OK) return fail(st);
+  if ((st = weights(&s->w_h, d->w_h, d->nh)) != EPHW_OK) return fail(st);
+  if ((st = weights(&s->w_c, d->w_c, d->nc)) != EPHW_OK) return fail(st);
+  if ((st = upload(&s->h_r, static_cast<const double*>(d->h_r), (size_t)2 * d->nh * d->nw * d->nw,
+                   &s->bytes)) != EPHW_OK)
+    return fail(st);
+  {
+    // C(R) / sqrt(M_kappa M_kappa') as complex128, the B operand of D(q)
+    std::vector<double> ism((size_t)nm), cs((size_t)2 * d->nc * nm * nm);
+    for (int a = 0; a < nm; ++a) ism[a] = 1.0 / sqrt(d->mass[a / 3]);
+    for (int64_t r = 0; r < d->nc; ++r)
+      for (int a = 0; a < nm; ++a)
+        for (int b = 0; b < nm; ++b) {
+          const size_t i = ((size_t)r * nm + a) * nm + b;
+          cs[2 * i] = d->c_r[i] * ism[a] * ism[b];
+          cs[2 * i + 1] = 0.0;
+        }
+    if ((st = upload(&s->c_scaled, cs.data(), cs.size(), &s->bytes)) != EPHW_OK) return fail(st);
+    if ((st = upload(&s->ism, ism.data(), ism.size(), &s->bytes)) != EPHW_OK) return fail(st);
+  }
+  {
+    const size_t gbytes = (size_t)d->np * d->ne * nm * d->nw * d->nw * csize(s->g_kind);
+    if ((st = dev_alloc(&s->g, gbytes)) != EPHW_OK) return fail(st);
+    s->bytes += (int64_t)gbytes;
+    if (hipMemcpy(s->g, d->g, gbytes, hipMemcpyHostToDevice) != hipSuccess) {
+      set_error("ephw_system_load: upload of g failed");
+      return fail(EPHW_EDEVICE);
+    }
+  }
+  *out = s;
+  return EPHW_OK;
+}
+
+ephw_status ephw_system_bytes(const ephw_system* s, int64_t* bytes) {
+  if (!s || !bytes) {
+    set_error("ephw_system_bytes: NULL argument");
+    return EPHW_EINVAL;
+  }
+  *bytes = s->bytes;
+  return EPHW_OK;
+}
+
+ephw_status ephw_set_q_batch(ephw_system* s, int32_t q_batch) {
+  if (!s || q_batch < 0 || q_batch > 65535) {
+    set_error("ephw_set_q_batch: need a system and 0 <= q_batch <= 65535");
+    return EPHW_EINVAL;
+  }
+  s->q_batch = q_batch;
+  return EPHW_OK;
+}
+
+ephw_status ephw_bands(ephw_system* s, const double* k, int64_t nk, double* eps, void* vecs,
+                       void* stream) {
+  if (!s || (!k && nk > 0) || nk < 0) {
+    set_error("ephw_bands: invalid argument");
+    return EPHW_EINVAL;
+  }
+  if (nk == 0) return EPHW_OK;
+  hipStream_t st = as_stream(stream);
+  const int64_t nw2 = (int64_t)s->nw * s->nw;
+  EPHW_TRY(ws_need(s, WS_PH, (size_t)nk * s->nh * 16));
+  EPHW_TRY(phase_matrix(0, k, nk, s->r_h, s->w_h, s->nh, wsp(s, WS_PH), nullptr, st));
+  double* e_out = eps;
+  double* v_out = static_cast<double*>(vecs);
+  if (!e_out) {
+    EPHW_TRY(ws_need(s, WS_EPS, (size_t)nk * s->nw * 8));
+    e_out = static_cast<double*>(wsp(s, WS_EPS));
+  }
+  if (!v_out) {
+    EPHW_TRY(ws_need(s, WS_V64, (size_t)nk * nw2 * 16));
+    v_out = static_cast<double*>(wsp(s, WS_V64));
+  }
+  return interp_eigh(s, static_cast<const double*>(wsp(s, WS_PH)), nk, s->nh, s->h_r, s->nw, e_out,
+                     v_out, st);
+}
+
+ephw_status ephw_phonons(ephw_system* s, const double* q, int64_t nq, double* lam, double* omega,
+                         void* evecs, void* stream) {
+  if (!s || (!q && nq > 0) || nq < 0) {
+    set_error("ephw_phonons: invalid argument");
+    return EPHW_EINVAL;
+  }
+  if (nq == 0) return EPHW_OK;
+  hipStream_t st = as_stream(stream);
+  const int nm = s->nm;
+  EPHW_TRY(ws_need(s, WS_PQC, (size_t)nq * s->nc * 16));
+  EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), nullptr, st));
+  double* l_out = lam;
+  if (!l_out) {
+    EPHW_TRY(ws_need(s, WS_LAM, (size_t)nq * nm * 8));
+    l_out = static_cast<double*>(wsp(s, WS_LAM));
+  }
+  double* e_out = static_cast<double*>(evecs);
+  if (!e_out) {
+    EPHW_TRY(ws_need(s, WS_E, (size_t)nq * nm * nm * 16));
+    e_out = static_cast<double*>(wsp(s, WS_E));
+  }
+  EPHW_TRY(interp_eigh(s, static_cast<const double*>(wsp(s, WS_PQC)), nq, s->nc, s->c_scaled, nm,
+                       l_out, e_out, st));
+  if (omega) EPHW_TRY(abs_sqrt(l_out, omega, nq * nm, st));
+  return EPHW_OK;
+}
+
+ephw_status ephw_phase_sum_rp(ephw_system* s, const double* q, int64_t nq, int32_t prec, void* out,
+                              void* stream) {
+  if (!s || ((!q || !out) && nq > 0) || nq < 0) {
+    set_error("ephw_phase_sum_rp: invalid argument");
+    return EPHW_EINVAL;
+  }
+  if (prec != EPHW_FP64 && prec != EPHW_FP32 && prec != EPHW_FP32_SPLIT) {
+    set_error("ephw_phase_sum_rp: unknown precision");
+    return EPHW_EINVAL;
+  }
+  const int kind = prec_kind(prec);
+  if (kind != s->g_kind) {
+    set_error("ephw_phase_sum_rp: precision does not match the stored g (FP64<->c128, FP32<->c64)");
+    return EPHW_EINVAL;
+  }
+  if (nq == 0) return EPHW_OK;
+  hipStream_t st = as_stream(stream);
+  const bool split = prec == EPHW_FP32_SPLIT;
+  EPHW_TRY(ws_need(s, WS_PQ, (size_t)nq * s->np * csize(kind)));
+  if (split) EPHW_TRY(ws_need(s, WS_PQ_LO, (size_t)nq * s->np * 8));
+  EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, s->np, wsp(s, WS_PQ),
+                        split ? wsp(s, WS_PQ_LO) : nullptr, st));
+  GemmParams p;
+  p.M = nq;
+  p.N = s->ne * s->nm * s->nw * s->nw;
+  p.K = s->np;
+  p.A = wsp(s, WS_PQ);
+  p.A_lo = split ? wsp(s, WS_PQ_LO) : nullptr;
+  p.lda = s->np;
+  p.B = s->g;
+  p.ldb = p.N;
+  p.C = out;
+  p.ldc = p.N;
+  return cgemm(kind, p, st);
+}
+
+ephw_status ephw_kset_free(ephw_kset* ks) {
+  if (!ks) return EPHW_OK;
+  (void)hipDeviceSynchronize();
+  void* ptrs[] = {ks->k, ks->pk, ks->pk_lo, ks->pkh, ks->eps, ks->v64, ks->vt};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete ks;
+  return EPHW_OK;
+}
+
+ephw_status ephw_kset_create(ephw_system* s, const double* k, int64_t nk, int32_t prec, void* stream,
+                             ephw_kset** out) {
+  if (!s || !k || !out || nk < 1) {
+    set_error("ephw_kset_create: invalid argument (need a system, a k list and nk >= 1)");
+    return EPHW_EINVAL;
+  }
+  if (prec != EPHW_FP64 && prec != EPHW_FP32 && prec != EPHW_FP32_SPLIT) {
+    set_error("ephw_kset_create: unknown precision");
+    return EPHW_EINVAL;
+  }
+  const int kind = prec_kind(prec);
+  if (kind != s->g_kind) {
+    set_error("ephw_kset_create: precision does not match the stored g (FP64<->c128, FP32<->c64)");
+    return EPHW_EINVAL;
+  }
+  *out = nullptr;
+  hipStream_t st = as_stream(stream);
+  ephw_kset* ks = new ephw_kset();
+  ks->sys = s;
+  ks->nk = nk;
+  ks->prec = prec;
+  const int64_t nw2 = (int64_t)s->nw * s->nw;
+  ephw_status e = EPHW_OK;
+  auto alloc = [&](void** p, size_t bytes) {
+    ephw_status r = dev_alloc(p, bytes);
+    if (r == EPHW_OK) ks->bytes += (int64_t)bytes;
+    return r;
+  };
+  auto fail = [&](ephw_status r) {
+    ephw_kset_free(ks);
+    return r;
+  };
+  if ((e = alloc((void**)&ks->k, (size_t)nk * 24)) != EPHW_OK) return fail(e);
+  if (hipMemcpyAsync(ks->k, k, (size_t)nk * 24, hipMemcpyDeviceToDevice, st) != hipSuccess) {
+    set_error("ephw_kset_create: copy of k failed");
+    return fail(EPHW_EDEVICE);
+  }
+  if ((e = alloc(&ks->pk, (size_t)nk * s->ne * csize(kind))) != EPHW_OK) return fail(e);
+  if (prec == EPHW_FP32_SPLIT && (e = alloc(&ks->pk_lo, (size_t)nk * s->ne * 8)) != EPHW_OK)
+    return fail(e);
+  if ((e = alloc((void**)&ks->pkh, (size_t)nk * s->nh * 16)) != EPHW_OK) return fail(e);
+  if ((e = alloc((void**)&ks->eps, (size_t)nk * s->nw * 8)) != EPHW_OK) return fail(e);
+  if ((e = alloc((void**)&ks->v64, (size_t)nk * nw2 * 16)) != EPHW_OK) return fail(e);
+  if ((e = alloc(&ks->vt, (size_t)nk * nw2 * csize(kind))) != EPHW_OK) return fail(e);
+  if ((e = phase_matrix(kind, ks->k, nk, s->r_e, s->w_e, s->ne, ks->pk, ks->pk_lo, st)) != EPHW_OK)
+    return fail(e);
+  if ((e = phase_matrix(0, ks->k, nk, s->r_h, s->w_h, s->nh, ks->pkh, nullptr, st)) != EPHW_OK)
+    return fail(e);
+  if ((e = interp_eigh(s, ks->pkh, nk, s->nh, s->h_r, s->nw, ks->eps, ks->v64, st)) != EPHW_OK)
+    return fail(e);
+  if ((e = cast_complex(kind, ks->v64, ks->vt, nk * nw2, st)) != EPHW_OK) return fail(e);
+  *out = ks;
+  return EPHW_OK;
+}
+
+ephw_status ephw_kset_bands(ephw_kset* ks, double* eps, void* vecs, void* stream) {
+  if (!ks) {
+    set_error("ephw_kset_bands: kset is NULL");
+    return EPHW_EINVAL;
+  }
+  hipStream_t st = as_stream(stream);
+  const ephw_system* s = ks->sys;
+  if (eps)
+    EPHW_HIP(hipMemcpyAsync(eps, ks->eps, (size_t)ks->nk * s->nw * 8, hipMemcpyDeviceToDevice, st));
+  if (vecs)
+    EPHW_HIP(hipMemcpyAsync(vecs, ks->v64, (size_t)ks->nk * s->nw * s->nw * 16,
+                            hipMemcpyDeviceToDevice, st));
+  return EPHW_OK;
+}
+
+ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index,
+                             int64_t q_offset, int32_t prec, uint32_t flags, void* g_out,
+                             double* band_sum, double* loss, uint64_t loss_seed, double* eps_kq,
+                             double* omega, void* stream) {
+  if (!ks || (!q && nq > 0) || nq < 0 || q_offset < 0) {
+    set_error("ephw_interpolate: invalid argument");
+    return EPHW_EINVAL;
+  }
+  if (prec != ks->prec) {
+    set_error("ephw_interpolate: precision differs from the k-set's");
+    return EPHW_EINVAL;
+  }
+  const uint32_t known = EPHW_OUT_G | EPHW_OUT_BAND_SUM | EPHW_OUT_LOSS | EPHW_OUT_WANNIER;
+  if (flags & ~known) {
+    set_error("ephw_interpolate: unknown output flag");
+    return EPHW_EINVAL;
+  }
+  if (((flags & EPHW_OUT_G) && !g_out) || ((flags & EPHW_OUT_BAND_SUM) && !band_sum) ||
+      ((flags & EPHW_OUT_LOSS) && !loss)) {
+    set_error("ephw_interpolate: a requested output buffer is NULL");
+    return EPHW_EINVAL;
+  }
+  if (!(flags & (EPHW_OUT_G | EPHW_OUT_BAND_SUM | EPHW_OUT_LOSS)) && !eps_kq && !omega) {
+    set_error("ephw_interpolate: nothing requested");
+    return EPHW_EINVAL;
+  }
+  ephw_system* s = ks->sys;
+  if ((flags & EPHW_OUT_WANNIER) && (flags & EPHW_OUT_LOSS)) {
+    set_error("ephw_interpolate: the loss is defined on the rotated g only");
+    return EPHW_EINVAL;
+  }
+  if (s->nw > 32) {
+    set_error("ephw_interpolate: this build rotates bands for nw <= 32");
+    return EPHW_EUNSUPPORTED;
+  }
+  if (nq == 0) return EPHW_OK;
+  hipStream_t st = as_stream(stream);
+  const int kind = prec_kind(prec);
+  const bool split = prec == EPHW_FP32_SPLIT;
+  const bool wannier = (flags & EPHW_OUT_WANNIER) != 0;
+  const int nw = s->nw, nm = s->nm;
+  const int64_t nw2 = (int64_t)nw * nw, E = nm * nw2, nk = ks->nk;
+  const size_t cs = csize(kind);
+  const int32_t qb = pick_q_batch(s, nk, nq, kind);
+
+  // --- per-call q side: Rp phases, D(q) eigensolve, mode vectors ----------
+  EPHW_TRY(ws_need(s, WS_PQ, (size_t)nq * s->np * cs));
+  if (split) EPHW_TRY(ws_need(s, WS_PQ_LO, (size_t)nq * s->np * 8));
+  EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, s->np, wsp(s, WS_PQ),
+                        split ? wsp(s, WS_PQ_LO) : nullptr, st));
+  EPHW_TRY(ws_need(s, WS_LAM, (size_t)nq * nm * 8));
+  EPHW_TRY(ws_need(s, WS_E, (size_t)nq * nm * nm * 16));
+  EPHW_TRY(ws_need(s, WS_PQC, (size_t)nq * s->nc * 16));
+  EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), nullptr, st));
+  EPHW_TRY(interp_eigh(s, static_cast<const double*>(wsp(s, WS_PQC)), nq, s->nc, s->c_scaled, nm,
+                       static_cast<double*>(wsp(s, WS_LAM)), static_cast<double*>(wsp(s, WS_E)), st));
+  if (omega) EPHW_TRY(abs_sqrt(static_cast<const double*>(wsp(s, WS_LAM)), omega, nq * nm, st));
+  EPHW_TRY(ws_need(s, WS_U, (size_t)nq * nm * nm * cs));
+  EPHW_TRY(mode_vectors(kind, static_cast<const double*>(wsp(s, WS_E)), nq, nm, s->ism,
+                        wsp(s, WS_U), st));
+  const bool need_g = (flags & (EPHW_OUT_G | EPHW_OUT_BAND_SUM | EPHW_OUT_LOSS)) != 0;
+  const bool need_kq_eig = !kq_index && (!wannier || eps_kq);
+
+  // --- per-batch workspaces -------------------------------------------------
+  if (need_g) {
+    EPHW_TRY(ws_need(s, WS_G, (size_t)qb * s->ne * E * cs));
+    EPHW_TRY(ws_need(s, WS_GNU, (size_t)qb * s->ne * E * cs));
+    EPHW_TRY(ws_need(s, WS_W, (size_t)nk * qb * E * cs));
+  }
+  if (need_kq_eig) {
+    EPHW_TRY(ws_need(s, WS_PQH, (size_t)nq * s->nh * 16));
+    EPHW_TRY(phase_matrix(0, q, nq, s->r_h, nullptr, s->nh, wsp(s, WS_PQH), nullptr, st));
+    EPHW_TRY(ws_need(s, WS_BQ, (size_t)qb * s->nh * nw2 * 16));
+    EPHW_TRY(ws_need(s, WS_HKQ, (size_t)qb * nk * nw2 * 16));
+    EPHW_TRY(ws_need(s, WS_EKQ, (size_t)qb * nk * nw * 8));
+    EPHW_TRY(ws_need(s, WS_VKQ64, (size_t)qb * nk * nw2 * 16));
+    EPHW_TRY(ws_need(s, WS_VKQ, (size_t)qb * nk * nw2 * cs));
+    const int64_t jw = jacobi_work_doubles(nw, (int64_t)qb * nk);
+    if (jw > 0) EPHW_TRY(ws_need(s, WS_JWORK, (size_t)jw * 8));
+  }
+  double* loss_part = nullptr;
+  if (flags & EPHW_OUT_LOSS) {
+    EPHW_TRY(ws_need(s, WS_LOSS, (size_t)qb * nk * 8));
+    loss_part = static_cast<double*>(wsp(s, WS_LOSS));
+  }
+
+  for (int64_t q0 = 0; q0 < nq; q0 += qb) {
+    const int32_t nb = (int32_t)((nq - q0) < qb ? (nq - q0) : qb);
+    // bands at k+q: H(k+q) = sum_R e^{2 pi i k.R} (e^{2 pi i q.R} H(R)), then FP64 Jacobi
+    if (need_kq_eig) {
+      EPHW_TRY(scale_rows_by_phase(static_cast<const double*>(wsp(s, WS_PQH)) + 2 * q0 * s->nh, nb,
+                                   s->h_r, s->nh, nw2, static_cast<double*>(wsp(s, WS_BQ)), st));
+      GemmParams h;
+      h.M = nk;
+      h.N = nw2;
+      h.K = s->nh;
+      h.batch = nb;
+      h.A = ks->pkh;
+      h.lda = s->nh;
+      h.strideA = 0;
+      h.B = wsp(s, WS_BQ);
+      h.ldb = nw2;
+      h.strideB = s->nh * nw2;
+      h.C = wsp(s, WS_HKQ);
+      h.ldc = nw2;
+      h.strideC = nk * nw2;
+      EPHW_TRY(cgemm(0, h, st));
+      double* ekq = eps_kq ? eps_kq + q0 * nk * nw : static_cast<double*>(wsp(s, WS_EKQ));
+      const int64_t jw = jacobi_work_doubles(nw, (int64_t)nb * nk);
+      EPHW_TRY(jacobi_eigh(static_cast<const double*>(wsp(s, WS_HKQ)), (int64_t)nb * nk, nw, ekq,
+                           static_cast<double*>(wsp(s, WS_VKQ64)),
+                           jw > 0 ? static_cast<double*>(wsp(s, WS_JWORK)) : nullptr,
+                           s->ctx->status, st));
+      EPHW_TRY(cast_complex(kind, static_cast<const double*>(wsp(s, WS_VKQ64)), wsp(s, WS_VKQ),
+                            (int64_t)nb * nk * nw2, st));
+    } else if (eps_kq && kq_index) {
+      // k+q on the k grid: its bands are the k-set's bands at the indexed point
+      EPHW_TRY(gather_rows(ks->eps, nk, kq_index + q0 * nk, (int64_t)nb * nk, nw,
+                           eps_kq + q0 * nk * nw, s->ctx->status, st));
+    }
+    if (!need_g) continue;
+    // Eq. (9): G[q][Re, ka, m', n'] = sum_Rp e^{i q.Rp} g(Re, Rp)
+    GemmParams rp;
+    rp.M = nb;
+    rp.N = s->ne * E;
+    rp.K = s->np;
+    rp.A = static_cast<const char*>(wsp(s, WS_PQ)) + (size_t)q0 * s->np * cs;
+    rp.A_lo = split ? static_cast<const char*>(wsp(s, WS_PQ_LO)) + (size_t)q0 * s->np * 8 : nullptr;
+    rp.lda = s->np;
+    rp.B = s->g;
+    rp.ldb = rp.N;
+    rp.C = wsp(s, WS_G);
+    rp.ldc = rp.N;
+    EPHW_TRY(cgemm(kind, rp, st));
+    // mode vectors u(q), hoisted to the g(Re,q) level; output [Re][q][nu][m'][n']
+    EPHW_TRY(mode_rotate(kind, wsp(s, WS_G),
+                         wannier ? nullptr
+                                 : static_cast<const char*>(wsp(s, WS_U)) + (size_t)q0 * nm * nm * cs,
+                         wsp(s, WS_GNU), s->ne, nb, nm, nw2, st));
+    // Eq. (10), Re part: W[k][q nu m' n'] = sum_Re e^{i k.Re} G_nu(Re, q)
+    GemmParams re;
+    re.M = nk;
+    re.N = (int64_t)nb * E;
+    re.K = s->ne;
+    re.A = ks->pk;
+    re.A_lo = split ? ks->pk_lo : nullptr;
+    re.lda = s->ne;
+    re.B = wsp(s, WS_GNU);
+    re.ldb = re.N;
+    re.C = wsp(s, WS_W);
+    re.ldc = re.N;
+    EPHW_TRY(cgemm(kind, re, st));
+    // band rotations V(k+q)^dagger W V(k) and the epilogues
+    BandRotateArgs br;
+    br.W = wsp(s, WS_W);
+    br.Vk = wannier ? nullptr : ks->vt;
+    br.Vkq = kq_index ? nullptr : wsp(s, WS_VKQ);
+    br.kq_index = kq_index ? kq_index + q0 * nk : nullptr;
+    br.nk = nk;
+    br.qb = nb;
+    br.nm = nm;
+    br.nw = nw;
+    br.flags = flags;
+    br.g_out = (flags & EPHW_OUT_G) ? static_cast<char*>(g_out) + (size_t)q0 * nk * E * cs : nullptr;
+    br.band_sum = (flags & EPHW_OUT_BAND_SUM) ? band_sum + q0 * nk * nm : nullptr;
+    br.loss_partial = loss_part;
+    br.loss_seed = loss_seed;
+    br.q_global0 = q_offset + q0;
+    br.status = s->ctx->status;
+    EPHW_TRY(band_rotate(kind, br, st));
+    if (flags & EPHW_OUT_LOSS) EPHW_TRY(sum_into(loss_part, (int64_t)nb * nk, loss, st));
+  }
+  return EPHW_OK;
+}
+
+}  // extern "C"

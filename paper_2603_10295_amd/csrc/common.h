@@ -1,0 +1,81 @@
+// Internal helpers shared by the libephw HIP sources (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/ephw.h"
+
+namespace ephw {
+
+// ---------------------------------------------------------------------------
+// complex values in registers
+// ---------------------------------------------------------------------------
+template <typename T>
+struct cplx {
+  T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// conj(a) * b
+template <typename T>
+__device__ __forceinline__ cplx<T> cmulc(cplx<T> a, cplx<T> b) {
+  return {a.re * b.re + a.im * b.im, a.re * b.im - a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ void cfma(cplx<T>& acc, cplx<T> a, cplx<T> b) {
+  acc.re = fma(a.re, b.re, fma(-a.im, b.im, acc.re));
+  acc.im = fma(a.re, b.im, fma(a.im, b.re, acc.im));
+}
+// acc += conj(a) * b
+template <typename T>
+__device__ __forceinline__ void cfmac(cplx<T>& acc, cplx<T> a, cplx<T> b) {
+  acc.re = fma(a.re, b.re, fma(a.im, b.im, acc.re));
+  acc.im = fma(a.re, b.im, fma(-a.im, b.re, acc.im));
+}
+
+template <typename T>
+__device__ __forceinline__ cplx<T> ld(const T* p, int64_t i) {
+  return {p[2 * i], p[2 * i + 1]};
+}
+template <typename T>
+__device__ __forceinline__ void st(T* p, int64_t i, cplx<T> v) {
+  p[2 * i] = v.re;
+  p[2 * i + 1] = v.im;
+}
+
+// ---------------------------------------------------------------------------
+// device status word bits (context-wide, read by ephw_ctx_check)
+// ---------------------------------------------------------------------------
+enum : uint32_t { kStatusNoConv = 1u, kStatusIndex = 2u };
+
+// ---------------------------------------------------------------------------
+// host-side error plumbing
+// ---------------------------------------------------------------------------
+void set_error(const std::string& msg);
+
+#define EPHW_HIP(expr)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess) {                                                         \
+      ::ephw::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));         \
+      return EPHW_EDEVICE;                                                          \
+    }                                                                               \
+  } while (0)
+
+#define EPHW_TRY(expr)                  \
+  do {                                  \
+    ephw_status s_ = (expr);            \
+    if (s_ != EPHW_OK) return s_;       \
+  } while (0)
+
+#define EPHW_CHECK_LAUNCH() EPHW_HIP(hipGetLastError())
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+}  // namespace ephw

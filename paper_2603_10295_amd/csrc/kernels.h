@@ -1,0 +1,63 @@
+// Launchers of the non-GEMM kernels of libephw.
+#pragma once
+
+#include "common.h"
+
+namespace ephw {
+
+// out[i][r] = w_r exp(2 pi i p_i.R_r) (w = NULL -> 1), argument reduced in FP64.
+// prec 0: out is c128.  prec 1: out is c64 (rounded), out_lo (optional) gets
+// the c64 rounding of the remainder, so hi + lo carries the FP64 phase.
+ephw_status phase_matrix(int prec, const double* pts, int64_t n, const int32_t* R, const double* w,
+                         int64_t nr, void* out, void* out_lo, hipStream_t s);
+
+// Hermitian eigensolve of a batch of n x n c128 matrices (cyclic Jacobi, FP64).
+// eps [batch][n] ascending; V [batch][n][n] c128, column j the eigenvector of eps j,
+// scaled so its largest-magnitude entry is real positive.  `work` must hold
+// jacobi_work_doubles(n, batch) doubles (0 for n <= 32).
+int64_t jacobi_work_doubles(int n, int64_t batch);
+ephw_status jacobi_eigh(const double* H, int64_t batch, int n, double* eps, double* V, double* work,
+                        uint32_t* status, hipStream_t s);
+
+// dst[i] = (T) src[i] for n complex values; T = float (prec 1) or a plain copy (prec 0)
+ephw_status cast_complex(int prec, const double* src, void* dst, int64_t n, hipStream_t s);
+
+// u[q][a][v] = e[q][a][v] * inv_sqrt_mass[a], stored as c128 (prec 0) or c64 (prec 1)
+ephw_status mode_vectors(int prec, const double* e, int64_t nq, int nm, const double* inv_sqrt_mass,
+                         void* u, hipStream_t s);
+// omega = sqrt(|lambda|)
+ephw_status abs_sqrt(const double* lam, double* omega, int64_t n, hipStream_t s);
+
+// B[q][r][ab] = phase[q][r] * H[r][ab]  (c128), the q factor of H(k+q)
+ephw_status scale_rows_by_phase(const double* phase, int64_t nq, const double* H, int64_t nr,
+                                int64_t nab, double* B, hipStream_t s);
+
+// Gnu[e][q][nu][mn] = sum_a u[q][a][nu] G[q][e][a][mn]  (u = NULL: Gnu = G transposed)
+ephw_status mode_rotate(int prec, const void* G, const void* u, void* Gnu, int64_t ne, int qb,
+                        int nm, int64_t nw2, hipStream_t s);
+
+struct BandRotateArgs {
+  const void* W;          // [nk][qb][nm][nw][nw]  (Re-GEMM output, row stride qb*nm*nw*nw)
+  const void* Vk;         // [nk][nw][nw] or NULL (identity: Wannier-gauge output)
+  const void* Vkq;        // [qb][nk][nw][nw] or NULL
+  const int32_t* kq_index;  // [qb][nk] (already offset to the batch) or NULL
+  int64_t nk;
+  int qb, nm, nw;
+  uint32_t flags;
+  void* g_out;            // [qb][nk][nm][nw][nw], offset to the batch
+  double* band_sum;       // [qb][nk][nm], offset to the batch
+  double* loss_partial;   // [qb*nk] per-pair partial sums, or NULL
+  uint64_t loss_seed;
+  int64_t q_global0;      // global index of the batch's first q
+  uint32_t* status;
+};
+ephw_status band_rotate(int prec, const BandRotateArgs& a, hipStream_t s);
+
+// dst[r][c] = src[idx[r]][c] (rows of width w); an index outside [0, nsrc) sets kStatusIndex
+ephw_status gather_rows(const double* src, int64_t nsrc, const int32_t* idx, int64_t cnt, int w,
+                        double* dst, uint32_t* status, hipStream_t s);
+
+// out[0] += sum of x[0..n) in a fixed order (deterministic)
+ephw_status sum_into(const double* x, int64_t n, double* out, hipStream_t s);
+
+}  // namespace ephw

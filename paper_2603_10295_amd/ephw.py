@@ -1,0 +1,263 @@
+"""ctypes binding of libephw (include/ephw.h).
+
+Argument marshalling only: every computation runs in the HIP library.  Device
+buffers are torch tensors on a ROCm device (their ``data_ptr()`` is passed
+through); the stream is torch's current stream unless one is given.  If the
+shared library is missing, importing the binding succeeds but every call
+raises ``EphwError`` - there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("EPHW_LIB", os.path.join(_HERE, "libephw.so"))
+
+# status codes, precisions, flags (mirror include/ephw.h)
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EUNSUPPORTED, EINDEX = range(7)
+FP64, FP32, FP32_SPLIT = 0, 1, 2
+C128, C64 = 0, 1
+OUT_G, OUT_BAND_SUM, OUT_LOSS, OUT_WANNIER = 1, 2, 4, 8
+
+EXPORTS = [
+    "ephw_ctx_create", "ephw_ctx_destroy", "ephw_ctx_check", "ephw_system_load",
+    "ephw_system_free", "ephw_system_bytes", "ephw_bands", "ephw_phonons", "ephw_phase_sum_rp",
+    "ephw_kset_create", "ephw_kset_free", "ephw_kset_bands", "ephw_interpolate",
+    "ephw_set_q_batch", "ephw_status_string", "ephw_last_error", "ephw_version",
+]
+
+
+class EphwError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        super().__init__(f"{where}: status {status} ({_status_name(status)}) {detail}".strip())
+
+
+def _status_name(s: int) -> str:
+    names = {OK: "ok", EINVAL: "EINVAL", ENOMEM: "ENOMEM", EDEVICE: "EDEVICE", ENOCONV: "ENOCONV",
+             EUNSUPPORTED: "EUNSUPPORTED", EINDEX: "EINDEX"}
+    return names.get(s, "unknown")
+
+
+class SystemDesc(ctypes.Structure):
+    _fields_ = [
+        ("nw", ctypes.c_int32), ("na", ctypes.c_int32),
+        ("ne", ctypes.c_int64), ("np", ctypes.c_int64), ("nh", ctypes.c_int64), ("nc", ctypes.c_int64),
+        ("r_e", ctypes.c_void_p), ("r_p", ctypes.c_void_p), ("r_h", ctypes.c_void_p), ("r_c", ctypes.c_void_p),
+        ("w_e", ctypes.c_void_p), ("w_p", ctypes.c_void_p), ("w_h", ctypes.c_void_p), ("w_c", ctypes.c_void_p),
+        ("h_r", ctypes.c_void_p), ("c_r", ctypes.c_void_p), ("mass", ctypes.c_void_p), ("g", ctypes.c_void_p),
+        ("g_dtype", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libephw.so once; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise EphwError(EDEVICE, "load", f"{LIB_PATH} not found; run `python -m paper_2603_10295_amd.build`")
+    # torch bundles its own HIP runtime under the same soname as ROCm's; loading
+    # torch first makes libephw bind to that one runtime instead of a second copy
+    import torch  # noqa: F401
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+    pp = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "ephw_ctx_create": [ctypes.c_int, pp],
+        "ephw_ctx_destroy": [vp],
+        "ephw_ctx_check": [vp, vp],
+        "ephw_system_load": [vp, ctypes.POINTER(SystemDesc), pp],
+        "ephw_system_free": [vp],
+        "ephw_system_bytes": [vp, ctypes.POINTER(ctypes.c_int64)],
+        "ephw_bands": [vp, vp, i64, vp, vp, vp],
+        "ephw_phonons": [vp, vp, i64, vp, vp, vp, vp],
+        "ephw_phase_sum_rp": [vp, vp, i64, i32, vp, vp],
+        "ephw_kset_create": [vp, vp, i64, i32, vp, pp],
+        "ephw_kset_free": [vp],
+        "ephw_kset_bands": [vp, vp, vp, vp],
+        "ephw_interpolate": [vp, vp, i64, vp, i64, i32, u32, vp, vp, vp, u64, vp, vp, vp],
+        "ephw_set_q_batch": [vp, i32],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int32
+    L.ephw_status_string.argtypes = [ctypes.c_int32]
+    L.ephw_status_string.restype = ctypes.c_char_p
+    L.ephw_last_error.argtypes = []
+    L.ephw_last_error.restype = ctypes.c_char_p
+    L.ephw_version.argtypes = []
+    L.ephw_version.restype = ctypes.c_int32
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != OK:
+        detail = lib().ephw_last_error().decode(errors="replace")
+        raise EphwError(status, where, detail)
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a torch tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("device buffers must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+# ----------------------------------------------------------------------------
+# thin object wrappers over the handles
+# ----------------------------------------------------------------------------
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().ephw_ctx_create(device, ctypes.byref(h)), "ephw_ctx_create")
+        self.handle = h
+        self.device = device
+
+    def check(self, stream=None):
+        _check(lib().ephw_ctx_check(self.handle, _stream(stream)), "ephw_ctx_check")
+
+    def close(self):
+        if self.handle:
+            lib().ephw_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _host(a, dtype):
+    if a is None:
+        return None
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class System:
+    """Library-owned device copy of a Wannier-space system (host numpy inputs)."""
+
+    def __init__(self, ctx: Context, *, nw, na, r_e, r_p, r_h, r_c, h_r, c_r, mass, g,
+                 w_e=None, w_p=None, w_h=None, w_c=None):
+        g_arr = np.asarray(g)
+        if g_arr.dtype == np.complex128:
+            gdt = C128
+        elif g_arr.dtype == np.complex64:
+            gdt = C64
+        else:
+            raise ValueError("g must be complex128 or complex64")
+        keep = dict(
+            r_e=_host(r_e, np.int32), r_p=_host(r_p, np.int32), r_h=_host(r_h, np.int32),
+            r_c=_host(r_c, np.int32), w_e=_host(w_e, np.float64), w_p=_host(w_p, np.float64),
+            w_h=_host(w_h, np.float64), w_c=_host(w_c, np.float64),
+            h_r=_host(h_r, np.complex128), c_r=_host(c_r, np.float64), mass=_host(mass, np.float64),
+            g=np.ascontiguousarray(g_arr))
+        d = SystemDesc()
+        d.nw, d.na = int(nw), int(na)
+        d.ne, d.np, d.nh, d.nc = (len(keep["r_e"]), len(keep["r_p"]), len(keep["r_h"]), len(keep["r_c"]))
+        for name in ("r_e", "r_p", "r_h", "r_c", "w_e", "w_p", "w_h", "w_c", "h_r", "c_r", "mass", "g"):
+            arr = keep[name]
+            setattr(d, name, None if arr is None else arr.ctypes.data)
+        d.g_dtype = gdt
+        h = ctypes.c_void_p()
+        _check(lib().ephw_system_load(ctx.handle, ctypes.byref(d), ctypes.byref(h)), "ephw_system_load")
+        self.handle = h
+        self.ctx = ctx
+        self.nw, self.na, self.nm = int(nw), int(na), 3 * int(na)
+        self.ne, self.np, self.nh, self.nc = d.ne, d.np, d.nh, d.nc
+        self.g_dtype = gdt
+
+    @classmethod
+    def from_synth(cls, ctx: Context, s) -> "System":
+        return cls(ctx, nw=s.nw, na=s.na, r_e=s.r_e, r_p=s.r_p, r_h=s.r_h, r_c=s.r_c, h_r=s.h_r,
+                   c_r=s.c_r, mass=s.mass, g=s.g, w_e=s.w_e, w_p=s.w_p, w_h=s.w_h, w_c=s.w_c)
+
+    def bytes(self) -> int:
+        v = ctypes.c_int64()
+        _check(lib().ephw_system_bytes(self.handle, ctypes.byref(v)), "ephw_system_bytes")
+        return v.value
+
+    def set_q_batch(self, qb: int):
+        _check(lib().ephw_set_q_batch(self.handle, int(qb)), "ephw_set_q_batch")
+
+    def close(self):
+        if self.handle:
+            lib().ephw_system_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def bands(sys: System, k, eps=None, vecs=None, stream=None):
+    _check(lib().ephw_bands(sys.handle, _ptr(k), k.shape[0], _ptr(eps), _ptr(vecs), _stream(stream)),
+           "ephw_bands")
+
+
+def phonons(sys: System, q, lam=None, omega=None, evecs=None, stream=None):
+    _check(lib().ephw_phonons(sys.handle, _ptr(q), q.shape[0], _ptr(lam), _ptr(omega), _ptr(evecs),
+                              _stream(stream)), "ephw_phonons")
+
+
+def phase_sum_rp(sys: System, q, prec: int, out, stream=None):
+    _check(lib().ephw_phase_sum_rp(sys.handle, _ptr(q), q.shape[0], prec, _ptr(out), _stream(stream)),
+           "ephw_phase_sum_rp")
+
+
+class KSet:
+    def __init__(self, sys: System, k, prec: int, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib().ephw_kset_create(sys.handle, _ptr(k), k.shape[0], prec, _stream(stream), ctypes.byref(h)),
+               "ephw_kset_create")
+        self.handle = h
+        self.sys = sys
+        self.nk = k.shape[0]
+        self.prec = prec
+
+    def bands(self, eps=None, vecs=None, stream=None):
+        _check(lib().ephw_kset_bands(self.handle, _ptr(eps), _ptr(vecs), _stream(stream)), "ephw_kset_bands")
+
+    def close(self):
+        if self.handle:
+            lib().ephw_kset_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def interpolate(ks: KSet, q, *, kq_index=None, q_offset: int = 0, flags: int = OUT_G, g_out=None,
+                band_sum=None, loss=None, loss_seed: int = 0, eps_kq=None, omega=None, stream=None):
+    _check(lib().ephw_interpolate(ks.handle, _ptr(q), q.shape[0], _ptr(kq_index), int(q_offset), ks.prec,
+                                  int(flags), _ptr(g_out), _ptr(band_sum), _ptr(loss), int(loss_seed),
+                                  _ptr(eps_kq), _ptr(omega), _stream(stream)), "ephw_interpolate")
+
+
+def version() -> int:
+    return int(lib().ephw_version())

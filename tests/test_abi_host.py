@@ -1,0 +1,96 @@
+"""CPU-side checks of the C ABI and the host accounting (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2603_10295_amd import ephw, model
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "ephw.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ephw_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declarations_are_exported():
+    names = declared_functions()
+    assert len(names) >= 15
+    assert sorted(ephw.EXPORTS) == names
+    L = ephw.lib()
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_status_strings_and_version():
+    L = ephw.lib()
+    for s in range(7):
+        assert L.ephw_status_string(s)
+    assert L.ephw_status_string(99) == b"unknown status"
+    assert ephw.version() == 100
+
+
+def test_null_arguments_rejected_before_any_device_call():
+    L = ephw.lib()
+    assert L.ephw_interpolate(None, None, 1, None, 0, 0, 1, None, None, None, 0, None, None, None) == ephw.EINVAL
+    assert b"invalid" in L.ephw_last_error()
+    assert L.ephw_system_load(None, None, None) == ephw.EINVAL
+    assert L.ephw_set_q_batch(None, 4) == ephw.EINVAL
+    assert L.ephw_ctx_check(None, None) == ephw.EINVAL
+    assert L.ephw_kset_create(None, None, 4, 0, None, None) == ephw.EINVAL
+    assert L.ephw_bands(None, None, 3, None, None, None) == ephw.EINVAL
+    assert L.ephw_phonons(None, None, 3, None, None, None, None) == ephw.EINVAL
+    assert L.ephw_phase_sum_rp(None, None, 3, 0, None, None) == ephw.EINVAL
+    assert L.ephw_ctx_create(0, None) == ephw.EINVAL
+    # freeing NULL handles is a no-op
+    assert L.ephw_system_free(None) == ephw.OK
+    assert L.ephw_kset_free(None) == ephw.OK
+    assert L.ephw_ctx_destroy(None) == ephw.OK
+
+
+def test_system_desc_layout_matches_header():
+    # int32 nw, na; int64 ne, np, nh, nc; 12 pointers; int32 g_dtype (+ padding)
+    assert ctypes.sizeof(ephw.SystemDesc) == 8 + 4 * 8 + 12 * 8 + 8
+
+
+# ----------------------------------------------------------------------------
+# accounting against the paper's printed numbers
+# ----------------------------------------------------------------------------
+
+def test_si_g_size_is_0p4_gb():
+    # bulk Si: Nb=8, Nm=6, Ne=617, Np=93 -> "0.4 GB" in double-complex
+    b = model.g_bytes(8, 6, 617, 93)
+    assert round(b / 1e9, 1) == 0.4
+
+
+def test_zsnr_table_sizes():
+    rows = [l.split() for l in open(os.path.join(ROOT, "tests", "golden", "zsnr_g_size.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 11
+    for w, nb, nm, ne, np_, printed in rows:
+        gib = model.g_bytes(int(nb), int(nm), int(ne), int(np_)) / 2 ** 30
+        digits = len(printed.split(".")[1]) if "." in printed else 0
+        assert round(gib, digits) == pytest.approx(float(printed)), (w, gib, printed)
+
+
+def test_nested_over_single_ratio_si():
+    # Eq. (12) for Si (Ne=617, Np=93, Nm=6) with Nk >> Np: about 1/93
+    r = model.nested_over_single(8, 6, 617, 93, nk=10 ** 7)
+    assert 1 / 95 < r < 1 / 90
+    # and it is the ratio of the two printed counts in that limit
+    exact = model.nested_loop_cmul(8, 6, 617, 93, 10 ** 7, 50) / model.single_loop_cmul(8, 6, 617, 93, 10 ** 7, 50)
+    assert exact == pytest.approx(r, rel=2e-2)
+
+
+def test_stage_counts_sum_to_the_reassociated_nested_loop():
+    c = model.stage_counts(8, 6, 1000, 1000, 8000, 8000)
+    assert c.rp == 8000 * 1000 * 1000 * 384
+    assert c.re == 8000 * 8000 * 1000 * 384
+    assert c.rot == 8000 * 8000 * 2 * 512 * 6
+    assert c.elems == 8000 * 8000 * 384
+    # the Re sum dominates the dense Si workload (about 88 % of the cMAC)
+    assert 0.85 < c.re / c.total < 0.9

@@ -1,0 +1,249 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+FP64 tolerances come from the arithmetic: phases are correctly rounded FP64,
+every sum has at most a few thousand terms of decaying size, and the Jacobi
+eigensolves stop at an off-diagonal norm of 1e-14 of the matrix norm, so
+Wannier-gauge sums agree to ~1e-13 of their largest element and
+gauge-invariant block sums of |g|^2 to ~1e-11 relative; the tests allow 10x.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL_W = 1e-12      # Wannier-gauge sums, relative to the largest element
+RTOL_S = 1e-10      # block sums of |g|^2, normwise relative
+
+
+@pytest.fixture(scope="module")
+def run():
+    from gpu_run import Runner
+    return Runner()
+
+
+@pytest.fixture(scope="module")
+def toy():
+    return synth.si_toy()
+
+
+@pytest.fixture(scope="module")
+def toy_ref(toy):
+    return oracle.interpolate(toy.system, toy.k, toy.q, return_all=True)
+
+
+def rel_max(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+def test_bands_match_lapack(run, toy):
+    sysh = run.system(toy.system)
+    k = np.concatenate([toy.k, toy.k + 1.0, [[0.0, 0.0, 0.0]]])
+    eps, vec = run.bands(sysh, k)
+    ref_eps, ref_v = oracle.bands(toy.system, k)
+    h = oracle.hamiltonian_k(toy.system, k)
+    hn = np.linalg.norm(h, axis=(1, 2))
+    assert np.abs(eps - ref_eps).max() <= 1e-12 * hn.max()
+    res = np.linalg.norm(h @ vec - vec * eps[:, None, :], axis=(1, 2))
+    assert np.all(res <= 1e-12 * hn)
+    orth = np.conj(np.swapaxes(vec, 1, 2)) @ vec - np.eye(toy.system.nw)
+    assert np.abs(orth).max() < 1e-13
+    # non-degenerate spectrum: each column equals LAPACK's up to a phase
+    ov = np.abs(np.einsum("kai,kai->ki", np.conj(ref_v), vec))
+    assert np.abs(ov - 1).max() < 1e-10
+
+
+def test_phonons_match_lapack(run, toy):
+    sysh = run.system(toy.system)
+    lam, om, ev = run.phonons(sysh, toy.q)
+    ref_lam, ref_om, _ = oracle.phonons(toy.system, toy.q)
+    scale = np.abs(ref_lam).max()
+    assert np.abs(lam - ref_lam).max() <= 1e-12 * scale
+    np.testing.assert_allclose(om, np.sqrt(np.abs(lam)), rtol=1e-15)
+    d = oracle.dynamical_q(toy.system, toy.q)
+    res = np.linalg.norm(d @ ev - ev * lam[:, None, :], axis=(1, 2))
+    assert res.max() <= 1e-12 * scale
+
+
+def test_phase_sum_rp_fp64(run, toy, toy_ref):
+    sysh = run.system(toy.system)
+    got = run.phase_sum_rp(sysh, toy.q, 0)
+    assert rel_max(got, toy_ref["g_req"]) < RTOL_W
+
+
+def test_single_r_pure_phase_on_gpu(run):
+    w = synth.si_toy()
+    s = w.system
+    e0, p0 = 62, 17
+    g0 = s.g[p0, e0].copy()
+    s.g = np.zeros_like(s.g)
+    s.g[p0, e0] = g0
+    from paper_2603_10295_amd import ephw
+    out = run.interpolate(run.system(s), w.k, w.q, 0, flags=ephw.OUT_G | ephw.OUT_WANNIER)
+    ang = 2 * np.pi * (w.k @ s.r_e[e0].astype(float))[None, :] + \
+        2 * np.pi * (w.q @ s.r_p[p0].astype(float))[:, None]
+    expect = np.exp(1j * ang)[:, :, None, None, None] * g0[None, None]
+    assert np.abs(out["g"] - expect).max() < 1e-13 * np.abs(g0).max()
+
+
+def test_wannier_gauge_fp64(run, toy, toy_ref):
+    from paper_2603_10295_amd import ephw
+    out = run.interpolate(run.system(toy.system), toy.k, toy.q, 0, flags=ephw.OUT_G | ephw.OUT_WANNIER)
+    assert rel_max(out["g"], toy_ref["gw"]) < RTOL_W
+
+
+@pytest.mark.parametrize("q_batch", [0, 5, 1])
+def test_interpolate_fp64_gauge_invariant(run, toy, toy_ref, q_batch):
+    out = run.interpolate(run.system(toy.system), toy.k, toy.q, 0, q_batch=q_batch, loss_seed=77)
+    r = toy_ref
+    np.testing.assert_allclose(out["eps_k"], r["eps_k"], atol=1e-12 * np.abs(r["eps_k"]).max())
+    np.testing.assert_allclose(out["eps_kq"], r["eps_kq"], atol=1e-12 * np.abs(r["eps_kq"]).max())
+    np.testing.assert_allclose(out["omega"], r["omega"], atol=1e-12 * r["omega"].max())
+    s_gpu = oracle.block_sums(np.abs(out["g"]) ** 2, r["eps_kq"], r["eps_k"], r["lam"])
+    s_ref = oracle.block_sums(np.abs(r["ghat"]) ** 2, r["eps_kq"], r["eps_k"], r["lam"])
+    norm, blk = oracle.compare_block_sums(s_gpu, s_ref)
+    assert norm < RTOL_S and blk < 100 * RTOL_S
+    t_ref = oracle.band_sums(r["ghat"])
+    assert rel_max(out["band_sum"], t_ref) < RTOL_S
+    np.testing.assert_allclose(out["band_sum"], oracle.band_sums(out["g"]), rtol=1e-12)
+    nq, nk = len(toy.q), len(toy.k)
+    iq, ik = np.divmod(np.arange(nq * nk), nk)
+    l_ref = oracle.weighted_loss(r["ghat"].reshape(nq * nk, *r["ghat"].shape[2:]), 77, iq, ik, nk)
+    assert abs(out["loss"] - l_ref) < 1e-11 * l_ref
+
+
+def test_interpolate_is_deterministic(run, toy):
+    sysh = run.system(toy.system)
+    a = run.interpolate(sysh, toy.k, toy.q, 0, loss_seed=3)
+    b = run.interpolate(sysh, toy.k, toy.q, 0, loss_seed=3)
+    assert np.array_equal(a["g"], b["g"]) and a["loss"] == b["loss"]
+    assert np.array_equal(a["band_sum"], b["band_sum"])
+
+
+def test_q_offset_enters_loss_weights(run, toy, toy_ref):
+    out = run.interpolate(run.system(toy.system), toy.k, toy.q[4:9], 0, q_offset=4, loss_seed=5,
+                          flags=None)
+    nk = len(toy.k)
+    iq, ik = np.divmod(np.arange(5 * nk), nk)
+    gh = toy_ref["ghat"][4:9].reshape(5 * nk, *toy_ref["ghat"].shape[2:])
+    l_ref = oracle.weighted_loss(gh, 5, iq + 4, ik, nk)
+    assert abs(out["loss"] - l_ref) < 1e-11 * l_ref
+
+
+def test_grid_kq_index_matches_direct_eigensolve(run):
+    # 4^3 grid: k+q on the grid, looked up vs. diagonalised per pair
+    s = synth.make_system(5, 1, synth.box((3, 3, 3)), synth.box((2, 2, 2)), [0, 55])
+    pts = synth.uniform_grid((4, 4, 4))
+    kqi = synth.grid_index_of_sum((4, 4, 4))
+    sysh = run.system(s)
+    a = run.interpolate(sysh, pts, pts[:12], 0, kq_index=kqi[:12])
+    b = run.interpolate(sysh, pts, pts[:12], 0)
+    ref = oracle.interpolate(s, pts, pts[:12], return_all=True)
+    for out in (a, b):
+        np.testing.assert_allclose(out["eps_kq"], ref["eps_kq"], atol=1e-12 * np.abs(ref["eps_kq"]).max())
+        sg = oracle.block_sums(np.abs(out["g"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+        sr = oracle.block_sums(np.abs(ref["ghat"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+        assert oracle.compare_block_sums(sg, sr)[0] < RTOL_S
+
+
+def test_edge_sizes(run):
+    # one k, one q, one band, one atom; an odd band count; empty q list
+    from paper_2603_10295_amd import ephw
+    for nw, na, nk, nq in [(1, 1, 1, 1), (3, 1, 2, 3), (7, 3, 5, 2)]:
+        s = synth.make_system(nw, na, synth.box((3, 1, 2)), synth.box((1, 2, 1)), [nw, na])
+        k = np.random.default_rng(nw).random((nk, 3))
+        q = np.random.default_rng(na + 10).random((nq, 3))
+        out = run.interpolate(run.system(s), k, q, 0)
+        ref = oracle.interpolate(s, k, q, return_all=True)
+        sg = oracle.block_sums(np.abs(out["g"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+        sr = oracle.block_sums(np.abs(ref["ghat"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+        assert oracle.compare_block_sums(sg, sr)[0] < RTOL_S
+    import torch
+    s = synth.si_toy().system
+    sysh = run.system(s)
+    ks = ephw.KSet(sysh, torch.zeros((2, 3), dtype=torch.float64, device="cuda:0"), ephw.FP64)
+    g = torch.empty(1, dtype=torch.complex128, device="cuda:0")
+    ephw.interpolate(ks, torch.zeros((0, 3), dtype=torch.float64, device="cuda:0"), g_out=g)
+    run.ctx.check()
+
+
+def test_precision_mismatch_rejected(run, toy):
+    from paper_2603_10295_amd import ephw
+    import torch
+    sysh = run.system(toy.system)             # complex128 g
+    with pytest.raises(ephw.EphwError) as e:
+        ephw.KSet(sysh, torch.zeros((2, 3), dtype=torch.float64, device="cuda:0"), ephw.FP32)
+    assert e.value.status == ephw.EINVAL
+
+
+def test_bad_kq_index_reported(run):
+    from paper_2603_10295_amd import ephw
+    s = synth.make_system(2, 1, synth.box((2, 2, 1)), synth.box((2, 1, 1)), [0, 3])
+    pts = synth.uniform_grid((2, 2, 1))
+    kqi = synth.grid_index_of_sum((2, 2, 1))
+    kqi[1, 2] = 99
+    with pytest.raises(ephw.EphwError) as e:
+        run.interpolate(run.system(s), pts, pts, 0, kq_index=kqi)
+    assert e.value.status == ephw.EINDEX
+
+
+def test_mos2_sampled_full_size(run):
+    """2D MoS2-like workload at full size (1000 k x 1000 q, FP64): every pair's
+    band sums and the loss on the GPU; the oracle checks a sample of q."""
+    from paper_2603_10295_amd import ephw
+    w = synth.mos2_2d()
+    sysh = run.system(w.system)
+    out = run.interpolate(sysh, w.k, w.q, 0, flags=ephw.OUT_BAND_SUM | ephw.OUT_LOSS, loss_seed=9)
+    sample = np.array([0, 377, 999])
+    ref = oracle.interpolate(w.system, w.k, w.q[sample], return_all=True)
+    t_ref = oracle.band_sums(ref["ghat"])
+    assert rel_max(out["band_sum"][sample], t_ref) < RTOL_S
+    np.testing.assert_allclose(out["eps_kq"][sample], ref["eps_kq"], atol=1e-12 * np.abs(ref["eps_kq"]).max())
+    np.testing.assert_allclose(out["omega"][sample], ref["omega"], atol=1e-12 * ref["omega"].max())
+    # the same sample with the rotated g stored
+    out_g = run.interpolate(sysh, w.k, w.q[sample], 0, q_offset=0, flags=ephw.OUT_G, want_eps_kq=False)
+    sg = oracle.block_sums(np.abs(out_g["g"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+    sr = oracle.block_sums(np.abs(ref["ghat"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+    assert oracle.compare_block_sums(sg, sr)[0] < RTOL_S
+    assert np.isfinite(out["loss"]) and out["loss"] > 0
+
+
+# ----------------------------------------------------------------------------
+# FP32 forms: complex64 g, FP32 MFMA phase sums, FP64 eigensolves.  The oracle
+# consumes the same complex64 values (upcast), so the error measured is the
+# arithmetic's; the bound is the 1e-5 relative error in gauge-invariant |g|^2.
+# ----------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def toy32():
+    w = synth.si_toy()
+    w.system.g = w.system.g.astype(np.complex64)
+    return w
+
+
+@pytest.fixture(scope="module")
+def toy32_ref(toy32):
+    return oracle.interpolate(toy32.system, toy32.k, toy32.q, return_all=True)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_phase_sum_rp_fp32(run, toy32, toy32_ref, prec):
+    got = run.phase_sum_rp(run.system(toy32.system), toy32.q, prec)
+    err = rel_max(got, toy32_ref["g_req"])
+    print(f"phase_sum_rp prec={prec}: max rel err {err:.2e}")
+    assert err < 2e-6
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_interpolate_fp32_gauge_invariant(run, toy32, toy32_ref, prec):
+    r = toy32_ref
+    out = run.interpolate(run.system(toy32.system), toy32.k, toy32.q, prec, loss_seed=11)
+    s_gpu = oracle.block_sums(np.abs(out["g"].astype(np.complex128)) ** 2, r["eps_kq"], r["eps_k"], r["lam"])
+    s_ref = oracle.block_sums(np.abs(r["ghat"]) ** 2, r["eps_kq"], r["eps_k"], r["lam"])
+    norm, blk = oracle.compare_block_sums(s_gpu, s_ref)
+    print(f"interpolate prec={prec}: |g|^2 block sums normwise {norm:.2e}, max blockwise {blk:.2e}")
+    assert norm < 1e-5
+    assert rel_max(out["band_sum"], oracle.band_sums(r["ghat"])) < 1e-5
+    np.testing.assert_allclose(out["eps_k"], r["eps_k"], atol=1e-12 * np.abs(r["eps_k"]).max())
