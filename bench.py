@@ -1,0 +1,300 @@
+#!/usr/bin/env python3
+"""Throughput of the e-ph Wannier interpolation on one MI355X.
+
+Workload (default): the dense Si-like precision system - Nw=8 bands, Nm=6
+modes, 10x10x10 boxes (Ne=Np=1000), k = q = the 20^3 uniform grid (8000
+each), g stored complex64.  One step is the whole path on that input:
+k-side phases + H(k) eigensolves, then every q in chunks: phases, D(q)
+eigensolves, the Rp phase GEMM (Eq. 9), mode rotation, the Re phase GEMM
+(Eq. 10), band rotations, storing every g_{mn nu}(k,q) (complex64) into a
+q-chunk output buffer.  Inputs are resident in HBM before timing starts.
+
+Reported: g(k,q) elements/s of the FP32-MFMA path (the value), the same
+workload on the FP64 path and the speedup, the error of both against the
+CPU oracle on a q sample, per-stage times from HIP events, the roofline of
+the dominant kernel, and the oracle's own throughput on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def parse(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="si_dense", choices=["si_dense", "mos2_2d", "si_toy"])
+    ap.add_argument("--grid", type=int, default=20, help="k = q = grid^3 for si_dense")
+    ap.add_argument("--q-chunk", type=int, default=1024)
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--cpu-sample-q", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--q-batch", type=int, default=0)
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="first run a plain device copy of this many GiB (HBM counter calibration)")
+    return ap.parse_args(argv)
+
+
+def workload(args):
+    import synth
+    if args.workload == "si_dense":
+        return synth.si_dense(m=args.grid)
+    if args.workload == "mos2_2d":
+        w = synth.mos2_2d()
+        w.system.g = w.system.g.astype(np.complex64)
+        w.precision = "fp32"
+        return w
+    w = synth.si_toy()
+    w.system.g = w.system.g.astype(np.complex64)
+    w.precision = "fp32"
+    return w
+
+
+class Path:
+    """One precision of the GPU path on a resident system."""
+
+    def __init__(self, ctx, system, prec, k, q, kqi, q_chunk, q_batch):
+        import torch
+        from paper_2603_10295_amd import ephw
+        self.ephw = ephw
+        self.ctx = ctx
+        self.sys = ephw.System.from_synth(ctx, system)
+        if q_batch:
+            self.sys.set_q_batch(q_batch)
+        self.prec = prec
+        self.k, self.q, self.kqi = k, q, kqi
+        self.q_chunk = min(q_chunk, q.shape[0])
+        s = system
+        dt = torch.complex128 if prec == ephw.FP64 else torch.complex64
+        self.out = torch.empty((self.q_chunk, k.shape[0], s.nm, s.nw, s.nw), dtype=dt, device="cuda:0")
+
+    def step(self):
+        E = self.ephw
+        ks = E.KSet(self.sys, self.k, self.prec)
+        nq = self.q.shape[0]
+        for q0 in range(0, nq, self.q_chunk):
+            q1 = min(nq, q0 + self.q_chunk)
+            E.interpolate(ks, self.q[q0:q1], kq_index=None if self.kqi is None else self.kqi[q0:q1],
+                          q_offset=q0, flags=E.OUT_G, g_out=self.out[: q1 - q0])
+        ks.close()
+
+    def sample(self, qs_idx):
+        """g for the sampled q (all k), copied to the host."""
+        import torch
+        E = self.ephw
+        ks = E.KSet(self.sys, self.k, self.prec)
+        n = len(qs_idx)
+        idx = torch.as_tensor(qs_idx, device="cuda:0")
+        out = torch.empty((n,) + tuple(self.out.shape[1:]), dtype=self.out.dtype, device="cuda:0")
+        E.interpolate(ks, self.q[idx].contiguous(),
+                      kq_index=None if self.kqi is None else self.kqi[idx].contiguous(),
+                      flags=E.OUT_G, g_out=out)
+        self.ctx.check()
+        res = out.cpu().numpy()
+        ks.close()
+        return res
+
+
+def timed(path, steps, warmup, profile=False):
+    import torch
+    for _ in range(warmup):
+        path.step()
+    path.ctx.check()
+    if profile:
+        path.sys.profile_read()
+        path.sys.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        path.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stages = None
+    if profile:
+        path.sys.profile(False)
+        stages = path.sys.profile_read()
+    path.ctx.check()
+    return (t1 - t0) / steps, stages
+
+
+def measured_traffic(kernel_tag: str, workgroups: int):
+    """HBM bytes per dispatch of a kernel from the committed counter summary,
+    or None when the GEMM source changed since the counters were taken."""
+    from paper_2603_10295_amd import rocprof_summary as rs
+    path = os.path.join(ROOT, "profiles", "cgemm_si_dense_nw8_nm6_ne1000_8000k_8000q_hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    lines = open(path).read().splitlines()
+    if not lines or f"digest {rs.source_digest()}" not in lines[0]:
+        return None
+    for l in lines:
+        if l.startswith("#") or kernel_tag not in l or f"[{workgroups} x" not in l:
+            continue
+        parts = l.split()
+        return (float(parts[3]) + float(parts[4])) * 1e9
+    return None
+
+
+def block_error(g_gpu, ref):
+    import oracle
+    s_gpu = oracle.block_sums(np.abs(g_gpu.astype(np.complex128)) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+    s_ref = oracle.block_sums(np.abs(ref["ghat"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+    return oracle.compare_block_sums(s_gpu, s_ref)
+
+
+def cpu_baseline(w, qs_idx):
+    """The oracle as it stands on a q sample (all k): returns (elems/s, seconds, ref)."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        threads = None
+    t0 = time.perf_counter()
+    ref = oracle.interpolate(w.system, w.k, w.q[qs_idx], return_all=True)
+    dt = time.perf_counter() - t0
+    s = w.system
+    elems = len(qs_idx) * len(w.k) * s.nm * s.nw * s.nw
+    return elems / dt, dt, ref, threads
+
+
+def main(argv=None):
+    args = parse(argv)
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the path shards over q across GPUs by design, see the design notes)", file=sys.stderr)
+        return 2
+    import torch
+    from paper_2603_10295_amd import ephw, model
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        return 2
+
+    if args.copy_calibration_gib > 0:
+        n = int(args.copy_calibration_gib * 2 ** 30) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: {n * 4} bytes read and written")
+        del src, dst
+
+    t_gen = time.perf_counter()
+    w = workload(args)
+    s = w.system
+    nk, nq = len(w.k), len(w.q)
+    log(f"workload {w.name}: nk={nk} nq={nq} nw={s.nw} nm={s.nm} ne={s.ne} np={s.np_} "
+        f"(generated in {time.perf_counter() - t_gen:.1f}s)")
+    k = torch.from_numpy(w.k).to("cuda:0")
+    q = torch.from_numpy(w.q).to("cuda:0")
+    kqi = torch.from_numpy(w.kq_index).to("cuda:0") if w.kq_index is not None else None
+    ctx = ephw.Context(0)
+    cnt = model.stage_counts(s.nw, s.nm, s.ne, s.np_, nk, nq, nh=len(s.r_h), kq_on_grid=w.kq_index is not None)
+
+    # ---- FP32 MFMA path (the headline) -----------------------------------
+    p32 = Path(ctx, s, ephw.FP32, k, q, kqi, args.q_chunk, args.q_batch)
+    log("FP32 path: warmup + timed steps")
+    t32, stages = timed(p32, args.steps, args.warmup, profile=True)
+    v32 = cnt.elems / t32
+    log(f"FP32: {t32 * 1e3:.1f} ms/step, {v32:.4e} elems/s")
+    re_ms, re_n = stages["re_gemm"]
+    qb32 = min(128, nq)
+    re_wg = -(-nk // 128) * -(-(qb32 * s.nm * s.nw * s.nw) // 128)   # workgroups of a full-batch Re GEMM
+    re_flops = 8.0 * cnt.re * args.steps
+    re_tflops = re_flops / (re_ms * 1e-3) / 1e12
+    rp_ms, rp_n = stages["rp_gemm"]
+    rp_tflops = 8.0 * cnt.rp * args.steps / (rp_ms * 1e-3) / 1e12
+    gemm_tflops = 8.0 * cnt.gemm * args.steps / ((re_ms + rp_ms) * 1e-3) / 1e12
+
+    # ---- oracle sample: CPU baseline and the error of the GPU paths -------
+    rng = np.random.default_rng(1234)
+    qs_idx = np.sort(rng.choice(nq, size=min(args.cpu_sample_q, nq), replace=False))
+    cpu = None
+    err32 = err64 = None
+    if not args.no_cpu_baseline:
+        log(f"oracle on {len(qs_idx)} q x {nk} k")
+        c_val, c_dt, ref, threads = cpu_baseline(w, qs_idx)
+        cores = len(os.sched_getaffinity(0))
+        cpu = {"value": c_val, "unit": "elems/s", "cores": cores, "blas_threads": threads, "kind": "oracle",
+               "seconds": round(c_dt, 2),
+               "sample": f"{len(qs_idx)} q (of {nq}) x all {nk} k of the same workload, "
+                         f"NumPy complex128 + LAPACK eigh, nested loop Eqs. (9)-(10)"}
+        log(f"oracle: {c_val:.4e} elems/s in {c_dt:.1f}s")
+        g32 = p32.sample(qs_idx)
+        err32 = block_error(g32, ref)
+        log(f"FP32 vs oracle: normwise {err32[0]:.2e}, max blockwise {err32[1]:.2e}")
+
+    # ---- FP64 path on the same values (complex64 g upcast) ----------------
+    fp64 = None
+    if not args.no_fp64:
+        del p32.out
+        s64 = type(s)(**{**s.__dict__, "g": s.g.astype(np.complex128)})
+        p64 = Path(ctx, s64, ephw.FP64, k, q, kqi, args.q_chunk, args.q_batch)
+        log("FP64 path: warmup + timed steps")
+        t64, st64 = timed(p64, args.fp64_steps, 1 if args.warmup else 0, profile=True)
+        fp64 = {"value": cnt.elems / t64, "ms_per_step": t64 * 1e3,
+                "re_gemm_tflops": 8.0 * cnt.re * args.fp64_steps / (st64["re_gemm"][0] * 1e-3) / 1e12,
+                "rp_gemm_tflops": 8.0 * cnt.rp * args.fp64_steps / (st64["rp_gemm"][0] * 1e-3) / 1e12,
+                "stages_ms": {k_: round(v[0] / args.fp64_steps, 3) for k_, v in st64.items()}}
+        log(f"FP64: {t64 * 1e3:.1f} ms/step")
+        if cpu is not None:
+            g64 = p64.sample(qs_idx)
+            err64 = block_error(g64, ref)
+            fp64["err_vs_oracle"] = {"normwise": err64[0], "max_blockwise": err64[1]}
+        p64.sys.close()
+
+    line = {
+        "metric": "g(k,q) elems/s (FP32 MFMA path)",
+        "value": v32,
+        "unit": "elems/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t32 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nw": s.nw, "nm": s.nm, "ne": s.ne, "np": s.np_, "nk": nk, "nq": nq,
+                   "g_dtype": "complex64", "eig": "fp64", "output": "g stored complex64, q-chunked",
+                   "q_chunk": p32.q_chunk},
+        "roofline": {"bound": "mfma", "achieved": re_tflops, "peak": model.PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": re_tflops / model.PEAK_FP32_TFLOPS,
+                     "traffic": measured_traffic("cgemm_kernel<float", re_wg),
+                     "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+                     "kernel": "cgemm_kernel<float> Re phase sum (Eq. 10)",
+                     "flops_per_launch": re_flops / max(1, re_n), "avg_launch_ms": re_ms / max(1, re_n),
+                     "launches": re_n},
+        "cpu_baseline": cpu,
+        "phase_gemm_tflops": {"re": re_tflops, "rp": rp_tflops, "both": gemm_tflops,
+                              "frac_of_fp32_peak": gemm_tflops / model.PEAK_FP32_TFLOPS},
+        "stages_ms_per_step": {k_: round(v[0] / args.steps, 3) for k_, v in stages.items()},
+        "err_vs_oracle": None if err32 is None else {"normwise": err32[0], "max_blockwise": err32[1],
+                                                     "sample_q": len(qs_idx)},
+        "fp64_gpu": fp64,
+        "fp32_vs_fp64_speedup": None if fp64 is None else fp64["ms_per_step"] / (t32 * 1e3),
+        "algorithmic_flops_per_step": 8.0 * cnt.total,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -183,6 +183,67 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
 /* Tuning knobs (0 = automatic).  q_batch: q points per Rp/Re GEMM sweep. */
 ephw_status ephw_set_q_batch(ephw_system* sys, int32_t q_batch);
 
+/* Per-stage GPU timing for benchmarks: while enabled, every stage of the calls
+   made on `sys` (and its k-sets) is bracketed by HIP events recorded on the
+   call's stream.  ephw_profile_read synchronises those events, writes the
+   summed milliseconds and launch counts of each stage (arrays of
+   EPHW_NSTAGES entries; either may be NULL) and clears the records. */
+#define EPHW_STAGE_PHASE     0  /* phase factors */
+#define EPHW_STAGE_EIG       1  /* H(k), D(q) interpolation + eigensolve */
+#define EPHW_STAGE_KQ_EIG    2  /* H(k+q) interpolation + eigensolve per pair */
+#define EPHW_STAGE_RP_GEMM   3  /* Eq. (9) phase sum */
+#define EPHW_STAGE_MODE_ROT  4  /* u(q) applied to g(Re,q) */
+#define EPHW_STAGE_RE_GEMM   5  /* Eq. (10) Re phase sum */
+#define EPHW_STAGE_BAND_ROT  6  /* V(k+q)^dagger g V(k) + epilogues */
+#define EPHW_STAGE_OTHER     7  /* casts, gathers, reductions */
+#define EPHW_NSTAGES         8
+ephw_status ephw_profile_enable(ephw_system* sys, int32_t enable);
+ephw_status ephw_profile_read(ephw_system* sys, double* ms, int64_t* launches);
+
+/* ---------------------------------------------------------------------------
+   Many systems in one pass (not in the paper: persistent multi-system batching).
+   Each item interpolates one k-set (of its own system) with a q list whose
+   k+q fall on the k grid (kq_index is required).  Per item, a shape (q points
+   per sweep, k points per tile, GEMM tile configuration) is chosen by the
+   autotuner; the pass then runs in rounds, and every stage of a round (the
+   Eq. (9) GEMMs, mode rotations, Eq. (10) GEMMs, band rotations, loss sums)
+   is one grouped launch over all systems; the GEMM stages are persistent
+   launches striding over the tiles of every system.  The whole pass is
+   captured once into a HIP graph and replayed by ephw_batch_run.
+   Outputs are the pointers given at ephw_batch_create (fixed for the batch's
+   lifetime); loss outputs accumulate (L +=) on every run.
+   --------------------------------------------------------------------------- */
+typedef struct ephw_batch ephw_batch;
+typedef struct ephw_batch_item {
+  ephw_kset* ks;             /* k set; its system and precision are used */
+  const double* q;           /* [nq][3] f64 (device) */
+  int64_t nq;
+  const int32_t* kq_index;   /* [nq][nk] int32 (device), required */
+  uint32_t flags;            /* EPHW_OUT_G / EPHW_OUT_BAND_SUM / EPHW_OUT_LOSS */
+  void* g_out;               /* as in ephw_interpolate */
+  double* band_sum;
+  double* loss;
+  uint64_t loss_seed;
+} ephw_batch_item;
+typedef struct ephw_batch_options {
+  int32_t tune;              /* 0: heuristic shapes; 1: time candidate shapes on the device */
+  const char* tune_cache;    /* file of tuned shapes (one JSON object per line) or NULL */
+  int32_t use_graph;         /* 1: capture the pass into a HIP graph */
+  int64_t item_workspace_bytes; /* per-item cap of the sweep buffers (0 = 1 GiB) */
+} ephw_batch_options;
+/* Plan a batch: validates items, tunes shapes, allocates the workspace.
+   All items must share one precision; nw <= 32 and nm <= 24 per system. */
+ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32_t n,
+                              const ephw_batch_options* opt, void* stream, ephw_batch** out);
+ephw_status ephw_batch_run(ephw_batch* b, void* stream);
+/* the shape chosen for item i: q points per sweep, k points per tile, GEMM tile
+   configuration of the Eq. (9) and Eq. (10) GEMMs (0 = 128-row tiles, 1 = 64x64) */
+ephw_status ephw_batch_shape(const ephw_batch* b, int32_t i, int32_t* q_batch, int32_t* k_tile,
+                             int32_t* cfg_rp, int32_t* cfg_re);
+/* number of rounds and of kernel launches in one pass */
+ephw_status ephw_batch_stats(const ephw_batch* b, int32_t* rounds, int32_t* launches);
+ephw_status ephw_batch_free(ephw_batch* b);
+
 const char* ephw_status_string(ephw_status s);
 const char* ephw_last_error(void);
 /* library version as MAJOR*10000 + MINOR*100 + PATCH */

@@ -7,116 +7,16 @@
 #include <string>
 #include <vector>
 
-#include "gemm.h"
-#include "kernels.h"
+#include "internal.h"
 
 namespace ephw {
 
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-namespace {
-
-// grow-only device buffer; reallocation waits for the device to go idle
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
-
-ephw_status dev_alloc(void** p, size_t bytes) {
-  if (bytes == 0) bytes = 16;
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
-    *p = nullptr;
-    return EPHW_ENOMEM;
-  }
-  return EPHW_OK;
-}
-
-ephw_status grow(DevBuf& b, size_t bytes, int64_t* owner_bytes) {
-  if (b.bytes >= bytes && b.p) return EPHW_OK;
-  if (b.p) {
-    EPHW_HIP(hipDeviceSynchronize());
-    EPHW_HIP(hipFree(b.p));
-    *owner_bytes -= (int64_t)b.bytes;
-    b.p = nullptr;
-    b.bytes = 0;
-  }
-  EPHW_TRY(dev_alloc(&b.p, bytes));
-  b.bytes = bytes;
-  *owner_bytes += (int64_t)bytes;
-  return EPHW_OK;
-}
-
-template <typename X>
-ephw_status upload(X** dst, const X* src, size_t count, int64_t* owner_bytes) {
-  void* p = nullptr;
-  EPHW_TRY(dev_alloc(&p, count * sizeof(X)));
-  *owner_bytes += (int64_t)(count * sizeof(X));
-  EPHW_HIP(hipMemcpy(p, src, count * sizeof(X), hipMemcpyHostToDevice));
-  *dst = static_cast<X*>(p);
-  return EPHW_OK;
-}
-
-int prec_kind(int32_t prec) { return prec == EPHW_FP64 ? 0 : 1; }
-size_t csize(int kind) { return kind == 0 ? 16 : 8; }
-
-}  // namespace
 }  // namespace ephw
 
-using namespace ephw;
-
-struct ephw_ctx {
-  int device = 0;
-  uint32_t* status = nullptr;
-};
-
-enum WsSlot {
-  WS_PQ, WS_PQ_LO, WS_PQH, WS_PQC, WS_D, WS_LAM, WS_E, WS_U, WS_G, WS_GNU, WS_W, WS_BQ, WS_HKQ,
-  WS_EKQ, WS_VKQ64, WS_VKQ, WS_JWORK, WS_LOSS, WS_PH, WS_HK, WS_EPS, WS_V64, WS_COUNT
-};
-
-struct ephw_system {
-  ephw_ctx* ctx = nullptr;
-  int nw = 0, na = 0, nm = 0;
-  int64_t ne = 0, np = 0, nh = 0, nc = 0;
-  int g_kind = 0;  // 0 = c128, 1 = c64
-  int32_t *r_e = nullptr, *r_p = nullptr, *r_h = nullptr, *r_c = nullptr;
-  double *w_e = nullptr, *w_p = nullptr, *w_h = nullptr, *w_c = nullptr;
-  double* h_r = nullptr;      // c128 [nh][nw][nw]
-  double* c_scaled = nullptr; // c128 [nc][nm][nm] = C / sqrt(M M')
-  double* ism = nullptr;      // [nm] 1/sqrt(M_kappa) per mode index
-  void* g = nullptr;
-  int32_t q_batch = 0;
-  int64_t bytes = 0;
-  DevBuf ws[WS_COUNT];
-};
-
-struct ephw_kset {
-  ephw_system* sys = nullptr;
-  int64_t nk = 0;
-  int32_t prec = 0;
-  int64_t bytes = 0;
-  double* k = nullptr;      // [nk][3]
-  void* pk = nullptr;       // T [nk][ne]
-  void* pk_lo = nullptr;    // float [nk][ne] (split)
-  double* pkh = nullptr;    // c128 [nk][nh]
-  double* eps = nullptr;    // [nk][nw]
-  double* v64 = nullptr;    // c128 [nk][nw][nw]
-  void* vt = nullptr;       // T [nk][nw][nw]
-};
-
 namespace {
-
-void* wsp(ephw_system* s, WsSlot slot) { return s->ws[slot].p; }
-
-ephw_status ws_need(ephw_system* s, WsSlot slot, size_t bytes) {
-  return grow(s->ws[slot], bytes, &s->bytes);
-}
-
-hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
 
 // FP64 interpolation + eigensolve: out_eps [n][dim], out_v c128 [n][dim][dim]
 // from A = phases [n][nr] (c128) and B = R-space matrices [nr][dim*dim] (c128).
@@ -124,6 +24,9 @@ ephw_status interp_eigh(ephw_system* s, const double* phase, int64_t n, int64_t 
                         int dim, double* out_eps, double* out_v, hipStream_t st) {
   const int64_t d2 = (int64_t)dim * dim;
   EPHW_TRY(ws_need(s, WS_HK, (size_t)n * d2 * 16));
+  const int64_t jw = jacobi_work_doubles(dim, n);
+  if (jw > 0) EPHW_TRY(ws_need(s, WS_JWORK, (size_t)jw * 8));
+  Stage sg_(s, EPHW_STAGE_EIG, st);
   GemmParams p;
   p.M = n;
   p.N = d2;
@@ -135,23 +38,22 @@ ephw_status interp_eigh(ephw_system* s, const double* phase, int64_t n, int64_t 
   p.C = wsp(s, WS_HK);
   p.ldc = d2;
   EPHW_TRY(cgemm(0, p, st));
-  const int64_t jw = jacobi_work_doubles(dim, n);
-  if (jw > 0) EPHW_TRY(ws_need(s, WS_JWORK, (size_t)jw * 8));
   return jacobi_eigh(static_cast<const double*>(wsp(s, WS_HK)), n, dim, out_eps, out_v,
                      jw > 0 ? static_cast<double*>(wsp(s, WS_JWORK)) : nullptr, s->ctx->status, st);
 }
 
 int32_t pick_q_batch(const ephw_system* s, int64_t nk, int64_t nq, int kind) {
   if (s->q_batch > 0) return (int32_t)(s->q_batch < nq ? s->q_batch : nq);
+  // q points per sweep: the Rp GEMM has M = q_batch, so a full 128-row tile
+  // wants 128; the workspace (Re-GEMM output + two g(Re,q) buffers) is capped
+  // at 8 GB of the 288 GB of HBM.
   const int64_t E = (int64_t)s->nm * s->nw * s->nw;
   const double per_q = (double)csize(kind) * E * ((double)nk + 2.0 * (double)s->ne);
-  int64_t qb = (int64_t)((4.0 * 1024 * 1024 * 1024) / per_q);
-  if (qb > 256) qb = 256;
+  int64_t qb = (int64_t)((8.0 * 1024 * 1024 * 1024) / per_q);
   if (qb >= 128) qb = 128;
   else if (qb >= 64) qb = 64;
   if (qb < 1) qb = 1;
   if (qb > nq) qb = nq;
-  if (qb > 65535) qb = 65535;
   return (int32_t)qb;
 }
 
@@ -239,6 +141,11 @@ ephw_status ephw_system_free(ephw_system* s) {
     if (p) (void)hipFree(p);
   for (auto& b : s->ws)
     if (b.p) (void)hipFree(b.p);
+  for (auto& r : s->prof.recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : s->prof.pool) (void)hipEventDestroy(e);
   delete s;
   return EPHW_OK;
 }
@@ -348,6 +255,42 @@ ephw_status ephw_set_q_batch(ephw_system* s, int32_t q_batch) {
   return EPHW_OK;
 }
 
+ephw_status ephw_profile_enable(ephw_system* s, int32_t enable) {
+  if (!s) {
+    set_error("ephw_profile_enable: system is NULL");
+    return EPHW_EINVAL;
+  }
+  s->prof.on = enable != 0;
+  return EPHW_OK;
+}
+
+ephw_status ephw_profile_read(ephw_system* s, double* ms, int64_t* launches) {
+  if (!s) {
+    set_error("ephw_profile_read: system is NULL");
+    return EPHW_EINVAL;
+  }
+  if (ms)
+    for (int i = 0; i < EPHW_NSTAGES; ++i) ms[i] = 0.0;
+  if (launches)
+    for (int i = 0; i < EPHW_NSTAGES; ++i) launches[i] = 0;
+  ephw_status result = EPHW_OK;
+  for (auto& r : s->prof.recs) {
+    float t = 0.f;
+    if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+      set_error("ephw_profile_read: event query failed");
+      result = EPHW_EDEVICE;
+    }
+    if (r.stage >= 0 && r.stage < EPHW_NSTAGES) {
+      if (ms) ms[r.stage] += (double)t;
+      if (launches) launches[r.stage] += 1;
+    }
+    s->prof.pool.push_back(r.a);
+    s->prof.pool.push_back(r.b);
+  }
+  s->prof.recs.clear();
+  return result;
+}
+
 ephw_status ephw_bands(ephw_system* s, const double* k, int64_t nk, double* eps, void* vecs,
                        void* stream) {
   if (!s || (!k && nk > 0) || nk < 0) {
@@ -358,7 +301,10 @@ ephw_status ephw_bands(ephw_system* s, const double* k, int64_t nk, double* eps,
   hipStream_t st = as_stream(stream);
   const int64_t nw2 = (int64_t)s->nw * s->nw;
   EPHW_TRY(ws_need(s, WS_PH, (size_t)nk * s->nh * 16));
-  EPHW_TRY(phase_matrix(0, k, nk, s->r_h, s->w_h, s->nh, wsp(s, WS_PH), nullptr, st));
+  {
+    Stage sg_(s, EPHW_STAGE_PHASE, st);
+    EPHW_TRY(phase_matrix(0, k, nk, s->r_h, s->w_h, s->nh, wsp(s, WS_PH), nullptr, st));
+  }
   double* e_out = eps;
   double* v_out = static_cast<double*>(vecs);
   if (!e_out) {
@@ -383,7 +329,10 @@ ephw_status ephw_phonons(ephw_system* s, const double* q, int64_t nq, double* la
   hipStream_t st = as_stream(stream);
   const int nm = s->nm;
   EPHW_TRY(ws_need(s, WS_PQC, (size_t)nq * s->nc * 16));
-  EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), nullptr, st));
+  {
+    Stage sg_(s, EPHW_STAGE_PHASE, st);
+    EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), nullptr, st));
+  }
   double* l_out = lam;
   if (!l_out) {
     EPHW_TRY(ws_need(s, WS_LAM, (size_t)nq * nm * 8));
@@ -396,7 +345,10 @@ ephw_status ephw_phonons(ephw_system* s, const double* q, int64_t nq, double* la
   }
   EPHW_TRY(interp_eigh(s, static_cast<const double*>(wsp(s, WS_PQC)), nq, s->nc, s->c_scaled, nm,
                        l_out, e_out, st));
-  if (omega) EPHW_TRY(abs_sqrt(l_out, omega, nq * nm, st));
+  {
+    Stage sg_(s, EPHW_STAGE_OTHER, st);
+    if (omega) EPHW_TRY(abs_sqrt(l_out, omega, nq * nm, st));
+  }
   return EPHW_OK;
 }
 
@@ -420,8 +372,11 @@ ephw_status ephw_phase_sum_rp(ephw_system* s, const double* q, int64_t nq, int32
   const bool split = prec == EPHW_FP32_SPLIT;
   EPHW_TRY(ws_need(s, WS_PQ, (size_t)nq * s->np * csize(kind)));
   if (split) EPHW_TRY(ws_need(s, WS_PQ_LO, (size_t)nq * s->np * 8));
-  EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, s->np, wsp(s, WS_PQ),
-                        split ? wsp(s, WS_PQ_LO) : nullptr, st));
+  {
+    Stage sg_(s, EPHW_STAGE_PHASE, st);
+    EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, s->np, wsp(s, WS_PQ),
+                          split ? wsp(s, WS_PQ_LO) : nullptr, st));
+  }
   GemmParams p;
   p.M = nq;
   p.N = s->ne * s->nm * s->nw * s->nw;
@@ -433,7 +388,10 @@ ephw_status ephw_phase_sum_rp(ephw_system* s, const double* q, int64_t nq, int32
   p.ldb = p.N;
   p.C = out;
   p.ldc = p.N;
-  return cgemm(kind, p, st);
+  {
+    Stage sg_(s, EPHW_STAGE_RP_GEMM, st);
+    return cgemm(kind, p, st);
+  }
 }
 
 ephw_status ephw_kset_free(ephw_kset* ks) {
@@ -490,13 +448,22 @@ ephw_status ephw_kset_create(ephw_system* s, const double* k, int64_t nk, int32_
   if ((e = alloc((void**)&ks->eps, (size_t)nk * s->nw * 8)) != EPHW_OK) return fail(e);
   if ((e = alloc((void**)&ks->v64, (size_t)nk * nw2 * 16)) != EPHW_OK) return fail(e);
   if ((e = alloc(&ks->vt, (size_t)nk * nw2 * csize(kind))) != EPHW_OK) return fail(e);
-  if ((e = phase_matrix(kind, ks->k, nk, s->r_e, s->w_e, s->ne, ks->pk, ks->pk_lo, st)) != EPHW_OK)
-    return fail(e);
-  if ((e = phase_matrix(0, ks->k, nk, s->r_h, s->w_h, s->nh, ks->pkh, nullptr, st)) != EPHW_OK)
-    return fail(e);
+  {
+    Stage sg_(s, EPHW_STAGE_PHASE, st);
+    if ((e = phase_matrix(kind, ks->k, nk, s->r_e, s->w_e, s->ne, ks->pk, ks->pk_lo, st)) != EPHW_OK)
+      return fail(e);
+  }
+  {
+    Stage sg_(s, EPHW_STAGE_PHASE, st);
+    if ((e = phase_matrix(0, ks->k, nk, s->r_h, s->w_h, s->nh, ks->pkh, nullptr, st)) != EPHW_OK)
+      return fail(e);
+  }
   if ((e = interp_eigh(s, ks->pkh, nk, s->nh, s->h_r, s->nw, ks->eps, ks->v64, st)) != EPHW_OK)
     return fail(e);
-  if ((e = cast_complex(kind, ks->v64, ks->vt, nk * nw2, st)) != EPHW_OK) return fail(e);
+  {
+    Stage sg_(s, EPHW_STAGE_OTHER, st);
+    if ((e = cast_complex(kind, ks->v64, ks->vt, nk * nw2, st)) != EPHW_OK) return fail(e);
+  }
   *out = ks;
   return EPHW_OK;
 }
@@ -564,18 +531,30 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
   // --- per-call q side: Rp phases, D(q) eigensolve, mode vectors ----------
   EPHW_TRY(ws_need(s, WS_PQ, (size_t)nq * s->np * cs));
   if (split) EPHW_TRY(ws_need(s, WS_PQ_LO, (size_t)nq * s->np * 8));
-  EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, s->np, wsp(s, WS_PQ),
-                        split ? wsp(s, WS_PQ_LO) : nullptr, st));
+  {
+    Stage sg_(s, EPHW_STAGE_PHASE, st);
+    EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, s->np, wsp(s, WS_PQ),
+                          split ? wsp(s, WS_PQ_LO) : nullptr, st));
+  }
   EPHW_TRY(ws_need(s, WS_LAM, (size_t)nq * nm * 8));
   EPHW_TRY(ws_need(s, WS_E, (size_t)nq * nm * nm * 16));
   EPHW_TRY(ws_need(s, WS_PQC, (size_t)nq * s->nc * 16));
-  EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), nullptr, st));
+  {
+    Stage sg_(s, EPHW_STAGE_PHASE, st);
+    EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), nullptr, st));
+  }
   EPHW_TRY(interp_eigh(s, static_cast<const double*>(wsp(s, WS_PQC)), nq, s->nc, s->c_scaled, nm,
                        static_cast<double*>(wsp(s, WS_LAM)), static_cast<double*>(wsp(s, WS_E)), st));
-  if (omega) EPHW_TRY(abs_sqrt(static_cast<const double*>(wsp(s, WS_LAM)), omega, nq * nm, st));
+  {
+    Stage sg_(s, EPHW_STAGE_OTHER, st);
+    if (omega) EPHW_TRY(abs_sqrt(static_cast<const double*>(wsp(s, WS_LAM)), omega, nq * nm, st));
+  }
   EPHW_TRY(ws_need(s, WS_U, (size_t)nq * nm * nm * cs));
-  EPHW_TRY(mode_vectors(kind, static_cast<const double*>(wsp(s, WS_E)), nq, nm, s->ism,
-                        wsp(s, WS_U), st));
+  {
+    Stage sg_(s, EPHW_STAGE_OTHER, st);
+    EPHW_TRY(mode_vectors(kind, static_cast<const double*>(wsp(s, WS_E)), nq, nm, s->ism,
+                          wsp(s, WS_U), st));
+  }
   const bool need_g = (flags & (EPHW_OUT_G | EPHW_OUT_BAND_SUM | EPHW_OUT_LOSS)) != 0;
   const bool need_kq_eig = !kq_index && (!wannier || eps_kq);
 
@@ -587,7 +566,10 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
   }
   if (need_kq_eig) {
     EPHW_TRY(ws_need(s, WS_PQH, (size_t)nq * s->nh * 16));
-    EPHW_TRY(phase_matrix(0, q, nq, s->r_h, nullptr, s->nh, wsp(s, WS_PQH), nullptr, st));
+    {
+      Stage sg_(s, EPHW_STAGE_PHASE, st);
+      EPHW_TRY(phase_matrix(0, q, nq, s->r_h, nullptr, s->nh, wsp(s, WS_PQH), nullptr, st));
+    }
     EPHW_TRY(ws_need(s, WS_BQ, (size_t)qb * s->nh * nw2 * 16));
     EPHW_TRY(ws_need(s, WS_HKQ, (size_t)qb * nk * nw2 * 16));
     EPHW_TRY(ws_need(s, WS_EKQ, (size_t)qb * nk * nw * 8));
@@ -606,6 +588,7 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
     const int32_t nb = (int32_t)((nq - q0) < qb ? (nq - q0) : qb);
     // bands at k+q: H(k+q) = sum_R e^{2 pi i k.R} (e^{2 pi i q.R} H(R)), then FP64 Jacobi
     if (need_kq_eig) {
+      Stage sg_(s, EPHW_STAGE_KQ_EIG, st);
       EPHW_TRY(scale_rows_by_phase(static_cast<const double*>(wsp(s, WS_PQH)) + 2 * q0 * s->nh, nb,
                                    s->h_r, s->nh, nw2, static_cast<double*>(wsp(s, WS_BQ)), st));
       GemmParams h;
@@ -633,8 +616,11 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
                             (int64_t)nb * nk * nw2, st));
     } else if (eps_kq && kq_index) {
       // k+q on the k grid: its bands are the k-set's bands at the indexed point
-      EPHW_TRY(gather_rows(ks->eps, nk, kq_index + q0 * nk, (int64_t)nb * nk, nw,
-                           eps_kq + q0 * nk * nw, s->ctx->status, st));
+      {
+        Stage sg_(s, EPHW_STAGE_OTHER, st);
+        EPHW_TRY(gather_rows(ks->eps, nk, kq_index + q0 * nk, (int64_t)nb * nk, nw,
+                             eps_kq + q0 * nk * nw, s->ctx->status, st));
+      }
     }
     if (!need_g) continue;
     // Eq. (9): G[q][Re, ka, m', n'] = sum_Rp e^{i q.Rp} g(Re, Rp)
@@ -649,12 +635,18 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
     rp.ldb = rp.N;
     rp.C = wsp(s, WS_G);
     rp.ldc = rp.N;
-    EPHW_TRY(cgemm(kind, rp, st));
+    {
+      Stage sg_(s, EPHW_STAGE_RP_GEMM, st);
+      EPHW_TRY(cgemm(kind, rp, st));
+    }
     // mode vectors u(q), hoisted to the g(Re,q) level; output [Re][q][nu][m'][n']
-    EPHW_TRY(mode_rotate(kind, wsp(s, WS_G),
-                         wannier ? nullptr
-                                 : static_cast<const char*>(wsp(s, WS_U)) + (size_t)q0 * nm * nm * cs,
-                         wsp(s, WS_GNU), s->ne, nb, nm, nw2, st));
+    {
+      Stage sg_(s, EPHW_STAGE_MODE_ROT, st);
+      EPHW_TRY(mode_rotate(kind, wsp(s, WS_G),
+                           wannier ? nullptr
+                                   : static_cast<const char*>(wsp(s, WS_U)) + (size_t)q0 * nm * nm * cs,
+                           wsp(s, WS_GNU), s->ne, nb, nm, nw2, st));
+    }
     // Eq. (10), Re part: W[k][q nu m' n'] = sum_Re e^{i k.Re} G_nu(Re, q)
     GemmParams re;
     re.M = nk;
@@ -667,7 +659,10 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
     re.ldb = re.N;
     re.C = wsp(s, WS_W);
     re.ldc = re.N;
-    EPHW_TRY(cgemm(kind, re, st));
+    {
+      Stage sg_(s, EPHW_STAGE_RE_GEMM, st);
+      EPHW_TRY(cgemm(kind, re, st));
+    }
     // band rotations V(k+q)^dagger W V(k) and the epilogues
     BandRotateArgs br;
     br.W = wsp(s, WS_W);
@@ -675,6 +670,8 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
     br.Vkq = kq_index ? nullptr : wsp(s, WS_VKQ);
     br.kq_index = kq_index ? kq_index + q0 * nk : nullptr;
     br.nk = nk;
+    br.k0 = 0;
+    br.nk_tile = nk;
     br.qb = nb;
     br.nm = nm;
     br.nw = nw;
@@ -685,8 +682,14 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
     br.loss_seed = loss_seed;
     br.q_global0 = q_offset + q0;
     br.status = s->ctx->status;
-    EPHW_TRY(band_rotate(kind, br, st));
-    if (flags & EPHW_OUT_LOSS) EPHW_TRY(sum_into(loss_part, (int64_t)nb * nk, loss, st));
+    {
+      Stage sg_(s, EPHW_STAGE_BAND_ROT, st);
+      EPHW_TRY(band_rotate(kind, br, st));
+    }
+    {
+      Stage sg_(s, EPHW_STAGE_OTHER, st);
+      if (flags & EPHW_OUT_LOSS) EPHW_TRY(sum_into(loss_part, (int64_t)nb * nk, loss, st));
+    }
   }
   return EPHW_OK;
 }

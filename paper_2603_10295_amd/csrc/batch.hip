@@ -1,0 +1,724 @@
+// Many systems in one pass: per-item shapes from the autotuner, rounds of
+// grouped launches over all systems, the pass captured into a HIP graph.
+//
+// Item i runs its units (q batch j, k tile t) in order, one unit per round;
+// a unit with t == 0 first needs the Eq. (9) GEMM and the mode rotation of
+// q batch j.  Every stage of a round is one launch over all items that take
+// part in it: the GEMM stages are persistent grouped GEMMs (a fixed grid of
+// one workgroup per CU strides over the tiles of every item, each item with
+// its own tile shape); the other stages are grouped block grids.
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <fstream>
+#include <map>
+#include <sstream>
+
+#include "internal.h"
+
+namespace {
+
+struct ItemPlan {
+  ephw_batch_item in{};
+  ephw_system* sys = nullptr;
+  ephw_kset* ks = nullptr;
+  int nw = 0, nm = 0;
+  int64_t ne = 0, np = 0, nc = 0, nk = 0, nq = 0, E = 0;
+  int32_t qb = 0, kt = 0, cfg_rp = 0, cfg_re = 0;
+  int64_t nqb = 0, nkt = 0;
+  int nuc = 1;
+  size_t lds_band = 0;
+  // workspace
+  void* pq = nullptr;      // T [nq][np]
+  double* pqc = nullptr;   // c128 [nq][nc]
+  double* dq = nullptr;    // c128 [nq][nm][nm]
+  double* lam = nullptr;   // [nq][nm]
+  double* ev = nullptr;    // c128 [nq][nm][nm]
+  void* u = nullptr;       // T [nq][nm][nm]
+  void* G = nullptr;       // T [qb][ne*E]
+  void* Gnu = nullptr;     // T [ne][qb*E]
+  void* W = nullptr;       // T [kt][qb*E]
+  double* lossp = nullptr; // [qb*kt]
+  size_t bytes() const;
+  int64_t units() const { return nqb * nkt; }
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Launch {
+  enum Kind { PHASE, GEMM, EIGH, MODEVEC, MODE, BAND, SUM } kind;
+  int prec = 0;
+  const void* jobs = nullptr;  // device descriptor array
+  int n = 0;
+  int64_t count = 0;           // total tiles (GEMM) or blocks
+  size_t lds = 0;
+  // PHASE / MODEVEC: direct arguments
+  int item = -1;
+};
+
+}  // namespace
+
+struct ephw_batch {
+  ephw_ctx* ctx = nullptr;
+  int kind = 0;
+  std::vector<ItemPlan> items;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  void* desc = nullptr;
+  size_t desc_bytes = 0;
+  std::vector<Launch> launches;
+  int rounds = 0;
+  int grid_gemm = 256;
+  bool use_graph = false;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+size_t ItemPlan::bytes() const {
+  const size_t cs = csize(sys->g_kind);
+  size_t b = 0;
+  b += align256((size_t)nq * np * cs);
+  b += align256((size_t)nq * nc * 16);
+  b += align256((size_t)nq * nm * nm * 16);
+  b += align256((size_t)nq * nm * 8);
+  b += align256((size_t)nq * nm * nm * 16);
+  b += align256((size_t)nq * nm * nm * cs);
+  b += align256((size_t)qb * ne * E * cs);
+  b += align256((size_t)qb * ne * E * cs);
+  b += align256((size_t)kt * qb * E * cs);
+  b += align256((size_t)qb * kt * 8);
+  return b;
+}
+
+void carve(ItemPlan& it, char* base) {
+  const size_t cs = csize(it.sys->g_kind);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    char* p = base + off;
+    off += align256(b);
+    return p;
+  };
+  it.pq = take((size_t)it.nq * it.np * cs);
+  it.pqc = reinterpret_cast<double*>(take((size_t)it.nq * it.nc * 16));
+  it.dq = reinterpret_cast<double*>(take((size_t)it.nq * it.nm * it.nm * 16));
+  it.lam = reinterpret_cast<double*>(take((size_t)it.nq * it.nm * 8));
+  it.ev = reinterpret_cast<double*>(take((size_t)it.nq * it.nm * it.nm * 16));
+  it.u = take((size_t)it.nq * it.nm * it.nm * cs);
+  it.G = take((size_t)it.qb * it.ne * it.E * cs);
+  it.Gnu = take((size_t)it.qb * it.ne * it.E * cs);
+  it.W = take((size_t)it.kt * it.qb * it.E * cs);
+  it.lossp = reinterpret_cast<double*>(take((size_t)it.qb * it.kt * 8));
+}
+
+// k points per tile that keep the item's sweep buffers within `cap` bytes
+int32_t k_tile_for(const ItemPlan& it, int32_t qb, int64_t cap) {
+  const double cs = (double)csize(it.sys->g_kind);
+  const double fixed = 2.0 * qb * it.ne * it.E * cs;
+  const double per_k = (double)qb * it.E * cs + 8.0 * qb;
+  if (fixed >= (double)cap) return 0;
+  int64_t kt = (int64_t)(((double)cap - fixed) / per_k);
+  if (kt > it.nk) kt = it.nk;
+  if (kt >= 128) kt -= kt % 64;  // whole 64-row tiles
+  return (int32_t)kt;
+}
+
+void set_shape(ItemPlan& it, int32_t qb, int32_t kt) {
+  it.qb = qb;
+  it.kt = kt;
+  it.cfg_rp = qb >= 128 ? 0 : 1;
+  it.cfg_re = kt >= 128 ? 0 : 1;
+  it.nqb = ceil_div(it.nq, qb);
+  it.nkt = ceil_div(it.nk, kt);
+}
+
+std::string shape_key(int kind, const ItemPlan& it) {
+  char buf[256];
+  snprintf(buf, sizeof(buf), "gfx950|%s|nw%d|nm%d|ne%lld|np%lld|nk%lld|nq%lld", kind == 0 ? "fp64" : "fp32",
+           it.nw, it.nm, (long long)it.ne, (long long)it.np, (long long)it.nk, (long long)it.nq);
+  return buf;
+}
+
+// tuned shapes: one JSON object per line {"key": "...", "qb": n, "kt": n}
+std::map<std::string, std::pair<int, int>> read_cache(const char* path) {
+  std::map<std::string, std::pair<int, int>> m;
+  if (!path) return m;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {
+    const size_t k0 = line.find("\"key\": \"");
+    const size_t q0 = line.find("\"qb\": ");
+    const size_t t0 = line.find("\"kt\": ");
+    if (k0 == std::string::npos || q0 == std::string::npos || t0 == std::string::npos) continue;
+    const size_t k1 = line.find('"', k0 + 8);
+    if (k1 == std::string::npos) continue;
+    m[line.substr(k0 + 8, k1 - k0 - 8)] = {atoi(line.c_str() + q0 + 6), atoi(line.c_str() + t0 + 6)};
+  }
+  return m;
+}
+
+void append_cache(const char* path, const std::string& key, int qb, int kt, double us_per_pair) {
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  f << "{\"key\": \"" << key << "\", \"qb\": " << qb << ", \"kt\": " << kt << ", \"us_per_kpair\": " << us_per_pair
+    << "}\n";
+}
+
+// ---- one unit of one item, launched directly (autotuning) ------------------
+ephw_status unit_direct(ItemPlan& it, int kind, int64_t j, int64_t t, hipStream_t st, uint32_t* status) {
+  const int64_t q0 = j * it.qb, nb = std::min<int64_t>(it.qb, it.nq - q0);
+  const int64_t k0 = t * it.kt, kl = std::min<int64_t>(it.kt, it.nk - k0);
+  const size_t cs = csize(kind);
+  GemmParams rp;
+  rp.M = nb;
+  rp.N = it.ne * it.E;
+  rp.K = it.np;
+  rp.A = static_cast<const char*>(it.pq) + (size_t)q0 * it.np * cs;
+  rp.lda = it.np;
+  rp.B = it.sys->g;
+  rp.ldb = rp.N;
+  rp.C = it.G;
+  rp.ldc = rp.N;
+  EPHW_TRY(cgemm(kind, rp, st));
+  EPHW_TRY(mode_rotate(kind, it.G, static_cast<const char*>(it.u) + (size_t)q0 * it.nm * it.nm * cs, it.Gnu,
+                       it.ne, (int)nb, it.nm, (int64_t)it.nw * it.nw, st));
+  GemmParams re;
+  re.M = kl;
+  re.N = nb * it.E;
+  re.K = it.ne;
+  re.A = static_cast<const char*>(it.ks->pk) + (size_t)k0 * it.ne * cs;
+  re.lda = it.ne;
+  re.B = it.Gnu;
+  re.ldb = re.N;
+  re.C = it.W;
+  re.ldc = re.N;
+  EPHW_TRY(cgemm(kind, re, st));
+  BandRotateArgs br;
+  br.W = it.W;
+  br.Vk = it.ks->vt;
+  br.Vkq = nullptr;
+  br.kq_index = it.in.kq_index + q0 * it.nk;
+  br.nk = it.nk;
+  br.k0 = k0;
+  br.nk_tile = kl;
+  br.qb = (int)nb;
+  br.nm = it.nm;
+  br.nw = it.nw;
+  br.flags = EPHW_OUT_LOSS;
+  br.g_out = nullptr;
+  br.band_sum = nullptr;
+  br.loss_partial = it.lossp;
+  br.loss_seed = 0;
+  br.q_global0 = q0;
+  br.status = status;
+  return band_rotate(kind, br, st);
+}
+
+ephw_status tune_item(ItemPlan& it, int kind, int64_t cap, bool measure, hipStream_t st, uint32_t* status,
+                      double* us_per_kpair) {
+  std::vector<int32_t> cands;
+  for (int32_t qb : {128, 64, 32, 16}) {
+    const int32_t q = (int32_t)std::min<int64_t>(qb, it.nq);
+    if (std::find(cands.begin(), cands.end(), q) == cands.end() && k_tile_for(it, q, cap) >= std::min<int64_t>(16, it.nk))
+      cands.push_back(q);
+  }
+  if (cands.empty()) {
+    set_error("ephw_batch_create: an item does not fit the per-item workspace cap");
+    return EPHW_ENOMEM;
+  }
+  *us_per_kpair = 0.0;
+  if (!measure) {
+    set_shape(it, cands[0], k_tile_for(it, cands[0], cap));
+    return EPHW_OK;
+  }
+  // the largest candidate's buffers serve every candidate
+  int32_t best_q = cands[0];
+  double best = 1e300;
+  size_t need = 0;
+  for (int32_t q : cands) {
+    set_shape(it, q, k_tile_for(it, q, cap));
+    need = std::max(need, it.bytes());
+  }
+  void* tmp = nullptr;
+  EPHW_TRY(dev_alloc(&tmp, need));
+  hipEvent_t a = nullptr, b = nullptr;
+  ephw_status rc = EPHW_OK;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) rc = EPHW_EDEVICE;
+  for (size_t ci = 0; ci < cands.size() && rc == EPHW_OK; ++ci) {
+    const int32_t q = cands[ci];
+    set_shape(it, q, k_tile_for(it, q, cap));
+    carve(it, static_cast<char*>(tmp));
+    // phases and mode vectors of the first q batch (values only matter for timing)
+    rc = phase_matrix(kind, it.in.q, std::min<int64_t>(q, it.nq), it.sys->r_p, it.sys->w_p, it.np, it.pq,
+                      nullptr, st);
+    if (rc == EPHW_OK) rc = hipMemsetAsync(it.u, 0, (size_t)q * it.nm * it.nm * csize(kind), st) == hipSuccess
+                                ? EPHW_OK : EPHW_EDEVICE;
+    for (int rep = 0; rep < 2 && rc == EPHW_OK; ++rep) {
+      (void)hipEventRecord(a, st);
+      rc = unit_direct(it, kind, 0, 0, st, status);
+      (void)hipEventRecord(b, st);
+    }
+    if (rc != EPHW_OK) break;
+    float ms = 0.f;
+    if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+      rc = EPHW_EDEVICE;
+      break;
+    }
+    const double pairs = (double)std::min<int64_t>(q, it.nq) * std::min<int64_t>(it.kt, it.nk);
+    const double us = 1e3 * ms / pairs * 1e3;  // microseconds per 1000 pairs
+    if (us < best) {
+      best = us;
+      best_q = q;
+    }
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipStreamSynchronize(st);
+  (void)hipFree(tmp);
+  if (rc != EPHW_OK) return rc;
+  set_shape(it, best_q, k_tile_for(it, best_q, cap));
+  *us_per_kpair = best;
+  return EPHW_OK;
+}
+
+// ---- descriptor staging ----------------------------------------------------
+struct HostDesc {
+  std::vector<char> bytes;
+  struct Fix {
+    size_t off;
+    Launch* l;
+  };
+  template <typename J>
+  size_t add(const std::vector<J>& v) {
+    const size_t off = align256(bytes.size());
+    bytes.resize(off + v.size() * sizeof(J));
+    memcpy(bytes.data() + off, v.data(), v.size() * sizeof(J));
+    return off;
+  }
+};
+
+ephw_status issue(ephw_batch* bt, hipStream_t st) {
+  uint32_t* status = bt->ctx->status;
+  for (const Launch& l : bt->launches) {
+    switch (l.kind) {
+      case Launch::PHASE: {
+        ItemPlan& it = bt->items[l.item];
+        EPHW_TRY(phase_matrix(bt->kind, it.in.q, it.nq, it.sys->r_p, it.sys->w_p, it.np, it.pq, nullptr, st));
+        EPHW_TRY(phase_matrix(0, it.in.q, it.nq, it.sys->r_c, it.sys->w_c, it.nc, it.pqc, nullptr, st));
+        break;
+      }
+      case Launch::MODEVEC: {
+        ItemPlan& it = bt->items[l.item];
+        EPHW_TRY(mode_vectors(bt->kind, it.ev, it.nq, it.nm, it.sys->ism, it.u, st));
+        break;
+      }
+      case Launch::GEMM:
+        EPHW_TRY(cgemm_grouped(l.prec, static_cast<const GroupProblem*>(l.jobs), l.n, l.count,
+                               (int)std::min<int64_t>(bt->grid_gemm, l.count), st));
+        break;
+      case Launch::EIGH:
+        EPHW_TRY(jacobi_eigh_grouped(static_cast<const EighJob*>(l.jobs), l.n, l.count, status, st));
+        break;
+      case Launch::MODE:
+        EPHW_TRY(mode_rotate_grouped(bt->kind, static_cast<const ModeRotateJob*>(l.jobs), l.n, l.count, l.lds, st));
+        break;
+      case Launch::BAND:
+        EPHW_TRY(band_rotate_grouped(bt->kind, static_cast<const BandRotateJob*>(l.jobs), l.n, l.count, l.lds, st));
+        break;
+      case Launch::SUM:
+        EPHW_TRY(sum_into_grouped(static_cast<const SumJob*>(l.jobs), l.n, st));
+        break;
+    }
+  }
+  return EPHW_OK;
+}
+
+// Builds the launch list of one pass; descriptor arrays are staged in `hd`
+// and their offsets fixed up once the device copy exists.
+void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, size_t>>& fix) {
+  const int kind = bt->kind;
+  const size_t cs = csize(kind);
+  auto push = [&](Launch l, size_t off) {
+    bt->launches.push_back(l);
+    fix.push_back({bt->launches.size() - 1, off});
+  };
+  // q side: phases per item, D(q) GEMMs (one grouped launch), eigensolves (one
+  // grouped launch), mode vectors per item
+  for (size_t i = 0; i < bt->items.size(); ++i) {
+    Launch l;
+    l.kind = Launch::PHASE;
+    l.item = (int)i;
+    bt->launches.push_back(l);
+  }
+  {
+    std::vector<GroupProblem> probs;
+    for (auto& it : bt->items) {
+      GroupProblem p;
+      p.M = it.nq;
+      p.N = (int64_t)it.nm * it.nm;
+      p.K = it.nc;
+      p.A = it.pqc;
+      p.lda = it.nc;
+      p.B = it.sys->c_scaled;
+      p.ldb = p.N;
+      p.C = it.dq;
+      p.ldc = p.N;
+      p.cfg = 1;
+      probs.push_back(p);
+    }
+    Launch l;
+    l.kind = Launch::GEMM;
+    l.prec = 0;
+    l.n = (int)probs.size();
+    l.count = cgemm_grouped_layout(0, probs.data(), l.n);
+    push(l, hd.add(probs));
+  }
+  {
+    std::vector<EighJob> jobs;
+    int64_t base = 0;
+    for (auto& it : bt->items) {
+      EighJob j;
+      j.H = it.dq;
+      j.eps = it.lam;
+      j.V = it.ev;
+      j.n = it.nm;
+      j.count = it.nq;
+      j.block_base = base;
+      base += it.nq;
+      jobs.push_back(j);
+    }
+    Launch l;
+    l.kind = Launch::EIGH;
+    l.n = (int)jobs.size();
+    l.count = base;
+    push(l, hd.add(jobs));
+  }
+  for (size_t i = 0; i < bt->items.size(); ++i) {
+    Launch l;
+    l.kind = Launch::MODEVEC;
+    l.item = (int)i;
+    bt->launches.push_back(l);
+  }
+  // rounds
+  int64_t rounds = 0;
+  for (auto& it : bt->items) rounds = std::max(rounds, it.units());
+  bt->rounds = (int)rounds;
+  for (int64_t r = 0; r < rounds; ++r) {
+    std::vector<GroupProblem> rp, re;
+    std::vector<ModeRotateJob> mj;
+    std::vector<BandRotateJob> bj;
+    std::vector<SumJob> sj;
+    int64_t mblocks = 0, bblocks = 0;
+    size_t mlds = 0, blds = 0;
+    for (auto& it : bt->items) {
+      if (r >= it.units()) continue;
+      const int64_t j = r / it.nkt, t = r % it.nkt;
+      const int64_t q0 = j * it.qb, nb = std::min<int64_t>(it.qb, it.nq - q0);
+      const int64_t k0 = t * it.kt, kl = std::min<int64_t>(it.kt, it.nk - k0);
+      const int64_t nw2 = (int64_t)it.nw * it.nw;
+      if (t == 0) {
+        GroupProblem p;
+        p.M = nb;
+        p.N = it.ne * it.E;
+        p.K = it.np;
+        p.A = static_cast<const char*>(it.pq) + (size_t)q0 * it.np * cs;
+        p.lda = it.np;
+        p.B = it.sys->g;
+        p.ldb = p.N;
+        p.C = it.G;
+        p.ldc = p.N;
+        p.cfg = it.cfg_rp;
+        rp.push_back(p);
+        ModeRotateJob m;
+        m.G = it.G;
+        m.u = static_cast<const char*>(it.u) + (size_t)q0 * it.nm * it.nm * cs;
+        m.Gnu = it.Gnu;
+        m.ne = it.ne;
+        m.nw2 = nw2;
+        m.qb = (int)nb;
+        m.nm = it.nm;
+        m.block_base = mblocks;
+        mblocks += nb * ceil_div(it.ne * nw2, 256);
+        mlds = std::max(mlds, (size_t)it.nm * it.nm * cs);
+        mj.push_back(m);
+      }
+      GroupProblem p;
+      p.M = kl;
+      p.N = nb * it.E;
+      p.K = it.ne;
+      p.A = static_cast<const char*>(it.ks->pk) + (size_t)k0 * it.ne * cs;
+      p.lda = it.ne;
+      p.B = it.Gnu;
+      p.ldb = p.N;
+      p.C = it.W;
+      p.ldc = p.N;
+      p.cfg = it.cfg_re;
+      re.push_back(p);
+      BandRotateJob b;
+      BandRotateArgs& br = b.args;
+      br.W = it.W;
+      br.Vk = it.ks->vt;
+      br.Vkq = nullptr;
+      br.kq_index = it.in.kq_index + q0 * it.nk;
+      br.nk = it.nk;
+      br.k0 = k0;
+      br.nk_tile = kl;
+      br.qb = (int)nb;
+      br.nm = it.nm;
+      br.nw = it.nw;
+      br.flags = it.in.flags;
+      br.g_out = (it.in.flags & EPHW_OUT_G) ? static_cast<char*>(it.in.g_out) + (size_t)q0 * it.nk * it.E * cs
+                                            : nullptr;
+      br.band_sum = (it.in.flags & EPHW_OUT_BAND_SUM) ? it.in.band_sum + q0 * it.nk * it.nm : nullptr;
+      br.loss_partial = (it.in.flags & EPHW_OUT_LOSS) ? it.lossp : nullptr;
+      br.loss_seed = it.in.loss_seed;
+      br.q_global0 = q0;
+      br.status = bt->ctx->status;
+      b.nuc = it.nuc;
+      b.block_base = bblocks;
+      bblocks += nb * kl;
+      blds = std::max(blds, it.lds_band);
+      bj.push_back(b);
+      if (it.in.flags & EPHW_OUT_LOSS) sj.push_back(SumJob{it.lossp, nb * kl, it.in.loss});
+    }
+    if (!rp.empty()) {
+      Launch l;
+      l.kind = Launch::GEMM;
+      l.prec = kind;
+      l.n = (int)rp.size();
+      l.count = cgemm_grouped_layout(kind, rp.data(), l.n);
+      push(l, hd.add(rp));
+      Launch m;
+      m.kind = Launch::MODE;
+      m.n = (int)mj.size();
+      m.count = mblocks;
+      m.lds = mlds;
+      push(m, hd.add(mj));
+    }
+    {
+      Launch l;
+      l.kind = Launch::GEMM;
+      l.prec = kind;
+      l.n = (int)re.size();
+      l.count = cgemm_grouped_layout(kind, re.data(), l.n);
+      push(l, hd.add(re));
+      Launch b;
+      b.kind = Launch::BAND;
+      b.n = (int)bj.size();
+      b.count = bblocks;
+      b.lds = blds;
+      push(b, hd.add(bj));
+    }
+    if (!sj.empty()) {
+      Launch l;
+      l.kind = Launch::SUM;
+      l.n = (int)sj.size();
+      l.count = (int64_t)sj.size();
+      push(l, hd.add(sj));
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+ephw_status ephw_batch_free(ephw_batch* b) {
+  if (!b) return EPHW_OK;
+  (void)hipDeviceSynchronize();
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->ws) (void)hipFree(b->ws);
+  if (b->desc) (void)hipFree(b->desc);
+  delete b;
+  return EPHW_OK;
+}
+
+ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32_t n,
+                              const ephw_batch_options* opt, void* stream, ephw_batch** out) {
+  if (!ctx || !items || n < 1 || !out) {
+    set_error("ephw_batch_create: need a context, n >= 1 items and an output handle");
+    return EPHW_EINVAL;
+  }
+  *out = nullptr;
+  ephw_batch_options o{};
+  o.use_graph = 1;
+  if (opt) o = *opt;
+  const int64_t cap = o.item_workspace_bytes > 0 ? o.item_workspace_bytes : ((int64_t)1 << 30);
+  hipStream_t st = as_stream(stream);
+  ephw_batch* bt = new ephw_batch();
+  bt->ctx = ctx;
+  auto fail = [&](ephw_status e) {
+    ephw_batch_free(bt);
+    return e;
+  };
+  for (int32_t i = 0; i < n; ++i) {
+    const ephw_batch_item& in = items[i];
+    if (!in.ks || (!in.q && in.nq > 0) || in.nq < 0 || !in.kq_index) {
+      set_error("ephw_batch_create: item " + std::to_string(i) + " needs a k-set, a q list and a k+q index");
+      return fail(EPHW_EINVAL);
+    }
+    const uint32_t known = EPHW_OUT_G | EPHW_OUT_BAND_SUM | EPHW_OUT_LOSS;
+    if ((in.flags & ~known) || !(in.flags & known) || ((in.flags & EPHW_OUT_G) && !in.g_out) ||
+        ((in.flags & EPHW_OUT_BAND_SUM) && !in.band_sum) || ((in.flags & EPHW_OUT_LOSS) && !in.loss)) {
+      set_error("ephw_batch_create: item " + std::to_string(i) + " has inconsistent output flags/buffers");
+      return fail(EPHW_EINVAL);
+    }
+    ItemPlan it;
+    it.in = in;
+    it.ks = in.ks;
+    it.sys = in.ks->sys;
+    const int kind = prec_kind(in.ks->prec);
+    if (i == 0) bt->kind = kind;
+    if (kind != bt->kind || in.ks->prec == EPHW_FP32_SPLIT) {
+      set_error("ephw_batch_create: all items must share one precision (FP64 or FP32)");
+      return fail(EPHW_EINVAL);
+    }
+    if (it.sys->ctx != ctx) {
+      set_error("ephw_batch_create: item system belongs to another context");
+      return fail(EPHW_EINVAL);
+    }
+    it.nw = it.sys->nw;
+    it.nm = it.sys->nm;
+    if (it.nw > 32 || it.nm > 24) {
+      set_error("ephw_batch_create: batched items need nw <= 32 and nm <= 24");
+      return fail(EPHW_EUNSUPPORTED);
+    }
+    it.ne = it.sys->ne;
+    it.np = it.sys->np;
+    it.nc = it.sys->nc;
+    it.nk = in.ks->nk;
+    it.nq = in.nq;
+    it.E = (int64_t)it.nm * it.nw * it.nw;
+    it.nuc = band_rotate_modes_per_chunk(kind, it.nw, it.nm, &it.lds_band);
+    bt->items.push_back(it);
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && cus > 0)
+    bt->grid_gemm = cus;
+  // shapes: cache, else tune (or heuristics)
+  auto cache = read_cache(o.tune_cache);
+  for (auto& it : bt->items) {
+    if (it.nq == 0) {  // nothing to do: smallest buffers, no units
+      set_shape(it, 1, 1);
+      continue;
+    }
+    const std::string key = shape_key(bt->kind, it);
+    auto f = cache.find(key);
+    if (f != cache.end() && f->second.first > 0 && f->second.second > 0 &&
+        k_tile_for(it, f->second.first, cap) >= f->second.second) {
+      set_shape(it, f->second.first, f->second.second);
+      continue;
+    }
+    double us = 0.0;
+    ephw_status e = tune_item(it, bt->kind, cap, o.tune != 0, st, ctx->status, &us);
+    if (e != EPHW_OK) return fail(e);
+    if (o.tune) {
+      append_cache(o.tune_cache, key, it.qb, it.kt, us);
+      cache[key] = {it.qb, it.kt};
+    }
+  }
+  // workspace
+  size_t total = 0;
+  for (auto& it : bt->items) total += it.bytes();
+  ephw_status e = dev_alloc(&bt->ws, total);
+  if (e != EPHW_OK) return fail(e);
+  bt->ws_bytes = total;
+  {
+    size_t off = 0;
+    for (auto& it : bt->items) {
+      carve(it, static_cast<char*>(bt->ws) + off);
+      off += it.bytes();
+    }
+  }
+  // launch list + descriptors
+  HostDesc hd;
+  std::vector<std::pair<size_t, size_t>> fix;
+  build_launches(bt, hd, fix);
+  if ((e = dev_alloc(&bt->desc, hd.bytes.size())) != EPHW_OK) return fail(e);
+  bt->desc_bytes = hd.bytes.size();
+  if (hipMemcpy(bt->desc, hd.bytes.data(), hd.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
+    set_error("ephw_batch_create: descriptor upload failed");
+    return fail(EPHW_EDEVICE);
+  }
+  for (auto& fx : fix) bt->launches[fx.first].jobs = static_cast<char*>(bt->desc) + fx.second;
+  // large-LDS band rotations need the attribute before any capture
+  size_t blds = 0;
+  for (auto& l : bt->launches)
+    if (l.kind == Launch::BAND) blds = std::max(blds, l.lds);
+  if ((e = band_rotate_grouped_prepare(bt->kind, blds)) != EPHW_OK) return fail(e);
+  bt->use_graph = o.use_graph != 0;
+  if (bt->use_graph) {
+    if (hipStreamCreateWithFlags(&bt->cap, hipStreamNonBlocking) != hipSuccess) {
+      set_error("ephw_batch_create: capture stream");
+      return fail(EPHW_EDEVICE);
+    }
+    if (hipStreamBeginCapture(bt->cap, hipStreamCaptureModeRelaxed) != hipSuccess) {
+      set_error("ephw_batch_create: hipStreamBeginCapture failed");
+      return fail(EPHW_EDEVICE);
+    }
+    ephw_status ie = issue(bt, bt->cap);
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(bt->cap, &g);
+    if (ie != EPHW_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(ie);
+    }
+    if (ce != hipSuccess || !g) {
+      set_error(std::string("ephw_batch_create: capture failed: ") + hipGetErrorString(ce));
+      return fail(EPHW_EDEVICE);
+    }
+    bt->graph = g;
+    if (hipGraphInstantiate(&bt->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      set_error("ephw_batch_create: hipGraphInstantiate failed");
+      return fail(EPHW_EDEVICE);
+    }
+  }
+  *out = bt;
+  return EPHW_OK;
+}
+
+ephw_status ephw_batch_run(ephw_batch* b, void* stream) {
+  if (!b) {
+    set_error("ephw_batch_run: batch is NULL");
+    return EPHW_EINVAL;
+  }
+  hipStream_t st = as_stream(stream);
+  if (b->exec) {
+    EPHW_HIP(hipGraphLaunch(b->exec, st));
+    return EPHW_OK;
+  }
+  return issue(b, st);
+}
+
+ephw_status ephw_batch_shape(const ephw_batch* b, int32_t i, int32_t* q_batch, int32_t* k_tile, int32_t* cfg_rp,
+                             int32_t* cfg_re) {
+  if (!b || i < 0 || i >= (int32_t)b->items.size()) {
+    set_error("ephw_batch_shape: no such item");
+    return EPHW_EINVAL;
+  }
+  const ItemPlan& it = b->items[i];
+  if (q_batch) *q_batch = it.qb;
+  if (k_tile) *k_tile = it.kt;
+  if (cfg_rp) *cfg_rp = it.cfg_rp;
+  if (cfg_re) *cfg_re = it.cfg_re;
+  return EPHW_OK;
+}
+
+ephw_status ephw_batch_stats(const ephw_batch* b, int32_t* rounds, int32_t* launches) {
+  if (!b) {
+    set_error("ephw_batch_stats: batch is NULL");
+    return EPHW_EINVAL;
+  }
+  int32_t nl = 0;
+  for (auto& l : b->launches) nl += (l.kind == Launch::PHASE) ? 2 : 1;
+  if (rounds) *rounds = b->rounds;
+  if (launches) *launches = nl;
+  return EPHW_OK;
+}
+
+}  // extern "C"

@@ -76,6 +76,6 @@ void set_error(const std::string& msg);
 
 #define EPHW_CHECK_LAUNCH() EPHW_HIP(hipGetLastError())
 
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 }  // namespace ephw

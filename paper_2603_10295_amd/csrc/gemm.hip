@@ -55,50 +55,58 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t id, int64_t n) {
   return (xcd < r) ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
+// One GEMM problem as seen by a tile: operand pointers already offset to the
+// batch entry, sizes and leading dimensions in complex elements.
+template <typename T>
+struct TileJob {
+  const T* A;
+  const T* Alo;
+  const T* B;
+  T* C;
+  int64_t M, N, K, lda, ldb, ldc;
+  T sa, sb;          // -1 conjugates the operand's imaginary part
+  bool accumulate;
+};
+
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool SPLIT>
+struct TileShape {
+  static constexpr int NT = 64 * WM * WN;
+  static constexpr int PAD = (sizeof(T) == 4) ? 4 : 2;
+  static constexpr int NA = SPLIT ? 4 : 2;
+  static constexpr size_t a_elems = (size_t)NA * BK * (BM + PAD);
+  static constexpr size_t b_elems = (size_t)2 * BK * (BN + PAD);
+  static constexpr size_t smem_elems = a_elems + b_elems;
+};
+
+// Computes the BM x BN tile at (m0, n0) of job j with the workgroup's
+// NT threads; `smem` holds TileShape::smem_elems values of T.
 template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SPLIT>
-__global__ void __launch_bounds__(64 * WM * WN)
-    cgemm_kernel(GemmParams p, int64_t tiles_m, int64_t tiles_n) {
-  constexpr int NT = 64 * WM * WN;
+__device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64_t n0, T* smem) {
+  using S = TileShape<T, BM, BN, BK, WM, WN, SPLIT>;
+  constexpr int NT = S::NT;
   constexpr int TM = BM / WM, TN = BN / WN;
   constexpr int FM = TM / 16, FN = TN / 16;
-  constexpr int PAD = (sizeof(T) == 4) ? 4 : 2;
-  constexpr int NA = SPLIT ? 4 : 2;
+  constexpr int PAD = S::PAD;
   constexpr int AE = BM * BK / NT, BE = BK * BN / NT;
+  constexpr int LA = BM + PAD, LB = BN + PAD;   // LDS row lengths
   static_assert(BM * BK % NT == 0 && BK * BN % NT == 0, "tile not divisible by threads");
   static_assert(TM % 16 == 0 && TN % 16 == 0 && BK % 4 == 0, "bad tile");
   using V4 = typename Mfma<T>::v4;
+  // planes: As[0] re, As[1] im (conj applied), As[2]/As[3] low parts; Bs[0] re, Bs[1] im
+  T* As = smem;
+  T* Bs = smem + S::a_elems;
+  auto AS = [&](int plane, int k, int m) -> T& { return As[(plane * BK + k) * LA + m]; };
+  auto BS = [&](int plane, int k, int n) -> T& { return Bs[(plane * BK + k) * LB + n]; };
 
-  __shared__ T As[NA][BK][BM + PAD];
-  __shared__ T Bs[2][BK][BN + PAD];
-
-  // --- tile coordinates ---------------------------------------------------
-  const int64_t ntiles = tiles_m * tiles_n;
-  const int64_t logical = xcd_remap(blockIdx.x, ntiles);
-  const int64_t per_group = (int64_t)kGroupM * tiles_n;
-  const int64_t group = logical / per_group;
-  const int64_t first_m = group * kGroupM;
-  const int64_t gsize = (tiles_m - first_m) < kGroupM ? (tiles_m - first_m) : kGroupM;
-  const int64_t in_group = logical % per_group;
-  const int64_t tm = first_m + in_group % gsize;
-  const int64_t tn = in_group / gsize;
-  const int64_t m0 = tm * BM, n0 = tn * BN;
-
-  const int64_t b = p.batch_base + blockIdx.y;
-  const T* A = static_cast<const T*>(p.A) + 2 * (p.offA ? p.offA[b] : b * p.strideA);
-  const T* Alo = SPLIT ? static_cast<const T*>(p.A_lo) + 2 * (p.offA ? p.offA[b] : b * p.strideA)
-                       : nullptr;
-  const T* B = static_cast<const T*>(p.B) + 2 * (p.offB ? p.offB[b] : b * p.strideB);
-  T* C = static_cast<T*>(p.C) + 2 * (p.offC ? p.offC[b] : b * p.strideC);
-  const int64_t M = p.M, N = p.N, K = p.K;
-  const T sa = p.conjA ? T(-1) : T(1);
-  const T sb = p.conjB ? T(-1) : T(1);
-
+  const T* A = j.A;
+  const T* Alo = j.Alo;
+  const T* B = j.B;
+  const int64_t M = j.M, N = j.N, K = j.K;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
 
-  // --- register staging -----------------------------------------------------
   T ra[AE][2], rb[BE][2], rl[SPLIT ? AE : 1][2];
 
   auto load = [&](int64_t k0) {
@@ -110,7 +118,7 @@ __global__ void __launch_bounds__(64 * WM * WN)
       const int64_t gm = m0 + mm, gk = k0 + kk;
       T re = 0, im = 0, lre = 0, lim = 0;
       if (gm < M && gk < K) {
-        const int64_t off = TA ? gk * p.lda + gm : gm * p.lda + gk;
+        const int64_t off = TA ? gk * j.lda + gm : gm * j.lda + gk;
         re = A[2 * off];
         im = A[2 * off + 1];
         if (SPLIT) { lre = Alo[2 * off]; lim = Alo[2 * off + 1]; }
@@ -127,7 +135,7 @@ __global__ void __launch_bounds__(64 * WM * WN)
       const int64_t gn = n0 + nn, gk = k0 + kk;
       T re = 0, im = 0;
       if (gn < N && gk < K) {
-        const int64_t off = TB ? gn * p.ldb + gk : gk * p.ldb + gn;
+        const int64_t off = TB ? gn * j.ldb + gk : gk * j.ldb + gn;
         re = B[2 * off];
         im = B[2 * off + 1];
       }
@@ -141,17 +149,17 @@ __global__ void __launch_bounds__(64 * WM * WN)
       const int e = tid + i * NT;
       int mm, kk;
       if (TA) { kk = e / BM; mm = e % BM; } else { mm = e / BK; kk = e % BK; }
-      As[0][kk][mm] = ra[i][0];
-      As[1][kk][mm] = sa * ra[i][1];
-      if (SPLIT) { As[2][kk][mm] = rl[i][0]; As[3][kk][mm] = sa * rl[i][1]; }
+      AS(0, kk, mm) = ra[i][0];
+      AS(1, kk, mm) = j.sa * ra[i][1];
+      if (SPLIT) { AS(2, kk, mm) = rl[i][0]; AS(3, kk, mm) = j.sa * rl[i][1]; }
     }
 #pragma unroll
     for (int i = 0; i < BE; ++i) {
       const int e = tid + i * NT;
       int nn, kk;
       if (TB) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }
-      Bs[0][kk][nn] = rb[i][0];
-      Bs[1][kk][nn] = sb * rb[i][1];
+      BS(0, kk, nn) = rb[i][0];
+      BS(1, kk, nn) = j.sb * rb[i][1];
     }
   };
 
@@ -159,12 +167,12 @@ __global__ void __launch_bounds__(64 * WM * WN)
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      acc_r[i][j] = V4{0, 0, 0, 0};
-      acc_i[i][j] = V4{0, 0, 0, 0};
+    for (int jj = 0; jj < FN; ++jj) {
+      acc_r[i][jj] = V4{0, 0, 0, 0};
+      acc_i[i][jj] = V4{0, 0, 0, 0};
     }
 
-  const int lrow = lane >> 4;   // k row inside one MFMA (0..3)
+  const int lrow = lane >> 4;   // k row inside one MFMA (0..3); also the lane group
   const int lcol = lane & 15;   // m (A) or n (B) inside one 16-block
 
   load(0);
@@ -179,39 +187,39 @@ __global__ void __launch_bounds__(64 * WM * WN)
       T ar[FM], ai[FM], nai[FM], br[FN], bi[FN];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
-        ar[i] = As[0][kr][wm * TM + i * 16 + lcol];
-        ai[i] = As[1][kr][wm * TM + i * 16 + lcol];
+        ar[i] = AS(0, kr, wm * TM + i * 16 + lcol);
+        ai[i] = AS(1, kr, wm * TM + i * 16 + lcol);
         nai[i] = -ai[i];
       }
 #pragma unroll
-      for (int j = 0; j < FN; ++j) {
-        br[j] = Bs[0][kr][wn * TN + j * 16 + lcol];
-        bi[j] = Bs[1][kr][wn * TN + j * 16 + lcol];
+      for (int jj = 0; jj < FN; ++jj) {
+        br[jj] = BS(0, kr, wn * TN + jj * 16 + lcol);
+        bi[jj] = BS(1, kr, wn * TN + jj * 16 + lcol);
       }
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-          acc_r[i][j] = Mfma<T>::op(ar[i], br[j], acc_r[i][j]);
-          acc_r[i][j] = Mfma<T>::op(nai[i], bi[j], acc_r[i][j]);
-          acc_i[i][j] = Mfma<T>::op(ar[i], bi[j], acc_i[i][j]);
-          acc_i[i][j] = Mfma<T>::op(ai[i], br[j], acc_i[i][j]);
+        for (int jj = 0; jj < FN; ++jj) {
+          acc_r[i][jj] = Mfma<T>::op(ar[i], br[jj], acc_r[i][jj]);
+          acc_r[i][jj] = Mfma<T>::op(nai[i], bi[jj], acc_r[i][jj]);
+          acc_i[i][jj] = Mfma<T>::op(ar[i], bi[jj], acc_i[i][jj]);
+          acc_i[i][jj] = Mfma<T>::op(ai[i], br[jj], acc_i[i][jj]);
         }
       if (SPLIT) {
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
-          ar[i] = As[2][kr][wm * TM + i * 16 + lcol];
-          ai[i] = As[3][kr][wm * TM + i * 16 + lcol];
+          ar[i] = AS(2, kr, wm * TM + i * 16 + lcol);
+          ai[i] = AS(3, kr, wm * TM + i * 16 + lcol);
           nai[i] = -ai[i];
         }
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
-          for (int j = 0; j < FN; ++j) {
-            acc_r[i][j] = Mfma<T>::op(ar[i], br[j], acc_r[i][j]);
-            acc_r[i][j] = Mfma<T>::op(nai[i], bi[j], acc_r[i][j]);
-            acc_i[i][j] = Mfma<T>::op(ar[i], bi[j], acc_i[i][j]);
-            acc_i[i][j] = Mfma<T>::op(ai[i], br[j], acc_i[i][j]);
+          for (int jj = 0; jj < FN; ++jj) {
+            acc_r[i][jj] = Mfma<T>::op(ar[i], br[jj], acc_r[i][jj]);
+            acc_r[i][jj] = Mfma<T>::op(nai[i], bi[jj], acc_r[i][jj]);
+            acc_i[i][jj] = Mfma<T>::op(ar[i], bi[jj], acc_i[i][jj]);
+            acc_i[i][jj] = Mfma<T>::op(ai[i], br[jj], acc_i[i][jj]);
           }
       }
     }
@@ -226,20 +234,120 @@ __global__ void __launch_bounds__(64 * WM * WN)
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < FN; ++j) {
-      const int64_t col = n0 + wn * TN + j * 16 + lcol;
+    for (int jj = 0; jj < FN; ++jj) {
+      const int64_t col = n0 + wn * TN + jj * 16 + lcol;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int64_t row = m0 + wm * TM + i * 16 + Mfma<T>::row(lrow, v);
         if (row < M && col < N) {
-          T* c = C + 2 * (row * p.ldc + col);
-          T re = acc_r[i][j][v], im = acc_i[i][j][v];
-          if (p.accumulate) { re += c[0]; im += c[1]; }
+          T* c = j.C + 2 * (row * j.ldc + col);
+          T re = acc_r[i][jj][v], im = acc_i[i][jj][v];
+          if (j.accumulate) { re += c[0]; im += c[1]; }
           c[0] = re;
           c[1] = im;
         }
       }
     }
+}
+
+// tile (tm, tn) of logical tile index t: groups of kGroupM tile-rows
+__device__ __forceinline__ void tile_coords(int64_t t, int64_t tiles_m, int64_t tiles_n, int64_t* tm,
+                                            int64_t* tn) {
+  const int64_t per_group = (int64_t)kGroupM * tiles_n;
+  const int64_t group = t / per_group;
+  const int64_t first_m = group * kGroupM;
+  const int64_t gsize = (tiles_m - first_m) < kGroupM ? (tiles_m - first_m) : kGroupM;
+  const int64_t in_group = t % per_group;
+  *tm = first_m + in_group % gsize;
+  *tn = in_group / gsize;
+}
+
+template <typename T>
+__device__ __forceinline__ TileJob<T> job_of(const GemmParams& p, int64_t b) {
+  const int64_t oa = p.offA ? p.offA[b] : b * p.strideA;
+  const int64_t ob = p.offB ? p.offB[b] : b * p.strideB;
+  const int64_t oc = p.offC ? p.offC[b] : b * p.strideC;
+  TileJob<T> j;
+  j.A = static_cast<const T*>(p.A) + 2 * oa;
+  j.Alo = p.A_lo ? static_cast<const T*>(p.A_lo) + 2 * oa : nullptr;
+  j.B = static_cast<const T*>(p.B) + 2 * ob;
+  j.C = static_cast<T*>(p.C) + 2 * oc;
+  j.M = p.M;
+  j.N = p.N;
+  j.K = p.K;
+  j.lda = p.lda;
+  j.ldb = p.ldb;
+  j.ldc = p.ldc;
+  j.sa = p.conjA ? T(-1) : T(1);
+  j.sb = p.conjB ? T(-1) : T(1);
+  j.accumulate = p.accumulate;
+  return j;
+}
+
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SPLIT>
+__global__ void __launch_bounds__(64 * WM * WN)
+    cgemm_kernel(GemmParams p, int64_t tiles_m, int64_t tiles_n) {
+  using S = TileShape<T, BM, BN, BK, WM, WN, SPLIT>;
+  __shared__ T smem[S::smem_elems];
+  const int64_t logical = xcd_remap(blockIdx.x, tiles_m * tiles_n);
+  int64_t tm, tn;
+  tile_coords(logical, tiles_m, tiles_n, &tm, &tn);
+  const TileJob<T> j = job_of<T>(p, p.batch_base + blockIdx.y);
+  gemm_tile<T, BM, BN, BK, WM, WN, TA, TB, SPLIT>(j, tm * BM, tn * BN, smem);
+}
+
+// Tile shapes of the grouped kernel: cfg 0 is the shape of the plain kernel,
+// cfg 1 a 64x64 tile for small problems.  Both use 4 waves.
+template <typename T>
+struct GroupCfg;
+template <>
+struct GroupCfg<float> {
+  using L = TileShape<float, 128, 128, 16, 2, 2, false>;
+  using S = TileShape<float, 64, 64, 16, 2, 2, false>;
+  static constexpr int LM = 128, LN = 128;
+};
+template <>
+struct GroupCfg<double> {
+  using L = TileShape<double, 128, 64, 16, 2, 2, false>;
+  using S = TileShape<double, 64, 64, 16, 2, 2, false>;
+  static constexpr int LM = 128, LN = 64;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    cgemm_grouped_kernel(const GroupProblem* __restrict__ probs, int n, int64_t total) {
+  using G = GroupCfg<T>;
+  constexpr size_t kSmem = G::L::smem_elems > G::S::smem_elems ? G::L::smem_elems : G::S::smem_elems;
+  __shared__ T smem[kSmem];
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (probs[mid].tile_base <= t) lo = mid; else hi = mid - 1;
+    }
+    const GroupProblem& P = probs[lo];
+    int64_t tm, tn;
+    tile_coords(t - P.tile_base, P.tiles_m, P.tiles_n, &tm, &tn);
+    TileJob<T> j;
+    j.A = static_cast<const T*>(P.A);
+    j.Alo = nullptr;
+    j.B = static_cast<const T*>(P.B);
+    j.C = static_cast<T*>(P.C);
+    j.M = P.M;
+    j.N = P.N;
+    j.K = P.K;
+    j.lda = P.lda;
+    j.ldb = P.ldb;
+    j.ldc = P.ldc;
+    j.sa = T(1);
+    j.sb = T(1);
+    j.accumulate = false;
+    if (P.cfg == 0)
+      gemm_tile<T, G::LM, G::LN, 16, 2, 2, false, false, false>(j, tm * G::LM, tn * G::LN, smem);
+    else
+      gemm_tile<T, 64, 64, 16, 2, 2, false, false, false>(j, tm * 64, tn * 64, smem);
+    __syncthreads();
+  }
 }
 
 template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SPLIT>
@@ -271,6 +379,44 @@ ephw_status dispatch_trans(const GemmParams& p, hipStream_t s) {
 }
 
 }  // namespace
+
+void cgemm_tile_shape(int prec, int cfg, int* bm, int* bn) {
+  if (cfg != 0) {
+    *bm = 64;
+    *bn = 64;
+  } else if (prec == 0) {
+    *bm = 128;
+    *bn = 64;
+  } else {
+    *bm = 128;
+    *bn = 128;
+  }
+}
+
+int64_t cgemm_grouped_layout(int prec, GroupProblem* probs, int n) {
+  int64_t base = 0;
+  for (int i = 0; i < n; ++i) {
+    int bm, bn;
+    cgemm_tile_shape(prec, probs[i].cfg, &bm, &bn);
+    probs[i].tiles_m = (probs[i].M > 0 && probs[i].K > 0) ? ceil_div(probs[i].M, bm) : 0;
+    probs[i].tiles_n = (probs[i].N > 0 && probs[i].K > 0) ? ceil_div(probs[i].N, bn) : 0;
+    probs[i].tile_base = base;
+    base += probs[i].tiles_m * probs[i].tiles_n;
+  }
+  return base;
+}
+
+ephw_status cgemm_grouped(int prec, const GroupProblem* d_probs, int n, int64_t total_tiles, int grid,
+                          hipStream_t stream) {
+  if (n <= 0 || total_tiles <= 0) return EPHW_OK;
+  if (grid <= 0) grid = 1;
+  if (prec == 0)
+    hipLaunchKernelGGL(cgemm_grouped_kernel<double>, dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles);
+  else
+    hipLaunchKernelGGL(cgemm_grouped_kernel<float>, dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles);
+  EPHW_CHECK_LAUNCH();
+  return EPHW_OK;
+}
 
 ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream) {
   if (p.M <= 0 || p.N <= 0 || p.batch <= 0) return EPHW_OK;

@@ -1,0 +1,157 @@
+// Internal handle types and helpers shared by the libephw host sources.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "gemm.h"
+#include "kernels.h"
+
+namespace ephw {
+
+// grow-only device buffer; reallocation waits for the device to go idle
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+inline ephw_status dev_alloc(void** p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+    *p = nullptr;
+    return EPHW_ENOMEM;
+  }
+  return EPHW_OK;
+}
+
+inline ephw_status grow(DevBuf& b, size_t bytes, int64_t* owner_bytes) {
+  if (b.bytes >= bytes && b.p) return EPHW_OK;
+  if (b.p) {
+    EPHW_HIP(hipDeviceSynchronize());
+    EPHW_HIP(hipFree(b.p));
+    *owner_bytes -= (int64_t)b.bytes;
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  EPHW_TRY(dev_alloc(&b.p, bytes));
+  b.bytes = bytes;
+  *owner_bytes += (int64_t)bytes;
+  return EPHW_OK;
+}
+
+template <typename X>
+inline ephw_status upload(X** dst, const X* src, size_t count, int64_t* owner_bytes) {
+  void* p = nullptr;
+  EPHW_TRY(dev_alloc(&p, count * sizeof(X)));
+  *owner_bytes += (int64_t)(count * sizeof(X));
+  EPHW_HIP(hipMemcpy(p, src, count * sizeof(X), hipMemcpyHostToDevice));
+  *dst = static_cast<X*>(p);
+  return EPHW_OK;
+}
+
+inline int prec_kind(int32_t prec) { return prec == EPHW_FP64 ? 0 : 1; }
+inline size_t csize(int kind) { return kind == 0 ? 16 : 8; }
+
+}  // namespace ephw
+
+using namespace ephw;
+
+struct ephw_ctx {
+  int device = 0;
+  uint32_t* status = nullptr;
+};
+
+enum WsSlot {
+  WS_PQ, WS_PQ_LO, WS_PQH, WS_PQC, WS_D, WS_LAM, WS_E, WS_U, WS_G, WS_GNU, WS_W, WS_BQ, WS_HKQ,
+  WS_EKQ, WS_VKQ64, WS_VKQ, WS_JWORK, WS_LOSS, WS_PH, WS_HK, WS_EPS, WS_V64, WS_COUNT
+};
+
+// HIP-event brackets around the stages of a call, summed on request
+struct Profiler {
+  bool on = false;
+  struct Rec {
+    int stage;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+
+struct ephw_system {
+  ephw_ctx* ctx = nullptr;
+  Profiler prof;
+  int nw = 0, na = 0, nm = 0;
+  int64_t ne = 0, np = 0, nh = 0, nc = 0;
+  int g_kind = 0;  // 0 = c128, 1 = c64
+  int32_t *r_e = nullptr, *r_p = nullptr, *r_h = nullptr, *r_c = nullptr;
+  double *w_e = nullptr, *w_p = nullptr, *w_h = nullptr, *w_c = nullptr;
+  double* h_r = nullptr;      // c128 [nh][nw][nw]
+  double* c_scaled = nullptr; // c128 [nc][nm][nm] = C / sqrt(M M')
+  double* ism = nullptr;      // [nm] 1/sqrt(M_kappa) per mode index
+  void* g = nullptr;
+  int32_t q_batch = 0;
+  int64_t bytes = 0;
+  DevBuf ws[WS_COUNT];
+};
+
+struct ephw_kset {
+  ephw_system* sys = nullptr;
+  int64_t nk = 0;
+  int32_t prec = 0;
+  int64_t bytes = 0;
+  double* k = nullptr;      // [nk][3]
+  void* pk = nullptr;       // T [nk][ne]
+  void* pk_lo = nullptr;    // float [nk][ne] (split)
+  double* pkh = nullptr;    // c128 [nk][nh]
+  double* eps = nullptr;    // [nk][nw]
+  double* v64 = nullptr;    // c128 [nk][nw][nw]
+  void* vt = nullptr;       // T [nk][nw][nw]
+};
+
+// Records a start event on construction and a stop event on destruction
+// when the system's profiler is on.
+struct Stage {
+  Profiler* p;
+  int stage;
+  hipStream_t st;
+  hipEvent_t a = nullptr;
+  Stage(ephw_system* s, int stage_, hipStream_t st_) : p(&s->prof), stage(stage_), st(st_) {
+    if (p->on) {
+      a = p->get();
+      if (a) (void)hipEventRecord(a, st);
+    }
+  }
+  ~Stage() {
+    if (p->on && a) {
+      hipEvent_t b = p->get();
+      if (b) {
+        (void)hipEventRecord(b, st);
+        p->recs.push_back({stage, a, b});
+      } else {
+        p->pool.push_back(a);
+      }
+    }
+  }
+};
+
+inline void* wsp(ephw_system* s, WsSlot slot) { return s->ws[slot].p; }
+
+inline ephw_status ws_need(ephw_system* s, WsSlot slot, size_t bytes) {
+  return grow(s->ws[slot], bytes, &s->bytes);
+}
+
+inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }
+

@@ -181,15 +181,13 @@ __device__ void jacobi_finish(const double* Ar, const double* Vr, const double* 
 
 constexpr int kSmallN = 32;
 
-__global__ void __launch_bounds__(64)
-    jacobi_small_kernel(const double* __restrict__ H, int n, double* __restrict__ eps,
-                        double* __restrict__ V, uint32_t* status) {
+__device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, int n, double* __restrict__ eps,
+                                                  double* __restrict__ V, uint32_t* status, int64_t b) {
   __shared__ double Ar[kSmallN * kSmallN], Ai[kSmallN * kSmallN];
   __shared__ double Vr[kSmallN * kSmallN], Vi[kSmallN * kSmallN];
   __shared__ double rc[kSmallN / 2], rs[kSmallN / 2], rer[kSmallN / 2], rei[kSmallN / 2];
   __shared__ int rp[kSmallN / 2], rq[kSmallN / 2], perm[kSmallN];
   __shared__ double phr[kSmallN], phi[kSmallN], red[1];
-  const int64_t b = blockIdx.x;
   const double* h = H + 2 * b * n * n;
   for (int e = threadIdx.x; e < n * n; e += 64) {
     Ar[e] = h[2 * e];
@@ -199,6 +197,24 @@ __global__ void __launch_bounds__(64)
   const bool ok = jacobi_core<64>(Ar, Ai, Vr, Vi, n, rc, rs, rer, rei, rp, rq, red);
   if (!ok && threadIdx.x == 0) atomicOr(status, kStatusNoConv);
   jacobi_finish<64>(Ar, Vr, Vi, n, perm, phr, phi, eps + b * n, V + 2 * b * n * n);
+}
+
+__global__ void __launch_bounds__(64)
+    jacobi_small_kernel(const double* __restrict__ H, int n, double* __restrict__ eps,
+                        double* __restrict__ V, uint32_t* status) {
+  jacobi_small_body(H, n, eps, V, status, blockIdx.x);
+}
+
+__global__ void __launch_bounds__(64) jacobi_grouped_kernel(const EighJob* __restrict__ jobs, int njobs,
+                                                             uint32_t* status) {
+  const int64_t b = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block_base <= b) lo = mid; else hi = mid - 1;
+  }
+  const EighJob& j = jobs[lo];
+  jacobi_small_body(j.H, j.n, j.eps, j.V, status, b - j.block_base);
 }
 
 __global__ void __launch_bounds__(256)
@@ -231,6 +247,14 @@ int64_t jacobi_work_doubles(int n, int64_t batch) {
   if (n <= kSmallN) return 0;
   const int64_t chunk = batch < kLargeChunk ? batch : kLargeChunk;
   return 4 * (int64_t)n * n * chunk;
+}
+
+ephw_status jacobi_eigh_grouped(const EighJob* d_jobs, int njobs, int64_t blocks, uint32_t* status,
+                                hipStream_t s) {
+  if (njobs <= 0 || blocks <= 0) return EPHW_OK;
+  hipLaunchKernelGGL(jacobi_grouped_kernel, dim3((unsigned)blocks), dim3(64), 0, s, d_jobs, njobs, status);
+  EPHW_CHECK_LAUNCH();
+  return EPHW_OK;
 }
 
 ephw_status jacobi_eigh(const double* H, int64_t batch, int n, double* eps, double* V, double* work,

@@ -19,6 +19,18 @@ int64_t jacobi_work_doubles(int n, int64_t batch);
 ephw_status jacobi_eigh(const double* H, int64_t batch, int n, double* eps, double* V, double* work,
                         uint32_t* status, hipStream_t s);
 
+// many small (n <= 32) eigensolves of different orders in one launch;
+// block b belongs to the job with the largest block_base <= b (count blocks each)
+struct EighJob {
+  const double* H;
+  double* eps;
+  double* V;
+  int n;
+  int64_t count, block_base;
+};
+ephw_status jacobi_eigh_grouped(const EighJob* d_jobs, int njobs, int64_t blocks, uint32_t* status,
+                                hipStream_t s);
+
 // dst[i] = (T) src[i] for n complex values; T = float (prec 1) or a plain copy (prec 0)
 ephw_status cast_complex(int prec, const double* src, void* dst, int64_t n, hipStream_t s);
 
@@ -37,21 +49,54 @@ ephw_status mode_rotate(int prec, const void* G, const void* u, void* Gnu, int64
                         int nm, int64_t nw2, hipStream_t s);
 
 struct BandRotateArgs {
-  const void* W;          // [nk][qb][nm][nw][nw]  (Re-GEMM output, row stride qb*nm*nw*nw)
+  const void* W;          // [nk_tile][qb][nm][nw][nw]  (Re-GEMM output, row stride qb*nm*nw*nw)
   const void* Vk;         // [nk][nw][nw] or NULL (identity: Wannier-gauge output)
   const void* Vkq;        // [qb][nk][nw][nw] or NULL
   const int32_t* kq_index;  // [qb][nk] (already offset to the batch) or NULL
-  int64_t nk;
+  int64_t nk;             // size of the k set (row stride of kq_index, g_out, band_sum)
+  int64_t k0 = 0;         // global index of the tile's first k
+  int64_t nk_tile = 0;    // k points in this tile (grid x)
   int qb, nm, nw;
   uint32_t flags;
   void* g_out;            // [qb][nk][nm][nw][nw], offset to the batch
   double* band_sum;       // [qb][nk][nm], offset to the batch
-  double* loss_partial;   // [qb*nk] per-pair partial sums, or NULL
+  double* loss_partial;   // [qb][nk_tile] per-pair partial sums, or NULL
   uint64_t loss_seed;
   int64_t q_global0;      // global index of the batch's first q
   uint32_t* status;
 };
 ephw_status band_rotate(int prec, const BandRotateArgs& a, hipStream_t s);
+// modes per LDS chunk of the band-rotation kernel and its dynamic LDS bytes
+int band_rotate_modes_per_chunk(int prec, int nw, int nm, size_t* lds_bytes);
+
+// grouped launches over many systems: block b belongs to the job with the
+// largest block_base <= b (jobs sorted by block_base)
+struct ModeRotateJob {
+  const void* G;
+  const void* u;
+  void* Gnu;
+  int64_t ne, nw2;
+  int qb, nm;
+  int64_t block_base;     // blocks: qb * ceil(ne*nw2/256)
+};
+ephw_status mode_rotate_grouped(int prec, const ModeRotateJob* d_jobs, int n, int64_t blocks, size_t lds,
+                                hipStream_t s);
+struct BandRotateJob {
+  BandRotateArgs args;
+  int nuc;
+  int64_t block_base;     // blocks: qb * nk_tile
+};
+// launches never change kernel attributes (they may be captured in a graph):
+// call band_rotate_grouped_prepare with the largest LDS size first
+ephw_status band_rotate_grouped_prepare(int prec, size_t lds);
+ephw_status band_rotate_grouped(int prec, const BandRotateJob* d_jobs, int n, int64_t blocks, size_t lds,
+                                hipStream_t s);
+struct SumJob {
+  const double* x;
+  int64_t n;
+  double* out;
+};
+ephw_status sum_into_grouped(const SumJob* d_jobs, int n, hipStream_t s);
 
 // dst[r][c] = src[idx[r]][c] (rows of width w); an index outside [0, nsrc) sets kStatusIndex
 ephw_status gather_rows(const double* src, int64_t nsrc, const int32_t* idx, int64_t cnt, int w,

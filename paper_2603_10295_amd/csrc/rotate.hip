@@ -49,11 +49,9 @@ __global__ void scale_rows_kernel(const double* __restrict__ ph, int64_t nq, con
 constexpr int kModeReg = 24;
 
 template <typename T>
-__global__ void mode_rotate_kernel(const T* __restrict__ G, const T* __restrict__ u, T* __restrict__ Gnu,
-                                   int64_t ne, int qb, int nm, int64_t nw2) {
-  extern __shared__ unsigned char smem_raw[];
-  T* us = reinterpret_cast<T*>(smem_raw);
-  const int q = blockIdx.y;
+__device__ __forceinline__ void mode_rotate_body(const T* __restrict__ G, const T* __restrict__ u,
+                                                 T* __restrict__ Gnu, int64_t ne, int qb, int nm,
+                                                 int64_t nw2, int q, int64_t bx, T* us) {
   const int64_t E = (int64_t)nm * nw2;
   if (u) {
     for (int i = threadIdx.x; i < nm * nm; i += blockDim.x) {
@@ -62,7 +60,7 @@ __global__ void mode_rotate_kernel(const T* __restrict__ G, const T* __restrict_
     }
     __syncthreads();
   }
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t idx = bx * blockDim.x + threadIdx.x;
   if (idx >= ne * nw2) return;
   const int64_t e = idx / nw2, mn = idx % nw2;
   const T* src = G + 2 * (((int64_t)q * ne + e) * E + mn);
@@ -99,6 +97,36 @@ __global__ void mode_rotate_kernel(const T* __restrict__ G, const T* __restrict_
   }
 }
 
+template <typename T>
+__global__ void mode_rotate_kernel(const T* __restrict__ G, const T* __restrict__ u, T* __restrict__ Gnu,
+                                   int64_t ne, int qb, int nm, int64_t nw2) {
+  extern __shared__ unsigned char smem_raw[];
+  mode_rotate_body<T>(G, u, Gnu, ne, qb, nm, nw2, blockIdx.y, blockIdx.x, reinterpret_cast<T*>(smem_raw));
+}
+
+// find the job whose [block_base, next block_base) holds block b
+template <typename J>
+__device__ __forceinline__ int find_job(const J* jobs, int n, int64_t b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block_base <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T>
+__global__ void mode_rotate_grouped_kernel(const ModeRotateJob* __restrict__ jobs, int n) {
+  extern __shared__ unsigned char smem_raw[];
+  const int64_t b = blockIdx.x;
+  const ModeRotateJob& j = jobs[find_job(jobs, n, b)];
+  const int64_t local = b - j.block_base;
+  const int64_t per_q = ceil_div(j.ne * j.nw2, (int64_t)blockDim.x);
+  mode_rotate_body<T>(static_cast<const T*>(j.G), static_cast<const T*>(j.u), static_cast<T*>(j.Gnu), j.ne,
+                      j.qb, j.nm, j.nw2, (int)(local / per_q), local % per_q,
+                      reinterpret_cast<T*>(smem_raw));
+}
+
 __device__ __forceinline__ double loss_weight(uint64_t seed, uint64_t index) {
   // SplitMix64 (Steele, Lea & Flood 2014): index-th output for `seed`
   uint64_t z = seed + (index + 1ull) * 0x9E3779B97F4A7C15ull;
@@ -113,12 +141,11 @@ __device__ __forceinline__ double loss_weight(uint64_t seed, uint64_t index) {
 constexpr int kRotThreads = 256;
 
 template <typename T>
-__global__ void __launch_bounds__(kRotThreads) band_rotate_kernel(BandRotateArgs a, int nuc) {
-  extern __shared__ unsigned char smem_raw[];
+__device__ __forceinline__ void band_rotate_body(const BandRotateArgs& a, int nuc, int64_t ik_local,
+                                                 int iq, unsigned char* smem_raw) {
   const int nw = a.nw, nm = a.nm;
   const int nw2 = nw * nw;
-  const int64_t ik = blockIdx.x;
-  const int iq = blockIdx.y;
+  const int64_t ik = a.k0 + ik_local;   // global k index
   const int64_t E = (int64_t)nm * nw2;
   const bool rot = a.Vk != nullptr;
   T* vk = reinterpret_cast<T*>(smem_raw);            // [nw][nw]
@@ -151,7 +178,7 @@ __global__ void __launch_bounds__(kRotThreads) band_rotate_kernel(BandRotateArgs
       vkq[2 * i + 1] = src[2 * i + 1];
     }
   }
-  const T* W = static_cast<const T*>(a.W) + 2 * (ik * (int64_t)a.qb * E + (int64_t)iq * E);
+  const T* W = static_cast<const T*>(a.W) + 2 * (ik_local * (int64_t)a.qb * E + (int64_t)iq * E);
   T* gout = a.g_out ? static_cast<T*>(a.g_out) + 2 * (((int64_t)iq * a.nk + ik) * E) : nullptr;
   const bool want_g = (a.flags & EPHW_OUT_G) && gout;
   const bool want_t = (a.flags & EPHW_OUT_BAND_SUM) && a.band_sum;
@@ -223,9 +250,25 @@ __global__ void __launch_bounds__(kRotThreads) band_rotate_kernel(BandRotateArgs
     if (tid == 0) {
       double s = 0.0;
       for (int w = 0; w < kRotThreads / 64; ++w) s += wred[w];
-      a.loss_partial[(int64_t)iq * a.nk + ik] = s;
+      a.loss_partial[(int64_t)iq * a.nk_tile + ik_local] = s;
     }
   }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRotThreads) band_rotate_kernel(BandRotateArgs a, int nuc) {
+  extern __shared__ unsigned char smem_raw[];
+  band_rotate_body<T>(a, nuc, blockIdx.x, blockIdx.y, smem_raw);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRotThreads) band_rotate_grouped_kernel(const BandRotateJob* __restrict__ jobs,
+                                                                          int n) {
+  extern __shared__ unsigned char smem_raw[];
+  const int64_t b = blockIdx.x;
+  const BandRotateJob& j = jobs[find_job(jobs, n, b)];
+  const int64_t local = b - j.block_base;
+  band_rotate_body<T>(j.args, j.nuc, local % j.args.nk_tile, (int)(local / j.args.nk_tile), smem_raw);
 }
 
 __global__ void sum_into_kernel(const double* __restrict__ x, int64_t n, double* __restrict__ out) {
@@ -319,8 +362,19 @@ ephw_status mode_rotate(int prec, const void* G, const void* u, void* Gnu, int64
   return EPHW_OK;
 }
 
+int band_rotate_modes_per_chunk(int prec, int nw, int nm, size_t* lds_bytes) {
+  const size_t esz = 2 * (prec == 0 ? 8 : 4);
+  const size_t nw2 = (size_t)nw * nw;
+  const size_t fixed = esz * 2 * nw2 + 8 * (kRotThreads / 64);
+  const size_t per_mode = (2 * esz + 8) * nw2;
+  int nuc = fixed + per_mode <= 65536 ? (int)((65536 - fixed) / per_mode) : 1;
+  if (nuc > nm) nuc = nm;
+  if (lds_bytes) *lds_bytes = fixed + per_mode * (size_t)nuc;
+  return nuc;
+}
+
 ephw_status band_rotate(int prec, const BandRotateArgs& a, hipStream_t s) {
-  if (a.nk <= 0 || a.qb <= 0) return EPHW_OK;
+  if (a.nk_tile <= 0 || a.qb <= 0) return EPHW_OK;
   if (a.nw > 32) {
     set_error("band_rotate: this kernel handles nw <= 32");
     return EPHW_EUNSUPPORTED;
@@ -342,15 +396,15 @@ ephw_status band_rotate(int prec, const BandRotateArgs& a, hipStream_t s) {
       EPHW_HIP(hipFuncSetAttribute((const void*)band_rotate_kernel<float>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   }
-  if (a.nk > 0x7fffffff || a.qb > 65535) {
+  if (a.nk_tile > 0x7fffffff || a.qb > 65535) {
     set_error("band_rotate: grid too large");
     return EPHW_EUNSUPPORTED;
   }
   if (prec == 0)
-    hipLaunchKernelGGL(band_rotate_kernel<double>, dim3((unsigned)a.nk, a.qb), dim3(kRotThreads), lds,
+    hipLaunchKernelGGL(band_rotate_kernel<double>, dim3((unsigned)a.nk_tile, a.qb), dim3(kRotThreads), lds,
                        s, a, nuc);
   else
-    hipLaunchKernelGGL(band_rotate_kernel<float>, dim3((unsigned)a.nk, a.qb), dim3(kRotThreads), lds,
+    hipLaunchKernelGGL(band_rotate_kernel<float>, dim3((unsigned)a.nk_tile, a.qb), dim3(kRotThreads), lds,
                        s, a, nuc);
   EPHW_CHECK_LAUNCH();
   return EPHW_OK;
@@ -361,6 +415,62 @@ ephw_status gather_rows(const double* src, int64_t nsrc, const int32_t* idx, int
   if (cnt <= 0 || w <= 0) return EPHW_OK;
   hipLaunchKernelGGL(gather_rows_kernel, dim3(grid1(cnt * w, 256)), dim3(256), 0, s, src, nsrc, idx,
                      cnt, w, dst, status);
+  EPHW_CHECK_LAUNCH();
+  return EPHW_OK;
+}
+
+ephw_status mode_rotate_grouped(int prec, const ModeRotateJob* d_jobs, int n, int64_t blocks, size_t lds,
+                                hipStream_t s) {
+  if (n <= 0 || blocks <= 0) return EPHW_OK;
+  if (prec == 0)
+    hipLaunchKernelGGL(mode_rotate_grouped_kernel<double>, dim3((unsigned)blocks), dim3(256), lds, s, d_jobs, n);
+  else
+    hipLaunchKernelGGL(mode_rotate_grouped_kernel<float>, dim3((unsigned)blocks), dim3(256), lds, s, d_jobs, n);
+  EPHW_CHECK_LAUNCH();
+  return EPHW_OK;
+}
+
+ephw_status band_rotate_grouped_prepare(int prec, size_t lds) {
+  if (lds <= 65536) return EPHW_OK;
+  if (prec == 0)
+    EPHW_HIP(hipFuncSetAttribute((const void*)band_rotate_grouped_kernel<double>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  else
+    EPHW_HIP(hipFuncSetAttribute((const void*)band_rotate_grouped_kernel<float>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  return EPHW_OK;
+}
+
+ephw_status band_rotate_grouped(int prec, const BandRotateJob* d_jobs, int n, int64_t blocks, size_t lds,
+                                hipStream_t s) {
+  if (n <= 0 || blocks <= 0) return EPHW_OK;
+  if (prec == 0)
+    hipLaunchKernelGGL(band_rotate_grouped_kernel<double>, dim3((unsigned)blocks), dim3(kRotThreads), lds, s,
+                       d_jobs, n);
+  else
+    hipLaunchKernelGGL(band_rotate_grouped_kernel<float>, dim3((unsigned)blocks), dim3(kRotThreads), lds, s,
+                       d_jobs, n);
+  EPHW_CHECK_LAUNCH();
+  return EPHW_OK;
+}
+
+__global__ void sum_into_grouped_kernel(const SumJob* __restrict__ jobs) {
+  __shared__ double red[256];
+  const SumJob& j = jobs[blockIdx.x];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < j.n; i += 256) s += j.x[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && j.n > 0) j.out[0] += red[0];
+}
+
+ephw_status sum_into_grouped(const SumJob* d_jobs, int n, hipStream_t s) {
+  if (n <= 0) return EPHW_OK;
+  hipLaunchKernelGGL(sum_into_grouped_kernel, dim3((unsigned)n), dim3(256), 0, s, d_jobs);
   EPHW_CHECK_LAUNCH();
   return EPHW_OK;
 }

@@ -27,8 +27,12 @@ EXPORTS = [
     "ephw_ctx_create", "ephw_ctx_destroy", "ephw_ctx_check", "ephw_system_load",
     "ephw_system_free", "ephw_system_bytes", "ephw_bands", "ephw_phonons", "ephw_phase_sum_rp",
     "ephw_kset_create", "ephw_kset_free", "ephw_kset_bands", "ephw_interpolate",
-    "ephw_set_q_batch", "ephw_status_string", "ephw_last_error", "ephw_version",
+    "ephw_set_q_batch", "ephw_profile_enable", "ephw_profile_read", "ephw_batch_create",
+    "ephw_batch_run", "ephw_batch_shape", "ephw_batch_stats", "ephw_batch_free", "ephw_status_string",
+    "ephw_last_error", "ephw_version",
 ]
+
+STAGES = ["phase", "eig", "kq_eig", "rp_gemm", "mode_rot", "re_gemm", "band_rot", "other"]
 
 
 class EphwError(RuntimeError):
@@ -52,6 +56,19 @@ class SystemDesc(ctypes.Structure):
         ("h_r", ctypes.c_void_p), ("c_r", ctypes.c_void_p), ("mass", ctypes.c_void_p), ("g", ctypes.c_void_p),
         ("g_dtype", ctypes.c_int32),
     ]
+
+
+class BatchItem(ctypes.Structure):
+    _fields_ = [
+        ("ks", ctypes.c_void_p), ("q", ctypes.c_void_p), ("nq", ctypes.c_int64),
+        ("kq_index", ctypes.c_void_p), ("flags", ctypes.c_uint32), ("g_out", ctypes.c_void_p),
+        ("band_sum", ctypes.c_void_p), ("loss", ctypes.c_void_p), ("loss_seed", ctypes.c_uint64),
+    ]
+
+
+class BatchOptions(ctypes.Structure):
+    _fields_ = [("tune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p), ("use_graph", ctypes.c_int32),
+                ("item_workspace_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -85,6 +102,13 @@ def lib() -> ctypes.CDLL:
         "ephw_kset_bands": [vp, vp, vp, vp],
         "ephw_interpolate": [vp, vp, i64, vp, i64, i32, u32, vp, vp, vp, u64, vp, vp, vp],
         "ephw_set_q_batch": [vp, i32],
+        "ephw_profile_enable": [vp, i32],
+        "ephw_profile_read": [vp, vp, vp],
+        "ephw_batch_create": [vp, ctypes.POINTER(BatchItem), i32, ctypes.POINTER(BatchOptions), vp, pp],
+        "ephw_batch_run": [vp, vp],
+        "ephw_batch_shape": [vp, i32, vp, vp, vp, vp],
+        "ephw_batch_stats": [vp, vp, vp],
+        "ephw_batch_free": [vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -200,6 +224,16 @@ class System:
     def set_q_batch(self, qb: int):
         _check(lib().ephw_set_q_batch(self.handle, int(qb)), "ephw_set_q_batch")
 
+    def profile(self, enable: bool):
+        _check(lib().ephw_profile_enable(self.handle, 1 if enable else 0), "ephw_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{stage: (milliseconds, launches)} summed since the last read."""
+        ms = (ctypes.c_double * len(STAGES))()
+        n = (ctypes.c_int64 * len(STAGES))()
+        _check(lib().ephw_profile_read(self.handle, ms, n), "ephw_profile_read")
+        return {s: (ms[i], int(n[i])) for i, s in enumerate(STAGES)}
+
     def close(self):
         if self.handle:
             lib().ephw_system_free(self.handle)
@@ -257,6 +291,62 @@ def interpolate(ks: KSet, q, *, kq_index=None, q_offset: int = 0, flags: int = O
     _check(lib().ephw_interpolate(ks.handle, _ptr(q), q.shape[0], _ptr(kq_index), int(q_offset), ks.prec,
                                   int(flags), _ptr(g_out), _ptr(band_sum), _ptr(loss), int(loss_seed),
                                   _ptr(eps_kq), _ptr(omega), _stream(stream)), "ephw_interpolate")
+
+
+class Batch:
+    """Many (k-set, q list) items interpolated in one pass (see ephw_batch_create).
+
+    items: list of dicts with keys ks, q, kq_index, flags and the output tensors
+    g_out / band_sum / loss, plus loss_seed.  Tensors must stay alive as long as
+    the batch (their pointers are baked into the captured pass).
+    """
+
+    def __init__(self, ctx: Context, items, *, tune: bool = False, tune_cache: Optional[str] = None,
+                 use_graph: bool = True, item_workspace_bytes: int = 0, stream=None):
+        arr = (BatchItem * len(items))()
+        self._keep = []
+        for i, it in enumerate(items):
+            arr[i].ks = it["ks"].handle
+            arr[i].q = _ptr(it["q"])
+            arr[i].nq = it["q"].shape[0]
+            arr[i].kq_index = _ptr(it["kq_index"])
+            arr[i].flags = int(it.get("flags", OUT_LOSS))
+            arr[i].g_out = _ptr(it.get("g_out"))
+            arr[i].band_sum = _ptr(it.get("band_sum"))
+            arr[i].loss = _ptr(it.get("loss"))
+            arr[i].loss_seed = int(it.get("loss_seed", 0))
+            self._keep.append(it)
+        opt = BatchOptions(1 if tune else 0, tune_cache.encode() if tune_cache else None, 1 if use_graph else 0,
+                           int(item_workspace_bytes))
+        h = ctypes.c_void_p()
+        _check(lib().ephw_batch_create(ctx.handle, arr, len(items), ctypes.byref(opt), _stream(stream),
+                                       ctypes.byref(h)), "ephw_batch_create")
+        self.handle = h
+        self.n = len(items)
+
+    def run(self, stream=None):
+        _check(lib().ephw_batch_run(self.handle, _stream(stream)), "ephw_batch_run")
+
+    def shape(self, i: int):
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib().ephw_batch_shape(self.handle, i, *[ctypes.byref(x) for x in v]), "ephw_batch_shape")
+        return dict(q_batch=v[0].value, k_tile=v[1].value, cfg_rp=v[2].value, cfg_re=v[3].value)
+
+    def stats(self):
+        r, l = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().ephw_batch_stats(self.handle, ctypes.byref(r), ctypes.byref(l)), "ephw_batch_stats")
+        return dict(rounds=r.value, launches=l.value)
+
+    def close(self):
+        if self.handle:
+            lib().ephw_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> int:

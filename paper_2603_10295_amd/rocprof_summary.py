@@ -1,0 +1,121 @@
+"""Summarise rocprofv3 result databases (SQLite) of libephw runs as text.
+
+    python -m paper_2603_10295_amd.rocprof_summary stats RESULTS.db [--command CMD]
+    python -m paper_2603_10295_amd.rocprof_summary traffic FETCH.db WRITE.db \
+        --copy-bytes BYTES [--command CMD]
+
+`stats` groups kernel dispatches by (kernel, grid) - the phase GEMMs of
+Eqs. (9) and (10) share one kernel but differ in grid - and prints calls,
+total/average/min/max duration.  `traffic` reads FETCH_SIZE and WRITE_SIZE
+(KiB per dispatch) from two counter runs, scales each by the factor that
+makes a plain device copy of `--copy-bytes` bytes read and write exactly that
+many bytes, and prints HBM bytes per dispatch per (kernel, grid) group.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import hashlib
+import os
+import re
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def short_name(name: str) -> str:
+    """Kernel name without namespaces and parameter list, keeping template arguments."""
+    n = name.replace("(anonymous namespace)::", "")
+    n = re.sub(r"^void ", "", n)
+    if n.endswith(")") and "(" in n:
+        n = n[: n.rfind("(")] if n.count("(") == 1 else n[: n.index("(")]
+    return n.replace("ephw::", "").strip()
+
+
+def source_digest() -> str:
+    """Hash of the GEMM source: the traffic figures hold only for this kernel."""
+    h = hashlib.sha256()
+    with open(os.path.join(HERE, "csrc", "gemm.hip"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stats(db: str, command: str = "") -> str:
+    c = sqlite3.connect(db)
+    rows = c.execute("select name, grid_x, grid_y, grid_z, workgroup_x, duration from kernels").fetchall()
+    groups = collections.defaultdict(list)
+    for name, gx, gy, gz, wx, dur in rows:
+        groups[(short_name(name), gx // max(1, wx), gy, gz)].append(dur)
+    total = sum(sum(v) for v in groups.values())
+    out = [f"# rocprofv3 kernel-trace stats: {os.path.basename(db)}",
+           f"# command: {command}" if command else "# command: (not recorded)",
+           "# grouped by (kernel, workgroups x, grid y, grid z); durations in ms",
+           f"{'calls':>6} {'total_ms':>11} {'avg_ms':>10} {'min_ms':>10} {'max_ms':>10} {'pct':>6}  kernel [wg_x x grid_y x grid_z]"]
+    for (name, bx, gy, gz), v in sorted(groups.items(), key=lambda kv: -sum(kv[1])):
+        out.append(f"{len(v):6d} {sum(v) / 1e6:11.3f} {sum(v) / len(v) / 1e6:10.4f} {min(v) / 1e6:10.4f} "
+                   f"{max(v) / 1e6:10.4f} {100 * sum(v) / total:6.2f}  {name} [{bx} x {gy} x {gz}]")
+    return "\n".join(out) + "\n"
+
+
+def _counter_groups(db: str, counter: str):
+    c = sqlite3.connect(db)
+    rows = c.execute("select kernel_name, grid_size_x, grid_size_y, workgroup_size_x, counter_name, value "
+                     "from counters_collection").fetchall()
+    groups = collections.defaultdict(list)
+    for name, gx, gy, wx, cname, val in rows:
+        if cname == counter:
+            groups[(short_name(name), gx // max(1, wx), gy)].append(val)
+    return groups
+
+
+def traffic(fetch_db: str, write_db: str, copy_bytes: int, command: str = "") -> str:
+    fg = _counter_groups(fetch_db, "FETCH_SIZE")
+    wg = _counter_groups(write_db, "WRITE_SIZE")
+
+    def copy_value(groups):
+        vals = [v for (n, _, _), vs in groups.items() if "copyBuffer" in n for v in vs]
+        return max(vals) if vals else None
+
+    kib = copy_bytes / 1024.0
+    cf, cw = copy_value(fg), copy_value(wg)
+    ff = kib / cf if cf else None
+    fw = kib / cw if cw else None
+    out = [f"# HBM traffic per dispatch from rocprofv3 counters (gemm.hip digest {source_digest()})",
+           f"# command: {command}" if command else "# command: (not recorded)",
+           f"# calibration: device copy of {copy_bytes} bytes read FETCH_SIZE={cf} KiB, WRITE_SIZE={cw} KiB",
+           f"# scale factors: fetch x{ff:.4f}, write x{fw:.4f}" if ff and fw else "# scale factors: unavailable",
+           f"{'disp':>5} {'fetch_KiB':>13} {'write_KiB':>13} {'read_GB':>9} {'write_GB':>9}  kernel [workgroups x grid_y]"]
+    keys = sorted(set(fg) | set(wg), key=lambda k: -(sum(fg.get(k, [0])) + sum(wg.get(k, [0]))))
+    for k in keys:
+        f = fg.get(k, [])
+        w = wg.get(k, [])
+        fa = sum(f) / len(f) if f else float("nan")
+        wa = sum(w) / len(w) if w else float("nan")
+        rd = fa * 1024 * (ff or float("nan")) / 1e9
+        wr = wa * 1024 * (fw or float("nan")) / 1e9
+        out.append(f"{max(len(f), len(w)):5d} {fa:13.1f} {wa:13.1f} {rd:9.3f} {wr:9.3f}  {k[0]} [{k[1]} x {k[2]}]")
+    return "\n".join(out) + "\n"
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("db")
+    s.add_argument("--command", default="")
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_db")
+    t.add_argument("write_db")
+    t.add_argument("--copy-bytes", type=int, required=True)
+    t.add_argument("--command", default="")
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        sys.stdout.write(stats(a.db, a.command))
+    else:
+        sys.stdout.write(traffic(a.fetch_db, a.write_db, a.copy_bytes, a.command))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -233,13 +233,16 @@ def si_dense(seed: int = 0, m: int = 20, g_dtype=np.complex64) -> Workload:
                     grid_index_of_sum((m, m, m)), "fp32", seed)
 
 
-def batch_systems(seed: int = 0, count: int = 32, max_grid: int = 16) -> list:
-    """Heterogeneous multi-system batch: Nw in [4,32], Na in [1,8], 3D boxes with
-    n_i in [4,10] and Ne=Np<=800, k = q = m^3 grid with m in [4, max_grid]."""
-    out = []
-    for s in range(count):
-        base = [seed, STREAM_SHAPE, s]
-        gen = rng(base, 0)
+G_CAP_BYTES = 2 * 2 ** 30
+
+
+def batch_shape(seed: int, s: int, max_grid: int = 16, g_cap_bytes: int = G_CAP_BYTES):
+    """Shape of system s of the multi-system batch: Nw in [4,32], Na in [1,8],
+    a 3D box with n_i in [4,10] and Ne=Np<=800, grid m in [4, max_grid].
+    Draws whose complex64 g would exceed g_cap_bytes are redrawn from the same
+    ranges (the unrestricted 32-system batch holds about 207 GB of g)."""
+    gen = rng([seed, STREAM_SHAPE, s], 0)
+    while True:
         nw = int(gen.integers(4, 33))
         na = int(gen.integers(1, 9))
         while True:
@@ -247,6 +250,19 @@ def batch_systems(seed: int = 0, count: int = 32, max_grid: int = 16) -> list:
             if n[0] * n[1] * n[2] <= 800:
                 break
         m = int(gen.integers(4, max_grid + 1))
+        ne = n[0] * n[1] * n[2]
+        if 8 * ne * ne * 3 * na * nw * nw <= g_cap_bytes:
+            return nw, na, n, m
+
+
+def batch_systems(seed: int = 0, count: int = 32, max_grid: int = 16,
+                  g_cap_bytes: int = G_CAP_BYTES) -> list:
+    """Heterogeneous multi-system batch (see batch_shape); complex64 g, k = q =
+    the m^3 grid of each system."""
+    out = []
+    for s in range(count):
+        base = [seed, STREAM_SHAPE, s]
+        nw, na, n, m = batch_shape(seed, s, max_grid, g_cap_bytes)
         r = box(n)
         sys_ = make_system(nw, na, r, r, base, g_dtype=np.complex64)
         pts = uniform_grid((m, m, m))
