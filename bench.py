@@ -37,7 +37,10 @@ def parse(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="si_dense", choices=["si_dense", "mos2_2d", "si_toy"])
+    ap.add_argument("--workload", default="si_dense", choices=["si_dense", "mos2_2d", "si_toy", "batch32"])
+    ap.add_argument("--batch-count", type=int, default=32)
+    ap.add_argument("--batch-max-grid", type=int, default=16)
+    ap.add_argument("--tune-cache", default="")
     ap.add_argument("--grid", type=int, default=20, help="k = q = grid^3 for si_dense")
     ap.add_argument("--q-chunk", type=int, default=1024)
     ap.add_argument("--fp64-steps", type=int, default=1)
@@ -173,8 +176,84 @@ def cpu_baseline(w, qs_idx):
     return elems / dt, dt, ref, threads
 
 
+def bench_batch(args):
+    """Many heterogeneous systems in one graph-captured pass (one grouped launch
+    per stage), against the same items run one system at a time."""
+    import torch
+    import synth
+    from paper_2603_10295_amd import ephw, model
+    t_gen = time.perf_counter()
+    ctx = ephw.Context(0)
+    items, keep, names = [], [], []
+    elems = 0.0
+    cnt_tot = None
+    for i in range(args.batch_count):
+        w = synth.batch_system(0, i, max_grid=args.batch_max_grid)   # generated, uploaded, freed one by one
+        names.append(w.name)
+        s = w.system
+        sysh = ephw.System.from_synth(ctx, s)
+        k = torch.from_numpy(w.k).to("cuda:0")
+        q = torch.from_numpy(w.q).to("cuda:0")
+        ks = ephw.KSet(sysh, k, ephw.FP32)
+        items.append(dict(ks=ks, q=q, kq_index=torch.from_numpy(w.kq_index).to("cuda:0"), flags=ephw.OUT_LOSS,
+                          loss=torch.zeros(1, dtype=torch.float64, device="cuda:0"), loss_seed=i))
+        keep.append(sysh)
+        c = model.stage_counts(s.nw, s.nm, s.ne, s.np_, len(w.k), len(w.q))
+        elems += c.elems
+        cnt_tot = c if cnt_tot is None else model.StageCounts(*(getattr(cnt_tot, f) + getattr(c, f)
+                                                               for f in ("rp", "modes", "re", "rot", "hkq", "elems")))
+        del w, s
+    log(f"batch of {len(names)} systems generated and uploaded in {time.perf_counter() - t_gen:.1f}s")
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter()
+    b = ephw.Batch(ctx, items, tune=True, tune_cache=args.tune_cache or None)
+    log(f"planned in {time.perf_counter() - t_tune:.1f}s: {b.stats()}")
+    for _ in range(max(1, args.warmup)):
+        b.run()
+    ctx.check()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.run()
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / args.steps
+    ctx.check()
+    # the same items, one system at a time (no grouping, no graph)
+    def one_by_one():
+        for it in items:
+            ephw.interpolate(it["ks"], it["q"], kq_index=it["kq_index"], flags=ephw.OUT_LOSS, loss=it["loss"],
+                             loss_seed=it["loss_seed"])
+    one_by_one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_by_one()
+    torch.cuda.synchronize()
+    ts = (time.perf_counter() - t0) / args.steps
+    ctx.check()
+    gemm_tf = 8.0 * cnt_tot.gemm / tb / 1e12
+    line = {
+        "metric": "g(k,q) elems/s (FP32 MFMA path, 32-system batch)", "value": elems / tb, "unit": "elems/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": tb * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": f"batch{len(names)}_capped2GiB_maxgrid{args.batch_max_grid}", "systems": len(names),
+                   "output": "weighted |g|^2 loss per system", **b.stats()},
+        "one_system_at_a_time_ms": ts * 1e3, "batch_speedup": ts / tb,
+        "phase_gemm_tflops_lower_bound": gemm_tf,
+        "algorithmic_flops_per_step": 8.0 * cnt_tot.total,
+        "shapes": [dict(system=names[i], **b.shape(i)) for i in range(len(items))],
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main(argv=None):
     args = parse(argv)
+    if args.workload == "batch32":
+        if args.gpus != 1:
+            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            return 2
+        return bench_batch(args)
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
               "(the path shards over q across GPUs by design, see the design notes)", file=sys.stderr)

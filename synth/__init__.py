@@ -255,20 +255,22 @@ def batch_shape(seed: int, s: int, max_grid: int = 16, g_cap_bytes: int = G_CAP_
             return nw, na, n, m
 
 
+def batch_system(seed: int, s: int, max_grid: int = 16, g_cap_bytes: int = G_CAP_BYTES) -> Workload:
+    """System s of the multi-system batch (see batch_shape); complex64 g, k = q =
+    the m^3 grid of the system."""
+    base = [seed, STREAM_SHAPE, s]
+    nw, na, n, m = batch_shape(seed, s, max_grid, g_cap_bytes)
+    r = box(n)
+    sys_ = make_system(nw, na, r, r, base, g_dtype=np.complex64)
+    pts = uniform_grid((m, m, m))
+    return Workload(f"batch{s}_nw{nw}_nm{3*na}_r{n[0]}x{n[1]}x{n[2]}_grid{m}^3",
+                    sys_, pts, pts.copy(), grid_index_of_sum((m, m, m)), "fp32", seed)
+
+
 def batch_systems(seed: int = 0, count: int = 32, max_grid: int = 16,
                   g_cap_bytes: int = G_CAP_BYTES) -> list:
-    """Heterogeneous multi-system batch (see batch_shape); complex64 g, k = q =
-    the m^3 grid of each system."""
-    out = []
-    for s in range(count):
-        base = [seed, STREAM_SHAPE, s]
-        nw, na, n, m = batch_shape(seed, s, max_grid, g_cap_bytes)
-        r = box(n)
-        sys_ = make_system(nw, na, r, r, base, g_dtype=np.complex64)
-        pts = uniform_grid((m, m, m))
-        out.append(Workload(f"batch{s}_nw{nw}_nm{3*na}_r{n[0]}x{n[1]}x{n[2]}_grid{m}^3",
-                            sys_, pts, pts.copy(), grid_index_of_sum((m, m, m)), "fp32", seed))
-    return out
+    """The whole heterogeneous batch (list of Workloads)."""
+    return [batch_system(seed, s, max_grid, g_cap_bytes) for s in range(count)]
 
 
 def ribbon_1d(seed: int = 0, nw: int = 200, na: int = 50, nk: int = 256, half: int = 5,
