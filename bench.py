@@ -37,7 +37,11 @@ def parse(argv=None):
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="si_dense", choices=["si_dense", "mos2_2d", "si_toy", "batch32"])
+    ap.add_argument("--workload", default="si_dense",
+                    choices=["si_dense", "mos2_2d", "si_toy", "batch32", "ribbon"])
+    ap.add_argument("--ribbon-nk", type=int, default=256, help="k = q = i/n along the ribbon axis")
+    ap.add_argument("--ribbon-nw", type=int, default=200)
+    ap.add_argument("--ribbon-na", type=int, default=50)
     ap.add_argument("--batch-count", type=int, default=32)
     ap.add_argument("--batch-max-grid", type=int, default=16)
     ap.add_argument("--tune-cache", default="")
@@ -247,8 +251,83 @@ def bench_batch(args):
     return 0
 
 
+def bench_ribbon(args):
+    """Differentiation workload: weighted |g|^2 loss over all pairs and its
+    gradients dL/dg(Re,Rp), dL/dk, dL/dq (hand-written adjoint), FP32 MFMA."""
+    import torch
+    import synth
+    from paper_2603_10295_amd import ephw, model
+    t_gen = time.perf_counter()
+    w = synth.ribbon_1d(nw=args.ribbon_nw, na=args.ribbon_na, nk=args.ribbon_nk)
+    s = w.system
+    nk, nq = len(w.k), len(w.q)
+    log(f"workload {w.name}: generated in {time.perf_counter() - t_gen:.1f}s, g {s.g.nbytes / 1e9:.2f} GB")
+    ctx = ephw.Context(0)
+    sysh = ephw.System.from_synth(ctx, s)
+    k = torch.from_numpy(w.k).to("cuda:0")
+    q = torch.from_numpy(w.q).to("cuda:0")
+    kqi = torch.from_numpy(w.kq_index).to("cuda:0")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    dg = torch.zeros(s.g.shape, dtype=torch.complex64, device="cuda:0")
+    dk = torch.zeros((nk, 3), dtype=torch.float64, device="cuda:0")
+    dq = torch.zeros((nq, 3), dtype=torch.float64, device="cuda:0")
+    del w.system.g
+
+    def fwd():
+        ks = ephw.KSet(sysh, k, ephw.FP32)
+        ephw.interpolate(ks, q, kq_index=kqi, flags=ephw.OUT_LOSS, loss=loss, loss_seed=1)
+        ks.close()
+
+    def bwd():
+        ks = ephw.KSet(sysh, k, ephw.FP32)
+        ephw.loss_backward(ks, q, kqi, loss_seed=1, loss=loss, dL_dg=dg, dL_dk=dk, dL_dq=dq)
+        ks.close()
+
+    def timed_call(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    for _ in range(args.warmup):
+        fwd()
+    sysh.profile_read()
+    sysh.profile(True)
+    t_f = min(timed_call(fwd) for _ in range(args.steps))
+    sysh.profile(False)
+    st_f = sysh.profile_read()
+    ctx.check()
+    log(f"forward: {t_f:.3f} s")
+    t_b = timed_call(bwd)
+    ctx.check()
+    log(f"backward (recompute + gradients): {t_b:.3f} s")
+    c = model.stage_counts(s.nw, s.nm, s.ne, s.np_, nk, nq)
+    line = {
+        "metric": "g(k,q) elems/s (FP32 MFMA path, loss forward; ribbon differentiation workload)",
+        "value": c.elems / t_f, "unit": "elems/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_f * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "nw": s.nw, "nm": s.nm, "ne": s.ne, "np": s.np_, "nk": nk, "nq": nq},
+        "forward_s": t_f, "backward_s": t_b,
+        "forward_algorithmic_tflops": 8.0 * c.total / t_f / 1e12,
+        "rotation_share_of_flops": c.rot / c.total,
+        "stages_forward_ms": {k_: round(v[0], 3) for k_, v in st_f.items()},
+        "gradient_norms": {"dL_dg": float(torch.linalg.vector_norm(dg).cpu()),
+                           "dL_dk": float(torch.linalg.vector_norm(dk).cpu()),
+                           "dL_dq": float(torch.linalg.vector_norm(dq).cpu())},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main(argv=None):
     args = parse(argv)
+    if args.workload == "ribbon":
+        if args.gpus != 1:
+            print("bench.py: this build runs on one GPU", file=sys.stderr)
+            return 2
+        return bench_ribbon(args)
     if args.workload == "batch32":
         if args.gpus != 1:
             print("bench.py: this build runs on one GPU", file=sys.stderr)

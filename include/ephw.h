@@ -122,6 +122,9 @@ typedef struct ephw_system_desc {
    1 <= na <= 86 (nm <= 258), every n >= 1. */
 ephw_status ephw_system_load(ephw_ctx* ctx, const ephw_system_desc* desc, ephw_system** out);
 ephw_status ephw_system_free(ephw_system* sys);
+/* Replace the system's g(Re,Rp) by `g` (DEVICE memory, same shape and element
+   type as at load), copied on `stream`; k-sets of the system stay valid. */
+ephw_status ephw_system_set_g(ephw_system* sys, const void* g, void* stream);
 /* bytes of library-owned device memory held by the system (tensors + workspace) */
 ephw_status ephw_system_bytes(const ephw_system* sys, int64_t* bytes);
 
@@ -180,8 +183,28 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
                              double* band_sum, double* loss, uint64_t loss_seed, double* eps_kq,
                              double* omega, void* stream);
 
+/* Loss and gradients (not in the paper: the adjoint of Eq. (7)).
+   L = sum over the k-set's points and the q list of w_{mn nu}(k,q) |g_{mn nu}(k,q)|^2
+   with the SplitMix64 weights of EPHW_OUT_LOSS (seed loss_seed, q index q_offset + iq).
+   One call recomputes the forward in (q batch, k tile) units and accumulates
+     loss   one f64: L +=
+     dL_dg  [np][ne][nm][nw][nw] c128 (FP64 k-set) or c64 (FP32), +=, gradient
+            dL/dRe g + i dL/dIm g with respect to the stored g(Re,Rp)
+     dL_dk  [nk][3] f64 +=, gradient with respect to the fractional k coordinates
+     dL_dq  [nq][3] f64 +=
+   (any of them may be NULL).  kq_index [nq][nk] (k+q on the k grid) is
+   required; V(k+q) is the k-set's eigenvector at that grid point, and its
+   derivative there gives both dL/dk and dL/dq of the pair.  Eigenvectors enter
+   through their first-order change dV = V (F o (V^dagger dH V)),
+   F_ij = 1/(eps_j - eps_i) (non-degenerate spectra). */
+ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index,
+                               int64_t q_offset, uint64_t loss_seed, double* loss, void* dL_dg,
+                               double* dL_dk, double* dL_dq, void* stream);
+
 /* Tuning knobs (0 = automatic).  q_batch: q points per Rp/Re GEMM sweep. */
 ephw_status ephw_set_q_batch(ephw_system* sys, int32_t q_batch);
+/* k points per tile of the unit loops (large-band rotations, the adjoint) */
+ephw_status ephw_set_k_tile(ephw_system* sys, int32_t k_tile);
 
 /* Per-stage GPU timing for benchmarks: while enabled, every stage of the calls
    made on `sys` (and its k-sets) is bracketed by HIP events recorded on the

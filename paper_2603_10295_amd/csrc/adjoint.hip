@@ -1,0 +1,1008 @@
+// Large-band rotations and the adjoint of the weighted loss
+//   L = sum_{q,k,nu,m,n} w_{mn nu}(k,q) |g_{mn nu}(k,q)|^2,
+// with g_nu = V(k+q)^dagger W_nu V(k), W_nu = sum_Re e^{ik.Re} G_nu(Re,q),
+// G_nu = sum_ka G_ka u_{ka,nu}(q), G = sum_Rp e^{iq.Rp} g(Re,Rp)  (Eqs. (7), (9), (10)).
+//
+// Per (q batch, k tile) unit the forward is recomputed (phase tiles are
+// regenerated from the k and q lists, never stored across units) and the
+// chain rule runs backwards through it:
+//   Ybar = 2 w g                           (fused into the GEMM producing g)
+//   Wbar_nu = V(k+q) Ybar_nu V(k)^dagger
+//   Vbar(k) = sum W_nu^dagger V(k+q) Ybar_nu,  Vbar(k+q) = sum W_nu V(k) Ybar_nu^dagger
+//   G_nu bar(Re,q) = sum_k e^{-ik.Re} Wbar(k,q);  G bar = conj(u) G_nu bar;  ubar = conj(G) G_nu bar^T
+//   dL/dg(Re,Rp) = sum_q e^{-iq.Rp} G bar(Re,q)
+// and k, q enter through (i) the phase factors, whose derivative is the phase
+// times 2 pi i R_d (so dL/dk_d = Re <Wbar, W'_d> with W'_d the Re sum taken
+// with those scaled phases), (ii) the eigenvectors: dL/dk_d = Re <Vbar, dV/dk_d>
+// with dV = V (F o (V^dagger dH V)), F_ij = 1/(eps_j - eps_i), the
+// first-order change of the eigenvectors (their phases held fixed; the loss
+// does not depend on them).  For k+q on the k grid, dV at the grid point
+// serves both dL/dk_i and dL/dq_j of the pair.
+#include <algorithm>
+
+#include "internal.h"
+
+namespace ephw {
+namespace {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// out[d][i][r] = ph[i][r] * (2 pi i R[r][d])
+template <typename T>
+__global__ void scale_phase_kernel(const T* __restrict__ ph, int64_t n, const int32_t* __restrict__ R, int64_t nr,
+                                   T* __restrict__ out) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 3 * n * nr) return;
+  const int64_t d = idx / (n * nr), ir = idx % (n * nr), r = ir % nr;
+  const T f = (T)(kTwoPi * (double)R[3 * r + d]);
+  const T re = ph[2 * ir], im = ph[2 * ir + 1];
+  out[2 * idx] = -f * im;
+  out[2 * idx + 1] = f * re;
+}
+
+// M[b][i][j] /= (eps[j] - eps[i]) off the diagonal, 0 on it; eps row = b % nrow
+__global__ void eig_mid_kernel(double* __restrict__ M, const double* __restrict__ eps, int64_t batch, int n,
+                               int64_t nrow) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= batch * n * n) return;
+  const int64_t b = idx / ((int64_t)n * n);
+  const int i = (int)((idx / n) % n), j = (int)(idx % n);
+  const double* e = eps + (b % nrow) * n;
+  if (i == j) {
+    M[2 * idx] = 0.0;
+    M[2 * idx + 1] = 0.0;
+  } else {
+    const double f = 1.0 / (e[j] - e[i]);
+    M[2 * idx] *= f;
+    M[2 * idx + 1] *= f;
+  }
+}
+
+// offsets of V(k+q) for the rotation GEMMs of one unit:
+//   per (il, iq, nu):  off[(il qb + iq) nm + nu] = kq_index[(q0+iq) nk + k0+il] * nw2
+//   per pair:          offp[il qb + iq]          = the same index * nw2
+__global__ void kq_offsets_kernel(const int32_t* __restrict__ kq, int64_t nk, int64_t q0, int64_t k0, int kl, int qb,
+                                  int nm, int64_t nw2, int64_t* __restrict__ off, int64_t* __restrict__ offp,
+                                  uint32_t* status) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= (int64_t)kl * qb * nm) return;
+  const int64_t pair = b / nm, il = pair / qb, iq = pair % qb;
+  int64_t j = kq[(q0 + iq) * nk + k0 + il];
+  if (j < 0 || j >= nk) {
+    if (b % nm == 0) atomicOr(status, kStatusIndex);
+    j = 0;
+  }
+  off[b] = j * nw2;
+  if (b % nm == 0) offp[pair] = j * nw2;
+}
+
+// out[(r / inner) so + (r % inner) si] (+)= Re sum_c conj(a[r][c]) b[row(r)][c];
+// one block per row, fixed-order tree sum
+template <typename T>
+__global__ void row_dot_kernel(const T* __restrict__ a, int64_t lda, const T* __restrict__ b, int64_t ldb,
+                               const int64_t* __restrict__ boff, int64_t cols, double* __restrict__ out,
+                               int64_t inner, int64_t so, int64_t si, int accumulate) {
+  __shared__ double red[256];
+  const int64_t r = blockIdx.x;
+  const T* ar = a + 2 * r * lda;
+  const T* br = b + 2 * (boff ? boff[r] : r * ldb);
+  double s = 0.0;
+  for (int64_t c = threadIdx.x; c < cols; c += 256)
+    s += (double)ar[2 * c] * (double)br[2 * c] + (double)ar[2 * c + 1] * (double)br[2 * c + 1];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double* o = out + (r / inner) * so + (r % inner) * si;
+    if (accumulate) *o += red[0];
+    else *o = red[0];
+  }
+}
+
+// dk[k][d] += sum_q ps[q][k][d]  and  dq[q][d] += sum_k ps[q][k][d]
+__global__ void pair_sums_kernel(const double* __restrict__ ps, int64_t nq, int64_t nk, double* __restrict__ dk,
+                                 double* __restrict__ dq) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < nk * 3) {
+    const int64_t k = idx / 3, d = idx % 3;
+    double s = 0.0;
+    for (int64_t q = 0; q < nq; ++q) s += ps[(q * nk + k) * 3 + d];
+    dk[idx] += s;
+  } else if (idx < nk * 3 + nq * 3) {
+    const int64_t j = idx - nk * 3, q = j / 3, d = j % 3;
+    double s = 0.0;
+    for (int64_t k = 0; k < nk; ++k) s += ps[(q * nk + k) * 3 + d];
+    dq[j] += s;
+  }
+}
+
+// C (+)= sum over chunks of partial[b][chunk] (M*N values each)
+template <typename T>
+__global__ void splitk_reduce_kernel(const T* __restrict__ part, int64_t batch, int chunks, int64_t mn, T* __restrict__ C,
+                                     int64_t ldc, int64_t n, int64_t strideC, int accumulate) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= batch * mn) return;
+  const int64_t b = idx / mn, e = idx % mn, row = e / n, col = e % n;
+  T re = 0, im = 0;
+  for (int c = 0; c < chunks; ++c) {
+    const T* p = part + 2 * ((b * chunks + c) * mn + e);
+    re += p[0];
+    im += p[1];
+  }
+  T* c = C + 2 * (b * strideC + row * ldc + col);
+  if (accumulate) {
+    re += c[0];
+    im += c[1];
+  }
+  c[0] = re;
+  c[1] = im;
+}
+
+template <typename T>
+__global__ void fill_zero_kernel(T* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = (T)0;
+}
+
+// per (pair, nu): ||W_nu||_F^2 (band sums need no rotation: V is unitary)
+template <typename T>
+__global__ void frob_kernel(const T* __restrict__ W, int64_t nw2, double* __restrict__ out, int64_t qb, int64_t nm,
+                            int64_t nk, int64_t k0, int64_t kl) {
+  __shared__ double red[256];
+  const int64_t b = blockIdx.x;  // (il, iq, nu)
+  const T* w = W + 2 * b * nw2;
+  double s = 0.0;
+  for (int64_t c = threadIdx.x; c < nw2; c += 256) s += (double)w[2 * c] * w[2 * c] + (double)w[2 * c + 1] * w[2 * c + 1];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int t = 128; t > 0; t >>= 1) {
+    if (threadIdx.x < t) red[threadIdx.x] += red[threadIdx.x + t];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t nu = b % nm, iq = (b / nm) % qb, il = b / (nm * qb);
+    out[((iq * nk) + k0 + il) * nm + nu] = red[0];
+  }
+}
+
+inline unsigned grid1(int64_t n, int bs) { return (unsigned)ceil_div(n, bs); }
+
+template <typename T>
+ephw_status launch_row_dot(const void* a, int64_t lda, const void* b, int64_t ldb, const int64_t* boff, int64_t rows,
+                           int64_t cols, double* out, int64_t inner, int64_t so, int64_t si, bool acc,
+                           hipStream_t s) {
+  if (rows <= 0) return EPHW_OK;
+  hipLaunchKernelGGL(row_dot_kernel<T>, dim3((unsigned)rows), dim3(256), 0, s, static_cast<const T*>(a), lda,
+                     static_cast<const T*>(b), ldb, boff, cols, out, inner, so, si, acc ? 1 : 0);
+  EPHW_CHECK_LAUNCH();
+  return EPHW_OK;
+}
+
+// plain form: out[r * ostride]
+ephw_status row_dot(int kind, const void* a, int64_t lda, const void* b, int64_t ldb, const int64_t* boff,
+                    int64_t rows, int64_t cols, double* out, int64_t ostride, bool acc, hipStream_t s) {
+  return kind == 0 ? launch_row_dot<double>(a, lda, b, ldb, boff, rows, cols, out, 1, ostride, 0, acc, s)
+                   : launch_row_dot<float>(a, lda, b, ldb, boff, rows, cols, out, 1, ostride, 0, acc, s);
+}
+
+ephw_status row_dot2(int kind, const void* a, int64_t lda, const void* b, int64_t ldb, const int64_t* boff,
+                     int64_t rows, int64_t cols, double* out, int64_t inner, int64_t so, int64_t si, bool acc,
+                     hipStream_t s) {
+  return kind == 0 ? launch_row_dot<double>(a, lda, b, ldb, boff, rows, cols, out, inner, so, si, acc, s)
+                   : launch_row_dot<float>(a, lda, b, ldb, boff, rows, cols, out, inner, so, si, acc, s);
+}
+
+ephw_status fill_zero(int kind_or_f64, void* p, int64_t complex_count, hipStream_t s) {
+  // kind 0/1: complex double/float elements; 2: plain doubles
+  if (complex_count <= 0) return EPHW_OK;
+  if (kind_or_f64 == 1) {
+    const int64_t n = 2 * complex_count;
+    hipLaunchKernelGGL(fill_zero_kernel<float>, dim3(grid1(n, 256)), dim3(256), 0, s, static_cast<float*>(p), n);
+  } else {
+    const int64_t n = kind_or_f64 == 0 ? 2 * complex_count : complex_count;
+    hipLaunchKernelGGL(fill_zero_kernel<double>, dim3(grid1(n, 256)), dim3(256), 0, s, static_cast<double*>(p), n);
+  }
+  EPHW_CHECK_LAUNCH();
+  return EPHW_OK;
+}
+
+ephw_status scale_phase(int kind, const void* ph, int64_t n, const int32_t* R, int64_t nr, void* out, hipStream_t s) {
+  const int64_t total = 3 * n * nr;
+  if (total <= 0) return EPHW_OK;
+  if (kind == 0)
+    hipLaunchKernelGGL(scale_phase_kernel<double>, dim3(grid1(total, 256)), dim3(256), 0, s,
+                       static_cast<const double*>(ph), n, R, nr, static_cast<double*>(out));
+  else
+    hipLaunchKernelGGL(scale_phase_kernel<float>, dim3(grid1(total, 256)), dim3(256), 0, s,
+                       static_cast<const float*>(ph), n, R, nr, static_cast<float*>(out));
+  EPHW_CHECK_LAUNCH();
+  return EPHW_OK;
+}
+
+// Split-K GEMM for small M x N with a long K: the K range is cut into `chunks`
+// equal pieces (chunks divides K), each a batch entry writing a partial
+// product; the partials are then summed in a fixed order into C.
+ephw_status cgemm_splitk(int kind, const GemmParams& p, int chunks, void* scratch, hipStream_t s) {
+  if (chunks <= 1 || p.K % chunks != 0 || p.offA || p.offB || p.offC || p.n1 != 1 || p.n2 != 1) return cgemm(kind, p, s);
+  const int64_t kc = p.K / chunks;
+  GemmParams q = p;
+  q.K = kc;
+  q.batch = p.batch * chunks;
+  q.n2 = chunks;
+  q.strideA = p.strideA;
+  q.strideA2 = p.transA ? kc * p.lda : kc;
+  q.strideB = p.strideB;
+  q.strideB2 = p.transB ? kc : kc * p.ldb;
+  q.C = scratch;
+  q.ldc = p.N;
+  q.strideC = p.M * p.N * chunks;
+  q.strideC2 = p.M * p.N;
+  q.accumulate = false;
+  q.loss = LossEpilogue();
+  EPHW_TRY(cgemm(kind, q, s));
+  const int64_t mn = p.M * p.N, total = p.batch * mn;
+  if (kind == 0)
+    hipLaunchKernelGGL(splitk_reduce_kernel<double>, dim3(grid1(total, 256)), dim3(256), 0, s,
+                       static_cast<const double*>(scratch), p.batch, chunks, mn, static_cast<double*>(p.C), p.ldc, p.N,
+                       p.strideC, p.accumulate ? 1 : 0);
+  else
+    hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3(grid1(total, 256)), dim3(256), 0, s,
+                       static_cast<const float*>(scratch), p.batch, chunks, mn, static_cast<float*>(p.C), p.ldc, p.N,
+                       p.strideC, p.accumulate ? 1 : 0);
+  EPHW_CHECK_LAUNCH();
+  return EPHW_OK;
+}
+
+// the number of K chunks: a divisor of K, at most `target`, chunks of >= min_len
+int splitk_chunks(int64_t K, int target, int64_t min_len) {
+  for (int c = target; c > 1; --c)
+    if (K % c == 0 && K / c >= min_len) return c;
+  return 1;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// eigenvector derivatives dV/dp_d = V (F o (V^H dM_d V)), d = 0..2, for n
+// points: phase [n][nr] (c128), R [nr][3], mats [nr][dim][dim] (c128), eps,
+// V (c128).  Output dV [3][n][dim][dim] in c128 (`out64`) and, if prec 1,
+// cast to c64 in `out`.
+// ---------------------------------------------------------------------------
+ephw_status eigvec_derivatives(ephw_system* s, const double* phase, const int32_t* R, int64_t n, int64_t nr,
+                               const double* mats, int dim, const double* eps, const double* V, double* out64,
+                               void* out, int kind, hipStream_t st) {
+  const int64_t d2 = (int64_t)dim * dim;
+  // scratch: scaled phases [3][n][nr], dM [3][n][d2], tmp [3][n][d2]
+  EPHW_TRY(ws_need(s, WS_ADJ_A, (size_t)3 * n * nr * 16));
+  EPHW_TRY(ws_need(s, WS_ADJ_B, (size_t)3 * n * d2 * 16));
+  EPHW_TRY(ws_need(s, WS_ADJ_C, (size_t)3 * n * d2 * 16));
+  double* sph = static_cast<double*>(wsp(s, WS_ADJ_A));
+  double* dm = static_cast<double*>(wsp(s, WS_ADJ_B));
+  double* tmp = static_cast<double*>(wsp(s, WS_ADJ_C));
+  EPHW_TRY(scale_phase(0, phase, n, R, nr, sph, st));
+  GemmParams g;
+  g.M = 3 * n;  // all three directions stacked as rows
+  g.N = d2;
+  g.K = nr;
+  g.A = sph;
+  g.lda = nr;
+  g.B = mats;
+  g.ldb = d2;
+  g.C = dm;
+  g.ldc = d2;
+  EPHW_TRY(cgemm(0, g, st));
+  // tmp = dM V   (batch (d, i): V index i)
+  GemmParams a;
+  a.M = dim;
+  a.N = dim;
+  a.K = dim;
+  a.batch = 3 * n;
+  a.n2 = n;
+  a.A = dm;
+  a.lda = dim;
+  a.strideA = n * d2;
+  a.strideA2 = d2;
+  a.B = V;
+  a.ldb = dim;
+  a.strideB = 0;
+  a.strideB2 = d2;
+  a.C = tmp;
+  a.ldc = dim;
+  a.strideC = n * d2;
+  a.strideC2 = d2;
+  EPHW_TRY(cgemm(0, a, st));
+  // dm = V^H tmp
+  GemmParams b = a;
+  b.A = V;
+  b.transA = true;
+  b.conjA = true;
+  b.strideA = 0;
+  b.strideA2 = d2;
+  b.B = tmp;
+  b.strideB = n * d2;
+  b.strideB2 = d2;
+  b.C = dm;
+  EPHW_TRY(cgemm(0, b, st));
+  hipLaunchKernelGGL(eig_mid_kernel, dim3(grid1(3 * n * d2, 256)), dim3(256), 0, st, dm, eps, 3 * n, dim, n);
+  EPHW_CHECK_LAUNCH();
+  // out64 = V dm
+  GemmParams c = a;
+  c.A = V;
+  c.strideA = 0;
+  c.strideA2 = d2;
+  c.B = dm;
+  c.strideB = n * d2;
+  c.strideB2 = d2;
+  c.C = out64;
+  EPHW_TRY(cgemm(0, c, st));
+  if (kind == 1 && out) EPHW_TRY(cast_complex(1, out64, out, 3 * n * d2, st));
+  return EPHW_OK;
+}
+
+}  // namespace ephw
+
+using namespace ephw;
+
+namespace {
+
+// (q batch, k tile) of the unit loops.  The four g(Re,q)-sized buffers get up
+// to 8 GB and the `nbuf` pair-sized buffers up to 24 GB of the 288 GB of HBM:
+// a large k tile matters because every k tile re-reads g(Re,q) in the Re GEMM.
+void unit_shape(const ephw_system* s, int64_t nq, int64_t nk, int64_t E, size_t cs, int nbuf, int64_t* qb_out,
+                int64_t* kt_out) {
+  int64_t qb = s->q_batch;
+  if (qb <= 0) {
+    qb = (int64_t)(8.0e9 / (4.0 * (double)s->ne * E * cs));
+    qb = std::max<int64_t>(1, std::min<int64_t>(qb, 8));
+  }
+  qb = std::min(qb, nq);
+  int64_t kt = (int64_t)(24.0e9 / ((double)nbuf * cs * qb * E));
+  if (kt < 1) kt = 1;
+  if (kt >= 64) kt -= kt % 16;
+  if (s->k_tile > 0) kt = s->k_tile;
+  *qb_out = qb;
+  *kt_out = std::min(kt, nk);
+}
+
+// the rotation GEMMs of one unit, batch b = (il, iq, nu) = ((il nb + iq) nm + nu)
+GemmParams rot_params(int64_t nw, int64_t nm, int64_t nb, int64_t kl) {
+  GemmParams p;
+  p.M = nw;
+  p.N = nw;
+  p.K = nw;
+  p.batch = kl * nb * nm;
+  p.n1 = nb;
+  p.n2 = nm;
+  p.lda = nw;
+  p.ldb = nw;
+  p.ldc = nw;
+  return p;
+}
+
+// standard per-(pair, nu) layout [pair][nu][nw][nw]: i0 = il, i1 = iq, i2 = nu
+void std_strides(int64_t* s0, int64_t* s1, int64_t* s2, int64_t nb, int64_t E, int64_t nw2) {
+  *s0 = nb * E;
+  *s1 = E;
+  *s2 = nw2;
+}
+// pair-transposed layout [pair][nw(row)][nm][nw(col)] with ld = nm*nw: i2 = nu shifts the column block
+void tr_strides(int64_t* s0, int64_t* s1, int64_t* s2, int64_t nb, int64_t E, int64_t nw) {
+  *s0 = nb * E;
+  *s1 = E;
+  *s2 = nw;
+}
+
+}  // namespace
+
+namespace ephw {
+
+// Eq. (7) for systems with more than 32 bands: the band rotations run as
+// batched GEMMs per (q batch, k tile) unit; outputs as in ephw_interpolate.
+ephw_status interpolate_large(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index, int64_t q_offset,
+                              uint32_t flags, void* g_out, double* band_sum, double* loss, uint64_t loss_seed,
+                              double* eps_kq, double* omega, hipStream_t st) {
+  ephw_system* s = ks->sys;
+  if (!kq_index) {
+    set_error("ephw_interpolate: systems with more than 32 bands need a k+q grid index table");
+    return EPHW_EUNSUPPORTED;
+  }
+  if (flags & EPHW_OUT_WANNIER) {
+    set_error("ephw_interpolate: the Wannier-gauge output is limited to nw <= 32");
+    return EPHW_EUNSUPPORTED;
+  }
+  const int kind = prec_kind(ks->prec);
+  const size_t cs = csize(kind);
+  const int64_t nw = s->nw, nm = s->nm, nw2 = nw * nw, E = nm * nw2, nk = ks->nk, ne = s->ne, np = s->np;
+  int64_t qb, kt;
+  unit_shape(s, nq, nk, E, cs, 2, &qb, &kt);
+  // q side
+  EPHW_TRY(ws_need(s, WS_PQ, (size_t)nq * np * cs));
+  EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, np, wsp(s, WS_PQ), nullptr, st));
+  EPHW_TRY(ws_need(s, WS_PQC, (size_t)nq * s->nc * 16));
+  EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), nullptr, st));
+  EPHW_TRY(ws_need(s, WS_LAM, (size_t)nq * nm * 8));
+  EPHW_TRY(ws_need(s, WS_E, (size_t)nq * nm * nm * 16));
+  EPHW_TRY(ws_need(s, WS_HK, (size_t)nq * nm * nm * 16));
+  {
+    GemmParams g;
+    g.M = nq;
+    g.N = nm * nm;
+    g.K = s->nc;
+    g.A = wsp(s, WS_PQC);
+    g.lda = s->nc;
+    g.B = s->c_scaled;
+    g.ldb = nm * nm;
+    g.C = wsp(s, WS_HK);
+    g.ldc = nm * nm;
+    EPHW_TRY(cgemm(0, g, st));
+    const int64_t jw = jacobi_work_doubles((int)nm, nq);
+    if (jw > 0) EPHW_TRY(ws_need(s, WS_JWORK, (size_t)jw * 8));
+    EPHW_TRY(jacobi_eigh(static_cast<const double*>(wsp(s, WS_HK)), nq, (int)nm, static_cast<double*>(wsp(s, WS_LAM)),
+                         static_cast<double*>(wsp(s, WS_E)), jw > 0 ? static_cast<double*>(wsp(s, WS_JWORK)) : nullptr,
+                         s->ctx->status, st));
+  }
+  if (omega) EPHW_TRY(abs_sqrt(static_cast<const double*>(wsp(s, WS_LAM)), omega, nq * nm, st));
+  EPHW_TRY(ws_need(s, WS_U, (size_t)nq * nm * nm * cs));
+  EPHW_TRY(mode_vectors(kind, static_cast<const double*>(wsp(s, WS_E)), nq, (int)nm, s->ism, wsp(s, WS_U), st));
+  const bool rot = (flags & (EPHW_OUT_G | EPHW_OUT_LOSS)) != 0;
+  const bool need_g = (flags & (EPHW_OUT_G | EPHW_OUT_BAND_SUM | EPHW_OUT_LOSS)) != 0;
+  const size_t gsz = (size_t)qb * ne * E * cs, wsz = (size_t)kt * qb * E * cs;
+  const int64_t rot_tiles = cgemm_tiles(kind, nw, nw);
+  if (need_g) {
+    EPHW_TRY(ws_need(s, WS_G, gsz));
+    EPHW_TRY(ws_need(s, WS_GNU, gsz));
+    EPHW_TRY(ws_need(s, WS_W, wsz));
+    EPHW_TRY(ws_need(s, WS_T, wsz));
+    EPHW_TRY(ws_need(s, WS_OFF, (size_t)(kt * qb * nm + kt * qb) * 8));
+    EPHW_TRY(ws_need(s, WS_LOSS, (size_t)kt * qb * nm * rot_tiles * 8));
+  }
+  char* pq = static_cast<char*>(wsp(s, WS_PQ));
+  char* u = static_cast<char*>(wsp(s, WS_U));
+  char* vt = static_cast<char*>(ks->vt);
+  for (int64_t q0 = 0; q0 < nq; q0 += qb) {
+    const int64_t nb = std::min(qb, nq - q0);
+    if (eps_kq)
+      EPHW_TRY(gather_rows(ks->eps, nk, kq_index + q0 * nk, nb * nk, (int)nw, eps_kq + q0 * nk * nw, s->ctx->status,
+                           st));
+    if (!need_g) continue;
+    char* G = static_cast<char*>(wsp(s, WS_G));
+    char* Gnu = static_cast<char*>(wsp(s, WS_GNU));
+    char* W = static_cast<char*>(wsp(s, WS_W));
+    char* Tm = static_cast<char*>(wsp(s, WS_T));
+    int64_t* off = static_cast<int64_t*>(wsp(s, WS_OFF));
+    int64_t* offp = off + kt * qb * nm;
+    double* lossp = static_cast<double*>(wsp(s, WS_LOSS));
+    GemmParams rp;
+    rp.M = nb;
+    rp.N = ne * E;
+    rp.K = np;
+    rp.A = pq + (size_t)q0 * np * cs;
+    rp.lda = np;
+    rp.B = s->g;
+    rp.ldb = rp.N;
+    rp.C = G;
+    rp.ldc = rp.N;
+    {
+      Stage sg_(s, EPHW_STAGE_RP_GEMM, st);
+      EPHW_TRY(cgemm(kind, rp, st));
+    }
+    {
+    Stage sgm_(s, EPHW_STAGE_MODE_ROT, st);
+    if (nm <= 24) {
+      EPHW_TRY(mode_rotate(kind, G, u + (size_t)q0 * nm * nm * cs, Gnu, ne, (int)nb, (int)nm, nw2, st));
+    } else {
+      GemmParams mr;
+      mr.M = nm;
+      mr.N = nw2;
+      mr.K = nm;
+      mr.batch = nb * ne;
+      mr.n2 = ne;
+      mr.A = u + (size_t)q0 * nm * nm * cs;
+      mr.transA = true;
+      mr.lda = nm;
+      mr.strideA = nm * nm;
+      mr.B = G;
+      mr.ldb = nw2;
+      mr.strideB = ne * E;
+      mr.strideB2 = E;
+      mr.C = Gnu;
+      mr.ldc = nw2;
+      mr.strideC = E;
+      mr.strideC2 = nb * E;
+      EPHW_TRY(cgemm(kind, mr, st));
+    }
+    }
+    for (int64_t k0 = 0; k0 < nk; k0 += kt) {
+      const int64_t kl = std::min(kt, nk - k0);
+      const int64_t nbat = kl * nb * nm;
+      GemmParams re;
+      re.M = kl;
+      re.N = nb * E;
+      re.K = ne;
+      re.A = static_cast<const char*>(ks->pk) + (size_t)k0 * ne * cs;
+      re.lda = ne;
+      re.B = Gnu;
+      re.ldb = re.N;
+      re.C = W;
+      re.ldc = re.N;
+      {
+        Stage sg_(s, EPHW_STAGE_RE_GEMM, st);
+        EPHW_TRY(cgemm(kind, re, st));
+      }
+      if (flags & EPHW_OUT_BAND_SUM) {
+        // T_nu = ||W_nu||_F^2: the band rotations are unitary
+        if (kind == 0)
+          hipLaunchKernelGGL(frob_kernel<double>, dim3((unsigned)nbat), dim3(256), 0, st,
+                             reinterpret_cast<const double*>(W), nw2, band_sum + q0 * nk * nm, nb, nm, nk, k0, kl);
+        else
+          hipLaunchKernelGGL(frob_kernel<float>, dim3((unsigned)nbat), dim3(256), 0, st,
+                             reinterpret_cast<const float*>(W), nw2, band_sum + q0 * nk * nm, nb, nm, nk, k0, kl);
+        EPHW_CHECK_LAUNCH();
+      }
+      if (!rot) continue;
+      hipLaunchKernelGGL(kq_offsets_kernel, dim3(grid1(nbat, 256)), dim3(256), 0, st, kq_index, nk, q0, k0, (int)kl,
+                         (int)nb, (int)nm, nw2, off, offp, s->ctx->status);
+      EPHW_CHECK_LAUNCH();
+      Stage sgr_(s, EPHW_STAGE_BAND_ROT, st);
+      GemmParams f4 = rot_params(nw, nm, nb, kl);
+      f4.A = W;
+      std_strides(&f4.strideA, &f4.strideA1, &f4.strideA2, nb, E, nw2);
+      f4.B = vt + (size_t)k0 * nw2 * cs;
+      f4.strideB = nw2;
+      f4.C = Tm;
+      std_strides(&f4.strideC, &f4.strideC1, &f4.strideC2, nb, E, nw2);
+      EPHW_TRY(cgemm(kind, f4, st));
+      GemmParams f5 = rot_params(nw, nm, nb, kl);
+      f5.A = vt;
+      f5.offA = off;
+      f5.transA = true;
+      f5.conjA = true;
+      f5.B = Tm;
+      std_strides(&f5.strideB, &f5.strideB1, &f5.strideB2, nb, E, nw2);
+      if (flags & EPHW_OUT_G) {
+        // g_out[(q0+iq) nk + k0+il][nu][m][n]
+        f5.C = static_cast<char*>(g_out) + ((size_t)q0 * nk + k0) * E * cs;
+        f5.strideC = E;
+        f5.strideC1 = nk * E;
+        f5.strideC2 = nw2;
+      } else {
+        f5.C = Tm;  // not written (loss only)
+      }
+      if (flags & EPHW_OUT_LOSS) {
+        f5.loss.on = true;
+        f5.loss.store = (flags & EPHW_OUT_G) != 0;
+        f5.loss.seed = loss_seed;
+        f5.loss.nk = nk;
+        f5.loss.nm = (int)nm;
+        f5.loss.nw = (int)nw;
+        f5.loss.qb = (int)nb;
+        f5.loss.q0 = q_offset + q0;
+        f5.loss.k0 = k0;
+        f5.loss.partial = lossp;
+      }
+      EPHW_TRY(cgemm(kind, f5, st));
+      if (flags & EPHW_OUT_LOSS) EPHW_TRY(sum_into(lossp, nbat * rot_tiles, loss, st));
+    }
+  }
+  return EPHW_OK;
+}
+
+}  // namespace ephw
+
+extern "C" {
+
+ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index, int64_t q_offset,
+                               uint64_t loss_seed, double* loss, void* dL_dg, double* dL_dk, double* dL_dq,
+                               void* stream) {
+  if (!ks || (!q && nq > 0) || nq < 0 || q_offset < 0 || !kq_index) {
+    set_error("ephw_loss_backward: need a k-set, a q list and a k+q index table");
+    return EPHW_EINVAL;
+  }
+  if (!loss && !dL_dg && !dL_dk && !dL_dq) {
+    set_error("ephw_loss_backward: nothing requested");
+    return EPHW_EINVAL;
+  }
+  if (ks->prec == EPHW_FP32_SPLIT) {
+    set_error("ephw_loss_backward: FP64 or FP32 k-sets only");
+    return EPHW_EUNSUPPORTED;
+  }
+  if (nq == 0) return EPHW_OK;
+  ephw_system* s = ks->sys;
+  hipStream_t st = as_stream(stream);
+  const int kind = prec_kind(ks->prec);
+  const size_t cs = csize(kind);
+  const int64_t nw = s->nw, nm = s->nm, nw2 = nw * nw, E = nm * nw2, nk = ks->nk, ne = s->ne, np = s->np;
+  // unit shape: q batch and k tile within a workspace budget
+  int64_t qb, kt;
+  unit_shape(s, nq, nk, E, cs, 7, &qb, &kt);
+
+  // ---- k side: eigenvector derivatives and scaled phases (cached in the k-set) ----
+  if (!ks->dv) {
+    void* p = nullptr;
+    EPHW_TRY(dev_alloc(&p, (size_t)3 * nk * nw2 * 16));
+    ks->dv64 = static_cast<double*>(p);
+    ks->bytes += (int64_t)3 * nk * nw2 * 16;
+    if (kind == 1) {
+      EPHW_TRY(dev_alloc(&p, (size_t)3 * nk * nw2 * 8));
+      ks->dv = p;
+      ks->bytes += (int64_t)3 * nk * nw2 * 8;
+    } else {
+      ks->dv = ks->dv64;
+    }
+    EPHW_TRY(dev_alloc(&p, (size_t)3 * nk * ne * cs));
+    ks->dpk = p;
+    ks->bytes += (int64_t)3 * nk * ne * cs;
+    EPHW_TRY(eigvec_derivatives(s, ks->pkh, s->r_h, nk, s->nh, s->h_r, (int)nw, ks->eps, ks->v64, ks->dv64,
+                                kind == 1 ? ks->dv : nullptr, kind, st));
+    EPHW_TRY(scale_phase(kind, ks->pk, nk, s->r_e, ne, ks->dpk, st));
+  }
+  // directions with a nonzero lattice component (the others have zero phase derivatives)
+  bool dir_e[3] = {false, false, false}, dir_p[3] = {false, false, false};
+  {
+    std::vector<int32_t> re(3 * ne), rp(3 * np);
+    EPHW_HIP(hipMemcpy(re.data(), s->r_e, re.size() * 4, hipMemcpyDeviceToHost));
+    EPHW_HIP(hipMemcpy(rp.data(), s->r_p, rp.size() * 4, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < ne; ++i)
+      for (int d = 0; d < 3; ++d) dir_e[d] = dir_e[d] || re[3 * i + d] != 0;
+    for (int64_t i = 0; i < np; ++i)
+      for (int d = 0; d < 3; ++d) dir_p[d] = dir_p[d] || rp[3 * i + d] != 0;
+  }
+
+  // ---- q side: phases, D(q) eigensolve, u, du/dq ----
+  EPHW_TRY(ws_need(s, WS_PQ, (size_t)nq * np * cs));
+  EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, np, wsp(s, WS_PQ), nullptr, st));
+  EPHW_TRY(ws_need(s, WS_DPQ, (size_t)3 * nq * np * cs));
+  EPHW_TRY(scale_phase(kind, wsp(s, WS_PQ), nq, s->r_p, np, wsp(s, WS_DPQ), st));
+  EPHW_TRY(ws_need(s, WS_PQC, (size_t)nq * s->nc * 16));
+  EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), nullptr, st));
+  EPHW_TRY(ws_need(s, WS_LAM, (size_t)nq * nm * 8));
+  EPHW_TRY(ws_need(s, WS_E, (size_t)nq * nm * nm * 16));
+  {
+    // D(q) = PqC C_scaled, then Jacobi
+    EPHW_TRY(ws_need(s, WS_HK, (size_t)nq * nm * nm * 16));
+    GemmParams g;
+    g.M = nq;
+    g.N = nm * nm;
+    g.K = s->nc;
+    g.A = wsp(s, WS_PQC);
+    g.lda = s->nc;
+    g.B = s->c_scaled;
+    g.ldb = nm * nm;
+    g.C = wsp(s, WS_HK);
+    g.ldc = nm * nm;
+    EPHW_TRY(cgemm(0, g, st));
+    const int64_t jw = jacobi_work_doubles((int)nm, nq);
+    if (jw > 0) EPHW_TRY(ws_need(s, WS_JWORK, (size_t)jw * 8));
+    EPHW_TRY(jacobi_eigh(static_cast<const double*>(wsp(s, WS_HK)), nq, (int)nm, static_cast<double*>(wsp(s, WS_LAM)),
+                         static_cast<double*>(wsp(s, WS_E)), jw > 0 ? static_cast<double*>(wsp(s, WS_JWORK)) : nullptr,
+                         s->ctx->status, st));
+  }
+  EPHW_TRY(ws_need(s, WS_U, (size_t)nq * nm * nm * cs));
+  EPHW_TRY(mode_vectors(kind, static_cast<const double*>(wsp(s, WS_E)), nq, (int)nm, s->ism, wsp(s, WS_U), st));
+  EPHW_TRY(ws_need(s, WS_DE64, (size_t)3 * nq * nm * nm * 16));
+  EPHW_TRY(ws_need(s, WS_DU, (size_t)3 * nq * nm * nm * cs));
+  EPHW_TRY(eigvec_derivatives(s, static_cast<const double*>(wsp(s, WS_PQC)), s->r_c, nq, s->nc, s->c_scaled, (int)nm,
+                              static_cast<const double*>(wsp(s, WS_LAM)), static_cast<const double*>(wsp(s, WS_E)),
+                              static_cast<double*>(wsp(s, WS_DE64)), nullptr, 0, st));
+  // du = de / sqrt(M) (per row), for the three directions
+  EPHW_TRY(mode_vectors(kind, static_cast<const double*>(wsp(s, WS_DE64)), 3 * nq, (int)nm, s->ism,
+                        wsp(s, WS_DU), st));
+
+  // ---- accumulators ----
+  EPHW_TRY(ws_need(s, WS_VKBAR, (size_t)nk * nw2 * cs));
+  EPHW_TRY(fill_zero(kind, wsp(s, WS_VKBAR), nk * nw2, st));
+  EPHW_TRY(ws_need(s, WS_PAIRS, (size_t)nq * nk * 3 * 8));
+  EPHW_TRY(fill_zero(2, wsp(s, WS_PAIRS), nq * nk * 3, st));
+  // dL/dk and dL/dq accumulate in the caller's buffers (scratch when not requested)
+  EPHW_TRY(ws_need(s, WS_DKACC, (size_t)(nk + nq) * 3 * 8));
+  double* dk_acc = dL_dk ? dL_dk : static_cast<double*>(wsp(s, WS_DKACC));
+  double* dq_acc = dL_dq ? dL_dq : static_cast<double*>(wsp(s, WS_DKACC)) + nk * 3;
+
+  // ---- per-unit buffers ----
+  const size_t gsz = (size_t)qb * ne * E * cs, wsz = (size_t)kt * qb * E * cs;
+  EPHW_TRY(ws_need(s, WS_G, gsz));
+  EPHW_TRY(ws_need(s, WS_GNU, gsz));
+  EPHW_TRY(ws_need(s, WS_GBAR, gsz));
+  EPHW_TRY(ws_need(s, WS_GNUBAR, gsz));
+  EPHW_TRY(ws_need(s, WS_W, wsz));
+  EPHW_TRY(ws_need(s, WS_T, wsz));
+  EPHW_TRY(ws_need(s, WS_YBAR, wsz));
+  EPHW_TRY(ws_need(s, WS_Z, wsz));
+  EPHW_TRY(ws_need(s, WS_WBAR, wsz));
+  EPHW_TRY(ws_need(s, WS_PAIRBAR, (size_t)kt * qb * nw2 * cs * 2));
+  EPHW_TRY(ws_need(s, WS_OFF, (size_t)(kt * qb * nm + kt * qb) * 8));
+  const int64_t rot_tiles = cgemm_tiles(kind, nw, nw);
+  EPHW_TRY(ws_need(s, WS_LOSS, (size_t)kt * qb * nm * rot_tiles * 8));
+  EPHW_TRY(ws_need(s, WS_UBAR, (size_t)qb * nm * nm * cs));
+  const int chunks_u = splitk_chunks(nw2, 16, 256);
+  EPHW_TRY(ws_need(s, WS_SPLIT, (size_t)std::max<int64_t>(qb * chunks_u * nm * nm, 1) * cs));
+  char* G = static_cast<char*>(wsp(s, WS_G));
+  char* Gnu = static_cast<char*>(wsp(s, WS_GNU));
+  char* Gbar = static_cast<char*>(wsp(s, WS_GBAR));
+  char* Gnubar = static_cast<char*>(wsp(s, WS_GNUBAR));
+  char* W = static_cast<char*>(wsp(s, WS_W));
+  char* Tm = static_cast<char*>(wsp(s, WS_T));
+  char* Yb = static_cast<char*>(wsp(s, WS_YBAR));
+  char* Z = static_cast<char*>(wsp(s, WS_Z));
+  char* Wb = static_cast<char*>(wsp(s, WS_WBAR));
+  char* Vkb_pair = static_cast<char*>(wsp(s, WS_PAIRBAR));
+  char* Vkqb_pair = Vkb_pair + (size_t)kt * qb * nw2 * cs;
+  int64_t* off = static_cast<int64_t*>(wsp(s, WS_OFF));
+  int64_t* offp = off + kt * qb * nm;
+  double* lossp = static_cast<double*>(wsp(s, WS_LOSS));
+  char* ubar = static_cast<char*>(wsp(s, WS_UBAR));
+  char* pq = static_cast<char*>(wsp(s, WS_PQ));
+  char* dpq = static_cast<char*>(wsp(s, WS_DPQ));
+  char* u = static_cast<char*>(wsp(s, WS_U));
+  char* du = static_cast<char*>(wsp(s, WS_DU));
+  char* vt = static_cast<char*>(ks->vt);
+  char* vkbar = static_cast<char*>(wsp(s, WS_VKBAR));
+  double* pairs = static_cast<double*>(wsp(s, WS_PAIRS));
+
+  for (int64_t q0 = 0; q0 < nq; q0 += qb) {
+    const int64_t nb = std::min(qb, nq - q0);
+    // Eq. (9): G [nb][ne E]
+    GemmParams rp;
+    rp.M = nb;
+    rp.N = ne * E;
+    rp.K = np;
+    rp.A = pq + (size_t)q0 * np * cs;
+    rp.lda = np;
+    rp.B = s->g;
+    rp.ldb = rp.N;
+    rp.C = G;
+    rp.ldc = rp.N;
+    EPHW_TRY(cgemm(kind, rp, st));
+    // mode vectors: Gnu[e][q] = u[q]^T G[q][e]  (batch (q, e))
+    GemmParams mr;
+    mr.M = nm;
+    mr.N = nw2;
+    mr.K = nm;
+    mr.batch = nb * ne;
+    mr.n2 = ne;
+    mr.A = u + (size_t)q0 * nm * nm * cs;
+    mr.transA = true;
+    mr.lda = nm;
+    mr.strideA = nm * nm;
+    mr.B = G;
+    mr.ldb = nw2;
+    mr.strideB = ne * E;
+    mr.strideB2 = E;
+    mr.C = Gnu;
+    mr.ldc = nw2;
+    mr.strideC = E;
+    mr.strideC2 = nb * E;
+    EPHW_TRY(cgemm(kind, mr, st));
+    for (int64_t k0 = 0; k0 < nk; k0 += kt) {
+      const int64_t kl = std::min(kt, nk - k0);
+      const int64_t nbat = kl * nb * nm;
+      // Eq. (10) Re sum: W [kl][nb E]
+      GemmParams re;
+      re.M = kl;
+      re.N = nb * E;
+      re.K = ne;
+      re.A = static_cast<const char*>(ks->pk) + (size_t)k0 * ne * cs;
+      re.lda = ne;
+      re.B = Gnu;
+      re.ldb = re.N;
+      re.C = W;
+      re.ldc = re.N;
+      EPHW_TRY(cgemm(kind, re, st));
+      hipLaunchKernelGGL(kq_offsets_kernel, dim3(grid1(nbat, 256)), dim3(256), 0, st, kq_index, nk, q0, k0, (int)kl,
+                         (int)nb, (int)nm, nw2, off, offp, s->ctx->status);
+      EPHW_CHECK_LAUNCH();
+      // T_nu = W_nu V(k), stored [pair][m'][nu][n]
+      GemmParams f4 = rot_params(nw, nm, nb, kl);
+      f4.A = W;
+      std_strides(&f4.strideA, &f4.strideA1, &f4.strideA2, nb, E, nw2);
+      f4.B = vt + (size_t)k0 * nw2 * cs;
+      f4.strideB = nw2;
+      f4.C = Tm;
+      f4.ldc = nm * nw;
+      tr_strides(&f4.strideC, &f4.strideC1, &f4.strideC2, nb, E, nw);
+      EPHW_TRY(cgemm(kind, f4, st));
+      // Ybar_nu = 2 w (V(k+q)^H T_nu), stored [pair][m][nu][n]; loss partials
+      GemmParams f5 = rot_params(nw, nm, nb, kl);
+      f5.A = vt;
+      f5.offA = off;
+      f5.transA = true;
+      f5.conjA = true;
+      f5.B = Tm;
+      f5.ldb = nm * nw;
+      tr_strides(&f5.strideB, &f5.strideB1, &f5.strideB2, nb, E, nw);
+      f5.C = Yb;
+      f5.ldc = nm * nw;
+      tr_strides(&f5.strideC, &f5.strideC1, &f5.strideC2, nb, E, nw);
+      f5.loss.on = true;
+      f5.loss.store = true;
+      f5.loss.grad_scale = true;
+      f5.loss.seed = loss_seed;
+      f5.loss.nk = nk;
+      f5.loss.nm = (int)nm;
+      f5.loss.nw = (int)nw;
+      f5.loss.qb = (int)nb;
+      f5.loss.q0 = q_offset + q0;
+      f5.loss.k0 = k0;
+      f5.loss.partial = lossp;
+      EPHW_TRY(cgemm(kind, f5, st));
+      if (loss) EPHW_TRY(sum_into(lossp, nbat * rot_tiles, loss, st));
+      // Z_nu = V(k+q) Ybar_nu  (standard layout)
+      GemmParams b1 = rot_params(nw, nm, nb, kl);
+      b1.A = vt;
+      b1.offA = off;
+      b1.B = Yb;
+      b1.ldb = nm * nw;
+      tr_strides(&b1.strideB, &b1.strideB1, &b1.strideB2, nb, E, nw);
+      b1.C = Z;
+      std_strides(&b1.strideC, &b1.strideC1, &b1.strideC2, nb, E, nw2);
+      EPHW_TRY(cgemm(kind, b1, st));
+      // Wbar_nu = Z_nu V(k)^H
+      GemmParams b2 = rot_params(nw, nm, nb, kl);
+      b2.A = Z;
+      std_strides(&b2.strideA, &b2.strideA1, &b2.strideA2, nb, E, nw2);
+      b2.B = vt + (size_t)k0 * nw2 * cs;
+      b2.transB = true;
+      b2.conjB = true;
+      b2.strideB = nw2;
+      b2.C = Wb;
+      std_strides(&b2.strideC, &b2.strideC1, &b2.strideC2, nb, E, nw2);
+      EPHW_TRY(cgemm(kind, b2, st));
+      // per pair: Vbar(k) part = W^H Z over (nu, m'); Vbar(k+q) = T Ybar^H over (nu, n)
+      GemmParams b3;
+      b3.M = nw;
+      b3.N = nw;
+      b3.K = nm * nw;
+      b3.batch = kl * nb;
+      b3.A = W;
+      b3.transA = true;
+      b3.conjA = true;
+      b3.lda = nw;
+      b3.strideA = E;
+      b3.B = Z;
+      b3.ldb = nw;
+      b3.strideB = E;
+      b3.C = Vkb_pair;
+      b3.ldc = nw;
+      b3.strideC = nw2;
+      EPHW_TRY(cgemm(kind, b3, st));
+      GemmParams b4 = b3;
+      b4.A = Tm;
+      b4.transA = false;
+      b4.conjA = false;
+      b4.lda = nm * nw;
+      b4.B = Yb;
+      b4.transB = true;
+      b4.conjB = true;
+      b4.ldb = nm * nw;
+      b4.C = Vkqb_pair;
+      EPHW_TRY(cgemm(kind, b4, st));
+      // Vbar(k) += sum over the unit's q of the pair parts (fixed order: iq ascending)
+      {
+        const int64_t total = kl * nw2;
+        if (kind == 0)
+          hipLaunchKernelGGL(splitk_reduce_kernel<double>, dim3(grid1(total, 256)), dim3(256), 0, st,
+                             reinterpret_cast<const double*>(Vkb_pair), kl, (int)nb, nw2,
+                             reinterpret_cast<double*>(vkbar + (size_t)k0 * nw2 * cs), nw2, nw2, nw2, 1);
+        else
+          hipLaunchKernelGGL(splitk_reduce_kernel<float>, dim3(grid1(total, 256)), dim3(256), 0, st,
+                             reinterpret_cast<const float*>(Vkb_pair), kl, (int)nb, nw2,
+                             reinterpret_cast<float*>(vkbar + (size_t)k0 * nw2 * cs), nw2, nw2, nw2, 1);
+        EPHW_CHECK_LAUNCH();
+      }
+      // pair scalars Re <Vbar(k+q), dV_d at the k+q grid point> -> pairs[(q0+iq) nk + k0+il][d];
+      // row r = il nb + iq of the pair buffers, offp[r] = grid index * nw2
+      for (int d = 0; d < 3; ++d)
+        EPHW_TRY(row_dot2(kind, Vkqb_pair, nw2, static_cast<const char*>(ks->dv) + (size_t)d * nk * nw2 * cs, 0, offp,
+                          kl * nb, nw2, pairs + (q0 * nk + k0) * 3 + d, nb, 3, nk * 3, false, st));
+      // Eq. (10) adjoint: Gnubar (+)= Pk^H Wbar
+      GemmParams b6;
+      b6.M = ne;
+      b6.N = nb * E;
+      b6.K = kl;
+      b6.A = static_cast<const char*>(ks->pk) + (size_t)k0 * ne * cs;
+      b6.transA = true;
+      b6.conjA = true;
+      b6.lda = ne;
+      b6.B = Wb;
+      b6.ldb = nb * E;
+      b6.C = Gnubar;
+      b6.ldc = nb * E;
+      b6.accumulate = k0 > 0;
+      EPHW_TRY(cgemm(kind, b6, st));
+      // k through the Re phases: dk_d += Re <Wbar, W'_d>, W'_d = (2 pi i Re_d Pk) Gnu
+      for (int d = 0; d < 3; ++d) {
+        if (!dir_e[d]) continue;
+        GemmParams wd = re;
+        wd.A = static_cast<const char*>(ks->dpk) + ((size_t)d * nk + k0) * ne * cs;
+        wd.C = Z;  // Z is free now: reuse as W'_d
+        EPHW_TRY(cgemm(kind, wd, st));
+        EPHW_TRY(row_dot(kind, Wb, nb * E, Z, nb * E, nullptr, kl, nb * E, dk_acc + k0 * 3 + d, 3, true, st));
+      }
+    }
+    // mode-vector adjoint: Gbar[q][e] = conj(u[q]) Gnubar[e][q]
+    GemmParams ma;
+    ma.M = nm;
+    ma.N = nw2;
+    ma.K = nm;
+    ma.batch = nb * ne;
+    ma.n2 = ne;
+    ma.A = u + (size_t)q0 * nm * nm * cs;
+    ma.conjA = true;
+    ma.lda = nm;
+    ma.strideA = nm * nm;
+    ma.B = Gnubar;
+    ma.ldb = nw2;
+    ma.strideB = E;
+    ma.strideB2 = nb * E;
+    ma.C = Gbar;
+    ma.ldc = nw2;
+    ma.strideC = ne * E;
+    ma.strideC2 = E;
+    EPHW_TRY(cgemm(kind, ma, st));
+    // ubar[q] = sum_e conj(G[q][e]) Gnubar[e][q]^T   (split-K over the band pairs)
+    for (int64_t e = 0; e < ne; ++e) {
+      GemmParams ub;
+      ub.M = nm;
+      ub.N = nm;
+      ub.K = nw2;
+      ub.batch = nb;
+      ub.A = G + (size_t)e * E * cs;
+      ub.conjA = true;
+      ub.lda = nw2;
+      ub.strideA = ne * E;
+      ub.B = Gnubar + (size_t)e * nb * E * cs;
+      ub.transB = true;
+      ub.ldb = nw2;
+      ub.strideB = E;
+      ub.C = ubar;
+      ub.ldc = nm;
+      ub.strideC = nm * nm;
+      ub.accumulate = e > 0;
+      EPHW_TRY(cgemm_splitk(kind, ub, chunks_u, wsp(s, WS_SPLIT), st));
+    }
+    // q through u: dq_d += Re <ubar[q], du_d[q]>
+    for (int d = 0; d < 3; ++d)
+      EPHW_TRY(row_dot(kind, ubar, nm * nm, du + ((size_t)d * nq + q0) * nm * nm * cs, nm * nm, nullptr, nb, nm * nm,
+                       dq_acc + q0 * 3 + d, 3, true, st));
+    // dL/dg += Pq^H Gbar
+    if (dL_dg) {
+      GemmParams dg;
+      dg.M = np;
+      dg.N = ne * E;
+      dg.K = nb;
+      dg.A = pq + (size_t)q0 * np * cs;
+      dg.transA = true;
+      dg.conjA = true;
+      dg.lda = np;
+      dg.B = Gbar;
+      dg.ldb = ne * E;
+      dg.C = dL_dg;
+      dg.ldc = ne * E;
+      dg.accumulate = true;
+      EPHW_TRY(cgemm(kind, dg, st));
+    }
+    // q through the Rp phases: dq_d += Re <Gbar, G'_d>, G'_d = (2 pi i Rp_d Pq) g
+    for (int d = 0; d < 3; ++d) {
+      if (!dir_p[d]) continue;
+      GemmParams gd = rp;
+      gd.A = dpq + ((size_t)d * nq + q0) * np * cs;
+      gd.C = Gnu;  // free after the k loop
+      EPHW_TRY(cgemm(kind, gd, st));
+      EPHW_TRY(row_dot(kind, Gbar, ne * E, Gnu, ne * E, nullptr, nb, ne * E, dq_acc + q0 * 3 + d, 3, true, st));
+    }
+  }
+  // k through V(k): dk_d += Re <Vbar(k), dV_d(k)>
+  for (int d = 0; d < 3; ++d)
+    EPHW_TRY(row_dot(kind, vkbar, nw2, static_cast<const char*>(ks->dv) + (size_t)d * nk * nw2 * cs, nw2, nullptr, nk,
+                     nw2, dk_acc + d, 3, true, st));
+  // k and q through V(k+q): sum the pair scalars over q (for k) and over k (for q)
+  hipLaunchKernelGGL(pair_sums_kernel, dim3(grid1((nk + nq) * 3, 256)), dim3(256), 0, st, pairs, nq, nk, dk_acc,
+                     dq_acc);
+  EPHW_CHECK_LAUNCH();
+  return EPHW_OK;
+}
+
+}  // extern "C"

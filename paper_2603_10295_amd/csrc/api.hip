@@ -237,6 +237,16 @@ ephw_status ephw_system_load(ephw_ctx* ctx, const ephw_system_desc* d, ephw_syst
   return EPHW_OK;
 }
 
+ephw_status ephw_system_set_g(ephw_system* s, const void* g, void* stream) {
+  if (!s || !g) {
+    set_error("ephw_system_set_g: NULL argument");
+    return EPHW_EINVAL;
+  }
+  const size_t bytes = (size_t)s->np * s->ne * s->nm * s->nw * s->nw * csize(s->g_kind);
+  EPHW_HIP(hipMemcpyAsync(s->g, g, bytes, hipMemcpyDeviceToDevice, as_stream(stream)));
+  return EPHW_OK;
+}
+
 ephw_status ephw_system_bytes(const ephw_system* s, int64_t* bytes) {
   if (!s || !bytes) {
     set_error("ephw_system_bytes: NULL argument");
@@ -289,6 +299,15 @@ ephw_status ephw_profile_read(ephw_system* s, double* ms, int64_t* launches) {
   }
   s->prof.recs.clear();
   return result;
+}
+
+ephw_status ephw_set_k_tile(ephw_system* s, int32_t k_tile) {
+  if (!s || k_tile < 0) {
+    set_error("ephw_set_k_tile: need a system and k_tile >= 0");
+    return EPHW_EINVAL;
+  }
+  s->k_tile = k_tile;
+  return EPHW_OK;
 }
 
 ephw_status ephw_bands(ephw_system* s, const double* k, int64_t nk, double* eps, void* vecs,
@@ -397,7 +416,8 @@ ephw_status ephw_phase_sum_rp(ephw_system* s, const double* q, int64_t nq, int32
 ephw_status ephw_kset_free(ephw_kset* ks) {
   if (!ks) return EPHW_OK;
   (void)hipDeviceSynchronize();
-  void* ptrs[] = {ks->k, ks->pk, ks->pk_lo, ks->pkh, ks->eps, ks->v64, ks->vt};
+  void* ptrs[] = {ks->k, ks->pk, ks->pk_lo, ks->pkh, ks->eps, ks->v64, ks->vt, ks->dv64, ks->dpk,
+                  ks->dv != ks->dv64 ? ks->dv : nullptr};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete ks;
@@ -514,11 +534,10 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
     set_error("ephw_interpolate: the loss is defined on the rotated g only");
     return EPHW_EINVAL;
   }
-  if (s->nw > 32) {
-    set_error("ephw_interpolate: this build rotates bands for nw <= 32");
-    return EPHW_EUNSUPPORTED;
-  }
   if (nq == 0) return EPHW_OK;
+  if (s->nw > 32)
+    return interpolate_large(ks, q, nq, kq_index, q_offset, flags, g_out, band_sum, loss, loss_seed, eps_kq, omega,
+                             as_stream(stream));
   hipStream_t st = as_stream(stream);
   const int kind = prec_kind(prec);
   const bool split = prec == EPHW_FP32_SPLIT;

@@ -5,11 +5,30 @@
 
 namespace ephw {
 
+// Weighted |C|^2 epilogue for the loss L = sum w |g|^2 (SplitMix64 weights).
+// Batch b is read as (il, iq, nu) = (b / (qb nm), (b / nm) % qb, b % nm): k
+// point k0 + il, q point q0 + iq, mode nu; row m and column n of C are band
+// indices.  Every workgroup writes the sum of w |c|^2 over its tile to
+// partial[b * tiles_per_batch + tile].  With grad_scale the stored value is
+// 2 w c (the gradient of L with respect to g) instead of c.
+struct LossEpilogue {
+  bool on = false;
+  bool store = true;        // also store C (plain or scaled)
+  bool grad_scale = false;
+  uint64_t seed = 0;
+  int64_t nk = 0;           // size of the k set (element index stride)
+  int nm = 0, nw = 0, qb = 0;
+  int64_t q0 = 0, k0 = 0;
+  double* partial = nullptr;
+};
+
 // All sizes, leading dimensions, strides and offsets count complex elements.
 // Operands are interleaved complex (T re, T im), T = double (prec 0) or float
 // (prec 1).  "trans" means the operand is stored transposed (A as [K][M],
-// B as [N][K]); "conj" conjugates it on load.  Batch b uses
-//   A + (offA ? offA[b] : b * strideA), likewise for B and C.
+// B as [N][K]); "conj" conjugates it on load.  Batch b is decomposed as
+// b = (i0 * n1 + i1) * n2 + i2 and uses
+//   A + (offA ? offA[b] : i0 * strideA + i1 * strideA1 + i2 * strideA2),
+// likewise for B and C (n1 = n2 = 1 gives the plain stride b * strideA).
 struct GemmParams {
   int64_t M = 0, N = 0, K = 0, batch = 1;
   const void* A = nullptr;
@@ -24,8 +43,13 @@ struct GemmParams {
   const int64_t* offC = nullptr;
   bool transA = false, conjA = false, transB = false, conjB = false;
   bool accumulate = false;
+  int64_t n1 = 1, n2 = 1;
+  int64_t strideA1 = 0, strideA2 = 0, strideB1 = 0, strideB2 = 0, strideC1 = 0, strideC2 = 0;
+  LossEpilogue loss;
   int64_t batch_base = 0;  // internal: first batch index of this launch
 };
+// workgroup tiles per batch entry of a GEMM (size of the loss partial block)
+int64_t cgemm_tiles(int prec, int64_t M, int64_t N);
 
 // prec: 0 = complex128 on FP64 MFMA, 1 = complex64 on FP32 MFMA
 ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream);

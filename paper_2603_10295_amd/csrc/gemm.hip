@@ -66,7 +66,19 @@ struct TileJob {
   int64_t M, N, K, lda, ldb, ldc;
   T sa, sb;          // -1 conjugates the operand's imaginary part
   bool accumulate;
+  LossEpilogue loss;          // loss.on false: plain store
+  int64_t batch;              // batch index (for the loss epilogue)
+  int64_t tile, ntiles;       // tile index within the batch entry, tiles per entry
 };
+
+__device__ __forceinline__ double splitmix_weight(uint64_t seed, uint64_t index) {
+  // SplitMix64 (Steele, Lea & Flood 2014): index-th output for `seed`
+  uint64_t z = seed + (index + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return 0.5 + (double)(z >> 40) * 0x1p-24;
+}
 
 template <typename T, int BM, int BN, int BK, int WM, int WN, bool SPLIT>
 struct TileShape {
@@ -109,6 +121,8 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
 
   T ra[AE][2], rb[BE][2], rl[SPLIT ? AE : 1][2];
 
+  // Branch-free loads: an out-of-range element reads element 0 (always
+  // valid) and is then replaced by zero, so the loop body is straight-line.
   auto load = [&](int64_t k0) {
 #pragma unroll
     for (int i = 0; i < AE; ++i) {
@@ -116,16 +130,16 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
       int mm, kk;
       if (TA) { kk = e / BM; mm = e % BM; } else { mm = e / BK; kk = e % BK; }
       const int64_t gm = m0 + mm, gk = k0 + kk;
-      T re = 0, im = 0, lre = 0, lim = 0;
-      if (gm < M && gk < K) {
-        const int64_t off = TA ? gk * j.lda + gm : gm * j.lda + gk;
-        re = A[2 * off];
-        im = A[2 * off + 1];
-        if (SPLIT) { lre = Alo[2 * off]; lim = Alo[2 * off + 1]; }
+      const bool ok = gm < M && gk < K;
+      const int64_t off = ok ? (TA ? gk * j.lda + gm : gm * j.lda + gk) : 0;
+      const T re = A[2 * off], im = A[2 * off + 1];
+      ra[i][0] = ok ? re : T(0);
+      ra[i][1] = ok ? im : T(0);
+      if (SPLIT) {
+        const T lre = Alo[2 * off], lim = Alo[2 * off + 1];
+        rl[i][0] = ok ? lre : T(0);
+        rl[i][1] = ok ? lim : T(0);
       }
-      ra[i][0] = re;
-      ra[i][1] = im;
-      if (SPLIT) { rl[i][0] = lre; rl[i][1] = lim; }
     }
 #pragma unroll
     for (int i = 0; i < BE; ++i) {
@@ -133,14 +147,11 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
       int nn, kk;
       if (TB) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }
       const int64_t gn = n0 + nn, gk = k0 + kk;
-      T re = 0, im = 0;
-      if (gn < N && gk < K) {
-        const int64_t off = TB ? gn * j.ldb + gk : gk * j.ldb + gn;
-        re = B[2 * off];
-        im = B[2 * off + 1];
-      }
-      rb[i][0] = re;
-      rb[i][1] = im;
+      const bool ok = gn < N && gk < K;
+      const int64_t off = ok ? (TB ? gn * j.ldb + gk : gk * j.ldb + gn) : 0;
+      const T re = B[2 * off], im = B[2 * off + 1];
+      rb[i][0] = ok ? re : T(0);
+      rb[i][1] = ok ? im : T(0);
     }
   };
   auto stash = [&]() {
@@ -175,12 +186,10 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
   const int lrow = lane >> 4;   // k row inside one MFMA (0..3); also the lane group
   const int lcol = lane & 15;   // m (A) or n (B) inside one 16-block
 
-  load(0);
-  stash();
-  __syncthreads();
-  for (int64_t k0 = 0; k0 < K; k0 += BK) {
-    const bool more = k0 + BK < K;
-    if (more) load(k0 + BK);
+  // One BK slab of MFMAs from LDS.  The four real products of every block are
+  // issued product by product across all blocks, so consecutive MFMAs never
+  // depend on each other.
+  auto compute = [&]() {
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + lrow;
@@ -199,12 +208,19 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int jj = 0; jj < FN; ++jj) {
-          acc_r[i][jj] = Mfma<T>::op(ar[i], br[jj], acc_r[i][jj]);
-          acc_r[i][jj] = Mfma<T>::op(nai[i], bi[jj], acc_r[i][jj]);
-          acc_i[i][jj] = Mfma<T>::op(ar[i], bi[jj], acc_i[i][jj]);
-          acc_i[i][jj] = Mfma<T>::op(ai[i], br[jj], acc_i[i][jj]);
-        }
+        for (int jj = 0; jj < FN; ++jj) acc_r[i][jj] = Mfma<T>::op(ar[i], br[jj], acc_r[i][jj]);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < FN; ++jj) acc_i[i][jj] = Mfma<T>::op(ar[i], bi[jj], acc_i[i][jj]);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < FN; ++jj) acc_r[i][jj] = Mfma<T>::op(nai[i], bi[jj], acc_r[i][jj]);
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < FN; ++jj) acc_i[i][jj] = Mfma<T>::op(ai[i], br[jj], acc_i[i][jj]);
       if (SPLIT) {
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
@@ -217,20 +233,64 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
 #pragma unroll
           for (int jj = 0; jj < FN; ++jj) {
             acc_r[i][jj] = Mfma<T>::op(ar[i], br[jj], acc_r[i][jj]);
-            acc_r[i][jj] = Mfma<T>::op(nai[i], bi[jj], acc_r[i][jj]);
             acc_i[i][jj] = Mfma<T>::op(ar[i], bi[jj], acc_i[i][jj]);
+          }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+          for (int jj = 0; jj < FN; ++jj) {
+            acc_r[i][jj] = Mfma<T>::op(nai[i], bi[jj], acc_r[i][jj]);
             acc_i[i][jj] = Mfma<T>::op(ai[i], br[jj], acc_i[i][jj]);
           }
       }
     }
+  };
+
+  // K loop: the next slab is fetched into registers while the current one is
+  // multiplied; the last slab is peeled so the loop body has no branches.
+  load(0);
+  stash();
+  __syncthreads();
+  const int64_t nslab = (K + BK - 1) / BK;
+  for (int64_t sl = 1; sl < nslab; ++sl) {
+    load(sl * BK);
+    compute();
     __syncthreads();
-    if (more) {
-      stash();
-      __syncthreads();
-    }
+    stash();
+    __syncthreads();
   }
+  compute();
 
   // --- epilogue: lane holds column lcol of every block, rows per Mfma<T>::row --
+  if (!j.loss.on) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int jj = 0; jj < FN; ++jj) {
+        const int64_t col = n0 + wn * TN + jj * 16 + lcol;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = m0 + wm * TM + i * 16 + Mfma<T>::row(lrow, v);
+          if (row < M && col < N) {
+            T* c = j.C + 2 * (row * j.ldc + col);
+            T re = acc_r[i][jj][v], im = acc_i[i][jj][v];
+            if (j.accumulate) { re += c[0]; im += c[1]; }
+            c[0] = re;
+            c[1] = im;
+          }
+        }
+      }
+    return;
+  }
+  // weighted |c|^2: element index ((((q nk + k) nm + nu) nw + m) nw + n)
+  const LossEpilogue& L = j.loss;
+  const int64_t il = j.batch / ((int64_t)L.qb * L.nm);
+  const int64_t iq = (j.batch / L.nm) % L.qb;
+  const int64_t nu = j.batch % L.nm;
+  const uint64_t base =
+      (((uint64_t)(L.q0 + iq) * (uint64_t)L.nk + (uint64_t)(L.k0 + il)) * (uint64_t)L.nm + (uint64_t)nu) *
+      (uint64_t)L.nw * (uint64_t)L.nw;
+  double part = 0.0;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -240,14 +300,34 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
       for (int v = 0; v < 4; ++v) {
         const int64_t row = m0 + wm * TM + i * 16 + Mfma<T>::row(lrow, v);
         if (row < M && col < N) {
-          T* c = j.C + 2 * (row * j.ldc + col);
-          T re = acc_r[i][jj][v], im = acc_i[i][jj][v];
-          if (j.accumulate) { re += c[0]; im += c[1]; }
-          c[0] = re;
-          c[1] = im;
+          const T re = acc_r[i][jj][v], im = acc_i[i][jj][v];
+          const double w = splitmix_weight(L.seed, base + (uint64_t)(row * L.nw + col));
+          part += w * ((double)re * (double)re + (double)im * (double)im);
+          if (L.store) {
+            T* c = j.C + 2 * (row * j.ldc + col);
+            if (L.grad_scale) {
+              c[0] = (T)(2.0 * w) * re;
+              c[1] = (T)(2.0 * w) * im;
+            } else {
+              c[0] = re;
+              c[1] = im;
+            }
+          }
         }
       }
     }
+  // workgroup sum in a fixed order: waves through LDS (free after the K loop)
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
+  double* red = reinterpret_cast<double*>(smem);
+  __syncthreads();
+  if (lane == 0) red[wave] = part;
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < WM * WN; ++w) tot += red[w];
+    L.partial[j.batch * j.ntiles + j.tile] = tot;
+  }
+  __syncthreads();
 }
 
 // tile (tm, tn) of logical tile index t: groups of kGroupM tile-rows
@@ -264,9 +344,10 @@ __device__ __forceinline__ void tile_coords(int64_t t, int64_t tiles_m, int64_t 
 
 template <typename T>
 __device__ __forceinline__ TileJob<T> job_of(const GemmParams& p, int64_t b) {
-  const int64_t oa = p.offA ? p.offA[b] : b * p.strideA;
-  const int64_t ob = p.offB ? p.offB[b] : b * p.strideB;
-  const int64_t oc = p.offC ? p.offC[b] : b * p.strideC;
+  const int64_t i2 = b % p.n2, i1 = (b / p.n2) % p.n1, i0 = b / (p.n1 * p.n2);
+  const int64_t oa = p.offA ? p.offA[b] : i0 * p.strideA + i1 * p.strideA1 + i2 * p.strideA2;
+  const int64_t ob = p.offB ? p.offB[b] : i0 * p.strideB + i1 * p.strideB1 + i2 * p.strideB2;
+  const int64_t oc = p.offC ? p.offC[b] : i0 * p.strideC + i1 * p.strideC1 + i2 * p.strideC2;
   TileJob<T> j;
   j.A = static_cast<const T*>(p.A) + 2 * oa;
   j.Alo = p.A_lo ? static_cast<const T*>(p.A_lo) + 2 * oa : nullptr;
@@ -281,6 +362,10 @@ __device__ __forceinline__ TileJob<T> job_of(const GemmParams& p, int64_t b) {
   j.sa = p.conjA ? T(-1) : T(1);
   j.sb = p.conjB ? T(-1) : T(1);
   j.accumulate = p.accumulate;
+  j.loss = p.loss;
+  j.batch = b;
+  j.tile = 0;
+  j.ntiles = 1;
   return j;
 }
 
@@ -292,7 +377,9 @@ __global__ void __launch_bounds__(64 * WM * WN)
   const int64_t logical = xcd_remap(blockIdx.x, tiles_m * tiles_n);
   int64_t tm, tn;
   tile_coords(logical, tiles_m, tiles_n, &tm, &tn);
-  const TileJob<T> j = job_of<T>(p, p.batch_base + blockIdx.y);
+  TileJob<T> j = job_of<T>(p, p.batch_base + blockIdx.y);
+  j.tile = tm * tiles_n + tn;
+  j.ntiles = tiles_m * tiles_n;
   gemm_tile<T, BM, BN, BK, WM, WN, TA, TB, SPLIT>(j, tm * BM, tn * BN, smem);
 }
 
@@ -342,6 +429,10 @@ __global__ void __launch_bounds__(256)
     j.sa = T(1);
     j.sb = T(1);
     j.accumulate = false;
+    j.loss = LossEpilogue();
+    j.batch = 0;
+    j.tile = 0;
+    j.ntiles = 1;
     if (P.cfg == 0)
       gemm_tile<T, G::LM, G::LN, 16, 2, 2, false, false, false>(j, tm * G::LM, tn * G::LN, smem);
     else
@@ -379,6 +470,10 @@ ephw_status dispatch_trans(const GemmParams& p, hipStream_t s) {
 }
 
 }  // namespace
+
+int64_t cgemm_tiles(int prec, int64_t M, int64_t N) {
+  return prec == 0 ? ceil_div(M, 128) * ceil_div(N, 64) : ceil_div(M, 128) * ceil_div(N, 128);
+}
 
 void cgemm_tile_shape(int prec, int cfg, int* bm, int* bn) {
   if (cfg != 0) {

@@ -55,6 +55,10 @@ inline ephw_status upload(X** dst, const X* src, size_t count, int64_t* owner_by
 inline int prec_kind(int32_t prec) { return prec == EPHW_FP64 ? 0 : 1; }
 inline size_t csize(int kind) { return kind == 0 ? 16 : 8; }
 
+ephw_status interpolate_large(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index, int64_t q_offset,
+                              uint32_t flags, void* g_out, double* band_sum, double* loss, uint64_t loss_seed,
+                              double* eps_kq, double* omega, hipStream_t st);
+
 }  // namespace ephw
 
 using namespace ephw;
@@ -66,7 +70,10 @@ struct ephw_ctx {
 
 enum WsSlot {
   WS_PQ, WS_PQ_LO, WS_PQH, WS_PQC, WS_D, WS_LAM, WS_E, WS_U, WS_G, WS_GNU, WS_W, WS_BQ, WS_HKQ,
-  WS_EKQ, WS_VKQ64, WS_VKQ, WS_JWORK, WS_LOSS, WS_PH, WS_HK, WS_EPS, WS_V64, WS_COUNT
+  WS_EKQ, WS_VKQ64, WS_VKQ, WS_JWORK, WS_LOSS, WS_PH, WS_HK, WS_EPS, WS_V64,
+  // adjoint and large-band rotations
+  WS_ADJ_A, WS_ADJ_B, WS_ADJ_C, WS_DPQ, WS_DE64, WS_DU, WS_VKBAR, WS_PAIRS, WS_DKACC, WS_GBAR, WS_GNUBAR, WS_T,
+  WS_YBAR, WS_Z, WS_WBAR, WS_PAIRBAR, WS_OFF, WS_UBAR, WS_SPLIT, WS_COUNT
 };
 
 // HIP-event brackets around the stages of a call, summed on request
@@ -103,6 +110,7 @@ struct ephw_system {
   double* ism = nullptr;      // [nm] 1/sqrt(M_kappa) per mode index
   void* g = nullptr;
   int32_t q_batch = 0;
+  int32_t k_tile = 0;
   int64_t bytes = 0;
   DevBuf ws[WS_COUNT];
 };
@@ -119,6 +127,10 @@ struct ephw_kset {
   double* eps = nullptr;    // [nk][nw]
   double* v64 = nullptr;    // c128 [nk][nw][nw]
   void* vt = nullptr;       // T [nk][nw][nw]
+  // derivatives for the adjoint, made on first use
+  double* dv64 = nullptr;   // c128 [3][nk][nw][nw]: dV/dk_d
+  void* dv = nullptr;       // T copy (aliases dv64 for FP64)
+  void* dpk = nullptr;      // T [3][nk][ne]: 2 pi i Re_d e^{2 pi i k.Re}
 };
 
 // Records a start event on construction and a stop event on destruction

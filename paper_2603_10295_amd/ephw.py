@@ -25,9 +25,9 @@ OUT_G, OUT_BAND_SUM, OUT_LOSS, OUT_WANNIER = 1, 2, 4, 8
 
 EXPORTS = [
     "ephw_ctx_create", "ephw_ctx_destroy", "ephw_ctx_check", "ephw_system_load",
-    "ephw_system_free", "ephw_system_bytes", "ephw_bands", "ephw_phonons", "ephw_phase_sum_rp",
+    "ephw_system_free", "ephw_system_set_g", "ephw_system_bytes", "ephw_bands", "ephw_phonons", "ephw_phase_sum_rp",
     "ephw_kset_create", "ephw_kset_free", "ephw_kset_bands", "ephw_interpolate",
-    "ephw_set_q_batch", "ephw_profile_enable", "ephw_profile_read", "ephw_batch_create",
+    "ephw_loss_backward", "ephw_set_q_batch", "ephw_set_k_tile", "ephw_profile_enable", "ephw_profile_read", "ephw_batch_create",
     "ephw_batch_run", "ephw_batch_shape", "ephw_batch_stats", "ephw_batch_free", "ephw_status_string",
     "ephw_last_error", "ephw_version",
 ]
@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
         "ephw_ctx_check": [vp, vp],
         "ephw_system_load": [vp, ctypes.POINTER(SystemDesc), pp],
         "ephw_system_free": [vp],
+        "ephw_system_set_g": [vp, vp, vp],
         "ephw_system_bytes": [vp, ctypes.POINTER(ctypes.c_int64)],
         "ephw_bands": [vp, vp, i64, vp, vp, vp],
         "ephw_phonons": [vp, vp, i64, vp, vp, vp, vp],
@@ -102,6 +103,8 @@ def lib() -> ctypes.CDLL:
         "ephw_kset_bands": [vp, vp, vp, vp],
         "ephw_interpolate": [vp, vp, i64, vp, i64, i32, u32, vp, vp, vp, u64, vp, vp, vp],
         "ephw_set_q_batch": [vp, i32],
+        "ephw_set_k_tile": [vp, i32],
+        "ephw_loss_backward": [vp, vp, i64, vp, i64, u64, vp, vp, vp, vp, vp],
         "ephw_profile_enable": [vp, i32],
         "ephw_profile_read": [vp, vp, vp],
         "ephw_batch_create": [vp, ctypes.POINTER(BatchItem), i32, ctypes.POINTER(BatchOptions), vp, pp],
@@ -216,6 +219,10 @@ class System:
         return cls(ctx, nw=s.nw, na=s.na, r_e=s.r_e, r_p=s.r_p, r_h=s.r_h, r_c=s.r_c, h_r=s.h_r,
                    c_r=s.c_r, mass=s.mass, g=s.g, w_e=s.w_e, w_p=s.w_p, w_h=s.w_h, w_c=s.w_c)
 
+    def set_g(self, g, stream=None):
+        """Copy a device tensor (same shape/dtype as the loaded g) into the system."""
+        _check(lib().ephw_system_set_g(self.handle, _ptr(g), _stream(stream)), "ephw_system_set_g")
+
     def bytes(self) -> int:
         v = ctypes.c_int64()
         _check(lib().ephw_system_bytes(self.handle, ctypes.byref(v)), "ephw_system_bytes")
@@ -223,6 +230,9 @@ class System:
 
     def set_q_batch(self, qb: int):
         _check(lib().ephw_set_q_batch(self.handle, int(qb)), "ephw_set_q_batch")
+
+    def set_k_tile(self, kt: int):
+        _check(lib().ephw_set_k_tile(self.handle, int(kt)), "ephw_set_k_tile")
 
     def profile(self, enable: bool):
         _check(lib().ephw_profile_enable(self.handle, 1 if enable else 0), "ephw_profile_enable")
@@ -347,6 +357,14 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def loss_backward(ks: KSet, q, kq_index, *, q_offset: int = 0, loss_seed: int = 0, loss=None, dL_dg=None,
+                  dL_dk=None, dL_dq=None, stream=None):
+    """L += sum w |g|^2 and the gradients (accumulated) for the k-set and q list."""
+    _check(lib().ephw_loss_backward(ks.handle, _ptr(q), q.shape[0], _ptr(kq_index), int(q_offset), int(loss_seed),
+                                    _ptr(loss), _ptr(dL_dg), _ptr(dL_dk), _ptr(dL_dq), _stream(stream)),
+           "ephw_loss_backward")
 
 
 def version() -> int:

@@ -247,3 +247,29 @@ def test_interpolate_fp32_gauge_invariant(run, toy32, toy32_ref, prec):
     assert norm < 1e-5
     assert rel_max(out["band_sum"], oracle.band_sums(r["ghat"])) < 1e-5
     np.testing.assert_allclose(out["eps_k"], r["eps_k"], atol=1e-12 * np.abs(r["eps_k"]).max())
+
+
+@pytest.mark.parametrize("nw,na", [(64, 1), (200, 50)])
+def test_large_jacobi_matches_lapack(run, nw, na):
+    """n > 32 eigensolves (global-memory Jacobi): the ribbon's H(k) (n = 200)
+    and D(q) (n = 150) orders."""
+    r = synth.axis_box(-2, 2, axis=1)
+    h_r = synth.hermitian_paired(r, nw, synth.rng([nw, 77], synth.STREAM_H), complex_=True)
+    c_r = synth.hermitian_paired(r, 3 * na, synth.rng([nw, 77], synth.STREAM_C), complex_=False)
+    # g plays no part in the eigensolves: a minimal one
+    s = synth.System(nw=nw, na=na, r_e=r[:1], r_p=r[:1], r_h=r, r_c=r, h_r=h_r, c_r=c_r, mass=np.ones(na),
+                     g=np.zeros((1, 1, 3 * na, nw, nw), dtype=np.complex64))
+    k = np.zeros((5, 3))
+    k[:, 1] = np.array([0.0, 0.1, 0.25, 0.5, 0.77])
+    sysh = run.system(s)
+    eps, vec = run.bands(sysh, k)
+    ref_eps, _ = oracle.bands(s, k)
+    h = oracle.hamiltonian_k(s, k)
+    hn = np.linalg.norm(h, axis=(1, 2))
+    assert np.abs(eps - ref_eps).max() <= 1e-11 * hn.max()
+    res = np.linalg.norm(h @ vec - vec * eps[:, None, :], axis=(1, 2))
+    assert np.all(res <= 1e-11 * hn)
+    assert np.abs(np.conj(np.swapaxes(vec, 1, 2)) @ vec - np.eye(nw)).max() < 1e-12
+    lam, om, ev = run.phonons(sysh, k)
+    ref_lam, _, _ = oracle.phonons(s, k)
+    assert np.abs(lam - ref_lam).max() <= 1e-11 * np.abs(ref_lam).max()
