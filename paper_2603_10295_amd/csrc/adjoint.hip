@@ -367,32 +367,25 @@ void unit_shape(const ephw_system* s, int64_t nq, int64_t nk, int64_t E, size_t 
   *kt_out = std::min(kt, nk);
 }
 
-// the rotation GEMMs of one unit, batch b = (il, iq, nu) = ((il nb + iq) nm + nu)
-GemmParams rot_params(int64_t nw, int64_t nm, int64_t nb, int64_t kl) {
+// Pair-stacked rotation GEMM: batch b = il nb + iq runs over the (k, q) pairs
+// of a unit; A is the pair's nm nw x nw stack of per-mode blocks (rows
+// (nu, row)), so every launch has nm nw rows and nw columns instead of nm
+// separate nw x nw products.  Pair buffers are [il][iq][E].
+GemmParams pair_params(int64_t nw, int64_t nm, int64_t nb, int64_t kl, int64_t E) {
   GemmParams p;
-  p.M = nw;
+  p.M = nm * nw;
   p.N = nw;
   p.K = nw;
-  p.batch = kl * nb * nm;
+  p.batch = kl * nb;
   p.n1 = nb;
-  p.n2 = nm;
   p.lda = nw;
   p.ldb = nw;
   p.ldc = nw;
+  p.strideA = nb * E;
+  p.strideA1 = E;
+  p.strideC = nb * E;
+  p.strideC1 = E;
   return p;
-}
-
-// standard per-(pair, nu) layout [pair][nu][nw][nw]: i0 = il, i1 = iq, i2 = nu
-void std_strides(int64_t* s0, int64_t* s1, int64_t* s2, int64_t nb, int64_t E, int64_t nw2) {
-  *s0 = nb * E;
-  *s1 = E;
-  *s2 = nw2;
-}
-// pair-transposed layout [pair][nw(row)][nm][nw(col)] with ld = nm*nw: i2 = nu shifts the column block
-void tr_strides(int64_t* s0, int64_t* s1, int64_t* s2, int64_t nb, int64_t E, int64_t nw) {
-  *s0 = nb * E;
-  *s1 = E;
-  *s2 = nw;
 }
 
 }  // namespace
@@ -450,14 +443,14 @@ ephw_status interpolate_large(ephw_kset* ks, const double* q, int64_t nq, const 
   const bool rot = (flags & (EPHW_OUT_G | EPHW_OUT_LOSS)) != 0;
   const bool need_g = (flags & (EPHW_OUT_G | EPHW_OUT_BAND_SUM | EPHW_OUT_LOSS)) != 0;
   const size_t gsz = (size_t)qb * ne * E * cs, wsz = (size_t)kt * qb * E * cs;
-  const int64_t rot_tiles = cgemm_tiles(kind, nw, nw);
+  const int64_t rot_tiles = cgemm_tiles(kind, nm * nw, nw);  // per pair
   if (need_g) {
     EPHW_TRY(ws_need(s, WS_G, gsz));
     EPHW_TRY(ws_need(s, WS_GNU, gsz));
     EPHW_TRY(ws_need(s, WS_W, wsz));
     EPHW_TRY(ws_need(s, WS_T, wsz));
     EPHW_TRY(ws_need(s, WS_OFF, (size_t)(kt * qb * nm + kt * qb) * 8));
-    EPHW_TRY(ws_need(s, WS_LOSS, (size_t)kt * qb * nm * rot_tiles * 8));
+    EPHW_TRY(ws_need(s, WS_LOSS, (size_t)kt * qb * rot_tiles * 8));
   }
   char* pq = static_cast<char*>(wsp(s, WS_PQ));
   char* u = static_cast<char*>(wsp(s, WS_U));
@@ -547,32 +540,35 @@ ephw_status interpolate_large(ephw_kset* ks, const double* q, int64_t nq, const 
                          (int)nb, (int)nm, nw2, off, offp, s->ctx->status);
       EPHW_CHECK_LAUNCH();
       Stage sgr_(s, EPHW_STAGE_BAND_ROT, st);
-      GemmParams f4 = rot_params(nw, nm, nb, kl);
+      // T'_nu = (W_nu V(k))^T: rows (nu, m) of W, each nw-row block stored transposed
+      GemmParams f4 = pair_params(nw, nm, nb, kl, E);
       f4.A = W;
-      std_strides(&f4.strideA, &f4.strideA1, &f4.strideA2, nb, E, nw2);
       f4.B = vt + (size_t)k0 * nw2 * cs;
       f4.strideB = nw2;
       f4.C = Tm;
-      std_strides(&f4.strideC, &f4.strideC1, &f4.strideC2, nb, E, nw2);
+      f4.tblock = nw;
+      f4.ldc = nw2;
       EPHW_TRY(cgemm(kind, f4, st));
-      GemmParams f5 = rot_params(nw, nm, nb, kl);
-      f5.A = vt;
-      f5.offA = off;
-      f5.transA = true;
-      f5.conjA = true;
-      f5.B = Tm;
-      std_strides(&f5.strideB, &f5.strideB1, &f5.strideB2, nb, E, nw2);
+      // g_nu[m'][n] = sum_m T'_nu[n][m] conj(V(k+q))[m][m']: rows (nu, n), columns m',
+      // stored block-transposed, i.e. in the [nu][m'][n] order of g
+      GemmParams f5 = pair_params(nw, nm, nb, kl, E);
+      f5.A = Tm;
+      f5.B = vt;
+      f5.offB = offp;
+      f5.conjB = true;
+      f5.tblock = nw;
+      f5.ldc = nw2;
       if (flags & EPHW_OUT_G) {
         // g_out[(q0+iq) nk + k0+il][nu][m][n]
         f5.C = static_cast<char*>(g_out) + ((size_t)q0 * nk + k0) * E * cs;
         f5.strideC = E;
         f5.strideC1 = nk * E;
-        f5.strideC2 = nw2;
       } else {
         f5.C = Tm;  // not written (loss only)
       }
       if (flags & EPHW_OUT_LOSS) {
         f5.loss.on = true;
+        f5.loss.layout = 1;
         f5.loss.store = (flags & EPHW_OUT_G) != 0;
         f5.loss.seed = loss_seed;
         f5.loss.nk = nk;
@@ -584,7 +580,7 @@ ephw_status interpolate_large(ephw_kset* ks, const double* q, int64_t nq, const 
         f5.loss.partial = lossp;
       }
       EPHW_TRY(cgemm(kind, f5, st));
-      if (flags & EPHW_OUT_LOSS) EPHW_TRY(sum_into(lossp, nbat * rot_tiles, loss, st));
+      if (flags & EPHW_OUT_LOSS) EPHW_TRY(sum_into(lossp, kl * nb * rot_tiles, loss, st));
     }
   }
   return EPHW_OK;
@@ -714,8 +710,8 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
   EPHW_TRY(ws_need(s, WS_WBAR, wsz));
   EPHW_TRY(ws_need(s, WS_PAIRBAR, (size_t)kt * qb * nw2 * cs * 2));
   EPHW_TRY(ws_need(s, WS_OFF, (size_t)(kt * qb * nm + kt * qb) * 8));
-  const int64_t rot_tiles = cgemm_tiles(kind, nw, nw);
-  EPHW_TRY(ws_need(s, WS_LOSS, (size_t)kt * qb * nm * rot_tiles * 8));
+  const int64_t rot_tiles = cgemm_tiles(kind, nm * nw, nw);  // per pair
+  EPHW_TRY(ws_need(s, WS_LOSS, (size_t)kt * qb * rot_tiles * 8));
   EPHW_TRY(ws_need(s, WS_UBAR, (size_t)qb * nm * nm * cs));
   const int chunks_u = splitk_chunks(nw2, 16, 256);
   EPHW_TRY(ws_need(s, WS_SPLIT, (size_t)std::max<int64_t>(qb * chunks_u * nm * nm, 1) * cs));
@@ -794,29 +790,24 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
       hipLaunchKernelGGL(kq_offsets_kernel, dim3(grid1(nbat, 256)), dim3(256), 0, st, kq_index, nk, q0, k0, (int)kl,
                          (int)nb, (int)nm, nw2, off, offp, s->ctx->status);
       EPHW_CHECK_LAUNCH();
-      // T_nu = W_nu V(k), stored [pair][m'][nu][n]
-      GemmParams f4 = rot_params(nw, nm, nb, kl);
+      // T'_nu = (W_nu V(k))^T, block-transposed store: [pair][nu][n][m']
+      GemmParams f4 = pair_params(nw, nm, nb, kl, E);
       f4.A = W;
-      std_strides(&f4.strideA, &f4.strideA1, &f4.strideA2, nb, E, nw2);
       f4.B = vt + (size_t)k0 * nw2 * cs;
       f4.strideB = nw2;
       f4.C = Tm;
-      f4.ldc = nm * nw;
-      tr_strides(&f4.strideC, &f4.strideC1, &f4.strideC2, nb, E, nw);
+      f4.tblock = nw;
+      f4.ldc = nw2;
       EPHW_TRY(cgemm(kind, f4, st));
-      // Ybar_nu = 2 w (V(k+q)^H T_nu), stored [pair][m][nu][n]; loss partials
-      GemmParams f5 = rot_params(nw, nm, nb, kl);
-      f5.A = vt;
-      f5.offA = off;
-      f5.transA = true;
-      f5.conjA = true;
-      f5.B = Tm;
-      f5.ldb = nm * nw;
-      tr_strides(&f5.strideB, &f5.strideB1, &f5.strideB2, nb, E, nw);
+      // Ybar'_nu = 2 w (V(k+q)^H T_nu)^T: rows (nu, n), columns m, [pair][nu][n][m]; loss partials
+      GemmParams f5 = pair_params(nw, nm, nb, kl, E);
+      f5.A = Tm;
+      f5.B = vt;
+      f5.offB = offp;
+      f5.conjB = true;
       f5.C = Yb;
-      f5.ldc = nm * nw;
-      tr_strides(&f5.strideC, &f5.strideC1, &f5.strideC2, nb, E, nw);
       f5.loss.on = true;
+      f5.loss.layout = 1;
       f5.loss.store = true;
       f5.loss.grad_scale = true;
       f5.loss.seed = loss_seed;
@@ -828,29 +819,28 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
       f5.loss.k0 = k0;
       f5.loss.partial = lossp;
       EPHW_TRY(cgemm(kind, f5, st));
-      if (loss) EPHW_TRY(sum_into(lossp, nbat * rot_tiles, loss, st));
-      // Z_nu = V(k+q) Ybar_nu  (standard layout)
-      GemmParams b1 = rot_params(nw, nm, nb, kl);
-      b1.A = vt;
-      b1.offA = off;
-      b1.B = Yb;
-      b1.ldb = nm * nw;
-      tr_strides(&b1.strideB, &b1.strideB1, &b1.strideB2, nb, E, nw);
+      if (loss) EPHW_TRY(sum_into(lossp, kl * nb * rot_tiles, loss, st));
+      // Z_nu = V(k+q) Ybar_nu: rows (nu, n) of Ybar', B = V(k+q)^T; block-transposed
+      // store gives the standard [pair][nu][m][n]
+      GemmParams b1 = pair_params(nw, nm, nb, kl, E);
+      b1.A = Yb;
+      b1.B = vt;
+      b1.offB = offp;
+      b1.transB = true;
       b1.C = Z;
-      std_strides(&b1.strideC, &b1.strideC1, &b1.strideC2, nb, E, nw2);
+      b1.tblock = nw;
+      b1.ldc = nw2;
       EPHW_TRY(cgemm(kind, b1, st));
-      // Wbar_nu = Z_nu V(k)^H
-      GemmParams b2 = rot_params(nw, nm, nb, kl);
+      // Wbar_nu = Z_nu V(k)^H: rows (nu, m) of Z
+      GemmParams b2 = pair_params(nw, nm, nb, kl, E);
       b2.A = Z;
-      std_strides(&b2.strideA, &b2.strideA1, &b2.strideA2, nb, E, nw2);
       b2.B = vt + (size_t)k0 * nw2 * cs;
       b2.transB = true;
       b2.conjB = true;
       b2.strideB = nw2;
       b2.C = Wb;
-      std_strides(&b2.strideC, &b2.strideC1, &b2.strideC2, nb, E, nw2);
       EPHW_TRY(cgemm(kind, b2, st));
-      // per pair: Vbar(k) part = W^H Z over (nu, m'); Vbar(k+q) = T Ybar^H over (nu, n)
+      // per pair: Vbar(k) part = sum_nu W_nu^H Z_nu; Vbar(k+q) part = sum_nu T_nu Ybar_nu^H
       GemmParams b3;
       b3.M = nw;
       b3.N = nw;
@@ -869,14 +859,11 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
       b3.strideC = nw2;
       EPHW_TRY(cgemm(kind, b3, st));
       GemmParams b4 = b3;
-      b4.A = Tm;
-      b4.transA = false;
+      b4.A = Tm;  // T' rows (nu, n) = K, columns m
+      b4.transA = true;
       b4.conjA = false;
-      b4.lda = nm * nw;
-      b4.B = Yb;
-      b4.transB = true;
+      b4.B = Yb;  // Ybar' rows (nu, n) = K, columns m''
       b4.conjB = true;
-      b4.ldb = nm * nw;
       b4.C = Vkqb_pair;
       EPHW_TRY(cgemm(kind, b4, st));
       // Vbar(k) += sum over the unit's q of the pair parts (fixed order: iq ascending)

@@ -548,7 +548,6 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
   ephw_batch_options o{};
   o.use_graph = 1;
   if (opt) o = *opt;
-  const int64_t cap = o.item_workspace_bytes > 0 ? o.item_workspace_bytes : ((int64_t)1 << 30);
   hipStream_t st = as_stream(stream);
   ephw_batch* bt = new ephw_batch();
   bt->ctx = ctx;
@@ -594,15 +593,41 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
     it.nk = in.ks->nk;
     it.nq = in.nq;
     it.E = (int64_t)it.nm * it.nw * it.nw;
+    if (!cgemm_grouped_fits(kind, it.np, it.ne * it.E) || !cgemm_grouped_fits(kind, it.ne, 128 * it.E) ||
+        !cgemm_grouped_fits(0, it.nc, (int64_t)it.nm * it.nm)) {
+      set_error("ephw_batch_create: item " + std::to_string(i) + " is too large for the grouped GEMM");
+      return fail(EPHW_EUNSUPPORTED);
+    }
     it.nuc = band_rotate_modes_per_chunk(kind, it.nw, it.nm, &it.lds_band);
     bt->items.push_back(it);
   }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && cus > 0)
     bt->grid_gemm = cus;
+  // Sweep-buffer cap per item: the given per-item cap, else a pass-wide
+  // budget (a quarter of free HBM, at most 32 GiB) shared in proportion to
+  // each item's Eq. (10) work, so the largest systems get the largest units.
+  std::vector<int64_t> caps(bt->items.size(), o.item_workspace_bytes);
+  if (o.item_workspace_bytes <= 0) {
+    size_t fr = 0, tot = 0;
+    if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+      set_error("ephw_batch_create: hipMemGetInfo failed");
+      return fail(EPHW_EDEVICE);
+    }
+    const double budget = std::min(32.0 * (1 << 30), 0.25 * (double)fr);
+    double wsum = 0.0;
+    for (auto& it : bt->items) wsum += (double)it.nk * it.nq * it.ne * it.E;
+    for (size_t i = 0; i < bt->items.size(); ++i) {
+      const ItemPlan& it = bt->items[i];
+      const double share = wsum > 0 ? budget * ((double)it.nk * it.nq * it.ne * it.E) / wsum : 0.0;
+      caps[i] = (int64_t)std::min(8.0 * (1 << 30), std::max(1.0 * (1 << 30), share));
+    }
+  }
   // shapes: cache, else tune (or heuristics)
   auto cache = read_cache(o.tune_cache);
-  for (auto& it : bt->items) {
+  for (size_t i = 0; i < bt->items.size(); ++i) {
+    ItemPlan& it = bt->items[i];
+    const int64_t cap = caps[i];
     if (it.nq == 0) {  // nothing to do: smallest buffers, no units
       set_shape(it, 1, 1);
       continue;

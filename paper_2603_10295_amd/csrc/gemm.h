@@ -6,15 +6,18 @@
 namespace ephw {
 
 // Weighted |C|^2 epilogue for the loss L = sum w |g|^2 (SplitMix64 weights).
-// Batch b is read as (il, iq, nu) = (b / (qb nm), (b / nm) % qb, b % nm): k
-// point k0 + il, q point q0 + iq, mode nu; row m and column n of C are band
-// indices.  Every workgroup writes the sum of w |c|^2 over its tile to
+// layout 0: batch b is (il, iq, nu) = (b / (qb nm), (b / nm) % qb, b % nm)
+// (k point k0 + il, q point q0 + iq, mode nu) and C's row m and column n are
+// band indices.  layout 1: batch b is the pair (il, iq) = (b / qb, b % qb),
+// row r of C is (nu, n) = (r / nw, r % nw) and column m is the other band.
+// Every workgroup writes the sum of w |c|^2 over its tile to
 // partial[b * tiles_per_batch + tile].  With grad_scale the stored value is
 // 2 w c (the gradient of L with respect to g) instead of c.
 struct LossEpilogue {
   bool on = false;
   bool store = true;        // also store C (plain or scaled)
   bool grad_scale = false;
+  int layout = 0;
   uint64_t seed = 0;
   int64_t nk = 0;           // size of the k set (element index stride)
   int nm = 0, nw = 0, qb = 0;
@@ -45,6 +48,10 @@ struct GemmParams {
   bool accumulate = false;
   int64_t n1 = 1, n2 = 1;
   int64_t strideA1 = 0, strideA2 = 0, strideB1 = 0, strideB2 = 0, strideC1 = 0, strideC2 = 0;
+  // tblock > 0: C is stored in blocks of tblock rows, each block transposed:
+  // element (r, c) goes to (r / tblock) * ldc + c * tblock + r % tblock
+  // (ldc is then the block stride).
+  int64_t tblock = 0;
   LossEpilogue loss;
   int64_t batch_base = 0;  // internal: first batch index of this launch
 };
@@ -69,6 +76,8 @@ struct GroupProblem {
   int64_t tiles_m = 0, tiles_n = 0, tile_base = 0;  // set by cgemm_grouped_layout
 };
 void cgemm_tile_shape(int prec, int cfg, int* bm, int* bn);
+// whether the grouped kernel can address operands with these leading dimensions
+bool cgemm_grouped_fits(int prec, int64_t lda, int64_t ldb);
 // fills tiles_m/tiles_n/tile_base of every problem; returns the total tile count
 int64_t cgemm_grouped_layout(int prec, GroupProblem* probs, int n);
 ephw_status cgemm_grouped(int prec, const GroupProblem* d_probs, int n, int64_t total_tiles, int grid,

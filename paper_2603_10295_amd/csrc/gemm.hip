@@ -66,6 +66,7 @@ struct TileJob {
   int64_t M, N, K, lda, ldb, ldc;
   T sa, sb;          // -1 conjugates the operand's imaginary part
   bool accumulate;
+  int64_t tblock;             // > 0: block-transposed C (see GemmParams)
   LossEpilogue loss;          // loss.on false: plain store
   int64_t batch;              // batch index (for the loss epilogue)
   int64_t tile, ntiles;       // tile index within the batch entry, tiles per entry
@@ -80,188 +81,301 @@ __device__ __forceinline__ double splitmix_weight(uint64_t seed, uint64_t index)
   return 0.5 + (double)(z >> 40) * 0x1p-24;
 }
 
+// 16-byte global chunks: two complex floats or one complex double.
+template <typename T>
+struct Chunk;
+template <>
+struct Chunk<float> {
+  static constexpr int CPC = 2;   // complex values per chunk
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  typedef float v2 __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Chunk<double> {
+  static constexpr int CPC = 1;
+  typedef double v4 __attribute__((ext_vector_type(2)));
+  typedef double v2 __attribute__((ext_vector_type(2)));
+};
+
+// Buffer resource over `bytes` bytes from `base` (clamped to the 32-bit
+// range field).  Loads past the end return zero, which pads the M, N and
+// (for the operand whose rows run along K) K tails of a tile for free.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
+  const uint64_t p = reinterpret_cast<uint64_t>(base);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)p);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(p >> 32));
+  uint32_t n = bytes <= 0 ? 0u : (bytes >= 0xffffffffll ? 0xffffffffu : (uint32_t)bytes);
+  n = __builtin_amdgcn_readfirstlane(n);
+  return __builtin_amdgcn_make_buffer_rsrc(reinterpret_cast<void*>(((uint64_t)hi << 32) | lo), (short)0, (int)n,
+                                           0x00020000);
+}
+
+template <typename T>
+__device__ __forceinline__ typename Chunk<T>::v4 load_chunk(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(typename Chunk<T>::v4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
 template <typename T, int BM, int BN, int BK, int WM, int WN, bool SPLIT>
 struct TileShape {
   static constexpr int NT = 64 * WM * WN;
-  static constexpr int PAD = (sizeof(T) == 4) ? 4 : 2;
-  static constexpr int NA = SPLIT ? 4 : 2;
-  static constexpr size_t a_elems = (size_t)NA * BK * (BM + PAD);
-  static constexpr size_t b_elems = (size_t)2 * BK * (BN + PAD);
-  static constexpr size_t smem_elems = a_elems + b_elems;
+  static constexpr int PADC = (sizeof(T) == 4) ? 2 : 1;  // complex values of padding per LDS row
+  static constexpr int LA = BM + PADC, LB = BN + PADC;
+  static constexpr int NA = SPLIT ? 2 : 1;                // A planes: value (+ low part)
+  // one pipeline stage: NA A slabs [BK][LA] and one B slab [BK][LB], complex T
+  static constexpr size_t stage_elems = (size_t)2 * BK * (NA * LA + LB);
+  static constexpr size_t smem_elems = 2 * stage_elems;   // two stages
 };
 
 // Computes the BM x BN tile at (m0, n0) of job j with the workgroup's
 // NT threads; `smem` holds TileShape::smem_elems values of T.
+//
+// Pipeline: global loads of slab s+1 go to registers (16-byte buffer loads)
+// while slab s is multiplied from one LDS stage; the registers are then
+// written to the other stage, so each slab costs one barrier.  LDS keeps
+// complex values interleaved, laid out [k][m] and [k][n], so one 8- or
+// 16-byte read gives a lane its (re, im) operand pair.
 template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SPLIT>
 __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64_t n0, T* smem) {
   using S = TileShape<T, BM, BN, BK, WM, WN, SPLIT>;
-  constexpr int NT = S::NT;
+  using C = Chunk<T>;
+  using V4 = typename C::v4;
+  using V2 = typename C::v2;
+  using Acc = typename Mfma<T>::v4;
+  constexpr int NT = S::NT, CPC = C::CPC;
   constexpr int TM = BM / WM, TN = BN / WN;
   constexpr int FM = TM / 16, FN = TN / 16;
-  constexpr int PAD = S::PAD;
-  constexpr int AE = BM * BK / NT, BE = BK * BN / NT;
-  constexpr int LA = BM + PAD, LB = BN + PAD;   // LDS row lengths
-  static_assert(BM * BK % NT == 0 && BK * BN % NT == 0, "tile not divisible by threads");
+  constexpr int LA = S::LA, LB = S::LB;
+  constexpr int CS = 2 * (int)sizeof(T);               // bytes per complex value
+  // global slab rows: A is [BM][BK] (TA: [BK][BM]), B is [BK][BN] (TB: [BN][BK])
+  constexpr int A_RC = (TA ? BM : BK) / CPC;           // chunks per slab row
+  constexpr int B_RC = (TB ? BK : BN) / CPC;
+  constexpr int AC = BM * BK / CPC / NT;               // chunks per thread
+  constexpr int BC = BK * BN / CPC / NT;
+  // Row-group mode (NT a multiple of the chunks per row): a thread's chunks
+  // share one slab column and sit RSTEP rows apart, so one 32-bit lane offset
+  // serves all of them with one buffer base per row group.  Otherwise each
+  // chunk has its own offset from the slab base.
+  constexpr bool A_GRP = NT % A_RC == 0, B_GRP = NT % B_RC == 0;
+  constexpr int A_RSTEP = A_GRP ? NT / A_RC : 0, B_RSTEP = B_GRP ? NT / B_RC : 0;
   static_assert(TM % 16 == 0 && TN % 16 == 0 && BK % 4 == 0, "bad tile");
-  using V4 = typename Mfma<T>::v4;
-  // planes: As[0] re, As[1] im (conj applied), As[2]/As[3] low parts; Bs[0] re, Bs[1] im
-  T* As = smem;
-  T* Bs = smem + S::a_elems;
-  auto AS = [&](int plane, int k, int m) -> T& { return As[(plane * BK + k) * LA + m]; };
-  auto BS = [&](int plane, int k, int n) -> T& { return Bs[(plane * BK + k) * LB + n]; };
+  static_assert(AC * NT * CPC == BM * BK && BC * NT * CPC == BK * BN, "tile not divisible by threads");
 
-  const T* A = j.A;
-  const T* Alo = j.Alo;
-  const T* B = j.B;
   const int64_t M = j.M, N = j.N, K = j.K;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave % WM, wn = wave / WM;
+  const int lrow = lane >> 4;   // k row inside one MFMA (0..3); also the lane group
+  const int lcol = lane & 15;   // m (A) or n (B) inside one 16-block
 
-  T ra[AE][2], rb[BE][2], rl[SPLIT ? AE : 1][2];
+  // slab row and chunk of a thread's i-th chunk
+  auto a_pos = [&](int i, int& r, int& ch) {
+    const int c = A_GRP ? tid : tid + i * NT;
+    r = c / A_RC + (A_GRP ? i * A_RSTEP : 0);
+    ch = c % A_RC;
+  };
+  auto b_pos = [&](int i, int& r, int& ch) {
+    const int c = B_GRP ? tid : tid + i * NT;
+    r = c / B_RC + (B_GRP ? i * B_RSTEP : 0);
+    ch = c % B_RC;
+  };
+  const uint32_t a_off0 = (uint32_t)(((int64_t)(tid / A_RC) * j.lda + (tid % A_RC) * CPC) * CS);
+  const uint32_t b_off0 = (uint32_t)(((int64_t)(tid / B_RC) * j.ldb + (tid % B_RC) * CPC) * CS);
+  const int64_t a_ext = TA ? (K - 1) * j.lda + M : (M - 1) * j.lda + K;   // complex values from A
+  const int64_t b_ext = TB ? (N - 1) * j.ldb + K : (K - 1) * j.ldb + N;
 
-  // Branch-free loads: an out-of-range element reads element 0 (always
-  // valid) and is then replaced by zero, so the loop body is straight-line.
+  V4 ra[AC], rb[BC], rl[SPLIT ? AC : 1];
+
   auto load = [&](int64_t k0) {
+    const int64_t ao = TA ? k0 * j.lda + m0 : m0 * j.lda + k0;
+    const int64_t bo = TB ? n0 * j.ldb + k0 : k0 * j.ldb + n0;
 #pragma unroll
-    for (int i = 0; i < AE; ++i) {
-      const int e = tid + i * NT;
-      int mm, kk;
-      if (TA) { kk = e / BM; mm = e % BM; } else { mm = e / BK; kk = e % BK; }
-      const int64_t gm = m0 + mm, gk = k0 + kk;
-      const bool ok = gm < M && gk < K;
-      const int64_t off = ok ? (TA ? gk * j.lda + gm : gm * j.lda + gk) : 0;
-      const T re = A[2 * off], im = A[2 * off + 1];
-      ra[i][0] = ok ? re : T(0);
-      ra[i][1] = ok ? im : T(0);
-      if (SPLIT) {
-        const T lre = Alo[2 * off], lim = Alo[2 * off + 1];
-        rl[i][0] = ok ? lre : T(0);
-        rl[i][1] = ok ? lim : T(0);
+    for (int i = 0; i < AC; ++i) {
+      if (A_GRP) {  // one resource per row group
+        const int64_t o = ao + (int64_t)i * A_RSTEP * j.lda;
+        ra[i] = load_chunk<T>(make_rsrc(j.A + 2 * o, (a_ext - o) * CS), a_off0);
+        if (SPLIT) rl[i] = load_chunk<T>(make_rsrc(j.Alo + 2 * o, (a_ext - o) * CS), a_off0);
+      } else {
+        int r, ch;
+        a_pos(i, r, ch);
+        const uint32_t off = (uint32_t)(((int64_t)r * j.lda + ch * CPC) * CS);
+        ra[i] = load_chunk<T>(make_rsrc(j.A + 2 * ao, (a_ext - ao) * CS), off);
+        if (SPLIT) rl[i] = load_chunk<T>(make_rsrc(j.Alo + 2 * ao, (a_ext - ao) * CS), off);
       }
     }
 #pragma unroll
-    for (int i = 0; i < BE; ++i) {
-      const int e = tid + i * NT;
-      int nn, kk;
-      if (TB) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }
-      const int64_t gn = n0 + nn, gk = k0 + kk;
-      const bool ok = gn < N && gk < K;
-      const int64_t off = ok ? (TB ? gn * j.ldb + gk : gk * j.ldb + gn) : 0;
-      const T re = B[2 * off], im = B[2 * off + 1];
-      rb[i][0] = ok ? re : T(0);
-      rb[i][1] = ok ? im : T(0);
+    for (int i = 0; i < BC; ++i) {
+      if (B_GRP) {
+        const int64_t o = bo + (int64_t)i * B_RSTEP * j.ldb;
+        rb[i] = load_chunk<T>(make_rsrc(j.B + 2 * o, (b_ext - o) * CS), b_off0);
+      } else {
+        int r, ch;
+        b_pos(i, r, ch);
+        const uint32_t off = (uint32_t)(((int64_t)r * j.ldb + ch * CPC) * CS);
+        rb[i] = load_chunk<T>(make_rsrc(j.B + 2 * bo, (b_ext - bo) * CS), off);
+      }
     }
-  };
-  auto stash = [&]() {
+    // K tail where K runs along a row: the next row's values must not enter
+    const int64_t klim = K - k0;
+    if (!TA && klim < BK) {
 #pragma unroll
-    for (int i = 0; i < AE; ++i) {
-      const int e = tid + i * NT;
-      int mm, kk;
-      if (TA) { kk = e / BM; mm = e % BM; } else { mm = e / BK; kk = e % BK; }
-      AS(0, kk, mm) = ra[i][0];
-      AS(1, kk, mm) = j.sa * ra[i][1];
-      if (SPLIT) { AS(2, kk, mm) = rl[i][0]; AS(3, kk, mm) = j.sa * rl[i][1]; }
+      for (int i = 0; i < AC; ++i) {
+        int r, ch;
+        a_pos(i, r, ch);
+#pragma unroll
+        for (int e = 0; e < CPC; ++e)
+          if (ch * CPC + e >= klim) {
+            ra[i][2 * e] = T(0);
+            ra[i][2 * e + 1] = T(0);
+            if (SPLIT) {
+              rl[i][2 * e] = T(0);
+              rl[i][2 * e + 1] = T(0);
+            }
+          }
+      }
     }
+    if (TB && klim < BK) {
 #pragma unroll
-    for (int i = 0; i < BE; ++i) {
-      const int e = tid + i * NT;
-      int nn, kk;
-      if (TB) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }
-      BS(0, kk, nn) = rb[i][0];
-      BS(1, kk, nn) = j.sb * rb[i][1];
+      for (int i = 0; i < BC; ++i) {
+        int r, ch;
+        b_pos(i, r, ch);
+#pragma unroll
+        for (int e = 0; e < CPC; ++e)
+          if (ch * CPC + e >= klim) {
+            rb[i][2 * e] = T(0);
+            rb[i][2 * e + 1] = T(0);
+          }
+      }
     }
   };
 
-  V4 acc_r[FM][FN], acc_i[FM][FN];
+  // registers -> LDS stage; conjugation is applied here
+  auto stash = [&](T* st) {
+    T* As = st;
+    T* Bs = st + 2 * BK * LA * S::NA;
+#pragma unroll
+    for (int p = 0; p < S::NA; ++p) {
+      T* Ap = As + p * 2 * BK * LA;
+#pragma unroll
+      for (int i = 0; i < AC; ++i) {
+        V4 v = (p == 0) ? ra[i] : rl[SPLIT ? i : 0];
+#pragma unroll
+        for (int e = 0; e < CPC; ++e) v[2 * e + 1] *= j.sa;
+        int r, ch;
+        a_pos(i, r, ch);
+        if (TA) {  // slab row r is k; the chunk holds CPC consecutive m
+          *reinterpret_cast<V4*>(Ap + 2 * (r * LA + ch * CPC)) = v;
+        } else {   // slab row r is m; the chunk holds CPC consecutive k
+#pragma unroll
+          for (int e = 0; e < CPC; ++e)
+            *reinterpret_cast<V2*>(Ap + 2 * ((ch * CPC + e) * LA + r)) = V2{v[2 * e], v[2 * e + 1]};
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < BC; ++i) {
+      V4 v = rb[i];
+#pragma unroll
+      for (int e = 0; e < CPC; ++e) v[2 * e + 1] *= j.sb;
+      int r, ch;
+      b_pos(i, r, ch);
+      if (!TB) {  // slab row r is k; the chunk holds CPC consecutive n
+        *reinterpret_cast<V4*>(Bs + 2 * (r * LB + ch * CPC)) = v;
+      } else {    // slab row r is n; the chunk holds CPC consecutive k
+#pragma unroll
+        for (int e = 0; e < CPC; ++e)
+          *reinterpret_cast<V2*>(Bs + 2 * ((ch * CPC + e) * LB + r)) = V2{v[2 * e], v[2 * e + 1]};
+      }
+    }
+  };
+
+  Acc acc_r[FM][FN], acc_i[FM][FN];
 #pragma unroll
   for (int i = 0; i < FM; ++i)
 #pragma unroll
     for (int jj = 0; jj < FN; ++jj) {
-      acc_r[i][jj] = V4{0, 0, 0, 0};
-      acc_i[i][jj] = V4{0, 0, 0, 0};
+      acc_r[i][jj] = Acc{0, 0, 0, 0};
+      acc_i[i][jj] = Acc{0, 0, 0, 0};
     }
 
-  const int lrow = lane >> 4;   // k row inside one MFMA (0..3); also the lane group
-  const int lcol = lane & 15;   // m (A) or n (B) inside one 16-block
-
-  // One BK slab of MFMAs from LDS.  The four real products of every block are
-  // issued product by product across all blocks, so consecutive MFMAs never
-  // depend on each other.
-  auto compute = [&]() {
+  // One BK slab of MFMAs from an LDS stage.  The four real products of every
+  // block are issued product by product across all blocks, so consecutive
+  // MFMAs never depend on each other.
+  auto compute = [&](const T* st) {
+    const T* As = st;
+    const T* Bs = st + 2 * BK * LA * S::NA;
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + lrow;
-      T ar[FM], ai[FM], nai[FM], br[FN], bi[FN];
+      V2 a[FM], b[FN];
+      T nai[FM];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
-        ar[i] = AS(0, kr, wm * TM + i * 16 + lcol);
-        ai[i] = AS(1, kr, wm * TM + i * 16 + lcol);
-        nai[i] = -ai[i];
+        a[i] = *reinterpret_cast<const V2*>(As + 2 * (kr * LA + wm * TM + i * 16 + lcol));
+        nai[i] = -a[i][1];
       }
 #pragma unroll
-      for (int jj = 0; jj < FN; ++jj) {
-        br[jj] = BS(0, kr, wn * TN + jj * 16 + lcol);
-        bi[jj] = BS(1, kr, wn * TN + jj * 16 + lcol);
-      }
+      for (int jj = 0; jj < FN; ++jj)
+        b[jj] = *reinterpret_cast<const V2*>(Bs + 2 * (kr * LB + wn * TN + jj * 16 + lcol));
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int jj = 0; jj < FN; ++jj) acc_r[i][jj] = Mfma<T>::op(ar[i], br[jj], acc_r[i][jj]);
+        for (int jj = 0; jj < FN; ++jj) acc_r[i][jj] = Mfma<T>::op(a[i][0], b[jj][0], acc_r[i][jj]);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int jj = 0; jj < FN; ++jj) acc_i[i][jj] = Mfma<T>::op(ar[i], bi[jj], acc_i[i][jj]);
+        for (int jj = 0; jj < FN; ++jj) acc_i[i][jj] = Mfma<T>::op(a[i][0], b[jj][1], acc_i[i][jj]);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int jj = 0; jj < FN; ++jj) acc_r[i][jj] = Mfma<T>::op(nai[i], bi[jj], acc_r[i][jj]);
+        for (int jj = 0; jj < FN; ++jj) acc_r[i][jj] = Mfma<T>::op(nai[i], b[jj][1], acc_r[i][jj]);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int jj = 0; jj < FN; ++jj) acc_i[i][jj] = Mfma<T>::op(ai[i], br[jj], acc_i[i][jj]);
+        for (int jj = 0; jj < FN; ++jj) acc_i[i][jj] = Mfma<T>::op(a[i][1], b[jj][0], acc_i[i][jj]);
       if (SPLIT) {
+        const T* Al = As + 2 * BK * LA;
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
-          ar[i] = AS(2, kr, wm * TM + i * 16 + lcol);
-          ai[i] = AS(3, kr, wm * TM + i * 16 + lcol);
-          nai[i] = -ai[i];
+          a[i] = *reinterpret_cast<const V2*>(Al + 2 * (kr * LA + wm * TM + i * 16 + lcol));
+          nai[i] = -a[i][1];
         }
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int jj = 0; jj < FN; ++jj) {
-            acc_r[i][jj] = Mfma<T>::op(ar[i], br[jj], acc_r[i][jj]);
-            acc_i[i][jj] = Mfma<T>::op(ar[i], bi[jj], acc_i[i][jj]);
+            acc_r[i][jj] = Mfma<T>::op(a[i][0], b[jj][0], acc_r[i][jj]);
+            acc_i[i][jj] = Mfma<T>::op(a[i][0], b[jj][1], acc_i[i][jj]);
           }
 #pragma unroll
         for (int i = 0; i < FM; ++i)
 #pragma unroll
           for (int jj = 0; jj < FN; ++jj) {
-            acc_r[i][jj] = Mfma<T>::op(nai[i], bi[jj], acc_r[i][jj]);
-            acc_i[i][jj] = Mfma<T>::op(ai[i], br[jj], acc_i[i][jj]);
+            acc_r[i][jj] = Mfma<T>::op(nai[i], b[jj][1], acc_r[i][jj]);
+            acc_i[i][jj] = Mfma<T>::op(a[i][1], b[jj][0], acc_i[i][jj]);
           }
       }
     }
   };
 
-  // K loop: the next slab is fetched into registers while the current one is
-  // multiplied; the last slab is peeled so the loop body has no branches.
-  load(0);
-  stash();
-  __syncthreads();
+  // K loop: one barrier per slab (see the pipeline note above)
   const int64_t nslab = (K + BK - 1) / BK;
-  for (int64_t sl = 1; sl < nslab; ++sl) {
-    load(sl * BK);
-    compute();
-    __syncthreads();
-    stash();
+  load(0);
+  stash(smem);
+  __syncthreads();
+  for (int64_t sl = 0; sl < nslab; ++sl) {
+    const bool more = sl + 1 < nslab;
+    if (more) load((sl + 1) * BK);
+    compute(smem + (sl & 1) * S::stage_elems);
+    if (more) stash(smem + ((sl + 1) & 1) * S::stage_elems);
     __syncthreads();
   }
-  compute();
 
   // --- epilogue: lane holds column lcol of every block, rows per Mfma<T>::row --
+  const int64_t tb = j.tblock;
+  auto c_index = [&](int64_t row, int64_t col) -> int64_t {
+    return tb > 0 ? (row / tb) * j.ldc + col * tb + row % tb : row * j.ldc + col;
+  };
   if (!j.loss.on) {
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -272,11 +386,10 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
         for (int v = 0; v < 4; ++v) {
           const int64_t row = m0 + wm * TM + i * 16 + Mfma<T>::row(lrow, v);
           if (row < M && col < N) {
-            T* c = j.C + 2 * (row * j.ldc + col);
-            T re = acc_r[i][jj][v], im = acc_i[i][jj][v];
-            if (j.accumulate) { re += c[0]; im += c[1]; }
-            c[0] = re;
-            c[1] = im;
+            V2* c = reinterpret_cast<V2*>(j.C + 2 * c_index(row, col));
+            V2 val{acc_r[i][jj][v], acc_i[i][jj][v]};
+            if (j.accumulate) val += *c;
+            *c = val;
           }
         }
       }
@@ -284,12 +397,13 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
   }
   // weighted |c|^2: element index ((((q nk + k) nm + nu) nw + m) nw + n)
   const LossEpilogue& L = j.loss;
-  const int64_t il = j.batch / ((int64_t)L.qb * L.nm);
-  const int64_t iq = (j.batch / L.nm) % L.qb;
-  const int64_t nu = j.batch % L.nm;
+  const int64_t per_q = L.layout == 0 ? (int64_t)L.qb * L.nm : (int64_t)L.qb;
+  const int64_t il = j.batch / per_q;
+  const int64_t iq = L.layout == 0 ? (j.batch / L.nm) % L.qb : j.batch % L.qb;
+  const int64_t nu = L.layout == 0 ? j.batch % L.nm : 0;
+  const uint64_t nw2 = (uint64_t)L.nw * (uint64_t)L.nw;
   const uint64_t base =
-      (((uint64_t)(L.q0 + iq) * (uint64_t)L.nk + (uint64_t)(L.k0 + il)) * (uint64_t)L.nm + (uint64_t)nu) *
-      (uint64_t)L.nw * (uint64_t)L.nw;
+      (((uint64_t)(L.q0 + iq) * (uint64_t)L.nk + (uint64_t)(L.k0 + il)) * (uint64_t)L.nm + (uint64_t)nu) * nw2;
   double part = 0.0;
 #pragma unroll
   for (int i = 0; i < FM; ++i)
@@ -301,10 +415,13 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
         const int64_t row = m0 + wm * TM + i * 16 + Mfma<T>::row(lrow, v);
         if (row < M && col < N) {
           const T re = acc_r[i][jj][v], im = acc_i[i][jj][v];
-          const double w = splitmix_weight(L.seed, base + (uint64_t)(row * L.nw + col));
+          const uint64_t el = L.layout == 0
+                                  ? (uint64_t)(row * L.nw + col)
+                                  : (uint64_t)(row / L.nw) * nw2 + (uint64_t)col * L.nw + (uint64_t)(row % L.nw);
+          const double w = splitmix_weight(L.seed, base + el);
           part += w * ((double)re * (double)re + (double)im * (double)im);
           if (L.store) {
-            T* c = j.C + 2 * (row * j.ldc + col);
+            T* c = j.C + 2 * c_index(row, col);
             if (L.grad_scale) {
               c[0] = (T)(2.0 * w) * re;
               c[1] = (T)(2.0 * w) * im;
@@ -362,6 +479,7 @@ __device__ __forceinline__ TileJob<T> job_of(const GemmParams& p, int64_t b) {
   j.sa = p.conjA ? T(-1) : T(1);
   j.sb = p.conjB ? T(-1) : T(1);
   j.accumulate = p.accumulate;
+  j.tblock = p.tblock;
   j.loss = p.loss;
   j.batch = b;
   j.tile = 0;
@@ -369,8 +487,9 @@ __device__ __forceinline__ TileJob<T> job_of(const GemmParams& p, int64_t b) {
   return j;
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SPLIT>
-__global__ void __launch_bounds__(64 * WM * WN)
+// OCC: waves per SIMD the register allocation must leave room for
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SPLIT, int OCC>
+__global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(OCC)))
     cgemm_kernel(GemmParams p, int64_t tiles_m, int64_t tiles_n) {
   using S = TileShape<T, BM, BN, BK, WM, WN, SPLIT>;
   __shared__ T smem[S::smem_elems];
@@ -429,6 +548,7 @@ __global__ void __launch_bounds__(256)
     j.sa = T(1);
     j.sb = T(1);
     j.accumulate = false;
+    j.tblock = 0;
     j.loss = LossEpilogue();
     j.batch = 0;
     j.tile = 0;
@@ -441,7 +561,21 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SPLIT>
+// The buffer loads address a row group of RSTEP operand rows with 32-bit
+// byte offsets from one base.
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
+bool lane_offsets_fit(int64_t lda, int64_t ldb) {
+  constexpr int CPC = Chunk<T>::CPC, NT = 64 * WM * WN;
+  constexpr int a_rc = (TA ? BM : BK) / CPC, b_rc = (TB ? BK : BN) / CPC;
+  // rows addressed from one base: a row group, or the whole slab
+  constexpr int64_t a_rstep = NT % a_rc == 0 ? NT / a_rc : (TA ? BK : BM);
+  constexpr int64_t b_rstep = NT % b_rc == 0 ? NT / b_rc : (TB ? BN : BK);
+  constexpr int64_t cs = 2 * sizeof(T);
+  const int64_t lim = (int64_t)1 << 31;
+  return lda >= 0 && ldb >= 0 && a_rstep * (lda + BM + BK) * cs < lim && b_rstep * (ldb + BN + BK) * cs < lim;
+}
+
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SPLIT, int OCC>
 ephw_status launch(const GemmParams& p0, hipStream_t stream) {
   const int64_t tiles_m = ceil_div(p0.M, BM), tiles_n = ceil_div(p0.N, BN);
   const int64_t ntiles = tiles_m * tiles_n;
@@ -449,11 +583,15 @@ ephw_status launch(const GemmParams& p0, hipStream_t stream) {
     set_error("cgemm: too many tiles");
     return EPHW_EUNSUPPORTED;
   }
+  if (!lane_offsets_fit<T, BM, BN, BK, WM, WN, TA, TB>(p0.lda, p0.ldb)) {
+    set_error("cgemm: leading dimension too large for 32-bit lane offsets");
+    return EPHW_EUNSUPPORTED;
+  }
   GemmParams p = p0;
   for (int64_t b0 = 0; b0 < p0.batch; b0 += 65535) {
     const int64_t nb = (p0.batch - b0) < 65535 ? (p0.batch - b0) : 65535;
     p.batch_base = b0;
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, WM, WN, TA, TB, SPLIT>),
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, WM, WN, TA, TB, SPLIT, OCC>),
                        dim3((unsigned)ntiles, (unsigned)nb), dim3(64 * WM * WN), 0, stream, p,
                        tiles_m, tiles_n);
     EPHW_CHECK_LAUNCH();
@@ -461,18 +599,33 @@ ephw_status launch(const GemmParams& p0, hipStream_t stream) {
   return EPHW_OK;
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool SPLIT>
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool SPLIT, int OCC>
 ephw_status dispatch_trans(const GemmParams& p, hipStream_t s) {
-  if (!p.transA && !p.transB) return launch<T, BM, BN, BK, WM, WN, false, false, SPLIT>(p, s);
-  if (p.transA && !p.transB) return launch<T, BM, BN, BK, WM, WN, true, false, SPLIT>(p, s);
-  if (!p.transA && p.transB) return launch<T, BM, BN, BK, WM, WN, false, true, SPLIT>(p, s);
-  return launch<T, BM, BN, BK, WM, WN, true, true, SPLIT>(p, s);
+  if (!p.transA && !p.transB) return launch<T, BM, BN, BK, WM, WN, false, false, SPLIT, OCC>(p, s);
+  if (p.transA && !p.transB) return launch<T, BM, BN, BK, WM, WN, true, false, SPLIT, OCC>(p, s);
+  if (!p.transA && p.transB) return launch<T, BM, BN, BK, WM, WN, false, true, SPLIT, OCC>(p, s);
+  return launch<T, BM, BN, BK, WM, WN, true, true, SPLIT, OCC>(p, s);
 }
 
 }  // namespace
 
+// Tile shape of the plain kernel (no split A): the default tile, or a 64 x 224
+// tile where it pads the output by at least 10% less (the band and mode
+// rotations of systems with 129..224 bands or modes, e.g. 200 x 200 blocks
+// pad to 256 x 224 instead of 256 x 256).
+void plain_shape(int prec, int64_t M, int64_t N, int* bm, int* bn) {
+  const int dm = 128, dn = prec == 0 ? 64 : 128;
+  const double pad_d = (double)(ceil_div(M, dm) * dm) * (double)(ceil_div(N, dn) * dn);
+  const double pad_w = (double)(ceil_div(M, 64) * 64) * (double)(ceil_div(N, 224) * 224);
+  const bool wide = pad_w < 0.9 * pad_d;
+  *bm = wide ? 64 : dm;
+  *bn = wide ? 224 : dn;
+}
+
 int64_t cgemm_tiles(int prec, int64_t M, int64_t N) {
-  return prec == 0 ? ceil_div(M, 128) * ceil_div(N, 64) : ceil_div(M, 128) * ceil_div(N, 128);
+  int bm, bn;
+  plain_shape(prec, M, N, &bm, &bn);
+  return ceil_div(M, bm) * ceil_div(N, bn);
 }
 
 void cgemm_tile_shape(int prec, int cfg, int* bm, int* bn) {
@@ -486,6 +639,14 @@ void cgemm_tile_shape(int prec, int cfg, int* bm, int* bn) {
     *bm = 128;
     *bn = 128;
   }
+}
+
+bool cgemm_grouped_fits(int prec, int64_t lda, int64_t ldb) {
+  if (prec == 0)
+    return lane_offsets_fit<double, GroupCfg<double>::LM, GroupCfg<double>::LN, 16, 2, 2, false, false>(lda, ldb) &&
+           lane_offsets_fit<double, 64, 64, 16, 2, 2, false, false>(lda, ldb);
+  return lane_offsets_fit<float, GroupCfg<float>::LM, GroupCfg<float>::LN, 16, 2, 2, false, false>(lda, ldb) &&
+         lane_offsets_fit<float, 64, 64, 16, 2, 2, false, false>(lda, ldb);
 }
 
 int64_t cgemm_grouped_layout(int prec, GroupProblem* probs, int n) {
@@ -524,10 +685,16 @@ ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream) {
       set_error("cgemm: split A is an FP32 feature");
       return EPHW_EINVAL;
     }
-    return dispatch_trans<double, 128, 64, 16, 2, 2, false>(p, stream);
+    int bm, bn;
+    plain_shape(0, p.M, p.N, &bm, &bn);
+    if (bn == 224) return dispatch_trans<double, 64, 224, 16, 2, 2, false, 1>(p, stream);
+    return dispatch_trans<double, 128, 64, 16, 2, 2, false, 1>(p, stream);
   }
-  if (p.A_lo) return dispatch_trans<float, 128, 128, 16, 2, 2, true>(p, stream);
-  return dispatch_trans<float, 128, 128, 16, 2, 2, false>(p, stream);
+  if (p.A_lo) return dispatch_trans<float, 128, 128, 16, 2, 2, true, 1>(p, stream);
+  int bm, bn;
+  plain_shape(1, p.M, p.N, &bm, &bn);
+  if (bn == 224) return dispatch_trans<float, 64, 224, 16, 2, 2, false, 2>(p, stream);
+  return dispatch_trans<float, 128, 128, 16, 2, 2, false, 2>(p, stream);
 }
 
 }  // namespace ephw
