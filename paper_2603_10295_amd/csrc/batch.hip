@@ -49,6 +49,8 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 struct Launch {
   enum Kind { PHASE, GEMM, EIGH, MODEVEC, MODE, BAND, SUM } kind;
   int prec = 0;
+  int cfg = 0;                 // GEMM: tile configuration of every problem in the launch
+  int grid = 0;                // GEMM: persistent workgroups
   const void* jobs = nullptr;  // device descriptor array
   int n = 0;
   int64_t count = 0;           // total tiles (GEMM) or blocks
@@ -69,7 +71,7 @@ struct ephw_batch {
   size_t desc_bytes = 0;
   std::vector<Launch> launches;
   int rounds = 0;
-  int grid_gemm = 256;
+  int cus = 256;
   bool use_graph = false;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -316,8 +318,8 @@ ephw_status issue(ephw_batch* bt, hipStream_t st) {
         break;
       }
       case Launch::GEMM:
-        EPHW_TRY(cgemm_grouped(l.prec, static_cast<const GroupProblem*>(l.jobs), l.n, l.count,
-                               (int)std::min<int64_t>(bt->grid_gemm, l.count), st));
+        EPHW_TRY(cgemm_grouped(l.prec, l.cfg, static_cast<const GroupProblem*>(l.jobs), l.n, l.count,
+                               (int)std::min<int64_t>(l.grid, l.count), st));
         break;
       case Launch::EIGH:
         EPHW_TRY(jacobi_eigh_grouped(static_cast<const EighJob*>(l.jobs), l.n, l.count, status, st));
@@ -336,6 +338,9 @@ ephw_status issue(ephw_batch* bt, hipStream_t st) {
   return EPHW_OK;
 }
 
+// LDS size classes of the band-rotation launches
+int lds_class(size_t b) { return b <= 16384 ? 0 : b <= 32768 ? 1 : b <= 65536 ? 2 : 3; }
+
 // Builds the launch list of one pass; descriptor arrays are staged in `hd`
 // and their offsets fixed up once the device copy exists.
 void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, size_t>>& fix) {
@@ -344,6 +349,23 @@ void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, 
   auto push = [&](Launch l, size_t off) {
     bt->launches.push_back(l);
     fix.push_back({bt->launches.size() - 1, off});
+  };
+  // grouped GEMM launches: one per tile configuration present
+  auto push_gemm = [&](int prec, const std::vector<GroupProblem>& all) {
+    for (int cfg = 0; cfg < 2; ++cfg) {
+      std::vector<GroupProblem> probs;
+      for (const GroupProblem& p : all)
+        if (p.cfg == cfg) probs.push_back(p);
+      if (probs.empty()) continue;
+      Launch l;
+      l.kind = Launch::GEMM;
+      l.prec = prec;
+      l.cfg = cfg;
+      l.grid = bt->cus * cgemm_grouped_blocks_per_cu(prec, cfg);
+      l.n = (int)probs.size();
+      l.count = cgemm_grouped_layout(prec, probs.data(), l.n);
+      push(l, hd.add(probs));
+    }
   };
   // q side: phases per item, D(q) GEMMs (one grouped launch), eigensolves (one
   // grouped launch), mode vectors per item
@@ -369,12 +391,7 @@ void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, 
       p.cfg = 1;
       probs.push_back(p);
     }
-    Launch l;
-    l.kind = Launch::GEMM;
-    l.prec = 0;
-    l.n = (int)probs.size();
-    l.count = cgemm_grouped_layout(0, probs.data(), l.n);
-    push(l, hd.add(probs));
+    push_gemm(0, probs);
   }
   {
     std::vector<EighJob> jobs;
@@ -410,6 +427,7 @@ void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, 
     std::vector<GroupProblem> rp, re;
     std::vector<ModeRotateJob> mj;
     std::vector<BandRotateJob> bj;
+    std::vector<size_t> bj_lds;
     std::vector<SumJob> sj;
     int64_t mblocks = 0, bblocks = 0;
     size_t mlds = 0, blds = 0;
@@ -482,15 +500,11 @@ void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, 
       bblocks += nb * kl;
       blds = std::max(blds, it.lds_band);
       bj.push_back(b);
+      bj_lds.push_back(it.lds_band);
       if (it.in.flags & EPHW_OUT_LOSS) sj.push_back(SumJob{it.lossp, nb * kl, it.in.loss});
     }
     if (!rp.empty()) {
-      Launch l;
-      l.kind = Launch::GEMM;
-      l.prec = kind;
-      l.n = (int)rp.size();
-      l.count = cgemm_grouped_layout(kind, rp.data(), l.n);
-      push(l, hd.add(rp));
+      push_gemm(kind, rp);
       Launch m;
       m.kind = Launch::MODE;
       m.n = (int)mj.size();
@@ -499,18 +513,31 @@ void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, 
       push(m, hd.add(mj));
     }
     {
-      Launch l;
-      l.kind = Launch::GEMM;
-      l.prec = kind;
-      l.n = (int)re.size();
-      l.count = cgemm_grouped_layout(kind, re.data(), l.n);
-      push(l, hd.add(re));
-      Launch b;
-      b.kind = Launch::BAND;
-      b.n = (int)bj.size();
-      b.count = bblocks;
-      b.lds = blds;
-      push(b, hd.add(bj));
+      push_gemm(kind, re);
+      // one band-rotation launch per LDS class: a launch runs at the
+      // occupancy its largest LDS request allows, so small systems are not
+      // held to the budget of the largest
+      for (int cls = 0; cls < 4; ++cls) {
+        std::vector<BandRotateJob> part;
+        int64_t blocks = 0;
+        size_t lds = 0;
+        for (size_t i = 0; i < bj.size(); ++i) {
+          if (lds_class(bj_lds[i]) != cls) continue;
+          BandRotateJob jb = bj[i];
+          const int64_t nblk = (int64_t)jb.args.qb * jb.args.nk_tile;
+          jb.block_base = blocks;
+          blocks += nblk;
+          lds = std::max(lds, bj_lds[i]);
+          part.push_back(jb);
+        }
+        if (part.empty()) continue;
+        Launch b;
+        b.kind = Launch::BAND;
+        b.n = (int)part.size();
+        b.count = blocks;
+        b.lds = lds;
+        push(b, hd.add(part));
+      }
     }
     if (!sj.empty()) {
       Launch l;
@@ -603,7 +630,7 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
   }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && cus > 0)
-    bt->grid_gemm = cus;
+    bt->cus = cus;
   // Sweep-buffer cap per item: the given per-item cap, else a pass-wide
   // budget (a quarter of free HBM, at most 32 GiB) shared in proportion to
   // each item's Eq. (10) work, so the largest systems get the largest units.

@@ -62,8 +62,9 @@ int64_t cgemm_tiles(int prec, int64_t M, int64_t N);
 ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream);
 
 // Many independent GEMMs C = A B (row-major, no transposes) in one persistent
-// launch: `grid` workgroups stride over the concatenated tile lists.  Each
-// problem picks its tile shape with `cfg` (0 = large, 1 = small).
+// launch: `grid` workgroups stride over the concatenated tile lists.  All
+// problems of one launch share a tile configuration `cfg` (0 = large,
+// 1 = small 64x64).
 struct GroupProblem {
   int64_t M = 0, N = 0, K = 0;
   const void* A = nullptr;
@@ -76,11 +77,14 @@ struct GroupProblem {
   int64_t tiles_m = 0, tiles_n = 0, tile_base = 0;  // set by cgemm_grouped_layout
 };
 void cgemm_tile_shape(int prec, int cfg, int* bm, int* bn);
+// workgroups of the grouped kernel one CU holds at once (its persistent grid
+// is this times the CU count)
+int cgemm_grouped_blocks_per_cu(int prec, int cfg);
 // whether the grouped kernel can address operands with these leading dimensions
 bool cgemm_grouped_fits(int prec, int64_t lda, int64_t ldb);
 // fills tiles_m/tiles_n/tile_base of every problem; returns the total tile count
 int64_t cgemm_grouped_layout(int prec, GroupProblem* probs, int n);
-ephw_status cgemm_grouped(int prec, const GroupProblem* d_probs, int n, int64_t total_tiles, int grid,
+ephw_status cgemm_grouped(int prec, int cfg, const GroupProblem* d_probs, int n, int64_t total_tiles, int grid,
                           hipStream_t stream);
 
 }  // namespace ephw

@@ -2,16 +2,19 @@
 // v_mfma_f32_16x16x4_f32).
 //
 // The phase sums of Eqs. (9) and (10) are dense complex contractions, so they
-// run here.  A complex product is four real MFMAs on planar (re, im) tiles:
+// run here.  A complex product is four real MFMAs on the (re, im) parts:
 //   Cr += Ar Br - Ai Bi,  Ci += Ar Bi + Ai Br
 // with the sign folded into a negated copy of Ai held in a register.
 //
 // Tiling: a workgroup of WM x WN waves owns a BM x BN tile of C; each wave
 // owns a (BM/WM) x (BN/WN) sub-tile made of 16x16 MFMA blocks.  K advances
-// in BK-wide slabs staged through LDS as [k][m] / [k][n] planes, so the lane
-// reads of every MFMA (16 consecutive m or n per k row) are conflict-free.
-// Global loads of the next slab are issued into registers before the MFMAs of
-// the current one (single LDS buffer, register prefetch).
+// in BK-deep slabs: 16-byte buffer loads bring slab s+1 into registers while
+// slab s is multiplied out of one of two LDS stages, then the registers are
+// written to the other stage (one barrier per slab).  LDS holds complex
+// values interleaved, [k][m] and [k][n], so each MFMA operand pair is one
+// 8- or 16-byte read and the 16 lanes of a row read consecutive addresses.
+// FP32: 128x128x16 tiles at two waves per SIMD (register budget 256);
+// FP64: 64x64x8 tiles; outputs 129..224 wide use 64x224 tiles.
 //
 // Workgroup order: hardware hands workgroups to the 8 XCDs round-robin, each
 // XCD with its own L2.  The tile index is remapped so that consecutive tiles
@@ -157,6 +160,9 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
   // chunk has its own offset from the slab base.
   constexpr bool A_GRP = NT % A_RC == 0, B_GRP = NT % B_RC == 0;
   constexpr int A_RSTEP = A_GRP ? NT / A_RC : 0, B_RSTEP = B_GRP ? NT / B_RC : 0;
+  // a whole number of waves per slab row: the row is wave-uniform and goes
+  // into the base, leaving only the in-row chunk offset per lane
+  constexpr bool A_WROW = A_GRP && A_RC % 64 == 0, B_WROW = B_GRP && B_RC % 64 == 0;
   static_assert(TM % 16 == 0 && TN % 16 == 0 && BK % 4 == 0, "bad tile");
   static_assert(AC * NT * CPC == BM * BK && BC * NT * CPC == BK * BN, "tile not divisible by threads");
 
@@ -179,8 +185,12 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
     r = c / B_RC + (B_GRP ? i * B_RSTEP : 0);
     ch = c % B_RC;
   };
-  const uint32_t a_off0 = (uint32_t)(((int64_t)(tid / A_RC) * j.lda + (tid % A_RC) * CPC) * CS);
-  const uint32_t b_off0 = (uint32_t)(((int64_t)(tid / B_RC) * j.ldb + (tid % B_RC) * CPC) * CS);
+  const int64_t a_row0 = A_WROW ? (int64_t)(tid / A_RC) * j.lda : 0;   // wave-uniform part
+  const int64_t b_row0 = B_WROW ? (int64_t)(tid / B_RC) * j.ldb : 0;
+  const uint32_t a_off0 =
+      (uint32_t)(((A_WROW ? 0 : (int64_t)(tid / A_RC) * j.lda) + (tid % A_RC) * CPC) * CS);
+  const uint32_t b_off0 =
+      (uint32_t)(((B_WROW ? 0 : (int64_t)(tid / B_RC) * j.ldb) + (tid % B_RC) * CPC) * CS);
   const int64_t a_ext = TA ? (K - 1) * j.lda + M : (M - 1) * j.lda + K;   // complex values from A
   const int64_t b_ext = TB ? (N - 1) * j.ldb + K : (K - 1) * j.ldb + N;
 
@@ -192,7 +202,7 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
 #pragma unroll
     for (int i = 0; i < AC; ++i) {
       if (A_GRP) {  // one resource per row group
-        const int64_t o = ao + (int64_t)i * A_RSTEP * j.lda;
+        const int64_t o = ao + (int64_t)i * A_RSTEP * j.lda + a_row0;
         ra[i] = load_chunk<T>(make_rsrc(j.A + 2 * o, (a_ext - o) * CS), a_off0);
         if (SPLIT) rl[i] = load_chunk<T>(make_rsrc(j.Alo + 2 * o, (a_ext - o) * CS), a_off0);
       } else {
@@ -206,7 +216,7 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
 #pragma unroll
     for (int i = 0; i < BC; ++i) {
       if (B_GRP) {
-        const int64_t o = bo + (int64_t)i * B_RSTEP * j.ldb;
+        const int64_t o = bo + (int64_t)i * B_RSTEP * j.ldb + b_row0;
         rb[i] = load_chunk<T>(make_rsrc(j.B + 2 * o, (b_ext - o) * CS), b_off0);
       } else {
         int r, ch;
@@ -502,30 +512,35 @@ __global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_
   gemm_tile<T, BM, BN, BK, WM, WN, TA, TB, SPLIT>(j, tm * BM, tn * BN, smem);
 }
 
-// Tile shapes of the grouped kernel: cfg 0 is the shape of the plain kernel,
-// cfg 1 a 64x64 tile for small problems.  Both use 4 waves.
+// Tile shapes of the grouped kernel: cfg 0 is the default tile of the plain
+// kernel (FP32 128x128, FP64 64x64), cfg 1 a 64x64 tile for small problems.
+// Both use 4 waves.
 template <typename T>
 struct GroupCfg;
 template <>
 struct GroupCfg<float> {
-  using L = TileShape<float, 128, 128, 16, 2, 2, false>;
-  using S = TileShape<float, 64, 64, 16, 2, 2, false>;
-  static constexpr int LM = 128, LN = 128;
+  static constexpr int LM = 128, LN = 128, LK = 16, SM = 64, SN = 64, SK = 16;
 };
 template <>
 struct GroupCfg<double> {
-  using L = TileShape<double, 128, 64, 16, 2, 2, false>;
-  using S = TileShape<double, 64, 64, 16, 2, 2, false>;
-  static constexpr int LM = 128, LN = 64;
+  static constexpr int LM = 64, LN = 64, LK = 8, SM = 64, SN = 64, SK = 8;
 };
 
-template <typename T>
-__global__ void __launch_bounds__(256)
+// One launch serves problems of one tile configuration (CFG), so each
+// instance gets the register budget of its own tile.
+template <typename T, int CFG>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     cgemm_grouped_kernel(const GroupProblem* __restrict__ probs, int n, int64_t total) {
   using G = GroupCfg<T>;
-  constexpr size_t kSmem = G::L::smem_elems > G::S::smem_elems ? G::L::smem_elems : G::S::smem_elems;
-  __shared__ T smem[kSmem];
-  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+  constexpr int BM = CFG == 0 ? G::LM : G::SM, BN = CFG == 0 ? G::LN : G::SN, BK = CFG == 0 ? G::LK : G::SK;
+  using Sh = TileShape<T, BM, BN, BK, 2, 2, false>;
+  __shared__ T smem[Sh::smem_elems];
+  // sweeps of gridDim.x consecutive tiles; within a sweep, consecutive tiles
+  // go to one XCD (workgroups are dealt to the XCDs round-robin)
+  for (int64_t base = 0; base < total; base += gridDim.x) {
+    const int64_t span = (total - base) < (int64_t)gridDim.x ? (total - base) : (int64_t)gridDim.x;
+    if ((int64_t)blockIdx.x >= span) break;
+    const int64_t t = base + xcd_remap(blockIdx.x, span);
     int lo = 0, hi = n - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -553,10 +568,7 @@ __global__ void __launch_bounds__(256)
     j.batch = 0;
     j.tile = 0;
     j.ntiles = 1;
-    if (P.cfg == 0)
-      gemm_tile<T, G::LM, G::LN, 16, 2, 2, false, false, false>(j, tm * G::LM, tn * G::LN, smem);
-    else
-      gemm_tile<T, 64, 64, 16, 2, 2, false, false, false>(j, tm * 64, tn * 64, smem);
+    gemm_tile<T, BM, BN, BK, 2, 2, false, false, false>(j, tm * BM, tn * BN, smem);
     __syncthreads();
   }
 }
@@ -567,12 +579,12 @@ template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB>
 bool lane_offsets_fit(int64_t lda, int64_t ldb) {
   constexpr int CPC = Chunk<T>::CPC, NT = 64 * WM * WN;
   constexpr int a_rc = (TA ? BM : BK) / CPC, b_rc = (TB ? BK : BN) / CPC;
-  // rows addressed from one base: a row group, or the whole slab
-  constexpr int64_t a_rstep = NT % a_rc == 0 ? NT / a_rc : (TA ? BK : BM);
-  constexpr int64_t b_rstep = NT % b_rc == 0 ? NT / b_rc : (TB ? BN : BK);
+  // rows a lane offset spans: none (wave-uniform row), a row group, or the whole slab
+  constexpr int64_t a_rows = NT % a_rc == 0 ? (a_rc % 64 == 0 ? 0 : NT / a_rc) : (TA ? BK : BM);
+  constexpr int64_t b_rows = NT % b_rc == 0 ? (b_rc % 64 == 0 ? 0 : NT / b_rc) : (TB ? BN : BK);
   constexpr int64_t cs = 2 * sizeof(T);
-  const int64_t lim = (int64_t)1 << 31;
-  return lda >= 0 && ldb >= 0 && a_rstep * (lda + BM + BK) * cs < lim && b_rstep * (ldb + BN + BK) * cs < lim;
+  const int64_t lim = ((int64_t)1 << 32) - 1024;
+  return lda >= 0 && ldb >= 0 && (a_rows * lda + BM + BK) * cs < lim && (b_rows * ldb + BN + BK) * cs < lim;
 }
 
 template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SPLIT, int OCC>
@@ -614,7 +626,7 @@ ephw_status dispatch_trans(const GemmParams& p, hipStream_t s) {
 // rotations of systems with 129..224 bands or modes, e.g. 200 x 200 blocks
 // pad to 256 x 224 instead of 256 x 256).
 void plain_shape(int prec, int64_t M, int64_t N, int* bm, int* bn) {
-  const int dm = 128, dn = prec == 0 ? 64 : 128;
+  const int dm = prec == 0 ? 64 : 128, dn = prec == 0 ? 64 : 128;
   const double pad_d = (double)(ceil_div(M, dm) * dm) * (double)(ceil_div(N, dn) * dn);
   const double pad_w = (double)(ceil_div(M, 64) * 64) * (double)(ceil_div(N, 224) * 224);
   const bool wide = pad_w < 0.9 * pad_d;
@@ -629,24 +641,36 @@ int64_t cgemm_tiles(int prec, int64_t M, int64_t N) {
 }
 
 void cgemm_tile_shape(int prec, int cfg, int* bm, int* bn) {
-  if (cfg != 0) {
-    *bm = 64;
-    *bn = 64;
-  } else if (prec == 0) {
-    *bm = 128;
-    *bn = 64;
+  if (prec == 0) {
+    *bm = cfg != 0 ? GroupCfg<double>::SM : GroupCfg<double>::LM;
+    *bn = cfg != 0 ? GroupCfg<double>::SN : GroupCfg<double>::LN;
   } else {
-    *bm = 128;
-    *bn = 128;
+    *bm = cfg != 0 ? GroupCfg<float>::SM : GroupCfg<float>::LM;
+    *bn = cfg != 0 ? GroupCfg<float>::SN : GroupCfg<float>::LN;
   }
 }
 
-bool cgemm_grouped_fits(int prec, int64_t lda, int64_t ldb) {
+template <typename T>
+bool grouped_fits(int64_t lda, int64_t ldb) {
+  using G = GroupCfg<T>;
+  return lane_offsets_fit<T, G::LM, G::LN, G::LK, 2, 2, false, false>(lda, ldb) &&
+         lane_offsets_fit<T, G::SM, G::SN, G::SK, 2, 2, false, false>(lda, ldb);
+}
+
+int cgemm_grouped_blocks_per_cu(int prec, int cfg) {
+  int n = 0;
+  hipError_t e;
   if (prec == 0)
-    return lane_offsets_fit<double, GroupCfg<double>::LM, GroupCfg<double>::LN, 16, 2, 2, false, false>(lda, ldb) &&
-           lane_offsets_fit<double, 64, 64, 16, 2, 2, false, false>(lda, ldb);
-  return lane_offsets_fit<float, GroupCfg<float>::LM, GroupCfg<float>::LN, 16, 2, 2, false, false>(lda, ldb) &&
-         lane_offsets_fit<float, 64, 64, 16, 2, 2, false, false>(lda, ldb);
+    e = cfg == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cgemm_grouped_kernel<double, 0>, 256, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cgemm_grouped_kernel<double, 1>, 256, 0);
+  else
+    e = cfg == 0 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cgemm_grouped_kernel<float, 0>, 256, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, cgemm_grouped_kernel<float, 1>, 256, 0);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+bool cgemm_grouped_fits(int prec, int64_t lda, int64_t ldb) {
+  return prec == 0 ? grouped_fits<double>(lda, ldb) : grouped_fits<float>(lda, ldb);
 }
 
 int64_t cgemm_grouped_layout(int prec, GroupProblem* probs, int n) {
@@ -662,16 +686,31 @@ int64_t cgemm_grouped_layout(int prec, GroupProblem* probs, int n) {
   return base;
 }
 
-ephw_status cgemm_grouped(int prec, const GroupProblem* d_probs, int n, int64_t total_tiles, int grid,
+ephw_status cgemm_grouped(int prec, int cfg, const GroupProblem* d_probs, int n, int64_t total_tiles, int grid,
                           hipStream_t stream) {
   if (n <= 0 || total_tiles <= 0) return EPHW_OK;
   if (grid <= 0) grid = 1;
-  if (prec == 0)
-    hipLaunchKernelGGL(cgemm_grouped_kernel<double>, dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles);
-  else
-    hipLaunchKernelGGL(cgemm_grouped_kernel<float>, dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles);
+  if (prec == 0) {
+    if (cfg == 0)
+      hipLaunchKernelGGL((cgemm_grouped_kernel<double, 0>), dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles);
+    else
+      hipLaunchKernelGGL((cgemm_grouped_kernel<double, 1>), dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles);
+  } else {
+    if (cfg == 0)
+      hipLaunchKernelGGL((cgemm_grouped_kernel<float, 0>), dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles);
+    else
+      hipLaunchKernelGGL((cgemm_grouped_kernel<float, 1>), dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles);
+  }
   EPHW_CHECK_LAUNCH();
   return EPHW_OK;
+}
+
+template <typename T, int BM, int BN, int BK, int WM, int WN>
+bool fits_any(const GemmParams& p) {
+  if (!p.transA && !p.transB) return lane_offsets_fit<T, BM, BN, BK, WM, WN, false, false>(p.lda, p.ldb);
+  if (p.transA && !p.transB) return lane_offsets_fit<T, BM, BN, BK, WM, WN, true, false>(p.lda, p.ldb);
+  if (!p.transA && p.transB) return lane_offsets_fit<T, BM, BN, BK, WM, WN, false, true>(p.lda, p.ldb);
+  return lane_offsets_fit<T, BM, BN, BK, WM, WN, true, true>(p.lda, p.ldb);
 }
 
 ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream) {
@@ -680,20 +719,26 @@ ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream) {
     set_error("cgemm: K must be positive");
     return EPHW_EINVAL;
   }
-  if (prec == 0) {
-    if (p.A_lo) {
-      set_error("cgemm: split A is an FP32 feature");
-      return EPHW_EINVAL;
-    }
-    int bm, bn;
-    plain_shape(0, p.M, p.N, &bm, &bn);
-    if (bn == 224) return dispatch_trans<double, 64, 224, 16, 2, 2, false, 1>(p, stream);
-    return dispatch_trans<double, 128, 64, 16, 2, 2, false, 1>(p, stream);
+  if (prec == 0 && p.A_lo) {
+    set_error("cgemm: split A is an FP32 feature");
+    return EPHW_EINVAL;
   }
   if (p.A_lo) return dispatch_trans<float, 128, 128, 16, 2, 2, true, 1>(p, stream);
   int bm, bn;
-  plain_shape(1, p.M, p.N, &bm, &bn);
-  if (bn == 224) return dispatch_trans<float, 64, 224, 16, 2, 2, false, 2>(p, stream);
+  plain_shape(prec, p.M, p.N, &bm, &bn);
+  // the 64x224 tile addresses a whole slab from one base; very long rows
+  // (e.g. g(Re,Rp) as the B operand) take the default tile instead
+  bool wide = bn == 224 && (prec == 0 ? fits_any<double, 64, 224, 16, 2, 2>(p) : fits_any<float, 64, 224, 16, 2, 2>(p));
+  if (bn == 224 && !wide && p.loss.on) {
+    // the loss partials are sized by cgemm_tiles for the wide tile
+    set_error("cgemm: loss epilogue with leading dimensions too large for the 64x224 tile");
+    return EPHW_EUNSUPPORTED;
+  }
+  if (prec == 0) {
+    if (wide) return dispatch_trans<double, 64, 224, 16, 2, 2, false, 1>(p, stream);
+    return dispatch_trans<double, 64, 64, 8, 2, 2, false, 2>(p, stream);
+  }
+  if (wide) return dispatch_trans<float, 64, 224, 16, 2, 2, false, 2>(p, stream);
   return dispatch_trans<float, 128, 128, 16, 2, 2, false, 2>(p, stream);
 }
 
