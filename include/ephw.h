@@ -252,10 +252,10 @@ typedef struct ephw_batch_options {
   int32_t tune;              /* 0: heuristic shapes; 1: time candidate shapes on the device */
   const char* tune_cache;    /* file of tuned shapes (one JSON object per line) or NULL */
   int32_t use_graph;         /* 1: capture the pass into a HIP graph */
-  int64_t item_workspace_bytes; /* per-item cap of the sweep buffers; 0: a pass-wide
-                                   budget (a quarter of free device memory, at most
-                                   32 GiB) split in proportion to each item's k x q x
-                                   Ne x Nm Nw^2 work, each item between 1 GiB and 8 GiB */
+  int64_t item_workspace_bytes; /* per-item cap of the sweep buffers; 0: what the
+                                   item's largest unit (128 q, every k) needs, between
+                                   1 GiB and 8 GiB, scaled down together when the items
+                                   would take more than half of the free device memory */
 } ephw_batch_options;
 /* Plan a batch: validates items, tunes shapes, allocates the workspace.
    All items must share one precision; nw <= 32 and nm <= 24 per system. */

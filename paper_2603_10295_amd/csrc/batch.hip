@@ -27,8 +27,8 @@ struct ItemPlan {
   int64_t ne = 0, np = 0, nc = 0, nk = 0, nq = 0, E = 0;
   int32_t qb = 0, kt = 0, cfg_rp = 0, cfg_re = 0;
   int64_t nqb = 0, nkt = 0;
-  int nuc = 1;
-  size_t lds_band = 0;
+  BandPlan band;       // band-rotation work split
+  int nwb = 4;         // band-rotation kernel instance
   // workspace
   void* pq = nullptr;      // T [nq][np]
   double* pqc = nullptr;   // c128 [nq][nc]
@@ -51,6 +51,7 @@ struct Launch {
   int prec = 0;
   int cfg = 0;                 // GEMM: tile configuration of every problem in the launch
   int grid = 0;                // GEMM: persistent workgroups
+  int qidx = -1;               // GEMM: index of its kGroupQueues work-queue counters
   const void* jobs = nullptr;  // device descriptor array
   int n = 0;
   int64_t count = 0;           // total tiles (GEMM) or blocks
@@ -70,6 +71,8 @@ struct ephw_batch {
   void* desc = nullptr;
   size_t desc_bytes = 0;
   std::vector<Launch> launches;
+  int* queues = nullptr;       // kGroupQueues counters per GEMM launch (in the descriptor buffer)
+  int nqueue = 0;              // GEMM launches
   int rounds = 0;
   int cus = 256;
   bool use_graph = false;
@@ -123,7 +126,7 @@ int32_t k_tile_for(const ItemPlan& it, int32_t qb, int64_t cap) {
   const double per_k = (double)qb * it.E * cs + 8.0 * qb;
   if (fixed >= (double)cap) return 0;
   int64_t kt = (int64_t)(((double)cap - fixed) / per_k);
-  if (kt > it.nk) kt = it.nk;
+  if (kt >= it.nk) return (int32_t)it.nk;
   if (kt >= 128) kt -= kt % 64;  // whole 64-row tiles
   return (int32_t)kt;
 }
@@ -304,6 +307,8 @@ struct HostDesc {
 
 ephw_status issue(ephw_batch* bt, hipStream_t st) {
   uint32_t* status = bt->ctx->status;
+  // the grouped GEMMs' work queues start from zero on every pass
+  EPHW_TRY(cgemm_grouped_reset(bt->queues, bt->nqueue * kGroupQueues, st));
   for (const Launch& l : bt->launches) {
     switch (l.kind) {
       case Launch::PHASE: {
@@ -319,7 +324,7 @@ ephw_status issue(ephw_batch* bt, hipStream_t st) {
       }
       case Launch::GEMM:
         EPHW_TRY(cgemm_grouped(l.prec, l.cfg, static_cast<const GroupProblem*>(l.jobs), l.n, l.count,
-                               (int)std::min<int64_t>(l.grid, l.count), st));
+                               (int)std::min<int64_t>(l.grid, l.count), bt->queues + l.qidx * kGroupQueues, st));
         break;
       case Launch::EIGH:
         EPHW_TRY(jacobi_eigh_grouped(static_cast<const EighJob*>(l.jobs), l.n, l.count, status, st));
@@ -328,7 +333,8 @@ ephw_status issue(ephw_batch* bt, hipStream_t st) {
         EPHW_TRY(mode_rotate_grouped(bt->kind, static_cast<const ModeRotateJob*>(l.jobs), l.n, l.count, l.lds, st));
         break;
       case Launch::BAND:
-        EPHW_TRY(band_rotate_grouped(bt->kind, static_cast<const BandRotateJob*>(l.jobs), l.n, l.count, l.lds, st));
+        EPHW_TRY(band_rotate_grouped(bt->kind, l.cfg, static_cast<const BandRotateJob*>(l.jobs), l.n, l.count, l.lds,
+                                     st));
         break;
       case Launch::SUM:
         EPHW_TRY(sum_into_grouped(static_cast<const SumJob*>(l.jobs), l.n, st));
@@ -337,9 +343,6 @@ ephw_status issue(ephw_batch* bt, hipStream_t st) {
   }
   return EPHW_OK;
 }
-
-// LDS size classes of the band-rotation launches
-int lds_class(size_t b) { return b <= 16384 ? 0 : b <= 32768 ? 1 : b <= 65536 ? 2 : 3; }
 
 // Builds the launch list of one pass; descriptor arrays are staged in `hd`
 // and their offsets fixed up once the device copy exists.
@@ -364,6 +367,7 @@ void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, 
       l.grid = bt->cus * cgemm_grouped_blocks_per_cu(prec, cfg);
       l.n = (int)probs.size();
       l.count = cgemm_grouped_layout(prec, probs.data(), l.n);
+      l.qidx = bt->nqueue++;
       push(l, hd.add(probs));
     }
   };
@@ -427,10 +431,11 @@ void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, 
     std::vector<GroupProblem> rp, re;
     std::vector<ModeRotateJob> mj;
     std::vector<BandRotateJob> bj;
+    std::vector<int> bj_cls;
     std::vector<size_t> bj_lds;
     std::vector<SumJob> sj;
-    int64_t mblocks = 0, bblocks = 0;
-    size_t mlds = 0, blds = 0;
+    int64_t mblocks = 0;
+    size_t mlds = 0;
     for (auto& it : bt->items) {
       if (r >= it.units()) continue;
       const int64_t j = r / it.nkt, t = r % it.nkt;
@@ -495,12 +500,12 @@ void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, 
       br.loss_seed = it.in.loss_seed;
       br.q_global0 = q0;
       br.status = bt->ctx->status;
-      b.nuc = it.nuc;
-      b.block_base = bblocks;
-      bblocks += nb * kl;
-      blds = std::max(blds, it.lds_band);
+      b.P = it.band.P;
+      b.nuc = it.band.nuc;
+      b.block_base = 0;
       bj.push_back(b);
-      bj_lds.push_back(it.lds_band);
+      bj_cls.push_back(it.nwb);
+      bj_lds.push_back(it.band.lds);
       if (it.in.flags & EPHW_OUT_LOSS) sj.push_back(SumJob{it.lossp, nb * kl, it.in.loss});
     }
     if (!rp.empty()) {
@@ -514,17 +519,24 @@ void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, 
     }
     {
       push_gemm(kind, re);
-      // one band-rotation launch per LDS class: a launch runs at the
-      // occupancy its largest LDS request allows, so small systems are not
-      // held to the budget of the largest
-      for (int cls = 0; cls < 4; ++cls) {
+      // one band-rotation launch per kernel instance (band count rounded up
+      // to a multiple of 4) and LDS size (in 8 KB steps): a launch runs at the
+      // occupancy its largest LDS request allows
+      std::vector<std::pair<int, size_t>> keys;
+      for (size_t i = 0; i < bj.size(); ++i) {
+        const std::pair<int, size_t> key{bj_cls[i], ceil_div((int64_t)bj_lds[i], 8192)};
+        if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
+      }
+      std::sort(keys.begin(), keys.end());
+      for (const auto& key : keys) {
+        const int cls = key.first;
         std::vector<BandRotateJob> part;
         int64_t blocks = 0;
         size_t lds = 0;
         for (size_t i = 0; i < bj.size(); ++i) {
-          if (lds_class(bj_lds[i]) != cls) continue;
+          if (bj_cls[i] != cls || (size_t)ceil_div((int64_t)bj_lds[i], 8192) != key.second) continue;
           BandRotateJob jb = bj[i];
-          const int64_t nblk = (int64_t)jb.args.qb * jb.args.nk_tile;
+          const int64_t nblk = (int64_t)jb.args.qb * ceil_div(jb.args.nk_tile, (int64_t)jb.P);
           jb.block_base = blocks;
           blocks += nblk;
           lds = std::max(lds, bj_lds[i]);
@@ -533,6 +545,7 @@ void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, 
         if (part.empty()) continue;
         Launch b;
         b.kind = Launch::BAND;
+        b.cfg = cls;
         b.n = (int)part.size();
         b.count = blocks;
         b.lds = lds;
@@ -625,15 +638,17 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
       set_error("ephw_batch_create: item " + std::to_string(i) + " is too large for the grouped GEMM");
       return fail(EPHW_EUNSUPPORTED);
     }
-    it.nuc = band_rotate_modes_per_chunk(kind, it.nw, it.nm, &it.lds_band);
+    it.band = band_rotate_plan(kind, it.nw, it.nm);
+    it.nwb = band_rotate_class(it.nw);
     bt->items.push_back(it);
   }
   int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && cus > 0)
     bt->cus = cus;
-  // Sweep-buffer cap per item: the given per-item cap, else a pass-wide
-  // budget (a quarter of free HBM, at most 32 GiB) shared in proportion to
-  // each item's Eq. (10) work, so the largest systems get the largest units.
+  // Sweep-buffer cap per item: the given per-item cap, else what the item's
+  // largest unit (128 q, every k) needs, at most 8 GiB; if the items together
+  // want more than half of the free HBM, every cap is scaled down to fit (not
+  // below 1 GiB).
   std::vector<int64_t> caps(bt->items.size(), o.item_workspace_bytes);
   if (o.item_workspace_bytes <= 0) {
     size_t fr = 0, tot = 0;
@@ -641,14 +656,18 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
       set_error("ephw_batch_create: hipMemGetInfo failed");
       return fail(EPHW_EDEVICE);
     }
-    const double budget = std::min(32.0 * (1 << 30), 0.25 * (double)fr);
-    double wsum = 0.0;
-    for (auto& it : bt->items) wsum += (double)it.nk * it.nq * it.ne * it.E;
+    const double gib = (double)(1 << 30);
+    const double budget = 0.5 * (double)fr;
+    double want = 0.0;
     for (size_t i = 0; i < bt->items.size(); ++i) {
       const ItemPlan& it = bt->items[i];
-      const double share = wsum > 0 ? budget * ((double)it.nk * it.nq * it.ne * it.E) / wsum : 0.0;
-      caps[i] = (int64_t)std::min(8.0 * (1 << 30), std::max(1.0 * (1 << 30), share));
+      const double cs = (double)csize(bt->kind), qb = (double)std::min<int64_t>(128, std::max<int64_t>(1, it.nq));
+      const double full = 2.0 * qb * it.ne * it.E * cs + (double)it.nk * qb * (it.E * cs + 8.0) + 64.0 * (1 << 20);
+      caps[i] = (int64_t)std::max(gib, std::min(8.0 * gib, full));
+      want += (double)caps[i];
     }
+    if (want > budget)
+      for (auto& c : caps) c = (int64_t)std::max(gib, (double)c * budget / want);
   }
   // shapes: cache, else tune (or heuristics)
   auto cache = read_cache(o.tune_cache);
@@ -691,18 +710,23 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
   HostDesc hd;
   std::vector<std::pair<size_t, size_t>> fix;
   build_launches(bt, hd, fix);
+  const size_t qoff = align256(hd.bytes.size());
+  hd.bytes.resize(qoff + (size_t)std::max(1, bt->nqueue) * kGroupQueues * sizeof(int), 0);
   if ((e = dev_alloc(&bt->desc, hd.bytes.size())) != EPHW_OK) return fail(e);
   bt->desc_bytes = hd.bytes.size();
+  bt->queues = reinterpret_cast<int*>(static_cast<char*>(bt->desc) + qoff);
   if (hipMemcpy(bt->desc, hd.bytes.data(), hd.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {
     set_error("ephw_batch_create: descriptor upload failed");
     return fail(EPHW_EDEVICE);
   }
   for (auto& fx : fix) bt->launches[fx.first].jobs = static_cast<char*>(bt->desc) + fx.second;
   // large-LDS band rotations need the attribute before any capture
-  size_t blds = 0;
-  for (auto& l : bt->launches)
-    if (l.kind == Launch::BAND) blds = std::max(blds, l.lds);
-  if ((e = band_rotate_grouped_prepare(bt->kind, blds)) != EPHW_OK) return fail(e);
+  for (int cls = 4; cls <= 32; cls += 4) {
+    size_t blds = 0;
+    for (auto& l : bt->launches)
+      if (l.kind == Launch::BAND && l.cfg == cls) blds = std::max(blds, l.lds);
+    if ((e = band_rotate_grouped_prepare(bt->kind, cls, blds)) != EPHW_OK) return fail(e);
+  }
   bt->use_graph = o.use_graph != 0;
   if (bt->use_graph) {
     if (hipStreamCreateWithFlags(&bt->cap, hipStreamNonBlocking) != hipSuccess) {

@@ -62,7 +62,8 @@ int64_t cgemm_tiles(int prec, int64_t M, int64_t N);
 ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream);
 
 // Many independent GEMMs C = A B (row-major, no transposes) in one persistent
-// launch: `grid` workgroups stride over the concatenated tile lists.  All
+// launch: `grid` workgroups take tiles of the concatenated tile lists from a
+// work queue (per-XCD ranges, then the others).  All
 // problems of one launch share a tile configuration `cfg` (0 = large,
 // 1 = small 64x64).
 struct GroupProblem {
@@ -84,7 +85,12 @@ int cgemm_grouped_blocks_per_cu(int prec, int cfg);
 bool cgemm_grouped_fits(int prec, int64_t lda, int64_t ldb);
 // fills tiles_m/tiles_n/tile_base of every problem; returns the total tile count
 int64_t cgemm_grouped_layout(int prec, GroupProblem* probs, int n);
+// `queue` points at kGroupQueues ints that must be zero when the launch
+// starts (cgemm_grouped_reset zeroes many with one kernel, so a captured graph
+// holds no memset node); the launch leaves them nonzero.
+constexpr int kGroupQueues = 8;
 ephw_status cgemm_grouped(int prec, int cfg, const GroupProblem* d_probs, int n, int64_t total_tiles, int grid,
-                          hipStream_t stream);
+                          int* queue, hipStream_t stream);
+ephw_status cgemm_grouped_reset(int* queues, int count, hipStream_t stream);
 
 }  // namespace ephw

@@ -50,6 +50,7 @@ struct Mfma<double> {
 
 constexpr int kGroupM = 8;
 constexpr int kXcds = 8;
+static_assert(kGroupQueues == kXcds, "one grouped-GEMM work queue per XCD");
 
 // bijection on [0, n): workgroup id -> logical tile, consecutive logical tiles on one XCD
 __device__ __forceinline__ int64_t xcd_remap(int64_t id, int64_t n) {
@@ -528,25 +529,56 @@ struct GroupCfg<double> {
 
 // One launch serves problems of one tile configuration (CFG), so each
 // instance gets the register budget of its own tile.
+// Work queue of the grouped kernel: the tile list is cut into kXcds
+// contiguous ranges, one per XCD, each with a counter in `queue` (zeroed
+// before the launch).  A workgroup takes tiles from its own XCD's range in
+// order (neighbouring tiles share A and B panels in that XCD's L2) and, once
+// that range is used up, from the other ranges; so workgroups that draw cheap
+// tiles (small K) take more of them.  Every range is handed out exactly once
+// and every workgroup stops after finding all ranges used up.
+__device__ __forceinline__ int64_t queue_lo(int q, int64_t total) { return (int64_t)q * total / kXcds; }
+
+__device__ __forceinline__ int64_t queue_grab(int* __restrict__ queue, int64_t total, int& q, int& tried) {
+  while (tried < kXcds) {
+    const int64_t t = queue_lo(q, total) + atomicAdd(&queue[q], 1);
+    if (t < queue_lo(q + 1, total)) return t;
+    q = (q + 1) % kXcds;
+    ++tried;
+  }
+  return -1;
+}
+
 template <typename T, int CFG>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-    cgemm_grouped_kernel(const GroupProblem* __restrict__ probs, int n, int64_t total) {
+    cgemm_grouped_kernel(const GroupProblem* __restrict__ probs, int n, int64_t total, int* __restrict__ queue) {
   using G = GroupCfg<T>;
   constexpr int BM = CFG == 0 ? G::LM : G::SM, BN = CFG == 0 ? G::LN : G::SN, BK = CFG == 0 ? G::LK : G::SK;
   using Sh = TileShape<T, BM, BN, BK, 2, 2, false>;
   __shared__ T smem[Sh::smem_elems];
-  // sweeps of gridDim.x consecutive tiles; within a sweep, consecutive tiles
-  // go to one XCD (workgroups are dealt to the XCDs round-robin)
-  for (int64_t base = 0; base < total; base += gridDim.x) {
-    const int64_t span = (total - base) < (int64_t)gridDim.x ? (total - base) : (int64_t)gridDim.x;
-    if ((int64_t)blockIdx.x >= span) break;
-    const int64_t t = base + xcd_remap(blockIdx.x, span);
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (probs[mid].tile_base <= t) lo = mid; else hi = mid - 1;
+  __shared__ int64_t s_next;
+  int q = blockIdx.x % kXcds, tried = 0;   // used by thread 0 only
+  if (threadIdx.x == 0) s_next = queue_grab(queue, total, q, tried);
+  __syncthreads();
+  int64_t t = s_next;
+  while (t >= 0) {
+    __syncthreads();   // every thread has read s_next
+    // the next grab from the current range is issued now and resolved after
+    // the tile, so its latency hides behind the tile's loads
+    int pending = 0;
+    if (threadIdx.x == 0 && tried < kXcds) pending = atomicAdd(&queue[q], 1);
+    // problem index: how many problems start at or before tile t, less one
+    // (one parallel load per 64 problems and a ballot per wave)
+    int lo = -1;
+    {
+      const int lane = threadIdx.x & 63;
+      int cnt = 0;
+      for (int i0 = 0; i0 < n; i0 += 64) {
+        const bool le = (i0 + lane < n) && probs[i0 + lane].tile_base <= t;
+        cnt += __popcll(__ballot(le));
+      }
+      lo = cnt - 1;
     }
-    const GroupProblem& P = probs[lo];
+    const GroupProblem P = probs[lo];
     int64_t tm, tn;
     tile_coords(t - P.tile_base, P.tiles_m, P.tiles_n, &tm, &tn);
     TileJob<T> j;
@@ -569,8 +601,26 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     j.tile = 0;
     j.ntiles = 1;
     gemm_tile<T, BM, BN, BK, 2, 2, false, false, false>(j, tm * BM, tn * BN, smem);
+    if (threadIdx.x == 0) {
+      int64_t nt = -1;
+      if (tried < kXcds) {
+        nt = queue_lo(q, total) + pending;
+        if (nt >= queue_lo(q + 1, total)) {
+          q = (q + 1) % kXcds;
+          ++tried;
+          nt = queue_grab(queue, total, q, tried);
+        }
+      }
+      s_next = nt;
+    }
     __syncthreads();
+    t = s_next;
   }
+}
+
+__global__ void zero_ints_kernel(int* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 // The buffer loads address a row group of RSTEP operand rows with 32-bit
@@ -687,20 +737,35 @@ int64_t cgemm_grouped_layout(int prec, GroupProblem* probs, int n) {
 }
 
 ephw_status cgemm_grouped(int prec, int cfg, const GroupProblem* d_probs, int n, int64_t total_tiles, int grid,
-                          hipStream_t stream) {
+                          int* queue, hipStream_t stream) {
   if (n <= 0 || total_tiles <= 0) return EPHW_OK;
   if (grid <= 0) grid = 1;
+  if (total_tiles > 0x7fffffffll) {
+    set_error("cgemm_grouped: too many tiles");
+    return EPHW_EUNSUPPORTED;
+  }
   if (prec == 0) {
     if (cfg == 0)
-      hipLaunchKernelGGL((cgemm_grouped_kernel<double, 0>), dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles);
+      hipLaunchKernelGGL((cgemm_grouped_kernel<double, 0>), dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles,
+                         queue);
     else
-      hipLaunchKernelGGL((cgemm_grouped_kernel<double, 1>), dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles);
+      hipLaunchKernelGGL((cgemm_grouped_kernel<double, 1>), dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles,
+                         queue);
   } else {
     if (cfg == 0)
-      hipLaunchKernelGGL((cgemm_grouped_kernel<float, 0>), dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles);
+      hipLaunchKernelGGL((cgemm_grouped_kernel<float, 0>), dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles,
+                         queue);
     else
-      hipLaunchKernelGGL((cgemm_grouped_kernel<float, 1>), dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles);
+      hipLaunchKernelGGL((cgemm_grouped_kernel<float, 1>), dim3(grid), dim3(256), 0, stream, d_probs, n, total_tiles,
+                         queue);
   }
+  EPHW_CHECK_LAUNCH();
+  return EPHW_OK;
+}
+
+ephw_status cgemm_grouped_reset(int* queues, int count, hipStream_t stream) {
+  if (count <= 0) return EPHW_OK;
+  hipLaunchKernelGGL(zero_ints_kernel, dim3((unsigned)ceil_div(count, 256)), dim3(256), 0, stream, queues, count);
   EPHW_CHECK_LAUNCH();
   return EPHW_OK;
 }

@@ -66,8 +66,15 @@ struct BandRotateArgs {
   uint32_t* status;
 };
 ephw_status band_rotate(int prec, const BandRotateArgs& a, hipStream_t s);
-// modes per LDS chunk of the band-rotation kernel and its dynamic LDS bytes
-int band_rotate_modes_per_chunk(int prec, int nw, int nm, size_t* lds_bytes);
+// Work split of the band-rotation kernel (Nw <= 32): P consecutive k per
+// workgroup, nuc modes per LDS chunk, dynamic LDS bytes.
+struct BandPlan {
+  int P = 1, nuc = 1;
+  size_t lds = 0;
+};
+BandPlan band_rotate_plan(int prec, int nw, int nm);
+// kernel instance of a band count: Nw rounded up to a multiple of 4
+int band_rotate_class(int nw);
 
 // grouped launches over many systems: block b belongs to the job with the
 // largest block_base <= b (jobs sorted by block_base)
@@ -83,13 +90,15 @@ ephw_status mode_rotate_grouped(int prec, const ModeRotateJob* d_jobs, int n, in
                                 hipStream_t s);
 struct BandRotateJob {
   BandRotateArgs args;
-  int nuc;
-  int64_t block_base;     // blocks: qb * nk_tile
+  int P, nuc;             // from band_rotate_plan
+  int64_t block_base;     // blocks: qb * ceil(nk_tile / P)
 };
-// launches never change kernel attributes (they may be captured in a graph):
-// call band_rotate_grouped_prepare with the largest LDS size first
-ephw_status band_rotate_grouped_prepare(int prec, size_t lds);
-ephw_status band_rotate_grouped(int prec, const BandRotateJob* d_jobs, int n, int64_t blocks, size_t lds,
+// All jobs of one grouped launch share the kernel instance `nwb`
+// (band_rotate_class).  Launches never change kernel attributes (they may be
+// captured in a graph): call band_rotate_grouped_prepare for each instance
+// with its largest LDS size first.
+ephw_status band_rotate_grouped_prepare(int prec, int nwb, size_t lds);
+ephw_status band_rotate_grouped(int prec, int nwb, const BandRotateJob* d_jobs, int n, int64_t blocks, size_t lds,
                                 hipStream_t s);
 struct SumJob {
   const double* x;

@@ -104,22 +104,26 @@ __global__ void mode_rotate_kernel(const T* __restrict__ G, const T* __restrict_
   mode_rotate_body<T>(G, u, Gnu, ne, qb, nm, nw2, blockIdx.y, blockIdx.x, reinterpret_cast<T*>(smem_raw));
 }
 
-// find the job whose [block_base, next block_base) holds block b
+// The job whose [block_base, next block_base) holds block b: block_base
+// ascends, so the index is the number of jobs with block_base <= b, less one.
+// Each wave counts with one parallel load per 64 jobs and a ballot (no chain
+// of dependent loads).
 template <typename J>
 __device__ __forceinline__ int find_job(const J* jobs, int n, int64_t b) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].block_base <= b) lo = mid; else hi = mid - 1;
+  const int lane = threadIdx.x & 63;
+  int cnt = 0;
+  for (int i0 = 0; i0 < n; i0 += 64) {
+    const bool le = (i0 + lane < n) && jobs[i0 + lane].block_base <= b;
+    cnt += __popcll(__ballot(le));
   }
-  return lo;
+  return cnt - 1;
 }
 
 template <typename T>
 __global__ void mode_rotate_grouped_kernel(const ModeRotateJob* __restrict__ jobs, int n) {
   extern __shared__ unsigned char smem_raw[];
   const int64_t b = blockIdx.x;
-  const ModeRotateJob& j = jobs[find_job(jobs, n, b)];
+  const ModeRotateJob j = jobs[find_job(jobs, n, b)];
   const int64_t local = b - j.block_base;
   const int64_t per_q = ceil_div(j.ne * j.nw2, (int64_t)blockDim.x);
   mode_rotate_body<T>(static_cast<const T*>(j.G), static_cast<const T*>(j.u), static_cast<T*>(j.Gnu), j.ne,
@@ -136,152 +140,261 @@ __device__ __forceinline__ double loss_weight(uint64_t seed, uint64_t index) {
   return 0.5 + (double)(z >> 40) * 0x1p-24;
 }
 
-// One workgroup per (k, q) pair.  LDS: V(k), V(k+q), then chunks of nu
-// matrices: X (the Re sums) and Tmp = X V(k).
+// Band rotation g_nu = V(k+q)^dagger X_nu V(k) for Nw <= 32, one row of one
+// mode per thread.  A workgroup takes P consecutive k of one q (P pairs
+// whose Nm*Nw rows fill the 256 threads) or, for larger pairs, one pair in
+// chunks of nuc modes.  Per chunk:
+//   1. the chunk's X rows are copied, coalesced, into LDS (rows padded to
+//      Nw+1 complex values to spread the banks); for Nw <= 8 each thread
+//      reads its own row into registers instead;
+//   2. thread (pair p, mode v, row m') forms T[m'][:] = X[m'][:] V(k) from
+//      its own X row and V(k) (an LDS broadcast, every lane of the pair
+//      reads the same element) and writes it over its X row;
+//   3. after a barrier thread (p, v, m) forms g[m][:] = sum_m'
+//      conj(V(k+q)[m'][m]) T[m'][:] from the mode's T rows;
+//   4. epilogues: store g (one contiguous row per thread), row sums of |g|^2
+//      (band sums, summed per mode in a fixed order), weighted |g|^2 (loss,
+//      summed per pair in a fixed order).
+// NWB is Nw rounded up to a multiple of 4; the column loops are unrolled to
+// NWB with a uniform guard, so the accumulators stay in registers.
 constexpr int kRotThreads = 256;
 
 template <typename T>
-__device__ __forceinline__ void band_rotate_body(const BandRotateArgs& a, int nuc, int64_t ik_local,
-                                                 int iq, unsigned char* smem_raw) {
-  const int nw = a.nw, nm = a.nm;
+struct BandLds {
+  T* vk;        // [P][nw2] complex
+  T* vkq;       // [P][nw2] complex
+  T* rows;      // [P * rows_pp][nw + 1] complex
+  double* red;  // [kRotThreads]
+};
+
+template <typename T>
+__device__ __forceinline__ BandLds<T> band_lds(unsigned char* smem_raw, int P, int nw, int rows_pp) {
+  BandLds<T> L;
   const int nw2 = nw * nw;
-  const int64_t ik = a.k0 + ik_local;   // global k index
+  L.vk = reinterpret_cast<T*>(smem_raw);
+  L.vkq = L.vk + 2 * P * nw2;
+  L.rows = L.vkq + 2 * P * nw2;
+  size_t off = (size_t)2 * sizeof(T) * ((size_t)2 * P * nw2 + (size_t)P * rows_pp * (nw + 1));
+  off = (off + 7) & ~(size_t)7;
+  L.red = reinterpret_cast<double*>(smem_raw + off);
+  return L;
+}
+
+template <typename T, int NWB>
+__device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, int nuc, int64_t kblk, int iq,
+                                               unsigned char* smem_raw) {
+  constexpr bool DIRECT = NWB <= 8;   // X rows fit in registers
+  const int nw = a.nw, nm = a.nm, nw2 = nw * nw, ld = nw + 1;
   const int64_t E = (int64_t)nm * nw2;
   const bool rot = a.Vk != nullptr;
-  T* vk = reinterpret_cast<T*>(smem_raw);            // [nw][nw]
-  T* vkq = vk + 2 * nw2;                              // [nw][nw]
-  T* xs = vkq + 2 * nw2;                              // [nuc][nw][nw]
-  T* ts = xs + 2 * nuc * nw2;                         // [nuc][nw][nw]
-  double* m2s = reinterpret_cast<double*>(ts + 2 * nuc * nw2);  // [nuc][nw][nw] |y|^2
-  double* red = m2s + nuc * nw2;                      // [kRotThreads/64]
   const int tid = threadIdx.x;
+  const int rows_pp = nuc * nw;
+  const int p = tid / rows_pp, r = tid % rows_pp;
+  const int vl = r / nw, mrow = r % nw;
+  const int64_t ik0 = kblk * P;                                    // first local k of the block
+  const int npair = (int)((a.nk_tile - ik0) < P ? (a.nk_tile - ik0) : P);
+  const bool in_pair = p < npair;
+  BandLds<T> L = band_lds<T>(smem_raw, P, nw, rows_pp);
 
   if (rot) {
     const T* Vk = static_cast<const T*>(a.Vk);
-    int64_t jk;
-    const T* src;
-    if (a.kq_index) {
-      int64_t id = a.kq_index[(int64_t)iq * a.nk + ik];
-      if (id < 0 || id >= a.nk) {
-        if (tid == 0) atomicOr(a.status, kStatusIndex);
-        id = 0;
+    for (int i = tid; i < npair * nw2; i += kRotThreads) {
+      const int pp = i / nw2, e = i % nw2;
+      const int64_t ik = a.k0 + ik0 + pp;
+      const T* src;
+      if (a.kq_index) {
+        int64_t id = a.kq_index[(int64_t)iq * a.nk + ik];
+        if (id < 0 || id >= a.nk) {
+          if (e == 0) atomicOr(a.status, kStatusIndex);
+          id = 0;
+        }
+        src = Vk + 2 * id * nw2;
+      } else {
+        src = static_cast<const T*>(a.Vkq) + 2 * ((int64_t)iq * a.nk + ik) * nw2;
       }
-      jk = id;
-      src = Vk + 2 * jk * nw2;
-    } else {
-      src = static_cast<const T*>(a.Vkq) + 2 * ((int64_t)iq * a.nk + ik) * nw2;
-    }
-    for (int i = tid; i < nw2; i += kRotThreads) {
-      vk[2 * i] = Vk[2 * (ik * nw2 + i)];
-      vk[2 * i + 1] = Vk[2 * (ik * nw2 + i) + 1];
-      vkq[2 * i] = src[2 * i];
-      vkq[2 * i + 1] = src[2 * i + 1];
+      L.vk[2 * i] = Vk[2 * (ik * nw2 + e)];
+      L.vk[2 * i + 1] = Vk[2 * (ik * nw2 + e) + 1];
+      L.vkq[2 * i] = src[2 * e];
+      L.vkq[2 * i + 1] = src[2 * e + 1];
     }
   }
-  const T* W = static_cast<const T*>(a.W) + 2 * (ik_local * (int64_t)a.qb * E + (int64_t)iq * E);
-  T* gout = a.g_out ? static_cast<T*>(a.g_out) + 2 * (((int64_t)iq * a.nk + ik) * E) : nullptr;
-  const bool want_g = (a.flags & EPHW_OUT_G) && gout;
+  const bool want_g = (a.flags & EPHW_OUT_G) && a.g_out;
   const bool want_t = (a.flags & EPHW_OUT_BAND_SUM) && a.band_sum;
   const bool want_l = (a.flags & EPHW_OUT_LOSS) && a.loss_partial;
-  const uint64_t pair_base =
-      ((uint64_t)(a.q_global0 + iq) * (uint64_t)a.nk + (uint64_t)ik) * (uint64_t)E;
+  const int64_t ik_l = ik0 + p;           // this thread's local k
+  const int64_t ik = a.k0 + ik_l;
+  const T* W = static_cast<const T*>(a.W);
   double lsum = 0.0;
 
   for (int v0 = 0; v0 < nm; v0 += nuc) {
     const int nv = (nm - v0) < nuc ? (nm - v0) : nuc;
-    __syncthreads();
-    for (int i = tid; i < nv * nw2; i += kRotThreads) {
-      xs[2 * i] = W[2 * ((int64_t)v0 * nw2 + i)];
-      xs[2 * i + 1] = W[2 * ((int64_t)v0 * nw2 + i) + 1];
+    const bool act = in_pair && vl < nv;
+    // 1. X rows of the chunk -> LDS (small bands: each thread reads its own
+    //    row straight into registers in step 2 instead)
+    const int cw = nv * nw2;   // complex values per pair in this chunk
+    for (int i = tid; i < ((DIRECT && rot) ? 0 : npair * cw); i += kRotThreads) {
+      const int pp = i / cw, e = i % cw;
+      const T* src = W + 2 * ((ik0 + pp) * (int64_t)a.qb * E + (int64_t)iq * E + (int64_t)v0 * nw2 + e);
+      T* dst = L.rows + 2 * ((pp * rows_pp + e / nw) * ld + e % nw);
+      dst[0] = src[0];
+      dst[1] = src[1];
     }
     __syncthreads();
+    T* own = L.rows + 2 * (tid * ld);
+    cplx<T> acc[NWB];
     if (rot) {
-      // Tmp[v][m'][n] = sum_n' X[v][m'][n'] V(k)[n'][n]
-      for (int i = tid; i < nv * nw2; i += kRotThreads) {
-        const int v = i / nw2, r = (i / nw) % nw, c = i % nw;
-        cplx<T> acc = {0, 0};
-        const T* xr = xs + 2 * (v * nw2 + r * nw);
-        for (int j = 0; j < nw; ++j)
-          cfma(acc, cplx<T>{xr[2 * j], xr[2 * j + 1]}, cplx<T>{vk[2 * (j * nw + c)], vk[2 * (j * nw + c) + 1]});
-        ts[2 * i] = acc.re;
-        ts[2 * i + 1] = acc.im;
+      // 2. T row = X row V(k)
+      if (act) {
+#pragma unroll
+        for (int n = 0; n < NWB; ++n) acc[n] = cplx<T>{0, 0};
+        const T* vkp = L.vk + 2 * p * nw2;
+        if (DIRECT) {
+          const T* xrow = W + 2 * (ik_l * (int64_t)a.qb * E + (int64_t)iq * E + (int64_t)(v0 + vl) * nw2 +
+                                   (int64_t)mrow * nw);
+          cplx<T> x[NWB];
+#pragma unroll
+          for (int j = 0; j < NWB; ++j) x[j] = j < nw ? cplx<T>{xrow[2 * j], xrow[2 * j + 1]} : cplx<T>{0, 0};
+#pragma unroll
+          for (int j = 0; j < NWB; ++j) {
+            const T* vr = vkp + 2 * j * nw;
+#pragma unroll
+            for (int n = 0; n < NWB; ++n)
+              if (j < nw && n < nw) cfma(acc[n], x[j], cplx<T>{vr[2 * n], vr[2 * n + 1]});
+          }
+        } else {
+          for (int j = 0; j < nw; ++j) {
+            const cplx<T> x{own[2 * j], own[2 * j + 1]};
+            const T* vr = vkp + 2 * j * nw;
+#pragma unroll
+            for (int n = 0; n < NWB; ++n)
+              if (n < nw) cfma(acc[n], x, cplx<T>{vr[2 * n], vr[2 * n + 1]});
+          }
+        }
+#pragma unroll
+        for (int n = 0; n < NWB; ++n)
+          if (n < nw) {
+            own[2 * n] = acc[n].re;
+            own[2 * n + 1] = acc[n].im;
+          }
       }
       __syncthreads();
+      // 3. g row m = sum_m' conj(V(k+q)[m'][m]) T[m'][:]
+      if (act) {
+#pragma unroll
+        for (int n = 0; n < NWB; ++n) acc[n] = cplx<T>{0, 0};
+        const T* vq = L.vkq + 2 * p * nw2;
+        const T* tb = L.rows + 2 * ((p * rows_pp + vl * nw) * ld);
+        for (int j = 0; j < nw; ++j) {
+          const cplx<T> c{vq[2 * (j * nw + mrow)], vq[2 * (j * nw + mrow) + 1]};
+          const T* tr = tb + 2 * j * ld;
+#pragma unroll
+          for (int n = 0; n < NWB; ++n)
+            if (n < nw) cfmac(acc[n], c, cplx<T>{tr[2 * n], tr[2 * n + 1]});
+        }
+      }
+    } else if (act) {
+#pragma unroll
+      for (int n = 0; n < NWB; ++n)
+        if (n < nw) acc[n] = cplx<T>{own[2 * n], own[2 * n + 1]};
     }
-    // Y[v][m][n] = sum_m' conj(V(k+q)[m'][m]) Tmp[v][m'][n]
-    for (int i = tid; i < nv * nw2; i += kRotThreads) {
-      const int v = i / nw2, r = (i / nw) % nw, c = i % nw;
-      cplx<T> y;
-      if (rot) {
-        y = {0, 0};
-        const T* tc = ts + 2 * (v * nw2 + c);
-        for (int j = 0; j < nw; ++j)
-          cfmac(y, cplx<T>{vkq[2 * (j * nw + r)], vkq[2 * (j * nw + r) + 1]},
-                cplx<T>{tc[2 * j * nw], tc[2 * j * nw + 1]});
-      } else {
-        y = {xs[2 * i], xs[2 * i + 1]};
-      }
-      const int64_t eidx = (int64_t)v0 * nw2 + i;
+    // 4. epilogues
+    double rsum = 0.0;
+    if (act) {
+      const int nu = v0 + vl;
+      const int64_t eoff = (int64_t)nu * nw2 + (int64_t)mrow * nw;   // element offset in the pair
       if (want_g) {
-        gout[2 * eidx] = y.re;
-        gout[2 * eidx + 1] = y.im;
+        T* go = static_cast<T*>(a.g_out) + 2 * (((int64_t)iq * a.nk + ik) * E + eoff);
+#pragma unroll
+        for (int n = 0; n < NWB; ++n)
+          if (n < nw) {
+            go[2 * n] = acc[n].re;
+            go[2 * n + 1] = acc[n].im;
+          }
       }
-      const double m2 = (double)y.re * (double)y.re + (double)y.im * (double)y.im;
-      if (want_t) m2s[i] = m2;
-      if (want_l) lsum += loss_weight(a.loss_seed, pair_base + (uint64_t)eidx) * m2;
+      const uint64_t base = ((uint64_t)(a.q_global0 + iq) * (uint64_t)a.nk + (uint64_t)ik) * (uint64_t)E +
+                            (uint64_t)eoff;
+#pragma unroll
+      for (int n = 0; n < NWB; ++n)
+        if (n < nw) {
+          const double m2 = (double)acc[n].re * (double)acc[n].re + (double)acc[n].im * (double)acc[n].im;
+          rsum += m2;
+          if (want_l) lsum += loss_weight(a.loss_seed, base + (uint64_t)n) * m2;
+        }
     }
     if (want_t) {
+      L.red[tid] = rsum;
       __syncthreads();
-      // fixed-order sum of |y|^2 over (m, n) for every mode of the chunk
-      for (int v = tid; v < nv; v += kRotThreads) {
-        const double* m2 = m2s + v * nw2;
+      // per (pair, mode): rows m = 0..nw-1 in order
+      for (int t = tid; t < npair * nv; t += kRotThreads) {
+        const int pp = t / nv, v = t % nv;
+        const double* rr = L.red + pp * rows_pp + v * nw;
         double s = 0.0;
-        for (int i = 0; i < nw2; ++i) s += m2[i];
-        a.band_sum[((int64_t)iq * a.nk + ik) * nm + v0 + v] = s;
+        for (int m = 0; m < nw; ++m) s += rr[m];
+        a.band_sum[((int64_t)iq * a.nk + a.k0 + ik0 + pp) * nm + v0 + v] = s;
       }
     }
+    __syncthreads();   // the rows buffer (and red) are rewritten by the next chunk
   }
   if (want_l) {
-    double* wred = red;
-    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off, 64);
+    L.red[tid] = lsum;
     __syncthreads();
-    if ((tid & 63) == 0) wred[tid >> 6] = lsum;
-    __syncthreads();
-    if (tid == 0) {
+    // per pair: its threads in order
+    if (tid < npair) {
+      const double* rr = L.red + tid * rows_pp;
       double s = 0.0;
-      for (int w = 0; w < kRotThreads / 64; ++w) s += wred[w];
-      a.loss_partial[(int64_t)iq * a.nk_tile + ik_local] = s;
+      for (int i = 0; i < rows_pp; ++i) s += rr[i];
+      a.loss_partial[(int64_t)iq * a.nk_tile + ik0 + tid] = s;
     }
   }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kRotThreads) band_rotate_kernel(BandRotateArgs a, int nuc) {
+template <typename T, int NWB>
+__global__ void __launch_bounds__(kRotThreads) band_rotate_kernel(BandRotateArgs a, int P, int nuc) {
   extern __shared__ unsigned char smem_raw[];
-  band_rotate_body<T>(a, nuc, blockIdx.x, blockIdx.y, smem_raw);
+  band_rows_body<T, NWB>(a, P, nuc, blockIdx.x, blockIdx.y, smem_raw);
 }
 
-template <typename T>
+template <typename T, int NWB>
 __global__ void __launch_bounds__(kRotThreads) band_rotate_grouped_kernel(const BandRotateJob* __restrict__ jobs,
                                                                           int n) {
   extern __shared__ unsigned char smem_raw[];
   const int64_t b = blockIdx.x;
-  const BandRotateJob& j = jobs[find_job(jobs, n, b)];
+  const BandRotateJob j = jobs[find_job(jobs, n, b)];   // by value: the fields stay in registers
   const int64_t local = b - j.block_base;
-  band_rotate_body<T>(j.args, j.nuc, local % j.args.nk_tile, (int)(local / j.args.nk_tile), smem_raw);
+  const int64_t kb = ceil_div(j.args.nk_tile, (int64_t)j.P);
+  band_rows_body<T, NWB>(j.args, j.P, j.nuc, local % kb, (int)(local / kb), smem_raw);
 }
 
-__global__ void sum_into_kernel(const double* __restrict__ x, int64_t n, double* __restrict__ out) {
-  __shared__ double red[256];
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) s += x[i];
-  red[threadIdx.x] = s;
+// out += sum of x[0..n) by one workgroup of kSumThreads, in a fixed order:
+// thread t sums x[t + kSumThreads (4 j + r)] into four partial sums r (four
+// independent load streams), then the workgroup adds them in a tree.
+constexpr int kSumThreads = 1024;
+
+__device__ __forceinline__ void block_sum_into(const double* __restrict__ x, int64_t n, double* __restrict__ out,
+                                               double* red) {
+  const int t = threadIdx.x;
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  int64_t i = t;
+  for (; i + 3 * kSumThreads < n; i += 4 * kSumThreads) {
+    s0 += x[i];
+    s1 += x[i + kSumThreads];
+    s2 += x[i + 2 * kSumThreads];
+    s3 += x[i + 3 * kSumThreads];
+  }
+  for (; i < n; i += kSumThreads) s0 += x[i];
+  red[t] = (s0 + s1) + (s2 + s3);
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+  for (int w = kSumThreads / 2; w > 0; w >>= 1) {
+    if (t < w) red[t] += red[t + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[0] += red[0];
+  if (t == 0 && n > 0) out[0] += red[0];
+}
+
+__global__ void __launch_bounds__(kSumThreads) sum_into_kernel(const double* __restrict__ x, int64_t n,
+                                                               double* __restrict__ out) {
+  __shared__ double red[kSumThreads];
+  block_sum_into(x, n, out, red);
 }
 
 __global__ void gather_rows_kernel(const double* __restrict__ src, int64_t nsrc,
@@ -362,50 +475,102 @@ ephw_status mode_rotate(int prec, const void* G, const void* u, void* Gnu, int64
   return EPHW_OK;
 }
 
-int band_rotate_modes_per_chunk(int prec, int nw, int nm, size_t* lds_bytes) {
-  const size_t esz = 2 * (prec == 0 ? 8 : 4);
-  const size_t nw2 = (size_t)nw * nw;
-  const size_t fixed = esz * 2 * nw2 + 8 * (kRotThreads / 64);
-  const size_t per_mode = (2 * esz + 8) * nw2;
-  int nuc = fixed + per_mode <= 65536 ? (int)((65536 - fixed) / per_mode) : 1;
-  if (nuc > nm) nuc = nm;
-  if (lds_bytes) *lds_bytes = fixed + per_mode * (size_t)nuc;
-  return nuc;
+namespace {
+
+size_t band_lds_bytes(int prec, int nw, int P, int nuc) {
+  const size_t cs = prec == 0 ? 16 : 8;
+  size_t b = cs * ((size_t)2 * P * nw * nw + (size_t)P * nuc * nw * (nw + 1));
+  b = (b + 7) & ~(size_t)7;
+  return b + 8 * kRotThreads;
+}
+
+template <typename T>
+using BandKernel = void (*)(BandRotateArgs, int, int);
+template <typename T>
+using BandGroupedKernel = void (*)(const BandRotateJob*, int);
+
+template <typename T>
+BandKernel<T> band_kernel(int nwb) {
+  switch (nwb) {
+    case 4: return band_rotate_kernel<T, 4>;
+    case 8: return band_rotate_kernel<T, 8>;
+    case 12: return band_rotate_kernel<T, 12>;
+    case 16: return band_rotate_kernel<T, 16>;
+    case 20: return band_rotate_kernel<T, 20>;
+    case 24: return band_rotate_kernel<T, 24>;
+    case 28: return band_rotate_kernel<T, 28>;
+    default: return band_rotate_kernel<T, 32>;
+  }
+}
+template <typename T>
+BandGroupedKernel<T> band_grouped_kernel(int nwb) {
+  switch (nwb) {
+    case 4: return band_rotate_grouped_kernel<T, 4>;
+    case 8: return band_rotate_grouped_kernel<T, 8>;
+    case 12: return band_rotate_grouped_kernel<T, 12>;
+    case 16: return band_rotate_grouped_kernel<T, 16>;
+    case 20: return band_rotate_grouped_kernel<T, 20>;
+    case 24: return band_rotate_grouped_kernel<T, 24>;
+    case 28: return band_rotate_grouped_kernel<T, 28>;
+    default: return band_rotate_grouped_kernel<T, 32>;
+  }
+}
+
+}  // namespace
+
+int band_rotate_class(int nw) { return 4 * (int)ceil_div(nw, 4); }
+
+BandPlan band_rotate_plan(int prec, int nw, int nm) {
+  BandPlan pl;
+  const int rows = nm * nw;
+  if (rows <= kRotThreads) {
+    pl.nuc = nm;
+    pl.P = kRotThreads / rows;
+  } else {
+    pl.nuc = kRotThreads / nw;
+    pl.P = 1;
+  }
+  // fit 64 KB of LDS (several workgroups per CU); if that leaves fewer than
+  // 128 busy threads, use up to 160 KB instead
+  for (size_t cap : {(size_t)65536, (size_t)163840}) {
+    int P = pl.P, nuc = pl.nuc;
+    while (band_lds_bytes(prec, nw, P, nuc) > cap && (P > 1 || nuc > 1)) {
+      if (P > 1) --P; else --nuc;
+    }
+    if (band_lds_bytes(prec, nw, P, nuc) <= cap && (P * nuc * nw >= 128 || cap > 65536)) {
+      pl.P = P;
+      pl.nuc = nuc;
+      break;
+    }
+  }
+  pl.lds = band_lds_bytes(prec, nw, pl.P, pl.nuc);
+  return pl;
 }
 
 ephw_status band_rotate(int prec, const BandRotateArgs& a, hipStream_t s) {
   if (a.nk_tile <= 0 || a.qb <= 0) return EPHW_OK;
-  if (a.nw > 32) {
-    set_error("band_rotate: this kernel handles nw <= 32");
+  if (a.nw > 32 || a.nw < 1) {
+    set_error("band_rotate: this kernel handles 1 <= nw <= 32");
     return EPHW_EUNSUPPORTED;
   }
-  const size_t esz = 2 * (prec == 0 ? 8 : 4);
-  const int nw2 = a.nw * a.nw;
-  // chunk of modes so that V(k), V(k+q), X, Tmp and |y|^2 fit in 64 KB of LDS
-  const size_t fixed = esz * 2 * nw2 + 8 * (kRotThreads / 64);
-  const size_t per_mode = (2 * esz + 8) * nw2;
-  int nuc = fixed + per_mode <= 65536 ? (int)((65536 - fixed) / per_mode) : 1;
-  if (nuc > a.nm) nuc = a.nm;
-  const size_t lds = fixed + per_mode * (size_t)nuc;
-  if (lds > 65536) {
-    // large FP64 bands: use the bigger LDS of gfx950 (160 KB per workgroup)
-    if (prec == 0)
-      EPHW_HIP(hipFuncSetAttribute((const void*)band_rotate_kernel<double>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    else
-      EPHW_HIP(hipFuncSetAttribute((const void*)band_rotate_kernel<float>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  }
-  if (a.nk_tile > 0x7fffffff || a.qb > 65535) {
+  const BandPlan pl = band_rotate_plan(prec, a.nw, a.nm);
+  const int64_t kb = ceil_div(a.nk_tile, (int64_t)pl.P);
+  if (kb > 0x7fffffff || a.qb > 65535) {
     set_error("band_rotate: grid too large");
     return EPHW_EUNSUPPORTED;
   }
-  if (prec == 0)
-    hipLaunchKernelGGL(band_rotate_kernel<double>, dim3((unsigned)a.nk_tile, a.qb), dim3(kRotThreads), lds,
-                       s, a, nuc);
-  else
-    hipLaunchKernelGGL(band_rotate_kernel<float>, dim3((unsigned)a.nk_tile, a.qb), dim3(kRotThreads), lds,
-                       s, a, nuc);
+  const int nwb = band_rotate_class(a.nw);
+  if (prec == 0) {
+    auto k = band_kernel<double>(nwb);
+    if (pl.lds > 65536)
+      EPHW_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds));
+    hipLaunchKernelGGL(k, dim3((unsigned)kb, a.qb), dim3(kRotThreads), pl.lds, s, a, pl.P, pl.nuc);
+  } else {
+    auto k = band_kernel<float>(nwb);
+    if (pl.lds > 65536)
+      EPHW_HIP(hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)pl.lds));
+    hipLaunchKernelGGL(k, dim3((unsigned)kb, a.qb), dim3(kRotThreads), pl.lds, s, a, pl.P, pl.nuc);
+  }
   EPHW_CHECK_LAUNCH();
   return EPHW_OK;
 }
@@ -430,54 +595,46 @@ ephw_status mode_rotate_grouped(int prec, const ModeRotateJob* d_jobs, int n, in
   return EPHW_OK;
 }
 
-ephw_status band_rotate_grouped_prepare(int prec, size_t lds) {
+ephw_status band_rotate_grouped_prepare(int prec, int nwb, size_t lds) {
   if (lds <= 65536) return EPHW_OK;
   if (prec == 0)
-    EPHW_HIP(hipFuncSetAttribute((const void*)band_rotate_grouped_kernel<double>,
+    EPHW_HIP(hipFuncSetAttribute((const void*)band_grouped_kernel<double>(nwb),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   else
-    EPHW_HIP(hipFuncSetAttribute((const void*)band_rotate_grouped_kernel<float>,
+    EPHW_HIP(hipFuncSetAttribute((const void*)band_grouped_kernel<float>(nwb),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   return EPHW_OK;
 }
 
-ephw_status band_rotate_grouped(int prec, const BandRotateJob* d_jobs, int n, int64_t blocks, size_t lds,
+ephw_status band_rotate_grouped(int prec, int nwb, const BandRotateJob* d_jobs, int n, int64_t blocks, size_t lds,
                                 hipStream_t s) {
   if (n <= 0 || blocks <= 0) return EPHW_OK;
   if (prec == 0)
-    hipLaunchKernelGGL(band_rotate_grouped_kernel<double>, dim3((unsigned)blocks), dim3(kRotThreads), lds, s,
-                       d_jobs, n);
+    hipLaunchKernelGGL(band_grouped_kernel<double>(nwb), dim3((unsigned)blocks), dim3(kRotThreads), lds, s, d_jobs,
+                       n);
   else
-    hipLaunchKernelGGL(band_rotate_grouped_kernel<float>, dim3((unsigned)blocks), dim3(kRotThreads), lds, s,
-                       d_jobs, n);
+    hipLaunchKernelGGL(band_grouped_kernel<float>(nwb), dim3((unsigned)blocks), dim3(kRotThreads), lds, s, d_jobs,
+                       n);
   EPHW_CHECK_LAUNCH();
   return EPHW_OK;
 }
 
-__global__ void sum_into_grouped_kernel(const SumJob* __restrict__ jobs) {
-  __shared__ double red[256];
-  const SumJob& j = jobs[blockIdx.x];
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < j.n; i += 256) s += j.x[i];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0 && j.n > 0) j.out[0] += red[0];
+__global__ void __launch_bounds__(kSumThreads) sum_into_grouped_kernel(const SumJob* __restrict__ jobs) {
+  __shared__ double red[kSumThreads];
+  const SumJob j = jobs[blockIdx.x];
+  block_sum_into(j.x, j.n, j.out, red);
 }
 
 ephw_status sum_into_grouped(const SumJob* d_jobs, int n, hipStream_t s) {
   if (n <= 0) return EPHW_OK;
-  hipLaunchKernelGGL(sum_into_grouped_kernel, dim3((unsigned)n), dim3(256), 0, s, d_jobs);
+  hipLaunchKernelGGL(sum_into_grouped_kernel, dim3((unsigned)n), dim3(kSumThreads), 0, s, d_jobs);
   EPHW_CHECK_LAUNCH();
   return EPHW_OK;
 }
 
 ephw_status sum_into(const double* x, int64_t n, double* out, hipStream_t s) {
   if (n <= 0) return EPHW_OK;
-  hipLaunchKernelGGL(sum_into_kernel, dim3(1), dim3(256), 0, s, x, n, out);
+  hipLaunchKernelGGL(sum_into_kernel, dim3(1), dim3(kSumThreads), 0, s, x, n, out);
   EPHW_CHECK_LAUNCH();
   return EPHW_OK;
 }
