@@ -76,18 +76,20 @@ __global__ void kq_offsets_kernel(const int32_t* __restrict__ kq, int64_t nk, in
   if (b % nm == 0) offp[pair] = j * nw2;
 }
 
-// out[(r / inner) so + (r % inner) si] (+)= Re sum_c conj(a[r][c]) b[row(r)][c];
-// one block per row, fixed-order tree sum
+// out[(r / inner) so + (r % inner) si] (+)= Re sum_c conj(a[r][c]) b[row(r)][c].
+// Block (s, r) sums columns [s cc, (s+1) cc) of row r in a fixed-order tree;
+// with one chunk per row it writes the result, otherwise part[r * S + s].
 template <typename T>
 __global__ void row_dot_kernel(const T* __restrict__ a, int64_t lda, const T* __restrict__ b, int64_t ldb,
-                               const int64_t* __restrict__ boff, int64_t cols, double* __restrict__ out,
-                               int64_t inner, int64_t so, int64_t si, int accumulate) {
+                               const int64_t* __restrict__ boff, int64_t cols, int64_t cc, double* __restrict__ out,
+                               int64_t inner, int64_t so, int64_t si, int accumulate, double* __restrict__ part) {
   __shared__ double red[256];
-  const int64_t r = blockIdx.x;
+  const int64_t r = blockIdx.y, sidx = blockIdx.x, S = gridDim.x;
   const T* ar = a + 2 * r * lda;
   const T* br = b + 2 * (boff ? boff[r] : r * ldb);
+  const int64_t c0 = sidx * cc, c1 = (c0 + cc) < cols ? (c0 + cc) : cols;
   double s = 0.0;
-  for (int64_t c = threadIdx.x; c < cols; c += 256)
+  for (int64_t c = c0 + threadIdx.x; c < c1; c += 256)
     s += (double)ar[2 * c] * (double)br[2 * c] + (double)ar[2 * c + 1] * (double)br[2 * c + 1];
   red[threadIdx.x] = s;
   __syncthreads();
@@ -96,10 +98,27 @@ __global__ void row_dot_kernel(const T* __restrict__ a, int64_t lda, const T* __
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    double* o = out + (r / inner) * so + (r % inner) * si;
-    if (accumulate) *o += red[0];
-    else *o = red[0];
+    if (S > 1) {
+      part[r * S + sidx] = red[0];
+    } else {
+      double* o = out + (r / inner) * so + (r % inner) * si;
+      if (accumulate) *o += red[0];
+      else *o = red[0];
+    }
   }
+}
+
+// second stage: out (+)= sum over the S chunk partials of each row, in order
+__global__ void row_dot_finish_kernel(const double* __restrict__ part, int64_t rows, int64_t S,
+                                      double* __restrict__ out, int64_t inner, int64_t so, int64_t si,
+                                      int accumulate) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  double s = 0.0;
+  for (int64_t i = 0; i < S; ++i) s += part[r * S + i];
+  double* o = out + (r / inner) * so + (r % inner) * si;
+  if (accumulate) *o += s;
+  else *o = s;
 }
 
 // dk[k][d] += sum_q ps[q][k][d]  and  dq[q][d] += sum_k ps[q][k][d]
@@ -170,29 +189,64 @@ __global__ void frob_kernel(const T* __restrict__ W, int64_t nw2, double* __rest
 
 inline unsigned grid1(int64_t n, int bs) { return (unsigned)ceil_div(n, bs); }
 
+// chunks per row: enough blocks to fill the chip (about 2048) when rows are
+// few, each chunk at least 4096 columns; the partials need rows * S doubles
+// (at most kRowDotPart in all, see row_dot_chunks)
+constexpr int64_t kRowDotPart = 4096;
+int64_t row_dot_chunks(int64_t rows, int64_t cols) {
+  if (rows <= 0 || rows >= 2048) return 1;
+  int64_t S = std::min<int64_t>(ceil_div(cols, 4096), ceil_div(2048, rows));
+  S = std::max<int64_t>(1, std::min<int64_t>(S, kRowDotPart / rows));
+  return S;
+}
+
 template <typename T>
 ephw_status launch_row_dot(const void* a, int64_t lda, const void* b, int64_t ldb, const int64_t* boff, int64_t rows,
-                           int64_t cols, double* out, int64_t inner, int64_t so, int64_t si, bool acc,
+                           int64_t cols, double* out, int64_t inner, int64_t so, int64_t si, bool acc, double* part,
                            hipStream_t s) {
   if (rows <= 0) return EPHW_OK;
-  hipLaunchKernelGGL(row_dot_kernel<T>, dim3((unsigned)rows), dim3(256), 0, s, static_cast<const T*>(a), lda,
-                     static_cast<const T*>(b), ldb, boff, cols, out, inner, so, si, acc ? 1 : 0);
-  EPHW_CHECK_LAUNCH();
+  if (rows > 65535 * 1024ll) {
+    set_error("row_dot: too many rows");
+    return EPHW_EUNSUPPORTED;
+  }
+  const int64_t S = part ? row_dot_chunks(rows, cols) : 1;
+  const int64_t cc = ceil_div(cols, S);
+  // grid.y holds rows: split very tall launches at multiples of `inner`
+  const int64_t rstep = std::max<int64_t>(inner, (65535 / inner) * inner);
+  if (rstep > 65535) {
+    set_error("row_dot: output block too tall");
+    return EPHW_EUNSUPPORTED;
+  }
+  for (int64_t r0 = 0; r0 < rows; r0 += rstep) {
+    const int64_t nr = std::min<int64_t>(rstep, rows - r0);
+    const T* ab = static_cast<const T*>(a) + 2 * r0 * lda;
+    const T* bb = static_cast<const T*>(b) + (boff ? 0 : 2 * r0 * ldb);
+    const int64_t* bo = boff ? boff + r0 : nullptr;
+    double* ob = out + (r0 / inner) * so + (r0 % inner) * si;
+    hipLaunchKernelGGL(row_dot_kernel<T>, dim3((unsigned)S, (unsigned)nr), dim3(256), 0, s, ab, lda, bb, ldb, bo,
+                       cols, cc, ob, inner, so, si, acc ? 1 : 0, part);
+    EPHW_CHECK_LAUNCH();
+    if (S > 1) {
+      hipLaunchKernelGGL(row_dot_finish_kernel, dim3(grid1(nr, 256)), dim3(256), 0, s, part, nr, S, ob, inner, so,
+                         si, acc ? 1 : 0);
+      EPHW_CHECK_LAUNCH();
+    }
+  }
   return EPHW_OK;
 }
 
 // plain form: out[r * ostride]
 ephw_status row_dot(int kind, const void* a, int64_t lda, const void* b, int64_t ldb, const int64_t* boff,
-                    int64_t rows, int64_t cols, double* out, int64_t ostride, bool acc, hipStream_t s) {
-  return kind == 0 ? launch_row_dot<double>(a, lda, b, ldb, boff, rows, cols, out, 1, ostride, 0, acc, s)
-                   : launch_row_dot<float>(a, lda, b, ldb, boff, rows, cols, out, 1, ostride, 0, acc, s);
+                    int64_t rows, int64_t cols, double* out, int64_t ostride, bool acc, double* part, hipStream_t s) {
+  return kind == 0 ? launch_row_dot<double>(a, lda, b, ldb, boff, rows, cols, out, 1, ostride, 0, acc, part, s)
+                   : launch_row_dot<float>(a, lda, b, ldb, boff, rows, cols, out, 1, ostride, 0, acc, part, s);
 }
 
 ephw_status row_dot2(int kind, const void* a, int64_t lda, const void* b, int64_t ldb, const int64_t* boff,
                      int64_t rows, int64_t cols, double* out, int64_t inner, int64_t so, int64_t si, bool acc,
-                     hipStream_t s) {
-  return kind == 0 ? launch_row_dot<double>(a, lda, b, ldb, boff, rows, cols, out, inner, so, si, acc, s)
-                   : launch_row_dot<float>(a, lda, b, ldb, boff, rows, cols, out, inner, so, si, acc, s);
+                     double* part, hipStream_t s) {
+  return kind == 0 ? launch_row_dot<double>(a, lda, b, ldb, boff, rows, cols, out, inner, so, si, acc, part, s)
+                   : launch_row_dot<float>(a, lda, b, ldb, boff, rows, cols, out, inner, so, si, acc, part, s);
 }
 
 ephw_status fill_zero(int kind_or_f64, void* p, int64_t complex_count, hipStream_t s) {
@@ -715,6 +769,14 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
   EPHW_TRY(ws_need(s, WS_UBAR, (size_t)qb * nm * nm * cs));
   const int chunks_u = splitk_chunks(nw2, 16, 256);
   EPHW_TRY(ws_need(s, WS_SPLIT, (size_t)std::max<int64_t>(qb * chunks_u * nm * nm, 1) * cs));
+  // the per-pair Vbar GEMMs (Nw x Nw outputs, K = Nm Nw) split K until a unit
+  // has about 1024 tiles
+  const int64_t pair_out_tiles = cgemm_tiles(kind, nw, nw);
+  const int chunks_b = splitk_chunks(
+      nm * nw, (int)std::min<int64_t>(16, std::max<int64_t>(1, ceil_div(1024, kt * qb * pair_out_tiles))), 256);
+  if (chunks_b > 1) EPHW_TRY(ws_need(s, WS_SPLITB, (size_t)kt * qb * chunks_b * nw2 * cs));
+  EPHW_TRY(ws_need(s, WS_DOTPART, (size_t)kRowDotPart * 8));
+  double* dotpart = static_cast<double*>(wsp(s, WS_DOTPART));
   char* G = static_cast<char*>(wsp(s, WS_G));
   char* Gnu = static_cast<char*>(wsp(s, WS_GNU));
   char* Gbar = static_cast<char*>(wsp(s, WS_GBAR));
@@ -857,7 +919,7 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
       b3.C = Vkb_pair;
       b3.ldc = nw;
       b3.strideC = nw2;
-      EPHW_TRY(cgemm(kind, b3, st));
+      EPHW_TRY(cgemm_splitk(kind, b3, chunks_b, wsp(s, WS_SPLITB), st));
       GemmParams b4 = b3;
       b4.A = Tm;  // T' rows (nu, n) = K, columns m
       b4.transA = true;
@@ -865,7 +927,7 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
       b4.B = Yb;  // Ybar' rows (nu, n) = K, columns m''
       b4.conjB = true;
       b4.C = Vkqb_pair;
-      EPHW_TRY(cgemm(kind, b4, st));
+      EPHW_TRY(cgemm_splitk(kind, b4, chunks_b, wsp(s, WS_SPLITB), st));
       // Vbar(k) += sum over the unit's q of the pair parts (fixed order: iq ascending)
       {
         const int64_t total = kl * nw2;
@@ -883,7 +945,7 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
       // row r = il nb + iq of the pair buffers, offp[r] = grid index * nw2
       for (int d = 0; d < 3; ++d)
         EPHW_TRY(row_dot2(kind, Vkqb_pair, nw2, static_cast<const char*>(ks->dv) + (size_t)d * nk * nw2 * cs, 0, offp,
-                          kl * nb, nw2, pairs + (q0 * nk + k0) * 3 + d, nb, 3, nk * 3, false, st));
+                          kl * nb, nw2, pairs + (q0 * nk + k0) * 3 + d, nb, 3, nk * 3, false, dotpart, st));
       // Eq. (10) adjoint: Gnubar (+)= Pk^H Wbar
       GemmParams b6;
       b6.M = ne;
@@ -906,7 +968,7 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
         wd.A = static_cast<const char*>(ks->dpk) + ((size_t)d * nk + k0) * ne * cs;
         wd.C = Z;  // Z is free now: reuse as W'_d
         EPHW_TRY(cgemm(kind, wd, st));
-        EPHW_TRY(row_dot(kind, Wb, nb * E, Z, nb * E, nullptr, kl, nb * E, dk_acc + k0 * 3 + d, 3, true, st));
+        EPHW_TRY(row_dot(kind, Wb, nb * E, Z, nb * E, nullptr, kl, nb * E, dk_acc + k0 * 3 + d, 3, true, dotpart, st));
       }
     }
     // mode-vector adjoint: Gbar[q][e] = conj(u[q]) Gnubar[e][q]
@@ -953,7 +1015,7 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
     // q through u: dq_d += Re <ubar[q], du_d[q]>
     for (int d = 0; d < 3; ++d)
       EPHW_TRY(row_dot(kind, ubar, nm * nm, du + ((size_t)d * nq + q0) * nm * nm * cs, nm * nm, nullptr, nb, nm * nm,
-                       dq_acc + q0 * 3 + d, 3, true, st));
+                       dq_acc + q0 * 3 + d, 3, true, dotpart, st));
     // dL/dg += Pq^H Gbar
     if (dL_dg) {
       GemmParams dg;
@@ -978,13 +1040,13 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
       gd.A = dpq + ((size_t)d * nq + q0) * np * cs;
       gd.C = Gnu;  // free after the k loop
       EPHW_TRY(cgemm(kind, gd, st));
-      EPHW_TRY(row_dot(kind, Gbar, ne * E, Gnu, ne * E, nullptr, nb, ne * E, dq_acc + q0 * 3 + d, 3, true, st));
+      EPHW_TRY(row_dot(kind, Gbar, ne * E, Gnu, ne * E, nullptr, nb, ne * E, dq_acc + q0 * 3 + d, 3, true, dotpart, st));
     }
   }
   // k through V(k): dk_d += Re <Vbar(k), dV_d(k)>
   for (int d = 0; d < 3; ++d)
     EPHW_TRY(row_dot(kind, vkbar, nw2, static_cast<const char*>(ks->dv) + (size_t)d * nk * nw2 * cs, nw2, nullptr, nk,
-                     nw2, dk_acc + d, 3, true, st));
+                     nw2, dk_acc + d, 3, true, dotpart, st));
   // k and q through V(k+q): sum the pair scalars over q (for k) and over k (for q)
   hipLaunchKernelGGL(pair_sums_kernel, dim3(grid1((nk + nq) * 3, 256)), dim3(256), 0, st, pairs, nq, nk, dk_acc,
                      dq_acc);
