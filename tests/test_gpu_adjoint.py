@@ -48,7 +48,9 @@ def rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
-@pytest.mark.parametrize("nw,na,q_batch,k_tile", [(5, 2, 0, 0), (3, 1, 5, 7), (36, 1, 4, 5)])
+# (40, 6, 2, 3): the per-pair Vbar GEMMs (K = Nm Nw = 720) split K in two and
+# the k row dot products split each row over column chunks
+@pytest.mark.parametrize("nw,na,q_batch,k_tile", [(5, 2, 0, 0), (3, 1, 5, 7), (36, 1, 4, 5), (40, 6, 2, 3)])
 def test_fp64_backward_matches_oracle(run, nw, na, q_batch, k_tile):
     s, pts, kqi = grid_system(nw=nw, na=na, seed=nw)
     got, _ = gpu_backward(run, s, pts, kqi, 0, seed=21, q_batch=q_batch, k_tile=k_tile)

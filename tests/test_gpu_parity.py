@@ -273,3 +273,32 @@ def test_large_jacobi_matches_lapack(run, nw, na):
     lam, om, ev = run.phonons(sysh, k)
     ref_lam, _, _ = oracle.phonons(s, k)
     assert np.abs(lam - ref_lam).max() <= 1e-11 * np.abs(ref_lam).max()
+
+
+@pytest.mark.parametrize("prec,nw,na", [(0, 4, 1), (0, 5, 2), (1, 9, 3), (0, 16, 4), (1, 17, 5), (0, 20, 6),
+                                        (1, 20, 6), (0, 31, 8)])
+def test_band_rotation_work_splits(run, prec, nw, na):
+    """Every band-rotation kernel instance (Nw rounded up to 4) and work split:
+    several k per workgroup (small Nm Nw), one pair with all modes, one pair in
+    mode chunks with a ragged last chunk (Nm Nw > 256), and the 160 KB LDS
+    form (FP64, Nw = 31, Nm = 24); ĝ, band sums and loss against the oracle,
+    plus the Wannier-gauge output through the same kernel."""
+    from paper_2603_10295_amd import ephw
+    s = synth.make_system(nw, na, synth.box((2, 2, 1)), synth.box((2, 1, 1)), [nw, na, 3],
+                          g_dtype=np.complex64 if prec else np.complex128)
+    gen = np.random.default_rng(nw * 10 + na)
+    k, q = gen.random((5, 3)), gen.random((3, 3))
+    sysh = run.system(s)
+    out = run.interpolate(sysh, k, q, prec, loss_seed=21)
+    ref = oracle.interpolate(s, k, q, return_all=True)
+    tol = RTOL_S if prec == 0 else 1e-5
+    sg = oracle.block_sums(np.abs(out["g"].astype(np.complex128)) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+    sr = oracle.block_sums(np.abs(ref["ghat"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+    assert oracle.compare_block_sums(sg, sr)[0] < tol
+    assert rel_max(out["band_sum"], oracle.band_sums(ref["ghat"])) < tol
+    iq, ik = np.divmod(np.arange(len(q) * len(k)), len(k))
+    l_ref = oracle.weighted_loss(ref["ghat"].reshape(len(q) * len(k), *ref["ghat"].shape[2:]), 21, iq, ik, len(k))
+    assert abs(out["loss"] - l_ref) < tol * l_ref
+    if prec == 0:
+        w = run.interpolate(sysh, k, q, 0, flags=ephw.OUT_G | ephw.OUT_WANNIER)
+        assert rel_max(w["g"], ref["gw"]) < RTOL_W
