@@ -145,16 +145,18 @@ __device__ __forceinline__ double loss_weight(uint64_t seed, uint64_t index) {
 // whose Nm*Nw rows fill the 256 threads) or, for larger pairs, one pair in
 // chunks of nuc modes.  Per chunk:
 //   1. the chunk's X rows are copied, coalesced, into LDS (rows padded to
-//      Nw+1 complex values to spread the banks); for Nw <= 8 each thread
-//      reads its own row into registers instead;
+//      Nw+1 complex values to spread the banks); in FP64 with Nw <= 8 each
+//      thread reads its own row into registers instead;
 //   2. thread (pair p, mode v, row m') forms T[m'][:] = X[m'][:] V(k) from
 //      its own X row and V(k) (an LDS broadcast, every lane of the pair
 //      reads the same element) and writes it over its X row;
 //   3. after a barrier thread (p, v, m) forms g[m][:] = sum_m'
 //      conj(V(k+q)[m'][m]) T[m'][:] from the mode's T rows;
-//   4. epilogues: store g (one contiguous row per thread), row sums of |g|^2
-//      (band sums, summed per mode in a fixed order), weighted |g|^2 (loss,
-//      summed per pair in a fixed order).
+//   4. epilogues: g rows staged back in LDS and stored coalesced (the P
+//      pairs are consecutive k, so the workgroup writes one contiguous
+//      range; FP64 with Nw <= 8 stores its rows directly), row sums of
+//      |g|^2 (band sums, summed per mode in a fixed order), weighted |g|^2
+//      (loss, summed per pair in a fixed order).
 // NWB is Nw rounded up to a multiple of 4; the column loops are unrolled to
 // NWB with a uniform guard, so the accumulators stay in registers.
 constexpr int kRotThreads = 256;
@@ -183,7 +185,10 @@ __device__ __forceinline__ BandLds<T> band_lds(unsigned char* smem_raw, int P, i
 template <typename T, int NWB>
 __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, int nuc, int64_t kblk, int iq,
                                                unsigned char* smem_raw) {
-  constexpr bool DIRECT = NWB <= 8;   // X rows fit in registers
+  // FP64 with Nw <= 8: X rows go straight from HBM to registers and g rows
+  // straight back (measured faster there); otherwise both pass through LDS so
+  // that the HBM loads and stores are coalesced
+  constexpr bool DIRECT = sizeof(T) == 8 && NWB <= 8;
   const int nw = a.nw, nm = a.nm, nw2 = nw * nw, ld = nw + 1;
   const int64_t E = (int64_t)nm * nw2;
   const bool rot = a.Vk != nullptr;
@@ -302,7 +307,7 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
     if (act) {
       const int nu = v0 + vl;
       const int64_t eoff = (int64_t)nu * nw2 + (int64_t)mrow * nw;   // element offset in the pair
-      if (want_g) {
+      if (want_g && DIRECT) {
         T* go = static_cast<T*>(a.g_out) + 2 * (((int64_t)iq * a.nk + ik) * E + eoff);
 #pragma unroll
         for (int n = 0; n < NWB; ++n)
@@ -320,6 +325,28 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
           rsum += m2;
           if (want_l) lsum += loss_weight(a.loss_seed, base + (uint64_t)n) * m2;
         }
+    }
+    if (want_g && !DIRECT) {
+      // stage the g rows in LDS and store the chunk coalesced: the P pairs of
+      // the workgroup are consecutive k, so their values are contiguous
+      __syncthreads();   // every T row has been read
+      if (act) {
+#pragma unroll
+        for (int n = 0; n < NWB; ++n)
+          if (n < nw) {
+            own[2 * n] = acc[n].re;
+            own[2 * n + 1] = acc[n].im;
+          }
+      }
+      __syncthreads();
+      T* go = static_cast<T*>(a.g_out) + 2 * (((int64_t)iq * a.nk + a.k0 + ik0) * E + (int64_t)v0 * nw2);
+      for (int i = tid; i < npair * cw; i += kRotThreads) {
+        const int pp = i / cw, e = i % cw;
+        const T* src = L.rows + 2 * ((pp * rows_pp + e / nw) * ld + e % nw);
+        T* dst = go + 2 * ((int64_t)pp * E + e);
+        dst[0] = src[0];
+        dst[1] = src[1];
+      }
     }
     if (want_t) {
       L.red[tid] = rsum;
