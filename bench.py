@@ -51,6 +51,8 @@ def parse(argv=None):
     ap.add_argument("--cpu-sample-q", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-split", action="store_true", help="skip the FP32 split-phase (hi + lo) measurement")
+    ap.add_argument("--split-steps", type=int, default=1)
     ap.add_argument("--q-batch", type=int, default=0)
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="first run a plain device copy of this many GiB (HBM counter calibration)")
@@ -398,10 +400,29 @@ def main(argv=None):
         err32 = block_error(g32, ref)
         log(f"FP32 vs oracle: normwise {err32[0]:.2e}, max blockwise {err32[1]:.2e}")
 
+    # ---- FP32 with compensated (hi + lo) phase products ------------------
+    split = None
+    if not args.no_split:
+        del p32.out
+        ps = Path(ctx, s, ephw.FP32_SPLIT, k, q, kqi, args.q_chunk, args.q_batch)
+        log("FP32 split-phase path: warmup + timed steps")
+        tsp, stsp = timed(ps, args.split_steps, 1 if args.warmup else 0, profile=True)
+        split = {"value": cnt.elems / tsp, "ms_per_step": tsp * 1e3,
+                 "re_gemm_ms_per_step": round(stsp["re_gemm"][0] / args.split_steps, 3),
+                 "note": "the Re and Rp phase GEMMs also multiply the FP32 low part of every phase "
+                         "(twice the MFMA work of the plain FP32 path)"}
+        log(f"FP32 split: {tsp * 1e3:.1f} ms/step")
+        if cpu is not None:
+            e = block_error(ps.sample(qs_idx), ref)
+            split["err_vs_oracle"] = {"normwise": e[0], "max_blockwise": e[1]}
+        del ps.out
+        ps.sys.close()
+
     # ---- FP64 path on the same values (complex64 g upcast) ----------------
     fp64 = None
     if not args.no_fp64:
-        del p32.out
+        if hasattr(p32, "out"):
+            del p32.out
         s64 = type(s)(**{**s.__dict__, "g": s.g.astype(np.complex128)})
         p64 = Path(ctx, s64, ephw.FP64, k, q, kqi, args.q_chunk, args.q_batch)
         log("FP64 path: warmup + timed steps")
@@ -448,6 +469,9 @@ def main(argv=None):
                                                      "sample_q": len(qs_idx)},
         "fp64_gpu": fp64,
         "fp32_vs_fp64_speedup": None if fp64 is None else fp64["ms_per_step"] / (t32 * 1e3),
+        "fp32_split": split,
+        "fp32_split_vs_fp64_speedup": None if (fp64 is None or split is None)
+        else fp64["ms_per_step"] / split["ms_per_step"],
         "algorithmic_flops_per_step": 8.0 * cnt.total,
     }
     print(json.dumps(line), flush=True)
