@@ -4,9 +4,11 @@
 // Item i runs its units (q batch j, k tile t) in order, one unit per round;
 // a unit with t == 0 first needs the Eq. (9) GEMM and the mode rotation of
 // q batch j.  Every stage of a round is one launch over all items that take
-// part in it: the GEMM stages are persistent grouped GEMMs (a fixed grid of
-// one workgroup per CU strides over the tiles of every item, each item with
-// its own tile shape); the other stages are grouped block grids.
+// part in it: the GEMM stages are persistent grouped GEMMs (one launch per
+// tile configuration; a fixed grid of resident workgroups takes the tiles of
+// every item from per-XCD work queues, zeroed by a kernel at the start of the
+// pass); the other stages are grouped block grids, the band rotations one
+// launch per kernel instance and LDS size.
 #include <stdio.h>
 #include <string.h>
 

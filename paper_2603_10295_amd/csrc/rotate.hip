@@ -4,8 +4,10 @@
 // with): G_nu(Re,q) = sum_{kappa alpha} G_{kappa alpha}(Re,q) u_{kappa alpha, nu}(q).
 // Band rotation (per (k, q) pair, after the Re sum):
 //   g_nu(k,q) = V(k+q)^dagger gW_nu(k,q) V(k).
-// Both are bandwidth-bound at the sizes of the stock workloads: the kernels
-// stream their operands once, coalesced, with the small matrices in LDS.
+// The mode rotation streams its operands once, coalesced, with u(q) in LDS
+// (HBM-bound).  The band rotation (Nw <= 32) keeps V(k), V(k+q) and the
+// rows of a chunk in LDS; it is HBM-bound at Nw = 8 and VALU-bound from
+// Nw of about 16 up.  Larger bands use pair-stacked GEMMs instead.
 #include "kernels.h"
 
 namespace ephw {
