@@ -403,8 +403,11 @@ using namespace ephw;
 namespace {
 
 // (q batch, k tile) of the unit loops.  The four g(Re,q)-sized buffers get up
-// to 8 GB and the `nbuf` pair-sized buffers up to 24 GB of the 288 GB of HBM:
-// a large k tile matters because every k tile re-reads g(Re,q) in the Re GEMM.
+// to 8 GB and the `nbuf` pair-sized buffers up to 48 GB of the 288 GB of HBM.
+// The k tile is the M of the Re GEMM (for small Ne a short-K, store-bound
+// GEMM whose 128-row tiles want many k) and every k tile re-reads g(Re,q);
+// a larger q batch at the same pair budget would shorten the k tile, which
+// measured slower on the ribbon than the Eq. (9) GEMM it speeds up.
 void unit_shape(const ephw_system* s, int64_t nq, int64_t nk, int64_t E, size_t cs, int nbuf, int64_t* qb_out,
                 int64_t* kt_out) {
   int64_t qb = s->q_batch;
@@ -413,7 +416,7 @@ void unit_shape(const ephw_system* s, int64_t nq, int64_t nk, int64_t E, size_t 
     qb = std::max<int64_t>(1, std::min<int64_t>(qb, 8));
   }
   qb = std::min(qb, nq);
-  int64_t kt = (int64_t)(24.0e9 / ((double)nbuf * cs * qb * E));
+  int64_t kt = (int64_t)(48.0e9 / ((double)nbuf * cs * qb * E));
   if (kt < 1) kt = 1;
   if (kt >= 64) kt -= kt % 16;
   if (s->k_tile > 0) kt = s->k_tile;

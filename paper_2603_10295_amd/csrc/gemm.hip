@@ -661,6 +661,115 @@ ephw_status launch(const GemmParams& p0, hipStream_t stream) {
   return EPHW_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Few-row GEMM (M <= MB): C[M][N] (+)= op(A)[M][K] B[K][N] with B row-major
+// and N large, e.g. the Eq. (9) sum of a small q batch (B = g(Re,Rp)) or
+// dL/dg += Pq^H Gbar.  Such a product is a stream over B and C: each thread
+// owns two adjacent columns (FP32; one for FP64), op(A) is staged in LDS in
+// K chunks and read as a broadcast, and the M accumulators of each column
+// stay in registers.  A 128-row MFMA tile would spend most of its work on
+// padding rows here.
+constexpr int kSkinnyThreads = 256, kSkinnyKC = 128;
+
+template <typename T, int MB>
+__global__ void __launch_bounds__(kSkinnyThreads) cgemm_skinny_kernel(GemmParams p) {
+  constexpr int CPC = Chunk<T>::CPC;
+  using V4 = typename Chunk<T>::v4;
+  __shared__ T sa[2 * MB * kSkinnyKC];
+  const TileJob<T> j = job_of<T>(p, p.batch_base + blockIdx.y);
+  const int64_t n0 = ((int64_t)blockIdx.x * kSkinnyThreads + threadIdx.x) * CPC;
+  const bool col_ok = n0 < j.N;
+  const bool pair_ok = CPC == 1 || n0 + 1 < j.N;
+  cplx<T> acc[MB][CPC];
+#pragma unroll
+  for (int m = 0; m < MB; ++m)
+#pragma unroll
+    for (int c = 0; c < CPC; ++c) acc[m][c] = cplx<T>{0, 0};
+  for (int64_t k0 = 0; k0 < j.K; k0 += kSkinnyKC) {
+    const int kc = (int)((j.K - k0) < kSkinnyKC ? (j.K - k0) : kSkinnyKC);
+    __syncthreads();
+    for (int i = threadIdx.x; i < MB * kc; i += kSkinnyThreads) {
+      const int m = i / kc, kk = i % kc;
+      T re = 0, im = 0;
+      if (m < j.M) {
+        const int64_t off = p.transA ? (k0 + kk) * j.lda + m : (int64_t)m * j.lda + k0 + kk;
+        re = j.A[2 * off];
+        im = j.sa * j.A[2 * off + 1];
+      }
+      sa[2 * (kk * MB + m)] = re;
+      sa[2 * (kk * MB + m) + 1] = im;
+    }
+    __syncthreads();
+    if (col_ok) {
+      const T* brow = j.B + 2 * (k0 * j.ldb + n0);
+#pragma unroll 4
+      for (int kk = 0; kk < kc; ++kk) {
+        T bv[2 * CPC];
+        if (pair_ok) {
+          const V4 v = *reinterpret_cast<const V4*>(brow + 2 * (int64_t)kk * j.ldb);
+#pragma unroll
+          for (int e = 0; e < 2 * CPC; ++e) bv[e] = v[e];
+        } else {
+          bv[0] = brow[2 * (int64_t)kk * j.ldb];
+          bv[1] = brow[2 * (int64_t)kk * j.ldb + 1];
+#pragma unroll
+          for (int e = 2; e < 2 * CPC; ++e) bv[e] = 0;
+        }
+        const T* ar = sa + 2 * kk * MB;
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+          const cplx<T> a{ar[2 * m], ar[2 * m + 1]};
+#pragma unroll
+          for (int c = 0; c < CPC; ++c) cfma(acc[m][c], a, cplx<T>{bv[2 * c], bv[2 * c + 1]});
+        }
+      }
+    }
+  }
+  if (!col_ok) return;
+#pragma unroll
+  for (int m = 0; m < MB; ++m) {
+    if (m >= j.M) break;
+#pragma unroll
+    for (int c = 0; c < CPC; ++c) {
+      if (c == 1 && !pair_ok) break;
+      T* cp = j.C + 2 * ((int64_t)m * j.ldc + n0 + c);
+      cplx<T> v = acc[m][c];
+      if (j.accumulate) {
+        v.re += cp[0];
+        v.im += cp[1];
+      }
+      cp[0] = v.re;
+      cp[1] = v.im;
+    }
+  }
+}
+
+template <typename T, int MB>
+ephw_status launch_skinny(const GemmParams& p0, hipStream_t stream) {
+  constexpr int CPC = Chunk<T>::CPC;
+  const int64_t blocks = ceil_div(p0.N, (int64_t)kSkinnyThreads * CPC);
+  if (blocks > 0x7fffffff) {
+    set_error("cgemm: too many columns");
+    return EPHW_EUNSUPPORTED;
+  }
+  GemmParams p = p0;
+  for (int64_t b0 = 0; b0 < p0.batch; b0 += 65535) {
+    const int64_t nb = (p0.batch - b0) < 65535 ? (p0.batch - b0) : 65535;
+    p.batch_base = b0;
+    hipLaunchKernelGGL((cgemm_skinny_kernel<T, MB>), dim3((unsigned)blocks, (unsigned)nb), dim3(kSkinnyThreads), 0,
+                       stream, p);
+    EPHW_CHECK_LAUNCH();
+  }
+  return EPHW_OK;
+}
+
+template <typename T>
+ephw_status dispatch_skinny(const GemmParams& p, hipStream_t s) {
+  if (p.M <= 4) return launch_skinny<T, 4>(p, s);
+  if (p.M <= 8) return launch_skinny<T, 8>(p, s);
+  return launch_skinny<T, 16>(p, s);
+}
+
 template <typename T, int BM, int BN, int BK, int WM, int WN, bool SPLIT, int OCC>
 ephw_status dispatch_trans(const GemmParams& p, hipStream_t s) {
   if (!p.transA && !p.transB) return launch<T, BM, BN, BK, WM, WN, false, false, SPLIT, OCC>(p, s);
@@ -789,6 +898,12 @@ ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream) {
     return EPHW_EINVAL;
   }
   if (p.A_lo) return dispatch_trans<float, 128, 128, 16, 2, 2, true, 1>(p, stream);
+  // few rows, many columns, B read straight: a stream over B and C
+  // (FP32 reads two complex values per 16-byte load: rows must start on 16 bytes)
+  if (p.M <= 16 && p.N >= 16384 && !p.transB && !p.conjB && !p.loss.on && p.tblock == 0 &&
+      (prec == 0 || (p.ldb % 2 == 0 && p.strideB % 2 == 0 && p.strideB1 % 2 == 0 && p.strideB2 % 2 == 0 &&
+                     !p.offB && reinterpret_cast<uintptr_t>(p.B) % 16 == 0)))
+    return prec == 0 ? dispatch_skinny<double>(p, stream) : dispatch_skinny<float>(p, stream);
   int bm, bn;
   plain_shape(prec, p.M, p.N, &bm, &bn);
   // the 64x224 tile addresses a whole slab from one base; very long rows
