@@ -302,3 +302,16 @@ def test_band_rotation_work_splits(run, prec, nw, na):
     if prec == 0:
         w = run.interpolate(sysh, k, q, 0, flags=ephw.OUT_G | ephw.OUT_WANNIER)
         assert rel_max(w["g"], ref["gw"]) < RTOL_W
+
+
+@pytest.mark.parametrize("prec,nq", [(0, 1), (0, 5), (1, 9), (1, 16), (0, 17), (2, 3)])
+def test_phase_sum_rp_few_q(run, prec, nq):
+    """Eq. (9) for a handful of q: at most 16 rows run as the streaming
+    few-row GEMM (K = Np = 210 spans two LDS chunks of op(A)), 17 rows on
+    the MFMA tiles; both against the oracle."""
+    s = synth.make_system(4, 1, synth.box((20, 20, 1)), synth.box((7, 6, 5)), [nq, prec, 8],
+                          g_dtype=np.complex128 if prec == 0 else np.complex64)
+    q = np.random.default_rng(nq).random((nq, 3))
+    got = run.phase_sum_rp(run.system(s), q, prec)
+    err = rel_max(got, oracle.g_re_q(s, q))
+    assert err < (RTOL_W if prec == 0 else 2e-6), err
