@@ -3,6 +3,7 @@
     python -m paper_2603_10295_amd.rocprof_summary stats RESULTS.db [--command CMD]
     python -m paper_2603_10295_amd.rocprof_summary traffic FETCH.db WRITE.db \
         --copy-bytes BYTES [--command CMD]
+    python -m paper_2603_10295_amd.rocprof_summary util COUNTERS.db [--command CMD]
 
 `stats` groups kernel dispatches by (kernel, grid) - the phase GEMMs of
 Eqs. (9) and (10) share one kernel but differ in grid - and prints calls,
@@ -98,6 +99,46 @@ def traffic(fetch_db: str, write_db: str, copy_bytes: int, command: str = "") ->
     return "\n".join(out) + "\n"
 
 
+def utilisation(db: str, simds: int = 1024, xcds: int = 8, command: str = "") -> str:
+    """Per (kernel, grid): MFMA busy share and clock from SQ_VALU_MFMA_BUSY_CYCLES
+    (summed over SIMDs) and GRBM_GUI_ACTIVE (summed over XCDs), with the
+    kernel's duration; plus LDS bank-conflict and LDS-wait cycles relative to
+    the MFMA busy cycles when present."""
+    c = sqlite3.connect(db)
+    rows = c.execute("select dispatch_id, kernel_name, grid_size_x, grid_size_y, workgroup_size_x, counter_name, "
+                     "value, start, end from counters_collection").fetchall()
+    per = collections.defaultdict(dict)
+    meta = {}
+    for d, name, gx, gy, wx, cname, val, t0, t1 in rows:
+        per[d][cname] = per[d].get(cname, 0.0) + val
+        meta[d] = (short_name(name), gx // max(1, wx), gy, (t1 - t0) * 1e-9)
+    groups = collections.defaultdict(list)
+    for d, v in per.items():
+        groups[meta[d][:3]].append((v, meta[d][3]))
+    out = [f"# MFMA utilisation per dispatch from rocprofv3 counters: {os.path.basename(db)}",
+           f"# command: {command}" if command else "# command: (not recorded)",
+           f"# mfma_busy = SQ_VALU_MFMA_BUSY_CYCLES / {simds} SIMDs / (GRBM_GUI_ACTIVE / {xcds} XCDs); "
+           f"clock = (GRBM_GUI_ACTIVE / {xcds}) / duration",
+           f"{'disp':>5} {'mfma_busy':>9} {'clock_GHz':>9} {'lds_conf':>9} {'lds_wait':>9} {'mfma_insts':>11}  "
+           f"kernel [workgroups x grid_y]"]
+    def avg(xs):
+        return sum(xs) / len(xs) if xs else float("nan")
+    keys = sorted(groups, key=lambda k: -sum(v.get("SQ_VALU_MFMA_BUSY_CYCLES", 0) for v, _ in groups[k]))
+    for k in keys:
+        vs = groups[k]
+        busy = avg([v.get("SQ_VALU_MFMA_BUSY_CYCLES", float("nan")) for v, _ in vs])
+        gui = avg([v.get("GRBM_GUI_ACTIVE", float("nan")) for v, _ in vs])
+        dur = avg([t for _, t in vs])
+        conf = avg([v.get("SQ_LDS_BANK_CONFLICT", float("nan")) for v, _ in vs])
+        lw = avg([v.get("SQ_WAIT_INST_LDS", float("nan")) for v, _ in vs])
+        ins = avg([v.get("SQ_INSTS_MFMA", float("nan")) for v, _ in vs])
+        util = busy / simds / (gui / xcds) if gui else float("nan")
+        clk = (gui / xcds) / dur / 1e9 if dur else float("nan")
+        out.append(f"{len(vs):5d} {util:9.3f} {clk:9.3f} {conf / busy if busy else float('nan'):9.4f} "
+                   f"{lw / busy if busy else float('nan'):9.4f} {ins:11.4g}  {k[0]} [{k[1]} x {k[2]}]")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -109,9 +150,14 @@ def main(argv=None) -> int:
     t.add_argument("write_db")
     t.add_argument("--copy-bytes", type=int, required=True)
     t.add_argument("--command", default="")
+    u = sub.add_parser("util")
+    u.add_argument("db")
+    u.add_argument("--command", default="")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         sys.stdout.write(stats(a.db, a.command))
+    elif a.cmd == "util":
+        sys.stdout.write(utilisation(a.db, command=a.command))
     else:
         sys.stdout.write(traffic(a.fetch_db, a.write_db, a.copy_bytes, a.command))
     return 0

@@ -96,13 +96,26 @@ def test_batch_without_graph_equals_graph(run):
     works = small_batch(count=4, seed=9)
     items_a, keep_a = make_items(run, works, ephw.OUT_BAND_SUM)
     items_b, keep_b = make_items(run, works, ephw.OUT_BAND_SUM)
+    import torch
     a = ephw.Batch(run.ctx, items_a, use_graph=True)
     b = ephw.Batch(run.ctx, items_b, use_graph=False)
-    a.run()
     b.run()
     run.ctx.check()
-    for x, y in zip(items_a, items_b):
-        assert np.array_equal(x["band_sum"].cpu().numpy(), y["band_sum"].cpu().numpy())
+    eager = [y["band_sum"].cpu().numpy() for y in items_b]
+    # several graph replays, with eager device work and synchronisation in
+    # between; every replay must equal the eager pass (the work-queue
+    # counters are re-zeroed by a kernel node on each replay)
+    for rep in range(3):
+        for x in items_a:
+            x["band_sum"].fill_(-1.0)
+        torch.cuda.synchronize()
+        a.run()
+        run.ctx.check()
+        scratch = torch.randn(1 << 20, device="cuda:0").sum()
+        torch.cuda.synchronize()
+        assert torch.isfinite(scratch)
+        for x, e in zip(items_a, eager):
+            assert np.array_equal(x["band_sum"].cpu().numpy(), e), rep
     a.close()
     b.close()
 
