@@ -224,6 +224,8 @@ def bench_batch(args):
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / args.steps
     ctx.check()
+    stats, shapes = b.stats(), [b.shape(i) for i in range(len(items))]
+    b.close()   # release the batch's sweep buffers before the one-at-a-time runs allocate theirs
     # the same items, one system at a time (no grouping, no graph)
     def one_by_one():
         for it in items:
@@ -243,11 +245,11 @@ def bench_batch(args):
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": tb * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
         "config": {"workload": f"batch{len(names)}_capped2GiB_maxgrid{args.batch_max_grid}", "systems": len(names),
-                   "output": "weighted |g|^2 loss per system", **b.stats()},
+                   "output": "weighted |g|^2 loss per system", **stats},
         "one_system_at_a_time_ms": ts * 1e3, "batch_speedup": ts / tb,
         "phase_gemm_tflops_lower_bound": gemm_tf,
         "algorithmic_flops_per_step": 8.0 * cnt_tot.total,
-        "shapes": [dict(system=names[i], **b.shape(i)) for i in range(len(items))],
+        "shapes": [dict(system=names[i], **shapes[i]) for i in range(len(items))],
     }
     print(json.dumps(line), flush=True)
     return 0
