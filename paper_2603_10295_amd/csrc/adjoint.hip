@@ -58,22 +58,20 @@ __global__ void eig_mid_kernel(double* __restrict__ M, const double* __restrict_
   }
 }
 
-// offsets of V(k+q) for the rotation GEMMs of one unit:
-//   per (il, iq, nu):  off[(il qb + iq) nm + nu] = kq_index[(q0+iq) nk + k0+il] * nw2
-//   per pair:          offp[il qb + iq]          = the same index * nw2
+// Complex offset of V(k+q) for each (k, q) pair of a unit:
+//   offp[il qb + iq] = kq_index[(q0+iq) nk + k0+il] * nw2
+// (an out-of-range index sets the status bit and reads V(k_0)).
 __global__ void kq_offsets_kernel(const int32_t* __restrict__ kq, int64_t nk, int64_t q0, int64_t k0, int kl, int qb,
-                                  int nm, int64_t nw2, int64_t* __restrict__ off, int64_t* __restrict__ offp,
-                                  uint32_t* status) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= (int64_t)kl * qb * nm) return;
-  const int64_t pair = b / nm, il = pair / qb, iq = pair % qb;
+                                  int64_t nw2, int64_t* __restrict__ offp, uint32_t* status) {
+  const int64_t pair = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (pair >= (int64_t)kl * qb) return;
+  const int64_t il = pair / qb, iq = pair % qb;
   int64_t j = kq[(q0 + iq) * nk + k0 + il];
   if (j < 0 || j >= nk) {
-    if (b % nm == 0) atomicOr(status, kStatusIndex);
+    atomicOr(status, kStatusIndex);
     j = 0;
   }
-  off[b] = j * nw2;
-  if (b % nm == 0) offp[pair] = j * nw2;
+  offp[pair] = j * nw2;
 }
 
 // out[(r / inner) so + (r % inner) si] (+)= Re sum_c conj(a[r][c]) b[row(r)][c].
@@ -506,7 +504,7 @@ ephw_status interpolate_large(ephw_kset* ks, const double* q, int64_t nq, const 
     EPHW_TRY(ws_need(s, WS_GNU, gsz));
     EPHW_TRY(ws_need(s, WS_W, wsz));
     EPHW_TRY(ws_need(s, WS_T, wsz));
-    EPHW_TRY(ws_need(s, WS_OFF, (size_t)(kt * qb * nm + kt * qb) * 8));
+    EPHW_TRY(ws_need(s, WS_OFF, (size_t)kt * qb * 8));
     EPHW_TRY(ws_need(s, WS_LOSS, (size_t)kt * qb * rot_tiles * 8));
   }
   char* pq = static_cast<char*>(wsp(s, WS_PQ));
@@ -522,8 +520,7 @@ ephw_status interpolate_large(ephw_kset* ks, const double* q, int64_t nq, const 
     char* Gnu = static_cast<char*>(wsp(s, WS_GNU));
     char* W = static_cast<char*>(wsp(s, WS_W));
     char* Tm = static_cast<char*>(wsp(s, WS_T));
-    int64_t* off = static_cast<int64_t*>(wsp(s, WS_OFF));
-    int64_t* offp = off + kt * qb * nm;
+    int64_t* offp = static_cast<int64_t*>(wsp(s, WS_OFF));
     double* lossp = static_cast<double*>(wsp(s, WS_LOSS));
     GemmParams rp;
     rp.M = nb;
@@ -593,8 +590,8 @@ ephw_status interpolate_large(ephw_kset* ks, const double* q, int64_t nq, const 
         EPHW_CHECK_LAUNCH();
       }
       if (!rot) continue;
-      hipLaunchKernelGGL(kq_offsets_kernel, dim3(grid1(nbat, 256)), dim3(256), 0, st, kq_index, nk, q0, k0, (int)kl,
-                         (int)nb, (int)nm, nw2, off, offp, s->ctx->status);
+      hipLaunchKernelGGL(kq_offsets_kernel, dim3(grid1(kl * nb, 256)), dim3(256), 0, st, kq_index, nk, q0, k0, (int)kl,
+                         (int)nb, nw2, offp, s->ctx->status);
       EPHW_CHECK_LAUNCH();
       Stage sgr_(s, EPHW_STAGE_BAND_ROT, st);
       // T'_nu = (W_nu V(k))^T: rows (nu, m) of W, each nw-row block stored transposed
@@ -766,7 +763,7 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
   EPHW_TRY(ws_need(s, WS_Z, wsz));
   EPHW_TRY(ws_need(s, WS_WBAR, wsz));
   EPHW_TRY(ws_need(s, WS_PAIRBAR, (size_t)kt * qb * nw2 * cs * 2));
-  EPHW_TRY(ws_need(s, WS_OFF, (size_t)(kt * qb * nm + kt * qb) * 8));
+  EPHW_TRY(ws_need(s, WS_OFF, (size_t)kt * qb * 8));
   const int64_t rot_tiles = cgemm_tiles(kind, nm * nw, nw);  // per pair
   EPHW_TRY(ws_need(s, WS_LOSS, (size_t)kt * qb * rot_tiles * 8));
   EPHW_TRY(ws_need(s, WS_UBAR, (size_t)qb * nm * nm * cs));
@@ -791,8 +788,7 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
   char* Wb = static_cast<char*>(wsp(s, WS_WBAR));
   char* Vkb_pair = static_cast<char*>(wsp(s, WS_PAIRBAR));
   char* Vkqb_pair = Vkb_pair + (size_t)kt * qb * nw2 * cs;
-  int64_t* off = static_cast<int64_t*>(wsp(s, WS_OFF));
-  int64_t* offp = off + kt * qb * nm;
+  int64_t* offp = static_cast<int64_t*>(wsp(s, WS_OFF));
   double* lossp = static_cast<double*>(wsp(s, WS_LOSS));
   char* ubar = static_cast<char*>(wsp(s, WS_UBAR));
   char* pq = static_cast<char*>(wsp(s, WS_PQ));
@@ -852,8 +848,8 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
       re.C = W;
       re.ldc = re.N;
       EPHW_TRY(cgemm(kind, re, st));
-      hipLaunchKernelGGL(kq_offsets_kernel, dim3(grid1(nbat, 256)), dim3(256), 0, st, kq_index, nk, q0, k0, (int)kl,
-                         (int)nb, (int)nm, nw2, off, offp, s->ctx->status);
+      hipLaunchKernelGGL(kq_offsets_kernel, dim3(grid1(kl * nb, 256)), dim3(256), 0, st, kq_index, nk, q0, k0, (int)kl,
+                         (int)nb, nw2, offp, s->ctx->status);
       EPHW_CHECK_LAUNCH();
       // T'_nu = (W_nu V(k))^T, block-transposed store: [pair][nu][n][m']
       GemmParams f4 = pair_params(nw, nm, nb, kl, E);
