@@ -48,7 +48,7 @@ def parse(argv=None):
     ap.add_argument("--grid", type=int, default=20, help="k = q = grid^3 for si_dense")
     ap.add_argument("--q-chunk", type=int, default=1024)
     ap.add_argument("--fp64-steps", type=int, default=1)
-    ap.add_argument("--cpu-sample-q", type=int, default=4)
+    ap.add_argument("--cpu-sample-q", type=int, default=12, help="q points of the oracle sample (about 15 s of host work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-split", action="store_true", help="skip the FP32 split-phase (hi + lo) measurement")
