@@ -58,6 +58,7 @@ struct Launch {
   int n = 0;
   int64_t count = 0;           // total tiles (GEMM) or blocks
   size_t lds = 0;
+  int order = 0;               // EIGH: largest matrix order among the jobs
   // PHASE / MODEVEC: direct arguments
   int item = -1;
 };
@@ -329,7 +330,7 @@ ephw_status issue(ephw_batch* bt, hipStream_t st) {
                                (int)std::min<int64_t>(l.grid, l.count), bt->queues + l.qidx * kGroupQueues, st));
         break;
       case Launch::EIGH:
-        EPHW_TRY(jacobi_eigh_grouped(static_cast<const EighJob*>(l.jobs), l.n, l.count, status, st));
+        EPHW_TRY(jacobi_eigh_grouped(static_cast<const EighJob*>(l.jobs), l.n, l.count, l.order, status, st));
         break;
       case Launch::MODE:
         EPHW_TRY(mode_rotate_grouped(bt->kind, static_cast<const ModeRotateJob*>(l.jobs), l.n, l.count, l.lds, st));
@@ -402,7 +403,9 @@ void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, 
   {
     std::vector<EighJob> jobs;
     int64_t base = 0;
+    int order = 0;
     for (auto& it : bt->items) {
+      order = std::max(order, it.nm);
       EighJob j;
       j.H = it.dq;
       j.eps = it.lam;
@@ -417,6 +420,7 @@ void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, 
     l.kind = Launch::EIGH;
     l.n = (int)jobs.size();
     l.count = base;
+    l.order = order;
     push(l, hd.add(jobs));
   }
   for (size_t i = 0; i < bt->items.size(); ++i) {

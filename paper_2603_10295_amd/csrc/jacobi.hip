@@ -10,7 +10,9 @@
 // plane once; sweeps repeat until the off-diagonal Frobenius norm is below
 // 1e-14 of the total norm.
 //
-// Small matrices (n <= 32) live in LDS, one 64-lane wavefront per matrix.
+// Small matrices (n <= 32) live in LDS, one 64-lane wavefront per matrix, with
+// the LDS sized to the order (about 4.4 KB at n = 11) so that the CU holds as
+// many solves as its registers allow: the solve is latency-bound.
 // Large matrices (n > 32) live in a global workspace, one 256-thread
 // workgroup per matrix (the rotation parameters stay in LDS).
 #include "kernels.h"
@@ -181,22 +183,43 @@ __device__ void jacobi_finish(const double* Ar, const double* Vr, const double* 
 
 constexpr int kSmallN = 32;
 
+// LDS of one small solve, sized to its order so that many solves share a CU:
+// A and V (re/im planes), the rotation parameters of one round, the sort
+// permutation and the phase fix of each column, one reduction slot.
+__host__ __device__ constexpr size_t small_lds_doubles(int n) {
+  return 4 * (size_t)n * n + 4 * (size_t)((n + 1) / 2) + 2 * (size_t)n + 1;
+}
+__host__ __device__ constexpr size_t small_lds_bytes(int n) {
+  return small_lds_doubles(n) * 8 + (2 * (size_t)((n + 1) / 2) + (size_t)n) * 4;
+}
+
 __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, int n, double* __restrict__ eps,
                                                   double* __restrict__ V, uint32_t* status, int64_t b) {
-  __shared__ double Ar[kSmallN * kSmallN], Ai[kSmallN * kSmallN];
-  __shared__ double Vr[kSmallN * kSmallN], Vi[kSmallN * kSmallN];
-  __shared__ double rc[kSmallN / 2], rs[kSmallN / 2], rer[kSmallN / 2], rei[kSmallN / 2];
-  __shared__ int rp[kSmallN / 2], rq[kSmallN / 2], perm[kSmallN];
-  __shared__ double phr[kSmallN], phi[kSmallN], red[1];
-  const double* h = H + 2 * b * n * n;
-  for (int e = threadIdx.x; e < n * n; e += 64) {
+  extern __shared__ double lds[];
+  const int nn = n * n, np = (n + 1) / 2;
+  double* Ar = lds;
+  double* Ai = Ar + nn;
+  double* Vr = Ai + nn;
+  double* Vi = Vr + nn;
+  double* rc = Vi + nn;
+  double* rs = rc + np;
+  double* rer = rs + np;
+  double* rei = rer + np;
+  double* phr = rei + np;
+  double* phi = phr + n;
+  double* red = phi + n;
+  int* rp = reinterpret_cast<int*>(lds + small_lds_doubles(n));
+  int* rq = rp + np;
+  int* perm = rq + np;
+  const double* h = H + 2 * b * nn;
+  for (int e = threadIdx.x; e < nn; e += 64) {
     Ar[e] = h[2 * e];
     Ai[e] = h[2 * e + 1];
   }
   __syncthreads();
   const bool ok = jacobi_core<64>(Ar, Ai, Vr, Vi, n, rc, rs, rer, rei, rp, rq, red);
   if (!ok && threadIdx.x == 0) atomicOr(status, kStatusNoConv);
-  jacobi_finish<64>(Ar, Vr, Vi, n, perm, phr, phi, eps + b * n, V + 2 * b * n * n);
+  jacobi_finish<64>(Ar, Vr, Vi, n, perm, phr, phi, eps + b * n, V + 2 * b * nn);
 }
 
 __global__ void __launch_bounds__(64)
@@ -205,6 +228,7 @@ __global__ void __launch_bounds__(64)
   jacobi_small_body(H, n, eps, V, status, blockIdx.x);
 }
 
+// dynamic LDS sized for the largest order among the jobs
 __global__ void __launch_bounds__(64) jacobi_grouped_kernel(const EighJob* __restrict__ jobs, int njobs,
                                                              uint32_t* status) {
   const int64_t b = blockIdx.x;
@@ -249,10 +273,15 @@ int64_t jacobi_work_doubles(int n, int64_t batch) {
   return 4 * (int64_t)n * n * chunk;
 }
 
-ephw_status jacobi_eigh_grouped(const EighJob* d_jobs, int njobs, int64_t blocks, uint32_t* status,
+ephw_status jacobi_eigh_grouped(const EighJob* d_jobs, int njobs, int64_t blocks, int max_n, uint32_t* status,
                                 hipStream_t s) {
   if (njobs <= 0 || blocks <= 0) return EPHW_OK;
-  hipLaunchKernelGGL(jacobi_grouped_kernel, dim3((unsigned)blocks), dim3(64), 0, s, d_jobs, njobs, status);
+  if (max_n < 1 || max_n > kSmallN) {
+    set_error("jacobi_eigh_grouped: matrix orders must be in [1, 32]");
+    return EPHW_EUNSUPPORTED;
+  }
+  hipLaunchKernelGGL(jacobi_grouped_kernel, dim3((unsigned)blocks), dim3(64), small_lds_bytes(max_n), s, d_jobs,
+                     njobs, status);
   EPHW_CHECK_LAUNCH();
   return EPHW_OK;
 }
@@ -267,7 +296,7 @@ ephw_status jacobi_eigh(const double* H, int64_t batch, int n, double* eps, doub
   if (n <= kSmallN) {
     for (int64_t b0 = 0; b0 < batch; b0 += 0x7fffffff) {
       const int64_t nb = (batch - b0) < 0x7fffffff ? (batch - b0) : 0x7fffffff;
-      hipLaunchKernelGGL(jacobi_small_kernel, dim3((unsigned)nb), dim3(64), 0, s,
+      hipLaunchKernelGGL(jacobi_small_kernel, dim3((unsigned)nb), dim3(64), small_lds_bytes(n), s,
                          H + 2 * b0 * n * n, n, eps + b0 * n, V + 2 * b0 * n * n, status);
       EPHW_CHECK_LAUNCH();
     }

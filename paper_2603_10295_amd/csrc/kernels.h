@@ -28,7 +28,7 @@ struct EighJob {
   int n;
   int64_t count, block_base;
 };
-ephw_status jacobi_eigh_grouped(const EighJob* d_jobs, int njobs, int64_t blocks, uint32_t* status,
+ephw_status jacobi_eigh_grouped(const EighJob* d_jobs, int njobs, int64_t blocks, int max_n, uint32_t* status,
                                 hipStream_t s);
 
 // dst[i] = (T) src[i] for n complex values; T = float (prec 1) or a plain copy (prec 0)

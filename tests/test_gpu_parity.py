@@ -249,10 +249,11 @@ def test_interpolate_fp32_gauge_invariant(run, toy32, toy32_ref, prec):
     np.testing.assert_allclose(out["eps_k"], r["eps_k"], atol=1e-12 * np.abs(r["eps_k"]).max())
 
 
-@pytest.mark.parametrize("nw,na", [(64, 1), (200, 50)])
-def test_large_jacobi_matches_lapack(run, nw, na):
-    """n > 32 eigensolves (global-memory Jacobi): the ribbon's H(k) (n = 200)
-    and D(q) (n = 150) orders."""
+@pytest.mark.parametrize("nw,na", [(1, 1), (11, 3), (32, 10), (64, 1), (200, 50)])
+def test_jacobi_matches_lapack(run, nw, na):
+    """Eigensolves of both Jacobi forms: LDS-resident, one wavefront each, with
+    the LDS sized to the order (n <= 32: 1, 3, 9, 11, 30, 32), and global-memory
+    (n > 32: 64 and the ribbon's H(k) at 200 and D(q) at 150)."""
     r = synth.axis_box(-2, 2, axis=1)
     h_r = synth.hermitian_paired(r, nw, synth.rng([nw, 77], synth.STREAM_H), complex_=True)
     c_r = synth.hermitian_paired(r, 3 * na, synth.rng([nw, 77], synth.STREAM_C), complex_=False)
