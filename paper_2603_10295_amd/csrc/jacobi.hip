@@ -11,9 +11,9 @@
 // 1e-14 of the total norm.
 //
 // Small matrices (n <= 32) live in LDS, one 64-lane wavefront per matrix, with
-// the LDS sized to the order (about 4.4 KB at n = 11) so that the CU holds as
-// many solves as its registers allow: the solve is latency-bound.
-// Large matrices (n > 32) live in a global workspace, one 256-thread
+// the LDS sized to the order (8 KB at n = 11) so that a CU holds as many
+// solves as its registers allow; each lane owns one 2x2 block of the round
+// (below).  Large matrices (n > 32) live in a global workspace, one 256-thread
 // workgroup per matrix (the rotation parameters stay in LDS).
 #include "kernels.h"
 
@@ -182,64 +182,313 @@ __device__ void jacobi_finish(const double* Ar, const double* Vr, const double* 
 }
 
 constexpr int kSmallN = 32;
+constexpr int kSmallPerBlock = 4;  // small solves (wavefronts) per workgroup
 
-// LDS of one small solve, sized to its order so that many solves share a CU:
-// A and V (re/im planes), the rotation parameters of one round, the sort
-// permutation and the phase fix of each column, one reduction slot.
-__host__ __device__ constexpr size_t small_lds_doubles(int n) {
-  return 4 * (size_t)n * n + 4 * (size_t)((n + 1) / 2) + 2 * (size_t)n + 1;
-}
-__host__ __device__ constexpr size_t small_lds_bytes(int n) {
-  return small_lds_doubles(n) * 8 + (2 * (size_t)((n + 1) / 2) + (size_t)n) * 4;
+// ---------------------------------------------------------------------------
+// Small solves (n <= 32): one 64-lane wavefront per matrix, A and V in LDS as
+// interleaved complex with the order padded to N2 = 2 NP (a zero row and
+// column for odd n, whose pair is then the identity).  In each round of the
+// tournament the NP disjoint planes cut A and V into NP^2 2x2 blocks, rows
+// {p_i, q_i} x columns {p_j, q_j}.  J_i^H A J_j and V J_j touch only block
+// (i, j), so one lane updates a block with no other lane's data.  A stays
+// exactly Hermitian: only its upper triangle is kept (an entry below the
+// diagonal is read as the conjugate of its transpose) and only blocks with
+// i <= j are computed.  The
+// NP (NP + 1) / 2 blocks of A and the NP^2 of V are one list of tasks of the
+// same shape (V's left rotation is the identity), 57 of them at n = 11, so
+// the round is a single pass over the wave.  The sweep's last round sums
+// |A|^2 (total and off-diagonal) over the blocks it wrote, so the stopping
+// test costs one wave reduction per sweep.
+//
+// Rotation parameters without divisions, for x = d - a, y = 2|b|:
+//   r = sqrt(x^2 + y^2), w = |x| + r, z = 1/sqrt(w^2 + y^2),
+//   c = w z, s = sign(x) y z, sigma = s b/|b|,
+// which are the t = sign(tau)/(|tau| + sqrt(1 + tau^2)) formulas above with
+// the common factors cleared; J = [[c, sigma], [-conj(sigma), c]].
+// ---------------------------------------------------------------------------
+template <int NP>
+struct SmallLayout {
+  static constexpr int N2 = 2 * NP;
+  static constexpr int NA = NP * (NP + 1) / 2;                   // blocks of A (i <= j)
+  static constexpr int NT = NA + NP * NP;                         // tasks: A blocks, then V blocks
+  static constexpr int TPL = (NT + 63) / 64;                      // tasks per lane
+  static constexpr size_t a_elems = (size_t)N2 * N2;            // complex
+  static constexpr size_t prm_elems = 2 * (size_t)NP;            // (c, 0), sigma per pair
+  static constexpr size_t fix_elems = (size_t)N2;                // phase fix per column
+  static constexpr size_t bytes = (2 * a_elems + prm_elems + fix_elems) * 16 + (size_t)N2 * 4;
+  static constexpr size_t slice_elems = (bytes + 15) / 16;       // one wavefront's share, 16-byte units
+};
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
 }
 
+// x' = c x - conj(sg) y ; y' = sg x + c y   (one row of [x y] J)
+__device__ __forceinline__ void rot_right(double2& x, double2& y, double c, double2 sg) {
+  const double2 nx = make_double2(fma(c, x.x, -fma(sg.x, y.x, sg.y * y.y)), fma(c, x.y, -fma(sg.x, y.y, -sg.y * y.x)));
+  const double2 ny = make_double2(fma(c, y.x, fma(sg.x, x.x, -sg.y * x.y)), fma(c, y.y, fma(sg.x, x.y, sg.y * x.x)));
+  x = nx;
+  y = ny;
+}
+
+// x' = c x - sg y ; y' = conj(sg) x + c y   (one column of J^H [x; y])
+__device__ __forceinline__ void rot_left(double2& x, double2& y, double c, double2 sg) {
+  const double2 nx = make_double2(fma(c, x.x, -fma(sg.x, y.x, -sg.y * y.y)), fma(c, x.y, -fma(sg.x, y.y, sg.y * y.x)));
+  const double2 ny = make_double2(fma(c, y.x, fma(sg.x, x.x, sg.y * x.y)), fma(c, y.y, fma(sg.x, x.y, -sg.y * x.x)));
+  x = nx;
+  y = ny;
+}
+
+__device__ __forceinline__ double norm2(double2 v) { return v.x * v.x + v.y * v.y; }
+
+__device__ __forceinline__ double2 ld_entry(const double2* X, int ld, int r, int c, bool tri) {
+  const bool sw = tri && r > c;
+  const double2 v = X[sw ? c * ld + r : r * ld + c];
+  return sw ? make_double2(v.x, -v.y) : v;
+}
+
+__device__ __forceinline__ void st_entry(double2* X, int ld, int r, int c, bool tri, double2 v) {
+  const bool sw = tri && r > c;
+  X[sw ? c * ld + r : r * ld + c] = sw ? make_double2(v.x, -v.y) : v;
+}
+
+// the solve of a matrix is one wavefront's: its LDS traffic needs only the
+// wave's own LDS operations complete, never a workgroup barrier
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+template <int NP>
 __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, int n, double* __restrict__ eps,
-                                                  double* __restrict__ V, uint32_t* status, int64_t b) {
-  extern __shared__ double lds[];
-  const int nn = n * n, np = (n + 1) / 2;
-  double* Ar = lds;
-  double* Ai = Ar + nn;
-  double* Vr = Ai + nn;
-  double* Vi = Vr + nn;
-  double* rc = Vi + nn;
-  double* rs = rc + np;
-  double* rer = rs + np;
-  double* rei = rer + np;
-  double* phr = rei + np;
-  double* phi = phr + n;
-  double* red = phi + n;
-  int* rp = reinterpret_cast<int*>(lds + small_lds_doubles(n));
-  int* rq = rp + np;
-  int* perm = rq + np;
-  const double* h = H + 2 * b * nn;
-  for (int e = threadIdx.x; e < nn; e += 64) {
-    Ar[e] = h[2 * e];
-    Ai[e] = h[2 * e + 1];
+                                                  double* __restrict__ Vout, uint32_t* status, int64_t b,
+                                                  double2* slice, int lane) {
+  using L = SmallLayout<NP>;
+  constexpr int N2 = L::N2;
+  double2* A = slice;
+  double2* V = A + L::a_elems;
+  double2* prm = V + L::a_elems;
+  double2* fix = prm + L::prm_elems;
+  int* perm = reinterpret_cast<int*>(fix + L::fix_elems);
+  const double2* h = reinterpret_cast<const double2*>(H) + b * n * n;
+  const double2 zero = make_double2(0.0, 0.0);
+
+  // this lane's tasks, packed as (is_v << 16) | (i << 8) | j; the list does not change between rounds
+  int task[L::TPL];
+#pragma unroll
+  for (int k = 0; k < L::TPL; ++k) {
+    const int t = lane + 64 * k;
+    int code = -1;
+    if (t < L::NA) {
+      int i = 0, rest = t;
+      while (rest >= NP - i) {
+        rest -= NP - i;
+        ++i;
+      }
+      code = (i << 8) | (i + rest);
+    } else if (t < L::NT) {
+      const int v = t - L::NA;
+      code = (1 << 16) | ((v / NP) << 8) | (v % NP);
+    }
+    task[k] = code;
   }
-  __syncthreads();
-  const bool ok = jacobi_core<64>(Ar, Ai, Vr, Vi, n, rc, rs, rer, rei, rp, rq, red);
-  if (!ok && threadIdx.x == 0) atomicOr(status, kStatusNoConv);
-  jacobi_finish<64>(Ar, Vr, Vi, n, perm, phr, phi, eps + b * n, V + 2 * b * nn);
+
+  double off = 0.0, tot = 0.0;
+  for (int e = lane; e < N2 * N2; e += 64) {
+    const int r = e / N2, c = e % N2;
+    const double2 v = (r < n && c < n) ? h[r * n + c] : zero;
+    A[e] = v;
+    V[e] = (r == c && r < n) ? make_double2(1.0, 0.0) : zero;
+    const double m = norm2(v);
+    tot += m;
+    off += r != c ? m : 0.0;
+  }
+  off = wave_sum(off);
+  tot = wave_sum(tot);
+  wave_sync();
+  bool converged = n <= 1 || off <= kOffTol2 * tot;
+  off = 0.0;
+  tot = 0.0;
+  for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
+#pragma unroll 1
+    for (int round = 0; round < N2 - 1; ++round) {
+      if (lane < NP) {
+        const int u = player_at(lane, round, N2), v = player_at(N2 - 1 - lane, round, N2);
+        const int p = u < v ? u : v, q = u < v ? v : u;
+        double c = 1.0;
+        double2 sg = zero;
+        if (q < n) {
+          const double2 bpq = A[p * N2 + q];
+          const double bm2 = norm2(bpq);
+          if (bm2 > 0.0) {
+            const double x = A[q * N2 + q].x - A[p * N2 + p].x;
+            const double ib = rsqrt(bm2);
+            const double y2 = 4.0 * bm2;
+            const double w = fabs(x) + sqrt(fma(x, x, y2));
+            const double z = rsqrt(fma(w, w, y2));
+            c = w * z;
+            const double s = (x >= 0.0 ? 2.0 : -2.0) * (bm2 * ib) * z;  // sign(x) y z
+            sg = make_double2(s * (bpq.x * ib), s * (bpq.y * ib));
+          }
+        }
+        prm[2 * lane] = make_double2(c, 0.0);
+        prm[2 * lane + 1] = sg;
+      }
+      wave_sync();
+      const bool last = round == N2 - 2;
+#pragma unroll
+      for (int k = 0; k < L::TPL; ++k) {
+        const int code = task[k];
+        if (code < 0) continue;
+        const bool is_v = code >= (1 << 16);
+        const int i = (code >> 8) & 0xff, j = code & 0xff;
+        const int ui = player_at(i, round, N2), vi = player_at(N2 - 1 - i, round, N2);
+        const int uj = player_at(j, round, N2), vj = player_at(N2 - 1 - j, round, N2);
+        const int pi = ui < vi ? ui : vi, qi = ui < vi ? vi : ui;
+        const int pj = uj < vj ? uj : vj, qj = uj < vj ? vj : uj;
+        const double cj = prm[2 * j].x;
+        const double2 sj = prm[2 * j + 1];
+        const double ci = is_v ? 1.0 : prm[2 * i].x;
+        const double2 si = is_v ? zero : prm[2 * i + 1];
+        double2* X = is_v ? V : A;
+        // A holds its upper triangle only: an entry below the diagonal is the
+        // conjugate of its transpose
+        const bool tri = !is_v;
+        double2 x00 = ld_entry(X, N2, pi, pj, tri), x01 = ld_entry(X, N2, pi, qj, tri);
+        double2 x10 = ld_entry(X, N2, qi, pj, tri), x11 = ld_entry(X, N2, qi, qj, tri);
+        rot_right(x00, x01, cj, sj);
+        rot_right(x10, x11, cj, sj);
+        rot_left(x00, x10, ci, si);
+        rot_left(x01, x11, ci, si);
+        const bool diag = !is_v && i == j;
+        if (diag) {
+          // a Hermitian 2x2 block: real diagonal; the plane's pair is annihilated exactly
+          x00.y = 0.0;
+          x11.y = 0.0;
+          if (norm2(si) > 0.0) {
+            x01 = zero;
+            x10 = zero;
+          } else {
+            x10 = make_double2(x01.x, -x01.y);
+          }
+        }
+        st_entry(X, N2, pi, pj, tri, x00);
+        st_entry(X, N2, pi, qj, tri, x01);
+        st_entry(X, N2, qi, pj, tri, x10);
+        st_entry(X, N2, qi, qj, tri, x11);
+        if (last && !is_v) {
+          const double d = norm2(x00) + norm2(x11), o = norm2(x01) + norm2(x10);
+          tot += diag ? d + o : 2.0 * (d + o);
+          off += diag ? o : 2.0 * (d + o);
+        }
+      }
+      wave_sync();
+    }
+    off = wave_sum(off);
+    tot = wave_sum(tot);
+    converged = off <= kOffTol2 * tot;
+    off = 0.0;
+    tot = 0.0;
+  }
+  if (!converged && lane == 0) atomicOr(status, kStatusNoConv);
+  // ascending order (ties by index), then each column's largest entry made real positive
+  if (lane < n) {
+    const double li = A[lane * N2 + lane].x;
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = A[j * N2 + j].x;
+      rank += (lj < li) || (lj == li && j < lane);
+    }
+    perm[rank] = lane;
+  }
+  wave_sync();
+  if (lane < n) {
+    const int src = perm[lane];
+    eps[b * n + lane] = A[src * N2 + src].x;
+    double best = -1.0;
+    double2 bv = make_double2(1.0, 0.0);
+    for (int r = 0; r < n; ++r) {
+      const double2 v = V[r * N2 + src];
+      const double m = norm2(v);
+      if (m > best) {
+        best = m;
+        bv = v;
+      }
+    }
+    const double mag = sqrt(best);
+    fix[lane] = mag > 0.0 ? make_double2(bv.x / mag, -bv.y / mag) : make_double2(1.0, 0.0);
+  }
+  wave_sync();
+  double2* out = reinterpret_cast<double2*>(Vout) + b * n * n;
+  for (int e = lane; e < n * n; e += 64) {
+    const int r = e / n, c = e % n;
+    const double2 v = V[r * N2 + perm[c]], f = fix[c];
+    out[e] = make_double2(v.x * f.x - v.y * f.y, v.x * f.y + v.y * f.x);
+  }
 }
 
-__global__ void __launch_bounds__(64)
-    jacobi_small_kernel(const double* __restrict__ H, int n, double* __restrict__ eps,
+// blockDim.x / 64 matrices per workgroup, one wavefront each: a CU's
+// workgroup slots would otherwise cap it at one single-wave solve per slot
+template <int NP>
+__global__ void __launch_bounds__(64 * kSmallPerBlock)
+    jacobi_small_kernel(const double* __restrict__ H, int64_t batch, int n, double* __restrict__ eps,
                         double* __restrict__ V, uint32_t* status) {
-  jacobi_small_body(H, n, eps, V, status, blockIdx.x);
+  extern __shared__ double2 jlds[];
+  const int wave = threadIdx.x >> 6;
+  const int64_t m = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (m >= batch) return;
+  jacobi_small_body<NP>(H, n, eps, V, status, m, jlds + wave * SmallLayout<NP>::slice_elems, threadIdx.x & 63);
 }
 
-// dynamic LDS sized for the largest order among the jobs
-__global__ void __launch_bounds__(64) jacobi_grouped_kernel(const EighJob* __restrict__ jobs, int njobs,
-                                                             uint32_t* status) {
-  const int64_t b = blockIdx.x;
+// NP covers the largest order among the jobs; smaller orders run padded
+template <int NP>
+__global__ void __launch_bounds__(64 * kSmallPerBlock)
+    jacobi_grouped_kernel(const EighJob* __restrict__ jobs, int njobs, int64_t total, uint32_t* status) {
+  extern __shared__ double2 jlds[];
+  const int wave = threadIdx.x >> 6;
+  const int64_t m = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  if (m >= total) return;
   int lo = 0, hi = njobs - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].block_base <= b) lo = mid; else hi = mid - 1;
+    if (jobs[mid].block_base <= m) lo = mid; else hi = mid - 1;
   }
   const EighJob& j = jobs[lo];
-  jacobi_small_body(j.H, j.n, j.eps, j.V, status, b - j.block_base);
+  jacobi_small_body<NP>(j.H, j.n, j.eps, j.V, status, m - j.block_base,
+                        jlds + wave * SmallLayout<NP>::slice_elems, threadIdx.x & 63);
 }
+
+using SmallKernel = void (*)(const double*, int64_t, int, double*, double*, uint32_t*);
+using GroupedKernel = void (*)(const EighJob*, int, int64_t, uint32_t*);
+
+template <int... NPs>
+struct SmallTable {
+  static SmallKernel small(int np) {
+    SmallKernel k = nullptr;
+    ((np == NPs ? (k = jacobi_small_kernel<NPs>, 0) : 0), ...);
+    return k;
+  }
+  static GroupedKernel grouped(int np) {
+    GroupedKernel k = nullptr;
+    ((np == NPs ? (k = jacobi_grouped_kernel<NPs>, 0) : 0), ...);
+    return k;
+  }
+  // solves per workgroup: up to kSmallPerBlock within the 64 KB of dynamic LDS
+  static int per_block(int np) {
+    size_t v = 0;
+    ((np == NPs ? (v = SmallLayout<NPs>::slice_elems * 16, 0) : 0), ...);
+    const size_t fit = v ? 65536 / v : 1;
+    return (int)(fit < (size_t)kSmallPerBlock ? (fit ? fit : 1) : kSmallPerBlock);
+  }
+  static size_t bytes(int np) {
+    size_t v = 0;
+    ((np == NPs ? (v = SmallLayout<NPs>::slice_elems * 16, 0) : 0), ...);
+    return v * per_block(np);
+  }
+};
+using Small = SmallTable<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16>;
 
 __global__ void __launch_bounds__(256)
     jacobi_large_kernel(const double* __restrict__ H, int n, double* __restrict__ eps,
@@ -273,15 +522,21 @@ int64_t jacobi_work_doubles(int n, int64_t batch) {
   return 4 * (int64_t)n * n * chunk;
 }
 
-ephw_status jacobi_eigh_grouped(const EighJob* d_jobs, int njobs, int64_t blocks, int max_n, uint32_t* status,
+ephw_status jacobi_eigh_grouped(const EighJob* d_jobs, int njobs, int64_t total, int max_n, uint32_t* status,
                                 hipStream_t s) {
-  if (njobs <= 0 || blocks <= 0) return EPHW_OK;
+  if (njobs <= 0 || total <= 0) return EPHW_OK;
   if (max_n < 1 || max_n > kSmallN) {
     set_error("jacobi_eigh_grouped: matrix orders must be in [1, 32]");
     return EPHW_EUNSUPPORTED;
   }
-  hipLaunchKernelGGL(jacobi_grouped_kernel, dim3((unsigned)blocks), dim3(64), small_lds_bytes(max_n), s, d_jobs,
-                     njobs, status);
+  const int np = (max_n + 1) / 2, per = Small::per_block(np);
+  const int64_t grid = (total + per - 1) / per;
+  if (grid > 0x7fffffff) {
+    set_error("jacobi_eigh_grouped: too many matrices for one launch");
+    return EPHW_EUNSUPPORTED;
+  }
+  hipLaunchKernelGGL(Small::grouped(np), dim3((unsigned)grid), dim3(64 * per), Small::bytes(np), s, d_jobs, njobs,
+                     total, status);
   EPHW_CHECK_LAUNCH();
   return EPHW_OK;
 }
@@ -289,15 +544,22 @@ ephw_status jacobi_eigh_grouped(const EighJob* d_jobs, int njobs, int64_t blocks
 ephw_status jacobi_eigh(const double* H, int64_t batch, int n, double* eps, double* V, double* work,
                         uint32_t* status, hipStream_t s) {
   if (batch <= 0) return EPHW_OK;
+  if ((reinterpret_cast<uintptr_t>(H) | reinterpret_cast<uintptr_t>(V)) & 15) {
+    set_error("jacobi_eigh: matrices and eigenvectors must be 16-byte aligned complex128 arrays");
+    return EPHW_EINVAL;
+  }
   if (n < 1 || n > 256) {
     set_error("jacobi_eigh: matrix order must be in [1, 256]");
     return EPHW_EUNSUPPORTED;
   }
   if (n <= kSmallN) {
-    for (int64_t b0 = 0; b0 < batch; b0 += 0x7fffffff) {
-      const int64_t nb = (batch - b0) < 0x7fffffff ? (batch - b0) : 0x7fffffff;
-      hipLaunchKernelGGL(jacobi_small_kernel, dim3((unsigned)nb), dim3(64), small_lds_bytes(n), s,
-                         H + 2 * b0 * n * n, n, eps + b0 * n, V + 2 * b0 * n * n, status);
+    const int np = (n + 1) / 2, per = Small::per_block(np);
+    const int64_t max_per_launch = (int64_t)0x7fffffff * per;
+    for (int64_t b0 = 0; b0 < batch; b0 += max_per_launch) {
+      const int64_t nb = (batch - b0) < max_per_launch ? (batch - b0) : max_per_launch;
+      const int64_t grid = (nb + per - 1) / per;
+      hipLaunchKernelGGL(Small::small(np), dim3((unsigned)grid), dim3(64 * per), Small::bytes(np), s,
+                         H + 2 * b0 * n * n, nb, n, eps + b0 * n, V + 2 * b0 * n * n, status);
       EPHW_CHECK_LAUNCH();
     }
     return EPHW_OK;

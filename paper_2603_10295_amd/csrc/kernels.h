@@ -20,7 +20,8 @@ ephw_status jacobi_eigh(const double* H, int64_t batch, int n, double* eps, doub
                         uint32_t* status, hipStream_t s);
 
 // many small (n <= 32) eigensolves of different orders in one launch;
-// block b belongs to the job with the largest block_base <= b (count blocks each)
+// matrix m of the launch belongs to the job with the largest block_base <= m
+// (count matrices each); total = all jobs' matrices, max_n their largest order
 struct EighJob {
   const double* H;
   double* eps;
@@ -28,7 +29,7 @@ struct EighJob {
   int n;
   int64_t count, block_base;
 };
-ephw_status jacobi_eigh_grouped(const EighJob* d_jobs, int njobs, int64_t blocks, int max_n, uint32_t* status,
+ephw_status jacobi_eigh_grouped(const EighJob* d_jobs, int njobs, int64_t total, int max_n, uint32_t* status,
                                 hipStream_t s);
 
 // dst[i] = (T) src[i] for n complex values; T = float (prec 1) or a plain copy (prec 0)
