@@ -217,7 +217,68 @@ struct SmallLayout {
   static constexpr size_t fix_elems = (size_t)N2;                // phase fix per column
   static constexpr size_t bytes = (2 * a_elems + prm_elems + fix_elems) * 16 + (size_t)N2 * 4;
   static constexpr size_t slice_elems = (bytes + 15) / 16;       // one wavefront's share, 16-byte units
+  // per-round task descriptors and plane pairs, shared by the workgroup's
+  // solves (which all have this padded order), when they fit
+  static constexpr size_t table_bytes = (size_t)(N2 - 1) * NT * 8 + (size_t)(N2 - 1) * NP * 4;
+  static constexpr bool kTable = table_bytes <= 32768;
+  static constexpr size_t table_elems = kTable ? (table_bytes + 15) / 16 : 0;
 };
+
+template <int NP>
+__device__ __forceinline__ void decode_task(int t, bool& is_v, int& i, int& j) {
+  constexpr int NA = SmallLayout<NP>::NA;
+  if (t < NA) {
+    int r = 0, rest = t;
+    while (rest >= NP - r) {
+      rest -= NP - r;
+      ++r;
+    }
+    is_v = false;
+    i = r;
+    j = r + rest;
+  } else {
+    const int v = t - NA;
+    is_v = true;
+    i = v / NP;
+    j = v % NP;
+  }
+}
+
+// plane of pair k in a round: p | q << 8 with p < q
+__device__ __forceinline__ int pair_pq(int k, int round, int n2) {
+  const int u = player_at(k, round, n2), v = player_at(n2 - 1 - k, round, n2);
+  return u < v ? (u | v << 8) : (v | u << 8);
+}
+
+// The four entries of task t's block in a round, as offsets into the solve's
+// slice (A at 0, V after it); bit 15 marks an entry of A below the diagonal,
+// held as the conjugate of its transpose.
+template <int NP>
+__device__ __forceinline__ uint2 task_entries(int t, int round) {
+  using L = SmallLayout<NP>;
+  constexpr int N2 = L::N2;
+  bool is_v;
+  int i, j;
+  decode_task<NP>(t, is_v, i, j);
+  const int pqi = pair_pq(i, round, N2), pqj = pair_pq(j, round, N2);
+  const int rr[2] = {pqi & 0xff, pqi >> 8}, cc[2] = {pqj & 0xff, pqj >> 8};
+  uint32_t d[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int r = rr[e >> 1], c = cc[e & 1];
+    d[e] = is_v ? (uint32_t)(L::a_elems + r * N2 + c)
+                : (r <= c ? (uint32_t)(r * N2 + c) : (uint32_t)(c * N2 + r) | 0x8000u);
+  }
+  return make_uint2(d[0] | d[1] << 16, d[2] | d[3] << 16);
+}
+
+template <int NP>
+__device__ void build_tables(uint2* ent, int* pq) {
+  using L = SmallLayout<NP>;
+  constexpr int N2 = L::N2;
+  for (int e = threadIdx.x; e < (N2 - 1) * L::NT; e += blockDim.x) ent[e] = task_entries<NP>(e % L::NT, e / L::NT);
+  for (int e = threadIdx.x; e < (N2 - 1) * NP; e += blockDim.x) pq[e] = pair_pq(e % NP, e / NP, N2);
+}
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
@@ -242,15 +303,16 @@ __device__ __forceinline__ void rot_left(double2& x, double2& y, double c, doubl
 
 __device__ __forceinline__ double norm2(double2 v) { return v.x * v.x + v.y * v.y; }
 
-__device__ __forceinline__ double2 ld_entry(const double2* X, int ld, int r, int c, bool tri) {
-  const bool sw = tri && r > c;
-  const double2 v = X[sw ? c * ld + r : r * ld + c];
-  return sw ? make_double2(v.x, -v.y) : v;
+// entry descriptor (15-bit offset, conjugate flag in bit 15) -> value
+__device__ __forceinline__ double flip_sign(double v, uint32_t d) {
+  return __longlong_as_double(__double_as_longlong(v) ^ ((long long)(d & 0x8000u) << 48));
 }
-
-__device__ __forceinline__ void st_entry(double2* X, int ld, int r, int c, bool tri, double2 v) {
-  const bool sw = tri && r > c;
-  X[sw ? c * ld + r : r * ld + c] = sw ? make_double2(v.x, -v.y) : v;
+__device__ __forceinline__ double2 ld_entry(const double2* X, uint32_t d) {
+  const double2 v = X[d & 0x7fffu];
+  return make_double2(v.x, flip_sign(v.y, d));
+}
+__device__ __forceinline__ void st_entry(double2* X, uint32_t d, double2 v) {
+  X[d & 0x7fffu] = make_double2(v.x, flip_sign(v.y, d));
 }
 
 // the solve of a matrix is one wavefront's: its LDS traffic needs only the
@@ -264,7 +326,7 @@ __device__ __forceinline__ void wave_sync() {
 template <int NP>
 __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, int n, double* __restrict__ eps,
                                                   double* __restrict__ Vout, uint32_t* status, int64_t b,
-                                                  double2* slice, int lane) {
+                                                  double2* slice, int lane, const uint2* ent, const int* pqt) {
   using L = SmallLayout<NP>;
   constexpr int N2 = L::N2;
   double2* A = slice;
@@ -281,16 +343,11 @@ __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, 
   for (int k = 0; k < L::TPL; ++k) {
     const int t = lane + 64 * k;
     int code = -1;
-    if (t < L::NA) {
-      int i = 0, rest = t;
-      while (rest >= NP - i) {
-        rest -= NP - i;
-        ++i;
-      }
-      code = (i << 8) | (i + rest);
-    } else if (t < L::NT) {
-      const int v = t - L::NA;
-      code = (1 << 16) | ((v / NP) << 8) | (v % NP);
+    if (t < L::NT) {
+      bool is_v;
+      int i, j;
+      decode_task<NP>(t, is_v, i, j);
+      code = (is_v ? 1 << 16 : 0) | (i << 8) | j;
     }
     task[k] = code;
   }
@@ -315,8 +372,8 @@ __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, 
 #pragma unroll 1
     for (int round = 0; round < N2 - 1; ++round) {
       if (lane < NP) {
-        const int u = player_at(lane, round, N2), v = player_at(N2 - 1 - lane, round, N2);
-        const int p = u < v ? u : v, q = u < v ? v : u;
+        const int pq = L::kTable ? pqt[round * NP + lane] : pair_pq(lane, round, N2);
+        const int p = pq & 0xff, q = pq >> 8;
         double c = 1.0;
         double2 sg = zero;
         if (q < n) {
@@ -344,20 +401,15 @@ __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, 
         if (code < 0) continue;
         const bool is_v = code >= (1 << 16);
         const int i = (code >> 8) & 0xff, j = code & 0xff;
-        const int ui = player_at(i, round, N2), vi = player_at(N2 - 1 - i, round, N2);
-        const int uj = player_at(j, round, N2), vj = player_at(N2 - 1 - j, round, N2);
-        const int pi = ui < vi ? ui : vi, qi = ui < vi ? vi : ui;
-        const int pj = uj < vj ? uj : vj, qj = uj < vj ? vj : uj;
+        const uint2 d = L::kTable ? ent[round * L::NT + lane + 64 * k] : task_entries<NP>(lane + 64 * k, round);
         const double cj = prm[2 * j].x;
         const double2 sj = prm[2 * j + 1];
         const double ci = is_v ? 1.0 : prm[2 * i].x;
         const double2 si = is_v ? zero : prm[2 * i + 1];
-        double2* X = is_v ? V : A;
         // A holds its upper triangle only: an entry below the diagonal is the
-        // conjugate of its transpose
-        const bool tri = !is_v;
-        double2 x00 = ld_entry(X, N2, pi, pj, tri), x01 = ld_entry(X, N2, pi, qj, tri);
-        double2 x10 = ld_entry(X, N2, qi, pj, tri), x11 = ld_entry(X, N2, qi, qj, tri);
+        // conjugate of its transpose (flagged in its descriptor)
+        double2 x00 = ld_entry(slice, d.x & 0xffff), x01 = ld_entry(slice, d.x >> 16);
+        double2 x10 = ld_entry(slice, d.y & 0xffff), x11 = ld_entry(slice, d.y >> 16);
         rot_right(x00, x01, cj, sj);
         rot_right(x10, x11, cj, sj);
         rot_left(x00, x10, ci, si);
@@ -374,10 +426,10 @@ __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, 
             x10 = make_double2(x01.x, -x01.y);
           }
         }
-        st_entry(X, N2, pi, pj, tri, x00);
-        st_entry(X, N2, pi, qj, tri, x01);
-        st_entry(X, N2, qi, pj, tri, x10);
-        st_entry(X, N2, qi, qj, tri, x11);
+        st_entry(slice, d.x & 0xffff, x00);
+        st_entry(slice, d.x >> 16, x01);
+        st_entry(slice, d.y & 0xffff, x10);
+        st_entry(slice, d.y >> 16, x11);
         if (last && !is_v) {
           const double d = norm2(x00) + norm2(x11), o = norm2(x01) + norm2(x10);
           tot += diag ? d + o : 2.0 * (d + o);
@@ -436,10 +488,17 @@ __global__ void __launch_bounds__(64 * kSmallPerBlock)
     jacobi_small_kernel(const double* __restrict__ H, int64_t batch, int n, double* __restrict__ eps,
                         double* __restrict__ V, uint32_t* status) {
   extern __shared__ double2 jlds[];
-  const int wave = threadIdx.x >> 6;
-  const int64_t m = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  using L = SmallLayout<NP>;
+  const int wave = threadIdx.x >> 6, per = blockDim.x >> 6;
+  uint2* ent = reinterpret_cast<uint2*>(jlds + per * L::slice_elems);
+  int* pqt = reinterpret_cast<int*>(ent + (L::N2 - 1) * L::NT);
+  if (L::kTable) {
+    build_tables<NP>(ent, pqt);
+    __syncthreads();
+  }
+  const int64_t m = (int64_t)blockIdx.x * per + wave;
   if (m >= batch) return;
-  jacobi_small_body<NP>(H, n, eps, V, status, m, jlds + wave * SmallLayout<NP>::slice_elems, threadIdx.x & 63);
+  jacobi_small_body<NP>(H, n, eps, V, status, m, jlds + wave * L::slice_elems, threadIdx.x & 63, ent, pqt);
 }
 
 // NP covers the largest order among the jobs; smaller orders run padded
@@ -447,8 +506,15 @@ template <int NP>
 __global__ void __launch_bounds__(64 * kSmallPerBlock)
     jacobi_grouped_kernel(const EighJob* __restrict__ jobs, int njobs, int64_t total, uint32_t* status) {
   extern __shared__ double2 jlds[];
-  const int wave = threadIdx.x >> 6;
-  const int64_t m = (int64_t)blockIdx.x * (blockDim.x >> 6) + wave;
+  using L = SmallLayout<NP>;
+  const int wave = threadIdx.x >> 6, per = blockDim.x >> 6;
+  uint2* ent = reinterpret_cast<uint2*>(jlds + per * L::slice_elems);
+  int* pqt = reinterpret_cast<int*>(ent + (L::N2 - 1) * L::NT);
+  if (L::kTable) {
+    build_tables<NP>(ent, pqt);
+    __syncthreads();
+  }
+  const int64_t m = (int64_t)blockIdx.x * per + wave;
   if (m >= total) return;
   int lo = 0, hi = njobs - 1;
   while (lo < hi) {
@@ -456,8 +522,8 @@ __global__ void __launch_bounds__(64 * kSmallPerBlock)
     if (jobs[mid].block_base <= m) lo = mid; else hi = mid - 1;
   }
   const EighJob& j = jobs[lo];
-  jacobi_small_body<NP>(j.H, j.n, j.eps, j.V, status, m - j.block_base,
-                        jlds + wave * SmallLayout<NP>::slice_elems, threadIdx.x & 63);
+  jacobi_small_body<NP>(j.H, j.n, j.eps, j.V, status, m - j.block_base, jlds + wave * L::slice_elems,
+                        threadIdx.x & 63, ent, pqt);
 }
 
 using SmallKernel = void (*)(const double*, int64_t, int, double*, double*, uint32_t*);
@@ -477,15 +543,15 @@ struct SmallTable {
   }
   // solves per workgroup: up to kSmallPerBlock within the 64 KB of dynamic LDS
   static int per_block(int np) {
-    size_t v = 0;
-    ((np == NPs ? (v = SmallLayout<NPs>::slice_elems * 16, 0) : 0), ...);
-    const size_t fit = v ? 65536 / v : 1;
+    size_t v = 0, t = 0;
+    ((np == NPs ? (v = SmallLayout<NPs>::slice_elems * 16, t = SmallLayout<NPs>::table_elems * 16, 0) : 0), ...);
+    const size_t fit = v ? (65536 - t) / v : 1;
     return (int)(fit < (size_t)kSmallPerBlock ? (fit ? fit : 1) : kSmallPerBlock);
   }
   static size_t bytes(int np) {
-    size_t v = 0;
-    ((np == NPs ? (v = SmallLayout<NPs>::slice_elems * 16, 0) : 0), ...);
-    return v * per_block(np);
+    size_t v = 0, t = 0;
+    ((np == NPs ? (v = SmallLayout<NPs>::slice_elems * 16, t = SmallLayout<NPs>::table_elems * 16, 0) : 0), ...);
+    return v * per_block(np) + t;
   }
 };
 using Small = SmallTable<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16>;
