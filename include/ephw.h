@@ -131,7 +131,8 @@ ephw_status ephw_system_bytes(const ephw_system* sys, int64_t* bytes);
 /* Electron bands on a k list (H(k) interpolation + FP64 eigensolve).
      k    [nk][3] f64 (device)
      eps  [nk][nw] f64 (device) or NULL
-     vecs [nk][nw][nw] c128 (device) or NULL; column j is the eigenvector of eps[j] */
+     vecs [nk][nw][nw] c128 (device) or NULL; column j is the eigenvector of eps[j]
+   vecs must be 16-byte aligned, as every c128 array is (EPHW_EINVAL otherwise). */
 ephw_status ephw_bands(ephw_system* sys, const double* k, int64_t nk, double* eps, void* vecs,
                        void* stream);
 
@@ -139,7 +140,8 @@ ephw_status ephw_bands(ephw_system* sys, const double* k, int64_t nk, double* ep
      q     [nq][3] f64 (device)
      lam   [nq][nm] f64 eigenvalues of D(q), or NULL
      omega [nq][nm] f64 sqrt(|lam|), or NULL
-     evecs [nq][nm][nm] c128 eigenvectors e (columns), or NULL  (u = e/sqrt(M)) */
+     evecs [nq][nm][nm] c128 eigenvectors e (columns), or NULL  (u = e/sqrt(M)),
+           16-byte aligned (EPHW_EINVAL otherwise) */
 ephw_status ephw_phonons(ephw_system* sys, const double* q, int64_t nq, double* lam,
                          double* omega, void* evecs, void* stream);
 
