@@ -184,6 +184,38 @@ __device__ __forceinline__ BandLds<T> band_lds(unsigned char* smem_raw, int P, i
   return L;
 }
 
+// floor(i / d) for 0 <= i < 2^22 from rd = 1.0f / d: (i + 1/2) / d lies at
+// least 1/(2d) from an integer, more than the float product's error
+__device__ __forceinline__ int div_rcp(int i, float rd) { return (int)(((float)i + 0.5f) * rd); }
+
+// complex values of a 16-byte chunk: 2 at c64, 1 at c128
+template <typename T>
+struct Chunk16 {
+  static constexpr int kVec = 16 / (2 * (int)sizeof(T));
+};
+
+// one 16-byte chunk of complex values between HBM (contiguous) and a padded
+// LDS row (8-byte aligned at c64); both values of a c64 chunk share the row
+template <typename T>
+__device__ __forceinline__ void chunk_to_lds(const T* src, T* dst) {
+  if constexpr (sizeof(T) == 4) {
+    const float4 v = *reinterpret_cast<const float4*>(src);
+    reinterpret_cast<float2*>(dst)[0] = make_float2(v.x, v.y);
+    reinterpret_cast<float2*>(dst)[1] = make_float2(v.z, v.w);
+  } else {
+    *reinterpret_cast<double2*>(dst) = *reinterpret_cast<const double2*>(src);
+  }
+}
+template <typename T>
+__device__ __forceinline__ void chunk_from_lds(const T* src, T* dst) {
+  if constexpr (sizeof(T) == 4) {
+    const float2 a = reinterpret_cast<const float2*>(src)[0], b = reinterpret_cast<const float2*>(src)[1];
+    *reinterpret_cast<float4*>(dst) = make_float4(a.x, a.y, b.x, b.y);
+  } else {
+    *reinterpret_cast<double2*>(dst) = *reinterpret_cast<const double2*>(src);
+  }
+}
+
 template <typename T, int NWB>
 __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, int nuc, int64_t kblk, int iq,
                                                unsigned char* smem_raw) {
@@ -195,6 +227,9 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
   const int64_t E = (int64_t)nm * nw2;
   const bool rot = a.Vk != nullptr;
   const int tid = threadIdx.x;
+  const bool vec_shape = E % Chunk16<T>::kVec == 0 && nw2 % Chunk16<T>::kVec == 0;
+  const bool vec = vec_shape && (reinterpret_cast<uintptr_t>(a.W) & 15) == 0;               // loads
+  const bool vec_g = vec_shape && (reinterpret_cast<uintptr_t>(a.g_out) & 15) == 0;         // stores
   const int rows_pp = nuc * nw;
   const int p = tid / rows_pp, r = tid % rows_pp;
   const int vl = r / nw, mrow = r % nw;
@@ -203,10 +238,11 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
   const bool in_pair = p < npair;
   BandLds<T> L = band_lds<T>(smem_raw, P, nw, rows_pp);
 
+  const float r_nw = 1.0f / (float)nw, r_nw2 = 1.0f / (float)nw2;
   if (rot) {
     const T* Vk = static_cast<const T*>(a.Vk);
     for (int i = tid; i < npair * nw2; i += kRotThreads) {
-      const int pp = i / nw2, e = i % nw2;
+      const int pp = div_rcp(i, r_nw2), e = i - pp * nw2;
       const int64_t ik = a.k0 + ik0 + pp;
       const T* src;
       if (a.kq_index) {
@@ -239,12 +275,22 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
     // 1. X rows of the chunk -> LDS (small bands: each thread reads its own
     //    row straight into registers in step 2 instead)
     const int cw = nv * nw2;   // complex values per pair in this chunk
-    for (int i = tid; i < ((DIRECT && rot) ? 0 : npair * cw); i += kRotThreads) {
-      const int pp = i / cw, e = i % cw;
+    // 16-byte chunks when every chunk's source offset is a multiple of the
+    // chunk (E and Nw^2 are); element by element otherwise
+    const int step = vec ? Chunk16<T>::kVec : 1;
+    const int cpp = cw / step;
+    const float r_cpp = 1.0f / (float)cpp;
+    for (int i = tid; i < ((DIRECT && rot) ? 0 : npair * cpp); i += kRotThreads) {
+      const int pp = div_rcp(i, r_cpp), e = (i - pp * cpp) * step;
+      const int row = div_rcp(e, r_nw), col = e - row * nw;
       const T* src = W + 2 * ((ik0 + pp) * (int64_t)a.qb * E + (int64_t)iq * E + (int64_t)v0 * nw2 + e);
-      T* dst = L.rows + 2 * ((pp * rows_pp + e / nw) * ld + e % nw);
-      dst[0] = src[0];
-      dst[1] = src[1];
+      T* dst = L.rows + 2 * ((pp * rows_pp + row) * ld + col);
+      if (vec) {
+        chunk_to_lds(src, dst);
+      } else {
+        dst[0] = src[0];
+        dst[1] = src[1];
+      }
     }
     __syncthreads();
     T* own = L.rows + 2 * (tid * ld);
@@ -342,12 +388,20 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
       }
       __syncthreads();
       T* go = static_cast<T*>(a.g_out) + 2 * (((int64_t)iq * a.nk + a.k0 + ik0) * E + (int64_t)v0 * nw2);
-      for (int i = tid; i < npair * cw; i += kRotThreads) {
-        const int pp = i / cw, e = i % cw;
-        const T* src = L.rows + 2 * ((pp * rows_pp + e / nw) * ld + e % nw);
+      const int gstep = vec_g ? Chunk16<T>::kVec : 1;
+      const int gpp = cw / gstep;
+      const float r_gpp = 1.0f / (float)gpp;
+      for (int i = tid; i < npair * gpp; i += kRotThreads) {
+        const int pp = div_rcp(i, r_gpp), e = (i - pp * gpp) * gstep;
+        const int row = div_rcp(e, r_nw), col = e - row * nw;
+        const T* src = L.rows + 2 * ((pp * rows_pp + row) * ld + col);
         T* dst = go + 2 * ((int64_t)pp * E + e);
-        dst[0] = src[0];
-        dst[1] = src[1];
+        if (vec_g) {
+          chunk_from_lds(src, dst);
+        } else {
+          dst[0] = src[0];
+          dst[1] = src[1];
+        }
       }
     }
     if (want_t) {
