@@ -185,6 +185,25 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
                              double* band_sum, double* loss, uint64_t loss_seed, double* eps_kq,
                              double* omega, void* stream);
 
+/* Gauge-invariant |g|^2 of stored matrix elements (the quantity Eq. (7)'s
+   results are compared by: eigenvectors of (near-)degenerate eigenvalues are
+   fixed only up to a unitary mixing inside their block).  For every pair,
+   element (nu, m, n) of out is the sum of |g_{m'n'nu'}|^2 over nu' in the
+   block of nu (modes at q), m' in the block of m (bands at k+q) and n' in the
+   block of n (bands at k), so every element of a block holds the block's sum.
+   A block is a run of the ascending list whose consecutive gaps are at most
+   rel_tol * max(1, max |value|) of that list (1e-6 is the usual choice).
+     prec    EPHW_FP64: g c128; EPHW_FP32 or EPHW_FP32_SPLIT: g c64
+     g       [nq][nk][nm][nw][nw] (device), as ephw_interpolate stores it
+     eps_kq  [nq][nk][nw] f64 (device), ascending: bands at k+q
+     eps_k   [nk][nw] f64 (device), ascending: bands at k
+     lam     [nq][nm] f64 (device), ascending: eigenvalues of D(q) (ephw_phonons)
+     out     [nq][nk][nm][nw][nw] f64 (device), caller-owned
+   Limits: 1 <= nw <= 256, 1 <= nm <= 258.  Enqueued on stream. */
+ephw_status ephw_degenerate_sums(int32_t prec, const void* g, int64_t nq, int64_t nk, int32_t nm, int32_t nw,
+                                 const double* eps_kq, const double* eps_k, const double* lam, double rel_tol,
+                                 double* out, void* stream);
+
 /* Loss and gradients (not in the paper: the adjoint of Eq. (7)).
    L = sum over the k-set's points and the q list of w_{mn nu}(k,q) |g_{mn nu}(k,q)|^2
    with the SplitMix64 weights of EPHW_OUT_LOSS (seed loss_seed, q index q_offset + iq).

@@ -713,4 +713,25 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
   return EPHW_OK;
 }
 
+ephw_status ephw_degenerate_sums(int32_t prec, const void* g, int64_t nq, int64_t nk, int32_t nm, int32_t nw,
+                                 const double* eps_kq, const double* eps_k, const double* lam, double rel_tol,
+                                 double* out, void* stream) {
+  if (prec != EPHW_FP64 && prec != EPHW_FP32 && prec != EPHW_FP32_SPLIT) {
+    set_error("ephw_degenerate_sums: unknown precision");
+    return EPHW_EINVAL;
+  }
+  if (nq < 0 || nk < 0 || nw < 1 || nw > 256 || nm < 1 || nm > 258 || !(rel_tol >= 0.0) ||
+      rel_tol > 1e300) {
+    set_error("ephw_degenerate_sums: sizes or tolerance out of range");
+    return EPHW_EINVAL;
+  }
+  if (nq * nk == 0) return EPHW_OK;
+  if (!g || !eps_kq || !eps_k || !lam || !out) {
+    set_error("ephw_degenerate_sums: a buffer is NULL");
+    return EPHW_EINVAL;
+  }
+  return degenerate_sums(prec == EPHW_FP64 ? 0 : 1, g, nq, nk, nm, nw, eps_kq, eps_k, lam, rel_tol, out,
+                         as_stream(stream));
+}
+
 }  // extern "C"

@@ -49,6 +49,15 @@ __device__ __forceinline__ void st(T* p, int64_t i, cplx<T> v) {
   p[2 * i + 1] = v.im;
 }
 
+// A wavefront that owns its LDS region alone needs only its own LDS
+// operations complete before it reads what other lanes wrote, never a
+// workgroup barrier.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // ---------------------------------------------------------------------------
 // device status word bits (context-wide, read by ephw_ctx_check)
 // ---------------------------------------------------------------------------

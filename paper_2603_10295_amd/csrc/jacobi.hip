@@ -315,13 +315,7 @@ __device__ __forceinline__ void st_entry(double2* X, uint32_t d, double2 v) {
   X[d & 0x7fffu] = make_double2(v.x, flip_sign(v.y, d));
 }
 
-// the solve of a matrix is one wavefront's: its LDS traffic needs only the
-// wave's own LDS operations complete, never a workgroup barrier
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-}
+// the solve of a matrix is one wavefront's (wave_sync, no workgroup barrier)
 
 template <int NP>
 __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, int n, double* __restrict__ eps,

@@ -32,6 +32,12 @@ struct EighJob {
 ephw_status jacobi_eigh_grouped(const EighJob* d_jobs, int njobs, int64_t total, int max_n, uint32_t* status,
                                 hipStream_t s);
 
+// out[q][k][nu][m][n] = sum of |g|^2 over the degenerate blocks of nu (lam[q]),
+// m (eps_kq[q][k]) and n (eps_k[k]); g c128 (prec 0) or c64
+ephw_status degenerate_sums(int prec, const void* g, int64_t nq, int64_t nk, int nm, int nw,
+                            const double* eps_kq, const double* eps_k, const double* lam, double rel_tol,
+                            double* out, hipStream_t s);
+
 // dst[i] = (T) src[i] for n complex values; T = float (prec 1) or a plain copy (prec 0)
 ephw_status cast_complex(int prec, const double* src, void* dst, int64_t n, hipStream_t s);
 

@@ -26,7 +26,7 @@ OUT_G, OUT_BAND_SUM, OUT_LOSS, OUT_WANNIER = 1, 2, 4, 8
 EXPORTS = [
     "ephw_ctx_create", "ephw_ctx_destroy", "ephw_ctx_check", "ephw_system_load",
     "ephw_system_free", "ephw_system_set_g", "ephw_system_bytes", "ephw_bands", "ephw_phonons", "ephw_phase_sum_rp",
-    "ephw_kset_create", "ephw_kset_free", "ephw_kset_bands", "ephw_interpolate",
+    "ephw_kset_create", "ephw_kset_free", "ephw_kset_bands", "ephw_interpolate", "ephw_degenerate_sums",
     "ephw_loss_backward", "ephw_set_q_batch", "ephw_set_k_tile", "ephw_profile_enable", "ephw_profile_read", "ephw_batch_create",
     "ephw_batch_run", "ephw_batch_shape", "ephw_batch_stats", "ephw_batch_free", "ephw_status_string",
     "ephw_last_error", "ephw_version",
@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
         "ephw_kset_free": [vp],
         "ephw_kset_bands": [vp, vp, vp, vp],
         "ephw_interpolate": [vp, vp, i64, vp, i64, i32, u32, vp, vp, vp, u64, vp, vp, vp],
+        "ephw_degenerate_sums": [i32, vp, i64, i64, i32, i32, vp, vp, vp, ctypes.c_double, vp, vp],
         "ephw_set_q_batch": [vp, i32],
         "ephw_set_k_tile": [vp, i32],
         "ephw_loss_backward": [vp, vp, i64, vp, i64, u64, vp, vp, vp, vp, vp],
@@ -301,6 +302,15 @@ def interpolate(ks: KSet, q, *, kq_index=None, q_offset: int = 0, flags: int = O
     _check(lib().ephw_interpolate(ks.handle, _ptr(q), q.shape[0], _ptr(kq_index), int(q_offset), ks.prec,
                                   int(flags), _ptr(g_out), _ptr(band_sum), _ptr(loss), int(loss_seed),
                                   _ptr(eps_kq), _ptr(omega), _stream(stream)), "ephw_interpolate")
+
+
+def degenerate_sums(prec: int, g, eps_kq, eps_k, lam, out, rel_tol: float = 1e-6, stream=None):
+    """out[q][k][nu][m][n] = |g|^2 summed over the degenerate blocks of nu, m, n.
+    g [nq][nk][nm][nw][nw] (c128 at FP64, c64 otherwise), eps_kq [nq][nk][nw],
+    eps_k [nk][nw], lam [nq][nm], out f64 shaped like g."""
+    nq, nk, nm, nw = g.shape[0], g.shape[1], g.shape[2], g.shape[3]
+    _check(lib().ephw_degenerate_sums(int(prec), _ptr(g), nq, nk, nm, nw, _ptr(eps_kq), _ptr(eps_k), _ptr(lam),
+                                      float(rel_tol), _ptr(out), _stream(stream)), "ephw_degenerate_sums")
 
 
 class Batch:

@@ -43,6 +43,14 @@ def test_null_arguments_rejected_before_any_device_call():
     assert L.ephw_ctx_check(None, None) == ephw.EINVAL
     assert L.ephw_kset_create(None, None, 4, 0, None, None) == ephw.EINVAL
     assert L.ephw_bands(None, None, 3, None, None, None) == ephw.EINVAL
+    # degenerate-block sums: precision, sizes, tolerance and buffers are checked on the host
+    assert L.ephw_degenerate_sums(7, None, 1, 1, 3, 4, None, None, None, 1e-6, None, None) == ephw.EINVAL
+    assert L.ephw_degenerate_sums(0, None, 1, 1, 3, 0, None, None, None, 1e-6, None, None) == ephw.EINVAL
+    assert L.ephw_degenerate_sums(0, None, 1, 1, 3, 4, None, None, None, -1.0, None, None) == ephw.EINVAL
+    assert L.ephw_degenerate_sums(0, None, 1, 1, 3, 4, None, None, None, float("nan"), None, None) == ephw.EINVAL
+    assert L.ephw_degenerate_sums(0, None, 2, 3, 3, 4, None, None, None, 1e-6, None, None) == ephw.EINVAL
+    assert b"NULL" in L.ephw_last_error()
+    assert L.ephw_degenerate_sums(1, None, 0, 3, 3, 4, None, None, None, 1e-6, None, None) == ephw.OK
     assert L.ephw_phonons(None, None, 3, None, None, None, None) == ephw.EINVAL
     assert L.ephw_phase_sum_rp(None, None, 3, 0, None, None) == ephw.EINVAL
     assert L.ephw_ctx_create(0, None) == ephw.EINVAL

@@ -316,3 +316,58 @@ def test_phase_sum_rp_few_q(run, prec, nq):
     got = run.phase_sum_rp(run.system(s), q, prec)
     err = rel_max(got, oracle.g_re_q(s, q))
     assert err < (RTOL_W if prec == 0 else 2e-6), err
+
+
+def block_index(starts, n):
+    """Block number of every index 0..n-1 for block start indices `starts`."""
+    return np.searchsorted(starts, np.arange(n), side="right") - 1
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_degenerate_sums_gauge_invariant(run, prec):
+    """Epilogue (ii), ephw_degenerate_sums, on bands made exactly two-fold
+    degenerate: H(R) = h(R) (x) 1_2, so inside each pair of bands the
+    eigenvectors are fixed only up to a 2x2 unitary and the two sides need
+    not agree on |g|^2 element by element.  Every element of the GPU output
+    must hold the oracle's sum over its block (bands at k+q, bands at k,
+    modes at q), the oracle grouping its own eigenvalues."""
+    import dataclasses
+    import torch
+    from paper_2603_10295_amd import ephw
+    from gpu_run import dev
+    r_e, r_p = synth.box((3, 2, 2)), synth.box((2, 2, 1))
+    base = [41, 3]
+    s = synth.make_system(8, 2, r_e, r_p, base)
+    h4 = synth.hermitian_paired(r_e, 4, synth.rng(base, synth.STREAM_H), complex_=True)
+    s.h_r = np.stack([np.kron(h, np.eye(2)) for h in h4])
+    if prec == 1:
+        s = dataclasses.replace(s, g=s.g.astype(np.complex64))
+    k = synth.random_points(5, synth.rng(base, synth.STREAM_K))
+    q = synth.random_points(3, synth.rng(base, synth.STREAM_Q))
+    sysh = run.system(s)
+    out = run.interpolate(sysh, k, q, prec, flags=ephw.OUT_G)
+    lam = run.phonons(sysh, q)[0]
+    d = torch.empty(out["g"].shape, dtype=torch.float64, device="cuda:0")
+    ephw.degenerate_sums(prec, dev(out["g"]), dev(out["eps_kq"]), dev(out["eps_k"]), dev(lam), d)
+    run.ctx.check()
+    d = d.cpu().numpy()
+
+    ref = oracle.interpolate(s, k, q, return_all=True)
+    sums = oracle.block_sums(np.abs(ref["ghat"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+    nm, nw = s.nm, s.nw
+    expected = np.empty_like(d)
+    i = 0
+    for iq in range(len(q)):
+        bv = block_index(oracle.degenerate_blocks(ref["lam"][iq]), nm)
+        for ik in range(len(k)):
+            assert len(oracle.degenerate_blocks(ref["eps_k"][ik])) == nw // 2   # the pairs are degenerate
+            bm = block_index(oracle.degenerate_blocks(ref["eps_kq"][iq, ik]), nw)
+            bn = block_index(oracle.degenerate_blocks(ref["eps_k"][ik]), nw)
+            expected[iq, ik] = sums[i][np.ix_(bv, bm, bn)]
+            i += 1
+    err = rel_max(d, expected)
+    raw = rel_max(np.abs(out["g"].astype(np.complex128)) ** 2, np.abs(ref["ghat"]) ** 2)
+    print(f"degenerate sums prec={prec}: max error {err:.2e} of the largest block sum "
+          f"(raw |g|^2 differ by {raw:.2e}: the gauge inside the blocks is free)")
+    assert err < (1e-10 if prec == 0 else 1e-5)
+    assert raw > 1e-6
