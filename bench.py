@@ -38,7 +38,7 @@ def parse(argv=None):
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="si_dense",
-                    choices=["si_dense", "mos2_2d", "si_toy", "batch32", "ribbon"])
+                    choices=["si_dense", "mos2_2d", "si_toy", "batch32", "ribbon", "coarse_si"])
     ap.add_argument("--ribbon-nk", type=int, default=256, help="k = q = i/n along the ribbon axis")
     ap.add_argument("--ribbon-nw", type=int, default=200)
     ap.add_argument("--ribbon-na", type=int, default=50)
@@ -323,22 +323,91 @@ def bench_ribbon(args):
     return 0
 
 
+def bench_coarse(args):
+    """Eq. (6), the coarse Bloch -> Wannier transform, on a Si-like system:
+    Nw 8, Nm 6, Re box 8^3 and Rp box 4^3 with the coarse k' = 8^3 and
+    q' = 4^3 grids they are complete residue systems of.  The Bloch input is
+    Eq. (7) on those grids; parity is the round trip back to g(Re,Rp)."""
+    import torch
+    import synth
+    from paper_2603_10295_amd import ephw
+    ne_box, np_box = (8, 8, 8), (4, 4, 4)
+    t_gen = time.perf_counter()
+    s = synth.make_system(8, 2, synth.box(ne_box), synth.box(np_box), [0, 11])
+    kc, qc = synth.uniform_grid(ne_box), synth.uniform_grid(np_box)
+    mk = np.asarray(ne_box)
+    ik, iq = np.rint(kc * mk).astype(np.int64), np.rint(qc * mk).astype(np.int64)
+    sm = (ik[None] + iq[:, None]) % mk
+    kqi_np = (sm[..., 0] * mk[1] * mk[2] + sm[..., 1] * mk[2] + sm[..., 2]).astype(np.int32)
+    nk, nq, E = len(kc), len(qc), s.nm * s.nw * s.nw
+    log(f"coarse workload: nk'={nk} nq'={nq} ne={s.ne} np={s.np_} E={E}, generated in "
+        f"{time.perf_counter() - t_gen:.1f}s")
+    ctx = ephw.Context(0)
+    k = torch.from_numpy(kc).to("cuda:0")
+    q = torch.from_numpy(qc).to("cuda:0")
+    kqi = torch.from_numpy(kqi_np).to("cuda:0")
+    # algorithmic flops: two band rotations per pair, the Re and Rp sums, the mode contraction
+    flops = 8.0 * (2 * nk * nq * s.nm * s.nw ** 3 + s.ne * nq * E * nk + nq * s.ne * s.nm * s.nm * s.nw ** 2
+                   + s.np_ * s.ne * E * nq)
+    results = {}
+    for prec, g_dtype, t_dtype in ((ephw.FP32, np.complex64, torch.complex64),
+                                   (ephw.FP64, np.complex128, torch.complex128)):
+        s.g = s.g.astype(g_dtype)
+        sysh = ephw.System.from_synth(ctx, s)
+        ks = ephw.KSet(sysh, k, prec)
+        g_b = torch.empty((nq, nk, s.nm, s.nw, s.nw), dtype=t_dtype, device="cuda:0")
+        ephw.interpolate(ks, q, kq_index=kqi, flags=ephw.OUT_G, g_out=g_b)
+        out = torch.empty((s.np_, s.ne, s.nm, s.nw, s.nw), dtype=t_dtype, device="cuda:0")
+        for _ in range(args.warmup):
+            ephw.wannier_transform(ks, q, kqi, g_b, out)
+        torch.cuda.synchronize()
+        steps = args.steps if prec == ephw.FP32 else max(1, args.fp64_steps)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ephw.wannier_transform(ks, q, kqi, g_b, out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        ctx.check()
+        ref = torch.from_numpy(s.g).to("cuda:0")
+        err = float((out.to(torch.complex128) - ref.to(torch.complex128)).abs().max() / ref.abs().max())
+        name = "fp32" if prec == ephw.FP32 else "fp64"
+        results[name] = {"ms": dt * 1e3, "tflops": flops / dt / 1e12, "round_trip_error": err}
+        log(f"{name}: {dt * 1e3:.2f} ms per transform, {flops / dt / 1e12:.1f} TFLOP/s algorithmic, "
+            f"round-trip error {err:.2e}")
+        ks.close()
+        sysh.close()
+        del g_b, out, ref
+    f32 = results["fp32"]
+    line = {
+        "metric": "Bloch elements/s through Eq. (6) (FP32 MFMA path, coarse Bloch -> Wannier transform)",
+        "value": nk * nq * E / (f32["ms"] * 1e-3), "unit": "elems/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": f32["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": "coarse_si_nw8_nm6_re8x8x8_rp4x4x4_k8x8x8_q4x4x4", "nw": s.nw, "nm": s.nm,
+                   "ne": s.ne, "np": s.np_, "nk": nk, "nq": nq},
+        "roofline": {"bound": "mfma", "achieved": f32["tflops"], "peak": 157.3, "unit": "TFLOP/s",
+                     "frac": f32["tflops"] / 157.3, "traffic": None, "kernel": "whole transform (GEMM-dominated)"},
+        "algorithmic_flops_per_step": flops,
+        "round_trip_error_fp32": f32["round_trip_error"],
+        "fp64": results["fp64"],
+        "fp32_vs_fp64_speedup": results["fp64"]["ms"] / f32["ms"],
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main(argv=None):
     args = parse(argv)
-    if args.workload == "ribbon":
-        if args.gpus != 1:
-            print("bench.py: this build runs on one GPU", file=sys.stderr)
-            return 2
-        return bench_ribbon(args)
-    if args.workload == "batch32":
-        if args.gpus != 1:
-            print("bench.py: this build runs on one GPU", file=sys.stderr)
-            return 2
-        return bench_batch(args)
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the path shards over q across GPUs by design, see the design notes)", file=sys.stderr)
         return 2
+    if args.workload == "ribbon":
+        return bench_ribbon(args)
+    if args.workload == "batch32":
+        return bench_batch(args)
+    if args.workload == "coarse_si":
+        return bench_coarse(args)
     import torch
     from paper_2603_10295_amd import ephw, model
     if not torch.cuda.is_available():

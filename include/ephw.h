@@ -185,6 +185,23 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
                              double* band_sum, double* loss, uint64_t loss_seed, double* eps_kq,
                              double* omega, void* stream);
 
+/* Eq. (6): the coarse Bloch -> Wannier transform, the inverse of Eq. (7)
+   when the k-set and the q list are the coarse grids commensurate with the
+   Re and Rp sets (complete residue boxes, k'+q' on the k grid):
+     g(Re,Rp) = 1/(Ne Np) sum_{k',q'} e^{-2 pi i (k'.Re + q'.Rp)}
+                sum_nu [V(k'+q') g_nu(k',q') V(k')^dagger] u^-1_{nu,ka}(q')
+   with U = V^dagger as in Eq. (7), u = e/sqrt(M) the mode vectors of D(q'),
+   and no lattice-vector weights (Eq. (6) has none).
+     ks       k-set on the coarse k' grid (its eigenvectors are V(k'))
+     q        [nq][3] f64 (device): the coarse q' points
+     kq_index [nq][nk] int32 (device), required: grid index of k'_i + q'_j in the set
+     g_bloch  [nq][nk][nm][nw][nw] (device): c128 for an FP64 set, c64 for FP32,
+              in the layout ephw_interpolate stores
+     g_out    [np][ne][nm][nw][nw] (device), same element type, overwritten
+   EPHW_FP32_SPLIT sets are not supported.  Enqueued on stream. */
+ephw_status ephw_wannier_transform(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index,
+                                   const void* g_bloch, void* g_out, void* stream);
+
 /* Gauge-invariant |g|^2 of stored matrix elements (the quantity Eq. (7)'s
    results are compared by: eigenvectors of (near-)degenerate eigenvalues are
    fixed only up to a unitary mixing inside their block).  For every pair,

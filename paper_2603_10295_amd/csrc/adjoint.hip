@@ -18,6 +18,11 @@
 // first-order change of the eigenvectors (their phases held fixed; the loss
 // does not depend on them).  For k+q on the k grid, dV at the grid point
 // serves both dL/dk_i and dL/dq_j of the pair.
+//
+// The coarse Bloch -> Wannier transform of Eq. (6) runs through the same
+// back-rotations and conjugate-phase sums (it is the inverse of Eq. (7) on a
+// commensurate grid): W_nu = V(k+q) g_nu V(k)^dagger, sum_k e^{-ik.Re},
+// then u^-1 in place of conj(u), sum_q e^{-iq.Rp}, and 1/(Ne Np).
 #include <algorithm>
 
 #include "internal.h"
@@ -56,6 +61,27 @@ __global__ void eig_mid_kernel(double* __restrict__ M, const double* __restrict_
     M[2 * idx] *= f;
     M[2 * idx + 1] *= f;
   }
+}
+
+// uinvT[q][a][v] = conj(e[q][a][v]) / ism[a]: the transpose of u^-1 for
+// u = diag(ism) e with e unitary (u^-1 = e^dagger diag(1/ism))
+template <typename T>
+__global__ void mode_inverse_kernel(const double* __restrict__ e, int64_t nq, int nm, const double* __restrict__ ism,
+                                    T* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t per = (int64_t)nm * nm;
+  if (i >= nq * per) return;
+  const int a = (int)((i % per) / nm);
+  out[2 * i] = (T)(e[2 * i] / ism[a]);
+  out[2 * i + 1] = (T)(-e[2 * i + 1] / ism[a]);
+}
+
+template <typename T>
+__global__ void scale_complex_kernel(T* __restrict__ x, int64_t n, double f) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  x[2 * i] = (T)((double)x[2 * i] * f);
+  x[2 * i + 1] = (T)((double)x[2 * i + 1] * f);
 }
 
 // Complex offset of V(k+q) for each (k, q) pair of a unit:
@@ -1050,6 +1076,186 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
   hipLaunchKernelGGL(pair_sums_kernel, dim3(grid1((nk + nq) * 3, 256)), dim3(256), 0, st, pairs, nq, nk, dk_acc,
                      dq_acc);
   EPHW_CHECK_LAUNCH();
+  return EPHW_OK;
+}
+
+// Eq. (6) on the k-set (coarse k' grid) and a q' list whose k'+q' fall on it.
+ephw_status ephw_wannier_transform(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index,
+                                   const void* g_bloch, void* g_out, void* stream) {
+  if (!ks || !q || nq <= 0 || !kq_index || !g_bloch || !g_out) {
+    set_error("ephw_wannier_transform: need a k-set, a q list, a k+q index table and both buffers");
+    return EPHW_EINVAL;
+  }
+  if (ks->prec == EPHW_FP32_SPLIT) {
+    set_error("ephw_wannier_transform: FP64 or FP32 k-sets only");
+    return EPHW_EUNSUPPORTED;
+  }
+  ephw_system* s = ks->sys;
+  hipStream_t st = as_stream(stream);
+  const int kind = prec_kind(ks->prec);
+  const size_t cs = csize(kind);
+  const int64_t nw = s->nw, nm = s->nm, nw2 = nw * nw, E = nm * nw2, nk = ks->nk, ne = s->ne, np = s->np;
+  // q batch: up to 128 q (the Re sum's N = qb E) within 8 GB for the two
+  // g(Re,q) buffers; k tile within 16 GB for the two pair buffers
+  int64_t qb = s->q_batch > 0 ? s->q_batch : (int64_t)(8.0e9 / (2.0 * (double)ne * E * cs));
+  qb = std::max<int64_t>(1, std::min<int64_t>({qb, 128, nq}));
+  int64_t kt = s->k_tile > 0 ? s->k_tile : (int64_t)(16.0e9 / (2.0 * (double)cs * qb * E));
+  kt = std::max<int64_t>(1, std::min(kt, nk));
+
+  // phases as Eq. (6) writes them (no lattice-vector weights); the q ones
+  // carry 1/(Ne Np)
+  EPHW_TRY(ws_need(s, WS_CPK, (size_t)nk * ne * cs));
+  EPHW_TRY(phase_matrix(kind, ks->k, nk, s->r_e, nullptr, ne, wsp(s, WS_CPK), nullptr, st));
+  EPHW_TRY(ws_need(s, WS_PQ, (size_t)nq * np * cs));
+  EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, nullptr, np, wsp(s, WS_PQ), nullptr, st));
+  {
+    const int64_t n = nq * np;
+    const double f = 1.0 / ((double)ne * (double)np);
+    if (kind == 0)
+      hipLaunchKernelGGL(scale_complex_kernel<double>, dim3(grid1(n, 256)), dim3(256), 0, st,
+                         static_cast<double*>(wsp(s, WS_PQ)), n, f);
+    else
+      hipLaunchKernelGGL(scale_complex_kernel<float>, dim3(grid1(n, 256)), dim3(256), 0, st,
+                         static_cast<float*>(wsp(s, WS_PQ)), n, f);
+    EPHW_CHECK_LAUNCH();
+  }
+  // modes at q': D(q') eigensolve, then (u^-1)^T
+  EPHW_TRY(ws_need(s, WS_PQC, (size_t)nq * s->nc * 16));
+  EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), nullptr, st));
+  EPHW_TRY(ws_need(s, WS_LAM, (size_t)nq * nm * 8));
+  EPHW_TRY(ws_need(s, WS_E, (size_t)nq * nm * nm * 16));
+  {
+    EPHW_TRY(ws_need(s, WS_HK, (size_t)nq * nm * nm * 16));
+    GemmParams g;
+    g.M = nq;
+    g.N = nm * nm;
+    g.K = s->nc;
+    g.A = wsp(s, WS_PQC);
+    g.lda = s->nc;
+    g.B = s->c_scaled;
+    g.ldb = nm * nm;
+    g.C = wsp(s, WS_HK);
+    g.ldc = nm * nm;
+    EPHW_TRY(cgemm(0, g, st));
+    const int64_t jw = jacobi_work_doubles((int)nm, nq);
+    if (jw > 0) EPHW_TRY(ws_need(s, WS_JWORK, (size_t)jw * 8));
+    EPHW_TRY(jacobi_eigh(static_cast<const double*>(wsp(s, WS_HK)), nq, (int)nm, static_cast<double*>(wsp(s, WS_LAM)),
+                         static_cast<double*>(wsp(s, WS_E)), jw > 0 ? static_cast<double*>(wsp(s, WS_JWORK)) : nullptr,
+                         s->ctx->status, st));
+  }
+  EPHW_TRY(ws_need(s, WS_UINV, (size_t)nq * nm * nm * cs));
+  {
+    const int64_t n = nq * nm * nm;
+    const double* e = static_cast<const double*>(wsp(s, WS_E));
+    if (kind == 0)
+      hipLaunchKernelGGL(mode_inverse_kernel<double>, dim3(grid1(n, 256)), dim3(256), 0, st, e, nq, (int)nm, s->ism,
+                         static_cast<double*>(wsp(s, WS_UINV)));
+    else
+      hipLaunchKernelGGL(mode_inverse_kernel<float>, dim3(grid1(n, 256)), dim3(256), 0, st, e, nq, (int)nm, s->ism,
+                         static_cast<float*>(wsp(s, WS_UINV)));
+    EPHW_CHECK_LAUNCH();
+  }
+
+  const size_t gsz = (size_t)qb * ne * E * cs, wsz = (size_t)kt * qb * E * cs;
+  EPHW_TRY(ws_need(s, WS_GBAR, gsz));
+  EPHW_TRY(ws_need(s, WS_GNUBAR, gsz));
+  EPHW_TRY(ws_need(s, WS_T, wsz));
+  EPHW_TRY(ws_need(s, WS_WBAR, wsz));
+  EPHW_TRY(ws_need(s, WS_OFF, (size_t)kt * qb * 8));
+  char* Gbar = static_cast<char*>(wsp(s, WS_GBAR));
+  char* Gnubar = static_cast<char*>(wsp(s, WS_GNUBAR));
+  char* Tm = static_cast<char*>(wsp(s, WS_T));
+  char* Wb = static_cast<char*>(wsp(s, WS_WBAR));
+  int64_t* offp = static_cast<int64_t*>(wsp(s, WS_OFF));
+  const char* cpk = static_cast<const char*>(wsp(s, WS_CPK));
+  const char* cpq = static_cast<const char*>(wsp(s, WS_PQ));
+  const char* uinv = static_cast<const char*>(wsp(s, WS_UINV));
+  const char* gb = static_cast<const char*>(g_bloch);
+  char* vt = static_cast<char*>(ks->vt);
+
+  for (int64_t q0 = 0; q0 < nq; q0 += qb) {
+    const int64_t nb = std::min(qb, nq - q0);
+    for (int64_t k0 = 0; k0 < nk; k0 += kt) {
+      const int64_t kl = std::min(kt, nk - k0);
+      hipLaunchKernelGGL(kq_offsets_kernel, dim3(grid1(kl * nb, 256)), dim3(256), 0, st, kq_index, nk, q0, k0, (int)kl,
+                         (int)nb, nw2, offp, s->ctx->status);
+      EPHW_CHECK_LAUNCH();
+      // T'_nu = (g_nu V(k)^dagger)^T, rows (nu, n') and columns m; the input
+      // pairs are q-major ([q][k][E]), the unit's pair buffers [il][iq][E]
+      GemmParams r1 = pair_params(nw, nm, nb, kl, E);
+      r1.A = gb + ((size_t)q0 * nk + k0) * E * cs;
+      r1.strideA = E;
+      r1.strideA1 = nk * E;
+      r1.B = vt + (size_t)k0 * nw2 * cs;
+      r1.strideB = nw2;
+      r1.transB = true;
+      r1.conjB = true;
+      r1.C = Tm;
+      r1.tblock = nw;
+      r1.ldc = nw2;
+      EPHW_TRY(cgemm(kind, r1, st));
+      // W_nu = V(k+q) g_nu V(k)^dagger: rows (nu, n') of T' times V(k+q)^T, stored
+      // block-transposed into [pair][nu][m'][n']
+      GemmParams r2 = pair_params(nw, nm, nb, kl, E);
+      r2.A = Tm;
+      r2.B = vt;
+      r2.offB = offp;
+      r2.transB = true;
+      r2.C = Wb;
+      r2.tblock = nw;
+      r2.ldc = nw2;
+      EPHW_TRY(cgemm(kind, r2, st));
+      // G_nu(Re, q) (+)= sum_k e^{-ik.Re} W_nu(k, q)
+      GemmParams rk;
+      rk.M = ne;
+      rk.N = nb * E;
+      rk.K = kl;
+      rk.A = cpk + (size_t)k0 * ne * cs;
+      rk.transA = true;
+      rk.conjA = true;
+      rk.lda = ne;
+      rk.B = Wb;
+      rk.ldb = nb * E;
+      rk.C = Gnubar;
+      rk.ldc = nb * E;
+      rk.accumulate = k0 > 0;
+      EPHW_TRY(cgemm(kind, rk, st));
+    }
+    // G[q][e][ka] = sum_nu u^-1_{nu,ka}(q) G_nu[e][q]
+    GemmParams mi;
+    mi.M = nm;
+    mi.N = nw2;
+    mi.K = nm;
+    mi.batch = nb * ne;
+    mi.n2 = ne;
+    mi.A = uinv + (size_t)q0 * nm * nm * cs;
+    mi.lda = nm;
+    mi.strideA = nm * nm;
+    mi.B = Gnubar;
+    mi.ldb = nw2;
+    mi.strideB = E;
+    mi.strideB2 = nb * E;
+    mi.C = Gbar;
+    mi.ldc = nw2;
+    mi.strideC = ne * E;
+    mi.strideC2 = E;
+    EPHW_TRY(cgemm(kind, mi, st));
+    // g(Re, Rp) (+)= 1/(Ne Np) sum_q e^{-iq.Rp} G(Re, q)
+    GemmParams rq;
+    rq.M = np;
+    rq.N = ne * E;
+    rq.K = nb;
+    rq.A = cpq + (size_t)q0 * np * cs;
+    rq.transA = true;
+    rq.conjA = true;
+    rq.lda = np;
+    rq.B = Gbar;
+    rq.ldb = ne * E;
+    rq.C = g_out;
+    rq.ldc = ne * E;
+    rq.accumulate = q0 > 0;
+    EPHW_TRY(cgemm(kind, rq, st));
+  }
   return EPHW_OK;
 }
 

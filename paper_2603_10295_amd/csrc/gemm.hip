@@ -788,6 +788,14 @@ void plain_shape(int prec, int64_t M, int64_t N, int* bm, int* bn) {
   const int dm = prec == 0 ? 64 : 128, dn = prec == 0 ? 64 : 128;
   const double pad_d = (double)(ceil_div(M, dm) * dm) * (double)(ceil_div(N, dn) * dn);
   const double pad_w = (double)(ceil_div(M, 64) * 64) * (double)(ceil_div(N, 224) * 224);
+  // FP32 only: 64x64 tiles for outputs that the 128x128 tile would mostly pad
+  // (e.g. the Nw-wide band rotations of a few bands)
+  const double pad_s = (double)(ceil_div(M, 64) * 64) * (double)(ceil_div(N, 64) * 64);
+  if (prec != 0 && pad_s < 0.5 * pad_d && pad_s < 0.5 * pad_w) {
+    *bm = 64;
+    *bn = 64;
+    return;
+  }
   const bool wide = pad_w < 0.9 * pad_d;
   *bm = wide ? 64 : dm;
   *bn = wide ? 224 : dn;
@@ -909,6 +917,11 @@ ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream) {
   // the 64x224 tile addresses a whole slab from one base; very long rows
   // (e.g. g(Re,Rp) as the B operand) take the default tile instead
   bool wide = bn == 224 && (prec == 0 ? fits_any<double, 64, 224, 16, 2, 2>(p) : fits_any<float, 64, 224, 16, 2, 2>(p));
+  const bool small = prec != 0 && bm == 64 && bn == 64 && fits_any<float, 64, 64, 16, 2, 2>(p);
+  if (prec != 0 && bm == 64 && bn == 64 && !small && p.loss.on) {
+    set_error("cgemm: leading dimension too large for the 64x64 tile's 32-bit lane offsets");
+    return EPHW_EUNSUPPORTED;
+  }
   if (bn == 224 && !wide && p.loss.on) {
     // the loss partials are sized by cgemm_tiles for the wide tile
     set_error("cgemm: loss epilogue with leading dimensions too large for the 64x224 tile");
@@ -919,6 +932,7 @@ ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream) {
     return dispatch_trans<double, 64, 64, 8, 2, 2, false, 2>(p, stream);
   }
   if (wide) return dispatch_trans<float, 64, 224, 16, 2, 2, false, 2>(p, stream);
+  if (small) return dispatch_trans<float, 64, 64, 16, 2, 2, false, 4>(p, stream);
   return dispatch_trans<float, 128, 128, 16, 2, 2, false, 2>(p, stream);
 }
 

@@ -26,7 +26,7 @@ OUT_G, OUT_BAND_SUM, OUT_LOSS, OUT_WANNIER = 1, 2, 4, 8
 EXPORTS = [
     "ephw_ctx_create", "ephw_ctx_destroy", "ephw_ctx_check", "ephw_system_load",
     "ephw_system_free", "ephw_system_set_g", "ephw_system_bytes", "ephw_bands", "ephw_phonons", "ephw_phase_sum_rp",
-    "ephw_kset_create", "ephw_kset_free", "ephw_kset_bands", "ephw_interpolate", "ephw_degenerate_sums",
+    "ephw_kset_create", "ephw_kset_free", "ephw_kset_bands", "ephw_interpolate", "ephw_degenerate_sums", "ephw_wannier_transform",
     "ephw_loss_backward", "ephw_set_q_batch", "ephw_set_k_tile", "ephw_profile_enable", "ephw_profile_read", "ephw_batch_create",
     "ephw_batch_run", "ephw_batch_shape", "ephw_batch_stats", "ephw_batch_free", "ephw_status_string",
     "ephw_last_error", "ephw_version",
@@ -103,6 +103,7 @@ def lib() -> ctypes.CDLL:
         "ephw_kset_bands": [vp, vp, vp, vp],
         "ephw_interpolate": [vp, vp, i64, vp, i64, i32, u32, vp, vp, vp, u64, vp, vp, vp],
         "ephw_degenerate_sums": [i32, vp, i64, i64, i32, i32, vp, vp, vp, ctypes.c_double, vp, vp],
+        "ephw_wannier_transform": [vp, vp, i64, vp, vp, vp, vp],
         "ephw_set_q_batch": [vp, i32],
         "ephw_set_k_tile": [vp, i32],
         "ephw_loss_backward": [vp, vp, i64, vp, i64, u64, vp, vp, vp, vp, vp],
@@ -302,6 +303,13 @@ def interpolate(ks: KSet, q, *, kq_index=None, q_offset: int = 0, flags: int = O
     _check(lib().ephw_interpolate(ks.handle, _ptr(q), q.shape[0], _ptr(kq_index), int(q_offset), ks.prec,
                                   int(flags), _ptr(g_out), _ptr(band_sum), _ptr(loss), int(loss_seed),
                                   _ptr(eps_kq), _ptr(omega), _stream(stream)), "ephw_interpolate")
+
+
+def wannier_transform(ks: KSet, q, kq_index, g_bloch, g_out, stream=None):
+    """Eq. (6): g_out[Rp][Re][ka][m'][n'] from g_bloch[q][k][nu][m][n] on the
+    coarse grids (the k-set's points and q, k+q on the set's grid)."""
+    _check(lib().ephw_wannier_transform(ks.handle, _ptr(q), q.shape[0], _ptr(kq_index), _ptr(g_bloch), _ptr(g_out),
+                                        _stream(stream)), "ephw_wannier_transform")
 
 
 def degenerate_sums(prec: int, g, eps_kq, eps_k, lam, out, rel_tol: float = 1e-6, stream=None):

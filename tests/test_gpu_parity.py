@@ -371,3 +371,78 @@ def test_degenerate_sums_gauge_invariant(run, prec):
           f"(raw |g|^2 differ by {raw:.2e}: the gauge inside the blocks is free)")
     assert err < (1e-10 if prec == 0 else 1e-5)
     assert raw > 1e-6
+
+
+def grid_kq_index(kgrid, qpts, m):
+    """Index of k_i + q_j in the lexicographic m-grid kgrid (q on that grid)."""
+    m = np.asarray(m)
+    ik = np.rint(kgrid * m).astype(np.int64)
+    iq = np.rint(qpts * m).astype(np.int64)
+    s = (ik[None, :, :] + iq[:, None, :]) % m
+    return (s[..., 0] * m[1] * m[2] + s[..., 1] * m[2] + s[..., 2]).astype(np.int32)
+
+
+def coarse_setup(prec):
+    """A system whose Re / Rp boxes are complete residue systems of the coarse
+    k' (4x2x2) and q' (2x2x1) grids, q' on the k' grid, unequal masses."""
+    import dataclasses
+    ne_box, np_box = (4, 2, 2), (2, 2, 1)
+    s = synth.make_system(4, 2, synth.box(ne_box), synth.box(np_box), [61, 5], mass=np.array([1.0, 2.5]))
+    if prec == 1:
+        s = dataclasses.replace(s, g=s.g.astype(np.complex64))
+    kc = synth.uniform_grid(ne_box)
+    qc = synth.uniform_grid(np_box)
+    return s, kc, qc, grid_kq_index(kc, qc, ne_box)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_wannier_transform_matches_oracle(run, prec):
+    """Eq. (6) on random Bloch-gauge input: the GPU transform against the
+    oracle's, the oracle given the GPU's eigenvectors and mode vectors (the
+    input is gauge-dependent, so both sides must use one gauge)."""
+    import torch
+    from paper_2603_10295_amd import ephw
+    from gpu_run import dev, cplx_dtype
+    s, kc, qc, kqi = coarse_setup(prec)
+    sysh = run.system(s)
+    nk, nq = len(kc), len(qc)
+    gen = np.random.default_rng(17)
+    shape = (nq, nk, s.nm, s.nw, s.nw)
+    g_kq = (gen.standard_normal(shape) + 1j * gen.standard_normal(shape)) / np.sqrt(2)
+    if prec == 1:
+        g_kq = g_kq.astype(np.complex64)
+    ks = ephw.KSet(sysh, dev(kc), prec)
+    out = torch.empty((s.np_, s.ne, s.nm, s.nw, s.nw), dtype=cplx_dtype(prec), device="cuda:0")
+    ephw.wannier_transform(ks, dev(qc), dev(kqi), dev(g_kq), out)
+    run.ctx.check()
+    got = out.cpu().numpy()
+    ks.close()
+    _, v_k = run.bands(sysh, kc)
+    _, _, e = run.phonons(sysh, qc)
+    u = e / np.sqrt(np.repeat(s.mass, 3))[None, :, None]
+    ref = oracle.coarse_transform(g_kq.astype(np.complex128), kc, qc, v_k, v_k[kqi], u, s.r_e, s.r_p)
+    err = rel_max(got, ref)
+    print(f"Eq. (6) prec={prec}: max error {err:.2e} of the largest element")
+    assert err < (1e-12 if prec == 0 else 1e-5)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_wannier_transform_inverts_interpolation(run, prec):
+    """Eq. (6) after Eq. (7) on the commensurate coarse grids gives back
+    g(Re,Rp) (both on the GPU, one gauge throughout)."""
+    import torch
+    from paper_2603_10295_amd import ephw
+    from gpu_run import dev, cplx_dtype
+    s, kc, qc, kqi = coarse_setup(prec)
+    sysh = run.system(s)
+    nk, nq = len(kc), len(qc)
+    ks = ephw.KSet(sysh, dev(kc), prec)
+    g = torch.empty((nq, nk, s.nm, s.nw, s.nw), dtype=cplx_dtype(prec), device="cuda:0")
+    ephw.interpolate(ks, dev(qc), kq_index=dev(kqi), flags=ephw.OUT_G, g_out=g)
+    back = torch.empty((s.np_, s.ne, s.nm, s.nw, s.nw), dtype=cplx_dtype(prec), device="cuda:0")
+    ephw.wannier_transform(ks, dev(qc), dev(kqi), g, back)
+    run.ctx.check()
+    ks.close()
+    err = rel_max(back.cpu().numpy().astype(np.complex128), s.g.astype(np.complex128))
+    print(f"Eq. (6) o Eq. (7) prec={prec}: max error {err:.2e} of the largest g(Re,Rp)")
+    assert err < (1e-12 if prec == 0 else 1e-5)
