@@ -38,7 +38,7 @@ def parse(argv=None):
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="si_dense",
-                    choices=["si_dense", "mos2_2d", "si_toy", "batch32", "ribbon", "coarse_si"])
+                    choices=["si_dense", "mos2_2d", "si_toy", "batch32", "ribbon", "coarse_si", "si_window"])
     ap.add_argument("--ribbon-nk", type=int, default=256, help="k = q = i/n along the ribbon axis")
     ap.add_argument("--ribbon-nw", type=int, default=200)
     ap.add_argument("--ribbon-na", type=int, default=50)
@@ -396,6 +396,99 @@ def bench_coarse(args):
     return 0
 
 
+def bench_window(args):
+    """Energy-window prescreening on the dense-Si grids (8000 k x 8000 q, Nw 8,
+    Nm 6, Ne = Np = 1000, FP32): the window takes the lowest tenth of the
+    lowest band's energies; one step is the k-set's bands, the screen, and
+    Eq. (7) on the active k and q (g stored), against the same pass over the
+    whole grids."""
+    import torch
+    import synth
+    from paper_2603_10295_amd import ephw, model
+    w = synth.si_dense(m=args.grid)
+    s = w.system
+    nk, nq = len(w.k), len(w.q)
+    ctx = ephw.Context(0)
+    sysh = ephw.System.from_synth(ctx, s)
+    k = torch.from_numpy(w.k).to("cuda:0")
+    q = torch.from_numpy(w.q).to("cuda:0")
+    kqi = torch.from_numpy(w.kq_index).to("cuda:0")
+    ks = ephw.KSet(sysh, k, ephw.FP32)
+    eps = torch.empty((nk, s.nw), dtype=torch.float64, device="cuda:0")
+    ks.bands(eps)
+    e0 = eps[:, 0].cpu().numpy()
+    ks.close()
+    lo, hi = float(e0.min()) - 1.0, float(np.quantile(e0, 0.1))
+    k_out = torch.empty((nk, 3), dtype=torch.float64, device="cuda:0")
+    q_out = torch.empty((nq, 3), dtype=torch.float64, device="cuda:0")
+    kq_out = torch.empty((nq, nk), dtype=torch.int32, device="cuda:0")
+    mask = torch.empty((nq, nk), dtype=torch.uint8, device="cuda:0")
+    qc = min(args.q_chunk, nq)
+    out = torch.empty((qc, nk, s.nm, s.nw, s.nw), dtype=torch.complex64, device="cuda:0")
+    state = {}
+
+    def step():
+        ks_f = ephw.KSet(sysh, k, ephw.FP32)
+        nks, nqs = ephw.window_screen(ks_f, q, kqi, lo, hi, k_out, q_out, kq_out, mask)
+        ks_f.close()
+        kq2 = kq_out.reshape(-1)[:nqs * nks].reshape(nqs, nks)
+        ks2 = ephw.KSet(sysh, k_out[:nks], ephw.FP32)
+        for q0 in range(0, nqs, qc):
+            q1 = min(nqs, q0 + qc)
+            g = out.reshape(-1)[:(q1 - q0) * nks * s.nm * s.nw * s.nw].reshape(q1 - q0, nks, s.nm, s.nw, s.nw)
+            ephw.interpolate(ks2, q_out[q0:q1], kq_index=kq2[q0:q1].contiguous(), q_offset=q0, flags=ephw.OUT_G,
+                             g_out=g)
+        ks2.close()
+        state.update(nks=nks, nqs=nqs, kq2=kq2)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ctx.check()
+    nks, nqs = state["nks"], state["nqs"]
+    msk = mask.reshape(-1)[:nqs * nks].reshape(nqs, nks)
+    kept = int(msk.sum().item())
+    log(f"window [{lo:.3f}, {hi:.3f}]: {nks}/{nk} k, {nqs}/{nq} q, {kept} kept pairs; {dt * 1e3:.1f} ms per pass")
+    # parity on two active q: every active k, kept pairs only, against the oracle
+    import oracle
+    ka = k_out[:nks].cpu().numpy()
+    qa = q_out[:nqs].cpu().numpy()
+    pick = [0, nqs // 2]
+    ks2 = ephw.KSet(sysh, k_out[:nks], ephw.FP32)
+    g = torch.empty((len(pick), nks, s.nm, s.nw, s.nw), dtype=torch.complex64, device="cuda:0")
+    idx = torch.as_tensor(pick, device="cuda:0")
+    ephw.interpolate(ks2, q_out[:nqs][idx].contiguous(), kq_index=state["kq2"][idx].contiguous(), flags=ephw.OUT_G,
+                     g_out=g)
+    ctx.check()
+    ks2.close()
+    ref = oracle.interpolate(s, ka, qa[pick], return_all=True)
+    keep = msk[idx].cpu().numpy().reshape(-1).astype(bool)
+    s_gpu = oracle.block_sums(np.abs(g.cpu().numpy().astype(np.complex128)) ** 2, ref["eps_kq"], ref["eps_k"],
+                              ref["lam"])
+    s_ref = oracle.block_sums(np.abs(ref["ghat"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+    err = oracle.compare_block_sums([a for a, f in zip(s_gpu, keep) if f], [b for b, f in zip(s_ref, keep) if f])
+    log(f"kept pairs of 2 q vs oracle: normwise {err[0]:.2e}")
+    E = s.nm * s.nw * s.nw
+    line = {
+        "metric": "full-grid g(k,q) elems/s covered by the energy-window pass (FP32 MFMA path)",
+        "value": nk * nq * E / dt, "unit": "elems/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"si_dense_window_nw8_nm6_ne1000_{nk}kx{nq}q_lowest10pct_band0", "nk": nk, "nq": nq,
+                   "window": [lo, hi]},
+        "active_k": nks, "active_q": nqs, "kept_pairs": kept, "computed_pairs": nks * nqs,
+        "kept_elems_per_s": kept * E / dt,
+        "err_vs_oracle_kept_pairs": {"normwise": err[0], "max_blockwise": err[1], "sample_q": len(pick)},
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main(argv=None):
     args = parse(argv)
     if args.gpus != 1:
@@ -408,6 +501,8 @@ def main(argv=None):
         return bench_batch(args)
     if args.workload == "coarse_si":
         return bench_coarse(args)
+    if args.workload == "si_window":
+        return bench_window(args)
     import torch
     from paper_2603_10295_amd import ephw, model
     if not torch.cuda.is_available():

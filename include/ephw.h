@@ -202,6 +202,28 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
 ephw_status ephw_wannier_transform(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index,
                                    const void* g_bloch, void* g_out, void* stream);
 
+/* Energy-window prescreening (the paper skips the matrix elements of states
+   outside an energy window before interpolating).  A k point of the set is
+   active when one of its bands lies in [e_lo, e_hi], a pair (k, q) when k
+   and k+q both are, and a q point when it has an active pair.  Outputs, for
+   running Eq. (7) on the active points only (a k-set made from k_out, the q
+   list q_out, the index table kq_out):
+     k_out     [nk][3] f64 (device): the active k points, ascending set order,
+               in the first *nk_out rows
+     nk_out    host int64: number of active k points
+     q_out     [nq][3] f64 (device): the active q points (first *nq_out rows)
+     nq_out    host int64
+     kq_out    [nq][nk] int32 (device): its first nq_out*nk_out entries, row
+               r = active q, column c = active k, hold the position of k+q in
+               k_out, or 0 where k+q is outside the window
+     pair_mask [nq][nk] uint8 (device) or NULL: same layout, 1 where k+q is in
+               the window (those pairs are the ones to keep)
+   kq_index [nq][nk] int32 (device, required for nq > 0): grid index of k+q
+   in the set.  The call synchronises the stream (the counts are host values). */
+ephw_status ephw_window_screen(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index, double e_lo,
+                               double e_hi, double* k_out, int64_t* nk_out, double* q_out, int64_t* nq_out,
+                               int32_t* kq_out, uint8_t* pair_mask, void* stream);
+
 /* Gauge-invariant |g|^2 of stored matrix elements (the quantity Eq. (7)'s
    results are compared by: eigenvectors of (near-)degenerate eigenvalues are
    fixed only up to a unitary mixing inside their block).  For every pair,

@@ -75,7 +75,9 @@ enum WsSlot {
   WS_ADJ_A, WS_ADJ_B, WS_ADJ_C, WS_DPQ, WS_DE64, WS_DU, WS_VKBAR, WS_PAIRS, WS_DKACC, WS_GBAR, WS_GNUBAR, WS_T,
   WS_YBAR, WS_Z, WS_WBAR, WS_PAIRBAR, WS_OFF, WS_UBAR, WS_SPLIT, WS_SPLITB, WS_DOTPART,
   // coarse Bloch -> Wannier transform
-  WS_CPK, WS_UINV, WS_COUNT
+  WS_CPK, WS_UINV,
+  // energy-window screen
+  WS_WINDOW, WS_COUNT
 };
 
 // HIP-event brackets around the stages of a call, summed on request

@@ -27,6 +27,7 @@ EXPORTS = [
     "ephw_ctx_create", "ephw_ctx_destroy", "ephw_ctx_check", "ephw_system_load",
     "ephw_system_free", "ephw_system_set_g", "ephw_system_bytes", "ephw_bands", "ephw_phonons", "ephw_phase_sum_rp",
     "ephw_kset_create", "ephw_kset_free", "ephw_kset_bands", "ephw_interpolate", "ephw_degenerate_sums", "ephw_wannier_transform",
+    "ephw_window_screen",
     "ephw_loss_backward", "ephw_set_q_batch", "ephw_set_k_tile", "ephw_profile_enable", "ephw_profile_read", "ephw_batch_create",
     "ephw_batch_run", "ephw_batch_shape", "ephw_batch_stats", "ephw_batch_free", "ephw_status_string",
     "ephw_last_error", "ephw_version",
@@ -104,6 +105,8 @@ def lib() -> ctypes.CDLL:
         "ephw_interpolate": [vp, vp, i64, vp, i64, i32, u32, vp, vp, vp, u64, vp, vp, vp],
         "ephw_degenerate_sums": [i32, vp, i64, i64, i32, i32, vp, vp, vp, ctypes.c_double, vp, vp],
         "ephw_wannier_transform": [vp, vp, i64, vp, vp, vp, vp],
+        "ephw_window_screen": [vp, vp, i64, vp, ctypes.c_double, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_int64),
+                               vp, ctypes.POINTER(ctypes.c_int64), vp, vp, vp],
         "ephw_set_q_batch": [vp, i32],
         "ephw_set_k_tile": [vp, i32],
         "ephw_loss_backward": [vp, vp, i64, vp, i64, u64, vp, vp, vp, vp, vp],
@@ -303,6 +306,18 @@ def interpolate(ks: KSet, q, *, kq_index=None, q_offset: int = 0, flags: int = O
     _check(lib().ephw_interpolate(ks.handle, _ptr(q), q.shape[0], _ptr(kq_index), int(q_offset), ks.prec,
                                   int(flags), _ptr(g_out), _ptr(band_sum), _ptr(loss), int(loss_seed),
                                   _ptr(eps_kq), _ptr(omega), _stream(stream)), "ephw_interpolate")
+
+
+def window_screen(ks: KSet, q, kq_index, e_lo: float, e_hi: float, k_out, q_out, kq_out, pair_mask=None,
+                  stream=None):
+    """Active k and q points of an energy window (see ephw_window_screen);
+    returns (nk_active, nq_active).  Synchronises the stream."""
+    nk = ctypes.c_int64(0)
+    nq = ctypes.c_int64(0)
+    _check(lib().ephw_window_screen(ks.handle, _ptr(q), q.shape[0], _ptr(kq_index), float(e_lo), float(e_hi),
+                                    _ptr(k_out), ctypes.byref(nk), _ptr(q_out), ctypes.byref(nq), _ptr(kq_out),
+                                    _ptr(pair_mask), _stream(stream)), "ephw_window_screen")
+    return nk.value, nq.value
 
 
 def wannier_transform(ks: KSet, q, kq_index, g_bloch, g_out, stream=None):

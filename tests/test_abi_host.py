@@ -52,6 +52,7 @@ def test_null_arguments_rejected_before_any_device_call():
     assert b"NULL" in L.ephw_last_error()
     assert L.ephw_degenerate_sums(1, None, 0, 3, 3, 4, None, None, None, 1e-6, None, None) == ephw.OK
     assert L.ephw_wannier_transform(None, None, 4, None, None, None, None) == ephw.EINVAL
+    assert L.ephw_window_screen(None, None, 4, None, 0.0, 1.0, None, None, None, None, None, None, None) == ephw.EINVAL
     assert L.ephw_phonons(None, None, 3, None, None, None, None) == ephw.EINVAL
     assert L.ephw_phase_sum_rp(None, None, 3, 0, None, None) == ephw.EINVAL
     assert L.ephw_ctx_create(0, None) == ephw.EINVAL

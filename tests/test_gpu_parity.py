@@ -446,3 +446,72 @@ def test_wannier_transform_inverts_interpolation(run, prec):
     err = rel_max(back.cpu().numpy().astype(np.complex128), s.g.astype(np.complex128))
     print(f"Eq. (6) o Eq. (7) prec={prec}: max error {err:.2e} of the largest g(Re,Rp)")
     assert err < (1e-12 if prec == 0 else 1e-5)
+
+
+def gap_edge(vals, target):
+    """A value between the two sorted neighbours of target in vals (a gap)."""
+    v = np.unique(vals)
+    i = int(np.searchsorted(v, target))
+    i = min(max(i, 1), len(v) - 1)
+    return 0.5 * (v[i - 1] + v[i])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_window_screen_and_windowed_interpolation(run, prec):
+    """Energy-window prescreening: the active k, q and pairs equal the sets
+    the oracle's eigenvalues define (window edges in gaps of the spectrum, so
+    rounding cannot move a point across them; integer results compared
+    exactly), and Eq. (7) on the compacted sets equals the oracle's g on the
+    kept pairs (degenerate-block sums)."""
+    import dataclasses
+    import torch
+    from paper_2603_10295_amd import ephw
+    from gpu_run import dev, cplx_dtype
+    m = (4, 4, 2)
+    s = synth.make_system(6, 2, synth.box((3, 3, 2)), synth.box((2, 2, 2)), [71, 2])
+    if prec == 1:
+        s = dataclasses.replace(s, g=s.g.astype(np.complex64))
+    kg = synth.uniform_grid(m)
+    qg = kg.copy()
+    kqi = synth.grid_index_of_sum(m)
+    nk, nq = len(kg), len(qg)
+    eps, _ = oracle.bands(s, kg)
+    lo = float(eps.min()) - 1.0
+    hi = gap_edge(eps, np.quantile(eps[:, 0], 0.4))
+    kact = np.any((eps >= lo) & (eps <= hi), axis=1)
+    pair = kact[None, :] & kact[kqi]
+    qact = pair.any(axis=1)
+    assert 0 < kact.sum() < nk and 0 < qact.sum()
+
+    sysh = run.system(s)
+    ks = ephw.KSet(sysh, dev(kg), prec)
+    k_out = torch.empty((nk, 3), dtype=torch.float64, device="cuda:0")
+    q_out = torch.empty((nq, 3), dtype=torch.float64, device="cuda:0")
+    kq_out = torch.empty((nq, nk), dtype=torch.int32, device="cuda:0")
+    mask = torch.empty((nq, nk), dtype=torch.uint8, device="cuda:0")
+    nks, nqs = ephw.window_screen(ks, dev(qg), dev(kqi), lo, hi, k_out, q_out, kq_out, mask)
+    run.ctx.check()
+    ks.close()
+    assert (nks, nqs) == (int(kact.sum()), int(qact.sum()))
+    ka, qa = np.flatnonzero(kact), np.flatnonzero(qact)
+    np.testing.assert_array_equal(k_out.cpu().numpy()[:nks], kg[ka])
+    np.testing.assert_array_equal(q_out.cpu().numpy()[:nqs], qg[qa])
+    msk = mask.cpu().numpy().reshape(-1)[:nqs * nks].reshape(nqs, nks).astype(bool)
+    np.testing.assert_array_equal(msk, pair[np.ix_(qa, ka)])
+    kq2 = kq_out.reshape(-1)[:nqs * nks].reshape(nqs, nks).contiguous()
+    pos = kq2.cpu().numpy()
+    np.testing.assert_array_equal(ka[pos][msk], kqi[np.ix_(qa, ka)][msk])   # k+q found in the compacted list
+
+    ks2 = ephw.KSet(sysh, k_out[:nks].contiguous(), prec)
+    g2 = torch.empty((nqs, nks, s.nm, s.nw, s.nw), dtype=cplx_dtype(prec), device="cuda:0")
+    ephw.interpolate(ks2, q_out[:nqs].contiguous(), kq_index=kq2, flags=ephw.OUT_G, g_out=g2)
+    run.ctx.check()
+    ks2.close()
+    ref = oracle.interpolate(s, kg[ka], qg[qa], return_all=True)
+    g2 = g2.cpu().numpy().astype(np.complex128)
+    s_gpu = oracle.block_sums(np.abs(g2) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+    s_ref = oracle.block_sums(np.abs(ref["ghat"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+    keep = msk.reshape(-1)
+    norm, _ = oracle.compare_block_sums([x for x, k_ in zip(s_gpu, keep) if k_], [x for x, k_ in zip(s_ref, keep) if k_])
+    print(f"window prec={prec}: {nks}/{nk} k, {nqs}/{nq} q, {int(msk.sum())} kept pairs; block sums {norm:.2e}")
+    assert norm < (RTOL_S if prec == 0 else 1e-5)
