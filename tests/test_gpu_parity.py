@@ -515,3 +515,71 @@ def test_window_screen_and_windowed_interpolation(run, prec):
     norm, _ = oracle.compare_block_sums([x for x, k_ in zip(s_gpu, keep) if k_], [x for x, k_ in zip(s_ref, keep) if k_])
     print(f"window prec={prec}: {nks}/{nk} k, {nqs}/{nq} q, {int(msk.sum())} kept pairs; block sums {norm:.2e}")
     assert norm < (RTOL_S if prec == 0 else 1e-5)
+
+
+def test_window_screen_empty_and_full(run):
+    """A window below every band keeps nothing; one around every band keeps
+    all k, all q and every pair, with the k+q table unchanged."""
+    import torch
+    from paper_2603_10295_amd import ephw
+    from gpu_run import dev
+    m = (3, 2, 2)
+    s = synth.make_system(4, 1, synth.box((3, 2, 2)), synth.box((2, 1, 1)), [73, 1])
+    kg = synth.uniform_grid(m)
+    kqi = synth.grid_index_of_sum(m)
+    nk = nq = len(kg)
+    eps, _ = oracle.bands(s, kg)
+    sysh = run.system(s)
+    ks = ephw.KSet(sysh, dev(kg), 0)
+    k_out = torch.empty((nk, 3), dtype=torch.float64, device="cuda:0")
+    q_out = torch.empty((nq, 3), dtype=torch.float64, device="cuda:0")
+    kq_out = torch.empty((nq, nk), dtype=torch.int32, device="cuda:0")
+    mask = torch.empty((nq, nk), dtype=torch.uint8, device="cuda:0")
+    lo = float(eps.min()) - 10.0
+    assert ephw.window_screen(ks, dev(kg), dev(kqi), lo, lo + 1.0, k_out, q_out, kq_out, mask) == (0, 0)
+    hi = float(eps.max()) + 10.0
+    assert ephw.window_screen(ks, dev(kg), dev(kqi), lo, hi, k_out, q_out, kq_out, mask) == (nk, nq)
+    run.ctx.check()
+    ks.close()
+    np.testing.assert_array_equal(k_out.cpu().numpy(), kg)
+    np.testing.assert_array_equal(kq_out.cpu().numpy(), kqi)
+    assert mask.cpu().numpy().all()
+
+
+def test_degenerate_sums_and_wannier_transform_beyond_32_bands(run):
+    """Nw = 34 (the band rotations run as pair-stacked GEMMs there): the
+    degenerate-block sums against the oracle's, and Eq. (6) o Eq. (7) = 1."""
+    import torch
+    from paper_2603_10295_amd import ephw
+    from gpu_run import dev
+    ne_box, np_box = (2, 2, 1), (2, 1, 1)
+    s = synth.make_system(34, 1, synth.box(ne_box), synth.box(np_box), [79, 4])
+    kc, qc = synth.uniform_grid(ne_box), synth.uniform_grid(np_box)
+    kqi = grid_kq_index(kc, qc, ne_box)
+    sysh = run.system(s)
+    ks = ephw.KSet(sysh, dev(kc), 0)
+    nk, nq = len(kc), len(qc)
+    g = torch.empty((nq, nk, s.nm, s.nw, s.nw), dtype=torch.complex128, device="cuda:0")
+    ekq = torch.empty((nq, nk, s.nw), dtype=torch.float64, device="cuda:0")
+    ephw.interpolate(ks, dev(qc), kq_index=dev(kqi), flags=ephw.OUT_G, g_out=g, eps_kq=ekq)
+    eps_k = torch.empty((nk, s.nw), dtype=torch.float64, device="cuda:0")
+    ks.bands(eps_k)
+    lam = dev(run.phonons(sysh, qc)[0])
+    d = torch.empty(g.shape, dtype=torch.float64, device="cuda:0")
+    ephw.degenerate_sums(0, g, ekq, eps_k, lam, d)
+    back = torch.empty(s.g.shape, dtype=torch.complex128, device="cuda:0")
+    ephw.wannier_transform(ks, dev(qc), dev(kqi), g, back)
+    run.ctx.check()
+    ks.close()
+    assert rel_max(back.cpu().numpy(), s.g) < 1e-12
+    ref = oracle.interpolate(s, kc, qc, return_all=True)
+    sums = oracle.block_sums(np.abs(ref["ghat"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+    d = d.cpu().numpy()
+    i = 0
+    for iq in range(nq):
+        bv = block_index(oracle.degenerate_blocks(ref["lam"][iq]), s.nm)
+        for ik in range(nk):
+            bm = block_index(oracle.degenerate_blocks(ref["eps_kq"][iq, ik]), s.nw)
+            bn = block_index(oracle.degenerate_blocks(ref["eps_k"][ik]), s.nw)
+            assert rel_max(d[iq, ik], sums[i][np.ix_(bv, bm, bn)]) < 1e-10
+            i += 1
