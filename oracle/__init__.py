@@ -25,4 +25,5 @@ from .core import (  # noqa: F401
     g_re_q, wannier_gauge_pairs, interpolate, interpolate_single_loop,
     coarse_transform, degenerate_blocks, block_sums, band_sums,
     splitmix64_weights, weighted_loss, compare_block_sums,
+    bose, fermi, gauss, linewidth,
 )

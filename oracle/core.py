@@ -279,3 +279,51 @@ def weighted_loss(ghat: np.ndarray, seed: int, iq: np.ndarray, ik: np.ndarray, n
     nm, nw = ghat.shape[1], ghat.shape[2]
     w = splitmix64_weights(seed, element_index(iq, ik, nk, nm, nw))
     return float(np.sum(w * np.abs(ghat) ** 2))
+
+
+# ---------------------------------------------------------------------------
+# Downstream reduction: phonon-limited electron linewidth (not printed in the
+# paper, which runs an electron self-energy on the interpolated g; this is the
+# textbook imaginary part of the Fan-Migdal self-energy with Gaussian
+# broadening, the reading recorded in the design notes)
+# ---------------------------------------------------------------------------
+
+def bose(omega: np.ndarray, temp: float) -> np.ndarray:
+    """Bose-Einstein occupation 1 / (exp(omega / T) - 1)."""
+    return 1.0 / np.expm1(np.asarray(omega, dtype=np.float64) / temp)
+
+
+def fermi(eps: np.ndarray, mu: float, temp: float) -> np.ndarray:
+    """Fermi-Dirac occupation 1 / (exp((eps - mu) / T) + 1), written as
+    (1 - tanh((eps - mu) / 2T)) / 2 so that it cannot overflow."""
+    return 0.5 * (1.0 - np.tanh(0.5 * (np.asarray(eps, dtype=np.float64) - mu) / temp))
+
+
+def gauss(x: np.ndarray, sigma: float) -> np.ndarray:
+    """Normalised Gaussian exp(-x^2 / (2 sigma^2)) / (sigma sqrt(2 pi))."""
+    return np.exp(-0.5 * (np.asarray(x) / sigma) ** 2) / (sigma * np.sqrt(2.0 * np.pi))
+
+
+def linewidth(ghat: np.ndarray, eps_k: np.ndarray, eps_kq: np.ndarray, omega: np.ndarray, temp: float,
+              mu: float, sigma: float, omega_min: float, nq_total: int) -> np.ndarray:
+    """Gamma[k][n] = (pi / Nq) sum over q, m and modes nu with omega >= omega_min of
+    |g_mn nu(k,q)|^2 / (2 omega) * [ (N + f_m) delta(e_n - e_m + omega)
+                                  + (N + 1 - f_m) delta(e_n - e_m - omega) ],
+    N = bose(omega), f_m = fermi(e_m(k+q)), e_n = eps_k[k][n]: phonon absorption
+    and emission by the state n at k into the states m at k+q.  The 1/(2 omega)
+    supplies the zero-point amplitude that the mode vectors u = e/sqrt(M) of
+    Eq. (2) leave out.  ghat [Nq][Nk][Nm][Nw][Nw] (nu, m, n); returns [Nk][Nw]."""
+    om = np.asarray(omega, dtype=np.float64)                          # [q][nu]
+    keep = om >= omega_min
+    om_safe = np.where(keep, om, 1.0)
+    n_b = np.where(keep, bose(om_safe, temp), 0.0)
+    amp = np.where(keep, 1.0 / (2.0 * om_safe), 0.0)
+    f_m = fermi(eps_kq, mu, temp)                                     # [q][k][m]
+    g2 = np.abs(ghat) ** 2                                            # [q][k][nu][m][n]
+    de = eps_k[None, :, None, :] - eps_kq[:, :, :, None]              # [q][k][m][n] = e_n - e_m
+    absorb = (n_b[:, None, :, None, None] + f_m[:, :, None, :, None]) * \
+        gauss(de[:, :, None, :, :] + om[:, None, :, None, None], sigma)
+    emit = (n_b[:, None, :, None, None] + 1.0 - f_m[:, :, None, :, None]) * \
+        gauss(de[:, :, None, :, :] - om[:, None, :, None, None], sigma)
+    w = amp[:, None, :, None, None] * (absorb + emit)                 # [q][k][nu][m][n]
+    return np.pi / nq_total * np.einsum("qkvmn,qkvmn->kn", g2, w)

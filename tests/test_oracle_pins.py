@@ -283,3 +283,109 @@ def test_element_index_layout():
     idx = element_index(np.array([2]), np.array([3]), nk=5, nm=4, nw=3)
     assert idx.shape == (1, 4, 3, 3)
     assert int(idx[0, 1, 2, 0]) == ((((2 * 5 + 3) * 4 + 1) * 3 + 2) * 3 + 0)
+
+
+# --------------------------------------------------------------------------
+# Downstream reduction (linewidth): components against library routines and
+# closed forms, the reduction through a sum rule and its invariances
+# --------------------------------------------------------------------------
+
+def test_linewidth_components():
+    from scipy import integrate, special
+    sigma = 0.037
+    norm = integrate.quad(lambda x: oracle.gauss(x, sigma), -1, 1, points=[0.0])[0]
+    var = integrate.quad(lambda x: x * x * oracle.gauss(x, sigma), -1, 1, points=[0.0])[0]
+    assert abs(norm - 1.0) < 1e-12 and abs(var - sigma ** 2) < 1e-12
+    e = np.linspace(-1.0, 1.0, 41)
+    np.testing.assert_allclose(oracle.fermi(e, 0.2, 0.05), special.expit(-(e - 0.2) / 0.05), rtol=1e-14)
+    t = 0.025
+    assert abs(oracle.bose(t * np.log(2.0), t) - 1.0) < 1e-14                # e^{w/T} = 2
+    w = np.linspace(0.01, 0.2, 9)
+    np.testing.assert_allclose(oracle.bose(w, t) + 1.0, oracle.bose(w, t) * np.exp(w / t), rtol=1e-12)
+
+
+def _linewidth_case(seed, nq=2, nk=3, nm=3, nw=4):
+    gen = np.random.default_rng(seed)
+    g = gen.standard_normal((nq, nk, nm, nw, nw)) + 1j * gen.standard_normal((nq, nk, nm, nw, nw))
+    eps_k = np.sort(gen.uniform(-0.5, 0.5, (nk, nw)), axis=1)
+    eps_kq = np.sort(gen.uniform(-0.5, 0.5, (nq, nk, nw)), axis=2)
+    omega = gen.uniform(0.02, 0.08, (nq, nm))
+    return g, eps_k, eps_kq, omega
+
+
+def test_linewidth_sum_rule_over_the_initial_energy():
+    """Integrating Gamma over the energy of the initial state turns both
+    Gaussians into 1, so the occupations add to N + f + N + 1 - f = 2N + 1
+    whatever the electron occupations are."""
+    from scipy import integrate
+    g, eps_k, eps_kq, omega = _linewidth_case(5, nk=1)
+    temp, mu, sigma = 0.03, 0.1, 0.02
+
+    def gamma_at(e):
+        ek = eps_k.copy()
+        ek[0, 0] = e
+        return oracle.linewidth(g, ek, eps_kq, omega, temp, mu, sigma, 0.0, 7)[0, 0]
+
+    peaks = np.sort(np.concatenate([(eps_kq[:, 0, :, None] + s * omega[:, None, :]).reshape(-1)
+                                    for s in (-1.0, 1.0)]))
+    total = integrate.quad(gamma_at, -2.0, 2.0, points=peaks, limit=400)[0]
+    n_b = oracle.bose(omega, temp)                                      # [q][nu]
+    expect = np.pi / 7 * np.sum(np.abs(g[:, 0, :, :, 0]) ** 2 * ((2.0 * n_b + 1.0) / (2.0 * omega))[:, :, None])
+    assert abs(total - expect) < 1e-9 * abs(expect)
+
+
+def test_linewidth_invariances():
+    """Unchanged by a unitary mixing of exactly degenerate final states (m)
+    or of modes of equal frequency; linear in |g|^2; additive over q; a mode
+    below omega_min contributes nothing."""
+    g, eps_k, eps_kq, omega = _linewidth_case(9)
+    args = (0.03, 0.05, 0.04, 0.0, 11)
+    base = oracle.linewidth(g, eps_k, eps_kq, omega, *args)
+    # degenerate m block {1, 2} at every (q, k): rotate g's m index inside it
+    ekq = eps_kq.copy()
+    ekq[..., 2] = ekq[..., 1]
+    ref = oracle.linewidth(g, eps_k, ekq, omega, *args)
+    th = 0.7
+    rot = np.array([[np.cos(th), np.sin(th) * np.exp(0.3j)], [-np.sin(th) * np.exp(-0.3j), np.cos(th)]])
+    g2 = g.copy()
+    g2[:, :, :, 1:3, :] = np.einsum("ab,qkvbn->qkvan", rot, g[:, :, :, 1:3, :])
+    np.testing.assert_allclose(oracle.linewidth(g2, eps_k, ekq, omega, *args), ref, rtol=1e-12)
+    # modes 0 and 1 of equal frequency: rotate g's nu index inside them
+    om = omega.copy()
+    om[:, 1] = om[:, 0]
+    ref = oracle.linewidth(g, eps_k, eps_kq, om, *args)
+    g3 = g.copy()
+    g3[:, :, 0:2] = np.einsum("ab,qkbmn->qkamn", rot, g[:, :, 0:2])
+    np.testing.assert_allclose(oracle.linewidth(g3, eps_k, eps_kq, om, *args), ref, rtol=1e-12)
+    # linear in |g|^2, additive over q
+    np.testing.assert_allclose(oracle.linewidth(2.0 * g, eps_k, eps_kq, omega, *args), 4.0 * base, rtol=1e-13)
+    parts = sum(oracle.linewidth(g[i:i + 1], eps_k, eps_kq[i:i + 1], omega[i:i + 1], *args) for i in range(len(g)))
+    np.testing.assert_allclose(parts, base, rtol=1e-13)
+    # omega_min removes mode 2 entirely: same as zeroing its g
+    cut = omega[:, 2].max() + 1e-3
+    om2 = omega.copy()
+    om2[:, 2] = 0.5 * cut
+    om2[:, :2] = np.maximum(om2[:, :2], cut)
+    g4 = g.copy()
+    g4[:, :, 2] = 0.0
+    np.testing.assert_allclose(oracle.linewidth(g, eps_k, eps_kq, om2, 0.03, 0.05, 0.04, cut, 11),
+                               oracle.linewidth(g4, eps_k, eps_kq, om2, 0.03, 0.05, 0.04, cut, 11), rtol=1e-13)
+
+
+def test_linewidth_zero_temperature_empty_final_states():
+    """At T -> 0 with every final state empty (mu far below), no phonon can be
+    absorbed and emission needs e_n = e_m + omega: Gamma vanishes for an
+    initial state below every e_m + omega and is positive on a resonance."""
+    g, eps_k, eps_kq, omega = _linewidth_case(13, nq=1, nk=1, nm=2, nw=3)
+    temp, mu, sigma = 1e-4, -50.0, 0.002
+    floor = float((eps_kq[0, 0, :, None] + omega[0][None, :]).min())
+    ek = eps_k.copy()
+    ek[0, 0] = floor - 20 * sigma
+    ek[0, 1] = float(eps_kq[0, 0, 1] + omega[0, 0])                     # emission resonance
+    ek[0, 2] = float(eps_kq[0, 0, 1] - omega[0, 0])                     # absorption resonance
+    gam = oracle.linewidth(g, ek, eps_kq, omega, temp, mu, sigma, 0.0, 1)[0]
+    assert gam[0] < 1e-30
+    assert gam[1] > 1.0
+    off = ek[0, 2] - (eps_kq[0, 0, :, None] + omega[0][None, :])       # distance to every emission resonance
+    if np.abs(off).min() > 20 * sigma:
+        assert gam[2] < 1e-30
