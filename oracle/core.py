@@ -294,9 +294,12 @@ def bose(omega: np.ndarray, temp: float) -> np.ndarray:
 
 
 def fermi(eps: np.ndarray, mu: float, temp: float) -> np.ndarray:
-    """Fermi-Dirac occupation 1 / (exp((eps - mu) / T) + 1), written as
-    (1 - tanh((eps - mu) / 2T)) / 2 so that it cannot overflow."""
-    return 0.5 * (1.0 - np.tanh(0.5 * (np.asarray(eps, dtype=np.float64) - mu) / temp))
+    """Fermi-Dirac occupation 1 / (exp(x) + 1), x = (eps - mu) / T, evaluated
+    as exp(-x) / (1 + exp(-x)) for x > 0 so that it neither overflows nor
+    loses its relative precision in the tail."""
+    x = (np.asarray(eps, dtype=np.float64) - mu) / temp
+    e = np.exp(-np.abs(x))
+    return np.where(x > 0, e / (1.0 + e), 1.0 / (1.0 + e))
 
 
 def gauss(x: np.ndarray, sigma: float) -> np.ndarray:
