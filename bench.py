@@ -38,7 +38,7 @@ def parse(argv=None):
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="si_dense",
-                    choices=["si_dense", "mos2_2d", "si_toy", "batch32", "ribbon", "coarse_si", "si_window"])
+                    choices=["si_dense", "mos2_2d", "si_toy", "batch32", "ribbon", "coarse_si", "si_window", "si_linewidth"])
     ap.add_argument("--ribbon-nk", type=int, default=256, help="k = q = i/n along the ribbon axis")
     ap.add_argument("--ribbon-nw", type=int, default=200)
     ap.add_argument("--ribbon-na", type=int, default=50)
@@ -489,6 +489,86 @@ def bench_window(args):
     return 0
 
 
+def bench_linewidth(args):
+    """The downstream reduction on the dense-Si grids (8000 k x 8000 q, FP32):
+    per q chunk, Eq. (7) stores g and the linewidth kernel reduces it over q
+    into gamma[k][n]; the reduction's own time is bracketed by HIP events."""
+    import torch
+    import synth
+    from paper_2603_10295_amd import ephw
+    w = synth.si_dense(m=args.grid)
+    s = w.system
+    nk, nq = len(w.k), len(w.q)
+    ctx = ephw.Context(0)
+    sysh = ephw.System.from_synth(ctx, s)
+    k = torch.from_numpy(w.k).to("cuda:0")
+    q = torch.from_numpy(w.q).to("cuda:0")
+    kqi = torch.from_numpy(w.kq_index).to("cuda:0")
+    qc = min(args.q_chunk, nq)
+    g = torch.empty((qc, nk, s.nm, s.nw, s.nw), dtype=torch.complex64, device="cuda:0")
+    ekq = torch.empty((qc, nk, s.nw), dtype=torch.float64, device="cuda:0")
+    om = torch.empty((qc, s.nm), dtype=torch.float64, device="cuda:0")
+    eps_k = torch.empty((nk, s.nw), dtype=torch.float64, device="cuda:0")
+    gamma = torch.zeros((nk, s.nw), dtype=torch.float64, device="cuda:0")
+    ks0 = ephw.KSet(sysh, k, ephw.FP32)
+    ks0.bands(eps_k)
+    e = eps_k.cpu().numpy()
+    ks0.close()
+    temp, mu, sigma = 0.02 * float(np.ptp(e)), float(np.median(e)), 0.01 * float(np.ptp(e))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    lw_ms = []
+
+    def step():
+        gamma.zero_()
+        ks = ephw.KSet(sysh, k, ephw.FP32)
+        ks.bands(eps_k)
+        t = 0.0
+        for q0 in range(0, nq, qc):
+            q1 = min(nq, q0 + qc)
+            b = q1 - q0
+            ephw.interpolate(ks, q[q0:q1], kq_index=kqi[q0:q1], q_offset=q0, flags=ephw.OUT_G, g_out=g[:b],
+                             eps_kq=ekq[:b], omega=om[:b])
+            ev[0].record()
+            ephw.linewidth(ephw.FP32, g[:b], eps_k, ekq[:b], om[:b], gamma, temperature=temp, mu=mu, sigma=sigma,
+                           nq_total=nq)
+            ev[1].record()
+            ev[1].synchronize()
+            t += ev[0].elapsed_time(ev[1])
+        ks.close()
+        lw_ms.append(t)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    lw_ms.clear()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ctx.check()
+    lw = sum(lw_ms) / len(lw_ms)
+    E = s.nm * s.nw * s.nw
+    elems = nk * nq * E
+    log(f"pass {dt * 1e3:.1f} ms, of which the linewidth reduction {lw:.1f} ms "
+        f"({elems * 8 / (lw * 1e-3) / 1e9:.0f} GB/s of g read)")
+    line = {
+        "metric": "g(k,q) elems/s reduced into linewidths (FP32 MFMA interpolation + FP64-weighted reduction)",
+        "value": elems / dt, "unit": "elems/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"si_dense_linewidth_nw8_nm6_ne1000_{nk}kx{nq}q", "nk": nk, "nq": nq,
+                   "temperature": temp, "mu": mu, "sigma": sigma},
+        "linewidth_ms_per_step": lw,
+        "roofline": {"bound": "hbm", "achieved": elems * 8 / (lw * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                     "frac": elems * 8 / (lw * 1e-3) / 1e9 / 8000.0, "traffic": None,
+                     "kernel": "linewidth_kernel<float> (g read once)"},
+        "gamma_norm": float(torch.linalg.vector_norm(gamma).cpu()),
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def main(argv=None):
     args = parse(argv)
     if args.gpus != 1:
@@ -503,6 +583,8 @@ def main(argv=None):
         return bench_coarse(args)
     if args.workload == "si_window":
         return bench_window(args)
+    if args.workload == "si_linewidth":
+        return bench_linewidth(args)
     import torch
     from paper_2603_10295_amd import ephw, model
     if not torch.cuda.is_available():

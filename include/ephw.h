@@ -224,6 +224,28 @@ ephw_status ephw_window_screen(ephw_kset* ks, const double* q, int64_t nq, const
                                double e_hi, double* k_out, int64_t* nk_out, double* q_out, int64_t* nq_out,
                                int32_t* kq_out, uint8_t* pair_mask, void* stream);
 
+/* A downstream reduction of stored matrix elements over q (the paper's MoS2
+   run computes an electron self-energy from the interpolated g): the
+   phonon-limited linewidth, the imaginary part of the Fan-Migdal self-energy
+   with Gaussian broadening,
+     gamma[k][n] += pi / nq_total * sum over q, modes nu with omega >= omega_min, bands m of
+        |g_{mn nu}(k,q)|^2 / (2 omega) * [ (N + f_m) G(e_n - e_m + omega) + (N + 1 - f_m) G(e_n - e_m - omega) ]
+   with e_n = eps_k[k][n], e_m = eps_kq[q][k][m], omega = omega[q][nu],
+   N = 1/(exp(omega/T) - 1), f_m = 1/(exp((e_m - mu)/T) + 1) and
+   G(x) = exp(-x^2 / (2 sigma^2)) / (sigma sqrt(2 pi)).  The 1/(2 omega) is the
+   zero-point amplitude that the mode vectors e/sqrt(M) of Eq. (2) leave out.
+   Calls on successive q chunks accumulate; nq_total is the full q count.
+     prec    EPHW_FP64: g c128; EPHW_FP32 / EPHW_FP32_SPLIT: g c64
+     g       [nq][nk][nm][nw][nw] (device), as ephw_interpolate stores it
+     eps_k [nk][nw], eps_kq [nq][nk][nw], omega [nq][nm]: f64 (device)
+     gamma   [nk][nw] f64 (device), accumulated (+=), caller-owned
+   temperature, sigma > 0 (energy units of eps); omega_min >= 0 drops soft modes.
+   Deterministic: every sum runs in a fixed order. */
+ephw_status ephw_linewidth(int32_t prec, const void* g, int64_t nq, int64_t nk, int32_t nm, int32_t nw,
+                           const double* eps_k, const double* eps_kq, const double* omega, double temperature,
+                           double mu, double sigma, double omega_min, int64_t nq_total, double* gamma,
+                           void* stream);
+
 /* Gauge-invariant |g|^2 of stored matrix elements (the quantity Eq. (7)'s
    results are compared by: eigenvectors of (near-)degenerate eigenvalues are
    fixed only up to a unitary mixing inside their block).  For every pair,

@@ -1,6 +1,8 @@
 // Host side of the libephw C ABI: validation, ownership, workspaces and the
 // sequencing of the interpolation (Eqs. (7), (9), (10)) on a HIP stream.
 #include <math.h>
+
+#include <cmath>
 #include <string.h>
 
 #include <map>
@@ -732,6 +734,29 @@ ephw_status ephw_degenerate_sums(int32_t prec, const void* g, int64_t nq, int64_
   }
   return degenerate_sums(prec == EPHW_FP64 ? 0 : 1, g, nq, nk, nm, nw, eps_kq, eps_k, lam, rel_tol, out,
                          as_stream(stream));
+}
+
+ephw_status ephw_linewidth(int32_t prec, const void* g, int64_t nq, int64_t nk, int32_t nm, int32_t nw,
+                           const double* eps_k, const double* eps_kq, const double* omega, double temperature,
+                           double mu, double sigma, double omega_min, int64_t nq_total, double* gamma,
+                           void* stream) {
+  if (prec != EPHW_FP64 && prec != EPHW_FP32 && prec != EPHW_FP32_SPLIT) {
+    set_error("ephw_linewidth: unknown precision");
+    return EPHW_EINVAL;
+  }
+  if (nq < 0 || nk < 0 || nw < 1 || nw > 256 || nm < 1 || nm > 258 || nq_total < 1 || !(temperature > 0.0) ||
+      !(sigma > 0.0) || !(omega_min >= 0.0) || !std::isfinite(mu) || !std::isfinite(temperature) ||
+      !std::isfinite(sigma) || !std::isfinite(omega_min)) {
+    set_error("ephw_linewidth: sizes or parameters out of range");
+    return EPHW_EINVAL;
+  }
+  if (nq * nk == 0) return EPHW_OK;
+  if (!g || !eps_k || !eps_kq || !omega || !gamma) {
+    set_error("ephw_linewidth: a buffer is NULL");
+    return EPHW_EINVAL;
+  }
+  return linewidth(prec == EPHW_FP64 ? 0 : 1, g, nq, nk, nm, nw, eps_k, eps_kq, omega, temperature, mu, sigma,
+                   omega_min, nq_total, gamma, as_stream(stream));
 }
 
 }  // extern "C"

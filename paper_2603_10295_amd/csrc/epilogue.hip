@@ -9,6 +9,9 @@
 //
 // One 64-lane wavefront per pair: the lanes first find each index's block
 // bounds (kept in LDS), then sum |g|^2 over the block of each element.
+//
+// The same file holds a downstream reduction of |g|^2 over q, the
+// phonon-limited linewidth of each state (below).
 #include "kernels.h"
 
 namespace ephw {
@@ -74,7 +77,164 @@ __global__ void __launch_bounds__(64 * kDegWaves)
   }
 }
 
+// Phonon-limited linewidth of the states n at k (imaginary part of the
+// Fan-Migdal self-energy, Gaussian broadening):
+//   gamma[k][n] += scale * sum over q, nu (omega >= omega_min), m of
+//     |g_mn nu|^2 / (2 omega) [ (N + f_m) G(e_n - e_m + omega) + (N + 1 - f_m) G(e_n - e_m - omega) ]
+// N Bose, f_m Fermi at e_m(k+q), G a normalised Gaussian of width sigma.
+// One workgroup per k; for Nw > 32 thread (row group rg, band n) sums column
+// n over the rows (q, nu, m) rg, rg + G, ..., then the row groups are added
+// in order.
+constexpr int kLwThreads = 256;
+
+struct LwParams {
+  double inv_t, mu, inv_sigma, gnorm, omega_min, scale;
+};
+
+__device__ __forceinline__ double fermi_occ(double e, const LwParams& p) {
+  const double x = (e - p.mu) * p.inv_t;
+  const double z = exp(-fabs(x));
+  return x > 0.0 ? z / (1.0 + z) : 1.0 / (1.0 + z);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kLwThreads)
+    linewidth_kernel(const T* __restrict__ g, int64_t nq, int64_t nk, int nm, int nw,
+                     const double* __restrict__ eps_k, const double* __restrict__ eps_kq,
+                     const double* __restrict__ omega, LwParams p, double* __restrict__ gamma) {
+  __shared__ double red[kLwThreads];
+  const int64_t ik = blockIdx.x;
+  const int groups = kLwThreads / nw > 0 ? kLwThreads / nw : 1;
+  const int tid = threadIdx.x, rg = tid / nw, n = tid % nw;
+  const bool act = rg < groups;
+  double acc = 0.0;
+  if (act) {
+    const double en = eps_k[ik * nw + n];
+    const int64_t rows = nq * nm * nw;   // (q, nu, m)
+    for (int64_t r = rg; r < rows; r += groups) {
+      const int64_t iq = r / ((int64_t)nm * nw);
+      const int rem = (int)(r - iq * nm * nw), nu = rem / nw, m = rem - nu * nw;
+      const double om = omega[iq * nm + nu];
+      if (om < p.omega_min) continue;
+      const double em = eps_kq[(iq * nk + ik) * nw + m];
+      const double nb = 1.0 / expm1(om * p.inv_t);
+      const double fm = fermi_occ(em, p);
+      const double a = (en - em + om) * p.inv_sigma, b = (en - em - om) * p.inv_sigma;
+      const double w = ((nb + fm) * exp(-0.5 * a * a) + (nb + 1.0 - fm) * exp(-0.5 * b * b)) * p.gnorm / (2.0 * om);
+      const int64_t i = ((iq * nk + ik) * nm + nu) * (int64_t)nw * nw + (int64_t)m * nw + n;
+      const double x = (double)g[2 * i], y = (double)g[2 * i + 1];
+      acc += w * (x * x + y * y);
+    }
+  }
+  red[tid] = act ? acc : 0.0;
+  __syncthreads();
+  if (tid < nw) {
+    double s = 0.0;
+    for (int j = 0; j < groups; ++j) s += red[j * nw + tid];
+    gamma[ik * nw + tid] += p.scale * s;
+  }
+}
+
+// Nw <= 32: thread per row (q, nu, m) with the NWB column sums in registers,
+// so the occupations N and f_m cost one evaluation per row instead of one per
+// element; per-column sums are added across the workgroup in a fixed order
+// (butterfly within each wave, then the waves in turn).
+template <typename T, int NWB>
+__global__ void __launch_bounds__(kLwThreads)
+    linewidth_rows_kernel(const T* __restrict__ g, int64_t nq, int64_t nk, int nm, int nw,
+                          const double* __restrict__ eps_k, const double* __restrict__ eps_kq,
+                          const double* __restrict__ omega, LwParams p, double* __restrict__ gamma) {
+  __shared__ double red[kLwThreads / 64];
+  const int64_t ik = blockIdx.x;
+  const int tid = threadIdx.x;
+  double en[NWB], acc[NWB];
+#pragma unroll
+  for (int n = 0; n < NWB; ++n) {
+    en[n] = n < nw ? eps_k[ik * nw + n] : 0.0;
+    acc[n] = 0.0;
+  }
+  const int64_t rows = nq * nm * nw;   // (q, nu, m)
+  for (int64_t r = tid; r < rows; r += kLwThreads) {
+    const int64_t iq = r / ((int64_t)nm * nw);
+    const int rem = (int)(r - iq * nm * nw), nu = rem / nw, m = rem - nu * nw;
+    const double om = omega[iq * nm + nu];
+    if (om < p.omega_min) continue;
+    const double em = eps_kq[(iq * nk + ik) * nw + m];
+    const double nb = 1.0 / expm1(om * p.inv_t);
+    const double fm = fermi_occ(em, p);
+    const double wa = (nb + fm) * p.gnorm / (2.0 * om), we = (nb + 1.0 - fm) * p.gnorm / (2.0 * om);
+    const T* row = g + 2 * ((((iq * nk + ik) * nm + nu) * (int64_t)nw + m) * nw);
+#pragma unroll
+    for (int n = 0; n < NWB; ++n) {
+      if (n < nw) {
+        const double a = (en[n] - em + om) * p.inv_sigma, b = (en[n] - em - om) * p.inv_sigma;
+        const double x = (double)row[2 * n], y = (double)row[2 * n + 1];
+        acc[n] += (wa * exp(-0.5 * a * a) + we * exp(-0.5 * b * b)) * (x * x + y * y);
+      }
+    }
+  }
+  const int lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+  for (int n = 0; n < NWB; ++n) {
+    if (n >= nw) break;   // nw is uniform: every thread leaves together
+    double v = acc[n];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int w = 0; w < kLwThreads / 64; ++w) s += red[w];
+      gamma[ik * nw + n] += p.scale * s;
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T>
+using LwKernel = void (*)(const T*, int64_t, int64_t, int, int, const double*, const double*, const double*,
+                          LwParams, double*);
+
+template <typename T>
+LwKernel<T> lw_rows_kernel(int nw) {
+  switch ((nw + 3) / 4) {
+    case 1: return linewidth_rows_kernel<T, 4>;
+    case 2: return linewidth_rows_kernel<T, 8>;
+    case 3: return linewidth_rows_kernel<T, 12>;
+    case 4: return linewidth_rows_kernel<T, 16>;
+    case 5: return linewidth_rows_kernel<T, 20>;
+    case 6: return linewidth_rows_kernel<T, 24>;
+    case 7: return linewidth_rows_kernel<T, 28>;
+    case 8: return linewidth_rows_kernel<T, 32>;
+    default: return linewidth_kernel<T>;
+  }
+}
+
 }  // namespace
+
+ephw_status linewidth(int prec, const void* g, int64_t nq, int64_t nk, int nm, int nw, const double* eps_k,
+                      const double* eps_kq, const double* omega, double temperature, double mu, double sigma,
+                      double omega_min, int64_t nq_total, double* gamma, hipStream_t s) {
+  if (nq == 0 || nk == 0) return EPHW_OK;
+  if (nk > 0x7fffffff) {
+    set_error("ephw_linewidth: more than 2^31 k points");
+    return EPHW_EUNSUPPORTED;
+  }
+  LwParams p;
+  p.inv_t = 1.0 / temperature;
+  p.mu = mu;
+  p.inv_sigma = 1.0 / sigma;
+  p.gnorm = 1.0 / (sigma * 2.5066282746310005024);   // 1 / (sigma sqrt(2 pi))
+  p.omega_min = omega_min;
+  p.scale = 3.14159265358979323846 / (double)nq_total;
+  if (prec == 0)
+    hipLaunchKernelGGL(lw_rows_kernel<double>(nw), dim3((unsigned)nk), dim3(kLwThreads), 0, s,
+                       static_cast<const double*>(g), nq, nk, nm, nw, eps_k, eps_kq, omega, p, gamma);
+  else
+    hipLaunchKernelGGL(lw_rows_kernel<float>(nw), dim3((unsigned)nk), dim3(kLwThreads), 0, s,
+                       static_cast<const float*>(g), nq, nk, nm, nw, eps_k, eps_kq, omega, p, gamma);
+  EPHW_CHECK_LAUNCH();
+  return EPHW_OK;
+}
 
 ephw_status degenerate_sums(int prec, const void* g, int64_t nq, int64_t nk, int nm, int nw,
                             const double* eps_kq, const double* eps_k, const double* lam, double rel_tol,

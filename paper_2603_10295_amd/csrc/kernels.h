@@ -38,6 +38,11 @@ ephw_status degenerate_sums(int prec, const void* g, int64_t nq, int64_t nk, int
                             const double* eps_kq, const double* eps_k, const double* lam, double rel_tol,
                             double* out, hipStream_t s);
 
+// gamma[k][n] += phonon-limited linewidth contributions of the q list (see epilogue.hip)
+ephw_status linewidth(int prec, const void* g, int64_t nq, int64_t nk, int nm, int nw, const double* eps_k,
+                      const double* eps_kq, const double* omega, double temperature, double mu, double sigma,
+                      double omega_min, int64_t nq_total, double* gamma, hipStream_t s);
+
 // dst[i] = (T) src[i] for n complex values; T = float (prec 1) or a plain copy (prec 0)
 ephw_status cast_complex(int prec, const double* src, void* dst, int64_t n, hipStream_t s);
 

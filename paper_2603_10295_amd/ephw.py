@@ -27,7 +27,7 @@ EXPORTS = [
     "ephw_ctx_create", "ephw_ctx_destroy", "ephw_ctx_check", "ephw_system_load",
     "ephw_system_free", "ephw_system_set_g", "ephw_system_bytes", "ephw_bands", "ephw_phonons", "ephw_phase_sum_rp",
     "ephw_kset_create", "ephw_kset_free", "ephw_kset_bands", "ephw_interpolate", "ephw_degenerate_sums", "ephw_wannier_transform",
-    "ephw_window_screen",
+    "ephw_window_screen", "ephw_linewidth",
     "ephw_loss_backward", "ephw_set_q_batch", "ephw_set_k_tile", "ephw_profile_enable", "ephw_profile_read", "ephw_batch_create",
     "ephw_batch_run", "ephw_batch_shape", "ephw_batch_stats", "ephw_batch_free", "ephw_status_string",
     "ephw_last_error", "ephw_version",
@@ -105,6 +105,8 @@ def lib() -> ctypes.CDLL:
         "ephw_interpolate": [vp, vp, i64, vp, i64, i32, u32, vp, vp, vp, u64, vp, vp, vp],
         "ephw_degenerate_sums": [i32, vp, i64, i64, i32, i32, vp, vp, vp, ctypes.c_double, vp, vp],
         "ephw_wannier_transform": [vp, vp, i64, vp, vp, vp, vp],
+        "ephw_linewidth": [i32, vp, i64, i64, i32, i32, vp, vp, vp, ctypes.c_double, ctypes.c_double,
+                           ctypes.c_double, ctypes.c_double, i64, vp, vp],
         "ephw_window_screen": [vp, vp, i64, vp, ctypes.c_double, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_int64),
                                vp, ctypes.POINTER(ctypes.c_int64), vp, vp, vp],
         "ephw_set_q_batch": [vp, i32],
@@ -318,6 +320,16 @@ def window_screen(ks: KSet, q, kq_index, e_lo: float, e_hi: float, k_out, q_out,
                                     _ptr(k_out), ctypes.byref(nk), _ptr(q_out), ctypes.byref(nq), _ptr(kq_out),
                                     _ptr(pair_mask), _stream(stream)), "ephw_window_screen")
     return nk.value, nq.value
+
+
+def linewidth(prec: int, g, eps_k, eps_kq, omega, gamma, *, temperature: float, mu: float, sigma: float,
+              omega_min: float = 0.0, nq_total: int = 0, stream=None):
+    """gamma[k][n] += phonon-limited linewidth from g [nq][nk][nm][nw][nw]
+    (see ephw_linewidth); nq_total defaults to this chunk's q count."""
+    nq, nk, nm, nw = g.shape[0], g.shape[1], g.shape[2], g.shape[3]
+    _check(lib().ephw_linewidth(int(prec), _ptr(g), nq, nk, nm, nw, _ptr(eps_k), _ptr(eps_kq), _ptr(omega),
+                                float(temperature), float(mu), float(sigma), float(omega_min),
+                                int(nq_total or nq), _ptr(gamma), _stream(stream)), "ephw_linewidth")
 
 
 def wannier_transform(ks: KSet, q, kq_index, g_bloch, g_out, stream=None):

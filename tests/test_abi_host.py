@@ -53,6 +53,12 @@ def test_null_arguments_rejected_before_any_device_call():
     assert L.ephw_degenerate_sums(1, None, 0, 3, 3, 4, None, None, None, 1e-6, None, None) == ephw.OK
     assert L.ephw_wannier_transform(None, None, 4, None, None, None, None) == ephw.EINVAL
     assert L.ephw_window_screen(None, None, 4, None, 0.0, 1.0, None, None, None, None, None, None, None) == ephw.EINVAL
+    # linewidth: temperature and width must be positive, buffers present
+    assert L.ephw_linewidth(0, None, 1, 1, 3, 4, None, None, None, 0.0, 0.0, 0.01, 0.0, 1, None, None) == ephw.EINVAL
+    assert L.ephw_linewidth(0, None, 1, 1, 3, 4, None, None, None, 0.02, 0.0, -1.0, 0.0, 1, None, None) == ephw.EINVAL
+    assert L.ephw_linewidth(0, None, 1, 1, 3, 4, None, None, None, 0.02, 0.0, 0.01, 0.0, 0, None, None) == ephw.EINVAL
+    assert L.ephw_linewidth(0, None, 1, 1, 3, 4, None, None, None, 0.02, 0.0, 0.01, 0.0, 1, None, None) == ephw.EINVAL
+    assert L.ephw_linewidth(1, None, 0, 1, 3, 4, None, None, None, 0.02, 0.0, 0.01, 0.0, 1, None, None) == ephw.OK
     assert L.ephw_phonons(None, None, 3, None, None, None, None) == ephw.EINVAL
     assert L.ephw_phase_sum_rp(None, None, 3, 0, None, None) == ephw.EINVAL
     assert L.ephw_ctx_create(0, None) == ephw.EINVAL

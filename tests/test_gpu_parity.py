@@ -548,7 +548,8 @@ def test_window_screen_empty_and_full(run):
 
 def test_degenerate_sums_and_wannier_transform_beyond_32_bands(run):
     """Nw = 34 (the band rotations run as pair-stacked GEMMs there): the
-    degenerate-block sums against the oracle's, and Eq. (6) o Eq. (7) = 1."""
+    degenerate-block sums and the linewidth (its element-per-thread form)
+    against the oracle's, and Eq. (6) o Eq. (7) = 1."""
     import torch
     from paper_2603_10295_amd import ephw
     from gpu_run import dev
@@ -583,3 +584,38 @@ def test_degenerate_sums_and_wannier_transform_beyond_32_bands(run):
             bn = block_index(oracle.degenerate_blocks(ref["eps_k"][ik]), s.nw)
             assert rel_max(d[iq, ik], sums[i][np.ix_(bv, bm, bn)]) < 1e-10
             i += 1
+    e = ref["eps_k"]
+    temp, mu, sigma = 0.1 * float(np.ptp(e)), float(np.median(e)), 0.2 * float(np.ptp(e))
+    om = dev(run.phonons(sysh, qc)[1])
+    gamma = torch.zeros((nk, s.nw), dtype=torch.float64, device="cuda:0")
+    ephw.linewidth(0, g, eps_k, ekq, om, gamma, temperature=temp, mu=mu, sigma=sigma)
+    run.ctx.check()
+    lw = oracle.linewidth(ref["ghat"], ref["eps_k"], ref["eps_kq"], ref["omega"], temp, mu, sigma, 0.0, nq)
+    assert rel_max(gamma.cpu().numpy(), lw) < 1e-10
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_linewidth_matches_oracle(run, prec):
+    """The downstream linewidth from the GPU's g, eigenvalues and frequencies
+    against the oracle's from its own (non-degenerate spectra: |g|^2 per
+    state is gauge free), accumulated over two q chunks."""
+    import dataclasses
+    import torch
+    from paper_2603_10295_amd import ephw
+    from gpu_run import dev
+    w = synth.si_toy()
+    s = w.system if prec == 0 else dataclasses.replace(w.system, g=w.system.g.astype(np.complex64))
+    k, q = w.k[:6], w.q[:5]
+    out = run.interpolate(run.system(s), k, q, prec, flags=ephw.OUT_G)
+    ref = oracle.interpolate(s, k, q, return_all=True)
+    e = ref["eps_k"]
+    temp, mu, sigma = 0.1 * float(np.ptp(e)), float(np.median(e)), 0.2 * float(np.ptp(e))
+    lw = oracle.linewidth(ref["ghat"], ref["eps_k"], ref["eps_kq"], ref["omega"], temp, mu, sigma, 0.0, len(q))
+    gamma = torch.zeros((len(k), s.nw), dtype=torch.float64, device="cuda:0")
+    for a, b in ((0, 2), (2, len(q))):
+        ephw.linewidth(prec, dev(out["g"][a:b]), dev(out["eps_k"]), dev(out["eps_kq"][a:b]), dev(out["omega"][a:b]),
+                       gamma, temperature=temp, mu=mu, sigma=sigma, nq_total=len(q))
+    run.ctx.check()
+    err = rel_max(gamma.cpu().numpy(), lw)
+    print(f"linewidth prec={prec}: max error {err:.2e} of the largest; range {lw.min():.3e}..{lw.max():.3e}")
+    assert err < (1e-10 if prec == 0 else 1e-5)
