@@ -219,7 +219,9 @@ ephw_status ephw_wannier_transform(ephw_kset* ks, const double* q, int64_t nq, c
      pair_mask [nq][nk] uint8 (device) or NULL: same layout, 1 where k+q is in
                the window (those pairs are the ones to keep)
    kq_index [nq][nk] int32 (device, required for nq > 0): grid index of k+q
-   in the set.  The call synchronises the stream (the counts are host values). */
+   in the set; entries outside [0, nk) count as inactive and set the
+   context's status word (EPHW_EINDEX from ephw_ctx_check).  The call
+   synchronises the stream (the counts are host values). */
 ephw_status ephw_window_screen(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index, double e_lo,
                                double e_hi, double* k_out, int64_t* nk_out, double* q_out, int64_t* nq_out,
                                int32_t* kq_out, uint8_t* pair_mask, void* stream);
