@@ -50,6 +50,8 @@ def parse(argv=None):
     ap.add_argument("--fp64-steps", type=int, default=1)
     ap.add_argument("--cpu-sample-q", type=int, default=12, help="q points of the oracle sample (about 15 s of host work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-one-thread-q", type=int, default=1,
+                    help="q points of the oracle's one-thread sample (0 skips it)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-split", action="store_true", help="skip the FP32 split-phase (hi + lo) measurement")
     ap.add_argument("--split-steps", type=int, default=1)
@@ -642,6 +644,15 @@ def main(argv=None):
                "sample": f"{len(qs_idx)} q (of {nq}) x all {nk} k of the same workload, "
                          f"NumPy complex128 + LAPACK eigh, nested loop Eqs. (9)-(10)"}
         log(f"oracle: {c_val:.4e} elems/s in {c_dt:.1f}s")
+        if args.cpu_one_thread_q > 0:
+            # the same oracle on one host thread (BLAS limited to 1), smaller sample
+            from threadpoolctl import threadpool_limits
+            q1 = qs_idx[:args.cpu_one_thread_q]
+            with threadpool_limits(limits=1):
+                v1, dt1, _, _ = cpu_baseline(w, q1)
+            cpu["one_thread"] = {"value": v1, "unit": "elems/s", "seconds": round(dt1, 2),
+                                 "sample": f"{len(q1)} q x all {nk} k, BLAS limited to 1 thread"}
+            log(f"oracle, 1 thread: {v1:.4e} elems/s in {dt1:.1f}s")
         g32 = p32.sample(qs_idx)
         err32 = block_error(g32, ref)
         log(f"FP32 vs oracle: normwise {err32[0]:.2e}, max blockwise {err32[1]:.2e}")
