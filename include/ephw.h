@@ -66,7 +66,7 @@ typedef int32_t ephw_status;
 #define EPHW_ENOMEM        2  /* device allocation failed */
 #define EPHW_EDEVICE       3  /* HIP runtime error */
 #define EPHW_ENOCONV       4  /* a Jacobi eigensolve hit its sweep limit */
-#define EPHW_EUNSUPPORTED  5  /* valid request this build does not handle */
+#define EPHW_EUNSUPPORTED  5  /* a valid request the library does not handle */
 #define EPHW_EINDEX        6  /* a k+q index table entry was out of range */
 
 /* arithmetic of the phase sums and rotations; eigensolves are always FP64 */
