@@ -666,8 +666,8 @@ def main(argv=None):
         tsp, stsp = timed(ps, args.split_steps, 1 if args.warmup else 0, profile=True)
         split = {"value": cnt.elems / tsp, "ms_per_step": tsp * 1e3,
                  "re_gemm_ms_per_step": round(stsp["re_gemm"][0] / args.split_steps, 3),
-                 "note": "the Re and Rp phase GEMMs also multiply the FP32 low part of every phase "
-                         "(twice the MFMA work of the plain FP32 path)"}
+                 "note": "the Re and Rp phase GEMMs also multiply the low part of every phase, "
+                         "through BF16 MFMAs (one slab of the low pass per 16-deep FP32 slab)"}
         log(f"FP32 split: {tsp * 1e3:.1f} ms/step")
         if cpu is not None:
             e = block_error(ps.sample(qs_idx), ref)

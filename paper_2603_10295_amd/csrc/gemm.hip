@@ -48,6 +48,21 @@ struct Mfma<double> {
   static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
 };
 
+// BF16 helpers for the low pass of split phases: truncation to the upper 16
+// bits (a relative error of 2^-8 on a term 2^-24 of the result)
+typedef short Bf4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void put_bf16(uint32_t& w, int half, float x) {
+  const uint32_t b = __float_as_uint(x);
+  w = half ? ((w & 0x0000ffffu) | (b & 0xffff0000u)) : (b >> 16);
+}
+__device__ __forceinline__ Bf4 pack4(const uint32_t (&w)[2]) {
+  return __builtin_bit_cast(Bf4, (uint64_t)w[0] | ((uint64_t)w[1] << 32));
+}
+__device__ __forceinline__ Bf4 pack4_neg(const uint32_t (&w)[2]) {
+  const uint64_t v = ((uint64_t)w[0] | ((uint64_t)w[1] << 32)) ^ 0x8000800080008000ull;
+  return __builtin_bit_cast(Bf4, v);
+}
+
 constexpr int kGroupM = 8;
 constexpr int kXcds = 8;
 static_assert(kGroupQueues == kXcds, "one grouped-GEMM work queue per XCD");
@@ -119,7 +134,10 @@ __device__ __forceinline__ typename Chunk<T>::v4 load_chunk(__amdgpu_buffer_rsrc
   return __builtin_bit_cast(typename Chunk<T>::v4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool SPLIT>
+// SPLIT: 0 no low part; 1 the low part of A through FP32 MFMAs; 2 through
+// BF16 MFMAs (its products are 2^-24 of the high part's, so BF16 operands
+// lose nothing that shows in the FP32 accumulator)
+template <typename T, int BM, int BN, int BK, int WM, int WN, int SPLIT>
 struct TileShape {
   static constexpr int NT = 64 * WM * WN;
   static constexpr int PADC = (sizeof(T) == 4) ? 2 : 1;  // complex values of padding per LDS row
@@ -138,7 +156,7 @@ struct TileShape {
 // written to the other stage, so each slab costs one barrier.  LDS keeps
 // complex values interleaved, laid out [k][m] and [k][n], so one 8- or
 // 16-byte read gives a lane its (re, im) operand pair.
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SPLIT>
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int SPLIT>
 __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64_t n0, T* smem) {
   using S = TileShape<T, BM, BN, BK, WM, WN, SPLIT>;
   using C = Chunk<T>;
@@ -309,6 +327,12 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
       acc_i[i][jj] = Acc{0, 0, 0, 0};
     }
 
+  // BF16 packs of the low pass (SPLIT == 2): two 32-bit words hold the four
+  // k steps of a slab
+  uint32_t lo_r[SPLIT == 2 ? FM : 1][2], lo_i[SPLIT == 2 ? FM : 1][2];
+  uint32_t bh_r[SPLIT == 2 ? FN : 1][2], bh_i[SPLIT == 2 ? FN : 1][2];
+  static_assert(SPLIT != 2 || (sizeof(T) == 4 && BK == 16), "the BF16 low pass packs one 16-deep FP32 slab");
+
   // One BK slab of MFMAs from an LDS stage.  The four real products of every
   // block are issued product by product across all blocks, so consecutive
   // MFMAs never depend on each other.
@@ -344,7 +368,7 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int jj = 0; jj < FN; ++jj) acc_i[i][jj] = Mfma<T>::op(a[i][1], b[jj][0], acc_i[i][jj]);
-      if (SPLIT) {
+      if constexpr (SPLIT == 1) {
         const T* Al = As + 2 * BK * LA;
 #pragma unroll
         for (int i = 0; i < FM; ++i) {
@@ -365,6 +389,37 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
             acc_r[i][jj] = Mfma<T>::op(nai[i], b[jj][1], acc_r[i][jj]);
             acc_i[i][jj] = Mfma<T>::op(a[i][1], b[jj][0], acc_i[i][jj]);
           }
+      }
+      if constexpr (SPLIT == 2) {
+        // k step s = kk / 4 fills BF16 slot s of the packs (both operands use
+        // k = 4 s + lane group, so the BF16 MFMA sums the same products)
+        const T* Al = As + 2 * BK * LA;
+        const int s = kk / 4;
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+          const V2 al = *reinterpret_cast<const V2*>(Al + 2 * (kr * LA + wm * TM + i * 16 + lcol));
+          put_bf16(lo_r[i][s >> 1], s & 1, al[0]);
+          put_bf16(lo_i[i][s >> 1], s & 1, al[1]);
+        }
+#pragma unroll
+        for (int jj = 0; jj < FN; ++jj) {
+          put_bf16(bh_r[jj][s >> 1], s & 1, b[jj][0]);
+          put_bf16(bh_i[jj][s >> 1], s & 1, b[jj][1]);
+        }
+        if (kk + 4 == BK) {
+#pragma unroll
+          for (int i = 0; i < FM; ++i) {
+            const Bf4 ar = pack4(lo_r[i]), ai = pack4(lo_i[i]), nai4 = pack4_neg(lo_i[i]);
+#pragma unroll
+            for (int jj = 0; jj < FN; ++jj) {
+              const Bf4 br = pack4(bh_r[jj]), bi = pack4(bh_i[jj]);
+              acc_r[i][jj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, br, acc_r[i][jj], 0, 0, 0);
+              acc_i[i][jj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bi, acc_i[i][jj], 0, 0, 0);
+              acc_r[i][jj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(nai4, bi, acc_r[i][jj], 0, 0, 0);
+              acc_i[i][jj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, br, acc_i[i][jj], 0, 0, 0);
+            }
+          }
+        }
       }
     }
   };
@@ -499,7 +554,7 @@ __device__ __forceinline__ TileJob<T> job_of(const GemmParams& p, int64_t b) {
 }
 
 // OCC: waves per SIMD the register allocation must leave room for
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SPLIT, int OCC>
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int SPLIT, int OCC>
 __global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(OCC)))
     cgemm_kernel(GemmParams p, int64_t tiles_m, int64_t tiles_n) {
   using S = TileShape<T, BM, BN, BK, WM, WN, SPLIT>;
@@ -553,7 +608,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     cgemm_grouped_kernel(const GroupProblem* __restrict__ probs, int n, int64_t total, int* __restrict__ queue) {
   using G = GroupCfg<T>;
   constexpr int BM = CFG == 0 ? G::LM : G::SM, BN = CFG == 0 ? G::LN : G::SN, BK = CFG == 0 ? G::LK : G::SK;
-  using Sh = TileShape<T, BM, BN, BK, 2, 2, false>;
+  using Sh = TileShape<T, BM, BN, BK, 2, 2, 0>;
   __shared__ T smem[Sh::smem_elems];
   __shared__ int64_t s_next;
   int q = blockIdx.x % kXcds, tried = 0;   // used by thread 0 only
@@ -600,7 +655,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     j.batch = 0;
     j.tile = 0;
     j.ntiles = 1;
-    gemm_tile<T, BM, BN, BK, 2, 2, false, false, false>(j, tm * BM, tn * BN, smem);
+    gemm_tile<T, BM, BN, BK, 2, 2, false, false, 0>(j, tm * BM, tn * BN, smem);
     if (threadIdx.x == 0) {
       int64_t nt = -1;
       if (tried < kXcds) {
@@ -637,7 +692,7 @@ bool lane_offsets_fit(int64_t lda, int64_t ldb) {
   return lda >= 0 && ldb >= 0 && (a_rows * lda + BM + BK) * cs < lim && (b_rows * ldb + BN + BK) * cs < lim;
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, bool SPLIT, int OCC>
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int SPLIT, int OCC>
 ephw_status launch(const GemmParams& p0, hipStream_t stream) {
   const int64_t tiles_m = ceil_div(p0.M, BM), tiles_n = ceil_div(p0.N, BN);
   const int64_t ntiles = tiles_m * tiles_n;
@@ -770,7 +825,7 @@ ephw_status dispatch_skinny(const GemmParams& p, hipStream_t s) {
   return launch_skinny<T, 16>(p, s);
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool SPLIT, int OCC>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int SPLIT, int OCC>
 ephw_status dispatch_trans(const GemmParams& p, hipStream_t s) {
   if (!p.transA && !p.transB) return launch<T, BM, BN, BK, WM, WN, false, false, SPLIT, OCC>(p, s);
   if (p.transA && !p.transB) return launch<T, BM, BN, BK, WM, WN, true, false, SPLIT, OCC>(p, s);
@@ -905,7 +960,7 @@ ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream) {
     set_error("cgemm: split A is an FP32 feature");
     return EPHW_EINVAL;
   }
-  if (p.A_lo) return dispatch_trans<float, 128, 128, 16, 2, 2, true, 1>(p, stream);
+  if (p.A_lo) return dispatch_trans<float, 128, 128, 16, 2, 2, 2, 2>(p, stream);
   // few rows, many columns, B read straight: a stream over B and C
   // (FP32 reads two complex values per 16-byte load: rows must start on 16 bytes)
   if (p.M <= 16 && p.N >= 16384 && !p.transB && !p.conjB && !p.loss.on && p.tblock == 0 &&
