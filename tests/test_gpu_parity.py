@@ -619,3 +619,31 @@ def test_linewidth_matches_oracle(run, prec):
     err = rel_max(gamma.cpu().numpy(), lw)
     print(f"linewidth prec={prec}: max error {err:.2e} of the largest; range {lw.min():.3e}..{lw.max():.3e}")
     assert err < (1e-10 if prec == 0 else 1e-5)
+
+
+def test_si_dense_sampled_full_size(run):
+    """The dense-Si workload at full size in the benchmark's launch shape
+    (8000 k set, q chunks of 1024, g stored, FP32): three q of the first chunk
+    against the oracle in block sums, with the 1e-5 bound."""
+    import torch
+    from paper_2603_10295_amd import ephw
+    from gpu_run import dev
+    w = synth.si_dense()
+    s = w.system
+    sysh = run.system(s)
+    nk = len(w.k)
+    ks = ephw.KSet(sysh, dev(w.k), ephw.FP32)
+    qc = 1024
+    g = torch.empty((qc, nk, s.nm, s.nw, s.nw), dtype=torch.complex64, device="cuda:0")
+    ephw.interpolate(ks, dev(w.q[:qc]), kq_index=dev(w.kq_index[:qc]), flags=ephw.OUT_G, g_out=g)
+    run.ctx.check()
+    sample = [0, 511, 1023]
+    got = g[sample].cpu().numpy().astype(np.complex128)
+    del g
+    ks.close()
+    ref = oracle.interpolate(s, w.k, w.q[sample], return_all=True)
+    sg = oracle.block_sums(np.abs(got) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+    sr = oracle.block_sums(np.abs(ref["ghat"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+    norm, blk = oracle.compare_block_sums(sg, sr)
+    print(f"dense Si full size, FP32: block sums normwise {norm:.2e}, max blockwise {blk:.2e}")
+    assert norm < 1e-5
