@@ -193,7 +193,7 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
    with U = V^dagger as in Eq. (7), u = e/sqrt(M) the mode vectors of D(q'),
    and no lattice-vector weights (Eq. (6) has none).
      ks       k-set on the coarse k' grid (its eigenvectors are V(k'))
-     q        [nq][3] f64 (device): the coarse q' points
+     q        [nq][3] f64 (device): the coarse q' points, nq >= 1
      kq_index [nq][nk] int32 (device), required: grid index of k'_i + q'_j in the set
      g_bloch  [nq][nk][nm][nw][nw] (device): c128 for an FP64 set, c64 for FP32,
               in the layout ephw_interpolate stores
