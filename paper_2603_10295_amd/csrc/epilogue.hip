@@ -91,6 +91,18 @@ struct LwParams {
   double inv_t, mu, inv_sigma, gnorm, omega_min, scale;
 };
 
+// exp(-x^2/2) of a scaled energy difference: in FP32 for c64 matrix elements
+// (a weight error near 1e-7, below the data's own), FP64 otherwise
+template <typename T>
+__device__ __forceinline__ double gauss_exp(double x) {
+  if constexpr (sizeof(T) == 4) {
+    const float f = (float)x;
+    return (double)expf(-0.5f * f * f);
+  } else {
+    return exp(-0.5 * x * x);
+  }
+}
+
 __device__ __forceinline__ double fermi_occ(double e, const LwParams& p) {
   const double x = (e - p.mu) * p.inv_t;
   const double z = exp(-fabs(x));
@@ -120,7 +132,7 @@ __global__ void __launch_bounds__(kLwThreads)
       const double nb = 1.0 / expm1(om * p.inv_t);
       const double fm = fermi_occ(em, p);
       const double a = (en - em + om) * p.inv_sigma, b = (en - em - om) * p.inv_sigma;
-      const double w = ((nb + fm) * exp(-0.5 * a * a) + (nb + 1.0 - fm) * exp(-0.5 * b * b)) * p.gnorm / (2.0 * om);
+      const double w = ((nb + fm) * gauss_exp<T>(a) + (nb + 1.0 - fm) * gauss_exp<T>(b)) * p.gnorm / (2.0 * om);
       const int64_t i = ((iq * nk + ik) * nm + nu) * (int64_t)nw * nw + (int64_t)m * nw + n;
       const double x = (double)g[2 * i], y = (double)g[2 * i + 1];
       acc += w * (x * x + y * y);
@@ -147,6 +159,7 @@ __global__ void __launch_bounds__(kLwThreads)
   __shared__ double red[kLwThreads / 64];
   const int64_t ik = blockIdx.x;
   const int tid = threadIdx.x;
+  const bool vec16 = (nw % 2 == 0) && (reinterpret_cast<uintptr_t>(g) & 15) == 0;
   double en[NWB], acc[NWB];
 #pragma unroll
   for (int n = 0; n < NWB; ++n) {
@@ -164,12 +177,33 @@ __global__ void __launch_bounds__(kLwThreads)
     const double fm = fermi_occ(em, p);
     const double wa = (nb + fm) * p.gnorm / (2.0 * om), we = (nb + 1.0 - fm) * p.gnorm / (2.0 * om);
     const T* row = g + 2 * ((((iq * nk + ik) * nm + nu) * (int64_t)nw + m) * nw);
+    double g2[NWB];
+    if constexpr (sizeof(T) == 4) {
+      if (vec16) {
+        // even Nw, 16-byte aligned rows: two complex values per load
+#pragma unroll
+        for (int n = 0; n < NWB; n += 2) {
+          if (n < nw) {
+            const float4 v = *reinterpret_cast<const float4*>(row + 2 * n);
+            g2[n] = (double)v.x * v.x + (double)v.y * v.y;
+            g2[n + 1] = (double)v.z * v.z + (double)v.w * v.w;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int n = 0; n < NWB; ++n)
+          if (n < nw) g2[n] = (double)row[2 * n] * row[2 * n] + (double)row[2 * n + 1] * row[2 * n + 1];
+      }
+    } else {
+#pragma unroll
+      for (int n = 0; n < NWB; ++n)
+        if (n < nw) g2[n] = (double)row[2 * n] * row[2 * n] + (double)row[2 * n + 1] * row[2 * n + 1];
+    }
 #pragma unroll
     for (int n = 0; n < NWB; ++n) {
       if (n < nw) {
         const double a = (en[n] - em + om) * p.inv_sigma, b = (en[n] - em - om) * p.inv_sigma;
-        const double x = (double)row[2 * n], y = (double)row[2 * n + 1];
-        acc[n] += (wa * exp(-0.5 * a * a) + we * exp(-0.5 * b * b)) * (x * x + y * y);
+        acc[n] += (wa * gauss_exp<T>(a) + we * gauss_exp<T>(b)) * g2[n];
       }
     }
   }
