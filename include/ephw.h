@@ -241,7 +241,8 @@ ephw_status ephw_window_screen(ephw_kset* ks, const double* q, int64_t nq, const
      g       [nq][nk][nm][nw][nw] (device), as ephw_interpolate stores it
      eps_k [nk][nw], eps_kq [nq][nk][nw], omega [nq][nm]: f64 (device)
      gamma   [nk][nw] f64 (device), accumulated (+=), caller-owned
-   temperature, sigma > 0 (energy units of eps); omega_min >= 0 drops soft modes.
+   temperature, sigma > 0 (energy units of eps); omega_min >= 0 drops soft modes,
+   and modes with omega = 0 never contribute (1/(2 omega) is undefined there).
    Occupations and sums are FP64; the Gaussians are FP32 for c64 g.
    Deterministic: every sum runs in a fixed order. */
 ephw_status ephw_linewidth(int32_t prec, const void* g, int64_t nq, int64_t nk, int32_t nm, int32_t nw,

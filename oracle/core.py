@@ -309,7 +309,8 @@ def gauss(x: np.ndarray, sigma: float) -> np.ndarray:
 
 def linewidth(ghat: np.ndarray, eps_k: np.ndarray, eps_kq: np.ndarray, omega: np.ndarray, temp: float,
               mu: float, sigma: float, omega_min: float, nq_total: int) -> np.ndarray:
-    """Gamma[k][n] = (pi / Nq) sum over q, m and modes nu with omega >= omega_min of
+    """Gamma[k][n] = (pi / Nq) sum over q, m and modes nu with omega >= omega_min
+    and omega > 0 of
     |g_mn nu(k,q)|^2 / (2 omega) * [ (N + f_m) delta(e_n - e_m + omega)
                                   + (N + 1 - f_m) delta(e_n - e_m - omega) ],
     N = bose(omega), f_m = fermi(e_m(k+q)), e_n = eps_k[k][n]: phonon absorption
@@ -317,7 +318,7 @@ def linewidth(ghat: np.ndarray, eps_k: np.ndarray, eps_kq: np.ndarray, omega: np
     supplies the zero-point amplitude that the mode vectors u = e/sqrt(M) of
     Eq. (2) leave out.  ghat [Nq][Nk][Nm][Nw][Nw] (nu, m, n); returns [Nk][Nw]."""
     om = np.asarray(omega, dtype=np.float64)                          # [q][nu]
-    keep = om >= omega_min
+    keep = (om >= omega_min) & (om > 0.0)                             # omega = 0: no zero-point amplitude
     om_safe = np.where(keep, om, 1.0)
     n_b = np.where(keep, bose(om_safe, temp), 0.0)
     amp = np.where(keep, 1.0 / (2.0 * om_safe), 0.0)

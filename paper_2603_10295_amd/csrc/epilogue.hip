@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(kLwThreads)
       const int64_t iq = r / ((int64_t)nm * nw);
       const int rem = (int)(r - iq * nm * nw), nu = rem / nw, m = rem - nu * nw;
       const double om = omega[iq * nm + nu];
-      if (om < p.omega_min) continue;
+      if (!(om > 0.0) || om < p.omega_min) continue;   // omega = 0: no zero-point amplitude
       const double em = eps_kq[(iq * nk + ik) * nw + m];
       const double nb = 1.0 / expm1(om * p.inv_t);
       const double fm = fermi_occ(em, p);
@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(kLwThreads)
     const int64_t iq = r / ((int64_t)nm * nw);
     const int rem = (int)(r - iq * nm * nw), nu = rem / nw, m = rem - nu * nw;
     const double om = omega[iq * nm + nu];
-    if (om < p.omega_min) continue;
+    if (!(om > 0.0) || om < p.omega_min) continue;   // omega = 0: no zero-point amplitude
     const double em = eps_kq[(iq * nk + ik) * nw + m];
     const double nb = 1.0 / expm1(om * p.inv_t);
     const double fm = fermi_occ(em, p);

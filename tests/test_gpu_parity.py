@@ -619,6 +619,19 @@ def test_linewidth_matches_oracle(run, prec):
     err = rel_max(gamma.cpu().numpy(), lw)
     print(f"linewidth prec={prec}: max error {err:.2e} of the largest; range {lw.min():.3e}..{lw.max():.3e}")
     assert err < (1e-10 if prec == 0 else 1e-5)
+    # a zero-frequency mode (omega_min = 0) contributes nothing on both sides
+    om0 = out["omega"].copy()
+    om0[:, 0] = 0.0
+    ref_om0 = ref["omega"].copy()
+    ref_om0[:, 0] = 0.0
+    lw0 = oracle.linewidth(ref["ghat"], ref["eps_k"], ref["eps_kq"], ref_om0, temp, mu, sigma, 0.0, len(q))
+    gamma.zero_()
+    ephw.linewidth(prec, dev(out["g"]), dev(out["eps_k"]), dev(out["eps_kq"]), dev(om0), gamma, temperature=temp,
+                   mu=mu, sigma=sigma)
+    run.ctx.check()
+    got0 = gamma.cpu().numpy()
+    assert np.all(np.isfinite(got0))
+    assert rel_max(got0, lw0) < (1e-10 if prec == 0 else 1e-5)
 
 
 def test_si_dense_sampled_full_size(run):

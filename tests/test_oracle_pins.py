@@ -389,3 +389,16 @@ def test_linewidth_zero_temperature_empty_final_states():
     off = ek[0, 2] - (eps_kq[0, 0, :, None] + omega[0][None, :])       # distance to every emission resonance
     if np.abs(off).min() > 20 * sigma:
         assert gam[2] < 1e-30
+
+
+def test_linewidth_zero_frequency_mode_is_dropped():
+    """A mode with omega = 0 has no zero-point amplitude: it contributes
+    nothing (rather than an infinite Bose factor) even with omega_min = 0."""
+    g, eps_k, eps_kq, omega = _linewidth_case(17)
+    om = omega.copy()
+    om[:, 0] = 0.0
+    g0 = g.copy()
+    g0[:, :, 0] = 0.0
+    a = oracle.linewidth(g, eps_k, eps_kq, om, 0.03, 0.05, 0.04, 0.0, 5)
+    assert np.all(np.isfinite(a))
+    np.testing.assert_allclose(a, oracle.linewidth(g0, eps_k, eps_kq, om, 0.03, 0.05, 0.04, 0.0, 5), rtol=1e-14)
