@@ -97,6 +97,20 @@ ephw_status ephw_ctx_destroy(ephw_ctx* ctx);
    Returns EPHW_OK, EPHW_ENOCONV or EPHW_EINDEX. */
 ephw_status ephw_ctx_check(ephw_ctx* ctx, void* stream);
 
+/* Limits of a context (blocking; waits for the device to go idle).
+     max_device_bytes  cap on the device memory held by the context's systems,
+                       k-sets and batches (tensors, workspaces, caches); an
+                       allocation that would pass it fails with EPHW_ENOMEM
+                       before any device allocation is attempted.  0 = no cap.
+     max_sweeps        Jacobi sweeps an eigensolve may take before it stops and
+                       raises EPHW_ENOCONV in the status word (the kernel still
+                       writes its current eigenvalues and vectors and exits
+                       normally); 0 <= max_sweeps <= 1000, default 40 (an order-n
+                       solve converges in well under 20 for n <= 256). */
+ephw_status ephw_ctx_set_limits(ephw_ctx* ctx, int64_t max_device_bytes, int32_t max_sweeps);
+/* device memory the context's objects hold now, and its cap (0 = none) */
+ephw_status ephw_ctx_memory(const ephw_ctx* ctx, int64_t* used, int64_t* limit);
+
 /* Wannier-space description of one material (Eqs. (3)-(5) inputs).  All
    pointers are HOST memory.  nm = 3*na.
      r_e [ne][3], r_p [np][3], r_h [nh][3], r_c [nc][3]   int32 lattice vectors
@@ -128,7 +142,10 @@ ephw_status ephw_system_set_g(ephw_system* sys, const void* g, void* stream);
 /* bytes of library-owned device memory held by the system (tensors + workspace) */
 ephw_status ephw_system_bytes(const ephw_system* sys, int64_t* bytes);
 
-/* Electron bands on a k list (H(k) interpolation + FP64 eigensolve).
+/* Electron bands on a k list (H(k) interpolation + FP64 eigensolve): the
+   gauge matrices of Eq. (5) (U(k) = V(k)^dagger; Results, "Computational
+   aspects of electron-phonon matrix interpolation") and the band energies the
+   energy window and the downstream reductions use.
      k    [nk][3] f64 (device)
      eps  [nk][nw] f64 (device) or NULL
      vecs [nk][nw][nw] c128 (device) or NULL; column j is the eigenvector of eps[j]
@@ -136,7 +153,9 @@ ephw_status ephw_system_bytes(const ephw_system* sys, int64_t* bytes);
 ephw_status ephw_bands(ephw_system* sys, const double* k, int64_t nk, double* eps, void* vecs,
                        void* stream);
 
-/* Phonons on a q list (D(q) interpolation + FP64 eigensolve).
+/* Phonons on a q list (D(q) interpolation + FP64 eigensolve): the mode
+   vectors u(q) that Eq. (2) projects the perturbing potential on, and the
+   frequencies omega(q).
      q     [nq][3] f64 (device)
      lam   [nq][nm] f64 eigenvalues of D(q), or NULL
      omega [nq][nm] f64 sqrt(|lam|), or NULL
@@ -202,8 +221,10 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
 ephw_status ephw_wannier_transform(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index,
                                    const void* g_bloch, void* g_out, void* stream);
 
-/* Energy-window prescreening (the paper skips the matrix elements of states
-   outside an energy window before interpolating).  A k point of the set is
+/* Energy-window prescreening (the Results section's single-node benchmark
+   skips the matrix elements of states outside an energy window before
+   interpolating; its practical guidance notes that the window cuts both the
+   contributing k points and bands).  A k point of the set is
    active when one of its bands lies in [e_lo, e_hi], a pair (k, q) when k
    and k+q both are, and a q point when it has an active pair.  Outputs, for
    running Eq. (7) on the active points only (a k-set made from k_out, the q
@@ -226,8 +247,9 @@ ephw_status ephw_window_screen(ephw_kset* ks, const double* q, int64_t nq, const
                                double e_hi, double* k_out, int64_t* nk_out, double* q_out, int64_t* nq_out,
                                int32_t* kq_out, uint8_t* pair_mask, void* stream);
 
-/* A downstream reduction of stored matrix elements over q (the paper's MoS2
-   run computes an electron self-energy from the interpolated g): the
+/* A downstream reduction of stored matrix elements over q (the multi-node
+   scalability runs of the Results section compute an electron self-energy
+   of MoS2 from the interpolated g; the formula is not printed there): the
    phonon-limited linewidth, the imaginary part of the Fan-Migdal self-energy
    with Gaussian broadening,
      gamma[k][n] += pi / nq_total * sum over q, modes nu with omega >= omega_min, bands m of
@@ -243,6 +265,9 @@ ephw_status ephw_window_screen(ephw_kset* ks, const double* q, int64_t nq, const
      gamma   [nk][nw] f64 (device), accumulated (+=), caller-owned
    temperature, sigma > 0 (energy units of eps); omega_min >= 0 drops soft modes,
    and modes with omega = 0 never contribute (1/(2 omega) is undefined there).
+   Callers should pass omega_min > 0: acoustic modes near q = 0, and modes of an
+   unstable D(q) (lambda < 0, omega = sqrt(|lambda|)), have small nonzero omega
+   whose weight ~ T / omega^2 would dominate gamma.
    Occupations and sums are FP64; the Gaussians are FP32 for c64 g.
    Deterministic: every sum runs in a fixed order. */
 ephw_status ephw_linewidth(int32_t prec, const void* g, int64_t nq, int64_t nk, int32_t nm, int32_t nw,

@@ -251,7 +251,7 @@ ephw_status tune_item(ItemPlan& it, int kind, int64_t cap, bool measure, hipStre
     need = std::max(need, it.bytes());
   }
   void* tmp = nullptr;
-  EPHW_TRY(dev_alloc(&tmp, need));
+  EPHW_TRY(dev_alloc(&tmp, need, &it.sys->ctx->mem));
   hipEvent_t a = nullptr, b = nullptr;
   ephw_status rc = EPHW_OK;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) rc = EPHW_EDEVICE;
@@ -286,6 +286,7 @@ ephw_status tune_item(ItemPlan& it, int kind, int64_t cap, bool measure, hipStre
   if (b) (void)hipEventDestroy(b);
   (void)hipStreamSynchronize(st);
   (void)hipFree(tmp);
+  dev_release(&it.sys->ctx->mem, (int64_t)need);
   if (rc != EPHW_OK) return rc;
   set_shape(it, best_q, k_tile_for(it, best_q, cap));
   *us_per_kpair = best;
@@ -578,8 +579,14 @@ ephw_status ephw_batch_free(ephw_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
-  if (b->ws) (void)hipFree(b->ws);
-  if (b->desc) (void)hipFree(b->desc);
+  if (b->ws) {
+    (void)hipFree(b->ws);
+    dev_release(&b->ctx->mem, (int64_t)b->ws_bytes);
+  }
+  if (b->desc) {
+    (void)hipFree(b->desc);
+    dev_release(&b->ctx->mem, (int64_t)b->desc_bytes);
+  }
   delete b;
   return EPHW_OK;
 }
@@ -702,7 +709,7 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
   // workspace
   size_t total = 0;
   for (auto& it : bt->items) total += it.bytes();
-  ephw_status e = dev_alloc(&bt->ws, total);
+  ephw_status e = dev_alloc(&bt->ws, total, &ctx->mem);
   if (e != EPHW_OK) return fail(e);
   bt->ws_bytes = total;
   {
@@ -718,7 +725,7 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
   build_launches(bt, hd, fix);
   const size_t qoff = align256(hd.bytes.size());
   hd.bytes.resize(qoff + (size_t)std::max(1, bt->nqueue) * kGroupQueues * sizeof(int), 0);
-  if ((e = dev_alloc(&bt->desc, hd.bytes.size())) != EPHW_OK) return fail(e);
+  if ((e = dev_alloc(&bt->desc, hd.bytes.size(), &ctx->mem)) != EPHW_OK) return fail(e);
   bt->desc_bytes = hd.bytes.size();
   bt->queues = reinterpret_cast<int*>(static_cast<char*>(bt->desc) + qoff);
   if (hipMemcpy(bt->desc, hd.bytes.data(), hd.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {

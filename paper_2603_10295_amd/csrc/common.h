@@ -62,6 +62,11 @@ __device__ __forceinline__ void wave_sync() {
 // device status word bits (context-wide, read by ephw_ctx_check)
 // ---------------------------------------------------------------------------
 enum : uint32_t { kStatusNoConv = 1u, kStatusIndex = 2u };
+// Jacobi sweeps before an eigensolve reports kStatusNoConv: the context's
+// second device word holds the limit (default kDefaultSweeps)
+constexpr int kDefaultSweeps = 40;
+constexpr int kMaxSweepLimit = 1000;
+__device__ __forceinline__ int sweep_limit(const uint32_t* status) { return (int)status[1]; }
 
 // ---------------------------------------------------------------------------
 // host-side error plumbing

@@ -1,6 +1,7 @@
 // Internal handle types and helpers shared by the libephw host sources.
 #pragma once
 
+#include <atomic>
 #include <string>
 #include <vector>
 
@@ -9,14 +10,28 @@
 
 namespace ephw {
 
+// Device memory a context's systems, k-sets and batches hold, against an
+// optional cap (limit 0 = none).  Allocations that would pass the cap fail
+// with EPHW_ENOMEM before hipMalloc is called.
+struct MemBudget {
+  int64_t limit = 0;
+  std::atomic<int64_t> used{0};
+};
+
 // grow-only device buffer; reallocation waits for the device to go idle
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
 };
 
-inline ephw_status dev_alloc(void** p, size_t bytes) {
+inline ephw_status dev_alloc(void** p, size_t bytes, MemBudget* budget = nullptr) {
   if (bytes == 0) bytes = 16;
+  *p = nullptr;
+  if (budget && budget->limit > 0 && budget->used.load() + (int64_t)bytes > budget->limit) {
+    set_error("allocation of " + std::to_string(bytes) + " bytes would exceed the context's device-memory limit of " +
+              std::to_string(budget->limit) + " bytes (" + std::to_string(budget->used.load()) + " in use)");
+    return EPHW_ENOMEM;
+  }
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -24,28 +39,34 @@ inline ephw_status dev_alloc(void** p, size_t bytes) {
     *p = nullptr;
     return EPHW_ENOMEM;
   }
+  if (budget) budget->used += (int64_t)bytes;
   return EPHW_OK;
 }
 
-inline ephw_status grow(DevBuf& b, size_t bytes, int64_t* owner_bytes) {
+inline void dev_release(MemBudget* budget, int64_t bytes) {
+  if (budget) budget->used -= bytes;
+}
+
+inline ephw_status grow(DevBuf& b, size_t bytes, int64_t* owner_bytes, MemBudget* budget) {
   if (b.bytes >= bytes && b.p) return EPHW_OK;
   if (b.p) {
     EPHW_HIP(hipDeviceSynchronize());
     EPHW_HIP(hipFree(b.p));
     *owner_bytes -= (int64_t)b.bytes;
+    dev_release(budget, (int64_t)b.bytes);
     b.p = nullptr;
     b.bytes = 0;
   }
-  EPHW_TRY(dev_alloc(&b.p, bytes));
+  EPHW_TRY(dev_alloc(&b.p, bytes, budget));
   b.bytes = bytes;
   *owner_bytes += (int64_t)bytes;
   return EPHW_OK;
 }
 
 template <typename X>
-inline ephw_status upload(X** dst, const X* src, size_t count, int64_t* owner_bytes) {
+inline ephw_status upload(X** dst, const X* src, size_t count, int64_t* owner_bytes, MemBudget* budget) {
   void* p = nullptr;
-  EPHW_TRY(dev_alloc(&p, count * sizeof(X)));
+  EPHW_TRY(dev_alloc(&p, count * sizeof(X), budget));
   *owner_bytes += (int64_t)(count * sizeof(X));
   EPHW_HIP(hipMemcpy(p, src, count * sizeof(X), hipMemcpyHostToDevice));
   *dst = static_cast<X*>(p);
@@ -65,7 +86,10 @@ using namespace ephw;
 
 struct ephw_ctx {
   int device = 0;
+  // device words: [0] status bits raised by kernels, [1] sweep limit of the
+  // Jacobi eigensolves (read by the kernels at run time)
   uint32_t* status = nullptr;
+  MemBudget mem;
 };
 
 enum WsSlot {
@@ -166,7 +190,7 @@ struct Stage {
 inline void* wsp(ephw_system* s, WsSlot slot) { return s->ws[slot].p; }
 
 inline ephw_status ws_need(ephw_system* s, WsSlot slot, size_t bytes) {
-  return grow(s->ws[slot], bytes, &s->bytes);
+  return grow(s->ws[slot], bytes, &s->bytes, &s->ctx->mem);
 }
 
 inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }

@@ -20,7 +20,6 @@
 namespace ephw {
 namespace {
 
-constexpr int kMaxSweeps = 40;
 constexpr double kOffTol2 = 1e-28;  // (off-diagonal norm / total norm)^2 at convergence
 
 __device__ __forceinline__ int player_at(int pos, int round, int n2) {
@@ -44,7 +43,7 @@ __device__ double block_sum(double v, double* red) {
 // On exit the diagonal of A holds the eigenvalues and V the eigenvectors.
 template <int NT>
 __device__ bool jacobi_core(double* Ar, double* Ai, double* Vr, double* Vi, int n, double* rc,
-                            double* rs, double* rer, double* rei, int* rp, int* rq, double* red) {
+                            double* rs, double* rer, double* rei, int* rp, int* rq, double* red, int max_sweeps) {
   const int tid = threadIdx.x;
   const int n2 = n + (n & 1);
   const int npairs = n2 / 2;
@@ -54,7 +53,7 @@ __device__ bool jacobi_core(double* Ar, double* Ai, double* Vr, double* Vi, int 
   }
   __syncthreads();
   bool converged = (n <= 1);
-  for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
+  for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
     double off = 0.0, tot = 0.0;
     for (int e = tid; e < n * n; e += NT) {
       const double v = Ar[e] * Ar[e] + Ai[e] * Ai[e];
@@ -362,7 +361,8 @@ __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, 
   bool converged = n <= 1 || off <= kOffTol2 * tot;
   off = 0.0;
   tot = 0.0;
-  for (int sweep = 0; sweep < kMaxSweeps && !converged; ++sweep) {
+  const int max_sweeps = sweep_limit(status);
+  for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
 #pragma unroll 1
     for (int round = 0; round < N2 - 1; ++round) {
       if (lane < NP) {
@@ -567,7 +567,7 @@ __global__ void __launch_bounds__(256)
     Ai[e] = h[2 * e + 1];
   }
   __syncthreads();
-  const bool ok = jacobi_core<256>(Ar, Ai, Vr, Vi, n, rc, rs, rer, rei, rp, rq, red);
+  const bool ok = jacobi_core<256>(Ar, Ai, Vr, Vi, n, rc, rs, rer, rei, rp, rq, red, sweep_limit(status));
   if (!ok && threadIdx.x == 0) atomicOr(status, kStatusNoConv);
   jacobi_finish<256>(Ar, Vr, Vi, n, perm, phr, phi, eps + b * n, V + 2 * b * nn);
 }

@@ -24,7 +24,7 @@ C128, C64 = 0, 1
 OUT_G, OUT_BAND_SUM, OUT_LOSS, OUT_WANNIER = 1, 2, 4, 8
 
 EXPORTS = [
-    "ephw_ctx_create", "ephw_ctx_destroy", "ephw_ctx_check", "ephw_system_load",
+    "ephw_ctx_create", "ephw_ctx_destroy", "ephw_ctx_check", "ephw_ctx_set_limits", "ephw_ctx_memory", "ephw_system_load",
     "ephw_system_free", "ephw_system_set_g", "ephw_system_bytes", "ephw_bands", "ephw_phonons", "ephw_phase_sum_rp",
     "ephw_kset_create", "ephw_kset_free", "ephw_kset_bands", "ephw_interpolate", "ephw_degenerate_sums", "ephw_wannier_transform",
     "ephw_window_screen", "ephw_linewidth",
@@ -92,6 +92,8 @@ def lib() -> ctypes.CDLL:
         "ephw_ctx_create": [ctypes.c_int, pp],
         "ephw_ctx_destroy": [vp],
         "ephw_ctx_check": [vp, vp],
+        "ephw_ctx_set_limits": [vp, i64, i32],
+        "ephw_ctx_memory": [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
         "ephw_system_load": [vp, ctypes.POINTER(SystemDesc), pp],
         "ephw_system_free": [vp],
         "ephw_system_set_g": [vp, vp, vp],
@@ -149,6 +151,26 @@ def _ptr(t) -> Optional[int]:
     return t.data_ptr()
 
 
+def _g_shape(prec: int, g, where: str):
+    """(nq, nk, nm, nw) of a stored g [nq][nk][nm][nw][nw], after checking that
+    its element type is the one `prec` reads (c128 at FP64, c64 otherwise):
+    the kernels size their reads from prec, not from the tensor."""
+    import torch
+    want = torch.complex128 if prec == FP64 else torch.complex64
+    if g.dtype != want:
+        raise ValueError(f"{where}: g is {g.dtype}, precision {prec} reads {want}")
+    if g.dim() != 5 or g.shape[3] != g.shape[4]:
+        raise ValueError(f"{where}: g must be [nq][nk][nm][nw][nw], got {tuple(g.shape)}")
+    return g.shape[0], g.shape[1], g.shape[2], g.shape[3]
+
+
+def _expect(t, shape, name: str):
+    """A float64 device buffer of the given shape."""
+    import torch
+    if t.dtype != torch.float64 or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be float64 {tuple(shape)}, got {t.dtype} {tuple(t.shape)}")
+
+
 def _stream(stream) -> Optional[int]:
     import torch
     if stream is None:
@@ -169,6 +191,17 @@ class Context:
 
     def check(self, stream=None):
         _check(lib().ephw_ctx_check(self.handle, _stream(stream)), "ephw_ctx_check")
+
+    def set_limits(self, max_device_bytes: int = 0, max_sweeps: int = 40):
+        """Cap the device memory the context's objects may hold (0 = none) and
+        the Jacobi sweeps per eigensolve (see ephw_ctx_set_limits)."""
+        _check(lib().ephw_ctx_set_limits(self.handle, int(max_device_bytes), int(max_sweeps)), "ephw_ctx_set_limits")
+
+    def memory(self):
+        """(bytes held by the context's objects, cap or 0)"""
+        u, l = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().ephw_ctx_memory(self.handle, ctypes.byref(u), ctypes.byref(l)), "ephw_ctx_memory")
+        return u.value, l.value
 
     def close(self):
         if self.handle:
@@ -326,7 +359,11 @@ def linewidth(prec: int, g, eps_k, eps_kq, omega, gamma, *, temperature: float, 
               omega_min: float = 0.0, nq_total: int = 0, stream=None):
     """gamma[k][n] += phonon-limited linewidth from g [nq][nk][nm][nw][nw]
     (see ephw_linewidth); nq_total defaults to this chunk's q count."""
-    nq, nk, nm, nw = g.shape[0], g.shape[1], g.shape[2], g.shape[3]
+    nq, nk, nm, nw = _g_shape(prec, g, "linewidth")
+    _expect(eps_k, (nk, nw), "eps_k")
+    _expect(eps_kq, (nq, nk, nw), "eps_kq")
+    _expect(omega, (nq, nm), "omega")
+    _expect(gamma, (nk, nw), "gamma")
     _check(lib().ephw_linewidth(int(prec), _ptr(g), nq, nk, nm, nw, _ptr(eps_k), _ptr(eps_kq), _ptr(omega),
                                 float(temperature), float(mu), float(sigma), float(omega_min),
                                 int(nq_total or nq), _ptr(gamma), _stream(stream)), "ephw_linewidth")
@@ -343,7 +380,11 @@ def degenerate_sums(prec: int, g, eps_kq, eps_k, lam, out, rel_tol: float = 1e-6
     """out[q][k][nu][m][n] = |g|^2 summed over the degenerate blocks of nu, m, n.
     g [nq][nk][nm][nw][nw] (c128 at FP64, c64 otherwise), eps_kq [nq][nk][nw],
     eps_k [nk][nw], lam [nq][nm], out f64 shaped like g."""
-    nq, nk, nm, nw = g.shape[0], g.shape[1], g.shape[2], g.shape[3]
+    nq, nk, nm, nw = _g_shape(prec, g, "degenerate_sums")
+    _expect(eps_kq, (nq, nk, nw), "eps_kq")
+    _expect(eps_k, (nk, nw), "eps_k")
+    _expect(lam, (nq, nm), "lam")
+    _expect(out, (nq, nk, nm, nw, nw), "out")
     _check(lib().ephw_degenerate_sums(int(prec), _ptr(g), nq, nk, nm, nw, _ptr(eps_kq), _ptr(eps_k), _ptr(lam),
                                       float(rel_tol), _ptr(out), _stream(stream)), "ephw_degenerate_sums")
 

@@ -129,7 +129,8 @@ def decaying_g(r_e: np.ndarray, r_p: np.ndarray, nm: int, nw: int,
     # draw one Rp slab at a time to bound host memory on large systems
     for p in range(npp):
         x = gen.standard_normal((ne, nm, nw, nw, 2), dtype=real_t)
-        slab = (x[..., 0] + 1j * x[..., 1]).astype(dtype) * inv
+        # the trailing (re, im) pairs read as complex values in place
+        slab = x.view(dtype)[..., 0] * inv
         out[p] = slab * env[p][:, None, None, None].astype(real_t)
     return out
 

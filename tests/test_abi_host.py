@@ -62,6 +62,8 @@ def test_null_arguments_rejected_before_any_device_call():
     assert L.ephw_phonons(None, None, 3, None, None, None, None) == ephw.EINVAL
     assert L.ephw_phase_sum_rp(None, None, 3, 0, None, None) == ephw.EINVAL
     assert L.ephw_ctx_create(0, None) == ephw.EINVAL
+    assert L.ephw_ctx_set_limits(None, 0, 40) == ephw.EINVAL
+    assert L.ephw_ctx_memory(None, None, None) == ephw.EINVAL
     # freeing NULL handles is a no-op
     assert L.ephw_system_free(None) == ephw.OK
     assert L.ephw_kset_free(None) == ephw.OK
@@ -110,3 +112,26 @@ def test_stage_counts_sum_to_the_reassociated_nested_loop():
     assert c.elems == 8000 * 8000 * 384
     # the Re sum dominates the dense Si workload (about 88 % of the cMAC)
     assert 0.85 < c.re / c.total < 0.9
+
+
+def test_wrappers_check_buffer_types_before_the_call():
+    """The kernels size their reads of g from the precision argument: the
+    binding refuses a g whose element type that precision does not read, and
+    side buffers of the wrong shape or type, before calling the library."""
+    import torch
+    g = torch.zeros((2, 3, 6, 4, 4), dtype=torch.complex64)
+    eps_k = torch.zeros((3, 4), dtype=torch.float64)
+    eps_kq = torch.zeros((2, 3, 4), dtype=torch.float64)
+    om = torch.zeros((2, 6), dtype=torch.float64)
+    gamma = torch.zeros((3, 4), dtype=torch.float64)
+    with pytest.raises(ValueError, match="reads"):
+        ephw.linewidth(ephw.FP64, g, eps_k, eps_kq, om, gamma, temperature=0.1, mu=0.0, sigma=0.1)
+    with pytest.raises(ValueError, match="eps_kq"):
+        ephw.linewidth(ephw.FP32, g, eps_k, eps_kq[:, :2], om, gamma, temperature=0.1, mu=0.0, sigma=0.1)
+    with pytest.raises(ValueError, match="gamma"):
+        ephw.linewidth(ephw.FP32, g, eps_k, eps_kq, om, gamma.float(), temperature=0.1, mu=0.0, sigma=0.1)
+    out = torch.zeros((2, 3, 6, 4, 4), dtype=torch.float64)
+    with pytest.raises(ValueError, match="reads"):
+        ephw.degenerate_sums(ephw.FP64, g, eps_kq, eps_k, om, out)
+    with pytest.raises(ValueError, match="lam"):
+        ephw.degenerate_sums(ephw.FP32, g, eps_kq, eps_k, om[:, :3], out)
