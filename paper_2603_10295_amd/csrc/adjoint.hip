@@ -698,17 +698,17 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
   // ---- k side: eigenvector derivatives and scaled phases (cached in the k-set) ----
   if (!ks->dv) {
     void* p = nullptr;
-    EPHW_TRY(dev_alloc(&p, (size_t)3 * nk * nw2 * 16, &s->ctx->mem));
+    EPHW_TRY(dev_alloc(&p, (size_t)3 * nk * nw2 * 16, ks->mem.get()));
     ks->dv64 = static_cast<double*>(p);
     ks->bytes += (int64_t)3 * nk * nw2 * 16;
     if (kind == 1) {
-      EPHW_TRY(dev_alloc(&p, (size_t)3 * nk * nw2 * 8, &s->ctx->mem));
+      EPHW_TRY(dev_alloc(&p, (size_t)3 * nk * nw2 * 8, ks->mem.get()));
       ks->dv = p;
       ks->bytes += (int64_t)3 * nk * nw2 * 8;
     } else {
       ks->dv = ks->dv64;
     }
-    EPHW_TRY(dev_alloc(&p, (size_t)3 * nk * ne * cs, &s->ctx->mem));
+    EPHW_TRY(dev_alloc(&p, (size_t)3 * nk * ne * cs, ks->mem.get()));
     ks->dpk = p;
     ks->bytes += (int64_t)3 * nk * ne * cs;
     EPHW_TRY(eigvec_derivatives(s, ks->pkh, s->r_h, nk, s->nh, s->h_r, (int)nw, ks->eps, ks->v64, ks->dv64,

@@ -118,7 +118,7 @@ ephw_status ephw_ctx_set_limits(ephw_ctx* ctx, int64_t max_device_bytes, int32_t
   EPHW_HIP(hipDeviceSynchronize());   // no kernel of the context reads the limit meanwhile
   const uint32_t sweeps = (uint32_t)max_sweeps;
   EPHW_HIP(hipMemcpy(ctx->status + 1, &sweeps, sizeof(sweeps), hipMemcpyHostToDevice));
-  ctx->mem.limit = max_device_bytes;
+  ctx->mem->limit = max_device_bytes;
   return EPHW_OK;
 }
 
@@ -127,8 +127,8 @@ ephw_status ephw_ctx_memory(const ephw_ctx* ctx, int64_t* used, int64_t* limit) 
     set_error("ephw_ctx_memory: ctx is NULL");
     return EPHW_EINVAL;
   }
-  if (used) *used = ctx->mem.used.load();
-  if (limit) *limit = ctx->mem.limit;
+  if (used) *used = ctx->mem->used.load();
+  if (limit) *limit = ctx->mem->limit;
   return EPHW_OK;
 }
 
@@ -168,7 +168,7 @@ ephw_status ephw_system_free(ephw_system* s) {
     if (p) (void)hipFree(p);
   for (auto& b : s->ws)
     if (b.p) (void)hipFree(b.p);
-  dev_release(&s->ctx->mem, s->bytes);
+  dev_release(s->mem.get(), s->bytes);
   for (auto& r : s->prof.recs) {
     (void)hipEventDestroy(r.a);
     (void)hipEventDestroy(r.b);
@@ -205,6 +205,7 @@ ephw_status ephw_system_load(ephw_ctx* ctx, const ephw_system_desc* d, ephw_syst
   EPHW_HIP(hipSetDevice(ctx->device));
   ephw_system* s = new ephw_system();
   s->ctx = ctx;
+  s->mem = ctx->mem;
   s->nw = d->nw;
   s->na = d->na;
   s->nm = 3 * d->na;
@@ -219,24 +220,24 @@ ephw_status ephw_system_load(ephw_ctx* ctx, const ephw_system_desc* d, ephw_syst
     ephw_system_free(s);
     return e;
   };
-  if ((st = upload(&s->r_e, d->r_e, 3 * d->ne, &s->bytes, &ctx->mem)) != EPHW_OK) return fail(st);
-  if ((st = upload(&s->r_p, d->r_p, 3 * d->np, &s->bytes, &ctx->mem)) != EPHW_OK) return fail(st);
-  if ((st = upload(&s->r_h, d->r_h, 3 * d->nh, &s->bytes, &ctx->mem)) != EPHW_OK) return fail(st);
-  if ((st = upload(&s->r_c, d->r_c, 3 * d->nc, &s->bytes, &ctx->mem)) != EPHW_OK) return fail(st);
+  if ((st = upload(&s->r_e, d->r_e, 3 * d->ne, &s->bytes, s->mem.get())) != EPHW_OK) return fail(st);
+  if ((st = upload(&s->r_p, d->r_p, 3 * d->np, &s->bytes, s->mem.get())) != EPHW_OK) return fail(st);
+  if ((st = upload(&s->r_h, d->r_h, 3 * d->nh, &s->bytes, s->mem.get())) != EPHW_OK) return fail(st);
+  if ((st = upload(&s->r_c, d->r_c, 3 * d->nc, &s->bytes, s->mem.get())) != EPHW_OK) return fail(st);
   auto weights = [&](double** dst, const double* w, int64_t n) {
     std::vector<double> ones;
     if (!w) {
       ones.assign((size_t)n, 1.0);
       w = ones.data();
     }
-    return upload(dst, w, (size_t)n, &s->bytes, &ctx->mem);
+    return upload(dst, w, (size_t)n, &s->bytes, s->mem.get());
   };
   if ((st = weights(&s->w_e, d->w_e, d->ne)) != EPHW_OK) return fail(st);
   if ((st = weights(&s->w_p, d->w_p, d->np)) != EPHW_OK) return fail(st);
   if ((st = weights(&s->w_h, d->w_h, d->nh)) != EPHW_OK) return fail(st);
   if ((st = weights(&s->w_c, d->w_c, d->nc)) != EPHW_OK) return fail(st);
   if ((st = upload(&s->h_r, static_cast<const double*>(d->h_r), (size_t)2 * d->nh * d->nw * d->nw,
-                   &s->bytes, &ctx->mem)) != EPHW_OK)
+                   &s->bytes, s->mem.get())) != EPHW_OK)
     return fail(st);
   {
     // C(R) / sqrt(M_kappa M_kappa') as complex128, the B operand of D(q)
@@ -249,12 +250,12 @@ ephw_status ephw_system_load(ephw_ctx* ctx, const ephw_system_desc* d, ephw_syst
           cs[2 * i] = d->c_r[i] * ism[a] * ism[b];
           cs[2 * i + 1] = 0.0;
         }
-    if ((st = upload(&s->c_scaled, cs.data(), cs.size(), &s->bytes, &ctx->mem)) != EPHW_OK) return fail(st);
-    if ((st = upload(&s->ism, ism.data(), ism.size(), &s->bytes, &ctx->mem)) != EPHW_OK) return fail(st);
+    if ((st = upload(&s->c_scaled, cs.data(), cs.size(), &s->bytes, s->mem.get())) != EPHW_OK) return fail(st);
+    if ((st = upload(&s->ism, ism.data(), ism.size(), &s->bytes, s->mem.get())) != EPHW_OK) return fail(st);
   }
   {
     const size_t gbytes = (size_t)d->np * d->ne * nm * d->nw * d->nw * csize(s->g_kind);
-    if ((st = dev_alloc(&s->g, gbytes, &ctx->mem)) != EPHW_OK) return fail(st);
+    if ((st = dev_alloc(&s->g, gbytes, s->mem.get())) != EPHW_OK) return fail(st);
     s->bytes += (int64_t)gbytes;
     if (hipMemcpy(s->g, d->g, gbytes, hipMemcpyHostToDevice) != hipSuccess) {
       set_error("ephw_system_load: upload of g failed");
@@ -448,7 +449,7 @@ ephw_status ephw_kset_free(ephw_kset* ks) {
                   ks->dv != ks->dv64 ? ks->dv : nullptr};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
-  dev_release(&ks->sys->ctx->mem, ks->bytes);
+  dev_release(ks->mem.get(), ks->bytes);
   delete ks;
   return EPHW_OK;
 }
@@ -472,12 +473,13 @@ ephw_status ephw_kset_create(ephw_system* s, const double* k, int64_t nk, int32_
   hipStream_t st = as_stream(stream);
   ephw_kset* ks = new ephw_kset();
   ks->sys = s;
+  ks->mem = s->mem;
   ks->nk = nk;
   ks->prec = prec;
   const int64_t nw2 = (int64_t)s->nw * s->nw;
   ephw_status e = EPHW_OK;
   auto alloc = [&](void** p, size_t bytes) {
-    ephw_status r = dev_alloc(p, bytes, &s->ctx->mem);
+    ephw_status r = dev_alloc(p, bytes, ks->mem.get());
     if (r == EPHW_OK) ks->bytes += (int64_t)bytes;
     return r;
   };

@@ -67,6 +67,7 @@ struct Launch {
 
 struct ephw_batch {
   ephw_ctx* ctx = nullptr;
+  std::shared_ptr<MemBudget> mem;   // the context's budget
   int kind = 0;
   std::vector<ItemPlan> items;
   void* ws = nullptr;
@@ -251,7 +252,7 @@ ephw_status tune_item(ItemPlan& it, int kind, int64_t cap, bool measure, hipStre
     need = std::max(need, it.bytes());
   }
   void* tmp = nullptr;
-  EPHW_TRY(dev_alloc(&tmp, need, &it.sys->ctx->mem));
+  EPHW_TRY(dev_alloc(&tmp, need, it.sys->mem.get()));
   hipEvent_t a = nullptr, b = nullptr;
   ephw_status rc = EPHW_OK;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) rc = EPHW_EDEVICE;
@@ -286,7 +287,7 @@ ephw_status tune_item(ItemPlan& it, int kind, int64_t cap, bool measure, hipStre
   if (b) (void)hipEventDestroy(b);
   (void)hipStreamSynchronize(st);
   (void)hipFree(tmp);
-  dev_release(&it.sys->ctx->mem, (int64_t)need);
+  dev_release(it.sys->mem.get(), (int64_t)need);
   if (rc != EPHW_OK) return rc;
   set_shape(it, best_q, k_tile_for(it, best_q, cap));
   *us_per_kpair = best;
@@ -581,11 +582,11 @@ ephw_status ephw_batch_free(ephw_batch* b) {
   if (b->cap) (void)hipStreamDestroy(b->cap);
   if (b->ws) {
     (void)hipFree(b->ws);
-    dev_release(&b->ctx->mem, (int64_t)b->ws_bytes);
+    dev_release(b->mem.get(), (int64_t)b->ws_bytes);
   }
   if (b->desc) {
     (void)hipFree(b->desc);
-    dev_release(&b->ctx->mem, (int64_t)b->desc_bytes);
+    dev_release(b->mem.get(), (int64_t)b->desc_bytes);
   }
   delete b;
   return EPHW_OK;
@@ -604,6 +605,7 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
   hipStream_t st = as_stream(stream);
   ephw_batch* bt = new ephw_batch();
   bt->ctx = ctx;
+  bt->mem = ctx->mem;
   auto fail = [&](ephw_status e) {
     ephw_batch_free(bt);
     return e;
@@ -709,7 +711,7 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
   // workspace
   size_t total = 0;
   for (auto& it : bt->items) total += it.bytes();
-  ephw_status e = dev_alloc(&bt->ws, total, &ctx->mem);
+  ephw_status e = dev_alloc(&bt->ws, total, bt->mem.get());
   if (e != EPHW_OK) return fail(e);
   bt->ws_bytes = total;
   {
@@ -725,7 +727,7 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
   build_launches(bt, hd, fix);
   const size_t qoff = align256(hd.bytes.size());
   hd.bytes.resize(qoff + (size_t)std::max(1, bt->nqueue) * kGroupQueues * sizeof(int), 0);
-  if ((e = dev_alloc(&bt->desc, hd.bytes.size(), &ctx->mem)) != EPHW_OK) return fail(e);
+  if ((e = dev_alloc(&bt->desc, hd.bytes.size(), bt->mem.get())) != EPHW_OK) return fail(e);
   bt->desc_bytes = hd.bytes.size();
   bt->queues = reinterpret_cast<int*>(static_cast<char*>(bt->desc) + qoff);
   if (hipMemcpy(bt->desc, hd.bytes.data(), hd.bytes.size(), hipMemcpyHostToDevice) != hipSuccess) {

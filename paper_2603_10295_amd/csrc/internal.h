@@ -2,6 +2,7 @@
 #pragma once
 
 #include <atomic>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -89,7 +90,9 @@ struct ephw_ctx {
   // device words: [0] status bits raised by kernels, [1] sweep limit of the
   // Jacobi eigensolves (read by the kernels at run time)
   uint32_t* status = nullptr;
-  MemBudget mem;
+  // shared with every object made on the context, so that objects freed
+  // after the context (in any order) still release their bytes safely
+  std::shared_ptr<MemBudget> mem = std::make_shared<MemBudget>();
 };
 
 enum WsSlot {
@@ -127,6 +130,7 @@ struct Profiler {
 
 struct ephw_system {
   ephw_ctx* ctx = nullptr;
+  std::shared_ptr<MemBudget> mem;   // the context's budget
   Profiler prof;
   int nw = 0, na = 0, nm = 0;
   int64_t ne = 0, np = 0, nh = 0, nc = 0;
@@ -145,6 +149,7 @@ struct ephw_system {
 
 struct ephw_kset {
   ephw_system* sys = nullptr;
+  std::shared_ptr<MemBudget> mem;   // the context's budget
   int64_t nk = 0;
   int32_t prec = 0;
   int64_t bytes = 0;
@@ -190,7 +195,7 @@ struct Stage {
 inline void* wsp(ephw_system* s, WsSlot slot) { return s->ws[slot].p; }
 
 inline ephw_status ws_need(ephw_system* s, WsSlot slot, size_t bytes) {
-  return grow(s->ws[slot], bytes, &s->bytes, &s->ctx->mem);
+  return grow(s->ws[slot], bytes, &s->bytes, s->mem.get());
 }
 
 inline hipStream_t as_stream(void* s) { return static_cast<hipStream_t>(s); }

@@ -111,28 +111,48 @@ def test_ribbon_shape_fp64_backward(run, golden):
     assert e_g < 1e-10 and e_s < 1e-10
     assert e_k < 1e-8 and e_q < 1e-8
 
-    # central differences (Richardson) of the GPU forward along the ribbon
-    # axis, with H(k+q) interpolated and diagonalised at the moved points
-    def loss_at(kk, qq):
-        ks2 = ephw.KSet(sysh, torch.from_numpy(kk).to("cuda:0"), ephw.FP64)
-        o = torch.zeros(1, dtype=torch.float64, device="cuda:0")
-        ephw.interpolate(ks2, torch.from_numpy(qq).to("cuda:0"), flags=ephw.OUT_LOSS, loss=o, loss_seed=LOSS_SEED)
-        run.ctx.check()
-        v = float(o.cpu()[0])
-        ks2.close()
-        return v
+    # Central differences (Richardson) of the GPU forward along the ribbon
+    # axis.  Above 32 bands the forward takes V(k+q) from a k grid, so the
+    # moved point k_i + h (or q_j + h) is evaluated with a k-set holding the
+    # grid and the grid shifted by h: every k + q of the moved configuration
+    # is then a point of the set.  The loss of the moved configuration is
+    # summed from the stored g with the loss weights of the unmoved one.
+    import oracle
+    from oracle import core
+    nk = len(w.k)
+    k8 = np.concatenate([w.k, w.k])
+    iq, ik = np.divmod(np.arange(nk * nk), nk)
+    wts = oracle.splitmix64_weights(LOSS_SEED, core.element_index(iq, ik, nk, s.nm, s.nw))
 
-    assert abs(loss_at(w.k, w.q) - got_loss) < 1e-11 * got_loss
+    def loss_moved(which, idx, x):
+        kk = k8.copy()
+        kk[nk:, 1] += x                                       # the shifted copy of the grid
+        qq = w.q.copy()
+        kqi8 = np.zeros((nk, 2 * nk), dtype=np.int32)
+        for j in range(nk):
+            for a in range(2 * nk):
+                kqi8[j, a] = (a % nk + j) % nk + (nk if a >= nk else 0)
+        sel = np.arange(nk)                                   # set position of each k_i
+        if which == "k":
+            sel[idx] = nk + idx
+        else:
+            qq[idx, 1] += x
+            kqi8[idx, :nk] += nk                              # k_a + q_idx + x = shifted grid point
+        ks2 = ephw.KSet(sysh, torch.from_numpy(kk).to("cuda:0"), ephw.FP64)
+        g = torch.empty((nk, 2 * nk, s.nm, s.nw, s.nw), dtype=torch.complex128, device="cuda:0")
+        ephw.interpolate(ks2, torch.from_numpy(qq).to("cuda:0"), kq_index=torch.from_numpy(kqi8).to("cuda:0"),
+                         flags=ephw.OUT_G, g_out=g)
+        run.ctx.check()
+        gh = g[:, torch.from_numpy(sel).to("cuda:0")].cpu().numpy()       # [q][k_i]
+        ks2.close()
+        return float(np.sum(wts * np.abs(gh.reshape(wts.shape)) ** 2))
+
+    assert abs(loss_moved("k", 0, 0.0) - got_loss) < 1e-11 * got_loss
     h = 1e-5
     worst = 0.0
     for which, idx in [("k", 1), ("k", 3), ("q", 0), ("q", 2)]:
-        def f(x):
-            kk, qq = w.k.copy(), w.q.copy()
-            (kk if which == "k" else qq)[idx, 1] = x
-            return loss_at(kk, qq)
-        x0 = (w.k if which == "k" else w.q)[idx, 1]
-        d1 = (f(x0 + h) - f(x0 - h)) / (2 * h)
-        d2 = (f(x0 + h / 2) - f(x0 - h / 2)) / h
+        d1 = (loss_moved(which, idx, h) - loss_moved(which, idx, -h)) / (2 * h)
+        d2 = (loss_moved(which, idx, h / 2) - loss_moved(which, idx, -h / 2)) / h
         fd = (4 * d2 - d1) / 3
         an = (dkh if which == "k" else dqh)[idx, 1]
         worst = max(worst, abs(fd - an) / scale)
