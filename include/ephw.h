@@ -204,6 +204,28 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
                              double* band_sum, double* loss, uint64_t loss_seed, double* eps_kq,
                              double* omega, void* stream);
 
+/* ephw_interpolate for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+   same arguments, outputs and results, but every intermediate buffer (phase
+   factors, mode vectors, the g(Re,q) sweeps, the Re-sum output, loss
+   partials, k+q eigensolves) lives in a static scratch array of the library,
+   256 MiB per device, which each device the library runs on holds until the
+   process ends.  No device memory is allocated or freed by the call.
+   - The q points are processed in batches small enough for the scratch (at
+     most the batch ephw_interpolate would take).  A call whose buffers do not
+     fit even at one q per batch returns EPHW_ENOMEM before enqueuing anything
+     (the per-call part grows with nq: split long q lists over calls).
+   - Every call on a device shares that device's scratch and leaves its
+     contents behind: calls that overlap on one device (different streams,
+     threads or processes sharing a context's device) race and must be
+     ordered by the caller.  Nothing in the scratch needs to start at zero.
+   - Systems with more than 32 bands return EPHW_EUNSUPPORTED.
+   - No stage events are recorded (ephw_profile_* does not see these calls). */
+ephw_status ephw_interpolate_noalloc(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index,
+                                     int64_t q_offset, int32_t prec, uint32_t flags, void* g_out,
+                                     double* band_sum, double* loss, uint64_t loss_seed, double* eps_kq,
+                                     double* omega, void* stream);
+
 /* Eq. (6): the coarse Bloch -> Wannier transform, the inverse of Eq. (7)
    when the k-set and the q list are the coarse grids commensurate with the
    Re and Rp sets (complete residue boxes, k'+q' on the k grid):

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -22,13 +23,12 @@ namespace {
 
 // FP64 interpolation + eigensolve: out_eps [n][dim], out_v c128 [n][dim][dim]
 // from A = phases [n][nr] (c128) and B = R-space matrices [nr][dim*dim] (c128).
-ephw_status interp_eigh(ephw_system* s, const double* phase, int64_t n, int64_t nr, const double* mats,
-                        int dim, double* out_eps, double* out_v, hipStream_t st) {
+// the same with caller-given buffers: hk [n][dim][dim] c128 and, for dim > 32,
+// jwork of jacobi_work_doubles(dim, n) doubles
+ephw_status interp_eigh_ws(ephw_system* s, const double* phase, int64_t n, int64_t nr, const double* mats, int dim,
+                           double* out_eps, double* out_v, double* hk, double* jwork, bool stages, hipStream_t st) {
   const int64_t d2 = (int64_t)dim * dim;
-  EPHW_TRY(ws_need(s, WS_HK, (size_t)n * d2 * 16));
-  const int64_t jw = jacobi_work_doubles(dim, n);
-  if (jw > 0) EPHW_TRY(ws_need(s, WS_JWORK, (size_t)jw * 8));
-  Stage sg_(s, EPHW_STAGE_EIG, st);
+  Stage sg_(s, EPHW_STAGE_EIG, st, stages);
   GemmParams p;
   p.M = n;
   p.N = d2;
@@ -37,11 +37,20 @@ ephw_status interp_eigh(ephw_system* s, const double* phase, int64_t n, int64_t 
   p.lda = nr;
   p.B = mats;
   p.ldb = d2;
-  p.C = wsp(s, WS_HK);
+  p.C = hk;
   p.ldc = d2;
   EPHW_TRY(cgemm(0, p, st));
-  return jacobi_eigh(static_cast<const double*>(wsp(s, WS_HK)), n, dim, out_eps, out_v,
-                     jw > 0 ? static_cast<double*>(wsp(s, WS_JWORK)) : nullptr, s->ctx->status, st);
+  return jacobi_eigh(hk, n, dim, out_eps, out_v, jwork, s->ctx->status, st);
+}
+
+ephw_status interp_eigh(ephw_system* s, const double* phase, int64_t n, int64_t nr, const double* mats,
+                        int dim, double* out_eps, double* out_v, hipStream_t st) {
+  const int64_t d2 = (int64_t)dim * dim;
+  EPHW_TRY(ws_need(s, WS_HK, (size_t)n * d2 * 16));
+  const int64_t jw = jacobi_work_doubles(dim, n);
+  if (jw > 0) EPHW_TRY(ws_need(s, WS_JWORK, (size_t)jw * 8));
+  return interp_eigh_ws(s, phase, n, nr, mats, dim, out_eps, out_v, static_cast<double*>(wsp(s, WS_HK)),
+                        jw > 0 ? static_cast<double*>(wsp(s, WS_JWORK)) : nullptr, true, st);
 }
 
 int32_t pick_q_batch(const ephw_system* s, int64_t nk, int64_t nq, int kind) {
@@ -534,113 +543,160 @@ ephw_status ephw_kset_bands(ephw_kset* ks, double* eps, void* vecs, void* stream
   return EPHW_OK;
 }
 
-ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index,
-                             int64_t q_offset, int32_t prec, uint32_t flags, void* g_out,
-                             double* band_sum, double* loss, uint64_t loss_seed, double* eps_kq,
-                             double* omega, void* stream) {
+}  // extern "C"
+
+// Static scratch of ephw_interpolate_noalloc: one copy per device, held from
+// the library's first use of a device to the end of the process.  Host code
+// never passes `scratch` itself to a kernel: it names the host-side shadow,
+// not the device copy; scratch_address() looks the device address up.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+// Device buffers of one interpolation call with Nw <= 32, carved from one
+// block (the system's workspace, or the static scratch of the entry point
+// that allocates nothing) in 256-byte aligned pieces.
+struct InterpWs {
+  void *pq = nullptr, *pq_lo = nullptr, *u = nullptr, *g = nullptr, *gnu = nullptr, *w = nullptr, *vkq = nullptr;
+  double *lam = nullptr, *e = nullptr, *pqc = nullptr, *hk = nullptr, *jwork = nullptr, *pqh = nullptr;
+  double *bq = nullptr, *hkq = nullptr, *ekq = nullptr, *vkq64 = nullptr, *loss = nullptr;
+  size_t bytes = 0;
+};
+
+// What a call needs, from its arguments (validated by the caller)
+struct InterpReq {
+  int64_t nk = 0, nq = 0;
+  int32_t prec = 0, qb = 1;
+  uint32_t flags = 0;
+  bool need_g = false, need_kq_eig = false;
+};
+
+InterpWs interp_layout(const ephw_system* s, const InterpReq& r, char* base) {
+  InterpWs w;
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return p;
+  };
+  auto takd = [&](size_t bytes) { return reinterpret_cast<double*>(take(bytes)); };
+  const int kind = prec_kind(r.prec);
+  const size_t cs = csize(kind);
+  const int64_t nw = s->nw, nm = s->nm, nw2 = nw * nw, E = nm * nw2, nk = r.nk, nq = r.nq, qb = r.qb;
+  w.pq = take((size_t)nq * s->np * cs);
+  if (r.prec == EPHW_FP32_SPLIT) w.pq_lo = take((size_t)nq * s->np * 8);
+  w.lam = takd((size_t)nq * nm * 8);
+  w.e = takd((size_t)nq * nm * nm * 16);
+  w.pqc = takd((size_t)nq * s->nc * 16);
+  w.hk = takd((size_t)nq * nm * nm * 16);
+  const int64_t jw_d = jacobi_work_doubles((int)nm, nq);
+  const int64_t jw_kq = r.need_kq_eig ? jacobi_work_doubles((int)nw, qb * nk) : 0;
+  const int64_t jw = jw_d > jw_kq ? jw_d : jw_kq;
+  if (jw > 0) w.jwork = takd((size_t)jw * 8);
+  w.u = take((size_t)nq * nm * nm * cs);
+  if (r.need_g) {
+    w.g = take((size_t)qb * s->ne * E * cs);
+    w.gnu = take((size_t)qb * s->ne * E * cs);
+    w.w = take((size_t)nk * qb * E * cs);
+  }
+  if (r.need_kq_eig) {
+    w.pqh = takd((size_t)nq * s->nh * 16);
+    w.bq = takd((size_t)qb * s->nh * nw2 * 16);
+    w.hkq = takd((size_t)qb * nk * nw2 * 16);
+    w.ekq = takd((size_t)qb * nk * nw * 8);
+    w.vkq64 = takd((size_t)qb * nk * nw2 * 16);
+    w.vkq = take((size_t)qb * nk * nw2 * cs);
+  }
+  if (r.flags & EPHW_OUT_LOSS) w.loss = takd((size_t)qb * nk * 8);
+  w.bytes = off;
+  return w;
+}
+
+// Host-side checks shared by both interpolation entry points; fills the request.
+ephw_status interp_validate(const char* who, ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index,
+                            int64_t q_offset, int32_t prec, uint32_t flags, void* g_out, double* band_sum,
+                            double* loss, double* eps_kq, double* omega, InterpReq* r) {
+  const std::string w(who);
   if (!ks || (!q && nq > 0) || nq < 0 || q_offset < 0) {
-    set_error("ephw_interpolate: invalid argument");
+    set_error(w + ": invalid argument");
     return EPHW_EINVAL;
   }
   if (prec != ks->prec) {
-    set_error("ephw_interpolate: precision differs from the k-set's");
+    set_error(w + ": precision differs from the k-set's");
     return EPHW_EINVAL;
   }
   const uint32_t known = EPHW_OUT_G | EPHW_OUT_BAND_SUM | EPHW_OUT_LOSS | EPHW_OUT_WANNIER;
   if (flags & ~known) {
-    set_error("ephw_interpolate: unknown output flag");
+    set_error(w + ": unknown output flag");
     return EPHW_EINVAL;
   }
   if (((flags & EPHW_OUT_G) && !g_out) || ((flags & EPHW_OUT_BAND_SUM) && !band_sum) ||
       ((flags & EPHW_OUT_LOSS) && !loss)) {
-    set_error("ephw_interpolate: a requested output buffer is NULL");
+    set_error(w + ": a requested output buffer is NULL");
     return EPHW_EINVAL;
   }
   if (!(flags & (EPHW_OUT_G | EPHW_OUT_BAND_SUM | EPHW_OUT_LOSS)) && !eps_kq && !omega) {
-    set_error("ephw_interpolate: nothing requested");
+    set_error(w + ": nothing requested");
     return EPHW_EINVAL;
   }
-  ephw_system* s = ks->sys;
   if ((flags & EPHW_OUT_WANNIER) && (flags & EPHW_OUT_LOSS)) {
-    set_error("ephw_interpolate: the loss is defined on the rotated g only");
+    set_error(w + ": the loss is defined on the rotated g only");
     return EPHW_EINVAL;
   }
-  if (nq == 0) return EPHW_OK;
-  if (s->nw > 32)
-    return interpolate_large(ks, q, nq, kq_index, q_offset, flags, g_out, band_sum, loss, loss_seed, eps_kq, omega,
-                             as_stream(stream));
-  hipStream_t st = as_stream(stream);
-  const int kind = prec_kind(prec);
-  const bool split = prec == EPHW_FP32_SPLIT;
+  const bool wannier = (flags & EPHW_OUT_WANNIER) != 0;
+  r->nk = ks->nk;
+  r->nq = nq;
+  r->prec = prec;
+  r->flags = flags;
+  r->need_g = (flags & (EPHW_OUT_G | EPHW_OUT_BAND_SUM | EPHW_OUT_LOSS)) != 0;
+  r->need_kq_eig = !kq_index && (!wannier || eps_kq);
+  return EPHW_OK;
+}
+
+// Eq. (7) for Nw <= 32 with every buffer in `w` (see interp_layout).
+ephw_status interpolate_small(ephw_kset* ks, const double* q, const int32_t* kq_index, int64_t q_offset,
+                              const InterpReq& r, void* g_out, double* band_sum, double* loss, uint64_t loss_seed,
+                              double* eps_kq, double* omega, const InterpWs& w, bool stages, hipStream_t st) {
+  ephw_system* s = ks->sys;
+  const int kind = prec_kind(r.prec);
+  const bool split = r.prec == EPHW_FP32_SPLIT;
+  const uint32_t flags = r.flags;
   const bool wannier = (flags & EPHW_OUT_WANNIER) != 0;
   const int nw = s->nw, nm = s->nm;
-  const int64_t nw2 = (int64_t)nw * nw, E = nm * nw2, nk = ks->nk;
+  const int64_t nw2 = (int64_t)nw * nw, E = nm * nw2, nk = ks->nk, nq = r.nq;
   const size_t cs = csize(kind);
-  const int32_t qb = pick_q_batch(s, nk, nq, kind);
+  const int32_t qb = r.qb;
 
   // --- per-call q side: Rp phases, D(q) eigensolve, mode vectors ----------
-  EPHW_TRY(ws_need(s, WS_PQ, (size_t)nq * s->np * cs));
-  if (split) EPHW_TRY(ws_need(s, WS_PQ_LO, (size_t)nq * s->np * 8));
   {
-    Stage sg_(s, EPHW_STAGE_PHASE, st);
-    EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, s->np, wsp(s, WS_PQ),
-                          split ? wsp(s, WS_PQ_LO) : nullptr, st));
+    Stage sg_(s, EPHW_STAGE_PHASE, st, stages);
+    EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, s->np, w.pq, split ? w.pq_lo : nullptr, st));
   }
-  EPHW_TRY(ws_need(s, WS_LAM, (size_t)nq * nm * 8));
-  EPHW_TRY(ws_need(s, WS_E, (size_t)nq * nm * nm * 16));
-  EPHW_TRY(ws_need(s, WS_PQC, (size_t)nq * s->nc * 16));
   {
-    Stage sg_(s, EPHW_STAGE_PHASE, st);
-    EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), nullptr, st));
+    Stage sg_(s, EPHW_STAGE_PHASE, st, stages);
+    EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, w.pqc, nullptr, st));
   }
-  EPHW_TRY(interp_eigh(s, static_cast<const double*>(wsp(s, WS_PQC)), nq, s->nc, s->c_scaled, nm,
-                       static_cast<double*>(wsp(s, WS_LAM)), static_cast<double*>(wsp(s, WS_E)), st));
+  EPHW_TRY(interp_eigh_ws(s, w.pqc, nq, s->nc, s->c_scaled, nm, w.lam, w.e, w.hk, w.jwork, stages, st));
   {
-    Stage sg_(s, EPHW_STAGE_OTHER, st);
-    if (omega) EPHW_TRY(abs_sqrt(static_cast<const double*>(wsp(s, WS_LAM)), omega, nq * nm, st));
+    Stage sg_(s, EPHW_STAGE_OTHER, st, stages);
+    if (omega) EPHW_TRY(abs_sqrt(w.lam, omega, nq * nm, st));
   }
-  EPHW_TRY(ws_need(s, WS_U, (size_t)nq * nm * nm * cs));
   {
-    Stage sg_(s, EPHW_STAGE_OTHER, st);
-    EPHW_TRY(mode_vectors(kind, static_cast<const double*>(wsp(s, WS_E)), nq, nm, s->ism,
-                          wsp(s, WS_U), st));
+    Stage sg_(s, EPHW_STAGE_OTHER, st, stages);
+    EPHW_TRY(mode_vectors(kind, w.e, nq, nm, s->ism, w.u, st));
   }
-  const bool need_g = (flags & (EPHW_OUT_G | EPHW_OUT_BAND_SUM | EPHW_OUT_LOSS)) != 0;
-  const bool need_kq_eig = !kq_index && (!wannier || eps_kq);
-
-  // --- per-batch workspaces -------------------------------------------------
-  if (need_g) {
-    EPHW_TRY(ws_need(s, WS_G, (size_t)qb * s->ne * E * cs));
-    EPHW_TRY(ws_need(s, WS_GNU, (size_t)qb * s->ne * E * cs));
-    EPHW_TRY(ws_need(s, WS_W, (size_t)nk * qb * E * cs));
-  }
-  if (need_kq_eig) {
-    EPHW_TRY(ws_need(s, WS_PQH, (size_t)nq * s->nh * 16));
-    {
-      Stage sg_(s, EPHW_STAGE_PHASE, st);
-      EPHW_TRY(phase_matrix(0, q, nq, s->r_h, nullptr, s->nh, wsp(s, WS_PQH), nullptr, st));
-    }
-    EPHW_TRY(ws_need(s, WS_BQ, (size_t)qb * s->nh * nw2 * 16));
-    EPHW_TRY(ws_need(s, WS_HKQ, (size_t)qb * nk * nw2 * 16));
-    EPHW_TRY(ws_need(s, WS_EKQ, (size_t)qb * nk * nw * 8));
-    EPHW_TRY(ws_need(s, WS_VKQ64, (size_t)qb * nk * nw2 * 16));
-    EPHW_TRY(ws_need(s, WS_VKQ, (size_t)qb * nk * nw2 * cs));
-    const int64_t jw = jacobi_work_doubles(nw, (int64_t)qb * nk);
-    if (jw > 0) EPHW_TRY(ws_need(s, WS_JWORK, (size_t)jw * 8));
-  }
-  double* loss_part = nullptr;
-  if (flags & EPHW_OUT_LOSS) {
-    EPHW_TRY(ws_need(s, WS_LOSS, (size_t)qb * nk * 8));
-    loss_part = static_cast<double*>(wsp(s, WS_LOSS));
+  if (r.need_kq_eig) {
+    Stage sg_(s, EPHW_STAGE_PHASE, st, stages);
+    EPHW_TRY(phase_matrix(0, q, nq, s->r_h, nullptr, s->nh, w.pqh, nullptr, st));
   }
 
   for (int64_t q0 = 0; q0 < nq; q0 += qb) {
     const int32_t nb = (int32_t)((nq - q0) < qb ? (nq - q0) : qb);
     // bands at k+q: H(k+q) = sum_R e^{2 pi i k.R} (e^{2 pi i q.R} H(R)), then FP64 Jacobi
-    if (need_kq_eig) {
-      Stage sg_(s, EPHW_STAGE_KQ_EIG, st);
-      EPHW_TRY(scale_rows_by_phase(static_cast<const double*>(wsp(s, WS_PQH)) + 2 * q0 * s->nh, nb,
-                                   s->h_r, s->nh, nw2, static_cast<double*>(wsp(s, WS_BQ)), st));
+    if (r.need_kq_eig) {
+      Stage sg_(s, EPHW_STAGE_KQ_EIG, st, stages);
+      EPHW_TRY(scale_rows_by_phase(w.pqh + 2 * q0 * s->nh, nb, s->h_r, s->nh, nw2, w.bq, st));
       GemmParams h;
       h.M = nk;
       h.N = nw2;
@@ -649,53 +705,44 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
       h.A = ks->pkh;
       h.lda = s->nh;
       h.strideA = 0;
-      h.B = wsp(s, WS_BQ);
+      h.B = w.bq;
       h.ldb = nw2;
       h.strideB = s->nh * nw2;
-      h.C = wsp(s, WS_HKQ);
+      h.C = w.hkq;
       h.ldc = nw2;
       h.strideC = nk * nw2;
       EPHW_TRY(cgemm(0, h, st));
-      double* ekq = eps_kq ? eps_kq + q0 * nk * nw : static_cast<double*>(wsp(s, WS_EKQ));
-      const int64_t jw = jacobi_work_doubles(nw, (int64_t)nb * nk);
-      EPHW_TRY(jacobi_eigh(static_cast<const double*>(wsp(s, WS_HKQ)), (int64_t)nb * nk, nw, ekq,
-                           static_cast<double*>(wsp(s, WS_VKQ64)),
-                           jw > 0 ? static_cast<double*>(wsp(s, WS_JWORK)) : nullptr,
-                           s->ctx->status, st));
-      EPHW_TRY(cast_complex(kind, static_cast<const double*>(wsp(s, WS_VKQ64)), wsp(s, WS_VKQ),
-                            (int64_t)nb * nk * nw2, st));
+      double* ekq = eps_kq ? eps_kq + q0 * nk * nw : w.ekq;
+      EPHW_TRY(jacobi_eigh(w.hkq, (int64_t)nb * nk, nw, ekq, w.vkq64, w.jwork, s->ctx->status, st));
+      EPHW_TRY(cast_complex(kind, w.vkq64, w.vkq, (int64_t)nb * nk * nw2, st));
     } else if (eps_kq && kq_index) {
       // k+q on the k grid: its bands are the k-set's bands at the indexed point
-      {
-        Stage sg_(s, EPHW_STAGE_OTHER, st);
-        EPHW_TRY(gather_rows(ks->eps, nk, kq_index + q0 * nk, (int64_t)nb * nk, nw,
-                             eps_kq + q0 * nk * nw, s->ctx->status, st));
-      }
+      Stage sg_(s, EPHW_STAGE_OTHER, st, stages);
+      EPHW_TRY(gather_rows(ks->eps, nk, kq_index + q0 * nk, (int64_t)nb * nk, nw, eps_kq + q0 * nk * nw,
+                           s->ctx->status, st));
     }
-    if (!need_g) continue;
+    if (!r.need_g) continue;
     // Eq. (9): G[q][Re, ka, m', n'] = sum_Rp e^{i q.Rp} g(Re, Rp)
     GemmParams rp;
     rp.M = nb;
     rp.N = s->ne * E;
     rp.K = s->np;
-    rp.A = static_cast<const char*>(wsp(s, WS_PQ)) + (size_t)q0 * s->np * cs;
-    rp.A_lo = split ? static_cast<const char*>(wsp(s, WS_PQ_LO)) + (size_t)q0 * s->np * 8 : nullptr;
+    rp.A = static_cast<const char*>(w.pq) + (size_t)q0 * s->np * cs;
+    rp.A_lo = split ? static_cast<const char*>(w.pq_lo) + (size_t)q0 * s->np * 8 : nullptr;
     rp.lda = s->np;
     rp.B = s->g;
     rp.ldb = rp.N;
-    rp.C = wsp(s, WS_G);
+    rp.C = w.g;
     rp.ldc = rp.N;
     {
-      Stage sg_(s, EPHW_STAGE_RP_GEMM, st);
+      Stage sg_(s, EPHW_STAGE_RP_GEMM, st, stages);
       EPHW_TRY(cgemm(kind, rp, st));
     }
     // mode vectors u(q), hoisted to the g(Re,q) level; output [Re][q][nu][m'][n']
     {
-      Stage sg_(s, EPHW_STAGE_MODE_ROT, st);
-      EPHW_TRY(mode_rotate(kind, wsp(s, WS_G),
-                           wannier ? nullptr
-                                   : static_cast<const char*>(wsp(s, WS_U)) + (size_t)q0 * nm * nm * cs,
-                           wsp(s, WS_GNU), s->ne, nb, nm, nw2, st));
+      Stage sg_(s, EPHW_STAGE_MODE_ROT, st, stages);
+      EPHW_TRY(mode_rotate(kind, w.g, wannier ? nullptr : static_cast<const char*>(w.u) + (size_t)q0 * nm * nm * cs,
+                           w.gnu, s->ne, nb, nm, nw2, st));
     }
     // Eq. (10), Re part: W[k][q nu m' n'] = sum_Re e^{i k.Re} G_nu(Re, q)
     GemmParams re;
@@ -705,19 +752,19 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
     re.A = ks->pk;
     re.A_lo = split ? ks->pk_lo : nullptr;
     re.lda = s->ne;
-    re.B = wsp(s, WS_GNU);
+    re.B = w.gnu;
     re.ldb = re.N;
-    re.C = wsp(s, WS_W);
+    re.C = w.w;
     re.ldc = re.N;
     {
-      Stage sg_(s, EPHW_STAGE_RE_GEMM, st);
+      Stage sg_(s, EPHW_STAGE_RE_GEMM, st, stages);
       EPHW_TRY(cgemm(kind, re, st));
     }
     // band rotations V(k+q)^dagger W V(k) and the epilogues
     BandRotateArgs br;
-    br.W = wsp(s, WS_W);
+    br.W = w.w;
     br.Vk = wannier ? nullptr : ks->vt;
-    br.Vkq = kq_index ? nullptr : wsp(s, WS_VKQ);
+    br.Vkq = kq_index ? nullptr : w.vkq;
     br.kq_index = kq_index ? kq_index + q0 * nk : nullptr;
     br.nk = nk;
     br.k0 = 0;
@@ -728,20 +775,99 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
     br.flags = flags;
     br.g_out = (flags & EPHW_OUT_G) ? static_cast<char*>(g_out) + (size_t)q0 * nk * E * cs : nullptr;
     br.band_sum = (flags & EPHW_OUT_BAND_SUM) ? band_sum + q0 * nk * nm : nullptr;
-    br.loss_partial = loss_part;
+    br.loss_partial = w.loss;
     br.loss_seed = loss_seed;
     br.q_global0 = q_offset + q0;
     br.status = s->ctx->status;
     {
-      Stage sg_(s, EPHW_STAGE_BAND_ROT, st);
+      Stage sg_(s, EPHW_STAGE_BAND_ROT, st, stages);
       EPHW_TRY(band_rotate(kind, br, st));
     }
     {
-      Stage sg_(s, EPHW_STAGE_OTHER, st);
-      if (flags & EPHW_OUT_LOSS) EPHW_TRY(sum_into(loss_part, (int64_t)nb * nk, loss, st));
+      Stage sg_(s, EPHW_STAGE_OTHER, st, stages);
+      if (flags & EPHW_OUT_LOSS) EPHW_TRY(sum_into(w.loss, (int64_t)nb * nk, loss, st));
     }
   }
   return EPHW_OK;
+}
+
+// Device address of `scratch` on the current device, looked up once per device.
+ephw_status scratch_address(int device, char** out) {
+  static std::mutex mu;
+  static std::map<int, char*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(device);
+  if (it != addr.end()) {
+    *out = it->second;
+    return EPHW_OK;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    set_error(std::string("hipGetSymbolAddress of the scratch array failed: ") + hipGetErrorString(e));
+    return EPHW_EDEVICE;
+  }
+  addr[device] = static_cast<char*>(p);
+  *out = static_cast<char*>(p);
+  return EPHW_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index,
+                             int64_t q_offset, int32_t prec, uint32_t flags, void* g_out,
+                             double* band_sum, double* loss, uint64_t loss_seed, double* eps_kq,
+                             double* omega, void* stream) {
+  InterpReq r;
+  EPHW_TRY(interp_validate("ephw_interpolate", ks, q, nq, kq_index, q_offset, prec, flags, g_out, band_sum, loss,
+                           eps_kq, omega, &r));
+  if (nq == 0) return EPHW_OK;
+  ephw_system* s = ks->sys;
+  if (s->nw > 32)
+    return interpolate_large(ks, q, nq, kq_index, q_offset, flags, g_out, band_sum, loss, loss_seed, eps_kq, omega,
+                             as_stream(stream));
+  r.qb = pick_q_batch(s, ks->nk, nq, prec_kind(prec));
+  const size_t need = interp_layout(s, r, nullptr).bytes;
+  EPHW_TRY(ws_need(s, WS_ARENA, need));
+  const InterpWs w = interp_layout(s, r, static_cast<char*>(wsp(s, WS_ARENA)));
+  return interpolate_small(ks, q, kq_index, q_offset, r, g_out, band_sum, loss, loss_seed, eps_kq, omega, w, true,
+                           as_stream(stream));
+}
+
+ephw_status ephw_interpolate_noalloc(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index,
+                                     int64_t q_offset, int32_t prec, uint32_t flags, void* g_out, double* band_sum,
+                                     double* loss, uint64_t loss_seed, double* eps_kq, double* omega, void* stream) {
+  InterpReq r;
+  EPHW_TRY(interp_validate("ephw_interpolate_noalloc", ks, q, nq, kq_index, q_offset, prec, flags, g_out, band_sum,
+                           loss, eps_kq, omega, &r));
+  if (nq == 0) return EPHW_OK;
+  ephw_system* s = ks->sys;
+  if (s->nw > 32) {
+    set_error("ephw_interpolate_noalloc: systems with more than 32 bands are not supported");
+    return EPHW_EUNSUPPORTED;
+  }
+  // the largest q batch (up to the one ephw_interpolate would take) whose
+  // buffers fit the scratch; the per-call buffers grow with nq, not with it
+  int32_t qb = pick_q_batch(s, ks->nk, nq, prec_kind(prec));
+  for (;;) {
+    r.qb = qb;
+    if (interp_layout(s, r, nullptr).bytes <= kScratchBytes) break;
+    if (qb == 1) {
+      set_error("ephw_interpolate_noalloc: the call needs " + std::to_string(interp_layout(s, r, nullptr).bytes) +
+                " bytes of scratch at one q per batch, more than the " + std::to_string(kScratchBytes) +
+                " bytes the library holds");
+      return EPHW_ENOMEM;
+    }
+    qb = qb / 2 > 0 ? qb / 2 : 1;
+  }
+  char* base = nullptr;
+  EPHW_TRY(scratch_address(s->ctx->device, &base));
+  const InterpWs w = interp_layout(s, r, base);
+  return interpolate_small(ks, q, kq_index, q_offset, r, g_out, band_sum, loss, loss_seed, eps_kq, omega, w, false,
+                           as_stream(stream));
 }
 
 ephw_status ephw_degenerate_sums(int32_t prec, const void* g, int64_t nq, int64_t nk, int32_t nm, int32_t nw,

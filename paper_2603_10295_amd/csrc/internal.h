@@ -104,7 +104,9 @@ enum WsSlot {
   // coarse Bloch -> Wannier transform
   WS_CPK, WS_UINV,
   // energy-window screen
-  WS_WINDOW, WS_COUNT
+  WS_WINDOW,
+  // the buffers of an interpolation call (Nw <= 32) in one block
+  WS_ARENA, WS_COUNT
 };
 
 // HIP-event brackets around the stages of a call, summed on request
@@ -173,8 +175,8 @@ struct Stage {
   int stage;
   hipStream_t st;
   hipEvent_t a = nullptr;
-  Stage(ephw_system* s, int stage_, hipStream_t st_) : p(&s->prof), stage(stage_), st(st_) {
-    if (p->on) {
+  Stage(ephw_system* s, int stage_, hipStream_t st_, bool enabled = true) : p(&s->prof), stage(stage_), st(st_) {
+    if (enabled && p->on) {
       a = p->get();
       if (a) (void)hipEventRecord(a, st);
     }
