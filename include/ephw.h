@@ -297,6 +297,23 @@ ephw_status ephw_linewidth(int32_t prec, const void* g, int64_t nq, int64_t nk, 
                            double mu, double sigma, double omega_min, int64_t nq_total, double* gamma,
                            void* stream);
 
+/* The reduction of ephw_linewidth applied to Eq. (7)'s matrix elements as they
+   are formed, without storing them (the way the paper's self-energy runs
+   consume g): gamma[k][n] += the sum over this q list, with the weights, the
+   1/(2 omega) amplitude and the parameters of ephw_linewidth, of
+   |g_{mn nu}(k,q)|^2 for every point k of the set.  eps_k, eps_kq and omega are
+   the library's own (the k-set's bands, the bands at k+q, sqrt(|lambda(q)|)).
+   For FP32 k-sets with Nw of 4 or 8 the rotations and the reduction run in the
+   epilogue of the Eq. (10) GEMM; otherwise each q batch's g goes through a
+   library workspace and the ephw_linewidth kernel.  Per-batch sums are added
+   in a fixed order (deterministic).
+     kq_index  [nq][nk] int32 or NULL, as in ephw_interpolate
+     gamma     [nk][nw] f64 (device), accumulated (+=)
+   Systems with more than 32 bands return EPHW_EUNSUPPORTED. */
+ephw_status ephw_interpolate_linewidth(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index,
+                                       double temperature, double mu, double sigma, double omega_min,
+                                       int64_t nq_total, double* gamma, void* stream);
+
 /* Gauge-invariant |g|^2 of stored matrix elements (the quantity Eq. (7)'s
    results are compared by: eigenvectors of (near-)degenerate eigenvalues are
    fixed only up to a unitary mixing inside their block).  For every pair,

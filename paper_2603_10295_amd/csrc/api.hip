@@ -561,6 +561,8 @@ struct InterpWs {
   void *pq = nullptr, *pq_lo = nullptr, *u = nullptr, *g = nullptr, *gnu = nullptr, *w = nullptr, *vkq = nullptr;
   double *lam = nullptr, *e = nullptr, *pqc = nullptr, *hk = nullptr, *jwork = nullptr, *pqh = nullptr;
   double *bq = nullptr, *hkq = nullptr, *ekq = nullptr, *vkq64 = nullptr, *loss = nullptr;
+  void* gchunk = nullptr;                          // rotated g of a batch for the linewidth (unfused)
+  double *om = nullptr, *lwp = nullptr;            // omega [nq][nm]; fused linewidth partials
   size_t bytes = 0;
 };
 
@@ -570,7 +572,23 @@ struct InterpReq {
   int32_t prec = 0, qb = 1;
   uint32_t flags = 0;
   bool need_g = false, need_kq_eig = false;
+  bool fused = false;        // band rotations in the Re-sum GEMM's epilogue (no W buffer)
+  bool lw = false;           // linewidth reduction of the rotated g (no g output)
+  LwParams lwp;              // its kernel parameters, from the arguments below
+  double temperature = 0, mu = 0, sigma = 0, omega_min = 0;
+  int64_t nq_total = 0;
+  double* gamma = nullptr;
 };
+
+// Whether every q batch of the call can take the fused band epilogue: FP32
+// without split phases, rotated output, and a Re-sum GEMM that runs on the
+// default 128x128 tile for both the full and the last batch.
+bool interp_fusable(const ephw_system* s, const InterpReq& r) {
+  if (r.prec != EPHW_FP32 || (r.flags & EPHW_OUT_WANNIER) || !r.need_g) return false;
+  const int64_t E = (int64_t)s->nm * s->nw * s->nw, tail = r.nq % r.qb;
+  return cgemm_band_fusable(1, r.nk, r.qb * E, s->nw, s->ne, r.qb * E) &&
+         (tail == 0 || cgemm_band_fusable(1, r.nk, tail * E, s->nw, s->ne, tail * E));
+}
 
 InterpWs interp_layout(const ephw_system* s, const InterpReq& r, char* base) {
   InterpWs w;
@@ -598,17 +616,28 @@ InterpWs interp_layout(const ephw_system* s, const InterpReq& r, char* base) {
   if (r.need_g) {
     w.g = take((size_t)qb * s->ne * E * cs);
     w.gnu = take((size_t)qb * s->ne * E * cs);
-    w.w = take((size_t)nk * qb * E * cs);
+    if (!r.fused) w.w = take((size_t)nk * qb * E * cs);
   }
   if (r.need_kq_eig) {
     w.pqh = takd((size_t)nq * s->nh * 16);
     w.bq = takd((size_t)qb * s->nh * nw2 * 16);
     w.hkq = takd((size_t)qb * nk * nw2 * 16);
-    w.ekq = takd((size_t)qb * nk * nw * 8);
     w.vkq64 = takd((size_t)qb * nk * nw2 * 16);
     w.vkq = take((size_t)qb * nk * nw2 * cs);
   }
-  if (r.flags & EPHW_OUT_LOSS) w.loss = takd((size_t)qb * nk * 8);
+  if (r.need_kq_eig || r.lw) w.ekq = takd((size_t)qb * nk * nw * 8);
+  if (r.flags & EPHW_OUT_LOSS) {
+    // per pair (band-rotation kernel) or per tile (fused epilogue)
+    const int64_t tiles = ceil_div(nk, 128) * ceil_div(qb * E, 128);
+    w.loss = takd((size_t)(tiles > qb * nk ? tiles : qb * nk) * 8);
+  }
+  if (r.lw) {
+    w.om = takd((size_t)nq * nm * 8);
+    if (r.fused)
+      w.lwp = takd((size_t)ceil_div(qb * E, 64) * nk * nw * 8);
+    else
+      w.gchunk = take((size_t)qb * nk * E * cs);
+  }
   w.bytes = off;
   return w;
 }
@@ -681,6 +710,7 @@ ephw_status interpolate_small(ephw_kset* ks, const double* q, const int32_t* kq_
   {
     Stage sg_(s, EPHW_STAGE_OTHER, st, stages);
     if (omega) EPHW_TRY(abs_sqrt(w.lam, omega, nq * nm, st));
+    if (r.lw) EPHW_TRY(abs_sqrt(w.lam, w.om, nq * nm, st));
   }
   {
     Stage sg_(s, EPHW_STAGE_OTHER, st, stages);
@@ -693,6 +723,7 @@ ephw_status interpolate_small(ephw_kset* ks, const double* q, const int32_t* kq_
 
   for (int64_t q0 = 0; q0 < nq; q0 += qb) {
     const int32_t nb = (int32_t)((nq - q0) < qb ? (nq - q0) : qb);
+    const double* ekq_b = nullptr;   // bands at k+q of this batch, [nb][nk][nw]
     // bands at k+q: H(k+q) = sum_R e^{2 pi i k.R} (e^{2 pi i q.R} H(R)), then FP64 Jacobi
     if (r.need_kq_eig) {
       Stage sg_(s, EPHW_STAGE_KQ_EIG, st, stages);
@@ -715,11 +746,13 @@ ephw_status interpolate_small(ephw_kset* ks, const double* q, const int32_t* kq_
       double* ekq = eps_kq ? eps_kq + q0 * nk * nw : w.ekq;
       EPHW_TRY(jacobi_eigh(w.hkq, (int64_t)nb * nk, nw, ekq, w.vkq64, w.jwork, s->ctx->status, st));
       EPHW_TRY(cast_complex(kind, w.vkq64, w.vkq, (int64_t)nb * nk * nw2, st));
-    } else if (eps_kq && kq_index) {
+      ekq_b = ekq;
+    } else if ((eps_kq || r.lw) && kq_index) {
       // k+q on the k grid: its bands are the k-set's bands at the indexed point
       Stage sg_(s, EPHW_STAGE_OTHER, st, stages);
-      EPHW_TRY(gather_rows(ks->eps, nk, kq_index + q0 * nk, (int64_t)nb * nk, nw, eps_kq + q0 * nk * nw,
-                           s->ctx->status, st));
+      double* ekq = eps_kq ? eps_kq + q0 * nk * nw : w.ekq;
+      EPHW_TRY(gather_rows(ks->eps, nk, kq_index + q0 * nk, (int64_t)nb * nk, nw, ekq, s->ctx->status, st));
+      ekq_b = ekq;
     }
     if (!r.need_g) continue;
     // Eq. (9): G[q][Re, ka, m', n'] = sum_Rp e^{i q.Rp} g(Re, Rp)
@@ -756,6 +789,39 @@ ephw_status interpolate_small(ephw_kset* ks, const double* q, const int32_t* kq_
     re.ldb = re.N;
     re.C = w.w;
     re.ldc = re.N;
+    if (r.fused) {
+      // band rotations and epilogues in the GEMM's epilogue: W never leaves the tile
+      BandEpilogue& b = re.band;
+      b.on = true;
+      b.nw = nw;
+      b.nm = nm;
+      b.nk = nk;
+      b.q_global0 = q_offset + q0;
+      b.Vk = ks->vt;
+      b.Vkq = kq_index ? nullptr : w.vkq;
+      b.kq_index = kq_index ? kq_index + q0 * nk : nullptr;
+      b.flags = flags & (EPHW_OUT_G | EPHW_OUT_BAND_SUM | EPHW_OUT_LOSS);
+      b.g_out = (flags & EPHW_OUT_G) ? static_cast<char*>(g_out) + (size_t)q0 * nk * E * cs : nullptr;
+      b.band_sum = (flags & EPHW_OUT_BAND_SUM) ? band_sum + q0 * nk * nm : nullptr;
+      b.loss_partial = w.loss;
+      b.loss_seed = loss_seed;
+      if (r.lw) {
+        b.lw_partial = w.lwp;
+        b.eps_k = ks->eps;
+        b.eps_kq = ekq_b;
+        b.omega = w.om + q0 * nm;
+        b.lw = r.lwp;
+      }
+      b.status = s->ctx->status;
+      {
+        Stage sg_(s, EPHW_STAGE_RE_GEMM, st, stages);
+        EPHW_TRY(cgemm(kind, re, st));
+      }
+      Stage sg_(s, EPHW_STAGE_OTHER, st, stages);
+      if (flags & EPHW_OUT_LOSS) EPHW_TRY(sum_into(w.loss, ceil_div(re.M, 128) * ceil_div(re.N, 128), loss, st));
+      if (r.lw) EPHW_TRY(add_column_sums(w.lwp, ceil_div(re.N, 64), nk * nw, r.lwp.scale, r.gamma, st));
+      continue;
+    }
     {
       Stage sg_(s, EPHW_STAGE_RE_GEMM, st, stages);
       EPHW_TRY(cgemm(kind, re, st));
@@ -772,8 +838,9 @@ ephw_status interpolate_small(ephw_kset* ks, const double* q, const int32_t* kq_
     br.qb = nb;
     br.nm = nm;
     br.nw = nw;
-    br.flags = flags;
-    br.g_out = (flags & EPHW_OUT_G) ? static_cast<char*>(g_out) + (size_t)q0 * nk * E * cs : nullptr;
+    br.flags = r.lw ? (flags | EPHW_OUT_G) : flags;
+    br.g_out = r.lw ? w.gchunk
+                    : (flags & EPHW_OUT_G) ? static_cast<char*>(g_out) + (size_t)q0 * nk * E * cs : nullptr;
     br.band_sum = (flags & EPHW_OUT_BAND_SUM) ? band_sum + q0 * nk * nm : nullptr;
     br.loss_partial = w.loss;
     br.loss_seed = loss_seed;
@@ -786,6 +853,10 @@ ephw_status interpolate_small(ephw_kset* ks, const double* q, const int32_t* kq_
     {
       Stage sg_(s, EPHW_STAGE_OTHER, st, stages);
       if (flags & EPHW_OUT_LOSS) EPHW_TRY(sum_into(w.loss, (int64_t)nb * nk, loss, st));
+      if (r.lw) {
+        EPHW_TRY(linewidth(kind, w.gchunk, nb, nk, nm, nw, ks->eps, ekq_b, w.om + q0 * nm, r.temperature, r.mu,
+                           r.sigma, r.omega_min, r.nq_total, r.gamma, st));
+      }
     }
   }
   return EPHW_OK;
@@ -830,10 +901,50 @@ ephw_status ephw_interpolate(ephw_kset* ks, const double* q, int64_t nq, const i
     return interpolate_large(ks, q, nq, kq_index, q_offset, flags, g_out, band_sum, loss, loss_seed, eps_kq, omega,
                              as_stream(stream));
   r.qb = pick_q_batch(s, ks->nk, nq, prec_kind(prec));
+  r.fused = interp_fusable(s, r);
   const size_t need = interp_layout(s, r, nullptr).bytes;
   EPHW_TRY(ws_need(s, WS_ARENA, need));
   const InterpWs w = interp_layout(s, r, static_cast<char*>(wsp(s, WS_ARENA)));
   return interpolate_small(ks, q, kq_index, q_offset, r, g_out, band_sum, loss, loss_seed, eps_kq, omega, w, true,
+                           as_stream(stream));
+}
+
+ephw_status ephw_interpolate_linewidth(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index,
+                                       double temperature, double mu, double sigma, double omega_min,
+                                       int64_t nq_total, double* gamma, void* stream) {
+  if (!ks || (!q && nq > 0) || nq < 0 || !gamma || nq_total < 1 || !(temperature > 0.0) || !(sigma > 0.0) ||
+      !(omega_min >= 0.0) || !std::isfinite(mu) || !std::isfinite(temperature) || !std::isfinite(sigma) ||
+      !std::isfinite(omega_min)) {
+    set_error("ephw_interpolate_linewidth: invalid argument");
+    return EPHW_EINVAL;
+  }
+  if (nq == 0) return EPHW_OK;
+  ephw_system* s = ks->sys;
+  if (s->nw > 32) {
+    set_error("ephw_interpolate_linewidth: systems with more than 32 bands are not supported");
+    return EPHW_EUNSUPPORTED;
+  }
+  InterpReq r;
+  r.nk = ks->nk;
+  r.nq = nq;
+  r.prec = ks->prec;
+  r.flags = 0;
+  r.need_g = true;
+  r.need_kq_eig = !kq_index;
+  r.lw = true;
+  r.lwp = lw_params(temperature, mu, sigma, omega_min, nq_total);
+  r.temperature = temperature;
+  r.mu = mu;
+  r.sigma = sigma;
+  r.omega_min = omega_min;
+  r.nq_total = nq_total;
+  r.gamma = gamma;
+  r.qb = pick_q_batch(s, ks->nk, nq, prec_kind(ks->prec));
+  r.fused = interp_fusable(s, r);
+  const size_t need = interp_layout(s, r, nullptr).bytes;
+  EPHW_TRY(ws_need(s, WS_ARENA, need));
+  const InterpWs w = interp_layout(s, r, static_cast<char*>(wsp(s, WS_ARENA)));
+  return interpolate_small(ks, q, kq_index, 0, r, nullptr, nullptr, nullptr, 0, nullptr, nullptr, w, true,
                            as_stream(stream));
 }
 
@@ -854,6 +965,7 @@ ephw_status ephw_interpolate_noalloc(ephw_kset* ks, const double* q, int64_t nq,
   int32_t qb = pick_q_batch(s, ks->nk, nq, prec_kind(prec));
   for (;;) {
     r.qb = qb;
+    r.fused = interp_fusable(s, r);
     if (interp_layout(s, r, nullptr).bytes <= kScratchBytes) break;
     if (qb == 1) {
       set_error("ephw_interpolate_noalloc: the call needs " + std::to_string(interp_layout(s, r, nullptr).bytes) +

@@ -59,6 +59,43 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // ---------------------------------------------------------------------------
+// phonon-limited linewidth weights (the downstream reduction of stored or
+// freshly rotated matrix elements): parameters and occupations
+// ---------------------------------------------------------------------------
+struct LwParams {
+  double inv_t = 0, mu = 0, inv_sigma = 0, gnorm = 0, omega_min = 0, scale = 0;
+};
+
+inline LwParams lw_params(double temperature, double mu, double sigma, double omega_min, int64_t nq_total) {
+  LwParams p;
+  p.inv_t = 1.0 / temperature;
+  p.mu = mu;
+  p.inv_sigma = 1.0 / sigma;
+  p.gnorm = 1.0 / (sigma * 2.5066282746310005024);   // 1 / (sigma sqrt(2 pi))
+  p.omega_min = omega_min;
+  p.scale = 3.14159265358979323846 / (double)nq_total;
+  return p;
+}
+
+// exp(-x^2/2) of a scaled energy difference: in FP32 for c64 matrix elements
+// (a weight error near 1e-7, below the data's own), FP64 otherwise
+template <typename T>
+__device__ __forceinline__ double gauss_exp(double x) {
+  if constexpr (sizeof(T) == 4) {
+    const float f = (float)x;
+    return (double)expf(-0.5f * f * f);
+  } else {
+    return exp(-0.5 * x * x);
+  }
+}
+
+__device__ __forceinline__ double fermi_occ(double e, const LwParams& p) {
+  const double x = (e - p.mu) * p.inv_t;
+  const double z = exp(-fabs(x));
+  return x > 0.0 ? z / (1.0 + z) : 1.0 / (1.0 + z);
+}
+
+// ---------------------------------------------------------------------------
 // device status word bits (context-wide, read by ephw_ctx_check)
 // ---------------------------------------------------------------------------
 enum : uint32_t { kStatusNoConv = 1u, kStatusIndex = 2u };

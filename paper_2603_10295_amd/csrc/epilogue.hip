@@ -87,28 +87,6 @@ __global__ void __launch_bounds__(64 * kDegWaves)
 // in order.
 constexpr int kLwThreads = 256;
 
-struct LwParams {
-  double inv_t, mu, inv_sigma, gnorm, omega_min, scale;
-};
-
-// exp(-x^2/2) of a scaled energy difference: in FP32 for c64 matrix elements
-// (a weight error near 1e-7, below the data's own), FP64 otherwise
-template <typename T>
-__device__ __forceinline__ double gauss_exp(double x) {
-  if constexpr (sizeof(T) == 4) {
-    const float f = (float)x;
-    return (double)expf(-0.5f * f * f);
-  } else {
-    return exp(-0.5 * x * x);
-  }
-}
-
-__device__ __forceinline__ double fermi_occ(double e, const LwParams& p) {
-  const double x = (e - p.mu) * p.inv_t;
-  const double z = exp(-fabs(x));
-  return x > 0.0 ? z / (1.0 + z) : 1.0 / (1.0 + z);
-}
-
 template <typename T>
 __global__ void __launch_bounds__(kLwThreads)
     linewidth_kernel(const T* __restrict__ g, int64_t nq, int64_t nk, int nm, int nw,
@@ -243,7 +221,24 @@ LwKernel<T> lw_rows_kernel(int nw) {
   }
 }
 
+__global__ void add_column_sums_kernel(const double* __restrict__ x, int64_t ncol, int64_t n, double scale,
+                                       double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int64_t c = 0; c < ncol; ++c) s += x[c * n + i];
+  out[i] += scale * s;
+}
+
 }  // namespace
+
+ephw_status add_column_sums(const double* x, int64_t ncol, int64_t n, double scale, double* out, hipStream_t s) {
+  if (n <= 0 || ncol <= 0) return EPHW_OK;
+  hipLaunchKernelGGL(add_column_sums_kernel, dim3((unsigned)ceil_div(n, (int64_t)256)), dim3(256), 0, s, x, ncol, n,
+                     scale, out);
+  EPHW_CHECK_LAUNCH();
+  return EPHW_OK;
+}
 
 ephw_status linewidth(int prec, const void* g, int64_t nq, int64_t nk, int nm, int nw, const double* eps_k,
                       const double* eps_kq, const double* omega, double temperature, double mu, double sigma,
@@ -253,13 +248,7 @@ ephw_status linewidth(int prec, const void* g, int64_t nq, int64_t nk, int nm, i
     set_error("ephw_linewidth: more than 2^31 k points");
     return EPHW_EUNSUPPORTED;
   }
-  LwParams p;
-  p.inv_t = 1.0 / temperature;
-  p.mu = mu;
-  p.inv_sigma = 1.0 / sigma;
-  p.gnorm = 1.0 / (sigma * 2.5066282746310005024);   // 1 / (sigma sqrt(2 pi))
-  p.omega_min = omega_min;
-  p.scale = 3.14159265358979323846 / (double)nq_total;
+  const LwParams p = lw_params(temperature, mu, sigma, omega_min, nq_total);
   if (prec == 0)
     hipLaunchKernelGGL(lw_rows_kernel<double>(nw), dim3((unsigned)nk), dim3(kLwThreads), 0, s,
                        static_cast<const double*>(g), nq, nk, nm, nw, eps_k, eps_kq, omega, p, gamma);

@@ -25,6 +25,39 @@ struct LossEpilogue {
   double* partial = nullptr;
 };
 
+// Band rotations fused into the epilogue of the Eq. (10) Re-sum GEMM (FP32,
+// 128x128 tiles, no transposes, Nw of 4 or 8 so that every Nw x Nw block of a
+// (q, nu) lies inside one wave's 64 columns).  C = W[k][(q, nu, m', n')] with
+// row r the k point r of the set and column c = (q, nu, m', n') of the batch;
+// instead of storing W the tile forms g_nu(k,q) = V(k+q)^dagger W_nu V(k)
+// (Eq. (7)'s band factors, U = V^dagger) and applies the epilogues:
+//   EPHW_OUT_G        g stored [q][k][nu][m][n]
+//   EPHW_OUT_BAND_SUM T_nu = sum_mn |g|^2 stored [q][k][nu]
+//   EPHW_OUT_LOSS     sum of w |g|^2 over the tile -> loss_partial[tile]
+//   lw_partial        linewidth terms of every element (the weights of
+//                     ephw_linewidth) summed over the (q, nu, m) of a wave's 64
+//                     columns -> lw_partial[c / 64][k][n]
+struct BandEpilogue {
+  bool on = false;
+  int nw = 0, nm = 0;
+  int64_t nk = 0;                 // k points of the set (rows of C; stride of kq_index, g_out, band_sum)
+  int64_t q_global0 = 0;          // position of the batch's first q in the caller's list (loss index)
+  const void* Vk = nullptr;       // [nk][nw][nw] c64, eigenvector columns V(k)
+  const void* Vkq = nullptr;      // [qb][nk][nw][nw] c64 V(k+q), or NULL: taken through kq_index
+  const int32_t* kq_index = nullptr;  // [qb][nk], offset to the batch
+  uint32_t flags = 0;             // EPHW_OUT_G / EPHW_OUT_BAND_SUM / EPHW_OUT_LOSS
+  void* g_out = nullptr;          // [qb][nk][nm][nw][nw] c64, offset to the batch
+  double* band_sum = nullptr;     // [qb][nk][nm], offset to the batch
+  double* loss_partial = nullptr; // [tiles of the launch]
+  uint64_t loss_seed = 0;
+  double* lw_partial = nullptr;   // [N / 64][nk][nw], or NULL: no linewidth terms
+  const double* eps_k = nullptr;  // [nk][nw]
+  const double* eps_kq = nullptr; // [qb][nk][nw]
+  const double* omega = nullptr;  // [qb][nm]
+  LwParams lw;
+  uint32_t* status = nullptr;     // kStatusIndex for an index outside [0, nk)
+};
+
 // All sizes, leading dimensions, strides and offsets count complex elements.
 // Operands are interleaved complex (T re, T im), T = double (prec 0) or float
 // (prec 1).  "trans" means the operand is stored transposed (A as [K][M],
@@ -53,8 +86,13 @@ struct GemmParams {
   // (ldc is then the block stride).
   int64_t tblock = 0;
   LossEpilogue loss;
+  BandEpilogue band;
   int64_t batch_base = 0;  // internal: first batch index of this launch
 };
+// whether cgemm can run the fused band epilogue for this Re-sum shape (FP32,
+// nw 4 or 8; always on 128x128 tiles, ceil(M/128) * ceil(N/128) of them);
+// otherwise the caller stores W and rotates
+bool cgemm_band_fusable(int prec, int64_t M, int64_t N, int nw, int64_t lda, int64_t ldb);
 // workgroup tiles per batch entry of a GEMM (size of the loss partial block)
 int64_t cgemm_tiles(int prec, int64_t M, int64_t N);
 

@@ -148,6 +148,194 @@ struct TileShape {
   static constexpr size_t smem_elems = 2 * stage_elems;   // two stages
 };
 
+// Fused band rotation of the FP32 128x128 Re-sum tile (see BandEpilogue).
+// Wave (wm, wn) holds W for 64 k points (rows) and 64 columns, i.e. 64/Nw^2
+// whole (q, nu) blocks of Nw x Nw.  Its rows go through LDS in two halves of
+// 32 k points (the wave's own 32 x 65 complex region; the K loop's stages are
+// free by then).  A lane owns one row (block b, m') of one k point per pass:
+//   1. T[m'][:] = W[m'][:] V(k), written over its W row (V(k) rows read from
+//      global memory, where every lane of the k point reads the same ones);
+//   2. after a wave-level wait, g[m][:] = sum_m' conj(V(k+q)[m'][m]) T[m'][:]
+//      with m = m' of the lane, from the block's T rows;
+//   3. the epilogues of the row: the g row stored (one contiguous Nw-element
+//      row), its |g|^2 summed over the block's lanes (band sum), w |g|^2 into
+//      the lane's loss sum, linewidth weights times |g|^2 into per-band sums
+//      that are reduced over the k point's lanes and stored per wave column.
+// Sums run in a fixed order (shuffle trees and a fixed wave order), so the
+// results are deterministic.
+template <int NW>
+__device__ __forceinline__ void band_epilogue(const TileJob<float>& j, const BandEpilogue& B, int64_t m0, int64_t n0,
+                                              typename Mfma<float>::v4 (&acc_r)[4][4],
+                                              typename Mfma<float>::v4 (&acc_i)[4][4], float* smem) {
+  constexpr int TM = 64, TN = 64, HR = 32, LDW = TN + 1;
+  constexpr int NW2 = NW * NW, RK = TN / NW, KPP = 64 / RK;   // rows per k point, k points per pass
+  static_assert(TN % NW2 == 0 && 64 % RK == 0, "blocks must tile a wave's columns");
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % 2, wn = wave / 2;
+  const int lrow = lane >> 4, lcol = lane & 15;
+  float* wl = smem + wave * (HR * LDW * 2);
+  const int r = lane % RK, kl = lane / RK;
+  const int blk = r / NW, mp = r % NW;
+  const int64_t cw0 = n0 + wn * TN;                 // first column of the wave
+  const int64_t col0 = cw0 + blk * NW2;             // first column of the lane's block
+  const int64_t E = (int64_t)B.nm * NW2;
+  const bool col_ok = col0 < j.N;
+  const int64_t ql = col_ok ? col0 / E : 0;
+  const int nu = col_ok ? (int)((col0 - ql * E) / NW2) : 0;
+  const bool want_g = (B.flags & EPHW_OUT_G) != 0, want_t = (B.flags & EPHW_OUT_BAND_SUM) != 0;
+  const bool want_l = (B.flags & EPHW_OUT_LOSS) != 0, want_w = B.lw_partial != nullptr;
+  const float* Vk = static_cast<const float*>(B.Vk);
+  const float* Vkq = static_cast<const float*>(B.Vkq);
+  // linewidth: the lane's mode (q, nu) fixes omega and its Bose factor
+  double om = 0.0, nbose = 0.0;
+  bool lw_mode = false;
+  if (want_w && col_ok) {
+    om = B.omega[ql * B.nm + nu];
+    lw_mode = om > 0.0 && om >= B.lw.omega_min;   // omega = 0: no zero-point amplitude
+    if (lw_mode) nbose = 1.0 / expm1(om * B.lw.inv_t);
+  }
+  double lsum = 0.0;
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    if (h == 0)
+      __syncthreads();   // every wave is done with the K loop's LDS stages
+    else
+      wave_sync();       // this wave is done with the first half's rows
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = ii * 16 + Mfma<float>::row(lrow, v), col = jj * 16 + lcol;
+          const float re = h == 0 ? acc_r[ii][jj][v] : acc_r[2 + ii][jj][v];
+          const float im = h == 0 ? acc_i[ii][jj][v] : acc_i[2 + ii][jj][v];
+          *reinterpret_cast<float2*>(wl + 2 * (row * LDW + col)) = make_float2(re, im);
+        }
+    wave_sync();
+#pragma unroll 1
+    for (int pass = 0; pass < HR / KPP; ++pass) {
+      const int krow = pass * KPP + kl;
+      const int64_t k = m0 + wm * TM + h * HR + krow;
+      const bool act = col_ok && k < j.M;
+      float* xrow = wl + 2 * (krow * LDW + blk * NW2 + mp * NW);
+      if (act) {
+        // 1. T[m'][:] = W[m'][:] V(k)
+        cplx<float> x[NW], t[NW];
+#pragma unroll
+        for (int n = 0; n < NW; ++n) {
+          x[n] = cplx<float>{xrow[2 * n], xrow[2 * n + 1]};
+          t[n] = cplx<float>{0.f, 0.f};
+        }
+        const float* vk = Vk + 2 * k * NW2;
+#pragma unroll
+        for (int a = 0; a < NW; ++a) {
+          cplx<float> vr[NW];
+#pragma unroll
+          for (int n = 0; n < NW; n += 2) {
+            const float4 v4 = *reinterpret_cast<const float4*>(vk + 2 * (a * NW + n));
+            vr[n] = cplx<float>{v4.x, v4.y};
+            vr[n + 1] = cplx<float>{v4.z, v4.w};
+          }
+#pragma unroll
+          for (int n = 0; n < NW; ++n) cfma(t[n], x[a], vr[n]);
+        }
+#pragma unroll
+        for (int n = 0; n < NW; ++n) {
+          xrow[2 * n] = t[n].re;
+          xrow[2 * n + 1] = t[n].im;
+        }
+      }
+      wave_sync();
+      cplx<float> g[NW];
+#pragma unroll
+      for (int n = 0; n < NW; ++n) g[n] = cplx<float>{0.f, 0.f};
+      if (act) {
+        // 2. g[m][:] = sum_m' conj(V(k+q)[m'][m]) T[m'][:]
+        const float* vq;
+        if (Vkq) {
+          vq = Vkq + 2 * ((ql * B.nk + k) * NW2);
+        } else {
+          int64_t id = B.kq_index[ql * B.nk + k];
+          if (id < 0 || id >= B.nk) {
+            if (mp == 0) atomicOr(B.status, kStatusIndex);
+            id = 0;
+          }
+          vq = Vk + 2 * id * NW2;
+        }
+        const float* tb = wl + 2 * (krow * LDW + blk * NW2);
+#pragma unroll
+        for (int a = 0; a < NW; ++a) {
+          const cplx<float> c{vq[2 * (a * NW + mp)], vq[2 * (a * NW + mp) + 1]};
+#pragma unroll
+          for (int n = 0; n < NW; ++n) cfmac(g[n], c, cplx<float>{tb[2 * (a * NW + n)], tb[2 * (a * NW + n) + 1]});
+        }
+      }
+      // 3. epilogues (shuffles below run on every lane; inactive rows add zero)
+      const int64_t eoff = (int64_t)nu * NW2 + (int64_t)mp * NW;   // element offset in the pair
+      double g2[NW], rs = 0.0;
+#pragma unroll
+      for (int n = 0; n < NW; ++n) {
+        g2[n] = (double)g[n].re * (double)g[n].re + (double)g[n].im * (double)g[n].im;
+        rs += g2[n];
+      }
+      if (act && want_g) {
+        float* go = static_cast<float*>(B.g_out) + 2 * ((ql * B.nk + k) * E + eoff);
+#pragma unroll
+        for (int n = 0; n < NW; n += 2)
+          *reinterpret_cast<float4*>(go + 2 * n) = make_float4(g[n].re, g[n].im, g[n + 1].re, g[n + 1].im);
+      }
+      if (want_t) {
+        double tv = rs;
+#pragma unroll
+        for (int off = 1; off < NW; off <<= 1) tv += __shfl_xor(tv, off, 64);
+        if (act && mp == 0) B.band_sum[(ql * B.nk + k) * B.nm + nu] = tv;
+      }
+      if (act && want_l) {
+        const uint64_t base = ((uint64_t)(B.q_global0 + ql) * (uint64_t)B.nk + (uint64_t)k) * (uint64_t)E +
+                              (uint64_t)eoff;
+#pragma unroll
+        for (int n = 0; n < NW; ++n) lsum += splitmix_weight(B.loss_seed, base + (uint64_t)n) * g2[n];
+      }
+      if (want_w) {
+        double lw[NW];
+#pragma unroll
+        for (int n = 0; n < NW; ++n) lw[n] = 0.0;
+        if (act && lw_mode) {
+          const double em = B.eps_kq[(ql * B.nk + k) * NW + mp];
+          const double fm = fermi_occ(em, B.lw);
+          const double wa = (nbose + fm) * B.lw.gnorm / (2.0 * om);
+          const double we = (nbose + 1.0 - fm) * B.lw.gnorm / (2.0 * om);
+#pragma unroll
+          for (int n = 0; n < NW; ++n) {
+            const double en = B.eps_k[k * NW + n];
+            const double a = (en - em + om) * B.lw.inv_sigma, b = (en - em - om) * B.lw.inv_sigma;
+            lw[n] = (wa * gauss_exp<float>(a) + we * gauss_exp<float>(b)) * g2[n];
+          }
+        }
+        // sum over the k point's rows (all blocks and bands m of the wave)
+#pragma unroll
+        for (int off = 1; off < RK; off <<= 1)
+#pragma unroll
+          for (int n = 0; n < NW; ++n) lw[n] += __shfl_xor(lw[n], off, 64);
+        double mine = 0.0;
+#pragma unroll
+        for (int n = 0; n < NW; ++n)
+          if (n == r) mine = lw[n];
+        if (r < NW && k < j.M && cw0 < j.N) B.lw_partial[((cw0 / TN) * B.nk + k) * NW + r] = mine;
+      }
+    }
+  }
+  if (want_l) {
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off, 64);
+    double* red = reinterpret_cast<double*>(smem);
+    __syncthreads();
+    if (lane == 0) red[wave] = lsum;
+    __syncthreads();
+    if (tid == 0) B.loss_partial[j.tile] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
 // Computes the BM x BN tile at (m0, n0) of job j with the workgroup's
 // NT threads; `smem` holds TileShape::smem_elems values of T.
 //
@@ -156,8 +344,9 @@ struct TileShape {
 // written to the other stage, so each slab costs one barrier.  LDS keeps
 // complex values interleaved, laid out [k][m] and [k][n], so one 8- or
 // 16-byte read gives a lane its (re, im) operand pair.
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int SPLIT>
-__device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64_t n0, T* smem) {
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int SPLIT, int BANDNW = 0>
+__device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64_t n0, T* smem,
+                                          const BandEpilogue* band = nullptr) {
   using S = TileShape<T, BM, BN, BK, WM, WN, SPLIT>;
   using C = Chunk<T>;
   using V4 = typename C::v4;
@@ -437,6 +626,12 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
     __syncthreads();
   }
 
+  if constexpr (BANDNW > 0) {
+    static_assert(sizeof(T) == 4 && BM == 128 && BN == 128 && WM == 2 && WN == 2 && SPLIT == 0,
+                  "the band epilogue runs on the FP32 128x128 tile");
+    band_epilogue<BANDNW>(j, *band, m0, n0, acc_r, acc_i, smem);
+    return;
+  }
   // --- epilogue: lane holds column lcol of every block, rows per Mfma<T>::row --
   const int64_t tb = j.tblock;
   auto c_index = [&](int64_t row, int64_t col) -> int64_t {
@@ -554,7 +749,7 @@ __device__ __forceinline__ TileJob<T> job_of(const GemmParams& p, int64_t b) {
 }
 
 // OCC: waves per SIMD the register allocation must leave room for
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int SPLIT, int OCC>
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int SPLIT, int OCC, int BANDNW = 0>
 __global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(OCC)))
     cgemm_kernel(GemmParams p, int64_t tiles_m, int64_t tiles_n) {
   using S = TileShape<T, BM, BN, BK, WM, WN, SPLIT>;
@@ -565,7 +760,7 @@ __global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_
   TileJob<T> j = job_of<T>(p, p.batch_base + blockIdx.y);
   j.tile = tm * tiles_n + tn;
   j.ntiles = tiles_m * tiles_n;
-  gemm_tile<T, BM, BN, BK, WM, WN, TA, TB, SPLIT>(j, tm * BM, tn * BN, smem);
+  gemm_tile<T, BM, BN, BK, WM, WN, TA, TB, SPLIT, BANDNW>(j, tm * BM, tn * BN, smem, &p.band);
 }
 
 // Tile shapes of the grouped kernel: cfg 0 is the default tile of the plain
@@ -692,7 +887,7 @@ bool lane_offsets_fit(int64_t lda, int64_t ldb) {
   return lda >= 0 && ldb >= 0 && (a_rows * lda + BM + BK) * cs < lim && (b_rows * ldb + BN + BK) * cs < lim;
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int SPLIT, int OCC>
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int SPLIT, int OCC, int BANDNW = 0>
 ephw_status launch(const GemmParams& p0, hipStream_t stream) {
   const int64_t tiles_m = ceil_div(p0.M, BM), tiles_n = ceil_div(p0.N, BN);
   const int64_t ntiles = tiles_m * tiles_n;
@@ -708,7 +903,7 @@ ephw_status launch(const GemmParams& p0, hipStream_t stream) {
   for (int64_t b0 = 0; b0 < p0.batch; b0 += 65535) {
     const int64_t nb = (p0.batch - b0) < 65535 ? (p0.batch - b0) : 65535;
     p.batch_base = b0;
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, WM, WN, TA, TB, SPLIT, OCC>),
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, WM, WN, TA, TB, SPLIT, OCC, BANDNW>),
                        dim3((unsigned)ntiles, (unsigned)nb), dim3(64 * WM * WN), 0, stream, p,
                        tiles_m, tiles_n);
     EPHW_CHECK_LAUNCH();
@@ -950,8 +1145,32 @@ bool fits_any(const GemmParams& p) {
   return lane_offsets_fit<T, BM, BN, BK, WM, WN, true, true>(p.lda, p.ldb);
 }
 
+// The fused epilogue always runs on the 128x128 tile (whatever tile the
+// padding rule would pick for a plain store): it saves the W round trip
+// through HBM and the separate band-rotation pass, more than any padding.
+bool cgemm_band_fusable(int prec, int64_t M, int64_t N, int nw, int64_t lda, int64_t ldb) {
+  if (prec != 1 || (nw != 4 && nw != 8) || M <= 0 || N <= 0) return false;
+  return ceil_div(M, 128) * ceil_div(N, 128) <= 0x7fffffff &&
+         lane_offsets_fit<float, 128, 128, 16, 2, 2, false, false>(lda, ldb);
+}
+
 ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream) {
   if (p.M <= 0 || p.N <= 0 || p.batch <= 0) return EPHW_OK;
+  if (p.band.on) {
+    const BandEpilogue& b = p.band;
+    if (!cgemm_band_fusable(prec, p.M, p.N, b.nw, p.lda, p.ldb) || p.A_lo || p.transA || p.transB || p.conjA ||
+        p.conjB || p.accumulate || p.loss.on || p.tblock != 0 || p.batch != 1 || p.M != b.nk ||
+        p.N % ((int64_t)b.nm * b.nw * b.nw) != 0 || !b.Vk || (!b.Vkq && !b.kq_index)) {
+      set_error("cgemm: this product cannot take the fused band epilogue");
+      return EPHW_EUNSUPPORTED;
+    }
+    if ((b.flags & EPHW_OUT_G) && reinterpret_cast<uintptr_t>(b.g_out) % 16 != 0) {
+      set_error("cgemm: the fused band epilogue stores g in 16-byte chunks (g must be 16-byte aligned)");
+      return EPHW_EINVAL;
+    }
+    return b.nw == 8 ? launch<float, 128, 128, 16, 2, 2, false, false, 0, 2, 8>(p, stream)
+                     : launch<float, 128, 128, 16, 2, 2, false, false, 0, 2, 4>(p, stream);
+  }
   if (p.K <= 0) {
     set_error("cgemm: K must be positive");
     return EPHW_EINVAL;

@@ -26,7 +26,7 @@ OUT_G, OUT_BAND_SUM, OUT_LOSS, OUT_WANNIER = 1, 2, 4, 8
 EXPORTS = [
     "ephw_ctx_create", "ephw_ctx_destroy", "ephw_ctx_check", "ephw_ctx_set_limits", "ephw_ctx_memory", "ephw_system_load",
     "ephw_system_free", "ephw_system_set_g", "ephw_system_bytes", "ephw_bands", "ephw_phonons", "ephw_phase_sum_rp",
-    "ephw_kset_create", "ephw_kset_free", "ephw_kset_bands", "ephw_interpolate", "ephw_interpolate_noalloc", "ephw_degenerate_sums", "ephw_wannier_transform",
+    "ephw_kset_create", "ephw_kset_free", "ephw_kset_bands", "ephw_interpolate", "ephw_interpolate_noalloc", "ephw_interpolate_linewidth", "ephw_degenerate_sums", "ephw_wannier_transform",
     "ephw_window_screen", "ephw_linewidth",
     "ephw_loss_backward", "ephw_set_q_batch", "ephw_set_k_tile", "ephw_profile_enable", "ephw_profile_read", "ephw_batch_create",
     "ephw_batch_run", "ephw_batch_shape", "ephw_batch_stats", "ephw_batch_free", "ephw_status_string",
@@ -106,6 +106,8 @@ def lib() -> ctypes.CDLL:
         "ephw_kset_bands": [vp, vp, vp, vp],
         "ephw_interpolate": [vp, vp, i64, vp, i64, i32, u32, vp, vp, vp, u64, vp, vp, vp],
         "ephw_interpolate_noalloc": [vp, vp, i64, vp, i64, i32, u32, vp, vp, vp, u64, vp, vp, vp],
+        "ephw_interpolate_linewidth": [vp, vp, i64, vp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                       ctypes.c_double, i64, vp, vp],
         "ephw_degenerate_sums": [i32, vp, i64, i64, i32, i32, vp, vp, vp, ctypes.c_double, vp, vp],
         "ephw_wannier_transform": [vp, vp, i64, vp, vp, vp, vp],
         "ephw_linewidth": [i32, vp, i64, i64, i32, i32, vp, vp, vp, ctypes.c_double, ctypes.c_double,
@@ -351,6 +353,17 @@ def interpolate_noalloc(ks: KSet, q, *, kq_index=None, q_offset: int = 0, flags:
     _check(lib().ephw_interpolate_noalloc(ks.handle, _ptr(q), q.shape[0], _ptr(kq_index), int(q_offset), ks.prec,
                                           int(flags), _ptr(g_out), _ptr(band_sum), _ptr(loss), int(loss_seed),
                                           _ptr(eps_kq), _ptr(omega), _stream(stream)), "ephw_interpolate_noalloc")
+
+
+def interpolate_linewidth(ks: KSet, q, gamma, *, kq_index=None, temperature: float, mu: float, sigma: float,
+                          omega_min: float = 0.0, nq_total: int = 0, stream=None):
+    """gamma[k][n] += the linewidth terms of Eq. (7)'s g for the k-set and q
+    list, with g never stored (see ephw_interpolate_linewidth); nq_total
+    defaults to this call's q count."""
+    _expect(gamma, (ks.nk, ks.sys.nw), "gamma")
+    _check(lib().ephw_interpolate_linewidth(ks.handle, _ptr(q), q.shape[0], _ptr(kq_index), float(temperature),
+                                            float(mu), float(sigma), float(omega_min), int(nq_total or q.shape[0]),
+                                            _ptr(gamma), _stream(stream)), "ephw_interpolate_linewidth")
 
 
 def window_screen(ks: KSet, q, kq_index, e_lo: float, e_hi: float, k_out, q_out, kq_out, pair_mask=None,
