@@ -152,47 +152,62 @@ struct TileShape {
 // Wave (wm, wn) holds W for 64 k points (rows) and 64 columns, i.e. 64/Nw^2
 // whole (q, nu) blocks of Nw x Nw.  Its rows go through LDS in two halves of
 // 32 k points (the wave's own 32 x 65 complex region; the K loop's stages are
-// free by then).  A lane owns one row (block b, m') of one k point per pass:
-//   1. T[m'][:] = W[m'][:] V(k), written over its W row (V(k) rows read from
-//      global memory, where every lane of the k point reads the same ones);
-//   2. after a wave-level wait, g[m][:] = sum_m' conj(V(k+q)[m'][m]) T[m'][:]
-//      with m = m' of the lane, from the block's T rows;
-//   3. the epilogues of the row: the g row stored (one contiguous Nw-element
-//      row), its |g|^2 summed over the block's lanes (band sum), w |g|^2 into
-//      the lane's loss sum, linewidth weights times |g|^2 into per-band sums
-//      that are reduced over the k point's lanes and stored per wave column.
-// Sums run in a fixed order (shuffle trees and a fixed wave order), so the
-// results are deterministic.
+// free by then).  Two lanes share a k point and split its 64/Nw rows (b, m')
+// into four-row groups: Nw = 8, one block, rows 4s..4s+3; Nw = 4, blocks
+// 2s, 2s+1, all four rows (s = lane parity).  Per half:
+//   1. T_b[m'][:] = W_b[m'][:] V(k) for the lane's rows, written over them in
+//      LDS; V(k) is read once per half, row by row (both lanes of the k point
+//      read the same rows);
+//   2. after a wave-level wait, g_b[m][:] = sum_m' conj(V(k+q_b)[m'][m]) T_b[m'][:]
+//      for the lane's output rows (the same four-row groups), T_b rows from
+//      LDS and V(k+q_b) rows (the lane's four columns) from global memory;
+//   3. the epilogues of the lane's rows: g stored (four contiguous rows),
+//      |g|^2 of a block summed over its lanes (band sum), w |g|^2 into the
+//      lane's loss sum, linewidth weights times |g|^2 summed per band n over
+//      the k point's rows and stored per wave column.
+// Sums run in a fixed order (shuffles and a fixed wave order), so the results
+// are deterministic.
 template <int NW>
 __device__ __forceinline__ void band_epilogue(const TileJob<float>& j, const BandEpilogue& B, int64_t m0, int64_t n0,
                                               typename Mfma<float>::v4 (&acc_r)[4][4],
                                               typename Mfma<float>::v4 (&acc_i)[4][4], float* smem) {
+  static_assert(NW == 4 || NW == 8, "four-row groups of whole blocks");
   constexpr int TM = 64, TN = 64, HR = 32, LDW = TN + 1;
-  constexpr int NW2 = NW * NW, RK = TN / NW, KPP = 64 / RK;   // rows per k point, k points per pass
-  static_assert(TN % NW2 == 0 && 64 % RK == 0, "blocks must tile a wave's columns");
+  constexpr int NW2 = NW * NW, NB = 8 / NW, MR = 4;   // blocks per lane, rows per block group
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave % 2, wn = wave / 2;
   const int lrow = lane >> 4, lcol = lane & 15;
   float* wl = smem + wave * (HR * LDW * 2);
-  const int r = lane % RK, kl = lane / RK;
-  const int blk = r / NW, mp = r % NW;
-  const int64_t cw0 = n0 + wn * TN;                 // first column of the wave
-  const int64_t col0 = cw0 + blk * NW2;             // first column of the lane's block
+  const int kl = lane >> 1, sb = lane & 1;               // k point within the half, lane of the pair
+  const int64_t cw0 = n0 + wn * TN;                      // first column of the wave
   const int64_t E = (int64_t)B.nm * NW2;
-  const bool col_ok = col0 < j.N;
-  const int64_t ql = col_ok ? col0 / E : 0;
-  const int nu = col_ok ? (int)((col0 - ql * E) / NW2) : 0;
   const bool want_g = (B.flags & EPHW_OUT_G) != 0, want_t = (B.flags & EPHW_OUT_BAND_SUM) != 0;
   const bool want_l = (B.flags & EPHW_OUT_LOSS) != 0, want_w = B.lw_partial != nullptr;
   const float* Vk = static_cast<const float*>(B.Vk);
   const float* Vkq = static_cast<const float*>(B.Vkq);
-  // linewidth: the lane's mode (q, nu) fixes omega and its Bose factor
-  double om = 0.0, nbose = 0.0;
-  bool lw_mode = false;
-  if (want_w && col_ok) {
-    om = B.omega[ql * B.nm + nu];
-    lw_mode = om > 0.0 && om >= B.lw.omega_min;   // omega = 0: no zero-point amplitude
-    if (lw_mode) nbose = 1.0 / expm1(om * B.lw.inv_t);
+  // the lane's blocks: column offset in the wave, first row, (q, nu), validity
+  int bcol[NB], brow0[NB], bnu[NB];
+  int64_t bq[NB];
+  bool bok[NB];
+  double bom[NB], bnb[NB];
+  bool blw[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int blk = NW == 8 ? 0 : 2 * sb + i;
+    brow0[i] = NW == 8 ? MR * sb : 0;
+    bcol[i] = blk * NW2;
+    const int64_t c0 = cw0 + bcol[i];
+    bok[i] = c0 < j.N;
+    bq[i] = bok[i] ? c0 / E : 0;
+    bnu[i] = bok[i] ? (int)((c0 - bq[i] * E) / NW2) : 0;
+    bom[i] = 0.0;
+    bnb[i] = 0.0;
+    blw[i] = false;
+    if (want_w && bok[i]) {
+      bom[i] = B.omega[bq[i] * B.nm + bnu[i]];
+      blw[i] = bom[i] > 0.0 && bom[i] >= B.lw.omega_min;   // omega = 0: no zero-point amplitude
+      if (blw[i]) bnb[i] = 1.0 / expm1(bom[i] * B.lw.inv_t);
+    }
   }
   double lsum = 0.0;
 #pragma unroll 1
@@ -213,117 +228,406 @@ __device__ __forceinline__ void band_epilogue(const TileJob<float>& j, const Ban
           *reinterpret_cast<float2*>(wl + 2 * (row * LDW + col)) = make_float2(re, im);
         }
     wave_sync();
+    const int64_t k = m0 + wm * TM + h * HR + kl;
+    const bool kok = k < j.M;
+    float* krow = wl + 2 * (kl * LDW);
+    // V(k+q_b) of the lane's blocks: the index is read now, ahead of its use
+    const float* vqb[NB];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      if (Vkq) {
+        vqb[i] = Vkq + 2 * ((bq[i] * B.nk + (kok ? k : 0)) * NW2);
+      } else {
+        int64_t id = (kok && bok[i]) ? B.kq_index[bq[i] * B.nk + k] : 0;
+        if (id < 0 || id >= B.nk) {
+          atomicOr(B.status, kStatusIndex);
+          id = 0;
+        }
+        vqb[i] = Vk + 2 * id * NW2;
+      }
+    }
+    // 1. T = W V(k) for the lane's rows (b, m'), written over them
+    if (kok) {
+      cplx<float> t[NB][MR][NW];
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+#pragma unroll
+        for (int r = 0; r < MR; ++r)
+#pragma unroll
+          for (int n = 0; n < NW; ++n) t[i][r][n] = cplx<float>{0.f, 0.f};
+      const float* vk = Vk + 2 * k * NW2;
+      // one V(k) row per iteration, the next row's loads in flight meanwhile
+      // (unrolling would hoist every row's loads and spill the accumulators of
+      // the second half)
+      float4 cur[NW / 2], nxt[NW / 2];
+#pragma unroll
+      for (int n = 0; n < NW; n += 2) cur[n / 2] = *reinterpret_cast<const float4*>(vk + 2 * n);
 #pragma unroll 1
-    for (int pass = 0; pass < HR / KPP; ++pass) {
-      const int krow = pass * KPP + kl;
-      const int64_t k = m0 + wm * TM + h * HR + krow;
-      const bool act = col_ok && k < j.M;
-      float* xrow = wl + 2 * (krow * LDW + blk * NW2 + mp * NW);
-      if (act) {
-        // 1. T[m'][:] = W[m'][:] V(k)
-        cplx<float> x[NW], t[NW];
+      for (int a = 0; a < NW; ++a) {
+        const int an = a + 1 < NW ? a + 1 : a;
 #pragma unroll
-        for (int n = 0; n < NW; ++n) {
-          x[n] = cplx<float>{xrow[2 * n], xrow[2 * n + 1]};
-          t[n] = cplx<float>{0.f, 0.f};
+        for (int n = 0; n < NW; n += 2) nxt[n / 2] = *reinterpret_cast<const float4*>(vk + 2 * (an * NW + n));
+        cplx<float> vr[NW];
+#pragma unroll
+        for (int n = 0; n < NW; n += 2) {
+          vr[n] = cplx<float>{cur[n / 2].x, cur[n / 2].y};
+          vr[n + 1] = cplx<float>{cur[n / 2].z, cur[n / 2].w};
         }
-        const float* vk = Vk + 2 * k * NW2;
 #pragma unroll
-        for (int a = 0; a < NW; ++a) {
-          cplx<float> vr[NW];
+        for (int i = 0; i < NB; ++i)
 #pragma unroll
-          for (int n = 0; n < NW; n += 2) {
-            const float4 v4 = *reinterpret_cast<const float4*>(vk + 2 * (a * NW + n));
-            vr[n] = cplx<float>{v4.x, v4.y};
-            vr[n + 1] = cplx<float>{v4.z, v4.w};
+          for (int r = 0; r < MR; ++r) {
+            const float2 x = *reinterpret_cast<const float2*>(krow + 2 * (bcol[i] + (brow0[i] + r) * NW + a));
+#pragma unroll
+            for (int n = 0; n < NW; ++n) cfma(t[i][r][n], cplx<float>{x.x, x.y}, vr[n]);
           }
 #pragma unroll
-          for (int n = 0; n < NW; ++n) cfma(t[n], x[a], vr[n]);
-        }
-#pragma unroll
-        for (int n = 0; n < NW; ++n) {
-          xrow[2 * n] = t[n].re;
-          xrow[2 * n + 1] = t[n].im;
-        }
+        for (int n = 0; n < NW / 2; ++n) cur[n] = nxt[n];
       }
-      wave_sync();
-      cplx<float> g[NW];
+      // every W value of the lane's rows has been read (the loop above is
+      // this lane's only reader of them): write T over them
 #pragma unroll
-      for (int n = 0; n < NW; ++n) g[n] = cplx<float>{0.f, 0.f};
-      if (act) {
-        // 2. g[m][:] = sum_m' conj(V(k+q)[m'][m]) T[m'][:]
-        const float* vq;
-        if (Vkq) {
-          vq = Vkq + 2 * ((ql * B.nk + k) * NW2);
-        } else {
-          int64_t id = B.kq_index[ql * B.nk + k];
-          if (id < 0 || id >= B.nk) {
-            if (mp == 0) atomicOr(B.status, kStatusIndex);
-            id = 0;
-          }
-          vq = Vk + 2 * id * NW2;
-        }
-        const float* tb = wl + 2 * (krow * LDW + blk * NW2);
+      for (int i = 0; i < NB; ++i)
 #pragma unroll
+        for (int r = 0; r < MR; ++r)
+#pragma unroll
+          for (int n = 0; n < NW; ++n)
+            *reinterpret_cast<float2*>(krow + 2 * (bcol[i] + (brow0[i] + r) * NW + n)) =
+                make_float2(t[i][r][n].re, t[i][r][n].im);
+    }
+    wave_sync();
+    // 2. g_b[m][:] = sum_m' conj(V(k+q_b)[m'][m]) T_b[m'][:] for the lane's rows m
+    cplx<float> g[NB][MR][NW];
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int r = 0; r < MR; ++r)
+#pragma unroll
+        for (int n = 0; n < NW; ++n) g[i][r][n] = cplx<float>{0.f, 0.f};
+    if (kok) {
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        if (!bok[i]) continue;
+        const float* vq = vqb[i];
+        // V(k+q)[a][m] for the lane's four columns m (16-byte aligned: m0 is 0 or 4),
+        // the next row's in flight meanwhile
+        float4 c01 = *reinterpret_cast<const float4*>(vq + 2 * brow0[i]);
+        float4 c23 = *reinterpret_cast<const float4*>(vq + 2 * (brow0[i] + 2));
+#pragma unroll 1
         for (int a = 0; a < NW; ++a) {
-          const cplx<float> c{vq[2 * (a * NW + mp)], vq[2 * (a * NW + mp) + 1]};
+          const int an = a + 1 < NW ? a + 1 : a;
+          const float4 n01 = *reinterpret_cast<const float4*>(vq + 2 * (an * NW + brow0[i]));
+          const float4 n23 = *reinterpret_cast<const float4*>(vq + 2 * (an * NW + brow0[i] + 2));
+          const cplx<float> c[MR] = {{c01.x, c01.y}, {c01.z, c01.w}, {c23.x, c23.y}, {c23.z, c23.w}};
 #pragma unroll
-          for (int n = 0; n < NW; ++n) cfmac(g[n], c, cplx<float>{tb[2 * (a * NW + n)], tb[2 * (a * NW + n) + 1]});
+          for (int n = 0; n < NW; ++n) {
+            const float2 tv = *reinterpret_cast<const float2*>(krow + 2 * (bcol[i] + a * NW + n));
+#pragma unroll
+            for (int r = 0; r < MR; ++r) cfmac(g[i][r][n], c[r], cplx<float>{tv.x, tv.y});
+          }
+          c01 = n01;
+          c23 = n23;
         }
       }
-      // 3. epilogues (shuffles below run on every lane; inactive rows add zero)
-      const int64_t eoff = (int64_t)nu * NW2 + (int64_t)mp * NW;   // element offset in the pair
-      double g2[NW], rs = 0.0;
+    }
+    // the g rows go back to LDS over the lane's own rows once every lane has
+    // read its T rows, so that the epilogues below hold one row at a time
+    wave_sync();
+    if (kok) {
 #pragma unroll
-      for (int n = 0; n < NW; ++n) {
-        g2[n] = (double)g[n].re * (double)g[n].re + (double)g[n].im * (double)g[n].im;
-        rs += g2[n];
-      }
-      if (act && want_g) {
-        float* go = static_cast<float*>(B.g_out) + 2 * ((ql * B.nk + k) * E + eoff);
+      for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int n = 0; n < NW; n += 2)
-          *reinterpret_cast<float4*>(go + 2 * n) = make_float4(g[n].re, g[n].im, g[n + 1].re, g[n + 1].im);
-      }
-      if (want_t) {
-        double tv = rs;
+        for (int r = 0; r < MR; ++r)
 #pragma unroll
-        for (int off = 1; off < NW; off <<= 1) tv += __shfl_xor(tv, off, 64);
-        if (act && mp == 0) B.band_sum[(ql * B.nk + k) * B.nm + nu] = tv;
-      }
-      if (act && want_l) {
-        const uint64_t base = ((uint64_t)(B.q_global0 + ql) * (uint64_t)B.nk + (uint64_t)k) * (uint64_t)E +
-                              (uint64_t)eoff;
+          for (int n = 0; n < NW; ++n)
+            *reinterpret_cast<float2*>(krow + 2 * (bcol[i] + (brow0[i] + r) * NW + n)) =
+                make_float2(g[i][r][n].re, g[i][r][n].im);
+    }
+    // 3. epilogues (the shuffles run on every lane; rows outside the tile add zero)
+    double lw[NW];
 #pragma unroll
-        for (int n = 0; n < NW; ++n) lsum += splitmix_weight(B.loss_seed, base + (uint64_t)n) * g2[n];
-      }
-      if (want_w) {
-        double lw[NW];
+    for (int n = 0; n < NW; ++n) lw[n] = 0.0;
 #pragma unroll
-        for (int n = 0; n < NW; ++n) lw[n] = 0.0;
-        if (act && lw_mode) {
-          const double em = B.eps_kq[(ql * B.nk + k) * NW + mp];
+    for (int i = 0; i < NB; ++i) {
+      const bool act = kok && bok[i];
+      const int64_t pair = bq[i] * B.nk + k;                   // (q, k) within the batch
+      const int64_t eoff = (int64_t)bnu[i] * NW2 + (int64_t)brow0[i] * NW;
+      const uint64_t base = ((uint64_t)(B.q_global0 + bq[i]) * (uint64_t)B.nk + (uint64_t)k) * (uint64_t)E +
+                            (uint64_t)eoff;
+      float* go = static_cast<float*>(B.g_out) + 2 * (pair * E + eoff);
+      double rs = 0.0;
+#pragma unroll 1
+      for (int r = 0; r < MR; ++r) {
+        const float* gr = krow + 2 * (bcol[i] + (brow0[i] + r) * NW);
+        float4 gv[NW / 2];
+#pragma unroll
+        for (int n = 0; n < NW; n += 2) {
+          const float2 a = *reinterpret_cast<const float2*>(gr + 2 * n);
+          const float2 b = *reinterpret_cast<const float2*>(gr + 2 * n + 2);
+          gv[n / 2] = act ? make_float4(a.x, a.y, b.x, b.y) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        if (act && want_g) {
+#pragma unroll
+          for (int n = 0; n < NW; n += 2) *reinterpret_cast<float4*>(go + 2 * (r * NW + n)) = gv[n / 2];
+        }
+        double g2[NW];
+#pragma unroll
+        for (int n = 0; n < NW; n += 2) {
+          const float4 v = gv[n / 2];
+          g2[n] = (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+          g2[n + 1] = (double)v.z * (double)v.z + (double)v.w * (double)v.w;
+        }
+#pragma unroll
+        for (int n = 0; n < NW; ++n) rs += g2[n];
+        if (act && want_l) {
+#pragma unroll
+          for (int n = 0; n < NW; ++n) lsum += splitmix_weight(B.loss_seed, base + (uint64_t)(r * NW + n)) * g2[n];
+        }
+        if (act && want_w && blw[i]) {
+          const double em = B.eps_kq[pair * NW + brow0[i] + r];
           const double fm = fermi_occ(em, B.lw);
-          const double wa = (nbose + fm) * B.lw.gnorm / (2.0 * om);
-          const double we = (nbose + 1.0 - fm) * B.lw.gnorm / (2.0 * om);
+          const double wa = (bnb[i] + fm) * B.lw.gnorm / (2.0 * bom[i]);
+          const double we = (bnb[i] + 1.0 - fm) * B.lw.gnorm / (2.0 * bom[i]);
 #pragma unroll
           for (int n = 0; n < NW; ++n) {
             const double en = B.eps_k[k * NW + n];
-            const double a = (en - em + om) * B.lw.inv_sigma, b = (en - em - om) * B.lw.inv_sigma;
-            lw[n] = (wa * gauss_exp<float>(a) + we * gauss_exp<float>(b)) * g2[n];
+            const double a = (en - em + bom[i]) * B.lw.inv_sigma, b = (en - em - bom[i]) * B.lw.inv_sigma;
+            lw[n] += (wa * gauss_exp<float>(a) + we * gauss_exp<float>(b)) * g2[n];
           }
         }
-        // sum over the k point's rows (all blocks and bands m of the wave)
+      }
+      if (want_t) {
+        // Nw = 8: the block's rows are split over the lane pair; Nw = 4: one lane holds the block
+        double tv = rs;
+        if (NW == 8) tv += __shfl_xor(tv, 1, 64);
+        if (act && (NW == 4 || sb == 0)) B.band_sum[pair * B.nm + bnu[i]] = tv;
+      }
+    }
+    if (want_w) {
+      // sum over the k point's rows: the lane pair holds all of them
 #pragma unroll
-        for (int off = 1; off < RK; off <<= 1)
-#pragma unroll
-          for (int n = 0; n < NW; ++n) lw[n] += __shfl_xor(lw[n], off, 64);
-        double mine = 0.0;
+      for (int n = 0; n < NW; ++n) lw[n] += __shfl_xor(lw[n], 1, 64);
+      if (kok && cw0 < j.N) {
+        double* dst = B.lw_partial + ((cw0 / TN) * B.nk + k) * NW;
 #pragma unroll
         for (int n = 0; n < NW; ++n)
-          if (n == r) mine = lw[n];
-        if (r < NW && k < j.M && cw0 < j.N) B.lw_partial[((cw0 / TN) * B.nk + k) * NW + r] = mine;
+          if ((n & 1) == sb) dst[n] = lw[n];
       }
+    }
+  }
+  if (want_l) {
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off, 64);
+    double* red = reinterpret_cast<double*>(smem);
+    __syncthreads();
+    if (lane == 0) red[wave] = lsum;
+    __syncthreads();
+    if (tid == 0) B.loss_partial[j.tile] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+// The same rotations for Nw = 8 when every tile's 128 columns are the two
+// modes (nu0, nu0 + 1) of one q (Nm even), on the matrix cores.  Per k point:
+//   T = W V(k) with the two modes' W rows stacked (16 rows (nu, m') x 8 bands,
+//   both modes share V(k)); g_nu^T = T_nu^T conj(V(k+q)) with rows (nu, n).
+// Each complex product is one 16x16 real MFMA product with K = 16 in the
+// real embedding [X_re X_im] [[Y_re, Y_im], [-Y_im, Y_re]] = [Z_re Z_im]
+// (four v_mfma_f32_16x16x4_f32), so the two rotations of a k point are
+// eight MFMAs (1.6 % of the tile's main loop).  The operands come from the
+// tile's W rows staged in LDS (both modes' waves), V(k) and V(k+q) from
+// global memory (two complex values per lane and k point); the transpose
+// between the products and the final store go through the k point's LDS
+// rows.  A wave takes 16 k points per half, KI of them per iteration as
+// independent MFMA chains.
+__device__ __forceinline__ float emb_b(int j_hi, bool c_lo, float re, float im, bool conj_b) {
+  // element (j, c) of the real embedding of Y (conj_b: of conj(Y)) given
+  // Y[j mod 8][c mod 8] = re + i im: j < 8 rows give (Re, Im) by column half,
+  // j >= 8 rows (-Im, Re)
+  const float yi = conj_b ? -im : im;
+  if (!j_hi) return c_lo ? re : yi;
+  return c_lo ? -yi : re;
+}
+
+__device__ __forceinline__ void band_epilogue_mfma8(const TileJob<float>& j, const BandEpilogue& B, int64_t m0,
+                                                    int64_t n0, typename Mfma<float>::v4 (&acc_r)[4][4],
+                                                    typename Mfma<float>::v4 (&acc_i)[4][4], float* smem) {
+  using V4 = typename Mfma<float>::v4;
+  constexpr int TM = 64, TN = 64, HR = 32, LDW = TN + 1, KI = 4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave % 2, wn = wave / 2;
+  const int lrow = lane >> 4, lcol = lane & 15;
+  const int g4 = lane >> 4, c16 = lane & 15, cc = c16 & 7;
+  const bool c_lo = c16 < 8;
+  const int64_t E = (int64_t)B.nm * 64;
+  const int64_t ql = n0 / E;                               // the tile's q (its columns lie in one q)
+  const int nu0 = (int)((n0 - ql * E) / 64);              // first of its two modes
+  const bool want_g = (B.flags & EPHW_OUT_G) != 0, want_t = (B.flags & EPHW_OUT_BAND_SUM) != 0;
+  const bool want_l = (B.flags & EPHW_OUT_LOSS) != 0, want_w = B.lw_partial != nullptr;
+  const float* Vk = static_cast<const float*>(B.Vk);
+  const float* Vkq = static_cast<const float*>(B.Vkq);
+  auto region = [&](int wm_, int nu_l) { return smem + (nu_l * 2 + wm_) * (HR * LDW * 2); };
+  // linewidth: the lane's mode in the second product's output is nu0 + g4 / 2
+  double om = 0.0, nbose = 0.0;
+  bool lw_mode = false;
+  if (want_w) {
+    om = B.omega[ql * B.nm + nu0 + g4 / 2];
+    lw_mode = om > 0.0 && om >= B.lw.omega_min;
+    if (lw_mode) nbose = 1.0 / expm1(om * B.lw.inv_t);
+  }
+  double lsum = 0.0;
+  float* wl = smem + wave * (HR * LDW * 2);
+  const int wsrc = wave >> 1, ksub = wave & 1;             // rows of wave-row wsrc, 16-row half ksub
+#pragma unroll 1
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();   // the K loop's stages / the previous half's rows are done with
+#pragma unroll
+    for (int ii = 0; ii < 2; ++ii)
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = ii * 16 + Mfma<float>::row(lrow, v), col = jj * 16 + lcol;
+          const float re = h == 0 ? acc_r[ii][jj][v] : acc_r[2 + ii][jj][v];
+          const float im = h == 0 ? acc_i[ii][jj][v] : acc_i[2 + ii][jj][v];
+          *reinterpret_cast<float2*>(wl + 2 * (row * LDW + col)) = make_float2(re, im);
+        }
+    __syncthreads();   // both modes' rows of every k point are staged
+#pragma unroll 1
+    for (int it = 0; it < 16; it += KI) {
+      int kl[KI];
+      int64_t k[KI];
+      bool kok[KI];
+#pragma unroll
+      for (int u = 0; u < KI; ++u) {
+        kl[u] = ksub * 16 + it + u;
+        k[u] = m0 + wsrc * TM + h * HR + kl[u];
+        kok[u] = k[u] < j.M;
+      }
+      // operands of the first product: V(k)[g][cc], V(k)[4+g][cc]; W rows
+      V4 acc[KI];
+      float2 v0[KI], v1[KI], u0[KI], u1[KI];
+#pragma unroll
+      for (int u = 0; u < KI; ++u) {
+        const int64_t kk = kok[u] ? k[u] : 0;
+        const float* vk = Vk + 2 * kk * 64;
+        v0[u] = *reinterpret_cast<const float2*>(vk + 2 * (g4 * 8 + cc));
+        v1[u] = *reinterpret_cast<const float2*>(vk + 2 * ((4 + g4) * 8 + cc));
+        const float* vq;
+        if (Vkq) {
+          vq = Vkq + 2 * ((ql * B.nk + kk) * 64);
+        } else {
+          int64_t id = kok[u] ? B.kq_index[ql * B.nk + kk] : 0;
+          if (id < 0 || id >= B.nk) {
+            atomicOr(B.status, kStatusIndex);
+            id = 0;
+          }
+          vq = Vk + 2 * id * 64;
+        }
+        u0[u] = *reinterpret_cast<const float2*>(vq + 2 * (g4 * 8 + cc));
+        u1[u] = *reinterpret_cast<const float2*>(vq + 2 * ((4 + g4) * 8 + cc));
+        acc[u] = V4{0.f, 0.f, 0.f, 0.f};
+      }
+      // T = W V(k): A[(nu, m')][(part, n')] = W_part[nu][m'][n'], lane row c16
+#pragma unroll
+      for (int u = 0; u < KI; ++u) {
+        const float* wr = region(wsrc, c16 >> 3) + 2 * (kl[u] * LDW + (c16 & 7) * 8);
+        const float2 w0 = *reinterpret_cast<const float2*>(wr + 2 * g4);
+        const float2 w1 = *reinterpret_cast<const float2*>(wr + 2 * (4 + g4));
+        const float a[4] = {w0.x, w1.x, w0.y, w1.y};
+        const float b[4] = {emb_b(0, c_lo, v0[u].x, v0[u].y, false), emb_b(0, c_lo, v1[u].x, v1[u].y, false),
+                            emb_b(1, c_lo, v0[u].x, v0[u].y, false), emb_b(1, c_lo, v1[u].x, v1[u].y, false)};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) acc[u] = Mfma<float>::op(a[s4], b[s4], acc[u]);
+      }
+      wave_sync();   // every lane has read its W operands
+      // T rows back to the k point's LDS rows: lane holds T_part[nu][m'][n],
+      // nu = g4 / 2, m' = 4 (g4 % 2) + i, part = c16 / 8, n = cc
+#pragma unroll
+      for (int u = 0; u < KI; ++u) {
+        float* tr = region(wsrc, g4 >> 1) + 2 * (kl[u] * LDW);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) tr[2 * ((4 * (g4 & 1) + i) * 8 + cc) + (c16 >> 3)] = acc[u][i];
+        acc[u] = V4{0.f, 0.f, 0.f, 0.f};
+      }
+      wave_sync();
+      // g^T = T^T conj(V(k+q)): A[(nu, n)][(part, m')] = T_part[nu][m'][n], lane row c16
+#pragma unroll
+      for (int u = 0; u < KI; ++u) {
+        const float* tr = region(wsrc, c16 >> 3) + 2 * (kl[u] * LDW);
+        const int n = c16 & 7;
+        const float a[4] = {tr[2 * (g4 * 8 + n)], tr[2 * ((4 + g4) * 8 + n)], tr[2 * (g4 * 8 + n) + 1],
+                            tr[2 * ((4 + g4) * 8 + n) + 1]};
+        const float b[4] = {emb_b(0, c_lo, u0[u].x, u0[u].y, true), emb_b(0, c_lo, u1[u].x, u1[u].y, true),
+                            emb_b(1, c_lo, u0[u].x, u0[u].y, true), emb_b(1, c_lo, u1[u].x, u1[u].y, true)};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) acc[u] = Mfma<float>::op(a[s4], b[s4], acc[u]);
+      }
+      wave_sync();   // every lane has read its T operands
+      // lane holds part c16 / 8 of g_nu[m][n], nu = nu0 + g4 / 2, n = 4 (g4 % 2) + i, m = cc
+#pragma unroll
+      for (int u = 0; u < KI; ++u) {
+        const int nul = g4 >> 1;
+        double vsq[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vsq[i] = (double)acc[u][i] * (double)acc[u][i];
+        const int64_t pair = ql * B.nk + k[u];
+        if (want_g) {
+          float* gr = region(wsrc, nul) + 2 * (kl[u] * LDW);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) gr[2 * (cc * 8 + 4 * (g4 & 1) + i) + (c16 >> 3)] = acc[u][i];
+        }
+        if (want_t) {
+          double tv = (vsq[0] + vsq[1]) + (vsq[2] + vsq[3]);
+#pragma unroll
+          for (int off = 1; off < 32; off <<= 1) tv += __shfl_xor(tv, off, 64);
+          if (kok[u] && (lane & 31) == 0) B.band_sum[pair * B.nm + nu0 + nul] = tv;
+        }
+        if (want_l && kok[u]) {
+          const uint64_t base = ((uint64_t)(B.q_global0 + ql) * (uint64_t)B.nk + (uint64_t)k[u]) * (uint64_t)E +
+                                (uint64_t)(nu0 + nul) * 64u + (uint64_t)cc * 8u + (uint64_t)(4 * (g4 & 1));
+#pragma unroll
+          for (int i = 0; i < 4; ++i) lsum += splitmix_weight(B.loss_seed, base + (uint64_t)i) * vsq[i];
+        }
+        if (want_w) {
+          double lw[4] = {0.0, 0.0, 0.0, 0.0};
+          if (kok[u] && lw_mode) {
+            const double em = B.eps_kq[pair * 8 + cc];
+            const double fm = fermi_occ(em, B.lw);
+            const double wa = (nbose + fm) * B.lw.gnorm / (2.0 * om);
+            const double we = (nbose + 1.0 - fm) * B.lw.gnorm / (2.0 * om);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const double en = B.eps_k[k[u] * 8 + 4 * (g4 & 1) + i];
+              const double x = (en - em + om) * B.lw.inv_sigma, y = (en - em - om) * B.lw.inv_sigma;
+              lw[i] = (wa * gauss_exp<float>(x) + we * gauss_exp<float>(y)) * vsq[i];
+            }
+          }
+          // sum over m and the part: the 16 lanes of a lane group
+#pragma unroll
+          for (int off = 1; off < 16; off <<= 1)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) lw[i] += __shfl_xor(lw[i], off, 64);
+          if (kok[u] && c16 == 0) {
+            double* dst = B.lw_partial + (((n0 + nul * TN) / TN) * B.nk + k[u]) * 8 + 4 * (g4 & 1);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) dst[i] = lw[i];
+          }
+        }
+      }
+      if (want_g) {
+        wave_sync();   // the k points' g blocks are complete in LDS
+        // each k point's two modes are 128 consecutive complex values of g:
+        // lane l stores values 2l, 2l + 1 (mode l / 32)
+#pragma unroll
+        for (int u = 0; u < KI; ++u) {
+          if (!kok[u]) continue;
+          const float* gr = region(wsrc, lane >> 5) + 2 * (kl[u] * LDW + 2 * (lane & 31));
+          const float2 x0 = *reinterpret_cast<const float2*>(gr);
+          const float2 x1 = *reinterpret_cast<const float2*>(gr + 2);
+          float* go = static_cast<float*>(B.g_out) + 2 * ((ql * B.nk + k[u]) * E + (int64_t)nu0 * 64 + 2 * lane);
+          *reinterpret_cast<float4*>(go) = make_float4(x0.x, x0.y, x1.x, x1.y);
+        }
+      }
+      wave_sync();   // the next k points' rows are other rows; keep the order simple
     }
   }
   if (want_l) {
@@ -629,7 +933,11 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
   if constexpr (BANDNW > 0) {
     static_assert(sizeof(T) == 4 && BM == 128 && BN == 128 && WM == 2 && WN == 2 && SPLIT == 0,
                   "the band epilogue runs on the FP32 128x128 tile");
-    band_epilogue<BANDNW>(j, *band, m0, n0, acc_r, acc_i, smem);
+    // BANDNW: 4 or 8 the rotations on VALU; 16 the Nw = 8 rotations on MFMA
+    if constexpr (BANDNW == 16)
+      band_epilogue_mfma8(j, *band, m0, n0, acc_r, acc_i, smem);
+    else
+      band_epilogue<BANDNW>(j, *band, m0, n0, acc_r, acc_i, smem);
     return;
   }
   // --- epilogue: lane holds column lcol of every block, rows per Mfma<T>::row --
@@ -1168,6 +1476,9 @@ ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream) {
       set_error("cgemm: the fused band epilogue stores g in 16-byte chunks (g must be 16-byte aligned)");
       return EPHW_EINVAL;
     }
+    // Nw = 8 with an even mode count: every tile holds two whole modes of one
+    // q, which the MFMA form of the rotations needs
+    if (b.nw == 8 && b.nm % 2 == 0) return launch<float, 128, 128, 16, 2, 2, false, false, 0, 2, 16>(p, stream);
     return b.nw == 8 ? launch<float, 128, 128, 16, 2, 2, false, false, 0, 2, 8>(p, stream)
                      : launch<float, 128, 128, 16, 2, 2, false, false, 0, 2, 4>(p, stream);
   }
