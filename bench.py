@@ -492,12 +492,14 @@ def bench_window(args):
 
 
 def bench_linewidth(args):
-    """The downstream reduction on the dense-Si grids (8000 k x 8000 q, FP32):
-    per q chunk, Eq. (7) stores g and the linewidth kernel reduces it over q
-    into gamma[k][n]; the reduction's own time is bracketed by HIP events."""
+    """The downstream reduction on the dense-Si grids (8000 k x 8000 q, FP32),
+    two ways: fused (ephw_interpolate_linewidth: the band rotations and the
+    linewidth terms in the Eq. (10) GEMM's epilogue, g never stored) and
+    stored (per q chunk, Eq. (7) stores g and ephw_linewidth reduces it).
+    Both gammas are compared; the fused pass is the headline of the line."""
     import torch
     import synth
-    from paper_2603_10295_amd import ephw
+    from paper_2603_10295_amd import ephw, model
     w = synth.si_dense(m=args.grid)
     s = w.system
     nk, nq = len(w.k), len(w.q)
@@ -507,9 +509,6 @@ def bench_linewidth(args):
     q = torch.from_numpy(w.q).to("cuda:0")
     kqi = torch.from_numpy(w.kq_index).to("cuda:0")
     qc = min(args.q_chunk, nq)
-    g = torch.empty((qc, nk, s.nm, s.nw, s.nw), dtype=torch.complex64, device="cuda:0")
-    ekq = torch.empty((qc, nk, s.nw), dtype=torch.float64, device="cuda:0")
-    om = torch.empty((qc, s.nm), dtype=torch.float64, device="cuda:0")
     eps_k = torch.empty((nk, s.nw), dtype=torch.float64, device="cuda:0")
     gamma = torch.zeros((nk, s.nw), dtype=torch.float64, device="cuda:0")
     ks0 = ephw.KSet(sysh, k, ephw.FP32)
@@ -517,13 +516,45 @@ def bench_linewidth(args):
     e = eps_k.cpu().numpy()
     ks0.close()
     temp, mu, sigma = 0.02 * float(np.ptp(e)), float(np.median(e)), 0.01 * float(np.ptp(e))
+    cnt = model.stage_counts(s.nw, s.nm, s.ne, s.np_, nk, nq, nh=len(s.r_h), kq_on_grid=True)
+
+    def fused_step():
+        gamma.zero_()
+        ks = ephw.KSet(sysh, k, ephw.FP32)
+        for q0 in range(0, nq, qc):
+            q1 = min(nq, q0 + qc)
+            ephw.interpolate_linewidth(ks, q[q0:q1], gamma, kq_index=kqi[q0:q1], temperature=temp, mu=mu,
+                                       sigma=sigma, nq_total=nq)
+        ks.close()
+
+    for _ in range(args.warmup):
+        fused_step()
+    torch.cuda.synchronize()
+    sysh.profile_read()
+    sysh.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fused_step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ctx.check()
+    stages = sysh.profile_read()
+    sysh.profile(False)
+    gamma_fused = gamma.cpu().numpy()
+    re_ms, re_n = stages["re_gemm"]
+    re_tflops = 8.0 * cnt.re * args.steps / (re_ms * 1e-3) / 1e12
+    log(f"fused pass {dt * 1e3:.1f} ms (Re GEMM with rotations and linewidth terms {re_ms / args.steps:.1f} ms)")
+
+    # the stored-g reference: Eq. (7) per q chunk into g, then ephw_linewidth
+    g = torch.empty((qc, nk, s.nm, s.nw, s.nw), dtype=torch.complex64, device="cuda:0")
+    ekq = torch.empty((qc, nk, s.nw), dtype=torch.float64, device="cuda:0")
+    om = torch.empty((qc, s.nm), dtype=torch.float64, device="cuda:0")
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     lw_ms = []
 
-    def step():
+    def stored_step():
         gamma.zero_()
         ks = ephw.KSet(sysh, k, ephw.FP32)
-        ks.bands(eps_k)
         t = 0.0
         for q0 in range(0, nq, qc):
             q1 = min(nq, q0 + qc)
@@ -539,33 +570,40 @@ def bench_linewidth(args):
         ks.close()
         lw_ms.append(t)
 
-    for _ in range(args.warmup):
-        step()
+    stored_step()
     torch.cuda.synchronize()
     lw_ms.clear()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    for _ in range(max(1, args.steps // 2)):
+        stored_step()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    dt_stored = (time.perf_counter() - t0) / max(1, args.steps // 2)
     ctx.check()
+    gamma_stored = gamma.cpu().numpy()
     lw = sum(lw_ms) / len(lw_ms)
+    diff = float(np.abs(gamma_fused - gamma_stored).max() / np.abs(gamma_stored).max())
     E = s.nm * s.nw * s.nw
     elems = nk * nq * E
-    log(f"pass {dt * 1e3:.1f} ms, of which the linewidth reduction {lw:.1f} ms "
-        f"({elems * 8 / (lw * 1e-3) / 1e9:.0f} GB/s of g read)")
+    log(f"stored-g pass {dt_stored * 1e3:.1f} ms, of which the linewidth reduction {lw:.1f} ms; "
+        f"fused vs stored gamma: {diff:.2e} of the largest")
     line = {
-        "metric": "g(k,q) elems/s reduced into linewidths (FP32 MFMA interpolation + FP64-weighted reduction)",
+        "metric": "g(k,q) elems/s reduced into linewidths (FP32 MFMA interpolation, rotations and "
+                  "FP64-weighted reduction fused, g not stored)",
         "value": elems / dt, "unit": "elems/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
         "data": "synthetic",
         "config": {"workload": f"si_dense_linewidth_nw8_nm6_ne1000_{nk}kx{nq}q", "nk": nk, "nq": nq,
-                   "temperature": temp, "mu": mu, "sigma": sigma},
-        "linewidth_ms_per_step": lw,
-        "roofline": {"bound": "hbm", "achieved": elems * 8 / (lw * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
-                     "frac": elems * 8 / (lw * 1e-3) / 1e9 / 8000.0, "traffic": None,
-                     "kernel": "linewidth_kernel<float> (g read once)"},
-        "gamma_norm": float(torch.linalg.vector_norm(gamma).cpu()),
+                   "temperature": temp, "mu": mu, "sigma": sigma, "q_chunk": qc},
+        "roofline": {"bound": "mfma", "achieved": re_tflops, "peak": model.PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": re_tflops / model.PEAK_FP32_TFLOPS, "traffic": None,
+                     "kernel": "cgemm_kernel<float> Re phase sum (Eq. 10) with the band rotations and linewidth "
+                               "terms in its epilogue (Re-sum flops credited only)",
+                     "avg_launch_ms": re_ms / max(1, re_n), "launches": re_n},
+        "stages_ms_per_step": {k_: round(v[0] / args.steps, 3) for k_, v in stages.items()},
+        "stored_g": {"ms_per_step": dt_stored * 1e3, "linewidth_ms_per_step": lw,
+                     "linewidth_read_GBps": elems * 8 / (lw * 1e-3) / 1e9},
+        "fused_vs_stored_gamma_rel": diff,
+        "gamma_norm": float(np.linalg.norm(gamma_fused)),
     }
     print(json.dumps(line), flush=True)
     return 0

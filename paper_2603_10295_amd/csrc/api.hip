@@ -634,7 +634,7 @@ InterpWs interp_layout(const ephw_system* s, const InterpReq& r, char* base) {
   if (r.lw) {
     w.om = takd((size_t)nq * nm * 8);
     if (r.fused)
-      w.lwp = takd((size_t)ceil_div(qb * E, 64) * nk * nw * 8);
+      w.lwp = takd((size_t)cgemm_band_lw_groups(nw, (int)nm, qb * E) * nk * nw * 8 + column_sum_scratch(nk * nw));
     else
       w.gchunk = take((size_t)qb * nk * E * cs);
   }
@@ -819,7 +819,11 @@ ephw_status interpolate_small(ephw_kset* ks, const double* q, const int32_t* kq_
       }
       Stage sg_(s, EPHW_STAGE_OTHER, st, stages);
       if (flags & EPHW_OUT_LOSS) EPHW_TRY(sum_into(w.loss, ceil_div(re.M, 128) * ceil_div(re.N, 128), loss, st));
-      if (r.lw) EPHW_TRY(add_column_sums(w.lwp, ceil_div(re.N, 64), nk * nw, r.lwp.scale, r.gamma, st));
+      if (r.lw) {
+        const int64_t groups = cgemm_band_lw_groups(nw, nm, re.N);
+        EPHW_TRY(add_column_sums(w.lwp, groups, nk * nw, r.lwp.scale, r.gamma,
+                                 w.lwp + cgemm_band_lw_groups(nw, nm, (int64_t)qb * E) * nk * nw, st));
+      }
       continue;
     }
     {

@@ -221,21 +221,44 @@ LwKernel<T> lw_rows_kernel(int nw) {
   }
 }
 
-__global__ void add_column_sums_kernel(const double* __restrict__ x, int64_t ncol, int64_t n, double scale,
-                                       double* __restrict__ out) {
+constexpr int64_t kColChunk = 16;     // columns per partial sum
+constexpr int64_t kColChunksMax = 64; // chunks held in the scratch (more: chunks of more columns)
+
+__global__ void column_chunk_sums_kernel(const double* __restrict__ x, int64_t ncol, int64_t n, int64_t chunk,
+                                         double* __restrict__ part) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.y * chunk;
+  if (i >= n) return;
+  const int64_t c1 = c0 + chunk < ncol ? c0 + chunk : ncol;
+  double s = 0.0;
+  for (int64_t c = c0; c < c1; ++c) s += x[c * n + i];
+  part[blockIdx.y * n + i] = s;
+}
+
+__global__ void add_chunk_sums_kernel(const double* __restrict__ part, int64_t nchunk, int64_t n, double scale,
+                                      double* __restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double s = 0.0;
-  for (int64_t c = 0; c < ncol; ++c) s += x[c * n + i];
+  for (int64_t c = 0; c < nchunk; ++c) s += part[c * n + i];
   out[i] += scale * s;
 }
 
 }  // namespace
 
-ephw_status add_column_sums(const double* x, int64_t ncol, int64_t n, double scale, double* out, hipStream_t s) {
+size_t column_sum_scratch(int64_t n) { return (size_t)kColChunksMax * (size_t)n * sizeof(double); }
+
+ephw_status add_column_sums(const double* x, int64_t ncol, int64_t n, double scale, double* out, double* scratch,
+                            hipStream_t s) {
   if (n <= 0 || ncol <= 0) return EPHW_OK;
-  hipLaunchKernelGGL(add_column_sums_kernel, dim3((unsigned)ceil_div(n, (int64_t)256)), dim3(256), 0, s, x, ncol, n,
-                     scale, out);
+  int64_t chunk = kColChunk;
+  while (ceil_div(ncol, chunk) > kColChunksMax) chunk *= 2;
+  const int64_t nchunk = ceil_div(ncol, chunk);
+  const unsigned gx = (unsigned)ceil_div(n, (int64_t)256);
+  hipLaunchKernelGGL(column_chunk_sums_kernel, dim3(gx, (unsigned)nchunk), dim3(256), 0, s, x, ncol, n, chunk,
+                     scratch);
+  EPHW_CHECK_LAUNCH();
+  hipLaunchKernelGGL(add_chunk_sums_kernel, dim3(gx), dim3(256), 0, s, scratch, nchunk, n, scale, out);
   EPHW_CHECK_LAUNCH();
   return EPHW_OK;
 }

@@ -35,8 +35,9 @@ struct LossEpilogue {
 //   EPHW_OUT_BAND_SUM T_nu = sum_mn |g|^2 stored [q][k][nu]
 //   EPHW_OUT_LOSS     sum of w |g|^2 over the tile -> loss_partial[tile]
 //   lw_partial        linewidth terms of every element (the weights of
-//                     ephw_linewidth) summed over the (q, nu, m) of a wave's 64
-//                     columns -> lw_partial[c / 64][k][n]
+//                     ephw_linewidth) summed over the (q, nu, m) of a column
+//                     group -> lw_partial[group][k][n], cgemm_band_lw_groups
+//                     groups of 64 or 128 columns
 struct BandEpilogue {
   bool on = false;
   int nw = 0, nm = 0;
@@ -50,7 +51,7 @@ struct BandEpilogue {
   double* band_sum = nullptr;     // [qb][nk][nm], offset to the batch
   double* loss_partial = nullptr; // [tiles of the launch]
   uint64_t loss_seed = 0;
-  double* lw_partial = nullptr;   // [N / 64][nk][nw], or NULL: no linewidth terms
+  double* lw_partial = nullptr;   // [groups][nk][nw], or NULL: no linewidth terms
   const double* eps_k = nullptr;  // [nk][nw]
   const double* eps_kq = nullptr; // [qb][nk][nw]
   const double* omega = nullptr;  // [qb][nm]
@@ -93,6 +94,8 @@ struct GemmParams {
 // nw 4 or 8; always on 128x128 tiles, ceil(M/128) * ceil(N/128) of them);
 // otherwise the caller stores W and rotates
 bool cgemm_band_fusable(int prec, int64_t M, int64_t N, int nw, int64_t lda, int64_t ldb);
+// column groups of the fused epilogue's linewidth partials for N columns
+int64_t cgemm_band_lw_groups(int nw, int nm, int64_t N);
 // workgroup tiles per batch entry of a GEMM (size of the loss partial block)
 int64_t cgemm_tiles(int prec, int64_t M, int64_t N);
 

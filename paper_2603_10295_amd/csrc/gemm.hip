@@ -447,6 +447,16 @@ __device__ __forceinline__ float emb_b(int j_hi, bool c_lo, float re, float im, 
   return c_lo ? -yi : re;
 }
 
+// exp(-x^2/2) and the Fermi occupation 1/(exp(x)+1) on the hardware exp2
+// (v_exp_f32, about 1 ulp): the fused epilogue's per-element weights
+__device__ __forceinline__ float gauss_fast(float x) {
+  return __builtin_amdgcn_exp2f(-0.72134752044448170368f * x * x);   // 0.5 log2(e)
+}
+__device__ __forceinline__ float fermi_fast(float x) {
+  const float z = __builtin_amdgcn_exp2f(-1.44269504088896340736f * fabsf(x));   // exp(-|x|)
+  return x > 0.f ? z / (1.f + z) : 1.f / (1.f + z);
+}
+
 __device__ __forceinline__ void band_epilogue_mfma8(const TileJob<float>& j, const BandEpilogue& B, int64_t m0,
                                                     int64_t n0, typename Mfma<float>::v4 (&acc_r)[4][4],
                                                     typename Mfma<float>::v4 (&acc_i)[4][4], float* smem) {
@@ -466,13 +476,17 @@ __device__ __forceinline__ void band_epilogue_mfma8(const TileJob<float>& j, con
   const float* Vkq = static_cast<const float*>(B.Vkq);
   auto region = [&](int wm_, int nu_l) { return smem + (nu_l * 2 + wm_) * (HR * LDW * 2); };
   // linewidth: the lane's mode in the second product's output is nu0 + g4 / 2
-  double om = 0.0, nbose = 0.0;
+  double om = 0.0, nbose = 0.0, amp0 = 0.0;
   bool lw_mode = false;
   if (want_w) {
     om = B.omega[ql * B.nm + nu0 + g4 / 2];
     lw_mode = om > 0.0 && om >= B.lw.omega_min;
-    if (lw_mode) nbose = 1.0 / expm1(om * B.lw.inv_t);
+    if (lw_mode) {
+      nbose = 1.0 / expm1(om * B.lw.inv_t);
+      amp0 = B.lw.gnorm / (2.0 * om);
+    }
   }
+  const float inv_sigma_f = (float)B.lw.inv_sigma;
   double lsum = 0.0;
   float* wl = smem + wave * (HR * LDW * 2);
   const int wsrc = wave >> 1, ksub = wave & 1;             // rows of wave-row wsrc, 16-row half ksub
@@ -588,29 +602,50 @@ __device__ __forceinline__ void band_epilogue_mfma8(const TileJob<float>& j, con
           for (int i = 0; i < 4; ++i) lsum += splitmix_weight(B.loss_seed, base + (uint64_t)i) * vsq[i];
         }
         if (want_w) {
+          // |g|^2 of the lane's four elements: the other part sits in lane c16 ^ 8
+          double s2[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float o = __shfl_xor(acc[u][i], 8, 64);
+            s2[i] = vsq[i] + (double)o * (double)o;
+          }
+          // the lane pair (c16, c16 ^ 8) splits the two terms: absorption
+          // (N + f_m) G(e_n - e_m + omega) on c16 < 8, emission (N + 1 - f_m)
+          // G(e_n - e_m - omega) on c16 >= 8
           double lw[4] = {0.0, 0.0, 0.0, 0.0};
           if (kok[u] && lw_mode) {
+            // c64 data: occupation and Gaussians from the hardware exp2 in
+            // FP32 (relative error near 1e-7, below the data's own); the energy
+            // differences in FP64
             const double em = B.eps_kq[pair * 8 + cc];
-            const double fm = fermi_occ(em, B.lw);
-            const double wa = (nbose + fm) * B.lw.gnorm / (2.0 * om);
-            const double we = (nbose + 1.0 - fm) * B.lw.gnorm / (2.0 * om);
+            const double fm = (double)fermi_fast((float)((em - B.lw.mu) * B.lw.inv_t));
+            const double amp = (c_lo ? nbose + fm : nbose + 1.0 - fm) * amp0;
+            const double sh = (c_lo ? om : -om) - em;
+            const double2 e01 = *reinterpret_cast<const double2*>(B.eps_k + k[u] * 8 + 4 * (g4 & 1));
+            const double2 e23 = *reinterpret_cast<const double2*>(B.eps_k + k[u] * 8 + 4 * (g4 & 1) + 2);
+            const double en[4] = {e01.x, e01.y, e23.x, e23.y};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-              const double en = B.eps_k[k[u] * 8 + 4 * (g4 & 1) + i];
-              const double x = (en - em + om) * B.lw.inv_sigma, y = (en - em - om) * B.lw.inv_sigma;
-              lw[i] = (wa * gauss_exp<float>(x) + we * gauss_exp<float>(y)) * vsq[i];
-            }
+            for (int i = 0; i < 4; ++i)
+              lw[i] = amp * (double)gauss_fast((float)(en[i] + sh) * inv_sigma_f) * s2[i];
           }
-          // sum over m and the part: the 16 lanes of a lane group
+          // sum over m, both terms and both modes for each band n: halve the
+          // four values over lane bits 0 and 1, then add over bits 2, 3 and 5
+          const int b0 = lane & 1, b1 = (lane >> 1) & 1;
+          double l2[2];
 #pragma unroll
-          for (int off = 1; off < 16; off <<= 1)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) lw[i] += __shfl_xor(lw[i], off, 64);
-          if (kok[u] && c16 == 0) {
-            double* dst = B.lw_partial + (((n0 + nul * TN) / TN) * B.nk + k[u]) * 8 + 4 * (g4 & 1);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) dst[i] = lw[i];
+          for (int jj = 0; jj < 2; ++jj) {
+            const double mine = b0 ? lw[2 + jj] : lw[jj];
+            const double other = b0 ? lw[jj] : lw[2 + jj];
+            l2[jj] = mine + __shfl_xor(other, 1, 64);
           }
+          double v = b1 ? l2[1] : l2[0];
+          v += __shfl_xor(b1 ? l2[0] : l2[1], 2, 64);
+          v += __shfl_xor(v, 4, 64);
+          v += __shfl_xor(v, 8, 64);
+          v += __shfl_xor(v, 32, 64);
+          // lanes c16 < 4 of groups 0 and 1 hold band n = 4 g4 + 2 b0 + b1
+          if (kok[u] && c16 < 4 && g4 < 2)
+            B.lw_partial[((n0 / 128) * B.nk + k[u]) * 8 + 4 * g4 + 2 * b0 + b1] = v;
         }
       }
       if (want_g) {
@@ -1460,6 +1495,12 @@ bool cgemm_band_fusable(int prec, int64_t M, int64_t N, int nw, int64_t lda, int
   if (prec != 1 || (nw != 4 && nw != 8) || M <= 0 || N <= 0) return false;
   return ceil_div(M, 128) * ceil_div(N, 128) <= 0x7fffffff &&
          lane_offsets_fit<float, 128, 128, 16, 2, 2, false, false>(lda, ldb);
+}
+
+// the MFMA form (Nw = 8, even Nm) sums a tile's two modes into one group of
+// 128 columns; the VALU forms write one group per wave's 64 columns
+int64_t cgemm_band_lw_groups(int nw, int nm, int64_t N) {
+  return (nw == 8 && nm % 2 == 0) ? ceil_div(N, 128) : ceil_div(N, 64);
 }
 
 ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream) {

@@ -39,8 +39,12 @@ ephw_status degenerate_sums(int prec, const void* g, int64_t nq, int64_t nk, int
                             double* out, hipStream_t s);
 
 // gamma[k][n] += phonon-limited linewidth contributions of the q list (see epilogue.hip)
-// out[i] += scale * sum_c x[c][i] for i < n, c < ncol, summed in order of c
-ephw_status add_column_sums(const double* x, int64_t ncol, int64_t n, double scale, double* out, hipStream_t s);
+// out[i] += scale * sum_c x[c][i] for i < n, c < ncol: partial sums over
+// fixed chunks of c into `scratch` (column_sum_scratch(n) bytes), then the
+// chunks in order (deterministic)
+size_t column_sum_scratch(int64_t n);
+ephw_status add_column_sums(const double* x, int64_t ncol, int64_t n, double scale, double* out, double* scratch,
+                            hipStream_t s);
 ephw_status linewidth(int prec, const void* g, int64_t nq, int64_t nk, int nm, int nw, const double* eps_k,
                       const double* eps_kq, const double* omega, double temperature, double mu, double sigma,
                       double omega_min, int64_t nq_total, double* gamma, hipStream_t s);
