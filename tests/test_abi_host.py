@@ -135,3 +135,50 @@ def test_wrappers_check_buffer_types_before_the_call():
         ephw.degenerate_sums(ephw.FP64, g, eps_kq, eps_k, om, out)
     with pytest.raises(ValueError, match="lam"):
         ephw.degenerate_sums(ephw.FP32, g, eps_kq, eps_k, om[:, :3], out)
+
+
+def test_host_validation_under_address_and_ub_sanitizers(tmp_path):
+    """The host side of every .hip source, compiled without device code and
+    with AddressSanitizer and UndefinedBehaviorSanitizer, linked with a C
+    driver that calls each entry point with invalid arguments
+    (tests/abi_host_check.c): every call returns its status with no invalid
+    access, overflow, undefined operation or leak."""
+    import concurrent.futures as cf
+    import glob
+    import shutil
+    import subprocess
+    from paper_2603_10295_amd import build as b
+
+    hipcc = b.hipcc()
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=all"]
+    host_only = [f"--offload-arch={b.ARCH}", "--offload-host-only", "-fgpu-rdc"]
+    inc = ["-I", os.path.join(ROOT, "include")]
+
+    def compile_one(src):
+        obj = str(tmp_path / (os.path.basename(src) + ".o"))
+        cmd = [hipcc, *host_only, "-x", "hip", "-std=c++17", "-O1", "-g", "-fPIC", "-fno-omit-frame-pointer",
+               *san, *inc, "-c", src, "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr[-3000:]
+        return obj
+
+    srcs = sorted(glob.glob(os.path.join(ROOT, "paper_2603_10295_amd", "csrc", "*.hip")))
+    with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        objs = list(ex.map(compile_one, srcs))
+    drv = str(tmp_path / "drv.o")
+    r = subprocess.run([gcc, "-std=c11", "-O1", "-g", "-fsanitize=address", "-fsanitize=undefined",
+                        "-fno-sanitize-recover=all", *inc, "-c", os.path.join(ROOT, "tests", "abi_host_check.c"),
+                        "-o", drv], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    exe = str(tmp_path / "abi_host_check")
+    r = subprocess.run([hipcc, *host_only, *san, drv, *objs, "-o", exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:exitcode=23:verify_asan_link_order=0",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=120)
+    assert r.returncode == 0, (r.returncode, r.stdout[-2000:], r.stderr[-4000:])
+    assert "abi_host_check: ok" in r.stdout
