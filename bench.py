@@ -47,14 +47,15 @@ def parse(argv=None):
     ap.add_argument("--tune-cache", default="")
     ap.add_argument("--grid", type=int, default=20, help="k = q = grid^3 for si_dense")
     ap.add_argument("--q-chunk", type=int, default=1024)
-    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--cpu-sample-q", type=int, default=12, help="q points of the oracle sample (about 15 s of host work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-one-thread-q", type=int, default=1,
                     help="q points of the oracle's one-thread sample (0 skips it)")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--no-split", action="store_true", help="skip the FP32 split-phase (hi + lo) measurement")
-    ap.add_argument("--split-steps", type=int, default=1)
+    ap.add_argument("--no-comp", action="store_true",
+                    help="skip the compensated FP32 (K-blocked accumulation) measurement")
+    ap.add_argument("--comp-steps", type=int, default=2)
     ap.add_argument("--q-batch", type=int, default=0)
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="first run a plain device copy of this many GiB (HBM counter calibration)")
@@ -160,10 +161,20 @@ def measured_traffic(kernel_tag: str, workgroups: int):
 
 
 def block_error(g_gpu, ref):
+    """(normwise, max blockwise, max scaled blockwise) errors of the degenerate-
+    block sums of |g|^2; the scaled form divides each block's error by
+    sqrt(S_block * max S) (blocks with S >= 1e-10 max S), the size that an
+    absolute error of g proportional to the largest |g| gives, so that blocks
+    far below the largest are not held to a relative bound no FP32 sum meets."""
     import oracle
     s_gpu = oracle.block_sums(np.abs(g_gpu.astype(np.complex128)) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
     s_ref = oracle.block_sums(np.abs(ref["ghat"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
-    return oracle.compare_block_sums(s_gpu, s_ref)
+    norm, blk = oracle.compare_block_sums(s_gpu, s_ref)
+    a = np.concatenate([x.reshape(-1) for x in s_gpu])
+    b = np.concatenate([x.reshape(-1) for x in s_ref])
+    keep = b >= 1e-10 * b.max()
+    scaled = float(np.max(np.abs(a[keep] - b[keep]) / np.sqrt(b[keep] * b.max())))
+    return norm, blk, scaled
 
 
 def cpu_baseline(w, qs_idx):
@@ -401,15 +412,19 @@ def bench_coarse(args):
 def bench_window(args):
     """Energy-window prescreening on the dense-Si grids (8000 k x 8000 q, Nw 8,
     Nm 6, Ne = Np = 1000, FP32): the window takes the lowest tenth of the
-    lowest band's energies; one step is the k-set's bands, the screen, and
-    Eq. (7) on the active k and q (g stored), against the same pass over the
-    whole grids."""
+    lowest band's energies.  Two forms of one step, each from the k-set's
+    bands to g stored on the kept pairs: (1) pair lists: ephw_window_pairs,
+    then Eq. (7) on the kept pairs only (ephw_interpolate_pairs, q chunks of
+    the pair list); (2) compacted sets: ephw_window_screen, then Eq. (7) on
+    every active k x active q pair with a mask of the kept ones.  Both against
+    the same pass over the whole grids (the headline workload)."""
     import torch
     import synth
     from paper_2603_10295_amd import ephw, model
     w = synth.si_dense(m=args.grid)
     s = w.system
     nk, nq = len(w.k), len(w.q)
+    E = s.nm * s.nw * s.nw
     ctx = ephw.Context(0)
     sysh = ephw.System.from_synth(ctx, s)
     k = torch.from_numpy(w.k).to("cuda:0")
@@ -421,70 +436,103 @@ def bench_window(args):
     e0 = eps[:, 0].cpu().numpy()
     ks.close()
     lo, hi = float(e0.min()) - 1.0, float(np.quantile(e0, 0.1))
+
+    def timed_steps(step):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        ctx.check()
+        return (time.perf_counter() - t0) / args.steps
+
+    # ---- (1) pair lists ----------------------------------------------------
+    ks_f = ephw.KSet(sysh, k, ephw.FP32)
+    start, pk, pkq = ephw.window_pairs(ks_f, kqi, lo, hi)
+    ks_f.close()
+    npairs = int(start[-1])
+    gp = torch.empty((max(npairs, 1), s.nm, s.nw, s.nw), dtype=torch.complex64, device="cuda:0")
+    qc = min(args.q_chunk, nq)
+
+    def step_pairs():
+        ks_p = ephw.KSet(sysh, k, ephw.FP32)
+        st, _, _ = ephw.window_pairs(ks_p, kqi, lo, hi, pk, pkq)
+        for q0 in range(0, nq, qc):
+            q1 = min(nq, q0 + qc)
+            p0 = int(st[q0])
+            ephw.interpolate_pairs(ks_p, q[q0:q1], st[q0:q1 + 1] - p0, pk[p0:], pkq[p0:], q_offset=q0,
+                                   flags=ephw.OUT_G, g_out=gp[p0:])
+        ks_p.close()
+
+    sysh.profile_read()
+    sysh.profile(True)
+    dt_pairs = timed_steps(step_pairs)
+    sysh.profile(False)
+    stages_pairs = {k_: round(v[0] / (args.steps + args.warmup), 3) for k_, v in sysh.profile_read().items()}
+    log(f"pairs: {npairs} kept of {nk * nq}; {dt_pairs * 1e3:.1f} ms per pass; stages {stages_pairs}")
+
+    # ---- (2) compacted sets with a pair mask -------------------------------
     k_out = torch.empty((nk, 3), dtype=torch.float64, device="cuda:0")
     q_out = torch.empty((nq, 3), dtype=torch.float64, device="cuda:0")
     kq_out = torch.empty((nq, nk), dtype=torch.int32, device="cuda:0")
     mask = torch.empty((nq, nk), dtype=torch.uint8, device="cuda:0")
-    qc = min(args.q_chunk, nq)
     out = torch.empty((qc, nk, s.nm, s.nw, s.nw), dtype=torch.complex64, device="cuda:0")
     state = {}
 
-    def step():
-        ks_f = ephw.KSet(sysh, k, ephw.FP32)
-        nks, nqs = ephw.window_screen(ks_f, q, kqi, lo, hi, k_out, q_out, kq_out, mask)
-        ks_f.close()
+    def step_masked():
+        ks_m = ephw.KSet(sysh, k, ephw.FP32)
+        nks, nqs = ephw.window_screen(ks_m, q, kqi, lo, hi, k_out, q_out, kq_out, mask)
+        ks_m.close()
         kq2 = kq_out.reshape(-1)[:nqs * nks].reshape(nqs, nks)
         ks2 = ephw.KSet(sysh, k_out[:nks], ephw.FP32)
         for q0 in range(0, nqs, qc):
             q1 = min(nqs, q0 + qc)
-            g = out.reshape(-1)[:(q1 - q0) * nks * s.nm * s.nw * s.nw].reshape(q1 - q0, nks, s.nm, s.nw, s.nw)
+            g = out.reshape(-1)[:(q1 - q0) * nks * E].reshape(q1 - q0, nks, s.nm, s.nw, s.nw)
             ephw.interpolate(ks2, q_out[q0:q1], kq_index=kq2[q0:q1].contiguous(), q_offset=q0, flags=ephw.OUT_G,
                              g_out=g)
         ks2.close()
-        state.update(nks=nks, nqs=nqs, kq2=kq2)
+        state.update(nks=nks, nqs=nqs)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    ctx.check()
+    dt_masked = timed_steps(step_masked)
     nks, nqs = state["nks"], state["nqs"]
-    msk = mask.reshape(-1)[:nqs * nks].reshape(nqs, nks)
-    kept = int(msk.sum().item())
-    log(f"window [{lo:.3f}, {hi:.3f}]: {nks}/{nk} k, {nqs}/{nq} q, {kept} kept pairs; {dt * 1e3:.1f} ms per pass")
-    # parity on two active q: every active k, kept pairs only, against the oracle
+    kept = int(mask.reshape(-1)[:nqs * nks].sum().item())
+    log(f"compacted sets: {nks}/{nk} k, {nqs}/{nq} q, {nks * nqs} pairs computed, {kept} kept; "
+        f"{dt_masked * 1e3:.1f} ms per pass")
+    del out
+
+    # parity of the pair path on two q against the oracle (kept pairs only)
     import oracle
-    ka = k_out[:nks].cpu().numpy()
-    qa = q_out[:nqs].cpu().numpy()
-    pick = [0, nqs // 2]
-    ks2 = ephw.KSet(sysh, k_out[:nks], ephw.FP32)
-    g = torch.empty((len(pick), nks, s.nm, s.nw, s.nw), dtype=torch.complex64, device="cuda:0")
-    idx = torch.as_tensor(pick, device="cuda:0")
-    ephw.interpolate(ks2, q_out[:nqs][idx].contiguous(), kq_index=state["kq2"][idx].contiguous(), flags=ephw.OUT_G,
-                     g_out=g)
-    ctx.check()
-    ks2.close()
-    ref = oracle.interpolate(s, ka, qa[pick], return_all=True)
-    keep = msk[idx].cpu().numpy().reshape(-1).astype(bool)
-    s_gpu = oracle.block_sums(np.abs(g.cpu().numpy().astype(np.complex128)) ** 2, ref["eps_kq"], ref["eps_k"],
-                              ref["lam"])
-    s_ref = oracle.block_sums(np.abs(ref["ghat"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
-    err = oracle.compare_block_sums([a for a, f in zip(s_gpu, keep) if f], [b for b, f in zip(s_ref, keep) if f])
-    log(f"kept pairs of 2 q vs oracle: normwise {err[0]:.2e}")
-    E = s.nm * s.nw * s.nw
+    pick = [int(np.flatnonzero(np.diff(start) > 0)[0]), nq // 2]
+    pick = [j for j in pick if start[j + 1] > start[j]]
+    sel_q = np.concatenate([np.full(int(start[j + 1] - start[j]), j) for j in pick])
+    sel_p = np.concatenate([np.arange(start[j], start[j + 1]) for j in pick])
+    sel_k = pk[torch.as_tensor(sel_p, device="cuda:0")].cpu().numpy()
+    got = gp[torch.as_tensor(sel_p, device="cuda:0")].cpu().numpy().astype(np.complex128)
+    ref = oracle.interpolate(s, w.k, w.q[pick], return_all=True)
+    qpos = {j: i for i, j in enumerate(pick)}
+    s_gpu, s_ref = [], []
+    for p_, (a, b) in enumerate(zip(sel_q, sel_k)):
+        a = qpos[a]
+        s_gpu += oracle.block_sums(np.abs(got[p_])[None, None] ** 2, ref["eps_kq"][a, b][None, None],
+                                   ref["eps_k"][b][None], ref["lam"][a][None])
+        s_ref += oracle.block_sums(np.abs(ref["ghat"][a, b])[None, None] ** 2, ref["eps_kq"][a, b][None, None],
+                                   ref["eps_k"][b][None], ref["lam"][a][None])
+    err = oracle.compare_block_sums(s_gpu, s_ref)
+    log(f"kept pairs of {len(pick)} q vs oracle: normwise {err[0]:.2e}, max blockwise {err[1]:.2e}")
     line = {
         "metric": "full-grid g(k,q) elems/s covered by the energy-window pass (FP32 MFMA path)",
-        "value": nk * nq * E / dt, "unit": "elems/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32",
-        "data": "synthetic",
+        "value": nk * nq * E / dt_pairs, "unit": "elems/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt_pairs * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
         "config": {"workload": f"si_dense_window_nw8_nm6_ne1000_{nk}kx{nq}q_lowest10pct_band0", "nk": nk, "nq": nq,
-                   "window": [lo, hi]},
-        "active_k": nks, "active_q": nqs, "kept_pairs": kept, "computed_pairs": nks * nqs,
-        "kept_elems_per_s": kept * E / dt,
+                   "window": [lo, hi], "form": "pair lists (ephw_window_pairs + ephw_interpolate_pairs)"},
+        "kept_pairs": npairs, "computed_pairs": npairs, "kept_elems_per_s": npairs * E / dt_pairs,
+        "stages_ms_per_step": stages_pairs,
+        "compacted_sets": {"ms_per_step": dt_masked * 1e3, "active_k": nks, "active_q": nqs,
+                           "computed_pairs": nks * nqs, "kept_pairs": kept},
+        "pairs_vs_compacted_sets_speedup": dt_masked / dt_pairs,
         "err_vs_oracle_kept_pairs": {"normwise": err[0], "max_blockwise": err[1], "sample_q": len(pick)},
     }
     print(json.dumps(line), flush=True)
@@ -693,25 +741,26 @@ def main(argv=None):
             log(f"oracle, 1 thread: {v1:.4e} elems/s in {dt1:.1f}s")
         g32 = p32.sample(qs_idx)
         err32 = block_error(g32, ref)
-        log(f"FP32 vs oracle: normwise {err32[0]:.2e}, max blockwise {err32[1]:.2e}")
+        log(f"FP32 vs oracle: normwise {err32[0]:.2e}, max blockwise {err32[1]:.2e}, scaled {err32[2]:.2e}")
 
-    # ---- FP32 with compensated (hi + lo) phase products ------------------
-    split = None
-    if not args.no_split:
+    # ---- compensated FP32: K-blocked accumulation in the phase GEMMs ------
+    comp = None
+    if not args.no_comp:
         del p32.out
-        ps = Path(ctx, s, ephw.FP32_SPLIT, k, q, kqi, args.q_chunk, args.q_batch)
-        log("FP32 split-phase path: warmup + timed steps")
-        tsp, stsp = timed(ps, args.split_steps, 1 if args.warmup else 0, profile=True)
-        split = {"value": cnt.elems / tsp, "ms_per_step": tsp * 1e3,
-                 "re_gemm_ms_per_step": round(stsp["re_gemm"][0] / args.split_steps, 3),
-                 "note": "the Re and Rp phase GEMMs also multiply the low part of every phase, "
-                         "through BF16 MFMAs (one slab of the low pass per 16-deep FP32 slab)"}
-        log(f"FP32 split: {tsp * 1e3:.1f} ms/step")
+        pc = Path(ctx, s, ephw.FP32_COMP, k, q, kqi, args.q_chunk, args.q_batch)
+        log("compensated FP32 path: warmup + timed steps")
+        tc, stc = timed(pc, args.comp_steps, 1 if args.warmup else 0, profile=True)
+        comp = {"value": cnt.elems / tc, "ms_per_step": tc * 1e3,
+                "re_gemm_ms_per_step": round(stc["re_gemm"][0] / args.comp_steps, 3),
+                "note": "both phase GEMMs accumulate in K blocks of 32 (fresh FP32 MFMA accumulators per "
+                        "block, block sums added in FP32); g stored, band rotations unfused"}
+        log(f"compensated FP32: {tc * 1e3:.1f} ms/step")
         if cpu is not None:
-            e = block_error(ps.sample(qs_idx), ref)
-            split["err_vs_oracle"] = {"normwise": e[0], "max_blockwise": e[1]}
-        del ps.out
-        ps.sys.close()
+            e = block_error(pc.sample(qs_idx), ref)
+            comp["err_vs_oracle"] = {"normwise": e[0], "max_blockwise": e[1], "max_scaled_blockwise": e[2]}
+            log(f"compensated FP32 vs oracle: normwise {e[0]:.2e}, max blockwise {e[1]:.2e}, scaled {e[2]:.2e}")
+        del pc.out
+        pc.sys.close()
 
     # ---- FP64 path on the same values (complex64 g upcast) ----------------
     fp64 = None
@@ -730,7 +779,8 @@ def main(argv=None):
         if cpu is not None:
             g64 = p64.sample(qs_idx)
             err64 = block_error(g64, ref)
-            fp64["err_vs_oracle"] = {"normwise": err64[0], "max_blockwise": err64[1]}
+            fp64["err_vs_oracle"] = {"normwise": err64[0], "max_blockwise": err64[1],
+                                     "max_scaled_blockwise": err64[2]}
         p64.sys.close()
 
     line = {
@@ -761,12 +811,13 @@ def main(argv=None):
                               "frac_of_fp32_peak": gemm_tflops / model.PEAK_FP32_TFLOPS},
         "stages_ms_per_step": {k_: round(v[0] / args.steps, 3) for k_, v in stages.items()},
         "err_vs_oracle": None if err32 is None else {"normwise": err32[0], "max_blockwise": err32[1],
+                                                     "max_scaled_blockwise": err32[2],
                                                      "sample_q": len(qs_idx)},
         "fp64_gpu": fp64,
         "fp32_vs_fp64_speedup": None if fp64 is None else fp64["ms_per_step"] / (t32 * 1e3),
-        "fp32_split": split,
-        "fp32_split_vs_fp64_speedup": None if (fp64 is None or split is None)
-        else fp64["ms_per_step"] / split["ms_per_step"],
+        "fp32_comp": comp,
+        "fp32_comp_vs_fp64_speedup": None if (fp64 is None or comp is None)
+        else fp64["ms_per_step"] / comp["ms_per_step"],
         "algorithmic_flops_per_step": 8.0 * cnt.total,
     }
     print(json.dumps(line), flush=True)

@@ -72,7 +72,12 @@ typedef int32_t ephw_status;
 /* arithmetic of the phase sums and rotations; eigensolves are always FP64 */
 #define EPHW_FP64        0  /* complex128 GEMMs on FP64 MFMA, g stored c128 */
 #define EPHW_FP32        1  /* complex64 GEMMs on FP32 MFMA, g stored c64 */
-#define EPHW_FP32_SPLIT  2  /* FP32 with phases split hi+lo (compensated phase products) */
+#define EPHW_FP32_COMP   2  /* compensated FP32: as EPHW_FP32, but each phase sum
+                               accumulates in K blocks of 32 (fresh FP32 MFMA
+                               accumulators per block, block sums added in FP32),
+                               which cuts the FP32 accumulation error, the
+                               dominant one, about 3x; backward, Eq. (6) and
+                               batches take FP64 or FP32 sets only */
 
 /* storage type of g(Re,Rp) */
 #define EPHW_C128 0
@@ -187,7 +192,7 @@ ephw_status ephw_kset_bands(ephw_kset* ks, double* eps, void* vecs, void* stream
               V(k_{kq_index[j][i]}) of the k-set (k+q on the k grid); otherwise
               H(k+q) is interpolated and diagonalised for every pair.
      q_offset index of q[0] in the caller's full q list (enters the loss weights)
-     prec     EPHW_FP64 / EPHW_FP32 / EPHW_FP32_SPLIT; must match the k-set's
+     prec     EPHW_FP64 / EPHW_FP32 / EPHW_FP32_COMP; must match the k-set's
      flags    EPHW_OUT_* bits
      g_out    [nq][nk][nm][nw][nw] c128 (FP64) or c64 (FP32*), if EPHW_OUT_G;
               with EPHW_OUT_WANNIER the same shape holds the unrotated sums
@@ -239,7 +244,7 @@ ephw_status ephw_interpolate_noalloc(ephw_kset* ks, const double* q, int64_t nq,
      g_bloch  [nq][nk][nm][nw][nw] (device): c128 for an FP64 set, c64 for FP32,
               in the layout ephw_interpolate stores
      g_out    [np][ne][nm][nw][nw] (device), same element type, overwritten
-   EPHW_FP32_SPLIT sets are not supported.  Enqueued on stream. */
+   EPHW_FP32_COMP sets are not supported.  Enqueued on stream. */
 ephw_status ephw_wannier_transform(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index,
                                    const void* g_bloch, void* g_out, void* stream);
 
@@ -269,6 +274,47 @@ ephw_status ephw_window_screen(ephw_kset* ks, const double* q, int64_t nq, const
                                double e_hi, double* k_out, int64_t* nk_out, double* q_out, int64_t* nq_out,
                                int32_t* kq_out, uint8_t* pair_mask, void* stream);
 
+/* The kept pairs of the same energy window as a list (the pre-screening of
+   the Results section's single-node benchmark, taken down to single (k, q)
+   pairs): pair (k, q) is kept when k and k+q (kq_index) both have a band in
+   [e_lo, e_hi].  Outputs, in CSR form by q:
+     pair_start [nq + 1] int64 (HOST): the kept pairs of q_j are
+                p = pair_start[j] .. pair_start[j+1]-1; pair_start[nq] is the total
+     pair_k     [capacity] int32 (device): k index (in the set) of pair p,
+                ascending within each q
+     pair_kq    [capacity] int32 (device): kq_index[j][pair_k[p]], the set
+                index of k+q
+   kq_index [nq][nk] int32 (device): as in ephw_window_screen (entries outside
+   [0, nk) count as dropped and set EPHW_EINDEX in the status word).
+   pair_start is always written; when the total exceeds `capacity` the call
+   returns EPHW_EINVAL without writing pair_k / pair_kq (the caller can size
+   them from pair_start[nq] and call again).  Synchronises the stream. */
+ephw_status ephw_window_pairs(ephw_kset* ks, const int32_t* kq_index, int64_t nq, double e_lo, double e_hi,
+                              int64_t* pair_start, int32_t* pair_k, int32_t* pair_kq, int64_t capacity,
+                              void* stream);
+
+/* Eq. (7) on a list of (k, q) pairs (Nw <= 32; FP64 or FP32 k-sets): for the
+   q list q [nq][3] f64 (device) and the pairs in the CSR form of
+   ephw_window_pairs (pair_start HOST [nq + 1]; pair_k, pair_kq device
+   [pair_start[nq]], k and k+q as indices into the k-set), computes for pair p
+   of q_j the g_{mn nu}(k, q_j) that ephw_interpolate gives at that k and q
+   (with the k+q grid index pair_kq[p]).  Only the kept pairs enter the Re sum
+   and the band rotations; q points without pairs are skipped entirely.
+     flags, loss_seed, q_offset  as in ephw_interpolate; the loss weights use
+              the element index of (q_offset + j, pair_k[p]) in the k-set, so
+              the loss equals that of ephw_interpolate over the same pairs
+     g_out    [npairs][nm][nw][nw] c128 (FP64) or c64 (FP32), if EPHW_OUT_G
+     band_sum [npairs][nm] f64, if EPHW_OUT_BAND_SUM
+     loss     one f64 (L +=), if EPHW_OUT_LOSS
+   pair_start must start at 0 and not decrease (checked on the host); pair
+   indices outside the k-set set EPHW_EINDEX in the status word.  The call
+   copies its pair offsets and per-q GEMM descriptors to the device through
+   pinned host memory the system owns; it does not synchronise the stream. */
+ephw_status ephw_interpolate_pairs(ephw_kset* ks, const double* q, int64_t nq, const int64_t* pair_start,
+                                   const int32_t* pair_k, const int32_t* pair_kq, int64_t q_offset, int32_t prec,
+                                   uint32_t flags, void* g_out, double* band_sum, double* loss, uint64_t loss_seed,
+                                   void* stream);
+
 /* A downstream reduction of stored matrix elements over q (the multi-node
    scalability runs of the Results section compute an electron self-energy
    of MoS2 from the interpolated g; the formula is not printed there): the
@@ -281,7 +327,7 @@ ephw_status ephw_window_screen(ephw_kset* ks, const double* q, int64_t nq, const
    G(x) = exp(-x^2 / (2 sigma^2)) / (sigma sqrt(2 pi)).  The 1/(2 omega) is the
    zero-point amplitude that the mode vectors e/sqrt(M) of Eq. (2) leave out.
    Calls on successive q chunks accumulate; nq_total is the full q count.
-     prec    EPHW_FP64: g c128; EPHW_FP32 / EPHW_FP32_SPLIT: g c64
+     prec    EPHW_FP64: g c128; EPHW_FP32 / EPHW_FP32_COMP: g c64
      g       [nq][nk][nm][nw][nw] (device), as ephw_interpolate stores it
      eps_k [nk][nw], eps_kq [nq][nk][nw], omega [nq][nm]: f64 (device)
      gamma   [nk][nw] f64 (device), accumulated (+=), caller-owned
@@ -322,7 +368,7 @@ ephw_status ephw_interpolate_linewidth(ephw_kset* ks, const double* q, int64_t n
    block of n (bands at k), so every element of a block holds the block's sum.
    A block is a run of the ascending list whose consecutive gaps are at most
    rel_tol * max(1, max |value|) of that list (1e-6 is the usual choice).
-     prec    EPHW_FP64: g c128; EPHW_FP32 or EPHW_FP32_SPLIT: g c64
+     prec    EPHW_FP64: g c128; EPHW_FP32 or EPHW_FP32_COMP: g c64
      g       [nq][nk][nm][nw][nw] (device), as ephw_interpolate stores it
      eps_kq  [nq][nk][nw] f64 (device), ascending: bands at k+q
      eps_k   [nk][nw] f64 (device), ascending: bands at k

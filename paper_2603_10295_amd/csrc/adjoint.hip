@@ -494,9 +494,9 @@ ephw_status interpolate_large(ephw_kset* ks, const double* q, int64_t nq, const 
   unit_shape(s, nq, nk, E, cs, 2, &qb, &kt);
   // q side
   EPHW_TRY(ws_need(s, WS_PQ, (size_t)nq * np * cs));
-  EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, np, wsp(s, WS_PQ), nullptr, st));
+  EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, np, wsp(s, WS_PQ), st));
   EPHW_TRY(ws_need(s, WS_PQC, (size_t)nq * s->nc * 16));
-  EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), nullptr, st));
+  EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), st));
   EPHW_TRY(ws_need(s, WS_LAM, (size_t)nq * nm * 8));
   EPHW_TRY(ws_need(s, WS_E, (size_t)nq * nm * nm * 16));
   EPHW_TRY(ws_need(s, WS_HK, (size_t)nq * nm * nm * 16));
@@ -681,7 +681,7 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
     set_error("ephw_loss_backward: nothing requested");
     return EPHW_EINVAL;
   }
-  if (ks->prec == EPHW_FP32_SPLIT) {
+  if (ks->prec == EPHW_FP32_COMP) {
     set_error("ephw_loss_backward: FP64 or FP32 k-sets only");
     return EPHW_EUNSUPPORTED;
   }
@@ -729,11 +729,11 @@ ephw_status ephw_loss_backward(ephw_kset* ks, const double* q, int64_t nq, const
 
   // ---- q side: phases, D(q) eigensolve, u, du/dq ----
   EPHW_TRY(ws_need(s, WS_PQ, (size_t)nq * np * cs));
-  EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, np, wsp(s, WS_PQ), nullptr, st));
+  EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, np, wsp(s, WS_PQ), st));
   EPHW_TRY(ws_need(s, WS_DPQ, (size_t)3 * nq * np * cs));
   EPHW_TRY(scale_phase(kind, wsp(s, WS_PQ), nq, s->r_p, np, wsp(s, WS_DPQ), st));
   EPHW_TRY(ws_need(s, WS_PQC, (size_t)nq * s->nc * 16));
-  EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), nullptr, st));
+  EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), st));
   EPHW_TRY(ws_need(s, WS_LAM, (size_t)nq * nm * 8));
   EPHW_TRY(ws_need(s, WS_E, (size_t)nq * nm * nm * 16));
   {
@@ -1086,7 +1086,7 @@ ephw_status ephw_wannier_transform(ephw_kset* ks, const double* q, int64_t nq, c
     set_error("ephw_wannier_transform: need a k-set, a q list, a k+q index table and both buffers");
     return EPHW_EINVAL;
   }
-  if (ks->prec == EPHW_FP32_SPLIT) {
+  if (ks->prec == EPHW_FP32_COMP) {
     set_error("ephw_wannier_transform: FP64 or FP32 k-sets only");
     return EPHW_EUNSUPPORTED;
   }
@@ -1105,9 +1105,9 @@ ephw_status ephw_wannier_transform(ephw_kset* ks, const double* q, int64_t nq, c
   // phases as Eq. (6) writes them (no lattice-vector weights); the q ones
   // carry 1/(Ne Np)
   EPHW_TRY(ws_need(s, WS_CPK, (size_t)nk * ne * cs));
-  EPHW_TRY(phase_matrix(kind, ks->k, nk, s->r_e, nullptr, ne, wsp(s, WS_CPK), nullptr, st));
+  EPHW_TRY(phase_matrix(kind, ks->k, nk, s->r_e, nullptr, ne, wsp(s, WS_CPK), st));
   EPHW_TRY(ws_need(s, WS_PQ, (size_t)nq * np * cs));
-  EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, nullptr, np, wsp(s, WS_PQ), nullptr, st));
+  EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, nullptr, np, wsp(s, WS_PQ), st));
   {
     const int64_t n = nq * np;
     const double f = 1.0 / ((double)ne * (double)np);
@@ -1121,7 +1121,7 @@ ephw_status ephw_wannier_transform(ephw_kset* ks, const double* q, int64_t nq, c
   }
   // modes at q': D(q') eigensolve, then (u^-1)^T
   EPHW_TRY(ws_need(s, WS_PQC, (size_t)nq * s->nc * 16));
-  EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), nullptr, st));
+  EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), st));
   EPHW_TRY(ws_need(s, WS_LAM, (size_t)nq * nm * 8));
   EPHW_TRY(ws_need(s, WS_E, (size_t)nq * nm * nm * 16));
   {

@@ -17,14 +17,6 @@ namespace ephw {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-}  // namespace ephw
-
-namespace {
-
-// FP64 interpolation + eigensolve: out_eps [n][dim], out_v c128 [n][dim][dim]
-// from A = phases [n][nr] (c128) and B = R-space matrices [nr][dim*dim] (c128).
-// the same with caller-given buffers: hk [n][dim][dim] c128 and, for dim > 32,
-// jwork of jacobi_work_doubles(dim, n) doubles
 ephw_status interp_eigh_ws(ephw_system* s, const double* phase, int64_t n, int64_t nr, const double* mats, int dim,
                            double* out_eps, double* out_v, double* hk, double* jwork, bool stages, hipStream_t st) {
   const int64_t d2 = (int64_t)dim * dim;
@@ -42,6 +34,10 @@ ephw_status interp_eigh_ws(ephw_system* s, const double* phase, int64_t n, int64
   EPHW_TRY(cgemm(0, p, st));
   return jacobi_eigh(hk, n, dim, out_eps, out_v, jwork, s->ctx->status, st);
 }
+
+}  // namespace ephw
+
+namespace {
 
 ephw_status interp_eigh(ephw_system* s, const double* phase, int64_t n, int64_t nr, const double* mats,
                         int dim, double* out_eps, double* out_v, hipStream_t st) {
@@ -183,6 +179,8 @@ ephw_status ephw_system_free(ephw_system* s) {
     (void)hipEventDestroy(r.b);
   }
   for (hipEvent_t e : s->prof.pool) (void)hipEventDestroy(e);
+  if (s->stage_host) (void)hipHostFree(s->stage_host);
+  if (s->staged) (void)hipEventDestroy(s->staged);
   delete s;
   return EPHW_OK;
 }
@@ -360,7 +358,7 @@ ephw_status ephw_bands(ephw_system* s, const double* k, int64_t nk, double* eps,
   EPHW_TRY(ws_need(s, WS_PH, (size_t)nk * s->nh * 16));
   {
     Stage sg_(s, EPHW_STAGE_PHASE, st);
-    EPHW_TRY(phase_matrix(0, k, nk, s->r_h, s->w_h, s->nh, wsp(s, WS_PH), nullptr, st));
+    EPHW_TRY(phase_matrix(0, k, nk, s->r_h, s->w_h, s->nh, wsp(s, WS_PH), st));
   }
   double* e_out = eps;
   double* v_out = static_cast<double*>(vecs);
@@ -388,7 +386,7 @@ ephw_status ephw_phonons(ephw_system* s, const double* q, int64_t nq, double* la
   EPHW_TRY(ws_need(s, WS_PQC, (size_t)nq * s->nc * 16));
   {
     Stage sg_(s, EPHW_STAGE_PHASE, st);
-    EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), nullptr, st));
+    EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, wsp(s, WS_PQC), st));
   }
   double* l_out = lam;
   if (!l_out) {
@@ -415,7 +413,7 @@ ephw_status ephw_phase_sum_rp(ephw_system* s, const double* q, int64_t nq, int32
     set_error("ephw_phase_sum_rp: invalid argument");
     return EPHW_EINVAL;
   }
-  if (prec != EPHW_FP64 && prec != EPHW_FP32 && prec != EPHW_FP32_SPLIT) {
+  if (prec != EPHW_FP64 && prec != EPHW_FP32 && prec != EPHW_FP32_COMP) {
     set_error("ephw_phase_sum_rp: unknown precision");
     return EPHW_EINVAL;
   }
@@ -426,20 +424,17 @@ ephw_status ephw_phase_sum_rp(ephw_system* s, const double* q, int64_t nq, int32
   }
   if (nq == 0) return EPHW_OK;
   hipStream_t st = as_stream(stream);
-  const bool split = prec == EPHW_FP32_SPLIT;
   EPHW_TRY(ws_need(s, WS_PQ, (size_t)nq * s->np * csize(kind)));
-  if (split) EPHW_TRY(ws_need(s, WS_PQ_LO, (size_t)nq * s->np * 8));
   {
     Stage sg_(s, EPHW_STAGE_PHASE, st);
-    EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, s->np, wsp(s, WS_PQ),
-                          split ? wsp(s, WS_PQ_LO) : nullptr, st));
+    EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, s->np, wsp(s, WS_PQ), st));
   }
   GemmParams p;
   p.M = nq;
   p.N = s->ne * s->nm * s->nw * s->nw;
   p.K = s->np;
   p.A = wsp(s, WS_PQ);
-  p.A_lo = split ? wsp(s, WS_PQ_LO) : nullptr;
+  p.compensated = prec == EPHW_FP32_COMP;
   p.lda = s->np;
   p.B = s->g;
   p.ldb = p.N;
@@ -454,7 +449,7 @@ ephw_status ephw_phase_sum_rp(ephw_system* s, const double* q, int64_t nq, int32
 ephw_status ephw_kset_free(ephw_kset* ks) {
   if (!ks) return EPHW_OK;
   (void)hipDeviceSynchronize();
-  void* ptrs[] = {ks->k, ks->pk, ks->pk_lo, ks->pkh, ks->eps, ks->v64, ks->vt, ks->dv64, ks->dpk,
+  void* ptrs[] = {ks->k, ks->pk, ks->pkh, ks->eps, ks->v64, ks->vt, ks->dv64, ks->dpk,
                   ks->dv != ks->dv64 ? ks->dv : nullptr};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -469,7 +464,7 @@ ephw_status ephw_kset_create(ephw_system* s, const double* k, int64_t nk, int32_
     set_error("ephw_kset_create: invalid argument (need a system, a k list and nk >= 1)");
     return EPHW_EINVAL;
   }
-  if (prec != EPHW_FP64 && prec != EPHW_FP32 && prec != EPHW_FP32_SPLIT) {
+  if (prec != EPHW_FP64 && prec != EPHW_FP32 && prec != EPHW_FP32_COMP) {
     set_error("ephw_kset_create: unknown precision");
     return EPHW_EINVAL;
   }
@@ -502,20 +497,18 @@ ephw_status ephw_kset_create(ephw_system* s, const double* k, int64_t nk, int32_
     return fail(EPHW_EDEVICE);
   }
   if ((e = alloc(&ks->pk, (size_t)nk * s->ne * csize(kind))) != EPHW_OK) return fail(e);
-  if (prec == EPHW_FP32_SPLIT && (e = alloc(&ks->pk_lo, (size_t)nk * s->ne * 8)) != EPHW_OK)
-    return fail(e);
   if ((e = alloc((void**)&ks->pkh, (size_t)nk * s->nh * 16)) != EPHW_OK) return fail(e);
   if ((e = alloc((void**)&ks->eps, (size_t)nk * s->nw * 8)) != EPHW_OK) return fail(e);
   if ((e = alloc((void**)&ks->v64, (size_t)nk * nw2 * 16)) != EPHW_OK) return fail(e);
   if ((e = alloc(&ks->vt, (size_t)nk * nw2 * csize(kind))) != EPHW_OK) return fail(e);
   {
     Stage sg_(s, EPHW_STAGE_PHASE, st);
-    if ((e = phase_matrix(kind, ks->k, nk, s->r_e, s->w_e, s->ne, ks->pk, ks->pk_lo, st)) != EPHW_OK)
+    if ((e = phase_matrix(kind, ks->k, nk, s->r_e, s->w_e, s->ne, ks->pk, st)) != EPHW_OK)
       return fail(e);
   }
   {
     Stage sg_(s, EPHW_STAGE_PHASE, st);
-    if ((e = phase_matrix(0, ks->k, nk, s->r_h, s->w_h, s->nh, ks->pkh, nullptr, st)) != EPHW_OK)
+    if ((e = phase_matrix(0, ks->k, nk, s->r_h, s->w_h, s->nh, ks->pkh, st)) != EPHW_OK)
       return fail(e);
   }
   if ((e = interp_eigh(s, ks->pkh, nk, s->nh, s->h_r, s->nw, ks->eps, ks->v64, st)) != EPHW_OK)
@@ -558,7 +551,7 @@ namespace {
 // block (the system's workspace, or the static scratch of the entry point
 // that allocates nothing) in 256-byte aligned pieces.
 struct InterpWs {
-  void *pq = nullptr, *pq_lo = nullptr, *u = nullptr, *g = nullptr, *gnu = nullptr, *w = nullptr, *vkq = nullptr;
+  void *pq = nullptr, *u = nullptr, *g = nullptr, *gnu = nullptr, *w = nullptr, *vkq = nullptr;
   double *lam = nullptr, *e = nullptr, *pqc = nullptr, *hk = nullptr, *jwork = nullptr, *pqh = nullptr;
   double *bq = nullptr, *hkq = nullptr, *ekq = nullptr, *vkq64 = nullptr, *loss = nullptr;
   void* gchunk = nullptr;                          // rotated g of a batch for the linewidth (unfused)
@@ -603,7 +596,6 @@ InterpWs interp_layout(const ephw_system* s, const InterpReq& r, char* base) {
   const size_t cs = csize(kind);
   const int64_t nw = s->nw, nm = s->nm, nw2 = nw * nw, E = nm * nw2, nk = r.nk, nq = r.nq, qb = r.qb;
   w.pq = take((size_t)nq * s->np * cs);
-  if (r.prec == EPHW_FP32_SPLIT) w.pq_lo = take((size_t)nq * s->np * 8);
   w.lam = takd((size_t)nq * nm * 8);
   w.e = takd((size_t)nq * nm * nm * 16);
   w.pqc = takd((size_t)nq * s->nc * 16);
@@ -689,7 +681,7 @@ ephw_status interpolate_small(ephw_kset* ks, const double* q, const int32_t* kq_
                               double* eps_kq, double* omega, const InterpWs& w, bool stages, hipStream_t st) {
   ephw_system* s = ks->sys;
   const int kind = prec_kind(r.prec);
-  const bool split = r.prec == EPHW_FP32_SPLIT;
+  const bool comp = r.prec == EPHW_FP32_COMP;
   const uint32_t flags = r.flags;
   const bool wannier = (flags & EPHW_OUT_WANNIER) != 0;
   const int nw = s->nw, nm = s->nm;
@@ -700,11 +692,11 @@ ephw_status interpolate_small(ephw_kset* ks, const double* q, const int32_t* kq_
   // --- per-call q side: Rp phases, D(q) eigensolve, mode vectors ----------
   {
     Stage sg_(s, EPHW_STAGE_PHASE, st, stages);
-    EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, s->np, w.pq, split ? w.pq_lo : nullptr, st));
+    EPHW_TRY(phase_matrix(kind, q, nq, s->r_p, s->w_p, s->np, w.pq, st));
   }
   {
     Stage sg_(s, EPHW_STAGE_PHASE, st, stages);
-    EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, w.pqc, nullptr, st));
+    EPHW_TRY(phase_matrix(0, q, nq, s->r_c, s->w_c, s->nc, w.pqc, st));
   }
   EPHW_TRY(interp_eigh_ws(s, w.pqc, nq, s->nc, s->c_scaled, nm, w.lam, w.e, w.hk, w.jwork, stages, st));
   {
@@ -718,7 +710,7 @@ ephw_status interpolate_small(ephw_kset* ks, const double* q, const int32_t* kq_
   }
   if (r.need_kq_eig) {
     Stage sg_(s, EPHW_STAGE_PHASE, st, stages);
-    EPHW_TRY(phase_matrix(0, q, nq, s->r_h, nullptr, s->nh, w.pqh, nullptr, st));
+    EPHW_TRY(phase_matrix(0, q, nq, s->r_h, nullptr, s->nh, w.pqh, st));
   }
 
   for (int64_t q0 = 0; q0 < nq; q0 += qb) {
@@ -761,7 +753,7 @@ ephw_status interpolate_small(ephw_kset* ks, const double* q, const int32_t* kq_
     rp.N = s->ne * E;
     rp.K = s->np;
     rp.A = static_cast<const char*>(w.pq) + (size_t)q0 * s->np * cs;
-    rp.A_lo = split ? static_cast<const char*>(w.pq_lo) + (size_t)q0 * s->np * 8 : nullptr;
+    rp.compensated = comp;
     rp.lda = s->np;
     rp.B = s->g;
     rp.ldb = rp.N;
@@ -783,7 +775,7 @@ ephw_status interpolate_small(ephw_kset* ks, const double* q, const int32_t* kq_
     re.N = (int64_t)nb * E;
     re.K = s->ne;
     re.A = ks->pk;
-    re.A_lo = split ? ks->pk_lo : nullptr;
+    re.compensated = comp;
     re.lda = s->ne;
     re.B = w.gnu;
     re.ldb = re.N;
@@ -989,7 +981,7 @@ ephw_status ephw_interpolate_noalloc(ephw_kset* ks, const double* q, int64_t nq,
 ephw_status ephw_degenerate_sums(int32_t prec, const void* g, int64_t nq, int64_t nk, int32_t nm, int32_t nw,
                                  const double* eps_kq, const double* eps_k, const double* lam, double rel_tol,
                                  double* out, void* stream) {
-  if (prec != EPHW_FP64 && prec != EPHW_FP32 && prec != EPHW_FP32_SPLIT) {
+  if (prec != EPHW_FP64 && prec != EPHW_FP32 && prec != EPHW_FP32_COMP) {
     set_error("ephw_degenerate_sums: unknown precision");
     return EPHW_EINVAL;
   }
@@ -1011,7 +1003,7 @@ ephw_status ephw_linewidth(int32_t prec, const void* g, int64_t nq, int64_t nk, 
                            const double* eps_k, const double* eps_kq, const double* omega, double temperature,
                            double mu, double sigma, double omega_min, int64_t nq_total, double* gamma,
                            void* stream) {
-  if (prec != EPHW_FP64 && prec != EPHW_FP32 && prec != EPHW_FP32_SPLIT) {
+  if (prec != EPHW_FP64 && prec != EPHW_FP32 && prec != EPHW_FP32_COMP) {
     set_error("ephw_linewidth: unknown precision");
     return EPHW_EINVAL;
   }

@@ -261,8 +261,7 @@ ephw_status tune_item(ItemPlan& it, int kind, int64_t cap, bool measure, hipStre
     set_shape(it, q, k_tile_for(it, q, cap));
     carve(it, static_cast<char*>(tmp));
     // phases and mode vectors of the first q batch (values only matter for timing)
-    rc = phase_matrix(kind, it.in.q, std::min<int64_t>(q, it.nq), it.sys->r_p, it.sys->w_p, it.np, it.pq,
-                      nullptr, st);
+    rc = phase_matrix(kind, it.in.q, std::min<int64_t>(q, it.nq), it.sys->r_p, it.sys->w_p, it.np, it.pq, st);
     if (rc == EPHW_OK) rc = hipMemsetAsync(it.u, 0, (size_t)q * it.nm * it.nm * csize(kind), st) == hipSuccess
                                 ? EPHW_OK : EPHW_EDEVICE;
     for (int rep = 0; rep < 2 && rc == EPHW_OK; ++rep) {
@@ -318,8 +317,8 @@ ephw_status issue(ephw_batch* bt, hipStream_t st) {
     switch (l.kind) {
       case Launch::PHASE: {
         ItemPlan& it = bt->items[l.item];
-        EPHW_TRY(phase_matrix(bt->kind, it.in.q, it.nq, it.sys->r_p, it.sys->w_p, it.np, it.pq, nullptr, st));
-        EPHW_TRY(phase_matrix(0, it.in.q, it.nq, it.sys->r_c, it.sys->w_c, it.nc, it.pqc, nullptr, st));
+        EPHW_TRY(phase_matrix(bt->kind, it.in.q, it.nq, it.sys->r_p, it.sys->w_p, it.np, it.pq, st));
+        EPHW_TRY(phase_matrix(0, it.in.q, it.nq, it.sys->r_c, it.sys->w_c, it.nc, it.pqc, st));
         break;
       }
       case Launch::MODEVEC: {
@@ -628,7 +627,7 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
     it.sys = in.ks->sys;
     const int kind = prec_kind(in.ks->prec);
     if (i == 0) bt->kind = kind;
-    if (kind != bt->kind || in.ks->prec == EPHW_FP32_SPLIT) {
+    if (kind != bt->kind || in.ks->prec == EPHW_FP32_COMP) {
       set_error("ephw_batch_create: all items must share one precision (FP64 or FP32)");
       return fail(EPHW_EINVAL);
     }

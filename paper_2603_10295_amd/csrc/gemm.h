@@ -71,7 +71,6 @@ struct GemmParams {
   const void* A = nullptr;
   int64_t lda = 0, strideA = 0;
   const int64_t* offA = nullptr;
-  const void* A_lo = nullptr;  // FP32 only: low part of a split A (same layout)
   const void* B = nullptr;
   int64_t ldb = 0, strideB = 0;
   const int64_t* offB = nullptr;
@@ -80,6 +79,9 @@ struct GemmParams {
   const int64_t* offC = nullptr;
   bool transA = false, conjA = false, transB = false, conjB = false;
   bool accumulate = false;
+  // FP32 only: K-blocked accumulation (fresh accumulators every 32 k, block
+  // sums added in FP32), the compensated form of EPHW_FP32_COMP
+  bool compensated = false;
   int64_t n1 = 1, n2 = 1;
   int64_t strideA1 = 0, strideA2 = 0, strideB1 = 0, strideB2 = 0, strideC1 = 0, strideC2 = 0;
   // tblock > 0: C is stored in blocks of tblock rows, each block transposed:

@@ -48,21 +48,6 @@ struct Mfma<double> {
   static __device__ __forceinline__ int row(int g, int v) { return g + 4 * v; }
 };
 
-// BF16 helpers for the low pass of split phases: truncation to the upper 16
-// bits (a relative error of 2^-8 on a term 2^-24 of the result)
-typedef short Bf4 __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void put_bf16(uint32_t& w, int half, float x) {
-  const uint32_t b = __float_as_uint(x);
-  w = half ? ((w & 0x0000ffffu) | (b & 0xffff0000u)) : (b >> 16);
-}
-__device__ __forceinline__ Bf4 pack4(const uint32_t (&w)[2]) {
-  return __builtin_bit_cast(Bf4, (uint64_t)w[0] | ((uint64_t)w[1] << 32));
-}
-__device__ __forceinline__ Bf4 pack4_neg(const uint32_t (&w)[2]) {
-  const uint64_t v = ((uint64_t)w[0] | ((uint64_t)w[1] << 32)) ^ 0x8000800080008000ull;
-  return __builtin_bit_cast(Bf4, v);
-}
-
 constexpr int kGroupM = 8;
 constexpr int kXcds = 8;
 static_assert(kGroupQueues == kXcds, "one grouped-GEMM work queue per XCD");
@@ -79,7 +64,6 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t id, int64_t n) {
 template <typename T>
 struct TileJob {
   const T* A;
-  const T* Alo;
   const T* B;
   T* C;
   int64_t M, N, K, lda, ldb, ldc;
@@ -134,17 +118,13 @@ __device__ __forceinline__ typename Chunk<T>::v4 load_chunk(__amdgpu_buffer_rsrc
   return __builtin_bit_cast(typename Chunk<T>::v4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
-// SPLIT: 0 no low part; 1 the low part of A through FP32 MFMAs; 2 through
-// BF16 MFMAs (its products are 2^-24 of the high part's, so BF16 operands
-// lose nothing that shows in the FP32 accumulator)
-template <typename T, int BM, int BN, int BK, int WM, int WN, int SPLIT>
+template <typename T, int BM, int BN, int BK, int WM, int WN>
 struct TileShape {
   static constexpr int NT = 64 * WM * WN;
   static constexpr int PADC = (sizeof(T) == 4) ? 2 : 1;  // complex values of padding per LDS row
   static constexpr int LA = BM + PADC, LB = BN + PADC;
-  static constexpr int NA = SPLIT ? 2 : 1;                // A planes: value (+ low part)
-  // one pipeline stage: NA A slabs [BK][LA] and one B slab [BK][LB], complex T
-  static constexpr size_t stage_elems = (size_t)2 * BK * (NA * LA + LB);
+  // one pipeline stage: an A slab [BK][LA] and a B slab [BK][LB], complex T
+  static constexpr size_t stage_elems = (size_t)2 * BK * (LA + LB);
   static constexpr size_t smem_elems = 2 * stage_elems;   // two stages
 };
 
@@ -683,10 +663,12 @@ __device__ __forceinline__ void band_epilogue_mfma8(const TileJob<float>& j, con
 // written to the other stage, so each slab costs one barrier.  LDS keeps
 // complex values interleaved, laid out [k][m] and [k][n], so one 8- or
 // 16-byte read gives a lane its (re, im) operand pair.
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int SPLIT, int BANDNW = 0>
+// KBLK > 0: K-blocked accumulation, a fresh accumulator every KBLK slabs
+// (the compensated FP32 form, see the K loop)
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int KBLK, int BANDNW = 0>
 __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64_t n0, T* smem,
                                           const BandEpilogue* band = nullptr) {
-  using S = TileShape<T, BM, BN, BK, WM, WN, SPLIT>;
+  using S = TileShape<T, BM, BN, BK, WM, WN>;
   using C = Chunk<T>;
   using V4 = typename C::v4;
   using V2 = typename C::v2;
@@ -741,7 +723,7 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
   const int64_t a_ext = TA ? (K - 1) * j.lda + M : (M - 1) * j.lda + K;   // complex values from A
   const int64_t b_ext = TB ? (N - 1) * j.ldb + K : (K - 1) * j.ldb + N;
 
-  V4 ra[AC], rb[BC], rl[SPLIT ? AC : 1];
+  V4 ra[AC], rb[BC];
 
   auto load = [&](int64_t k0) {
     const int64_t ao = TA ? k0 * j.lda + m0 : m0 * j.lda + k0;
@@ -751,13 +733,11 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
       if (A_GRP) {  // one resource per row group
         const int64_t o = ao + (int64_t)i * A_RSTEP * j.lda + a_row0;
         ra[i] = load_chunk<T>(make_rsrc(j.A + 2 * o, (a_ext - o) * CS), a_off0);
-        if (SPLIT) rl[i] = load_chunk<T>(make_rsrc(j.Alo + 2 * o, (a_ext - o) * CS), a_off0);
       } else {
         int r, ch;
         a_pos(i, r, ch);
         const uint32_t off = (uint32_t)(((int64_t)r * j.lda + ch * CPC) * CS);
         ra[i] = load_chunk<T>(make_rsrc(j.A + 2 * ao, (a_ext - ao) * CS), off);
-        if (SPLIT) rl[i] = load_chunk<T>(make_rsrc(j.Alo + 2 * ao, (a_ext - ao) * CS), off);
       }
     }
 #pragma unroll
@@ -784,10 +764,6 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
           if (ch * CPC + e >= klim) {
             ra[i][2 * e] = T(0);
             ra[i][2 * e + 1] = T(0);
-            if (SPLIT) {
-              rl[i][2 * e] = T(0);
-              rl[i][2 * e + 1] = T(0);
-            }
           }
       }
     }
@@ -809,24 +785,20 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
   // registers -> LDS stage; conjugation is applied here
   auto stash = [&](T* st) {
     T* As = st;
-    T* Bs = st + 2 * BK * LA * S::NA;
+    T* Bs = st + 2 * BK * LA;
 #pragma unroll
-    for (int p = 0; p < S::NA; ++p) {
-      T* Ap = As + p * 2 * BK * LA;
+    for (int i = 0; i < AC; ++i) {
+      V4 v = ra[i];
 #pragma unroll
-      for (int i = 0; i < AC; ++i) {
-        V4 v = (p == 0) ? ra[i] : rl[SPLIT ? i : 0];
+      for (int e = 0; e < CPC; ++e) v[2 * e + 1] *= j.sa;
+      int r, ch;
+      a_pos(i, r, ch);
+      if (TA) {  // slab row r is k; the chunk holds CPC consecutive m
+        *reinterpret_cast<V4*>(As + 2 * (r * LA + ch * CPC)) = v;
+      } else {   // slab row r is m; the chunk holds CPC consecutive k
 #pragma unroll
-        for (int e = 0; e < CPC; ++e) v[2 * e + 1] *= j.sa;
-        int r, ch;
-        a_pos(i, r, ch);
-        if (TA) {  // slab row r is k; the chunk holds CPC consecutive m
-          *reinterpret_cast<V4*>(Ap + 2 * (r * LA + ch * CPC)) = v;
-        } else {   // slab row r is m; the chunk holds CPC consecutive k
-#pragma unroll
-          for (int e = 0; e < CPC; ++e)
-            *reinterpret_cast<V2*>(Ap + 2 * ((ch * CPC + e) * LA + r)) = V2{v[2 * e], v[2 * e + 1]};
-        }
+        for (int e = 0; e < CPC; ++e)
+          *reinterpret_cast<V2*>(As + 2 * ((ch * CPC + e) * LA + r)) = V2{v[2 * e], v[2 * e + 1]};
       }
     }
 #pragma unroll
@@ -855,18 +827,12 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
       acc_i[i][jj] = Acc{0, 0, 0, 0};
     }
 
-  // BF16 packs of the low pass (SPLIT == 2): two 32-bit words hold the four
-  // k steps of a slab
-  uint32_t lo_r[SPLIT == 2 ? FM : 1][2], lo_i[SPLIT == 2 ? FM : 1][2];
-  uint32_t bh_r[SPLIT == 2 ? FN : 1][2], bh_i[SPLIT == 2 ? FN : 1][2];
-  static_assert(SPLIT != 2 || (sizeof(T) == 4 && BK == 16), "the BF16 low pass packs one 16-deep FP32 slab");
-
   // One BK slab of MFMAs from an LDS stage.  The four real products of every
   // block are issued product by product across all blocks, so consecutive
   // MFMAs never depend on each other.
   auto compute = [&](const T* st) {
     const T* As = st;
-    const T* Bs = st + 2 * BK * LA * S::NA;
+    const T* Bs = st + 2 * BK * LA;
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       const int kr = kk + lrow;
@@ -896,60 +862,35 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
       for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int jj = 0; jj < FN; ++jj) acc_i[i][jj] = Mfma<T>::op(a[i][1], b[jj][0], acc_i[i][jj]);
-      if constexpr (SPLIT == 1) {
-        const T* Al = As + 2 * BK * LA;
-#pragma unroll
-        for (int i = 0; i < FM; ++i) {
-          a[i] = *reinterpret_cast<const V2*>(Al + 2 * (kr * LA + wm * TM + i * 16 + lcol));
-          nai[i] = -a[i][1];
-        }
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int jj = 0; jj < FN; ++jj) {
-            acc_r[i][jj] = Mfma<T>::op(a[i][0], b[jj][0], acc_r[i][jj]);
-            acc_i[i][jj] = Mfma<T>::op(a[i][0], b[jj][1], acc_i[i][jj]);
-          }
-#pragma unroll
-        for (int i = 0; i < FM; ++i)
-#pragma unroll
-          for (int jj = 0; jj < FN; ++jj) {
-            acc_r[i][jj] = Mfma<T>::op(nai[i], b[jj][1], acc_r[i][jj]);
-            acc_i[i][jj] = Mfma<T>::op(a[i][1], b[jj][0], acc_i[i][jj]);
-          }
-      }
-      if constexpr (SPLIT == 2) {
-        // k step s = kk / 4 fills BF16 slot s of the packs (both operands use
-        // k = 4 s + lane group, so the BF16 MFMA sums the same products)
-        const T* Al = As + 2 * BK * LA;
-        const int s = kk / 4;
-#pragma unroll
-        for (int i = 0; i < FM; ++i) {
-          const V2 al = *reinterpret_cast<const V2*>(Al + 2 * (kr * LA + wm * TM + i * 16 + lcol));
-          put_bf16(lo_r[i][s >> 1], s & 1, al[0]);
-          put_bf16(lo_i[i][s >> 1], s & 1, al[1]);
-        }
-#pragma unroll
-        for (int jj = 0; jj < FN; ++jj) {
-          put_bf16(bh_r[jj][s >> 1], s & 1, b[jj][0]);
-          put_bf16(bh_i[jj][s >> 1], s & 1, b[jj][1]);
-        }
-        if (kk + 4 == BK) {
-#pragma unroll
-          for (int i = 0; i < FM; ++i) {
-            const Bf4 ar = pack4(lo_r[i]), ai = pack4(lo_i[i]), nai4 = pack4_neg(lo_i[i]);
-#pragma unroll
-            for (int jj = 0; jj < FN; ++jj) {
-              const Bf4 br = pack4(bh_r[jj]), bi = pack4(bh_i[jj]);
-              acc_r[i][jj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, br, acc_r[i][jj], 0, 0, 0);
-              acc_i[i][jj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ar, bi, acc_i[i][jj], 0, 0, 0);
-              acc_r[i][jj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(nai4, bi, acc_r[i][jj], 0, 0, 0);
-              acc_i[i][jj] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ai, br, acc_i[i][jj], 0, 0, 0);
-            }
-          }
-        }
-      }
     }
+  };
+
+  // K-blocked accumulation (the compensated FP32 form): the MFMA
+  // accumulators start from zero every KBLK slabs and each block's partial
+  // sum is added into a second set of registers.  One accumulator summing
+  // all K products in order picks up a rounding error that grows with the
+  // size of the running sum; over K = 1000 that is the dominant error of the
+  // FP32 phase sums, well above the rounding of the phases themselves.
+  Acc sum_r[KBLK ? FM : 1][KBLK ? FN : 1], sum_i[KBLK ? FM : 1][KBLK ? FN : 1];
+  if constexpr (KBLK > 0) {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int jj = 0; jj < FN; ++jj) {
+        sum_r[i][jj] = Acc{0, 0, 0, 0};
+        sum_i[i][jj] = Acc{0, 0, 0, 0};
+      }
+  }
+  auto fold = [&]() {
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int jj = 0; jj < FN; ++jj) {
+        sum_r[i][jj] += acc_r[i][jj];
+        sum_i[i][jj] += acc_i[i][jj];
+        acc_r[i][jj] = Acc{0, 0, 0, 0};
+        acc_i[i][jj] = Acc{0, 0, 0, 0};
+      }
   };
 
   // K loop: one barrier per slab (see the pipeline note above)
@@ -961,12 +902,27 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
     const bool more = sl + 1 < nslab;
     if (more) load((sl + 1) * BK);
     compute(smem + (sl & 1) * S::stage_elems);
+    if constexpr (KBLK > 0) {
+      if ((sl + 1) % KBLK == 0) fold();
+    }
     if (more) stash(smem + ((sl + 1) & 1) * S::stage_elems);
     __syncthreads();
   }
+  if constexpr (KBLK > 0) {
+    // the last (partial) block, then the blocked sum back into the accumulators
+    // the epilogues read
+    if (nslab % KBLK != 0) fold();
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int jj = 0; jj < FN; ++jj) {
+        acc_r[i][jj] = sum_r[i][jj];
+        acc_i[i][jj] = sum_i[i][jj];
+      }
+  }
 
   if constexpr (BANDNW > 0) {
-    static_assert(sizeof(T) == 4 && BM == 128 && BN == 128 && WM == 2 && WN == 2 && SPLIT == 0,
+    static_assert(sizeof(T) == 4 && BM == 128 && BN == 128 && WM == 2 && WN == 2 && KBLK == 0,
                   "the band epilogue runs on the FP32 128x128 tile");
     // BANDNW: 4 or 8 the rotations on VALU; 16 the Nw = 8 rotations on MFMA
     if constexpr (BANDNW == 16)
@@ -1071,7 +1027,6 @@ __device__ __forceinline__ TileJob<T> job_of(const GemmParams& p, int64_t b) {
   const int64_t oc = p.offC ? p.offC[b] : i0 * p.strideC + i1 * p.strideC1 + i2 * p.strideC2;
   TileJob<T> j;
   j.A = static_cast<const T*>(p.A) + 2 * oa;
-  j.Alo = p.A_lo ? static_cast<const T*>(p.A_lo) + 2 * oa : nullptr;
   j.B = static_cast<const T*>(p.B) + 2 * ob;
   j.C = static_cast<T*>(p.C) + 2 * oc;
   j.M = p.M;
@@ -1092,10 +1047,10 @@ __device__ __forceinline__ TileJob<T> job_of(const GemmParams& p, int64_t b) {
 }
 
 // OCC: waves per SIMD the register allocation must leave room for
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int SPLIT, int OCC, int BANDNW = 0>
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int KBLK, int OCC, int BANDNW = 0>
 __global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(OCC)))
     cgemm_kernel(GemmParams p, int64_t tiles_m, int64_t tiles_n) {
-  using S = TileShape<T, BM, BN, BK, WM, WN, SPLIT>;
+  using S = TileShape<T, BM, BN, BK, WM, WN>;
   __shared__ T smem[S::smem_elems];
   const int64_t logical = xcd_remap(blockIdx.x, tiles_m * tiles_n);
   int64_t tm, tn;
@@ -1103,7 +1058,7 @@ __global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_
   TileJob<T> j = job_of<T>(p, p.batch_base + blockIdx.y);
   j.tile = tm * tiles_n + tn;
   j.ntiles = tiles_m * tiles_n;
-  gemm_tile<T, BM, BN, BK, WM, WN, TA, TB, SPLIT, BANDNW>(j, tm * BM, tn * BN, smem, &p.band);
+  gemm_tile<T, BM, BN, BK, WM, WN, TA, TB, KBLK, BANDNW>(j, tm * BM, tn * BN, smem, &p.band);
 }
 
 // Tile shapes of the grouped kernel: cfg 0 is the default tile of the plain
@@ -1146,7 +1101,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     cgemm_grouped_kernel(const GroupProblem* __restrict__ probs, int n, int64_t total, int* __restrict__ queue) {
   using G = GroupCfg<T>;
   constexpr int BM = CFG == 0 ? G::LM : G::SM, BN = CFG == 0 ? G::LN : G::SN, BK = CFG == 0 ? G::LK : G::SK;
-  using Sh = TileShape<T, BM, BN, BK, 2, 2, 0>;
+  using Sh = TileShape<T, BM, BN, BK, 2, 2>;
   __shared__ T smem[Sh::smem_elems];
   __shared__ int64_t s_next;
   int q = blockIdx.x % kXcds, tried = 0;   // used by thread 0 only
@@ -1176,7 +1131,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     tile_coords(t - P.tile_base, P.tiles_m, P.tiles_n, &tm, &tn);
     TileJob<T> j;
     j.A = static_cast<const T*>(P.A);
-    j.Alo = nullptr;
     j.B = static_cast<const T*>(P.B);
     j.C = static_cast<T*>(P.C);
     j.M = P.M;
@@ -1230,7 +1184,7 @@ bool lane_offsets_fit(int64_t lda, int64_t ldb) {
   return lda >= 0 && ldb >= 0 && (a_rows * lda + BM + BK) * cs < lim && (b_rows * ldb + BN + BK) * cs < lim;
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int SPLIT, int OCC, int BANDNW = 0>
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int KBLK, int OCC, int BANDNW = 0>
 ephw_status launch(const GemmParams& p0, hipStream_t stream) {
   const int64_t tiles_m = ceil_div(p0.M, BM), tiles_n = ceil_div(p0.N, BN);
   const int64_t ntiles = tiles_m * tiles_n;
@@ -1246,7 +1200,7 @@ ephw_status launch(const GemmParams& p0, hipStream_t stream) {
   for (int64_t b0 = 0; b0 < p0.batch; b0 += 65535) {
     const int64_t nb = (p0.batch - b0) < 65535 ? (p0.batch - b0) : 65535;
     p.batch_base = b0;
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, WM, WN, TA, TB, SPLIT, OCC, BANDNW>),
+    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, WM, WN, TA, TB, KBLK, OCC, BANDNW>),
                        dim3((unsigned)ntiles, (unsigned)nb), dim3(64 * WM * WN), 0, stream, p,
                        tiles_m, tiles_n);
     EPHW_CHECK_LAUNCH();
@@ -1363,12 +1317,12 @@ ephw_status dispatch_skinny(const GemmParams& p, hipStream_t s) {
   return launch_skinny<T, 16>(p, s);
 }
 
-template <typename T, int BM, int BN, int BK, int WM, int WN, int SPLIT, int OCC>
+template <typename T, int BM, int BN, int BK, int WM, int WN, int KBLK, int OCC>
 ephw_status dispatch_trans(const GemmParams& p, hipStream_t s) {
-  if (!p.transA && !p.transB) return launch<T, BM, BN, BK, WM, WN, false, false, SPLIT, OCC>(p, s);
-  if (p.transA && !p.transB) return launch<T, BM, BN, BK, WM, WN, true, false, SPLIT, OCC>(p, s);
-  if (!p.transA && p.transB) return launch<T, BM, BN, BK, WM, WN, false, true, SPLIT, OCC>(p, s);
-  return launch<T, BM, BN, BK, WM, WN, true, true, SPLIT, OCC>(p, s);
+  if (!p.transA && !p.transB) return launch<T, BM, BN, BK, WM, WN, false, false, KBLK, OCC>(p, s);
+  if (p.transA && !p.transB) return launch<T, BM, BN, BK, WM, WN, true, false, KBLK, OCC>(p, s);
+  if (!p.transA && p.transB) return launch<T, BM, BN, BK, WM, WN, false, true, KBLK, OCC>(p, s);
+  return launch<T, BM, BN, BK, WM, WN, true, true, KBLK, OCC>(p, s);
 }
 
 }  // namespace
@@ -1507,7 +1461,7 @@ ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream) {
   if (p.M <= 0 || p.N <= 0 || p.batch <= 0) return EPHW_OK;
   if (p.band.on) {
     const BandEpilogue& b = p.band;
-    if (!cgemm_band_fusable(prec, p.M, p.N, b.nw, p.lda, p.ldb) || p.A_lo || p.transA || p.transB || p.conjA ||
+    if (!cgemm_band_fusable(prec, p.M, p.N, b.nw, p.lda, p.ldb) || p.compensated || p.transA || p.transB || p.conjA ||
         p.conjB || p.accumulate || p.loss.on || p.tblock != 0 || p.batch != 1 || p.M != b.nk ||
         p.N % ((int64_t)b.nm * b.nw * b.nw) != 0 || !b.Vk || (!b.Vkq && !b.kq_index)) {
       set_error("cgemm: this product cannot take the fused band epilogue");
@@ -1527,11 +1481,15 @@ ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream) {
     set_error("cgemm: K must be positive");
     return EPHW_EINVAL;
   }
-  if (prec == 0 && p.A_lo) {
-    set_error("cgemm: split A is an FP32 feature");
-    return EPHW_EINVAL;
+  if (p.compensated) {
+    if (prec == 0) {
+      set_error("cgemm: K-blocked accumulation is an FP32 form");
+      return EPHW_EINVAL;
+    }
+    // eight waves of 64 x 32 outputs: the second set of accumulators fits the
+    // register budget of two waves per SIMD
+    return dispatch_trans<float, 128, 128, 16, 2, 4, 2, 2>(p, stream);
   }
-  if (p.A_lo) return dispatch_trans<float, 128, 128, 16, 2, 2, 2, 2>(p, stream);
   // few rows, many columns, B read straight: a stream over B and C
   // (FP32 reads two complex values per 16-byte load: rows must start on 16 bytes)
   if (p.M <= 16 && p.N >= 16384 && !p.transB && !p.conjB && !p.loss.on && p.tblock == 0 &&

@@ -77,6 +77,13 @@ inline ephw_status upload(X** dst, const X* src, size_t count, int64_t* owner_by
 inline int prec_kind(int32_t prec) { return prec == EPHW_FP64 ? 0 : 1; }
 inline size_t csize(int kind) { return kind == 0 ? 16 : 8; }
 
+// FP64 interpolation + eigensolve: out_eps [n][dim], out_v c128 [n][dim][dim]
+// from A = phases [n][nr] (c128) and B = R-space matrices [nr][dim*dim] (c128),
+// with caller-given buffers: hk [n][dim][dim] c128 and, for dim > 32, jwork of
+// jacobi_work_doubles(dim, n) doubles
+ephw_status interp_eigh_ws(ephw_system* s, const double* phase, int64_t n, int64_t nr, const double* mats, int dim,
+                           double* out_eps, double* out_v, double* hk, double* jwork, bool stages, hipStream_t st);
+
 ephw_status interpolate_large(ephw_kset* ks, const double* q, int64_t nq, const int32_t* kq_index, int64_t q_offset,
                               uint32_t flags, void* g_out, double* band_sum, double* loss, uint64_t loss_seed,
                               double* eps_kq, double* omega, hipStream_t st);
@@ -96,15 +103,15 @@ struct ephw_ctx {
 };
 
 enum WsSlot {
-  WS_PQ, WS_PQ_LO, WS_PQH, WS_PQC, WS_D, WS_LAM, WS_E, WS_U, WS_G, WS_GNU, WS_W, WS_BQ, WS_HKQ,
+  WS_PQ, WS_PQH, WS_PQC, WS_D, WS_LAM, WS_E, WS_U, WS_G, WS_GNU, WS_W, WS_BQ, WS_HKQ,
   WS_EKQ, WS_VKQ64, WS_VKQ, WS_JWORK, WS_LOSS, WS_PH, WS_HK, WS_EPS, WS_V64,
   // adjoint and large-band rotations
   WS_ADJ_A, WS_ADJ_B, WS_ADJ_C, WS_DPQ, WS_DE64, WS_DU, WS_VKBAR, WS_PAIRS, WS_DKACC, WS_GBAR, WS_GNUBAR, WS_T,
   WS_YBAR, WS_Z, WS_WBAR, WS_PAIRBAR, WS_OFF, WS_UBAR, WS_SPLIT, WS_SPLITB, WS_DOTPART,
   // coarse Bloch -> Wannier transform
   WS_CPK, WS_UINV,
-  // energy-window screen
-  WS_WINDOW,
+  // energy-window screen and the pair-list interpolation
+  WS_WINDOW, WS_PAIRSET,
   // the buffers of an interpolation call (Nw <= 32) in one block
   WS_ARENA, WS_COUNT
 };
@@ -147,6 +154,11 @@ struct ephw_system {
   int32_t k_tile = 0;
   int64_t bytes = 0;
   DevBuf ws[WS_COUNT];
+  // pinned host staging of per-call descriptors (pair lists), reused once the
+  // copy recorded by `staged` has completed
+  void* stage_host = nullptr;
+  size_t stage_bytes = 0;
+  hipEvent_t staged = nullptr;
 };
 
 struct ephw_kset {
@@ -157,7 +169,6 @@ struct ephw_kset {
   int64_t bytes = 0;
   double* k = nullptr;      // [nk][3]
   void* pk = nullptr;       // T [nk][ne]
-  void* pk_lo = nullptr;    // float [nk][ne] (split)
   double* pkh = nullptr;    // c128 [nk][nh]
   double* eps = nullptr;    // [nk][nw]
   double* v64 = nullptr;    // c128 [nk][nw][nw]

@@ -6,10 +6,9 @@
 namespace ephw {
 
 // out[i][r] = w_r exp(2 pi i p_i.R_r) (w = NULL -> 1), argument reduced in FP64.
-// prec 0: out is c128.  prec 1: out is c64 (rounded), out_lo (optional) gets
-// the c64 rounding of the remainder, so hi + lo carries the FP64 phase.
+// prec 0: out is c128.  prec 1: out is c64, the FP64 phase rounded.
 ephw_status phase_matrix(int prec, const double* pts, int64_t n, const int32_t* R, const double* w,
-                         int64_t nr, void* out, void* out_lo, hipStream_t s);
+                         int64_t nr, void* out, hipStream_t s);
 
 // Hermitian eigensolve of a batch of n x n c128 matrices (cyclic Jacobi, FP64).
 // eps [batch][n] ascending; V [batch][n][n] c128, column j the eigenvector of eps j,
@@ -82,6 +81,13 @@ struct BandRotateArgs {
   uint64_t loss_seed;
   int64_t q_global0;      // global index of the batch's first q
   uint32_t* status;
+  // Pair mode (pair_k set): the "k points" are a list of (k, q) pairs with
+  // qb = 1; W, g_out, band_sum and loss_partial are indexed by pair, V(k) is
+  // Vk[pair_k[p]], V(k+q) is Vk[kq_index[p]], and the loss element index uses
+  // the pair's own (q_global0 + pair_q[p], pair_k[p]) in a set of nk_set points.
+  const int32_t* pair_k = nullptr;
+  const int32_t* pair_q = nullptr;
+  int64_t nk_set = 0;
 };
 ephw_status band_rotate(int prec, const BandRotateArgs& a, hipStream_t s);
 // Work split of the band-rotation kernel (Nw <= 32): P consecutive k per

@@ -2,8 +2,8 @@
 //
 // p is fractional (FP64) and R integer, so p.R is formed in FP64 and reduced
 // to (-1/2, 1/2] by subtracting its nearest integer before sincospi; the
-// reduced argument keeps full FP64 accuracy however large |R| is.  For the
-// FP32 forms the FP64 phase is rounded to a (hi, lo) pair of floats.
+// reduced argument keeps full FP64 accuracy however large |R| is.  The FP32
+// forms take the FP64 phase rounded to complex64.
 #include "kernels.h"
 
 namespace ephw {
@@ -11,8 +11,7 @@ namespace {
 
 template <typename T>
 __global__ void phase_kernel(const double* __restrict__ pts, int64_t n, const int32_t* __restrict__ R,
-                             const double* __restrict__ w, int64_t nr, T* __restrict__ out,
-                             T* __restrict__ out_lo) {
+                             const double* __restrict__ w, int64_t nr, T* __restrict__ out) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * nr) return;
   const int64_t i = idx / nr, r = idx % nr;
@@ -26,29 +25,24 @@ __global__ void phase_kernel(const double* __restrict__ pts, int64_t n, const in
     sn *= wr;
     cs *= wr;
   }
-  const T hr = (T)cs, hi = (T)sn;
-  out[2 * idx] = hr;
-  out[2 * idx + 1] = hi;
-  if (out_lo) {
-    out_lo[2 * idx] = (T)(cs - (double)hr);
-    out_lo[2 * idx + 1] = (T)(sn - (double)hi);
-  }
+  out[2 * idx] = (T)cs;
+  out[2 * idx + 1] = (T)sn;
 }
 
 }  // namespace
 
 ephw_status phase_matrix(int prec, const double* pts, int64_t n, const int32_t* R, const double* w,
-                         int64_t nr, void* out, void* out_lo, hipStream_t s) {
+                         int64_t nr, void* out, hipStream_t s) {
   const int64_t total = n * nr;
   if (total <= 0) return EPHW_OK;
   const int bs = 256;
   const int64_t grid = ceil_div(total, bs);
   if (prec == 0) {
     hipLaunchKernelGGL(phase_kernel<double>, dim3((unsigned)grid), dim3(bs), 0, s, pts, n, R, w, nr,
-                       static_cast<double*>(out), static_cast<double*>(out_lo));
+                       static_cast<double*>(out));
   } else {
     hipLaunchKernelGGL(phase_kernel<float>, dim3((unsigned)grid), dim3(bs), 0, s, pts, n, R, w, nr,
-                       static_cast<float*>(out), static_cast<float*>(out_lo));
+                       static_cast<float*>(out));
   }
   EPHW_CHECK_LAUNCH();
   return EPHW_OK;

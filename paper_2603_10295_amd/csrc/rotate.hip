@@ -239,15 +239,25 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
   BandLds<T> L = band_lds<T>(smem_raw, P, nw, rows_pp);
 
   const float r_nw = 1.0f / (float)nw, r_nw2 = 1.0f / (float)nw2;
+  const bool pairs = a.pair_k != nullptr;
+  const int64_t nset = pairs ? a.nk_set : a.nk;   // points V and the k+q indices refer to
   if (rot) {
     const T* Vk = static_cast<const T*>(a.Vk);
     for (int i = tid; i < npair * nw2; i += kRotThreads) {
       const int pp = div_rcp(i, r_nw2), e = i - pp * nw2;
       const int64_t ik = a.k0 + ik0 + pp;
+      int64_t kv = ik;   // row of V(k)
+      if (pairs) {
+        kv = a.pair_k[ik];
+        if (kv < 0 || kv >= nset) {
+          if (e == 0) atomicOr(a.status, kStatusIndex);
+          kv = 0;
+        }
+      }
       const T* src;
       if (a.kq_index) {
         int64_t id = a.kq_index[(int64_t)iq * a.nk + ik];
-        if (id < 0 || id >= a.nk) {
+        if (id < 0 || id >= nset) {
           if (e == 0) atomicOr(a.status, kStatusIndex);
           id = 0;
         }
@@ -255,8 +265,8 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
       } else {
         src = static_cast<const T*>(a.Vkq) + 2 * ((int64_t)iq * a.nk + ik) * nw2;
       }
-      L.vk[2 * i] = Vk[2 * (ik * nw2 + e)];
-      L.vk[2 * i + 1] = Vk[2 * (ik * nw2 + e) + 1];
+      L.vk[2 * i] = Vk[2 * (kv * nw2 + e)];
+      L.vk[2 * i + 1] = Vk[2 * (kv * nw2 + e) + 1];
       L.vkq[2 * i] = src[2 * e];
       L.vkq[2 * i + 1] = src[2 * e + 1];
     }
@@ -364,8 +374,11 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
             go[2 * n + 1] = acc[n].im;
           }
       }
-      const uint64_t base = ((uint64_t)(a.q_global0 + iq) * (uint64_t)a.nk + (uint64_t)ik) * (uint64_t)E +
-                            (uint64_t)eoff;
+      uint64_t base = ((uint64_t)(a.q_global0 + iq) * (uint64_t)a.nk + (uint64_t)ik) * (uint64_t)E +
+                      (uint64_t)eoff;
+      if (pairs && want_l)
+        base = ((uint64_t)(a.q_global0 + a.pair_q[ik]) * (uint64_t)a.nk_set + (uint64_t)a.pair_k[ik]) *
+                   (uint64_t)E + (uint64_t)eoff;
 #pragma unroll
       for (int n = 0; n < NWB; ++n)
         if (n < nw) {

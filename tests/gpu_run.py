@@ -96,3 +96,15 @@ class Runner:
             out["eps_kq"] = ekq.cpu().numpy()
         ks.close()
         return out
+
+
+def scaled_block_error(s_gpu, s_ref):
+    """Largest |S_gpu - S_ref| / sqrt(S_ref * max S_ref) over the degenerate-block
+    sums of |g|^2 (blocks with S_ref >= 1e-10 max S_ref).  An absolute error
+    eta * |g|max in the elements of g changes a block sum S by about
+    2 eta sqrt(S * max S), so this bounds eta; the plain relative error of
+    blocks far below the largest is not something an FP32 sum can bound."""
+    a = np.concatenate([x.reshape(-1) for x in s_gpu])
+    b = np.concatenate([x.reshape(-1) for x in s_ref])
+    keep = b >= 1e-10 * b.max()
+    return float(np.max(np.abs(a[keep] - b[keep]) / np.sqrt(b[keep] * b.max())))

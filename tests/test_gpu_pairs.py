@@ -1,0 +1,179 @@
+"""GPU parity of the pair-list path of the energy-window pre-screening.
+
+ephw_window_pairs must list exactly the pairs the oracle's eigenvalues keep
+(integer output, compared exactly, window edges placed in gaps of the
+spectrum so rounding cannot move a state across them);
+ephw_interpolate_pairs must give, on every kept pair, the g of
+ephw_interpolate at the same (k, q) (same k-set, same V) and the oracle's g
+in degenerate-block sums; its loss equals the oracle's weighted loss over the
+kept pairs with the full-grid element indices.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+RTOL_W = 1e-12      # FP64: same V on both sides, sums of a few hundred terms
+RTOL_S = 1e-10      # FP64 block sums against the oracle
+RTOL_32 = 1e-5      # FP32
+
+
+@pytest.fixture(scope="module")
+def run():
+    from gpu_run import Runner
+    return Runner()
+
+
+def gap_edge(vals, target):
+    """A value between the two sorted neighbours of target in vals (a gap)."""
+    v = np.unique(vals)
+    i = int(np.searchsorted(v, target))
+    i = min(max(i, 1), len(v) - 1)
+    return 0.5 * (v[i - 1] + v[i])
+
+
+def window_case(prec, seed=71, m=(4, 4, 2), frac=0.4):
+    s = synth.make_system(6, 2, synth.box((3, 3, 2)), synth.box((2, 2, 2)), [seed, 2])
+    if prec != 0:
+        s = dataclasses.replace(s, g=s.g.astype(np.complex64))
+    kg = synth.uniform_grid(m)
+    kqi = synth.grid_index_of_sum(m)
+    eps, _ = oracle.bands(s, kg)
+    lo = float(eps.min()) - 1.0
+    hi = gap_edge(eps, np.quantile(eps[:, 0], frac))
+    kact = np.any((eps >= lo) & (eps <= hi), axis=1)
+    keep = kact[None, :] & kact[kqi]          # [q][k]
+    return s, kg, kg.copy(), kqi, lo, hi, keep
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_window_pairs_match_the_oracle_window(run, prec):
+    from paper_2603_10295_amd import ephw
+    from gpu_run import dev
+    s, kg, qg, kqi, lo, hi, keep = window_case(prec)
+    assert 0 < keep.sum() < keep.size and not keep.all(axis=1).any() and (~keep).all(axis=1).any()
+    ks = ephw.KSet(run.system(s), dev(kg), prec)
+    start, pk, pkq = ephw.window_pairs(ks, dev(kqi), lo, hi)
+    run.ctx.check()
+    ks.close()
+    want_start = np.concatenate([[0], np.cumsum(keep.sum(axis=1))])
+    np.testing.assert_array_equal(start, want_start)
+    iq, ik = np.nonzero(keep)                 # q-major, ascending k within each q
+    np.testing.assert_array_equal(pk.cpu().numpy()[:len(ik)], ik)
+    np.testing.assert_array_equal(pkq.cpu().numpy()[:len(ik)], kqi[iq, ik])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_interpolate_pairs_matches_full_path_and_oracle(run, prec):
+    import torch
+    from paper_2603_10295_amd import ephw
+    from gpu_run import dev, cplx_dtype
+    s, kg, qg, kqi, lo, hi, keep = window_case(prec)
+    nk, nq = len(kg), len(qg)
+    sysh = run.system(s)
+    ks = ephw.KSet(sysh, dev(kg), prec)
+    start, pk, pkq = ephw.window_pairs(ks, dev(kqi), lo, hi)
+    npairs = int(start[-1])
+    q_off, seed = 5, 23
+    g = torch.empty((npairs, s.nm, s.nw, s.nw), dtype=cplx_dtype(prec), device="cuda:0")
+    t = torch.empty((npairs, s.nm), dtype=torch.float64, device="cuda:0")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    ephw.interpolate_pairs(ks, dev(qg), start, pk, pkq, q_offset=q_off,
+                           flags=ephw.OUT_G | ephw.OUT_BAND_SUM | ephw.OUT_LOSS, g_out=g, band_sum=t, loss=loss,
+                           loss_seed=seed)
+    # the full path on every pair of the same k-set
+    gf = torch.empty((nq, nk, s.nm, s.nw, s.nw), dtype=cplx_dtype(prec), device="cuda:0")
+    ephw.interpolate(ks, dev(qg), kq_index=dev(kqi), q_offset=q_off, flags=ephw.OUT_G, g_out=gf)
+    run.ctx.check()
+    ks.close()
+    iq, ik = np.nonzero(keep)
+    gp = g.cpu().numpy().astype(np.complex128)
+    full = gf.cpu().numpy().astype(np.complex128)[iq, ik]
+    err_full = float(np.abs(gp - full).max() / np.abs(full).max())
+    # against the oracle (its own k+q eigensolves: block sums)
+    ref = oracle.interpolate(s, kg, qg, return_all=True)
+    s_gpu = []
+    s_ref = []
+    for p, (a, b) in enumerate(zip(iq, ik)):
+        s_gpu += oracle.block_sums(np.abs(gp[p])[None, None] ** 2, ref["eps_kq"][a, b][None, None],
+                                   ref["eps_k"][b][None], ref["lam"][a][None])
+        s_ref += oracle.block_sums(np.abs(ref["ghat"][a, b])[None, None] ** 2, ref["eps_kq"][a, b][None, None],
+                                   ref["eps_k"][b][None], ref["lam"][a][None])
+    norm, _ = oracle.compare_block_sums(s_gpu, s_ref)
+    t_ref = oracle.band_sums(ref["ghat"])[iq, ik]
+    t_err = float(np.abs(t.cpu().numpy() - t_ref).max() / np.abs(t_ref).max())
+    l_ref = oracle.weighted_loss(ref["ghat"][iq, ik], seed, iq + q_off, ik, nk)
+    l_err = abs(float(loss.cpu().numpy()[0]) - l_ref) / l_ref
+    print(f"pairs prec={prec}: {npairs} of {nq * nk}; vs full path {err_full:.2e}, block sums {norm:.2e}, "
+          f"band sums {t_err:.2e}, loss {l_err:.2e}")
+    tol_full = RTOL_W if prec == 0 else RTOL_32
+    tol = RTOL_S if prec == 0 else RTOL_32
+    assert err_full < tol_full and norm < tol and t_err < tol and l_err < tol
+
+
+def test_interpolate_pairs_edge_cases(run):
+    """Empty window (no pair: nothing enqueued, outputs untouched), a window
+    holding every pair (equal to the full path), ragged q batches (q_batch 3
+    over 32 q with empty q in between), the Wannier gauge, and invalid CSR
+    offsets refused on the host."""
+    import torch
+    from paper_2603_10295_amd import ephw
+    from gpu_run import dev
+    s, kg, qg, kqi, lo, hi, keep = window_case(0, seed=72)
+    nk, nq = len(kg), len(qg)
+    sysh = run.system(s)
+    ks = ephw.KSet(sysh, dev(kg), 0)
+    eps = oracle.bands(s, kg)[0]
+    # empty window
+    start, pk, pkq = ephw.window_pairs(ks, dev(kqi), float(eps.max()) + 1.0, float(eps.max()) + 2.0)
+    assert int(start[-1]) == 0 and not start.any()
+    loss = torch.full((1,), 7.0, dtype=torch.float64, device="cuda:0")
+    ephw.interpolate_pairs(ks, dev(qg), start, pk, pkq, flags=ephw.OUT_LOSS, loss=loss)
+    run.ctx.check()
+    assert float(loss.cpu()[0]) == 7.0
+    # every pair kept, ragged batches
+    start, pk, pkq = ephw.window_pairs(ks, dev(kqi), float(eps.min()) - 1.0, float(eps.max()) + 1.0)
+    assert int(start[-1]) == nq * nk
+    sysh.set_q_batch(3)
+    g = torch.empty((nq * nk, s.nm, s.nw, s.nw), dtype=torch.complex128, device="cuda:0")
+    ephw.interpolate_pairs(ks, dev(qg), start, pk, pkq, flags=ephw.OUT_G, g_out=g)
+    gw = torch.empty_like(g)
+    ephw.interpolate_pairs(ks, dev(qg), start, pk, pkq, flags=ephw.OUT_G | ephw.OUT_WANNIER, g_out=gw)
+    sysh.set_q_batch(0)
+    gf = torch.empty((nq, nk, s.nm, s.nw, s.nw), dtype=torch.complex128, device="cuda:0")
+    ephw.interpolate(ks, dev(qg), kq_index=dev(kqi), flags=ephw.OUT_G, g_out=gf)
+    run.ctx.check()
+    full = gf.cpu().numpy().reshape(nq * nk, s.nm, s.nw, s.nw)
+    assert np.abs(g.cpu().numpy() - full).max() < RTOL_W * np.abs(full).max()
+    ref = oracle.interpolate(s, kg, qg, return_all=True)
+    gw_ref = ref["gw"]     # Eq. (9)-(10) sums before the mode and band rotations
+    np.testing.assert_allclose(gw.cpu().numpy().reshape(gw_ref.shape), gw_ref, rtol=0,
+                               atol=RTOL_W * np.abs(gw_ref).max())
+    # only q 1 and q 30 own pairs (every other q skipped)
+    start = np.zeros(nq + 1, dtype=np.int64)
+    start[2:] = 3
+    start[31:] = 3 + nk
+    sel_k = np.concatenate([[0, 5, 9], np.arange(nk)]).astype(np.int32)
+    sel_q = np.concatenate([[1, 1, 1], np.full(nk, 30)])
+    pk = dev(sel_k)
+    pkq = dev(kqi[sel_q, sel_k].astype(np.int32))
+    g2 = torch.empty((3 + nk, s.nm, s.nw, s.nw), dtype=torch.complex128, device="cuda:0")
+    ephw.interpolate_pairs(ks, dev(qg), start, pk, pkq, flags=ephw.OUT_G, g_out=g2)
+    run.ctx.check()
+    full = gf.cpu().numpy()[sel_q, sel_k]
+    assert np.abs(g2.cpu().numpy() - full).max() < RTOL_W * np.abs(full).max()
+    # invalid offsets are refused before anything is enqueued
+    bad = start.copy()
+    bad[5] = 10
+    with pytest.raises(ephw.EphwError):
+        ephw.interpolate_pairs(ks, dev(qg), bad, pk, pkq, flags=ephw.OUT_G, g_out=g2)
+    bad = start.copy()
+    bad[0] = 1
+    with pytest.raises(ephw.EphwError):
+        ephw.interpolate_pairs(ks, dev(qg), bad, pk, pkq, flags=ephw.OUT_G, g_out=g2)
+    ks.close()

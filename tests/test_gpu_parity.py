@@ -16,6 +16,10 @@ pytestmark = pytest.mark.gpu
 
 RTOL_W = 1e-12      # Wannier-gauge sums, relative to the largest element
 RTOL_S = 1e-10      # block sums of |g|^2, normwise relative
+# FP32 forms: the stated 1e-5 relative error in |g|^2, normwise over the block
+# sums, and block by block as 1e-5 sqrt(S max S) (an error of the elements of g
+# up to about 5e-6 of the largest |g|; see gpu_run.scaled_block_error)
+RTOL_S32 = 1e-5
 
 
 @pytest.fixture(scope="module")
@@ -238,13 +242,17 @@ def test_phase_sum_rp_fp32(run, toy32, toy32_ref, prec):
 
 @pytest.mark.parametrize("prec", [1, 2])
 def test_interpolate_fp32_gauge_invariant(run, toy32, toy32_ref, prec):
+    from gpu_run import scaled_block_error
     r = toy32_ref
     out = run.interpolate(run.system(toy32.system), toy32.k, toy32.q, prec, loss_seed=11)
     s_gpu = oracle.block_sums(np.abs(out["g"].astype(np.complex128)) ** 2, r["eps_kq"], r["eps_k"], r["lam"])
     s_ref = oracle.block_sums(np.abs(r["ghat"]) ** 2, r["eps_kq"], r["eps_k"], r["lam"])
     norm, blk = oracle.compare_block_sums(s_gpu, s_ref)
-    print(f"interpolate prec={prec}: |g|^2 block sums normwise {norm:.2e}, max blockwise {blk:.2e}")
-    assert norm < 1e-5
+    scaled = scaled_block_error(s_gpu, s_ref)
+    print(f"interpolate prec={prec}: |g|^2 block sums normwise {norm:.2e}, max blockwise {blk:.2e}, "
+          f"scaled {scaled:.2e}")
+    assert norm < RTOL_S32
+    assert scaled < RTOL_S32
     assert rel_max(out["band_sum"], oracle.band_sums(r["ghat"])) < 1e-5
     np.testing.assert_allclose(out["eps_k"], r["eps_k"], atol=1e-12 * np.abs(r["eps_k"]).max())
 
@@ -636,27 +644,37 @@ def test_linewidth_matches_oracle(run, prec):
 
 def test_si_dense_sampled_full_size(run):
     """The dense-Si workload at full size in the benchmark's launch shape
-    (8000 k set, q chunks of 1024, g stored, FP32): three q of the first chunk
-    against the oracle in block sums, with the 1e-5 bound."""
+    (8000 k set, q chunks of 1024, g stored): three q of the first chunk
+    against the oracle in block sums, plain FP32 and compensated FP32 (K-blocked
+    accumulation), both within the 1e-5 bounds; the K blocks must cut the
+    normwise error at least in half (the accumulation over K = Ne = Np = 1000
+    is the dominant FP32 error; blocks of 32 remove about 3/4 of it)."""
     import torch
     from paper_2603_10295_amd import ephw
-    from gpu_run import dev
+    from gpu_run import dev, scaled_block_error
     w = synth.si_dense()
     s = w.system
     sysh = run.system(s)
     nk = len(w.k)
-    ks = ephw.KSet(sysh, dev(w.k), ephw.FP32)
     qc = 1024
-    g = torch.empty((qc, nk, s.nm, s.nw, s.nw), dtype=torch.complex64, device="cuda:0")
-    ephw.interpolate(ks, dev(w.q[:qc]), kq_index=dev(w.kq_index[:qc]), flags=ephw.OUT_G, g_out=g)
-    run.ctx.check()
     sample = [0, 511, 1023]
-    got = g[sample].cpu().numpy().astype(np.complex128)
-    del g
-    ks.close()
     ref = oracle.interpolate(s, w.k, w.q[sample], return_all=True)
-    sg = oracle.block_sums(np.abs(got) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
     sr = oracle.block_sums(np.abs(ref["ghat"]) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
-    norm, blk = oracle.compare_block_sums(sg, sr)
-    print(f"dense Si full size, FP32: block sums normwise {norm:.2e}, max blockwise {blk:.2e}")
-    assert norm < 1e-5
+    errs = {}
+    for prec in (ephw.FP32, ephw.FP32_COMP):
+        ks = ephw.KSet(sysh, dev(w.k), prec)
+        g = torch.empty((qc, nk, s.nm, s.nw, s.nw), dtype=torch.complex64, device="cuda:0")
+        ephw.interpolate(ks, dev(w.q[:qc]), kq_index=dev(w.kq_index[:qc]), flags=ephw.OUT_G, g_out=g)
+        run.ctx.check()
+        got = g[sample].cpu().numpy().astype(np.complex128)
+        del g
+        ks.close()
+        sg = oracle.block_sums(np.abs(got) ** 2, ref["eps_kq"], ref["eps_k"], ref["lam"])
+        norm, blk = oracle.compare_block_sums(sg, sr)
+        scaled = scaled_block_error(sg, sr)
+        errs[prec] = norm
+        print(f"dense Si full size, prec {prec}: block sums normwise {norm:.2e}, max blockwise {blk:.2e}, "
+              f"scaled {scaled:.2e}")
+        assert norm < RTOL_S32
+        assert scaled < RTOL_S32
+    assert errs[ephw.FP32_COMP] < 0.5 * errs[ephw.FP32], errs
