@@ -47,6 +47,8 @@ def parse(argv=None):
     ap.add_argument("--tune-cache", default="")
     ap.add_argument("--grid", type=int, default=20, help="k = q = grid^3 for si_dense")
     ap.add_argument("--q-chunk", type=int, default=1024)
+    ap.add_argument("--pair-order", type=int, default=-1,
+                    help="si_window pair lists: 0 by q, 1 by k, -1 the cheaper (fewer groups owning pairs)")
     ap.add_argument("--fp64-steps", type=int, default=2)
     ap.add_argument("--cpu-sample-q", type=int, default=12, help="q points of the oracle sample (about 15 s of host work)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -450,20 +452,25 @@ def bench_window(args):
 
     # ---- (1) pair lists ----------------------------------------------------
     ks_f = ephw.KSet(sysh, k, ephw.FP32)
-    start, pk, pkq = ephw.window_pairs(ks_f, kqi, lo, hi)
+    order, start, po, pkq = ephw.window_pairs(ks_f, kqi, lo, hi, order=args.pair_order)
     ks_f.close()
     npairs = int(start[-1])
     gp = torch.empty((max(npairs, 1), s.nm, s.nw, s.nw), dtype=torch.complex64, device="cuda:0")
     qc = min(args.q_chunk, nq)
+    order_name = {ephw.PAIRS_BY_Q: "by q", ephw.PAIRS_BY_K: "by k"}[order]
 
     def step_pairs():
         ks_p = ephw.KSet(sysh, k, ephw.FP32)
-        st, _, _ = ephw.window_pairs(ks_p, kqi, lo, hi, pk, pkq)
-        for q0 in range(0, nq, qc):
-            q1 = min(nq, q0 + qc)
-            p0 = int(st[q0])
-            ephw.interpolate_pairs(ks_p, q[q0:q1], st[q0:q1 + 1] - p0, pk[p0:], pkq[p0:], q_offset=q0,
-                                   flags=ephw.OUT_G, g_out=gp[p0:])
+        o, st, _, _ = ephw.window_pairs(ks_p, kqi, lo, hi, order=order, pair_other=po, pair_kq=pkq)
+        if o == ephw.PAIRS_BY_K:
+            # the whole list at once: every k's q are in one group
+            ephw.interpolate_pairs(ks_p, q, o, st, po, pkq, flags=ephw.OUT_G, g_out=gp)
+        else:
+            for q0 in range(0, nq, qc):
+                q1 = min(nq, q0 + qc)
+                p0 = int(st[q0])
+                ephw.interpolate_pairs(ks_p, q[q0:q1], o, st[q0:q1 + 1] - p0, po[p0:], pkq[p0:], q_offset=q0,
+                                       flags=ephw.OUT_G, g_out=gp[p0:])
         ks_p.close()
 
     sysh.profile_read()
@@ -471,7 +478,8 @@ def bench_window(args):
     dt_pairs = timed_steps(step_pairs)
     sysh.profile(False)
     stages_pairs = {k_: round(v[0] / (args.steps + args.warmup), 3) for k_, v in sysh.profile_read().items()}
-    log(f"pairs: {npairs} kept of {nk * nq}; {dt_pairs * 1e3:.1f} ms per pass; stages {stages_pairs}")
+    log(f"pairs ({order_name}): {npairs} kept of {nk * nq}; {dt_pairs * 1e3:.1f} ms per pass; "
+        f"stages {stages_pairs}")
 
     # ---- (2) compacted sets with a pair mask -------------------------------
     k_out = torch.empty((nk, 3), dtype=torch.float64, device="cuda:0")
@@ -504,11 +512,14 @@ def bench_window(args):
 
     # parity of the pair path on two q against the oracle (kept pairs only)
     import oracle
-    pick = [int(np.flatnonzero(np.diff(start) > 0)[0]), nq // 2]
-    pick = [j for j in pick if start[j + 1] > start[j]]
-    sel_q = np.concatenate([np.full(int(start[j + 1] - start[j]), j) for j in pick])
-    sel_p = np.concatenate([np.arange(start[j], start[j + 1]) for j in pick])
-    sel_k = pk[torch.as_tensor(sel_p, device="cuda:0")].cpu().numpy()
+    # every pair's (q, k) from the list, then all kept pairs of two q
+    other = po[:npairs].cpu().numpy()
+    major = np.repeat(np.arange(len(start) - 1), np.diff(start))
+    pair_q, pair_k = (major, other) if order == ephw.PAIRS_BY_Q else (other, major)
+    pick = [int(pair_q.min()), int(np.median(pair_q))]
+    pick = sorted(set(pick))
+    sel_p = np.flatnonzero(np.isin(pair_q, pick))
+    sel_q, sel_k = pair_q[sel_p], pair_k[sel_p]
     got = gp[torch.as_tensor(sel_p, device="cuda:0")].cpu().numpy().astype(np.complex128)
     ref = oracle.interpolate(s, w.k, w.q[pick], return_all=True)
     qpos = {j: i for i, j in enumerate(pick)}
@@ -527,7 +538,8 @@ def bench_window(args):
         "warmup": args.warmup, "ms_per_step": dt_pairs * 1e3, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
         "config": {"workload": f"si_dense_window_nw8_nm6_ne1000_{nk}kx{nq}q_lowest10pct_band0", "nk": nk, "nq": nq,
-                   "window": [lo, hi], "form": "pair lists (ephw_window_pairs + ephw_interpolate_pairs)"},
+                   "window": [lo, hi],
+                   "form": f"pair lists grouped {order_name} (ephw_window_pairs + ephw_interpolate_pairs)"},
         "kept_pairs": npairs, "computed_pairs": npairs, "kept_elems_per_s": npairs * E / dt_pairs,
         "stages_ms_per_step": stages_pairs,
         "compacted_sets": {"ms_per_step": dt_masked * 1e3, "active_k": nks, "active_q": nqs,

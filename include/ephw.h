@@ -90,6 +90,11 @@ typedef int32_t ephw_status;
 #define EPHW_OUT_WANNIER    8u  /* skip the band and mode rotations: store the
                                    Re/Rp phase sums g_{m'n' kappa alpha}(k,q) */
 
+/* grouping of a (k, q) pair list (ephw_window_pairs, ephw_interpolate_pairs) */
+#define EPHW_PAIRS_BY_Q   0  /* CSR over the q list; the other index of a pair is k */
+#define EPHW_PAIRS_BY_K   1  /* CSR over the k-set; the other index of a pair is q */
+#define EPHW_PAIRS_AUTO  -1  /* ephw_window_pairs picks the cheaper of the two */
+
 typedef struct ephw_ctx ephw_ctx;
 typedef struct ephw_system ephw_system;
 typedef struct ephw_kset ephw_kset;
@@ -277,43 +282,58 @@ ephw_status ephw_window_screen(ephw_kset* ks, const double* q, int64_t nq, const
 /* The kept pairs of the same energy window as a list (the pre-screening of
    the Results section's single-node benchmark, taken down to single (k, q)
    pairs): pair (k, q) is kept when k and k+q (kq_index) both have a band in
-   [e_lo, e_hi].  Outputs, in CSR form by q:
-     pair_start [nq + 1] int64 (HOST): the kept pairs of q_j are
-                p = pair_start[j] .. pair_start[j+1]-1; pair_start[nq] is the total
-     pair_k     [capacity] int32 (device): k index (in the set) of pair p,
-                ascending within each q
-     pair_kq    [capacity] int32 (device): kq_index[j][pair_k[p]], the set
+   [e_lo, e_hi].  The list is grouped (CSR) by q or by k:
+     order      EPHW_PAIRS_BY_Q, EPHW_PAIRS_BY_K, or EPHW_PAIRS_AUTO: by k when
+                fewer k than q own a kept pair (the cheaper nesting order for
+                ephw_interpolate_pairs), else by q
+     order_out  host int32 or NULL: the grouping used
+     pair_start HOST int64, [nq + 1] (by q) or [nk + 1] (by k; for AUTO give
+                max(nq, nk) + 1): the pairs of group j are
+                p = pair_start[j] .. pair_start[j+1]-1; the last entry is the total
+     pair_other [capacity] int32 (device): k index in the set (by q) or q index
+                in the list (by k) of pair p, ascending within each group
+     pair_kq    [capacity] int32 (device): kq_index[q][k] of pair p, the set
                 index of k+q
    kq_index [nq][nk] int32 (device): as in ephw_window_screen (entries outside
    [0, nk) count as dropped and set EPHW_EINDEX in the status word).
    pair_start is always written; when the total exceeds `capacity` the call
-   returns EPHW_EINVAL without writing pair_k / pair_kq (the caller can size
-   them from pair_start[nq] and call again).  Synchronises the stream. */
+   returns EPHW_EINVAL without writing the device lists (the caller can size
+   them from the total and call again).  Synchronises the stream. */
 ephw_status ephw_window_pairs(ephw_kset* ks, const int32_t* kq_index, int64_t nq, double e_lo, double e_hi,
-                              int64_t* pair_start, int32_t* pair_k, int32_t* pair_kq, int64_t capacity,
-                              void* stream);
+                              int32_t order, int32_t* order_out, int64_t* pair_start, int32_t* pair_other,
+                              int32_t* pair_kq, int64_t capacity, void* stream);
 
-/* Eq. (7) on a list of (k, q) pairs (Nw <= 32; FP64 or FP32 k-sets): for the
-   q list q [nq][3] f64 (device) and the pairs in the CSR form of
-   ephw_window_pairs (pair_start HOST [nq + 1]; pair_k, pair_kq device
-   [pair_start[nq]], k and k+q as indices into the k-set), computes for pair p
-   of q_j the g_{mn nu}(k, q_j) that ephw_interpolate gives at that k and q
-   (with the k+q grid index pair_kq[p]).  Only the kept pairs enter the Re sum
-   and the band rotations; q points without pairs are skipped entirely.
+/* Eq. (7) on a list of (k, q) pairs (Nw <= 32; FP64 or FP32 k-sets) in the
+   form ephw_window_pairs writes (order EPHW_PAIRS_BY_Q or EPHW_PAIRS_BY_K;
+   pair_start HOST; pair_other and pair_kq device [pair_start[last]]): for
+   pair p, with k = its k-set index and q = its row of the list q [nq][3] f64
+   (device), computes the g_{mn nu}(k, q) that ephw_interpolate gives at that
+   k and q with the k+q grid index pair_kq[p].  Only kept pairs enter the
+   phase sums' pair stage and the rotations.  The grouping selects the
+   nesting order of the two phase sums:
+     by q: per q, Eq. (9) over all Re (one GEMM per batch of q), then the Re
+           sum of Eq. (10) for that q's kept k only;
+     by k: per k, the Re sum first over all Rp (one batched GEMM per chunk of
+           k), then the Rp sum of Eq. (9) for that k's kept q only, then the
+           mode vectors u(q) per pair.
+   The first stage costs (points of its group that own a pair) x Ne x Np x
+   Nw^2 Nm, the second (kept pairs) x (Ne or Np) x Nw^2 Nm, so grouping by
+   the index with fewer such points is the cheaper order.
      flags, loss_seed, q_offset  as in ephw_interpolate; the loss weights use
-              the element index of (q_offset + j, pair_k[p]) in the k-set, so
-              the loss equals that of ephw_interpolate over the same pairs
+              the element index of (q_offset + q, k) in the k-set, so the loss
+              equals that of ephw_interpolate over the same pairs
      g_out    [npairs][nm][nw][nw] c128 (FP64) or c64 (FP32), if EPHW_OUT_G
      band_sum [npairs][nm] f64, if EPHW_OUT_BAND_SUM
      loss     one f64 (L +=), if EPHW_OUT_LOSS
    pair_start must start at 0 and not decrease (checked on the host); pair
-   indices outside the k-set set EPHW_EINDEX in the status word.  The call
-   copies its pair offsets and per-q GEMM descriptors to the device through
-   pinned host memory the system owns; it does not synchronise the stream. */
-ephw_status ephw_interpolate_pairs(ephw_kset* ks, const double* q, int64_t nq, const int64_t* pair_start,
-                                   const int32_t* pair_k, const int32_t* pair_kq, int64_t q_offset, int32_t prec,
-                                   uint32_t flags, void* g_out, double* band_sum, double* loss, uint64_t loss_seed,
-                                   void* stream);
+   indices outside the k-set or the q list set EPHW_EINDEX in the status
+   word.  The call copies its group offsets and per-group GEMM descriptors to
+   the device through pinned host memory the system owns; it does not
+   synchronise the stream. */
+ephw_status ephw_interpolate_pairs(ephw_kset* ks, const double* q, int64_t nq, int32_t order,
+                                   const int64_t* pair_start, const int32_t* pair_other, const int32_t* pair_kq,
+                                   int64_t q_offset, int32_t prec, uint32_t flags, void* g_out, double* band_sum,
+                                   double* loss, uint64_t loss_seed, void* stream);
 
 /* A downstream reduction of stored matrix elements over q (the multi-node
    scalability runs of the Results section compute an electron self-energy

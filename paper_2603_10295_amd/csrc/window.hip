@@ -6,8 +6,10 @@
 // ascending order), maps each selected pair's k+q grid index into the
 // compacted k list and marks the pairs whose k+q is active, so that Eq. (7)
 // then runs on the compacted sets only.  ephw_window_pairs goes one step
-// further and lists the kept pairs themselves (CSR by q), the input of
-// ephw_interpolate_pairs, which computes nothing for the pairs it drops.
+// further and lists the kept pairs themselves (CSR by q or by k), the input
+// of ephw_interpolate_pairs, which computes nothing for the pairs it drops.
+#include <vector>
+
 #include "internal.h"
 
 namespace ephw {
@@ -101,31 +103,35 @@ __global__ void window_pairs_kernel(const int32_t* __restrict__ kq, int64_t nk, 
 
 int64_t grid_of(int64_t n, int t) { return (n + t - 1) / t; }
 
-// Pair lists (CSR by q) of the pairs whose k and k+q both have a band in the
-// window.  One workgroup per q; each thread takes a contiguous run of k.
+// Pair lists of the pairs whose k and k+q both have a band in the window,
+// grouped by q (CSR over the q list, each q's k ascending) or by k (CSR over
+// the k-set, each k's q ascending).  One workgroup per q or per k; a thread
+// takes a contiguous run of the other index.
 constexpr int kPairThreads = 256;
 
-__device__ __forceinline__ bool pair_kept(const int32_t* __restrict__ kq_row, const int32_t* __restrict__ kflag,
-                                          int64_t nk, int64_t ik, uint32_t* status, int32_t* j_out) {
-  const int32_t j = kq_row[ik];
+// whether pair (q row `kq_row`, k = ik) is kept; j = index of k+q
+__device__ __forceinline__ bool pair_kept(int32_t j, const int32_t* __restrict__ kflag, int64_t nk, int64_t ik,
+                                          uint32_t* status) {
   if (j < 0 || j >= nk) {
     atomicOr(status, kStatusIndex);
     return false;
   }
-  *j_out = j;
   return kflag[ik] && kflag[j];
 }
 
+// by q: count[iq] = kept k of q iq.  by k: count[ik] = kept q of k ik.
 __global__ void __launch_bounds__(kPairThreads)
-    pair_count_kernel(const int32_t* __restrict__ kq, int64_t nk, const int32_t* __restrict__ kflag,
-                      int64_t* __restrict__ count, uint32_t* status) {
+    pair_count_kernel(const int32_t* __restrict__ kq, int64_t nq, int64_t nk, const int32_t* __restrict__ kflag,
+                      int by_k, int64_t* __restrict__ count, uint32_t* status) {
   __shared__ int64_t part[kPairThreads];
-  const int64_t iq = blockIdx.x;
-  const int32_t* row = kq + iq * nk;
+  const int64_t major = blockIdx.x;
+  const int64_t n_other = by_k ? nq : nk;
   int64_t c = 0;
-  for (int64_t ik = threadIdx.x; ik < nk; ik += kPairThreads) {
-    int32_t j;
-    c += pair_kept(row, kflag, nk, ik, status, &j) ? 1 : 0;
+  if (!by_k || kflag[major]) {
+    for (int64_t o = threadIdx.x; o < n_other; o += kPairThreads) {
+      const int64_t iq = by_k ? o : major, ik = by_k ? major : o;
+      c += pair_kept(kq[iq * nk + ik], kflag, nk, ik, status) ? 1 : 0;
+    }
   }
   part[threadIdx.x] = c;
   __syncthreads();
@@ -133,49 +139,26 @@ __global__ void __launch_bounds__(kPairThreads)
     if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) count[iq] = part[0];
+  if (threadIdx.x == 0) count[major] = part[0];
 }
 
-// start[i] = sum of count[0..i) for i = 0..n (one workgroup)
-__global__ void __launch_bounds__(kScanThreads)
-    exclusive_scan_kernel(const int64_t* __restrict__ count, int64_t n, int64_t* __restrict__ start) {
-  __shared__ int64_t part[kScanThreads];
-  const int t = threadIdx.x;
-  const int64_t chunk = (n + kScanThreads - 1) / kScanThreads;
-  const int64_t b = t * chunk, e = (b + chunk) < n ? (b + chunk) : n;
-  int64_t c = 0;
-  for (int64_t i = b; i < e; ++i) c += count[i];
-  part[t] = c;
-  __syncthreads();
-  for (int off = 1; off < kScanThreads; off <<= 1) {
-    const int64_t v = t >= off ? part[t - off] : 0;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
-  }
-  int64_t pos = part[t] - c;
-  for (int64_t i = b; i < e; ++i) {
-    start[i] = pos;
-    pos += count[i];
-  }
-  if (t == kScanThreads - 1) start[n] = part[t];
-}
-
-// the kept pairs of q in ascending k: pair_k = k, pair_kq = index of k+q
+// the kept pairs of one q (by k: of one k) in ascending order of the other
+// index: other = k (by q) or q (by k), pair_kq = index of k+q
 __global__ void __launch_bounds__(kPairThreads)
-    pair_fill_kernel(const int32_t* __restrict__ kq, int64_t nk, const int32_t* __restrict__ kflag,
-                     const int64_t* __restrict__ start, int32_t* __restrict__ pair_k, int32_t* __restrict__ pair_kq,
-                     uint32_t* status) {
+    pair_fill_kernel(const int32_t* __restrict__ kq, int64_t nq, int64_t nk, const int32_t* __restrict__ kflag,
+                     int by_k, const int64_t* __restrict__ start, int32_t* __restrict__ other,
+                     int32_t* __restrict__ pair_kq, uint32_t* status) {
   __shared__ int64_t part[kPairThreads];
-  const int64_t iq = blockIdx.x;
-  const int32_t* row = kq + iq * nk;
+  const int64_t major = blockIdx.x;
+  if (start[major + 1] == start[major]) return;   // uniform across the workgroup
+  const int64_t n_other = by_k ? nq : nk;
   const int t = threadIdx.x;
-  const int64_t chunk = (nk + kPairThreads - 1) / kPairThreads;
-  const int64_t b = t * chunk, e = (b + chunk) < nk ? (b + chunk) : nk;
+  const int64_t chunk = (n_other + kPairThreads - 1) / kPairThreads;
+  const int64_t b = t * chunk, e = (b + chunk) < n_other ? (b + chunk) : n_other;
   int64_t c = 0;
-  for (int64_t ik = b; ik < e; ++ik) {
-    int32_t j;
-    c += pair_kept(row, kflag, nk, ik, status, &j) ? 1 : 0;
+  for (int64_t o = b; o < e; ++o) {
+    const int64_t iq = by_k ? o : major, ik = by_k ? major : o;
+    c += pair_kept(kq[iq * nk + ik], kflag, nk, ik, status) ? 1 : 0;
   }
   part[t] = c;
   __syncthreads();
@@ -185,11 +168,12 @@ __global__ void __launch_bounds__(kPairThreads)
     part[t] += v;
     __syncthreads();
   }
-  int64_t pos = start[iq] + part[t] - c;
-  for (int64_t ik = b; ik < e; ++ik) {
-    int32_t j;
-    if (pair_kept(row, kflag, nk, ik, status, &j)) {
-      pair_k[pos] = (int32_t)ik;
+  int64_t pos = start[major] + part[t] - c;
+  for (int64_t o = b; o < e; ++o) {
+    const int64_t iq = by_k ? o : major, ik = by_k ? major : o;
+    const int32_t j = kq[iq * nk + ik];
+    if (pair_kept(j, kflag, nk, ik, status)) {
+      other[pos] = (int32_t)o;
       pair_kq[pos] = j;
       ++pos;
     }
@@ -270,9 +254,10 @@ ephw_status ephw_window_screen(ephw_kset* ks, const double* q, int64_t nq, const
 }
 
 ephw_status ephw_window_pairs(ephw_kset* ks, const int32_t* kq_index, int64_t nq, double e_lo, double e_hi,
-                             int64_t* pair_start, int32_t* pair_k, int32_t* pair_kq, int64_t capacity,
-                             void* stream) {
-  if (!ks || nq < 0 || (nq > 0 && !kq_index) || !pair_start || capacity < 0 || !(e_lo <= e_hi)) {
+                             int32_t order, int32_t* order_out, int64_t* pair_start, int32_t* pair_other,
+                             int32_t* pair_kq, int64_t capacity, void* stream) {
+  if (!ks || nq < 0 || (nq > 0 && !kq_index) || !pair_start || capacity < 0 || !(e_lo <= e_hi) ||
+      (order != EPHW_PAIRS_BY_Q && order != EPHW_PAIRS_BY_K && order != EPHW_PAIRS_AUTO)) {
     set_error("ephw_window_pairs: invalid argument");
     return EPHW_EINVAL;
   }
@@ -280,44 +265,73 @@ ephw_status ephw_window_pairs(ephw_kset* ks, const int32_t* kq_index, int64_t nq
   hipStream_t st = as_stream(stream);
   const int64_t nk = ks->nk;
   if (nq == 0 || nk == 0) {
-    for (int64_t i = 0; i <= nq; ++i) pair_start[i] = 0;
+    const int32_t ord = order == EPHW_PAIRS_BY_K ? EPHW_PAIRS_BY_K : EPHW_PAIRS_BY_Q;
+    const int64_t n = ord == EPHW_PAIRS_BY_K ? nk : nq;
+    for (int64_t i = 0; i <= n; ++i) pair_start[i] = 0;
+    if (order_out) *order_out = ord;
     return EPHW_OK;
   }
   if (nk > 0x7fffffff || nq > 0x7fffffff) {
     set_error("ephw_window_pairs: more than 2^31 points");
     return EPHW_EUNSUPPORTED;
   }
-  // workspace: start [nq + 1] and count [nq] (int64), k flags [nk] (int32)
-  EPHW_TRY(ws_need(s, WS_WINDOW, (size_t)(2 * nq + 1) * 8 + (size_t)nk * 4 + 256));
+  const bool want_q = order != EPHW_PAIRS_BY_K, want_k = order != EPHW_PAIRS_BY_Q;
+  // workspace: start [max(nq, nk) + 1], counts by q [nq] and by k [nk] (int64), k flags [nk] (int32)
+  const int64_t nmax = nq > nk ? nq : nk;
+  EPHW_TRY(ws_need(s, WS_WINDOW, (size_t)(nmax + 1 + nq + nk) * 8 + (size_t)nk * 4 + 256));
   char* base = static_cast<char*>(wsp(s, WS_WINDOW));
   int64_t* start = reinterpret_cast<int64_t*>(base);
-  int64_t* count = start + nq + 1;
-  int32_t* kflag = reinterpret_cast<int32_t*>(count + nq);
+  int64_t* cnt_q = start + nmax + 1;
+  int64_t* cnt_k = cnt_q + nq;
+  int32_t* kflag = reinterpret_cast<int32_t*>(cnt_k + nk);
   hipLaunchKernelGGL(band_window_flags_kernel, dim3((unsigned)grid_of(nk, 256)), dim3(256), 0, st, ks->eps, nk,
                      s->nw, e_lo, e_hi, kflag);
   EPHW_CHECK_LAUNCH();
-  hipLaunchKernelGGL(pair_count_kernel, dim3((unsigned)nq), dim3(kPairThreads), 0, st, kq_index, nk, kflag, count,
-                     s->ctx->status);
-  EPHW_CHECK_LAUNCH();
-  hipLaunchKernelGGL(exclusive_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, count, nq, start);
-  EPHW_CHECK_LAUNCH();
-  EPHW_HIP(hipMemcpyAsync(pair_start, start, (size_t)(nq + 1) * 8, hipMemcpyDeviceToHost, st));
+  if (want_q) {
+    hipLaunchKernelGGL(pair_count_kernel, dim3((unsigned)nq), dim3(kPairThreads), 0, st, kq_index, nq, nk, kflag, 0,
+                       cnt_q, s->ctx->status);
+    EPHW_CHECK_LAUNCH();
+  }
+  if (want_k) {
+    hipLaunchKernelGGL(pair_count_kernel, dim3((unsigned)nk), dim3(kPairThreads), 0, st, kq_index, nq, nk, kflag, 1,
+                       cnt_k, s->ctx->status);
+    EPHW_CHECK_LAUNCH();
+  }
+  std::vector<int64_t> hq(want_q ? nq : 0), hk(want_k ? nk : 0);
+  if (want_q) EPHW_HIP(hipMemcpyAsync(hq.data(), cnt_q, (size_t)nq * 8, hipMemcpyDeviceToHost, st));
+  if (want_k) EPHW_HIP(hipMemcpyAsync(hk.data(), cnt_k, (size_t)nk * 8, hipMemcpyDeviceToHost, st));
   EPHW_HIP(hipStreamSynchronize(st));
-  const int64_t total = pair_start[nq];
+  // the cheaper nesting order (see ephw_interpolate_pairs): group by the
+  // index with fewer points that own a pair
+  int32_t ord = order;
+  if (order == EPHW_PAIRS_AUTO) {
+    int64_t aq = 0, ak = 0;
+    for (int64_t c : hq) aq += c > 0;
+    for (int64_t c : hk) ak += c > 0;
+    ord = ak < aq ? EPHW_PAIRS_BY_K : EPHW_PAIRS_BY_Q;
+  }
+  if (order_out) *order_out = ord;
+  const std::vector<int64_t>& cnt = ord == EPHW_PAIRS_BY_K ? hk : hq;
+  const int64_t n = (int64_t)cnt.size();
+  pair_start[0] = 0;
+  for (int64_t i = 0; i < n; ++i) pair_start[i + 1] = pair_start[i] + cnt[i];
+  const int64_t total = pair_start[n];
   if (total > capacity) {
     set_error("ephw_window_pairs: " + std::to_string(total) + " pairs kept, more than the capacity of " +
               std::to_string(capacity) + " (pair_start holds the counts)");
     return EPHW_EINVAL;
   }
-  if (total > 0) {
-    if (!pair_k || !pair_kq) {
-      set_error("ephw_window_pairs: pair_k and pair_kq are required when pairs are kept");
-      return EPHW_EINVAL;
-    }
-    hipLaunchKernelGGL(pair_fill_kernel, dim3((unsigned)nq), dim3(kPairThreads), 0, st, kq_index, nk, kflag, start,
-                       pair_k, pair_kq, s->ctx->status);
-    EPHW_CHECK_LAUNCH();
+  if (total == 0) return EPHW_OK;
+  if (!pair_other || !pair_kq) {
+    set_error("ephw_window_pairs: pair_other and pair_kq are required when pairs are kept");
+    return EPHW_EINVAL;
   }
+  EPHW_HIP(hipMemcpyAsync(start, pair_start, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, st));
+  hipLaunchKernelGGL(pair_fill_kernel, dim3((unsigned)n), dim3(kPairThreads), 0, st, kq_index, nq, nk, kflag,
+                     ord == EPHW_PAIRS_BY_K ? 1 : 0, start, pair_other, pair_kq, s->ctx->status);
+  EPHW_CHECK_LAUNCH();
+  // the offsets were copied from the caller's host array: finish before returning
+  EPHW_HIP(hipStreamSynchronize(st));
   return EPHW_OK;
 }
 

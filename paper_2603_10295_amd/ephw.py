@@ -20,6 +20,7 @@ LIB_PATH = os.environ.get("EPHW_LIB", os.path.join(_HERE, "libephw.so"))
 # status codes, precisions, flags (mirror include/ephw.h)
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, EUNSUPPORTED, EINDEX = range(7)
 FP64, FP32, FP32_COMP = 0, 1, 2
+PAIRS_BY_Q, PAIRS_BY_K, PAIRS_AUTO = 0, 1, -1
 C128, C64 = 0, 1
 OUT_G, OUT_BAND_SUM, OUT_LOSS, OUT_WANNIER = 1, 2, 4, 8
 
@@ -114,8 +115,8 @@ def lib() -> ctypes.CDLL:
                            ctypes.c_double, ctypes.c_double, i64, vp, vp],
         "ephw_window_screen": [vp, vp, i64, vp, ctypes.c_double, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_int64),
                                vp, ctypes.POINTER(ctypes.c_int64), vp, vp, vp],
-        "ephw_window_pairs": [vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp, vp, i64, vp],
-        "ephw_interpolate_pairs": [vp, vp, i64, vp, vp, vp, i64, i32, u32, vp, vp, vp, u64, vp],
+        "ephw_window_pairs": [vp, vp, i64, ctypes.c_double, ctypes.c_double, i32, vp, vp, vp, vp, i64, vp],
+        "ephw_interpolate_pairs": [vp, vp, i64, i32, vp, vp, vp, i64, i32, u32, vp, vp, vp, u64, vp],
         "ephw_set_q_batch": [vp, i32],
         "ephw_set_k_tile": [vp, i32],
         "ephw_loss_backward": [vp, vp, i64, vp, i64, u64, vp, vp, vp, vp, vp],
@@ -380,45 +381,50 @@ def window_screen(ks: KSet, q, kq_index, e_lo: float, e_hi: float, k_out, q_out,
     return nk.value, nq.value
 
 
-def window_pairs(ks: KSet, kq_index, e_lo: float, e_hi: float, pair_k=None, pair_kq=None, stream=None):
+def window_pairs(ks: KSet, kq_index, e_lo: float, e_hi: float, order: int = PAIRS_AUTO, pair_other=None,
+                 pair_kq=None, stream=None):
     """Kept (k, q) pairs of an energy window as CSR lists (see
-    ephw_window_pairs).  Returns (pair_start, pair_k, pair_kq): pair_start a
-    host int64 array of nq + 1 offsets, the other two int32 device tensors of
-    the kept pairs (allocated here when not given or too small).
-    Synchronises the stream."""
+    ephw_window_pairs).  Returns (order, pair_start, pair_other, pair_kq):
+    the grouping used, a host int64 array of group offsets, and int32 device
+    tensors (the other index of each pair, the k+q index), allocated here when
+    not given or too small.  Synchronises the stream."""
     import numpy as np
     import torch
     nq = kq_index.shape[0]
-    start = np.zeros(nq + 1, dtype=np.int64)
-    cap = 0 if pair_k is None else min(pair_k.numel(), pair_kq.numel())
-    st = lib().ephw_window_pairs(ks.handle, _ptr(kq_index), nq, float(e_lo), float(e_hi),
-                                 start.ctypes.data_as(ctypes.c_void_p), _ptr(pair_k), _ptr(pair_kq), cap,
-                                 _stream(stream))
-    total = int(start[nq])
+    start = np.zeros(max(nq, ks.nk) + 1, dtype=np.int64)
+    cap = 0 if pair_other is None else min(pair_other.numel(), pair_kq.numel())
+    used = ctypes.c_int32(-2)
+
+    def call(cap_, po, pkq):
+        return lib().ephw_window_pairs(ks.handle, _ptr(kq_index), nq, float(e_lo), float(e_hi), int(order),
+                                       ctypes.byref(used), start.ctypes.data_as(ctypes.c_void_p), _ptr(po),
+                                       _ptr(pkq), cap_, _stream(stream))
+    st = call(cap, pair_other, pair_kq)
+    n = ks.nk if used.value == PAIRS_BY_K else nq
+    total = int(start[n])
     if st == EINVAL and total > cap:
-        pair_k = torch.empty(max(total, 1), dtype=torch.int32, device=kq_index.device)
+        pair_other = torch.empty(max(total, 1), dtype=torch.int32, device=kq_index.device)
         pair_kq = torch.empty(max(total, 1), dtype=torch.int32, device=kq_index.device)
-        st = lib().ephw_window_pairs(ks.handle, _ptr(kq_index), nq, float(e_lo), float(e_hi),
-                                     start.ctypes.data_as(ctypes.c_void_p), _ptr(pair_k), _ptr(pair_kq), total,
-                                     _stream(stream))
+        st = call(total, pair_other, pair_kq)
     _check(st, "ephw_window_pairs")
-    if pair_k is None:
-        pair_k = torch.empty(0, dtype=torch.int32, device=kq_index.device)
+    if pair_other is None:
+        pair_other = torch.empty(0, dtype=torch.int32, device=kq_index.device)
         pair_kq = torch.empty(0, dtype=torch.int32, device=kq_index.device)
-    return start, pair_k, pair_kq
+    return used.value, start[:n + 1].copy(), pair_other, pair_kq
 
 
-def interpolate_pairs(ks: KSet, q, pair_start, pair_k, pair_kq, *, q_offset: int = 0, flags: int = OUT_G,
-                      g_out=None, band_sum=None, loss=None, loss_seed: int = 0, stream=None):
+def interpolate_pairs(ks: KSet, q, order: int, pair_start, pair_other, pair_kq, *, q_offset: int = 0,
+                      flags: int = OUT_G, g_out=None, band_sum=None, loss=None, loss_seed: int = 0, stream=None):
     """Eq. (7) on the kept pairs of a CSR pair list (see ephw_interpolate_pairs);
-    pair_start is a host int64 array of q.shape[0] + 1 offsets."""
+    pair_start is a host int64 array of group offsets (nq + 1 by q, nk + 1 by k)."""
     import numpy as np
     import torch
     start = np.ascontiguousarray(pair_start, dtype=np.int64)
-    if start.shape != (q.shape[0] + 1,):
-        raise ValueError(f"pair_start must hold nq + 1 = {q.shape[0] + 1} offsets, got {start.shape}")
+    n = q.shape[0] if order == PAIRS_BY_Q else ks.nk
+    if start.shape != (n + 1,):
+        raise ValueError(f"pair_start must hold {n + 1} offsets for this grouping, got {start.shape}")
     npairs = int(start[-1])
-    for name, t in (("pair_k", pair_k), ("pair_kq", pair_kq)):
+    for name, t in (("pair_other", pair_other), ("pair_kq", pair_kq)):
         if t.dtype != torch.int32 or t.numel() < npairs:
             raise ValueError(f"{name} must be int32 with at least {npairs} entries")
     s = ks.sys
@@ -428,9 +434,10 @@ def interpolate_pairs(ks: KSet, q, pair_start, pair_k, pair_kq, *, q_offset: int
             raise ValueError(f"g_out must be {want} [>= {npairs}][{s.nm}][{s.nw}][{s.nw}]")
     if band_sum is not None and (band_sum.dtype != torch.float64 or band_sum.numel() < npairs * s.nm):
         raise ValueError(f"band_sum must be float64 with at least {npairs * s.nm} entries")
-    _check(lib().ephw_interpolate_pairs(ks.handle, _ptr(q), q.shape[0], start.ctypes.data_as(ctypes.c_void_p),
-                                        _ptr(pair_k), _ptr(pair_kq), int(q_offset), ks.prec, int(flags),
-                                        _ptr(g_out), _ptr(band_sum), _ptr(loss), int(loss_seed), _stream(stream)),
+    _check(lib().ephw_interpolate_pairs(ks.handle, _ptr(q), q.shape[0], int(order),
+                                        start.ctypes.data_as(ctypes.c_void_p), _ptr(pair_other), _ptr(pair_kq),
+                                        int(q_offset), ks.prec, int(flags), _ptr(g_out), _ptr(band_sum), _ptr(loss),
+                                        int(loss_seed), _stream(stream)),
            "ephw_interpolate_pairs")
 
 

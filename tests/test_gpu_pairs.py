@@ -52,24 +52,63 @@ def window_case(prec, seed=71, m=(4, 4, 2), frac=0.4):
 
 
 @pytest.mark.parametrize("prec", [0, 1])
-def test_window_pairs_match_the_oracle_window(run, prec):
+@pytest.mark.parametrize("order", [0, 1])
+def test_window_pairs_match_the_oracle_window(run, prec, order):
+    """Both groupings (by q: each q's k ascending; by k: each k's q ascending)."""
     from paper_2603_10295_amd import ephw
     from gpu_run import dev
     s, kg, qg, kqi, lo, hi, keep = window_case(prec)
     assert 0 < keep.sum() < keep.size and not keep.all(axis=1).any() and (~keep).all(axis=1).any()
     ks = ephw.KSet(run.system(s), dev(kg), prec)
-    start, pk, pkq = ephw.window_pairs(ks, dev(kqi), lo, hi)
+    used, start, other, pkq = ephw.window_pairs(ks, dev(kqi), lo, hi, order=order)
     run.ctx.check()
     ks.close()
-    want_start = np.concatenate([[0], np.cumsum(keep.sum(axis=1))])
+    assert used == order
+    if order == ephw.PAIRS_BY_Q:
+        want_start = np.concatenate([[0], np.cumsum(keep.sum(axis=1))])
+        iq, ik = np.nonzero(keep)             # q-major, ascending k within each q
+        want_other = ik
+    else:
+        want_start = np.concatenate([[0], np.cumsum(keep.sum(axis=0))])
+        ik, iq = np.nonzero(keep.T)           # k-major, ascending q within each k
+        want_other = iq
     np.testing.assert_array_equal(start, want_start)
-    iq, ik = np.nonzero(keep)                 # q-major, ascending k within each q
-    np.testing.assert_array_equal(pk.cpu().numpy()[:len(ik)], ik)
+    np.testing.assert_array_equal(other.cpu().numpy()[:len(ik)], want_other)
     np.testing.assert_array_equal(pkq.cpu().numpy()[:len(ik)], kqi[iq, ik])
 
 
+def test_window_pairs_auto_picks_the_smaller_grouping(run):
+    """A window that keeps few k (every q keeps some pair) is listed by k, and
+    with a k+q table that sends every k to one kept point the list is by q
+    when fewer q than k own pairs."""
+    from paper_2603_10295_amd import ephw
+    from gpu_run import dev
+    s, kg, qg, kqi, lo, hi, keep = window_case(0, frac=0.1)
+    ks = ephw.KSet(run.system(s), dev(kg), 0)
+    ak, aq = int(keep.any(axis=0).sum()), int(keep.any(axis=1).sum())
+    used, start, _, _ = ephw.window_pairs(ks, dev(kqi), lo, hi)
+    assert used == (ephw.PAIRS_BY_K if ak < aq else ephw.PAIRS_BY_Q), (ak, aq)
+    assert int(start[-1]) == int(keep.sum())
+    # k+q of q row j is always k point j: q row j keeps pairs only when k_j is
+    # active, so as many q as active k own pairs, each with every active k
+    eps = oracle.bands(s, kg)[0]
+    kact = np.any((eps >= lo) & (eps <= hi), axis=1)
+    tab = np.repeat(np.arange(len(kg), dtype=np.int32)[:, None], len(kg), axis=1)
+    tab_keep = kact[None, :] & kact[tab]
+    used2, start2, _, _ = ephw.window_pairs(ks, dev(tab), lo, hi)
+    ak2, aq2 = int(tab_keep.any(axis=0).sum()), int(tab_keep.any(axis=1).sum())
+    assert used2 == (ephw.PAIRS_BY_K if ak2 < aq2 else ephw.PAIRS_BY_Q), (ak2, aq2)
+    assert int(start2[-1]) == int(tab_keep.sum())
+    run.ctx.check()
+    ks.close()
+
+
 @pytest.mark.parametrize("prec", [0, 1])
-def test_interpolate_pairs_matches_full_path_and_oracle(run, prec):
+@pytest.mark.parametrize("order", [0, 1])
+def test_interpolate_pairs_matches_full_path_and_oracle(run, prec, order):
+    """Both nesting orders: by q (Eq. (9) first, the Re sum per q on its kept
+    k) and by k (the Re sum first, the Rp sum per k on its kept q, mode
+    vectors per pair)."""
     import torch
     from paper_2603_10295_amd import ephw
     from gpu_run import dev, cplx_dtype
@@ -77,13 +116,13 @@ def test_interpolate_pairs_matches_full_path_and_oracle(run, prec):
     nk, nq = len(kg), len(qg)
     sysh = run.system(s)
     ks = ephw.KSet(sysh, dev(kg), prec)
-    start, pk, pkq = ephw.window_pairs(ks, dev(kqi), lo, hi)
+    used, start, other, pkq = ephw.window_pairs(ks, dev(kqi), lo, hi, order=order)
     npairs = int(start[-1])
     q_off, seed = 5, 23
     g = torch.empty((npairs, s.nm, s.nw, s.nw), dtype=cplx_dtype(prec), device="cuda:0")
     t = torch.empty((npairs, s.nm), dtype=torch.float64, device="cuda:0")
     loss = torch.zeros(1, dtype=torch.float64, device="cuda:0")
-    ephw.interpolate_pairs(ks, dev(qg), start, pk, pkq, q_offset=q_off,
+    ephw.interpolate_pairs(ks, dev(qg), used, start, other, pkq, q_offset=q_off,
                            flags=ephw.OUT_G | ephw.OUT_BAND_SUM | ephw.OUT_LOSS, g_out=g, band_sum=t, loss=loss,
                            loss_seed=seed)
     # the full path on every pair of the same k-set
@@ -91,7 +130,10 @@ def test_interpolate_pairs_matches_full_path_and_oracle(run, prec):
     ephw.interpolate(ks, dev(qg), kq_index=dev(kqi), q_offset=q_off, flags=ephw.OUT_G, g_out=gf)
     run.ctx.check()
     ks.close()
-    iq, ik = np.nonzero(keep)
+    if order == ephw.PAIRS_BY_Q:
+        iq, ik = np.nonzero(keep)
+    else:
+        ik, iq = np.nonzero(keep.T)
     gp = g.cpu().numpy().astype(np.complex128)
     full = gf.cpu().numpy().astype(np.complex128)[iq, ik]
     err_full = float(np.abs(gp - full).max() / np.abs(full).max())
@@ -99,8 +141,8 @@ def test_interpolate_pairs_matches_full_path_and_oracle(run, prec):
     ref = oracle.interpolate(s, kg, qg, return_all=True)
     s_gpu = []
     s_ref = []
-    for p, (a, b) in enumerate(zip(iq, ik)):
-        s_gpu += oracle.block_sums(np.abs(gp[p])[None, None] ** 2, ref["eps_kq"][a, b][None, None],
+    for p_, (a, b) in enumerate(zip(iq, ik)):
+        s_gpu += oracle.block_sums(np.abs(gp[p_])[None, None] ** 2, ref["eps_kq"][a, b][None, None],
                                    ref["eps_k"][b][None], ref["lam"][a][None])
         s_ref += oracle.block_sums(np.abs(ref["ghat"][a, b])[None, None] ** 2, ref["eps_kq"][a, b][None, None],
                                    ref["eps_k"][b][None], ref["lam"][a][None])
@@ -109,17 +151,19 @@ def test_interpolate_pairs_matches_full_path_and_oracle(run, prec):
     t_err = float(np.abs(t.cpu().numpy() - t_ref).max() / np.abs(t_ref).max())
     l_ref = oracle.weighted_loss(ref["ghat"][iq, ik], seed, iq + q_off, ik, nk)
     l_err = abs(float(loss.cpu().numpy()[0]) - l_ref) / l_ref
-    print(f"pairs prec={prec}: {npairs} of {nq * nk}; vs full path {err_full:.2e}, block sums {norm:.2e}, "
-          f"band sums {t_err:.2e}, loss {l_err:.2e}")
-    tol_full = RTOL_W if prec == 0 else RTOL_32
+    print(f"pairs prec={prec} order={order}: {npairs} of {nq * nk}; vs full path {err_full:.2e}, "
+          f"block sums {norm:.2e}, band sums {t_err:.2e}, loss {l_err:.2e}")
+    # by q runs the full path's arithmetic; by k sums in the other order
+    tol_full = (RTOL_W if prec == 0 else RTOL_32) if order == 1 else (RTOL_W if prec == 0 else 1e-6)
     tol = RTOL_S if prec == 0 else RTOL_32
     assert err_full < tol_full and norm < tol and t_err < tol and l_err < tol
 
 
-def test_interpolate_pairs_edge_cases(run):
+@pytest.mark.parametrize("order", [0, 1])
+def test_interpolate_pairs_edge_cases(run, order):
     """Empty window (no pair: nothing enqueued, outputs untouched), a window
-    holding every pair (equal to the full path), ragged q batches (q_batch 3
-    over 32 q with empty q in between), the Wannier gauge, and invalid CSR
+    holding every pair (equal to the full path) in small chunks, the Wannier
+    gauge, groups without pairs between groups with pairs, and invalid CSR
     offsets refused on the host."""
     import torch
     from paper_2603_10295_amd import ephw
@@ -130,40 +174,44 @@ def test_interpolate_pairs_edge_cases(run):
     ks = ephw.KSet(sysh, dev(kg), 0)
     eps = oracle.bands(s, kg)[0]
     # empty window
-    start, pk, pkq = ephw.window_pairs(ks, dev(kqi), float(eps.max()) + 1.0, float(eps.max()) + 2.0)
+    used, start, other, pkq = ephw.window_pairs(ks, dev(kqi), float(eps.max()) + 1.0, float(eps.max()) + 2.0,
+                                                order=order)
     assert int(start[-1]) == 0 and not start.any()
     loss = torch.full((1,), 7.0, dtype=torch.float64, device="cuda:0")
-    ephw.interpolate_pairs(ks, dev(qg), start, pk, pkq, flags=ephw.OUT_LOSS, loss=loss)
+    ephw.interpolate_pairs(ks, dev(qg), used, start, other, pkq, flags=ephw.OUT_LOSS, loss=loss)
     run.ctx.check()
     assert float(loss.cpu()[0]) == 7.0
-    # every pair kept, ragged batches
-    start, pk, pkq = ephw.window_pairs(ks, dev(kqi), float(eps.min()) - 1.0, float(eps.max()) + 1.0)
+    # every pair kept; by q in batches of 3 q
+    used, start, other, pkq = ephw.window_pairs(ks, dev(kqi), float(eps.min()) - 1.0, float(eps.max()) + 1.0,
+                                                order=order)
     assert int(start[-1]) == nq * nk
     sysh.set_q_batch(3)
     g = torch.empty((nq * nk, s.nm, s.nw, s.nw), dtype=torch.complex128, device="cuda:0")
-    ephw.interpolate_pairs(ks, dev(qg), start, pk, pkq, flags=ephw.OUT_G, g_out=g)
+    ephw.interpolate_pairs(ks, dev(qg), used, start, other, pkq, flags=ephw.OUT_G, g_out=g)
     gw = torch.empty_like(g)
-    ephw.interpolate_pairs(ks, dev(qg), start, pk, pkq, flags=ephw.OUT_G | ephw.OUT_WANNIER, g_out=gw)
+    ephw.interpolate_pairs(ks, dev(qg), used, start, other, pkq, flags=ephw.OUT_G | ephw.OUT_WANNIER, g_out=gw)
     sysh.set_q_batch(0)
     gf = torch.empty((nq, nk, s.nm, s.nw, s.nw), dtype=torch.complex128, device="cuda:0")
     ephw.interpolate(ks, dev(qg), kq_index=dev(kqi), flags=ephw.OUT_G, g_out=gf)
     run.ctx.check()
-    full = gf.cpu().numpy().reshape(nq * nk, s.nm, s.nw, s.nw)
+    perm = (lambda a: a) if order == 0 else (lambda a: np.swapaxes(a, 0, 1))
+    full = perm(gf.cpu().numpy()).reshape(nq * nk, s.nm, s.nw, s.nw)
     assert np.abs(g.cpu().numpy() - full).max() < RTOL_W * np.abs(full).max()
     ref = oracle.interpolate(s, kg, qg, return_all=True)
-    gw_ref = ref["gw"]     # Eq. (9)-(10) sums before the mode and band rotations
-    np.testing.assert_allclose(gw.cpu().numpy().reshape(gw_ref.shape), gw_ref, rtol=0,
-                               atol=RTOL_W * np.abs(gw_ref).max())
-    # only q 1 and q 30 own pairs (every other q skipped)
-    start = np.zeros(nq + 1, dtype=np.int64)
+    gw_ref = perm(ref["gw"]).reshape(nq * nk, s.nm, s.nw, s.nw)   # sums before the mode and band rotations
+    np.testing.assert_allclose(gw.cpu().numpy(), gw_ref, rtol=0, atol=RTOL_W * np.abs(gw_ref).max())
+    # only groups 1 and 30 own pairs (every other group skipped)
+    n = nq if order == 0 else nk
+    start = np.zeros(n + 1, dtype=np.int64)
     start[2:] = 3
-    start[31:] = 3 + nk
-    sel_k = np.concatenate([[0, 5, 9], np.arange(nk)]).astype(np.int32)
-    sel_q = np.concatenate([[1, 1, 1], np.full(nk, 30)])
-    pk = dev(sel_k)
+    start[31:] = 3 + 32
+    sel_major = np.concatenate([[1, 1, 1], np.full(32, 30)])
+    sel_other = np.concatenate([[0, 5, 9], np.arange(32)]).astype(np.int32)
+    sel_q, sel_k = (sel_major, sel_other) if order == 0 else (sel_other, sel_major)
+    po = dev(sel_other)
     pkq = dev(kqi[sel_q, sel_k].astype(np.int32))
-    g2 = torch.empty((3 + nk, s.nm, s.nw, s.nw), dtype=torch.complex128, device="cuda:0")
-    ephw.interpolate_pairs(ks, dev(qg), start, pk, pkq, flags=ephw.OUT_G, g_out=g2)
+    g2 = torch.empty((35, s.nm, s.nw, s.nw), dtype=torch.complex128, device="cuda:0")
+    ephw.interpolate_pairs(ks, dev(qg), order, start, po, pkq, flags=ephw.OUT_G, g_out=g2)
     run.ctx.check()
     full = gf.cpu().numpy()[sel_q, sel_k]
     assert np.abs(g2.cpu().numpy() - full).max() < RTOL_W * np.abs(full).max()
@@ -171,9 +219,9 @@ def test_interpolate_pairs_edge_cases(run):
     bad = start.copy()
     bad[5] = 10
     with pytest.raises(ephw.EphwError):
-        ephw.interpolate_pairs(ks, dev(qg), bad, pk, pkq, flags=ephw.OUT_G, g_out=g2)
+        ephw.interpolate_pairs(ks, dev(qg), order, bad, po, pkq, flags=ephw.OUT_G, g_out=g2)
     bad = start.copy()
     bad[0] = 1
     with pytest.raises(ephw.EphwError):
-        ephw.interpolate_pairs(ks, dev(qg), bad, pk, pkq, flags=ephw.OUT_G, g_out=g2)
+        ephw.interpolate_pairs(ks, dev(qg), order, bad, po, pkq, flags=ephw.OUT_G, g_out=g2)
     ks.close()
