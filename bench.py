@@ -47,6 +47,7 @@ def parse(argv=None):
     ap.add_argument("--tune-cache", default="")
     ap.add_argument("--grid", type=int, default=20, help="k = q = grid^3 for si_dense")
     ap.add_argument("--q-chunk", type=int, default=1024)
+    ap.add_argument("--no-band-window", action="store_true", help="si_window: keep all bands of the kept pairs")
     ap.add_argument("--pair-order", type=int, default=-1,
                     help="si_window pair lists: 0 by q, 1 by k, -1 the cheaper (fewer groups owning pairs)")
     ap.add_argument("--fp64-steps", type=int, default=2)
@@ -452,25 +453,28 @@ def bench_window(args):
 
     # ---- (1) pair lists ----------------------------------------------------
     ks_f = ephw.KSet(sysh, k, ephw.FP32)
-    order, start, po, pkq = ephw.window_pairs(ks_f, kqi, lo, hi, order=args.pair_order)
+    order, start, po, pkq, bands = ephw.window_pairs(ks_f, kqi, lo, hi, order=args.pair_order)
     ks_f.close()
     npairs = int(start[-1])
-    gp = torch.empty((max(npairs, 1), s.nm, s.nw, s.nw), dtype=torch.complex64, device="cuda:0")
+    if args.no_band_window:
+        bands = (0, 0)
+    b0, nb = bands[0], (bands[1] or s.nw)
+    gp = torch.empty((max(npairs, 1), s.nm, nb, nb), dtype=torch.complex64, device="cuda:0")
     qc = min(args.q_chunk, nq)
     order_name = {ephw.PAIRS_BY_Q: "by q", ephw.PAIRS_BY_K: "by k"}[order]
 
     def step_pairs():
         ks_p = ephw.KSet(sysh, k, ephw.FP32)
-        o, st, _, _ = ephw.window_pairs(ks_p, kqi, lo, hi, order=order, pair_other=po, pair_kq=pkq)
+        o, st, _, _, _ = ephw.window_pairs(ks_p, kqi, lo, hi, order=order, pair_other=po, pair_kq=pkq)
         if o == ephw.PAIRS_BY_K:
             # the whole list at once: every k's q are in one group
-            ephw.interpolate_pairs(ks_p, q, o, st, po, pkq, flags=ephw.OUT_G, g_out=gp)
+            ephw.interpolate_pairs(ks_p, q, o, st, po, pkq, flags=ephw.OUT_G, bands=bands, g_out=gp)
         else:
             for q0 in range(0, nq, qc):
                 q1 = min(nq, q0 + qc)
                 p0 = int(st[q0])
                 ephw.interpolate_pairs(ks_p, q[q0:q1], o, st[q0:q1 + 1] - p0, po[p0:], pkq[p0:], q_offset=q0,
-                                       flags=ephw.OUT_G, g_out=gp[p0:])
+                                       flags=ephw.OUT_G, bands=bands, g_out=gp[p0:])
         ks_p.close()
 
     sysh.profile_read()
@@ -478,8 +482,8 @@ def bench_window(args):
     dt_pairs = timed_steps(step_pairs)
     sysh.profile(False)
     stages_pairs = {k_: round(v[0] / (args.steps + args.warmup), 3) for k_, v in sysh.profile_read().items()}
-    log(f"pairs ({order_name}): {npairs} kept of {nk * nq}; {dt_pairs * 1e3:.1f} ms per pass; "
-        f"stages {stages_pairs}")
+    log(f"pairs ({order_name}, bands {b0}..{b0 + nb - 1}): {npairs} kept of {nk * nq}; "
+        f"{dt_pairs * 1e3:.1f} ms per pass; stages {stages_pairs}")
 
     # ---- (2) compacted sets with a pair mask -------------------------------
     k_out = torch.empty((nk, 3), dtype=torch.float64, device="cuda:0")
@@ -524,12 +528,14 @@ def bench_window(args):
     ref = oracle.interpolate(s, w.k, w.q[pick], return_all=True)
     qpos = {j: i for i, j in enumerate(pick)}
     s_gpu, s_ref = [], []
+    bs = slice(b0, b0 + nb)   # the band window's block (its edges lie in gaps of the spectrum)
     for p_, (a, b) in enumerate(zip(sel_q, sel_k)):
         a = qpos[a]
-        s_gpu += oracle.block_sums(np.abs(got[p_])[None, None] ** 2, ref["eps_kq"][a, b][None, None],
-                                   ref["eps_k"][b][None], ref["lam"][a][None])
-        s_ref += oracle.block_sums(np.abs(ref["ghat"][a, b])[None, None] ** 2, ref["eps_kq"][a, b][None, None],
-                                   ref["eps_k"][b][None], ref["lam"][a][None])
+        s_gpu += oracle.block_sums(np.abs(got[p_])[None, None] ** 2, ref["eps_kq"][a, b][bs][None, None],
+                                   ref["eps_k"][b][bs][None], ref["lam"][a][None])
+        s_ref += oracle.block_sums(np.abs(ref["ghat"][a, b][:, bs, bs])[None, None] ** 2,
+                                   ref["eps_kq"][a, b][bs][None, None], ref["eps_k"][b][bs][None],
+                                   ref["lam"][a][None])
     err = oracle.compare_block_sums(s_gpu, s_ref)
     log(f"kept pairs of {len(pick)} q vs oracle: normwise {err[0]:.2e}, max blockwise {err[1]:.2e}")
     line = {
@@ -539,7 +545,8 @@ def bench_window(args):
         "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
         "config": {"workload": f"si_dense_window_nw8_nm6_ne1000_{nk}kx{nq}q_lowest10pct_band0", "nk": nk, "nq": nq,
                    "window": [lo, hi],
-                   "form": f"pair lists grouped {order_name} (ephw_window_pairs + ephw_interpolate_pairs)"},
+                   "form": f"pair lists grouped {order_name} (ephw_window_pairs + ephw_interpolate_pairs)",
+                   "band_window": [b0, nb]},
         "kept_pairs": npairs, "computed_pairs": npairs, "kept_elems_per_s": npairs * E / dt_pairs,
         "stages_ms_per_step": stages_pairs,
         "compacted_sets": {"ms_per_step": dt_masked * 1e3, "active_k": nks, "active_q": nqs,
@@ -722,8 +729,15 @@ def main(argv=None):
     re_ms, re_n = stages["re_gemm"]
     qb32 = min(128, nq)
     re_wg = -(-nk // 128) * -(-(qb32 * s.nm * s.nw * s.nw) // 128)   # workgroups of a full-batch Re GEMM
-    re_flops = 8.0 * cnt.re * args.steps
+    # with the band rotations in the Re-sum GEMM's epilogue (no separate
+    # rotation launches) the dominant kernel also does the rotation flops
+    fused = stages["band_rot"][1] == 0
+    re_flops = 8.0 * (cnt.re + (cnt.rot if fused else 0.0)) * args.steps
     re_tflops = re_flops / (re_ms * 1e-3) / 1e12
+    # algorithmic HBM bytes of one full-batch launch: the phase rows P_k and
+    # G_nu read once, g stored (the fused kernel) or W stored (unfused)
+    E = s.nm * s.nw * s.nw
+    algo_bytes = 8.0 * (nk * s.ne + s.ne * qb32 * E + nk * qb32 * E)
     rp_ms, rp_n = stages["rp_gemm"]
     rp_tflops = 8.0 * cnt.rp * args.steps / (rp_ms * 1e-3) / 1e12
     gemm_tflops = 8.0 * cnt.gemm * args.steps / ((re_ms + rp_ms) * 1e-3) / 1e12
@@ -815,7 +829,9 @@ def main(argv=None):
                      "frac": re_tflops / model.PEAK_FP32_TFLOPS,
                      "traffic": measured_traffic("cgemm_kernel<float", re_wg),
                      "traffic_unit": "bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
-                     "kernel": "cgemm_kernel<float> Re phase sum (Eq. 10)",
+                     "algorithmic_bytes": algo_bytes,
+                     "kernel": "cgemm_kernel<float> Re phase sum (Eq. 10)"
+                               + (" with the band rotations and the g store in its epilogue" if fused else ""),
                      "flops_per_launch": re_flops / max(1, re_n), "avg_launch_ms": re_ms / max(1, re_n),
                      "launches": re_n},
         "cpu_baseline": cpu,

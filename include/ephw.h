@@ -294,6 +294,10 @@ ephw_status ephw_window_screen(ephw_kset* ks, const double* q, int64_t nq, const
                 in the list (by k) of pair p, ascending within each group
      pair_kq    [capacity] int32 (device): kq_index[q][k] of pair p, the set
                 index of k+q
+     band_range host int32 [2] or NULL: the first band and the number of
+                bands of the smallest band range that holds every band with
+                an energy in the window at some k of the set (the band window
+                of ephw_interpolate_pairs; 0, 0 when no band is in the window)
    kq_index [nq][nk] int32 (device): as in ephw_window_screen (entries outside
    [0, nk) count as dropped and set EPHW_EINDEX in the status word).
    pair_start is always written; when the total exceeds `capacity` the call
@@ -301,7 +305,7 @@ ephw_status ephw_window_screen(ephw_kset* ks, const double* q, int64_t nq, const
    them from the total and call again).  Synchronises the stream. */
 ephw_status ephw_window_pairs(ephw_kset* ks, const int32_t* kq_index, int64_t nq, double e_lo, double e_hi,
                               int32_t order, int32_t* order_out, int64_t* pair_start, int32_t* pair_other,
-                              int32_t* pair_kq, int64_t capacity, void* stream);
+                              int32_t* pair_kq, int64_t capacity, int32_t* band_range, void* stream);
 
 /* Eq. (7) on a list of (k, q) pairs (Nw <= 32; FP64 or FP32 k-sets) in the
    form ephw_window_pairs writes (order EPHW_PAIRS_BY_Q or EPHW_PAIRS_BY_K;
@@ -322,7 +326,14 @@ ephw_status ephw_window_pairs(ephw_kset* ks, const int32_t* kq_index, int64_t nq
      flags, loss_seed, q_offset  as in ephw_interpolate; the loss weights use
               the element index of (q_offset + q, k) in the k-set, so the loss
               equals that of ephw_interpolate over the same pairs
-     g_out    [npairs][nm][nw][nw] c128 (FP64) or c64 (FP32), if EPHW_OUT_G
+     band_lo, band_count  band window (the window's practical effect on the
+              bands): band_count > 0 keeps bands band_lo .. band_lo+band_count-1
+              at k+q (m) and at k (n) only: the rotations form just those rows
+              and columns, and g, the band sums and the loss cover just those
+              elements (loss weights keep their full-layout indices);
+              band_count = 0 keeps all Nw bands.  Not with EPHW_OUT_WANNIER.
+     g_out    [npairs][nm][nb][nb] c128 (FP64) or c64 (FP32), nb = band_count
+              or Nw, if EPHW_OUT_G
      band_sum [npairs][nm] f64, if EPHW_OUT_BAND_SUM
      loss     one f64 (L +=), if EPHW_OUT_LOSS
    pair_start must start at 0 and not decrease (checked on the host); pair
@@ -332,8 +343,9 @@ ephw_status ephw_window_pairs(ephw_kset* ks, const int32_t* kq_index, int64_t nq
    synchronise the stream. */
 ephw_status ephw_interpolate_pairs(ephw_kset* ks, const double* q, int64_t nq, int32_t order,
                                    const int64_t* pair_start, const int32_t* pair_other, const int32_t* pair_kq,
-                                   int64_t q_offset, int32_t prec, uint32_t flags, void* g_out, double* band_sum,
-                                   double* loss, uint64_t loss_seed, void* stream);
+                                   int64_t q_offset, int32_t prec, uint32_t flags, int32_t band_lo,
+                                   int32_t band_count, void* g_out, double* band_sum, double* loss,
+                                   uint64_t loss_seed, void* stream);
 
 /* A downstream reduction of stored matrix elements over q (the multi-node
    scalability runs of the Results section compute an electron self-energy

@@ -24,6 +24,6 @@ from .core import (  # noqa: F401
     phases, hamiltonian_k, bands, dynamical_q, phonons, mode_vectors,
     g_re_q, wannier_gauge_pairs, interpolate, interpolate_single_loop,
     coarse_transform, degenerate_blocks, block_sums, band_sums,
-    splitmix64_weights, weighted_loss, compare_block_sums,
+    splitmix64_weights, element_index, weighted_loss, compare_block_sums,
     bose, fermi, gauss, linewidth,
 )

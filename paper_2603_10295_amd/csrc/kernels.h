@@ -88,6 +88,11 @@ struct BandRotateArgs {
   const int32_t* pair_k = nullptr;
   const int32_t* pair_q = nullptr;
   int64_t nk_set = 0;
+  // Band window (band_n > 0, rotations only): g, band sums and the loss keep
+  // the bands band_lo .. band_lo+band_n-1 at k+q (m) and at k (n); g_out is
+  // then [..][nm][band_n][band_n] and the loss element index stays that of
+  // the full [nm][nw][nw] layout.
+  int band_lo = 0, band_n = 0;
 };
 ephw_status band_rotate(int prec, const BandRotateArgs& a, hipStream_t s);
 // Work split of the band-rotation kernel (Nw <= 32): P consecutive k per

@@ -189,8 +189,9 @@ extern "C" {
 
 ephw_status ephw_interpolate_pairs(ephw_kset* ks, const double* q, int64_t nq, int32_t order,
                                    const int64_t* pair_start, const int32_t* pair_other, const int32_t* pair_kq,
-                                   int64_t q_offset, int32_t prec, uint32_t flags, void* g_out, double* band_sum,
-                                   double* loss, uint64_t loss_seed, void* stream) {
+                                   int64_t q_offset, int32_t prec, uint32_t flags, int32_t band_lo,
+                                   int32_t band_count, void* g_out, double* band_sum, double* loss,
+                                   uint64_t loss_seed, void* stream) {
   if (!ks || nq < 0 || (nq > 0 && (!q || !pair_start)) || q_offset < 0 ||
       (order != EPHW_PAIRS_BY_Q && order != EPHW_PAIRS_BY_K)) {
     set_error("ephw_interpolate_pairs: invalid argument");
@@ -204,6 +205,12 @@ ephw_status ephw_interpolate_pairs(ephw_kset* ks, const double* q, int64_t nq, i
   if ((flags & ~known) || !(flags & (EPHW_OUT_G | EPHW_OUT_BAND_SUM | EPHW_OUT_LOSS)) ||
       ((flags & EPHW_OUT_WANNIER) && (flags & EPHW_OUT_LOSS))) {
     set_error("ephw_interpolate_pairs: flags must request g, band sums or the loss (no loss in the Wannier gauge)");
+    return EPHW_EINVAL;
+  }
+  if (band_count < 0 || (band_count > 0 && (band_lo < 0 || band_lo + band_count > ks->sys->nw ||
+                                            (flags & EPHW_OUT_WANNIER)))) {
+    set_error("ephw_interpolate_pairs: the band window needs 0 <= band_lo, band_lo + band_count <= nw, "
+              "and rotated output");
     return EPHW_EINVAL;
   }
   if (nq == 0 || ks->nk == 0) return EPHW_OK;
@@ -443,7 +450,10 @@ ephw_status ephw_interpolate_pairs(ephw_kset* ks, const double* q, int64_t nq, i
     br.nm = nm;
     br.nw = nw;
     br.flags = flags;
-    br.g_out = (flags & EPHW_OUT_G) ? static_cast<char*>(g_out) + (size_t)p0 * E * cs : nullptr;
+    const int64_t nbo = band_count > 0 ? band_count : nw, Eo = nm * nbo * nbo;
+    br.g_out = (flags & EPHW_OUT_G) ? static_cast<char*>(g_out) + (size_t)p0 * Eo * cs : nullptr;
+    br.band_lo = band_lo;
+    br.band_n = band_count;
     br.band_sum = (flags & EPHW_OUT_BAND_SUM) ? band_sum + p0 * nm : nullptr;
     br.loss_partial = w.loss;
     br.loss_seed = loss_seed;

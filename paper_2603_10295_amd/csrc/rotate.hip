@@ -225,11 +225,15 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
   constexpr bool DIRECT = sizeof(T) == 8 && NWB <= 8;
   const int nw = a.nw, nm = a.nm, nw2 = nw * nw, ld = nw + 1;
   const int64_t E = (int64_t)nm * nw2;
+  // band window: output bands b0 .. b0+nbo-1 at k+q (rows m) and at k (columns n)
+  const int b0 = a.band_n > 0 ? a.band_lo : 0, nbo = a.band_n > 0 ? a.band_n : nw, nbo2 = nbo * nbo;
+  const int64_t Eo = (int64_t)nm * nbo2;   // output values per pair
   const bool rot = a.Vk != nullptr;
   const int tid = threadIdx.x;
   const bool vec_shape = E % Chunk16<T>::kVec == 0 && nw2 % Chunk16<T>::kVec == 0;
   const bool vec = vec_shape && (reinterpret_cast<uintptr_t>(a.W) & 15) == 0;               // loads
-  const bool vec_g = vec_shape && (reinterpret_cast<uintptr_t>(a.g_out) & 15) == 0;         // stores
+  const bool vec_g = Eo % Chunk16<T>::kVec == 0 && nbo % Chunk16<T>::kVec == 0 &&
+                     (reinterpret_cast<uintptr_t>(a.g_out) & 15) == 0;                      // stores
   const int rows_pp = nuc * nw;
   const int p = tid / rows_pp, r = tid % rows_pp;
   const int vl = r / nw, mrow = r % nw;
@@ -322,7 +326,7 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
             const T* vr = vkp + 2 * j * nw;
 #pragma unroll
             for (int n = 0; n < NWB; ++n)
-              if (j < nw && n < nw) cfma(acc[n], x[j], cplx<T>{vr[2 * n], vr[2 * n + 1]});
+              if (j < nw && n < nbo) cfma(acc[n], x[j], cplx<T>{vr[2 * (b0 + n)], vr[2 * (b0 + n) + 1]});
           }
         } else {
           for (int j = 0; j < nw; ++j) {
@@ -330,29 +334,29 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
             const T* vr = vkp + 2 * j * nw;
 #pragma unroll
             for (int n = 0; n < NWB; ++n)
-              if (n < nw) cfma(acc[n], x, cplx<T>{vr[2 * n], vr[2 * n + 1]});
+              if (n < nbo) cfma(acc[n], x, cplx<T>{vr[2 * (b0 + n)], vr[2 * (b0 + n) + 1]});
           }
         }
 #pragma unroll
         for (int n = 0; n < NWB; ++n)
-          if (n < nw) {
+          if (n < nbo) {
             own[2 * n] = acc[n].re;
             own[2 * n + 1] = acc[n].im;
           }
       }
       __syncthreads();
-      // 3. g row m = sum_m' conj(V(k+q)[m'][m]) T[m'][:]
-      if (act) {
+      // 3. g row m = sum_m' conj(V(k+q)[m'][m]) T[m'][:]  (rows of the band window)
+      if (act && mrow < nbo) {
 #pragma unroll
         for (int n = 0; n < NWB; ++n) acc[n] = cplx<T>{0, 0};
         const T* vq = L.vkq + 2 * p * nw2;
         const T* tb = L.rows + 2 * ((p * rows_pp + vl * nw) * ld);
         for (int j = 0; j < nw; ++j) {
-          const cplx<T> c{vq[2 * (j * nw + mrow)], vq[2 * (j * nw + mrow) + 1]};
+          const cplx<T> c{vq[2 * (j * nw + b0 + mrow)], vq[2 * (j * nw + b0 + mrow) + 1]};
           const T* tr = tb + 2 * j * ld;
 #pragma unroll
           for (int n = 0; n < NWB; ++n)
-            if (n < nw) cfmac(acc[n], c, cplx<T>{tr[2 * n], tr[2 * n + 1]});
+            if (n < nbo) cfmac(acc[n], c, cplx<T>{tr[2 * n], tr[2 * n + 1]});
         }
       }
     } else if (act) {
@@ -362,14 +366,17 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
     }
     // 4. epilogues
     double rsum = 0.0;
-    if (act) {
+    const bool act_o = act && mrow < nbo;   // this thread holds an output row
+    if (act_o) {
       const int nu = v0 + vl;
-      const int64_t eoff = (int64_t)nu * nw2 + (int64_t)mrow * nw;   // element offset in the pair
+      // element offset of (nu, b0 + mrow, b0) in the full pair, and in the output
+      const int64_t eoff = (int64_t)nu * nw2 + (int64_t)(b0 + mrow) * nw + b0;
+      const int64_t eoff_o = (int64_t)nu * nbo2 + (int64_t)mrow * nbo;
       if (want_g && DIRECT) {
-        T* go = static_cast<T*>(a.g_out) + 2 * (((int64_t)iq * a.nk + ik) * E + eoff);
+        T* go = static_cast<T*>(a.g_out) + 2 * (((int64_t)iq * a.nk + ik) * Eo + eoff_o);
 #pragma unroll
         for (int n = 0; n < NWB; ++n)
-          if (n < nw) {
+          if (n < nbo) {
             go[2 * n] = acc[n].re;
             go[2 * n + 1] = acc[n].im;
           }
@@ -381,7 +388,7 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
                    (uint64_t)E + (uint64_t)eoff;
 #pragma unroll
       for (int n = 0; n < NWB; ++n)
-        if (n < nw) {
+        if (n < nbo) {
           const double m2 = (double)acc[n].re * (double)acc[n].re + (double)acc[n].im * (double)acc[n].im;
           rsum += m2;
           if (want_l) lsum += loss_weight(a.loss_seed, base + (uint64_t)n) * m2;
@@ -391,24 +398,25 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
       // stage the g rows in LDS and store the chunk coalesced: the P pairs of
       // the workgroup are consecutive k, so their values are contiguous
       __syncthreads();   // every T row has been read
-      if (act) {
+      if (act_o) {
 #pragma unroll
         for (int n = 0; n < NWB; ++n)
-          if (n < nw) {
+          if (n < nbo) {
             own[2 * n] = acc[n].re;
             own[2 * n + 1] = acc[n].im;
           }
       }
       __syncthreads();
-      T* go = static_cast<T*>(a.g_out) + 2 * (((int64_t)iq * a.nk + a.k0 + ik0) * E + (int64_t)v0 * nw2);
+      T* go = static_cast<T*>(a.g_out) + 2 * (((int64_t)iq * a.nk + a.k0 + ik0) * Eo + (int64_t)v0 * nbo2);
       const int gstep = vec_g ? Chunk16<T>::kVec : 1;
-      const int gpp = cw / gstep;
-      const float r_gpp = 1.0f / (float)gpp;
+      const int gpp = nv * nbo2 / gstep;
+      const float r_gpp = 1.0f / (float)gpp, r_nbo = 1.0f / (float)nbo, r_nbo2 = 1.0f / (float)nbo2;
       for (int i = tid; i < npair * gpp; i += kRotThreads) {
         const int pp = div_rcp(i, r_gpp), e = (i - pp * gpp) * gstep;
-        const int row = div_rcp(e, r_nw), col = e - row * nw;
-        const T* src = L.rows + 2 * ((pp * rows_pp + row) * ld + col);
-        T* dst = go + 2 * ((int64_t)pp * E + e);
+        const int v = div_rcp(e, r_nbo2), rem = e - v * nbo2;
+        const int mr = div_rcp(rem, r_nbo), col = rem - mr * nbo;
+        const T* src = L.rows + 2 * ((pp * rows_pp + v * nw + mr) * ld + col);
+        T* dst = go + 2 * ((int64_t)pp * Eo + e);
         if (vec_g) {
           chunk_from_lds(src, dst);
         } else {
@@ -648,6 +656,10 @@ ephw_status band_rotate(int prec, const BandRotateArgs& a, hipStream_t s) {
   if (a.nw > 32 || a.nw < 1) {
     set_error("band_rotate: this kernel handles 1 <= nw <= 32");
     return EPHW_EUNSUPPORTED;
+  }
+  if (a.band_n > 0 && (!a.Vk || a.band_lo < 0 || a.band_lo + a.band_n > a.nw)) {
+    set_error("band_rotate: the band window needs the rotations and 0 <= band_lo, band_lo + band_n <= nw");
+    return EPHW_EINVAL;
   }
   const BandPlan pl = band_rotate_plan(prec, a.nw, a.nm);
   const int64_t kb = ceil_div(a.nk_tile, (int64_t)pl.P);

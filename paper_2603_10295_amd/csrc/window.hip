@@ -103,6 +103,15 @@ __global__ void window_pairs_kernel(const int32_t* __restrict__ kq, int64_t nk, 
 
 int64_t grid_of(int64_t n, int t) { return (n + t - 1) / t; }
 
+// bflag[b] = 1 when band b has an energy in the window at some k of the set
+__global__ void band_any_kernel(const double* __restrict__ eps, int64_t nk, int nw, double lo, double hi,
+                                int32_t* __restrict__ bflag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nk * nw) return;
+  const double e = eps[i];
+  if (e >= lo && e <= hi) atomicOr(&bflag[i % nw], 1);
+}
+
 // Pair lists of the pairs whose k and k+q both have a band in the window,
 // grouped by q (CSR over the q list, each q's k ascending) or by k (CSR over
 // the k-set, each k's q ascending).  One workgroup per q or per k; a thread
@@ -255,7 +264,7 @@ ephw_status ephw_window_screen(ephw_kset* ks, const double* q, int64_t nq, const
 
 ephw_status ephw_window_pairs(ephw_kset* ks, const int32_t* kq_index, int64_t nq, double e_lo, double e_hi,
                              int32_t order, int32_t* order_out, int64_t* pair_start, int32_t* pair_other,
-                             int32_t* pair_kq, int64_t capacity, void* stream) {
+                             int32_t* pair_kq, int64_t capacity, int32_t* band_range, void* stream) {
   if (!ks || nq < 0 || (nq > 0 && !kq_index) || !pair_start || capacity < 0 || !(e_lo <= e_hi) ||
       (order != EPHW_PAIRS_BY_Q && order != EPHW_PAIRS_BY_K && order != EPHW_PAIRS_AUTO)) {
     set_error("ephw_window_pairs: invalid argument");
@@ -269,6 +278,7 @@ ephw_status ephw_window_pairs(ephw_kset* ks, const int32_t* kq_index, int64_t nq
     const int64_t n = ord == EPHW_PAIRS_BY_K ? nk : nq;
     for (int64_t i = 0; i <= n; ++i) pair_start[i] = 0;
     if (order_out) *order_out = ord;
+    if (band_range) band_range[0] = band_range[1] = 0;
     return EPHW_OK;
   }
   if (nk > 0x7fffffff || nq > 0x7fffffff) {
@@ -276,17 +286,25 @@ ephw_status ephw_window_pairs(ephw_kset* ks, const int32_t* kq_index, int64_t nq
     return EPHW_EUNSUPPORTED;
   }
   const bool want_q = order != EPHW_PAIRS_BY_K, want_k = order != EPHW_PAIRS_BY_Q;
-  // workspace: start [max(nq, nk) + 1], counts by q [nq] and by k [nk] (int64), k flags [nk] (int32)
+  // workspace: start [max(nq, nk) + 1], counts by q [nq] and by k [nk] (int64),
+  // k flags [nk] and band flags [nw] (int32)
   const int64_t nmax = nq > nk ? nq : nk;
-  EPHW_TRY(ws_need(s, WS_WINDOW, (size_t)(nmax + 1 + nq + nk) * 8 + (size_t)nk * 4 + 256));
+  EPHW_TRY(ws_need(s, WS_WINDOW, (size_t)(nmax + 1 + nq + nk) * 8 + (size_t)(nk + s->nw) * 4 + 256));
   char* base = static_cast<char*>(wsp(s, WS_WINDOW));
   int64_t* start = reinterpret_cast<int64_t*>(base);
   int64_t* cnt_q = start + nmax + 1;
   int64_t* cnt_k = cnt_q + nq;
   int32_t* kflag = reinterpret_cast<int32_t*>(cnt_k + nk);
+  int32_t* bflag = kflag + nk;
   hipLaunchKernelGGL(band_window_flags_kernel, dim3((unsigned)grid_of(nk, 256)), dim3(256), 0, st, ks->eps, nk,
                      s->nw, e_lo, e_hi, kflag);
   EPHW_CHECK_LAUNCH();
+  if (band_range) {
+    EPHW_HIP(hipMemsetAsync(bflag, 0, (size_t)s->nw * 4, st));
+    hipLaunchKernelGGL(band_any_kernel, dim3((unsigned)grid_of(nk * s->nw, 256)), dim3(256), 0, st, ks->eps, nk,
+                       s->nw, e_lo, e_hi, bflag);
+    EPHW_CHECK_LAUNCH();
+  }
   if (want_q) {
     hipLaunchKernelGGL(pair_count_kernel, dim3((unsigned)nq), dim3(kPairThreads), 0, st, kq_index, nq, nk, kflag, 0,
                        cnt_q, s->ctx->status);
@@ -298,9 +316,22 @@ ephw_status ephw_window_pairs(ephw_kset* ks, const int32_t* kq_index, int64_t nq
     EPHW_CHECK_LAUNCH();
   }
   std::vector<int64_t> hq(want_q ? nq : 0), hk(want_k ? nk : 0);
+  std::vector<int32_t> hb(band_range ? s->nw : 0);
   if (want_q) EPHW_HIP(hipMemcpyAsync(hq.data(), cnt_q, (size_t)nq * 8, hipMemcpyDeviceToHost, st));
   if (want_k) EPHW_HIP(hipMemcpyAsync(hk.data(), cnt_k, (size_t)nk * 8, hipMemcpyDeviceToHost, st));
+  if (band_range) EPHW_HIP(hipMemcpyAsync(hb.data(), bflag, (size_t)s->nw * 4, hipMemcpyDeviceToHost, st));
   EPHW_HIP(hipStreamSynchronize(st));
+  if (band_range) {
+    // the smallest band range holding every band with an energy in the window
+    int lo = -1, hi = -1;
+    for (int b = 0; b < s->nw; ++b)
+      if (hb[b]) {
+        if (lo < 0) lo = b;
+        hi = b;
+      }
+    band_range[0] = lo < 0 ? 0 : lo;
+    band_range[1] = lo < 0 ? 0 : hi - lo + 1;
+  }
   // the cheaper nesting order (see ephw_interpolate_pairs): group by the
   // index with fewer points that own a pair
   int32_t ord = order;

@@ -115,8 +115,8 @@ def lib() -> ctypes.CDLL:
                            ctypes.c_double, ctypes.c_double, i64, vp, vp],
         "ephw_window_screen": [vp, vp, i64, vp, ctypes.c_double, ctypes.c_double, vp, ctypes.POINTER(ctypes.c_int64),
                                vp, ctypes.POINTER(ctypes.c_int64), vp, vp, vp],
-        "ephw_window_pairs": [vp, vp, i64, ctypes.c_double, ctypes.c_double, i32, vp, vp, vp, vp, i64, vp],
-        "ephw_interpolate_pairs": [vp, vp, i64, i32, vp, vp, vp, i64, i32, u32, vp, vp, vp, u64, vp],
+        "ephw_window_pairs": [vp, vp, i64, ctypes.c_double, ctypes.c_double, i32, vp, vp, vp, vp, i64, vp, vp],
+        "ephw_interpolate_pairs": [vp, vp, i64, i32, vp, vp, vp, i64, i32, u32, i32, i32, vp, vp, vp, u64, vp],
         "ephw_set_q_batch": [vp, i32],
         "ephw_set_k_tile": [vp, i32],
         "ephw_loss_backward": [vp, vp, i64, vp, i64, u64, vp, vp, vp, vp, vp],
@@ -384,21 +384,23 @@ def window_screen(ks: KSet, q, kq_index, e_lo: float, e_hi: float, k_out, q_out,
 def window_pairs(ks: KSet, kq_index, e_lo: float, e_hi: float, order: int = PAIRS_AUTO, pair_other=None,
                  pair_kq=None, stream=None):
     """Kept (k, q) pairs of an energy window as CSR lists (see
-    ephw_window_pairs).  Returns (order, pair_start, pair_other, pair_kq):
-    the grouping used, a host int64 array of group offsets, and int32 device
-    tensors (the other index of each pair, the k+q index), allocated here when
-    not given or too small.  Synchronises the stream."""
+    ephw_window_pairs).  Returns (order, pair_start, pair_other, pair_kq,
+    band_range): the grouping used, a host int64 array of group offsets, int32
+    device tensors (the other index of each pair, the k+q index), allocated
+    here when not given or too small, and (first band, band count) of the
+    window's bands.  Synchronises the stream."""
     import numpy as np
     import torch
     nq = kq_index.shape[0]
     start = np.zeros(max(nq, ks.nk) + 1, dtype=np.int64)
     cap = 0 if pair_other is None else min(pair_other.numel(), pair_kq.numel())
     used = ctypes.c_int32(-2)
+    bands = (ctypes.c_int32 * 2)(0, 0)
 
     def call(cap_, po, pkq):
         return lib().ephw_window_pairs(ks.handle, _ptr(kq_index), nq, float(e_lo), float(e_hi), int(order),
                                        ctypes.byref(used), start.ctypes.data_as(ctypes.c_void_p), _ptr(po),
-                                       _ptr(pkq), cap_, _stream(stream))
+                                       _ptr(pkq), cap_, bands, _stream(stream))
     st = call(cap, pair_other, pair_kq)
     n = ks.nk if used.value == PAIRS_BY_K else nq
     total = int(start[n])
@@ -410,13 +412,15 @@ def window_pairs(ks: KSet, kq_index, e_lo: float, e_hi: float, order: int = PAIR
     if pair_other is None:
         pair_other = torch.empty(0, dtype=torch.int32, device=kq_index.device)
         pair_kq = torch.empty(0, dtype=torch.int32, device=kq_index.device)
-    return used.value, start[:n + 1].copy(), pair_other, pair_kq
+    return used.value, start[:n + 1].copy(), pair_other, pair_kq, (int(bands[0]), int(bands[1]))
 
 
 def interpolate_pairs(ks: KSet, q, order: int, pair_start, pair_other, pair_kq, *, q_offset: int = 0,
-                      flags: int = OUT_G, g_out=None, band_sum=None, loss=None, loss_seed: int = 0, stream=None):
+                      flags: int = OUT_G, bands=(0, 0), g_out=None, band_sum=None, loss=None, loss_seed: int = 0,
+                      stream=None):
     """Eq. (7) on the kept pairs of a CSR pair list (see ephw_interpolate_pairs);
-    pair_start is a host int64 array of group offsets (nq + 1 by q, nk + 1 by k)."""
+    pair_start is a host int64 array of group offsets (nq + 1 by q, nk + 1 by k);
+    bands = (first band, count) of the band window ((0, 0): all bands)."""
     import numpy as np
     import torch
     start = np.ascontiguousarray(pair_start, dtype=np.int64)
@@ -428,16 +432,17 @@ def interpolate_pairs(ks: KSet, q, order: int, pair_start, pair_other, pair_kq, 
         if t.dtype != torch.int32 or t.numel() < npairs:
             raise ValueError(f"{name} must be int32 with at least {npairs} entries")
     s = ks.sys
+    nb = int(bands[1]) if int(bands[1]) > 0 else s.nw
     if g_out is not None:
         want = torch.complex128 if ks.prec == FP64 else torch.complex64
-        if g_out.dtype != want or tuple(g_out.shape[1:]) != (s.nm, s.nw, s.nw) or g_out.shape[0] < npairs:
-            raise ValueError(f"g_out must be {want} [>= {npairs}][{s.nm}][{s.nw}][{s.nw}]")
+        if g_out.dtype != want or tuple(g_out.shape[1:]) != (s.nm, nb, nb) or g_out.shape[0] < npairs:
+            raise ValueError(f"g_out must be {want} [>= {npairs}][{s.nm}][{nb}][{nb}]")
     if band_sum is not None and (band_sum.dtype != torch.float64 or band_sum.numel() < npairs * s.nm):
         raise ValueError(f"band_sum must be float64 with at least {npairs * s.nm} entries")
     _check(lib().ephw_interpolate_pairs(ks.handle, _ptr(q), q.shape[0], int(order),
                                         start.ctypes.data_as(ctypes.c_void_p), _ptr(pair_other), _ptr(pair_kq),
-                                        int(q_offset), ks.prec, int(flags), _ptr(g_out), _ptr(band_sum), _ptr(loss),
-                                        int(loss_seed), _stream(stream)),
+                                        int(q_offset), ks.prec, int(flags), int(bands[0]), int(bands[1]),
+                                        _ptr(g_out), _ptr(band_sum), _ptr(loss), int(loss_seed), _stream(stream)),
            "ephw_interpolate_pairs")
 
 

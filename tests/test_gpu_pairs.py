@@ -60,7 +60,7 @@ def test_window_pairs_match_the_oracle_window(run, prec, order):
     s, kg, qg, kqi, lo, hi, keep = window_case(prec)
     assert 0 < keep.sum() < keep.size and not keep.all(axis=1).any() and (~keep).all(axis=1).any()
     ks = ephw.KSet(run.system(s), dev(kg), prec)
-    used, start, other, pkq = ephw.window_pairs(ks, dev(kqi), lo, hi, order=order)
+    used, start, other, pkq, _ = ephw.window_pairs(ks, dev(kqi), lo, hi, order=order)
     run.ctx.check()
     ks.close()
     assert used == order
@@ -86,7 +86,7 @@ def test_window_pairs_auto_picks_the_smaller_grouping(run):
     s, kg, qg, kqi, lo, hi, keep = window_case(0, frac=0.1)
     ks = ephw.KSet(run.system(s), dev(kg), 0)
     ak, aq = int(keep.any(axis=0).sum()), int(keep.any(axis=1).sum())
-    used, start, _, _ = ephw.window_pairs(ks, dev(kqi), lo, hi)
+    used, start, _, _, _ = ephw.window_pairs(ks, dev(kqi), lo, hi)
     assert used == (ephw.PAIRS_BY_K if ak < aq else ephw.PAIRS_BY_Q), (ak, aq)
     assert int(start[-1]) == int(keep.sum())
     # k+q of q row j is always k point j: q row j keeps pairs only when k_j is
@@ -95,7 +95,7 @@ def test_window_pairs_auto_picks_the_smaller_grouping(run):
     kact = np.any((eps >= lo) & (eps <= hi), axis=1)
     tab = np.repeat(np.arange(len(kg), dtype=np.int32)[:, None], len(kg), axis=1)
     tab_keep = kact[None, :] & kact[tab]
-    used2, start2, _, _ = ephw.window_pairs(ks, dev(tab), lo, hi)
+    used2, start2, _, _, _ = ephw.window_pairs(ks, dev(tab), lo, hi)
     ak2, aq2 = int(tab_keep.any(axis=0).sum()), int(tab_keep.any(axis=1).sum())
     assert used2 == (ephw.PAIRS_BY_K if ak2 < aq2 else ephw.PAIRS_BY_Q), (ak2, aq2)
     assert int(start2[-1]) == int(tab_keep.sum())
@@ -116,7 +116,7 @@ def test_interpolate_pairs_matches_full_path_and_oracle(run, prec, order):
     nk, nq = len(kg), len(qg)
     sysh = run.system(s)
     ks = ephw.KSet(sysh, dev(kg), prec)
-    used, start, other, pkq = ephw.window_pairs(ks, dev(kqi), lo, hi, order=order)
+    used, start, other, pkq, _ = ephw.window_pairs(ks, dev(kqi), lo, hi, order=order)
     npairs = int(start[-1])
     q_off, seed = 5, 23
     g = torch.empty((npairs, s.nm, s.nw, s.nw), dtype=cplx_dtype(prec), device="cuda:0")
@@ -174,7 +174,7 @@ def test_interpolate_pairs_edge_cases(run, order):
     ks = ephw.KSet(sysh, dev(kg), 0)
     eps = oracle.bands(s, kg)[0]
     # empty window
-    used, start, other, pkq = ephw.window_pairs(ks, dev(kqi), float(eps.max()) + 1.0, float(eps.max()) + 2.0,
+    used, start, other, pkq, _ = ephw.window_pairs(ks, dev(kqi), float(eps.max()) + 1.0, float(eps.max()) + 2.0,
                                                 order=order)
     assert int(start[-1]) == 0 and not start.any()
     loss = torch.full((1,), 7.0, dtype=torch.float64, device="cuda:0")
@@ -182,7 +182,7 @@ def test_interpolate_pairs_edge_cases(run, order):
     run.ctx.check()
     assert float(loss.cpu()[0]) == 7.0
     # every pair kept; by q in batches of 3 q
-    used, start, other, pkq = ephw.window_pairs(ks, dev(kqi), float(eps.min()) - 1.0, float(eps.max()) + 1.0,
+    used, start, other, pkq, _ = ephw.window_pairs(ks, dev(kqi), float(eps.min()) - 1.0, float(eps.max()) + 1.0,
                                                 order=order)
     assert int(start[-1]) == nq * nk
     sysh.set_q_batch(3)
@@ -225,3 +225,58 @@ def test_interpolate_pairs_edge_cases(run, order):
     with pytest.raises(ephw.EphwError):
         ephw.interpolate_pairs(ks, dev(qg), order, bad, po, pkq, flags=ephw.OUT_G, g_out=g2)
     ks.close()
+
+
+@pytest.mark.parametrize("prec,order", [(0, 0), (1, 1), (0, 1)])
+def test_interpolate_pairs_band_window(run, prec, order):
+    """The band window: the screen's band range equals the range of the bands
+    the oracle's eigenvalues put in the window; g, band sums and loss on that
+    range equal the sub-blocks of the all-band pair path (same V, same sums)
+    and the oracle's weighted loss over those elements."""
+    import torch
+    from paper_2603_10295_amd import ephw
+    from gpu_run import dev, cplx_dtype
+    s, kg, qg, kqi, lo, hi, keep = window_case(prec)
+    eps = oracle.bands(s, kg)[0]
+    # a window around the second band (inside gaps): bands 1.. of the range
+    hi = gap_edge(eps, np.quantile(eps[:, 2], 0.5))
+    lo = gap_edge(eps, np.quantile(eps[:, 1], 0.5))
+    inwin = (eps >= lo) & (eps <= hi)
+    kact = inwin.any(axis=1)
+    keep = kact[None, :] & kact[kqi]
+    bset = np.flatnonzero(inwin.any(axis=0))
+    b0, nb = int(bset.min()), int(bset.max() - bset.min() + 1)
+    assert 0 < nb < s.nw and keep.any()
+    nk = len(kg)
+    ks = ephw.KSet(run.system(s), dev(kg), prec)
+    used, start, other, pkq, band_range = ephw.window_pairs(ks, dev(kqi), lo, hi, order=order)
+    assert band_range == (b0, nb)
+    npairs = int(start[-1])
+    assert npairs == int(keep.sum())
+    flags = ephw.OUT_G | ephw.OUT_BAND_SUM | ephw.OUT_LOSS
+    gfull = torch.empty((npairs, s.nm, s.nw, s.nw), dtype=cplx_dtype(prec), device="cuda:0")
+    ephw.interpolate_pairs(ks, dev(qg), used, start, other, pkq, flags=ephw.OUT_G, g_out=gfull)
+    g = torch.empty((npairs, s.nm, nb, nb), dtype=cplx_dtype(prec), device="cuda:0")
+    t = torch.empty((npairs, s.nm), dtype=torch.float64, device="cuda:0")
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    ephw.interpolate_pairs(ks, dev(qg), used, start, other, pkq, flags=flags, bands=band_range, g_out=g,
+                           band_sum=t, loss=loss, loss_seed=31)
+    run.ctx.check()
+    ks.close()
+    sub = gfull.cpu().numpy()[:, :, b0:b0 + nb, b0:b0 + nb]
+    assert np.array_equal(g.cpu().numpy(), sub)
+    np.testing.assert_allclose(t.cpu().numpy(), (np.abs(sub.astype(np.complex128)) ** 2).sum(axis=(2, 3)),
+                               rtol=1e-12 if prec == 0 else 1e-6)
+    if order == ephw.PAIRS_BY_Q:
+        iq, ik = np.nonzero(keep)
+    else:
+        ik, iq = np.nonzero(keep.T)
+    ref = oracle.interpolate(s, kg, qg, return_all=True)
+    w = oracle.splitmix64_weights(31, oracle.element_index(iq, ik, nk, s.nm, s.nw))[:, :, b0:b0 + nb, b0:b0 + nb]
+    ghat = ref["ghat"][iq, ik][:, :, b0:b0 + nb, b0:b0 + nb]
+    # the window's bands sit in gaps of the spectrum, so the sub-block sums are
+    # gauge invariant when no degenerate block straddles the range edges
+    l_ref = float(np.sum(w * np.abs(ghat) ** 2))
+    l_err = abs(float(loss.cpu().numpy()[0]) - l_ref) / l_ref
+    print(f"band window prec={prec} order={order}: bands {b0}..{b0 + nb - 1}, {npairs} pairs, loss {l_err:.2e}")
+    assert l_err < (1e-10 if prec == 0 else 1e-5)
