@@ -44,6 +44,8 @@ def parse(argv=None):
     ap.add_argument("--ribbon-na", type=int, default=50)
     ap.add_argument("--batch-count", type=int, default=32)
     ap.add_argument("--batch-max-grid", type=int, default=16)
+    ap.add_argument("--batch-uncapped", action="store_true",
+                    help="batch32: the systems as drawn, no cap on the size of g (g drawn on the device)")
     ap.add_argument("--tune-cache", default="")
     ap.add_argument("--grid", type=int, default=20, help="k = q = grid^3 for si_dense")
     ap.add_argument("--q-chunk", type=int, default=1024)
@@ -196,9 +198,37 @@ def cpu_baseline(w, qs_idx):
     return elems / dt, dt, ref, threads
 
 
+def device_g(s, seed: int):
+    """complex64 g(Re,Rp) of system s drawn on the device: complex normal
+    (re, im iid N(0, 1/2)) times exp(-(|Re| + |Rp|)/2), the value distribution
+    of the host generator, from torch's counter-based device generator (for
+    systems too large to draw on the host; nothing compares them with the
+    host-drawn values)."""
+    import torch
+    dev_ = "cuda:0"
+    ne, npp = len(s.r_e), len(s.r_p)
+    nre = torch.from_numpy(np.linalg.norm(s.r_e.astype(np.float64), axis=1)).to(dev_)
+    nrp = torch.from_numpy(np.linalg.norm(s.r_p.astype(np.float64), axis=1)).to(dev_)
+    env = torch.exp(-0.5 * (nrp[:, None] + nre[None, :])).to(torch.float32)
+    out = torch.empty((npp, ne, s.nm, s.nw, s.nw), dtype=torch.complex64, device=dev_)
+    gen = torch.Generator(device=dev_)
+    gen.manual_seed(seed)
+    per = max(1, int(2 ** 28 // max(1, ne * s.nm * s.nw * s.nw)))   # Rp rows per draw
+    for p0 in range(0, npp, per):
+        p1 = min(npp, p0 + per)
+        x = torch.randn((p1 - p0, ne, s.nm, s.nw, s.nw, 2), generator=gen, device=dev_, dtype=torch.float32)
+        x.mul_(0.7071067811865476 * env[p0:p1, :, None, None, None, None])
+        out[p0:p1] = torch.view_as_complex(x)
+        del x
+    return out
+
+
 def bench_batch(args):
     """Many heterogeneous systems in one graph-captured pass (one grouped launch
-    per stage), against the same items run one system at a time."""
+    per stage), against the same items run one system at a time (each system
+    timed on its own after a warm-up call, its workspace released before the
+    next).  --batch-uncapped draws the 32 systems with no cap on the size of
+    g (about 207 GB of complex64 g in all, generated on the device)."""
     import torch
     import synth
     from paper_2603_10295_amd import ephw, model
@@ -207,11 +237,24 @@ def bench_batch(args):
     items, keep, names = [], [], []
     elems = 0.0
     cnt_tot = None
+    cap = None if args.batch_uncapped else synth.G_CAP_BYTES
+    g_bytes = 0
     for i in range(args.batch_count):
-        w = synth.batch_system(0, i, max_grid=args.batch_max_grid)   # generated, uploaded, freed one by one
+        # generated, uploaded, freed one by one
+        w = synth.batch_system(0, i, max_grid=args.batch_max_grid, g_cap_bytes=cap, with_g=cap is not None)
         names.append(w.name)
         s = w.system
-        sysh = ephw.System.from_synth(ctx, s)
+        if cap is None:
+            sysh = ephw.System.from_synth(ctx, s, g_dtype=ephw.C64)
+            g = device_g(s, seed=1000 + i)
+            sysh.set_g(g)
+            torch.cuda.synchronize()
+            g_bytes += g.numel() * 8
+            del g
+            log(f"system {i}: {w.name}, g {g_bytes / 1e9:.1f} GB so far")
+        else:
+            sysh = ephw.System.from_synth(ctx, s)
+            g_bytes += s.g.nbytes
         k = torch.from_numpy(w.k).to("cuda:0")
         q = torch.from_numpy(w.q).to("cuda:0")
         ks = ephw.KSet(sysh, k, ephw.FP32)
@@ -240,26 +283,36 @@ def bench_batch(args):
     ctx.check()
     stats, shapes = b.stats(), [b.shape(i) for i in range(len(items))]
     b.close()   # release the batch's sweep buffers before the one-at-a-time runs allocate theirs
-    # the same items, one system at a time (no grouping, no graph)
-    def one_by_one():
-        for it in items:
+    # the same items, one system at a time (no grouping, no graph): each
+    # system warmed up and timed on its own, its workspace then released
+    ts = 0.0
+    per_system_ms = []
+    for it, sysh in zip(items, keep):
+        def one():
             ephw.interpolate(it["ks"], it["q"], kq_index=it["kq_index"], flags=ephw.OUT_LOSS, loss=it["loss"],
                              loss_seed=it["loss_seed"])
-    one_by_one()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        one_by_one()
-    torch.cuda.synchronize()
-    ts = (time.perf_counter() - t0) / args.steps
-    ctx.check()
+        one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            one()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        ts += dt
+        per_system_ms.append(round(dt * 1e3, 3))
+        ctx.check()
+        sysh.trim()
+    log(f"one at a time: {ts * 1e3:.1f} ms; batched {tb * 1e3:.1f} ms")
     gemm_tf = 8.0 * cnt_tot.gemm / tb / 1e12
     line = {
         "metric": "g(k,q) elems/s (FP32 MFMA path, 32-system batch)", "value": elems / tb, "unit": "elems/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": tb * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
-        "config": {"workload": f"batch{len(names)}_capped2GiB_maxgrid{args.batch_max_grid}", "systems": len(names),
+        "config": {"workload": f"batch{len(names)}_{'uncapped' if cap is None else 'capped2GiB'}"
+                               f"_maxgrid{args.batch_max_grid}", "systems": len(names),
+                   "g_bytes": g_bytes, "g_source": "device generator" if cap is None else "host generator",
                    "output": "weighted |g|^2 loss per system", **stats},
+        "one_system_at_a_time_per_system_ms": per_system_ms,
         "one_system_at_a_time_ms": ts * 1e3, "batch_speedup": ts / tb,
         "phase_gemm_tflops_lower_bound": gemm_tf,
         "algorithmic_flops_per_step": 8.0 * cnt_tot.total,

@@ -143,12 +143,18 @@ typedef struct ephw_system_desc {
 } ephw_system_desc;
 
 /* Copy a system to the device (blocking).  Limits: 1 <= nw <= 256,
-   1 <= na <= 86 (nm <= 258), every n >= 1. */
+   1 <= na <= 86 (nm <= 258), every n >= 1.  g may be NULL: its device copy
+   is then allocated but not written, and must be filled with
+   ephw_system_set_g before any call reads it (for g generated on the
+   device, e.g. systems too large to stage on the host). */
 ephw_status ephw_system_load(ephw_ctx* ctx, const ephw_system_desc* desc, ephw_system** out);
 ephw_status ephw_system_free(ephw_system* sys);
 /* Replace the system's g(Re,Rp) by `g` (DEVICE memory, same shape and element
    type as at load), copied on `stream`; k-sets of the system stay valid. */
 ephw_status ephw_system_set_g(ephw_system* sys, const void* g, void* stream);
+/* Release the system's workspaces (the buffers its calls grow and keep for
+   reuse; the next call allocates them again).  Waits for the device. */
+ephw_status ephw_system_trim(ephw_system* sys);
 /* bytes of library-owned device memory held by the system (tensors + workspace) */
 ephw_status ephw_system_bytes(const ephw_system* sys, int64_t* bytes);
 

@@ -196,7 +196,7 @@ ephw_status ephw_system_load(ephw_ctx* ctx, const ephw_system_desc* d, ephw_syst
     set_error("ephw_system_load: sizes out of range (1<=nw<=256, 1<=na<=86, counts >= 1)");
     return EPHW_EINVAL;
   }
-  if (!d->r_e || !d->r_p || !d->r_h || !d->r_c || !d->h_r || !d->c_r || !d->mass || !d->g) {
+  if (!d->r_e || !d->r_p || !d->r_h || !d->r_c || !d->h_r || !d->c_r || !d->mass) {
     set_error("ephw_system_load: a required array is NULL");
     return EPHW_EINVAL;
   }
@@ -264,12 +264,33 @@ ephw_status ephw_system_load(ephw_ctx* ctx, const ephw_system_desc* d, ephw_syst
     const size_t gbytes = (size_t)d->np * d->ne * nm * d->nw * d->nw * csize(s->g_kind);
     if ((st = dev_alloc(&s->g, gbytes, s->mem.get())) != EPHW_OK) return fail(st);
     s->bytes += (int64_t)gbytes;
-    if (hipMemcpy(s->g, d->g, gbytes, hipMemcpyHostToDevice) != hipSuccess) {
+    // g NULL: the caller fills it on the device with ephw_system_set_g
+    if (d->g && hipMemcpy(s->g, d->g, gbytes, hipMemcpyHostToDevice) != hipSuccess) {
       set_error("ephw_system_load: upload of g failed");
       return fail(EPHW_EDEVICE);
     }
   }
   *out = s;
+  return EPHW_OK;
+}
+
+ephw_status ephw_system_trim(ephw_system* s) {
+  if (!s) {
+    set_error("ephw_system_trim: NULL argument");
+    return EPHW_EINVAL;
+  }
+  bool any = false;
+  for (auto& b : s->ws) any = any || b.p;
+  if (!any) return EPHW_OK;
+  EPHW_HIP(hipDeviceSynchronize());
+  for (auto& b : s->ws)
+    if (b.p) {
+      EPHW_HIP(hipFree(b.p));
+      s->bytes -= (int64_t)b.bytes;
+      dev_release(s->mem.get(), (int64_t)b.bytes);
+      b.p = nullptr;
+      b.bytes = 0;
+    }
   return EPHW_OK;
 }
 

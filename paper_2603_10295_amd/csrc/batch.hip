@@ -234,6 +234,11 @@ ephw_status tune_item(ItemPlan& it, int kind, int64_t cap, bool measure, hipStre
     if (std::find(cands.begin(), cands.end(), q) == cands.end() && k_tile_for(it, q, cap) >= std::min<int64_t>(16, it.nk))
       cands.push_back(q);
   }
+  // items whose two g(Re,q) sweeps at 16 q do not fit the cap take fewer q
+  for (int32_t qb = 8; cands.empty() && qb >= 1; qb /= 2) {
+    const int32_t q = (int32_t)std::min<int64_t>(qb, it.nq);
+    if (k_tile_for(it, q, cap) >= std::min<int64_t>(16, it.nk)) cands.push_back(q);
+  }
   if (cands.empty()) {
     set_error("ephw_batch_create: an item does not fit the per-item workspace cap");
     return EPHW_ENOMEM;
@@ -682,6 +687,14 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
     }
     if (want > budget)
       for (auto& c : caps) c = (int64_t)std::max(gib, (double)c * budget / want);
+    // never below what one q with a 16-point k tile needs
+    for (size_t i = 0; i < bt->items.size(); ++i) {
+      const ItemPlan& it = bt->items[i];
+      const double cs = (double)csize(bt->kind);
+      const double least = 2.0 * it.ne * it.E * cs + (double)std::min<int64_t>(16, it.nk) * (it.E * cs + 8.0) +
+                           (double)(1 << 20);
+      caps[i] = std::max(caps[i], (int64_t)least);
+    }
   }
   // shapes: cache, else tune (or heuristics)
   auto cache = read_cache(o.tune_cache);

@@ -752,7 +752,14 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
         rb[i] = load_chunk<T>(make_rsrc(j.B + 2 * bo, (b_ext - bo) * CS), off);
       }
     }
-    // K tail where K runs along a row: the next row's values must not enter
+  };
+
+  // registers -> LDS stage of the slab at k0; conjugation is applied here,
+  // and the K tail where K runs along a row (the next row's values must not
+  // enter).  The tail is masked here rather than right after the loads: a
+  // select on the loaded registers would make the wave wait for the loads at
+  // the top of the slab instead of after its MFMAs.
+  auto stash = [&](T* st, int64_t k0) {
     const int64_t klim = K - k0;
     if (!TA && klim < BK) {
 #pragma unroll
@@ -780,10 +787,6 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
           }
       }
     }
-  };
-
-  // registers -> LDS stage; conjugation is applied here
-  auto stash = [&](T* st) {
     T* As = st;
     T* Bs = st + 2 * BK * LA;
 #pragma unroll
@@ -896,7 +899,7 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
   // K loop: one barrier per slab (see the pipeline note above)
   const int64_t nslab = (K + BK - 1) / BK;
   load(0);
-  stash(smem);
+  stash(smem, 0);
   __syncthreads();
   for (int64_t sl = 0; sl < nslab; ++sl) {
     const bool more = sl + 1 < nslab;
@@ -905,7 +908,7 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
     if constexpr (KBLK > 0) {
       if ((sl + 1) % KBLK == 0) fold();
     }
-    if (more) stash(smem + ((sl + 1) & 1) * S::stage_elems);
+    if (more) stash(smem + ((sl + 1) & 1) * S::stage_elems, (sl + 1) * BK);
     __syncthreads();
   }
   if constexpr (KBLK > 0) {

@@ -26,7 +26,7 @@ OUT_G, OUT_BAND_SUM, OUT_LOSS, OUT_WANNIER = 1, 2, 4, 8
 
 EXPORTS = [
     "ephw_ctx_create", "ephw_ctx_destroy", "ephw_ctx_check", "ephw_ctx_set_limits", "ephw_ctx_memory", "ephw_system_load",
-    "ephw_system_free", "ephw_system_set_g", "ephw_system_bytes", "ephw_bands", "ephw_phonons", "ephw_phase_sum_rp",
+    "ephw_system_free", "ephw_system_set_g", "ephw_system_trim", "ephw_system_bytes", "ephw_bands", "ephw_phonons", "ephw_phase_sum_rp",
     "ephw_kset_create", "ephw_kset_free", "ephw_kset_bands", "ephw_interpolate", "ephw_interpolate_noalloc", "ephw_interpolate_linewidth", "ephw_degenerate_sums", "ephw_wannier_transform",
     "ephw_window_screen", "ephw_window_pairs", "ephw_interpolate_pairs", "ephw_linewidth",
     "ephw_loss_backward", "ephw_set_q_batch", "ephw_set_k_tile", "ephw_profile_enable", "ephw_profile_read", "ephw_batch_create",
@@ -98,6 +98,7 @@ def lib() -> ctypes.CDLL:
         "ephw_system_load": [vp, ctypes.POINTER(SystemDesc), pp],
         "ephw_system_free": [vp],
         "ephw_system_set_g": [vp, vp, vp],
+        "ephw_system_trim": [vp],
         "ephw_system_bytes": [vp, ctypes.POINTER(ctypes.c_int64)],
         "ephw_bands": [vp, vp, i64, vp, vp, vp],
         "ephw_phonons": [vp, vp, i64, vp, vp, vp, vp],
@@ -231,9 +232,15 @@ class System:
     """Library-owned device copy of a Wannier-space system (host numpy inputs)."""
 
     def __init__(self, ctx: Context, *, nw, na, r_e, r_p, r_h, r_c, h_r, c_r, mass, g,
-                 w_e=None, w_p=None, w_h=None, w_c=None):
-        g_arr = np.asarray(g)
-        if g_arr.dtype == np.complex128:
+                 w_e=None, w_p=None, w_h=None, w_c=None, g_dtype=None):
+        """g None: the device copy is allocated but not written (fill it with
+        set_g); g_dtype (C128 or C64) then gives its element type."""
+        g_arr = None if g is None else np.asarray(g)
+        if g_arr is None:
+            if g_dtype not in (C128, C64):
+                raise ValueError("without g, g_dtype must be C128 or C64")
+            gdt = g_dtype
+        elif g_arr.dtype == np.complex128:
             gdt = C128
         elif g_arr.dtype == np.complex64:
             gdt = C64
@@ -244,7 +251,7 @@ class System:
             r_c=_host(r_c, np.int32), w_e=_host(w_e, np.float64), w_p=_host(w_p, np.float64),
             w_h=_host(w_h, np.float64), w_c=_host(w_c, np.float64),
             h_r=_host(h_r, np.complex128), c_r=_host(c_r, np.float64), mass=_host(mass, np.float64),
-            g=np.ascontiguousarray(g_arr))
+            g=None if g_arr is None else np.ascontiguousarray(g_arr))
         d = SystemDesc()
         d.nw, d.na = int(nw), int(na)
         d.ne, d.np, d.nh, d.nc = (len(keep["r_e"]), len(keep["r_p"]), len(keep["r_h"]), len(keep["r_c"]))
@@ -261,9 +268,13 @@ class System:
         self.g_dtype = gdt
 
     @classmethod
-    def from_synth(cls, ctx: Context, s) -> "System":
+    def from_synth(cls, ctx: Context, s, g_dtype=None) -> "System":
         return cls(ctx, nw=s.nw, na=s.na, r_e=s.r_e, r_p=s.r_p, r_h=s.r_h, r_c=s.r_c, h_r=s.h_r,
-                   c_r=s.c_r, mass=s.mass, g=s.g, w_e=s.w_e, w_p=s.w_p, w_h=s.w_h, w_c=s.w_c)
+                   c_r=s.c_r, mass=s.mass, g=s.g, w_e=s.w_e, w_p=s.w_p, w_h=s.w_h, w_c=s.w_c, g_dtype=g_dtype)
+
+    def trim(self):
+        """Release the system's workspaces (see ephw_system_trim)."""
+        _check(lib().ephw_system_trim(self.handle), "ephw_system_trim")
 
     def set_g(self, g, stream=None):
         """Copy a device tensor (same shape/dtype as the loaded g) into the system."""

@@ -179,11 +179,13 @@ class Workload:
 
 
 def make_system(nw: int, na: int, r_e: np.ndarray, r_p: np.ndarray, base: Sequence[int],
-                g_dtype=np.complex128, mass: Optional[np.ndarray] = None) -> System:
+                g_dtype=np.complex128, mass: Optional[np.ndarray] = None, with_g: bool = True) -> System:
+    """with_g False leaves g None (its stream is then not drawn): for systems
+    whose g is generated on the device instead."""
     nm = 3 * na
     h_r = hermitian_paired(r_e, nw, rng(base, STREAM_H), complex_=True)
     c_r = hermitian_paired(r_p, nm, rng(base, STREAM_C), complex_=False)
-    g = decaying_g(r_e, r_p, nm, nw, rng(base, STREAM_G), g_dtype)
+    g = decaying_g(r_e, r_p, nm, nw, rng(base, STREAM_G), g_dtype) if with_g else None
     if mass is None:
         mass = np.ones(na, dtype=np.float64)
     return System(nw=nw, na=na, r_e=r_e, r_p=r_p, r_h=r_e.copy(), r_c=r_p.copy(),
@@ -237,11 +239,12 @@ def si_dense(seed: int = 0, m: int = 20, g_dtype=np.complex64) -> Workload:
 G_CAP_BYTES = 2 * 2 ** 30
 
 
-def batch_shape(seed: int, s: int, max_grid: int = 16, g_cap_bytes: int = G_CAP_BYTES):
+def batch_shape(seed: int, s: int, max_grid: int = 16, g_cap_bytes: Optional[int] = G_CAP_BYTES):
     """Shape of system s of the multi-system batch: Nw in [4,32], Na in [1,8],
     a 3D box with n_i in [4,10] and Ne=Np<=800, grid m in [4, max_grid].
     Draws whose complex64 g would exceed g_cap_bytes are redrawn from the same
-    ranges (the unrestricted 32-system batch holds about 207 GB of g)."""
+    ranges (None: no cap; the unrestricted 32-system batch holds about 207 GB
+    of g)."""
     gen = rng([seed, STREAM_SHAPE, s], 0)
     while True:
         nw = int(gen.integers(4, 33))
@@ -252,17 +255,18 @@ def batch_shape(seed: int, s: int, max_grid: int = 16, g_cap_bytes: int = G_CAP_
                 break
         m = int(gen.integers(4, max_grid + 1))
         ne = n[0] * n[1] * n[2]
-        if 8 * ne * ne * 3 * na * nw * nw <= g_cap_bytes:
+        if g_cap_bytes is None or 8 * ne * ne * 3 * na * nw * nw <= g_cap_bytes:
             return nw, na, n, m
 
 
-def batch_system(seed: int, s: int, max_grid: int = 16, g_cap_bytes: int = G_CAP_BYTES) -> Workload:
+def batch_system(seed: int, s: int, max_grid: int = 16, g_cap_bytes: Optional[int] = G_CAP_BYTES,
+                 with_g: bool = True) -> Workload:
     """System s of the multi-system batch (see batch_shape); complex64 g, k = q =
     the m^3 grid of the system."""
     base = [seed, STREAM_SHAPE, s]
     nw, na, n, m = batch_shape(seed, s, max_grid, g_cap_bytes)
     r = box(n)
-    sys_ = make_system(nw, na, r, r, base, g_dtype=np.complex64)
+    sys_ = make_system(nw, na, r, r, base, g_dtype=np.complex64, with_g=with_g)
     pts = uniform_grid((m, m, m))
     return Workload(f"batch{s}_nw{nw}_nm{3*na}_r{n[0]}x{n[1]}x{n[2]}_grid{m}^3",
                     sys_, pts, pts.copy(), grid_index_of_sum((m, m, m)), "fp32", seed)

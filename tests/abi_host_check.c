@@ -47,6 +47,14 @@ int main(void) {
   expect("system_load NULL", ephw_system_load(NULL, NULL, NULL), EPHW_EINVAL);
   expect("system_set_g NULL", ephw_system_set_g(NULL, NULL, NULL), EPHW_EINVAL);
   expect("system_bytes NULL", ephw_system_bytes(NULL, NULL), EPHW_EINVAL);
+  expect("system_trim NULL", ephw_system_trim(NULL), EPHW_EINVAL);
+  expect("window_pairs NULL",
+         ephw_window_pairs(NULL, NULL, 4, 0.0, 1.0, EPHW_PAIRS_AUTO, NULL, NULL, NULL, NULL, 0, NULL, NULL),
+         EPHW_EINVAL);
+  expect("interpolate_pairs NULL",
+         ephw_interpolate_pairs(NULL, NULL, 4, EPHW_PAIRS_BY_Q, NULL, NULL, NULL, 0, 1, EPHW_OUT_G, 0, 0, NULL, NULL,
+                                NULL, 0, NULL),
+         EPHW_EINVAL);
   expect("set_q_batch NULL", ephw_set_q_batch(NULL, 4), EPHW_EINVAL);
   expect("set_k_tile NULL", ephw_set_k_tile(NULL, 4), EPHW_EINVAL);
   expect("kset_create NULL", ephw_kset_create(NULL, NULL, 4, 0, NULL, NULL), EPHW_EINVAL);

@@ -678,3 +678,36 @@ def test_si_dense_sampled_full_size(run):
         assert norm < RTOL_S32
         assert scaled < RTOL_S32
     assert errs[ephw.FP32_COMP] < 0.5 * errs[ephw.FP32], errs
+
+
+def test_system_loaded_without_g_then_set_on_device(run):
+    """A system loaded with g NULL and filled with ephw_system_set_g from
+    device memory gives the same g(k,q) as one loaded from the host; trimming
+    its workspaces between calls changes nothing."""
+    import torch
+    from paper_2603_10295_amd import ephw
+    from gpu_run import dev
+    s = synth.si_toy(nk=5, nq=4).system
+    k = synth.si_toy(nk=5, nq=4).k
+    q = synth.si_toy(nk=5, nq=4).q
+    a = run.system(s)
+    b = ephw.System.from_synth(run.ctx, dataclasses_replace_g(s, None), g_dtype=ephw.C128)
+    b.set_g(dev(s.g))
+    outs = []
+    for sysh in (a, b):
+        ks = ephw.KSet(sysh, dev(k), ephw.FP64)
+        g = torch.empty((len(q), len(k), s.nm, s.nw, s.nw), dtype=torch.complex128, device="cuda:0")
+        ephw.interpolate(ks, dev(q), flags=ephw.OUT_G, g_out=g)
+        sysh.trim()
+        g2 = torch.empty_like(g)
+        ephw.interpolate(ks, dev(q), flags=ephw.OUT_G, g_out=g2)
+        run.ctx.check()
+        outs.append((g.cpu().numpy(), g2.cpu().numpy()))
+        ks.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][0], outs[1][1])
+    b.close()
+
+
+def dataclasses_replace_g(s, g):
+    import dataclasses
+    return dataclasses.replace(s, g=g)
