@@ -665,7 +665,11 @@ __device__ __forceinline__ void band_epilogue_mfma8(const TileJob<float>& j, con
 // 16-byte read gives a lane its (re, im) operand pair.
 // KBLK > 0: K-blocked accumulation, a fresh accumulator every KBLK slabs
 // (the compensated FP32 form, see the K loop)
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int KBLK, int BANDNW = 0>
+// FLAT: both operands' whole extents fit 32-bit byte offsets from the
+// tile's origin (checked at launch), so one buffer resource per operand
+// serves every slab and a slab only adds a uniform offset
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int KBLK, int BANDNW = 0,
+          bool FLAT = false>
 __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64_t n0, T* smem,
                                           const BandEpilogue* band = nullptr) {
   using S = TileShape<T, BM, BN, BK, WM, WN>;
@@ -725,7 +729,23 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
 
   V4 ra[AC], rb[BC];
 
+  static_assert(!FLAT || (A_GRP && B_GRP), "the flat loader addresses chunks by row group");
+  const int64_t ao0 = TA ? m0 : m0 * j.lda, bo0 = TB ? n0 * j.ldb : n0;
+  const __amdgpu_buffer_rsrc_t rsa = make_rsrc(j.A + 2 * ao0, FLAT ? (a_ext - ao0) * CS : 0);
+  const __amdgpu_buffer_rsrc_t rsb = make_rsrc(j.B + 2 * bo0, FLAT ? (b_ext - bo0) * CS : 0);
+  const uint32_t a_row_bytes = (uint32_t)(a_row0 * CS), b_row_bytes = (uint32_t)(b_row0 * CS);
   auto load = [&](int64_t k0) {
+    if constexpr (FLAT) {
+      const uint32_t ka = (uint32_t)((TA ? k0 * j.lda : k0) * CS);
+      const uint32_t kb = (uint32_t)((TB ? k0 : k0 * j.ldb) * CS);
+#pragma unroll
+      for (int i = 0; i < AC; ++i)
+        ra[i] = load_chunk<T>(rsa, a_off0 + a_row_bytes + (uint32_t)((int64_t)i * A_RSTEP * j.lda * CS) + ka);
+#pragma unroll
+      for (int i = 0; i < BC; ++i)
+        rb[i] = load_chunk<T>(rsb, b_off0 + b_row_bytes + (uint32_t)((int64_t)i * B_RSTEP * j.ldb * CS) + kb);
+      return;
+    }
     const int64_t ao = TA ? k0 * j.lda + m0 : m0 * j.lda + k0;
     const int64_t bo = TB ? n0 * j.ldb + k0 : k0 * j.ldb + n0;
 #pragma unroll
@@ -1050,7 +1070,8 @@ __device__ __forceinline__ TileJob<T> job_of(const GemmParams& p, int64_t b) {
 }
 
 // OCC: waves per SIMD the register allocation must leave room for
-template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int KBLK, int OCC, int BANDNW = 0>
+template <typename T, int BM, int BN, int BK, int WM, int WN, bool TA, bool TB, int KBLK, int OCC, int BANDNW = 0,
+          bool FLAT = false>
 __global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_eu(OCC)))
     cgemm_kernel(GemmParams p, int64_t tiles_m, int64_t tiles_n) {
   using S = TileShape<T, BM, BN, BK, WM, WN>;
@@ -1061,7 +1082,7 @@ __global__ void __launch_bounds__(64 * WM * WN) __attribute__((amdgpu_waves_per_
   TileJob<T> j = job_of<T>(p, p.batch_base + blockIdx.y);
   j.tile = tm * tiles_n + tn;
   j.ntiles = tiles_m * tiles_n;
-  gemm_tile<T, BM, BN, BK, WM, WN, TA, TB, KBLK, BANDNW>(j, tm * BM, tn * BN, smem, &p.band);
+  gemm_tile<T, BM, BN, BK, WM, WN, TA, TB, KBLK, BANDNW, FLAT>(j, tm * BM, tn * BN, smem, &p.band);
 }
 
 // Tile shapes of the grouped kernel: cfg 0 is the default tile of the plain
@@ -1200,12 +1221,24 @@ ephw_status launch(const GemmParams& p0, hipStream_t stream) {
     return EPHW_EUNSUPPORTED;
   }
   GemmParams p = p0;
+  // the flat loader for the FP32 128x128 tile when both operands' whole
+  // extents (per batch entry) fit 32-bit byte offsets
+  constexpr bool kFlatTile = sizeof(T) == 4 && BM == 128 && BN == 128 && WM == 2 && WN == 2 && !TA && !TB;
+  bool flat = false;
+  if constexpr (kFlatTile) {
+    constexpr int64_t cs = 2 * (int64_t)sizeof(T), lim = ((int64_t)1 << 32) - 4096;
+    const int64_t a_ext = (p0.M - 1) * p0.lda + p0.K, b_ext = (p0.K - 1) * p0.ldb + p0.N;
+    flat = (a_ext + BM + BK) * cs < lim && (b_ext + BN + BK) * cs < lim;
+  }
   for (int64_t b0 = 0; b0 < p0.batch; b0 += 65535) {
     const int64_t nb = (p0.batch - b0) < 65535 ? (p0.batch - b0) : 65535;
     p.batch_base = b0;
-    hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, WM, WN, TA, TB, KBLK, OCC, BANDNW>),
-                       dim3((unsigned)ntiles, (unsigned)nb), dim3(64 * WM * WN), 0, stream, p,
-                       tiles_m, tiles_n);
+    if (flat)
+      hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, WM, WN, TA, TB, KBLK, OCC, BANDNW, kFlatTile>),
+                         dim3((unsigned)ntiles, (unsigned)nb), dim3(64 * WM * WN), 0, stream, p, tiles_m, tiles_n);
+    else
+      hipLaunchKernelGGL((cgemm_kernel<T, BM, BN, BK, WM, WN, TA, TB, KBLK, OCC, BANDNW>),
+                         dim3((unsigned)ntiles, (unsigned)nb), dim3(64 * WM * WN), 0, stream, p, tiles_m, tiles_n);
     EPHW_CHECK_LAUNCH();
   }
   return EPHW_OK;
