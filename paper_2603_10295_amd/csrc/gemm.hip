@@ -1221,13 +1221,16 @@ ephw_status launch(const GemmParams& p0, hipStream_t stream) {
     return EPHW_EUNSUPPORTED;
   }
   GemmParams p = p0;
-  // the flat loader for the FP32 128x128 tile when both operands' whole
-  // extents (per batch entry) fit 32-bit byte offsets
-  constexpr bool kFlatTile = sizeof(T) == 4 && BM == 128 && BN == 128 && WM == 2 && WN == 2 && !TA && !TB;
+  // the flat loader (untransposed operands, tiles whose threads load whole
+  // row groups) when both operands' whole extents (per batch entry) fit
+  // 32-bit byte offsets
+  constexpr int kCpc = Chunk<T>::CPC, kNt = 64 * WM * WN;
+  constexpr bool kFlatTile = !TA && !TB && kNt % (BK / kCpc) == 0 && kNt % (BN / kCpc) == 0;
   bool flat = false;
   if constexpr (kFlatTile) {
     constexpr int64_t cs = 2 * (int64_t)sizeof(T), lim = ((int64_t)1 << 32) - 4096;
-    const int64_t a_ext = (p0.M - 1) * p0.lda + p0.K, b_ext = (p0.K - 1) * p0.ldb + p0.N;
+    const int64_t a_ext = TA ? (p0.K - 1) * p0.lda + p0.M : (p0.M - 1) * p0.lda + p0.K;
+    const int64_t b_ext = TB ? (p0.N - 1) * p0.ldb + p0.K : (p0.K - 1) * p0.ldb + p0.N;
     flat = (a_ext + BM + BK) * cs < lim && (b_ext + BN + BK) * cs < lim;
   }
   for (int64_t b0 = 0; b0 < p0.batch; b0 += 65535) {
