@@ -95,15 +95,22 @@ struct BandRotateArgs {
   int band_lo = 0, band_n = 0;
 };
 ephw_status band_rotate(int prec, const BandRotateArgs& a, hipStream_t s);
-// Work split of the band-rotation kernel (Nw <= 32): P consecutive k per
-// workgroup, nuc modes per LDS chunk, dynamic LDS bytes.
+// Work split of a band-rotation launch (Nw <= 32, rotations without a band
+// window): P consecutive k per workgroup, nuc modes per LDS chunk, dynamic
+// LDS bytes.  The matrix-core kernel takes P = 4 (one wavefront per pair,
+// all modes, static LDS).
 struct BandPlan {
   int P = 1, nuc = 1;
   size_t lds = 0;
 };
 BandPlan band_rotate_plan(int prec, int nw, int nm);
-// kernel instance of a band count: Nw rounded up to a multiple of 4
+// kernel instance of a band count: -16 or -32 (the padded size) for the
+// matrix-core kernel, else Nw rounded up to a multiple of 4 (row kernel)
 int band_rotate_class(int nw);
+// whether the rotations of this band count run on the matrix cores
+// (8 < Nw <= 32; band_rotate keeps the row kernel for a band window and for
+// the Wannier-gauge output).  Loss partials stay one per pair either way.
+bool band_rotate_on_mfma(int nw);
 
 // grouped launches over many systems: block b belongs to the job with the
 // largest block_base <= b (jobs sorted by block_base)

@@ -9,6 +9,7 @@
 // rows of a chunk in LDS; it is HBM-bound at Nw = 8 and VALU-bound from
 // Nw of about 16 up.  Larger bands use pair-stacked GEMMs instead.
 #include "kernels.h"
+#include "mfma.h"
 
 namespace ephw {
 namespace {
@@ -452,6 +453,219 @@ __device__ __forceinline__ void band_rows_body(const BandRotateArgs& a, int P, i
   }
 }
 
+// Band rotations on the matrix cores for 8 < Nw <= 32 (no band window):
+// one wavefront per (k, q) pair, looping over its modes.  Per mode the two
+// complex products T = W_nu V(k) and g_nu = V(k+q)^dagger T run as 16x16
+// MFMA blocks of an NP x NP problem (NP = 16 or 32, rows and columns past Nw
+// zero; K steps past Nw skipped), each complex block product four real
+// MFMAs per K step of 4 (the minus sign of the complex product on a negated
+// operand).  T goes from the MFMA output layout to the B-operand layout of
+// the second product through the wave's own LDS tile.  V(k) (B operand of the
+// first product) and V(k+q)^dagger (A operand of the second) stay in
+// registers for all modes of the pair.  Epilogues as in the row kernel: g
+// rows stored, band sums and the pair's weighted |g|^2 summed in a fixed
+// order (lane butterflies).
+constexpr int kRotMfmaWaves = 4;
+
+template <typename T, int NB>
+struct RotMfmaTile {
+  static constexpr int NP = 16 * NB, LDT = NP + 1;
+  T t[kRotMfmaWaves][NP * LDT];   // per wave: one part of T as [NP][NP + 1]
+};
+
+template <typename T, int NB>
+__device__ __forceinline__ void band_mfma_body(const BandRotateArgs& a, int64_t kblk, int iq,
+                                               RotMfmaTile<T, NB>& tile) {
+  using M = Mfma<T>;
+  using V4 = typename M::v4;
+  constexpr int NP = 16 * NB, NS = NP / 4, LDT = NP + 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int c = lane & 15, g = lane >> 4;
+  const int64_t ik = kblk * kRotMfmaWaves + wave;   // local k of the tile (or pair)
+  if (ik >= a.nk_tile) return;   // no barrier below: a whole wave leaves together
+  const int nw = a.nw, nm = a.nm, nw2 = nw * nw, nsl = (nw + 3) / 4;
+  const int64_t E = (int64_t)nm * nw2;
+  const bool pairs = a.pair_k != nullptr;
+  const int64_t nset = pairs ? a.nk_set : a.nk;
+  const int64_t kl = a.k0 + ik;
+  int64_t kv = kl;
+  if (pairs) {
+    kv = a.pair_k[kl];
+    if (kv < 0 || kv >= nset) {
+      if (lane == 0) atomicOr(a.status, kStatusIndex);
+      kv = 0;
+    }
+  }
+  const T* Vk = static_cast<const T*>(a.Vk);
+  const T* Vq;
+  if (a.kq_index) {
+    int64_t id = a.kq_index[(int64_t)iq * a.nk + kl];
+    if (id < 0 || id >= nset) {
+      if (lane == 0) atomicOr(a.status, kStatusIndex);
+      id = 0;
+    }
+    Vq = Vk + 2 * id * nw2;
+  } else {
+    Vq = static_cast<const T*>(a.Vkq) + 2 * ((int64_t)iq * a.nk + kl) * nw2;
+  }
+  const T* Vkk = Vk + 2 * kv * nw2;
+  // V(k) as the B operand: B[kk][j] = V(k)[kk][j], kk = 4s + g, j = 16 jb + c
+  T bre[NB][NS], bim[NB][NS];
+  // V(k+q)^dagger as the A operand: A[i][kk] = conj(V(k+q)[kk][i]), i = 16 ib + c
+  T are[NB][NS], aim[NB][NS];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int st = 0; st < NS; ++st) {
+      const int kk = 4 * st + g, jj = 16 * b + c;
+      const bool ok = kk < nw && jj < nw;
+      bre[b][st] = ok ? Vkk[2 * (kk * nw + jj)] : T(0);
+      bim[b][st] = ok ? Vkk[2 * (kk * nw + jj) + 1] : T(0);
+      are[b][st] = ok ? Vq[2 * (kk * nw + jj)] : T(0);
+      aim[b][st] = ok ? -Vq[2 * (kk * nw + jj) + 1] : T(0);
+    }
+  const T* W = static_cast<const T*>(a.W) + 2 * ((ik * (int64_t)a.qb + iq) * E);
+  const int64_t pair_row = (int64_t)iq * a.nk + kl;   // row of g_out / band_sum
+  const bool want_g = (a.flags & EPHW_OUT_G) && a.g_out;
+  const bool want_t = (a.flags & EPHW_OUT_BAND_SUM) && a.band_sum;
+  const bool want_l = (a.flags & EPHW_OUT_LOSS) && a.loss_partial;
+  uint64_t lbase = 0;
+  if (want_l)
+    lbase = pairs ? ((uint64_t)(a.q_global0 + a.pair_q[kl]) * (uint64_t)nset + (uint64_t)kv) * (uint64_t)E
+                  : ((uint64_t)(a.q_global0 + iq) * (uint64_t)a.nk + (uint64_t)kl) * (uint64_t)E;
+  T* Tl = tile.t[wave];
+  double lsum = 0.0;
+  for (int nu = 0; nu < nm; ++nu) {
+    const T* Wn = W + 2 * (int64_t)nu * nw2;
+    // W_nu as the A operand: A[i][kk] = W[i][kk], i = 16 ib + c, kk = 4s + g
+    T wre[NB][NS], wim[NB][NS];
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int st = 0; st < NS; ++st) {
+        const int ii = 16 * b + c, kk = 4 * st + g;
+        const bool ok = ii < nw && kk < nw;
+        wre[b][st] = ok ? Wn[2 * (ii * nw + kk)] : T(0);
+        wim[b][st] = ok ? Wn[2 * (ii * nw + kk) + 1] : T(0);
+      }
+    // T = W V(k)
+    V4 tr[NB][NB], ti[NB][NB];
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) {
+        tr[ib][jb] = V4{0, 0, 0, 0};
+        ti[ib][jb] = V4{0, 0, 0, 0};
+      }
+#pragma unroll
+    for (int st = 0; st < NS; ++st)
+      if (st < nsl)   // k steps past Nw hold zeros only
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+          tr[ib][jb] = M::op(wre[ib][st], bre[jb][st], tr[ib][jb]);
+          ti[ib][jb] = M::op(wre[ib][st], bim[jb][st], ti[ib][jb]);
+          tr[ib][jb] = M::op(-wim[ib][st], bim[jb][st], tr[ib][jb]);
+          ti[ib][jb] = M::op(wim[ib][st], bre[jb][st], ti[ib][jb]);
+        }
+    // T from the output layout to the B-operand layout through the wave's LDS
+    // tile, the real parts first, then the imaginary parts.  The wave's LDS
+    // accesses complete in order: the fences only keep the compiler from
+    // moving reads above the writes they depend on (or writes above the reads
+    // of the previous part).
+    T tre[NB][NS], tim[NB][NS];
+#pragma unroll
+    for (int part = 0; part < 2; ++part) {
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            Tl[(16 * ib + M::row(g, v)) * LDT + 16 * jb + c] = part ? ti[ib][jb][v] : tr[ib][jb][v];
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+          const T x = Tl[(4 * st + g) * LDT + 16 * jb + c];
+          if (part) tim[jb][st] = x;
+          else tre[jb][st] = x;
+        }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    }
+    // g = V(k+q)^dagger T
+    V4 gr[NB][NB], gi[NB][NB];
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) {
+        gr[ib][jb] = V4{0, 0, 0, 0};
+        gi[ib][jb] = V4{0, 0, 0, 0};
+      }
+#pragma unroll
+    for (int st = 0; st < NS; ++st)
+      if (st < nsl)
+#pragma unroll
+      for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+        for (int jb = 0; jb < NB; ++jb) {
+          gr[ib][jb] = M::op(are[ib][st], tre[jb][st], gr[ib][jb]);
+          gi[ib][jb] = M::op(are[ib][st], tim[jb][st], gi[ib][jb]);
+          gr[ib][jb] = M::op(-aim[ib][st], tim[jb][st], gr[ib][jb]);
+          gi[ib][jb] = M::op(aim[ib][st], tre[jb][st], gi[ib][jb]);
+        }
+    // epilogues of the mode
+    double tsum = 0.0;
+#pragma unroll
+    for (int ib = 0; ib < NB; ++ib)
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int m = 16 * ib + M::row(g, v), n = 16 * jb + c;
+          if (m < nw && n < nw) {
+            const T re = gr[ib][jb][v], im = gi[ib][jb][v];
+            const int64_t e = (int64_t)nu * nw2 + (int64_t)m * nw + n;
+            if (want_g) {
+              T* go = static_cast<T*>(a.g_out) + 2 * (pair_row * E + e);
+              go[0] = re;
+              go[1] = im;
+            }
+            const double m2 = (double)re * (double)re + (double)im * (double)im;
+            tsum += m2;
+            if (want_l) lsum += loss_weight(a.loss_seed, lbase + (uint64_t)e) * m2;
+          }
+        }
+    if (want_t) {
+      for (int off = 32; off > 0; off >>= 1) tsum += __shfl_xor(tsum, off, 64);
+      if (lane == 0) a.band_sum[pair_row * nm + nu] = tsum;
+    }
+  }
+  if (want_l) {
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
+    if (lane == 0) a.loss_partial[(int64_t)iq * a.nk_tile + ik] = lsum;
+  }
+}
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(64 * kRotMfmaWaves) band_rotate_mfma_kernel(BandRotateArgs a) {
+  __shared__ RotMfmaTile<T, NB> tile;
+  band_mfma_body<T, NB>(a, blockIdx.x, blockIdx.y, tile);
+}
+
+template <typename T, int NB>
+__global__ void __launch_bounds__(64 * kRotMfmaWaves) band_rotate_mfma_grouped_kernel(
+    const BandRotateJob* __restrict__ jobs, int n) {
+  __shared__ RotMfmaTile<T, NB> tile;
+  const int64_t b = blockIdx.x;
+  const BandRotateJob j = jobs[find_job(jobs, n, b)];
+  const int64_t local = b - j.block_base;
+  const int64_t kb = ceil_div(j.args.nk_tile, (int64_t)kRotMfmaWaves);
+  band_mfma_body<T, NB>(j.args, local % kb, (int)(local / kb), tile);
+}
+
 template <typename T, int NWB>
 __global__ void __launch_bounds__(kRotThreads) band_rotate_kernel(BandRotateArgs a, int P, int nuc) {
   extern __shared__ unsigned char smem_raw[];
@@ -609,6 +823,8 @@ BandKernel<T> band_kernel(int nwb) {
 template <typename T>
 BandGroupedKernel<T> band_grouped_kernel(int nwb) {
   switch (nwb) {
+    case -16: return band_rotate_mfma_grouped_kernel<T, 1>;
+    case -32: return band_rotate_mfma_grouped_kernel<T, 2>;
     case 4: return band_rotate_grouped_kernel<T, 4>;
     case 8: return band_rotate_grouped_kernel<T, 8>;
     case 12: return band_rotate_grouped_kernel<T, 12>;
@@ -620,11 +836,7 @@ BandGroupedKernel<T> band_grouped_kernel(int nwb) {
   }
 }
 
-}  // namespace
-
-int band_rotate_class(int nw) { return 4 * (int)ceil_div(nw, 4); }
-
-BandPlan band_rotate_plan(int prec, int nw, int nm) {
+BandPlan band_rows_plan(int prec, int nw, int nm) {
   BandPlan pl;
   const int rows = nm * nw;
   if (rows <= kRotThreads) {
@@ -651,6 +863,27 @@ BandPlan band_rotate_plan(int prec, int nw, int nm) {
   return pl;
 }
 
+}  // namespace
+
+bool band_rotate_on_mfma(int nw) { return nw > 8 && nw <= 32; }
+
+int band_rotate_class(int nw) {
+  if (band_rotate_on_mfma(nw)) return nw <= 16 ? -16 : -32;
+  return 4 * (int)ceil_div(nw, 4);
+}
+
+BandPlan band_rotate_plan(int prec, int nw, int nm) {
+  if (band_rotate_on_mfma(nw)) {
+    BandPlan pl;
+    pl.P = kRotMfmaWaves;
+    pl.nuc = nm;
+    pl.lds = 0;
+    return pl;
+  }
+  return band_rows_plan(prec, nw, nm);
+}
+
+
 ephw_status band_rotate(int prec, const BandRotateArgs& a, hipStream_t s) {
   if (a.nk_tile <= 0 || a.qb <= 0) return EPHW_OK;
   if (a.nw > 32 || a.nw < 1) {
@@ -661,13 +894,30 @@ ephw_status band_rotate(int prec, const BandRotateArgs& a, hipStream_t s) {
     set_error("band_rotate: the band window needs the rotations and 0 <= band_lo, band_lo + band_n <= nw");
     return EPHW_EINVAL;
   }
-  const BandPlan pl = band_rotate_plan(prec, a.nw, a.nm);
+  if (band_rotate_on_mfma(a.nw) && a.Vk && a.band_n == 0) {
+    const int64_t nbk = ceil_div(a.nk_tile, (int64_t)kRotMfmaWaves);
+    if (nbk > 0x7fffffff || a.qb > 65535) {
+      set_error("band_rotate: grid too large");
+      return EPHW_EUNSUPPORTED;
+    }
+    const dim3 grid((unsigned)nbk, (unsigned)a.qb), block(64 * kRotMfmaWaves);
+    if (prec == 0) {
+      if (a.nw <= 16) hipLaunchKernelGGL((band_rotate_mfma_kernel<double, 1>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((band_rotate_mfma_kernel<double, 2>), grid, block, 0, s, a);
+    } else {
+      if (a.nw <= 16) hipLaunchKernelGGL((band_rotate_mfma_kernel<float, 1>), grid, block, 0, s, a);
+      else hipLaunchKernelGGL((band_rotate_mfma_kernel<float, 2>), grid, block, 0, s, a);
+    }
+    EPHW_CHECK_LAUNCH();
+    return EPHW_OK;
+  }
+  const BandPlan pl = band_rows_plan(prec, a.nw, a.nm);
   const int64_t kb = ceil_div(a.nk_tile, (int64_t)pl.P);
   if (kb > 0x7fffffff || a.qb > 65535) {
     set_error("band_rotate: grid too large");
     return EPHW_EUNSUPPORTED;
   }
-  const int nwb = band_rotate_class(a.nw);
+  const int nwb = 4 * (int)ceil_div(a.nw, 4);
   if (prec == 0) {
     auto k = band_kernel<double>(nwb);
     if (pl.lds > 65536)

@@ -23,9 +23,9 @@ def run():
     return Runner()
 
 
-def small_batch(count=6, seed=3):
+def small_batch(count=6, seed=3, max_grid=5):
     # heterogeneous shapes from the batch generator, capped small for the oracle
-    return synth.batch_systems(seed=seed, count=count, max_grid=5, g_cap_bytes=24 * 2 ** 20)
+    return synth.batch_systems(seed=seed, count=count, max_grid=max_grid, g_cap_bytes=24 * 2 ** 20)
 
 
 def make_items(run, works, flags):
@@ -49,16 +49,21 @@ def make_items(run, works, flags):
     return items, keep
 
 
-def test_batch_matches_oracle_and_replays(run, tmp_path):
+@pytest.mark.parametrize("seed,max_grid", [(3, 5), (25, 4)])
+def test_batch_matches_oracle_and_replays(run, tmp_path, seed, max_grid):
     """Every item of a heterogeneous batch against the oracle on ALL of its
     pairs, through quantities that depend on the eigenvectors V(k), V(k+q):
     the gauge-invariant block sums of the batch's own stored g (a wrong V,
     k+q index or item offset mixes non-degenerate blocks) and the batch's own
     weighted loss (the weights differ per (nu, m, n) element).  The band sums
-    T_nu, which any unitary V leaves unchanged, are checked beside them."""
+    T_nu, which any unitary V leaves unchanged, are checked beside them.
+    Seed 3 draws band counts 4..7 (row kernel), seed 25 also Nw = 9 and 13
+    (the matrix-core rotations, one grouped launch for both)."""
     import torch
     from paper_2603_10295_amd import ephw
-    works = small_batch()
+    works = small_batch(seed=seed, max_grid=max_grid)
+    if seed == 25:
+        assert sorted(w.system.nw for w in works if w.system.nw > 8) == [9, 13]
     assert len({(w.system.nw, w.system.nm, w.system.ne) for w in works}) > 3   # heterogeneous
     items, keep = make_items(run, works, ephw.OUT_G | ephw.OUT_BAND_SUM | ephw.OUT_LOSS)
     cache = str(tmp_path / "tune.jsonl")
