@@ -933,11 +933,42 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
     return;
   }
   // --- epilogue: lane holds column lcol of every block, rows per Mfma<T>::row --
-  const int64_t tb = j.tblock;
-  auto c_index = [&](int64_t row, int64_t col) -> int64_t {
-    return tb > 0 ? (row / tb) * j.ldc + col * tb + row % tb : row * j.ldc + col;
-  };
-  if (!j.loss.on) {
+  double part = 0.0;
+  const LossEpilogue& L = j.loss;
+  if constexpr (sizeof(T) == 8) {
+    // FP64: offsets per element (the 64x224 FP64 tiles sit at the register
+    // limit; hoisting the row offsets out of the column loop spills there)
+    const int64_t tb = j.tblock;
+    auto c_index = [&](int64_t row, int64_t col) -> int64_t {
+      return tb > 0 ? (row / tb) * j.ldc + col * tb + row % tb : row * j.ldc + col;
+    };
+    if (!j.loss.on) {
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int jj = 0; jj < FN; ++jj) {
+          const int64_t col = n0 + wn * TN + jj * 16 + lcol;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int64_t row = m0 + wm * TM + i * 16 + Mfma<T>::row(lrow, v);
+            if (row < M && col < N) {
+              V2* c = reinterpret_cast<V2*>(j.C + 2 * c_index(row, col));
+              V2 val{acc_r[i][jj][v], acc_i[i][jj][v]};
+              if (j.accumulate) val += *c;
+              *c = val;
+            }
+          }
+        }
+      return;
+    }
+    // weighted |c|^2: element index ((((q nk + k) nm + nu) nw + m) nw + n)
+    const int64_t per_q = L.layout == 0 ? (int64_t)L.qb * L.nm : (int64_t)L.qb;
+    const int64_t il = j.batch / per_q;
+    const int64_t iq = L.layout == 0 ? (j.batch / L.nm) % L.qb : j.batch % L.qb;
+    const int64_t nu = L.layout == 0 ? j.batch % L.nm : 0;
+    const uint64_t nw2 = (uint64_t)L.nw * (uint64_t)L.nw;
+    const uint64_t base =
+        (((uint64_t)(L.q0 + iq) * (uint64_t)L.nk + (uint64_t)(L.k0 + il)) * (uint64_t)L.nm + (uint64_t)nu) * nw2;
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -947,53 +978,133 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
         for (int v = 0; v < 4; ++v) {
           const int64_t row = m0 + wm * TM + i * 16 + Mfma<T>::row(lrow, v);
           if (row < M && col < N) {
-            V2* c = reinterpret_cast<V2*>(j.C + 2 * c_index(row, col));
-            V2 val{acc_r[i][jj][v], acc_i[i][jj][v]};
-            if (j.accumulate) val += *c;
-            *c = val;
-          }
-        }
-      }
-    return;
-  }
-  // weighted |c|^2: element index ((((q nk + k) nm + nu) nw + m) nw + n)
-  const LossEpilogue& L = j.loss;
-  const int64_t per_q = L.layout == 0 ? (int64_t)L.qb * L.nm : (int64_t)L.qb;
-  const int64_t il = j.batch / per_q;
-  const int64_t iq = L.layout == 0 ? (j.batch / L.nm) % L.qb : j.batch % L.qb;
-  const int64_t nu = L.layout == 0 ? j.batch % L.nm : 0;
-  const uint64_t nw2 = (uint64_t)L.nw * (uint64_t)L.nw;
-  const uint64_t base =
-      (((uint64_t)(L.q0 + iq) * (uint64_t)L.nk + (uint64_t)(L.k0 + il)) * (uint64_t)L.nm + (uint64_t)nu) * nw2;
-  double part = 0.0;
-#pragma unroll
-  for (int i = 0; i < FM; ++i)
-#pragma unroll
-    for (int jj = 0; jj < FN; ++jj) {
-      const int64_t col = n0 + wn * TN + jj * 16 + lcol;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t row = m0 + wm * TM + i * 16 + Mfma<T>::row(lrow, v);
-        if (row < M && col < N) {
-          const T re = acc_r[i][jj][v], im = acc_i[i][jj][v];
-          const uint64_t el = L.layout == 0
-                                  ? (uint64_t)(row * L.nw + col)
-                                  : (uint64_t)(row / L.nw) * nw2 + (uint64_t)col * L.nw + (uint64_t)(row % L.nw);
-          const double w = splitmix_weight(L.seed, base + el);
-          part += w * ((double)re * (double)re + (double)im * (double)im);
-          if (L.store) {
-            T* c = j.C + 2 * c_index(row, col);
-            if (L.grad_scale) {
-              c[0] = (T)(2.0 * w) * re;
-              c[1] = (T)(2.0 * w) * im;
-            } else {
-              c[0] = re;
-              c[1] = im;
+            const T re = acc_r[i][jj][v], im = acc_i[i][jj][v];
+            const uint64_t el = L.layout == 0
+                                    ? (uint64_t)(row * L.nw + col)
+                                    : (uint64_t)(row / L.nw) * nw2 + (uint64_t)col * L.nw + (uint64_t)(row % L.nw);
+            const double w = splitmix_weight(L.seed, base + el);
+            part += w * ((double)re * (double)re + (double)im * (double)im);
+            if (L.store) {
+              T* c = j.C + 2 * c_index(row, col);
+              if (L.grad_scale) {
+                c[0] = (T)(2.0 * w) * re;
+                c[1] = (T)(2.0 * w) * im;
+              } else {
+                c[0] = re;
+                c[1] = im;
+              }
             }
           }
         }
       }
+  } else {
+    // C offset of element (row, col) = row_off(row) + col * cstep: the row part
+    // takes one division per row of the lane, not one per element
+    const int64_t tb = j.tblock;
+    const int64_t cstep = tb > 0 ? tb : 1;
+    auto row_off = [&](int64_t row) -> int64_t {
+      if (tb > 0) {
+        const int64_t blk = row / tb;
+        return blk * j.ldc + (row - blk * tb);
+      }
+      return row * j.ldc;
+    };
+    if (!j.loss.on) {
+      if constexpr (sizeof(T) == 4) {
+        // Block-transposed FP32 output: the four rows 4g..4g+3 of a lane are
+        // consecutive in C (rows of one Nw block, Nw a multiple of 4), so the
+        // lane stores them as two 16-byte chunks.
+        if (tb > 0 && tb % 4 == 0 && j.ldc % 4 == 0 && (reinterpret_cast<uintptr_t>(j.C) & 31) == 0 &&
+            !j.accumulate) {
+#pragma unroll
+          for (int i = 0; i < FM; ++i) {
+            const int64_t row0 = m0 + wm * TM + i * 16 + Mfma<T>::row(lrow, 0);
+            const int64_t ro = row_off(row0);
+            const bool all4 = row0 + 3 < M;
+#pragma unroll
+            for (int jj = 0; jj < FN; ++jj) {
+              const int64_t col = n0 + wn * TN + jj * 16 + lcol;
+              if (col >= N) continue;
+              T* c = j.C + 2 * (ro + col * cstep);
+              if (all4) {
+                reinterpret_cast<V4*>(c)[0] = V4{acc_r[i][jj][0], acc_i[i][jj][0], acc_r[i][jj][1], acc_i[i][jj][1]};
+                reinterpret_cast<V4*>(c)[1] = V4{acc_r[i][jj][2], acc_i[i][jj][2], acc_r[i][jj][3], acc_i[i][jj][3]};
+              } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                  if (row0 + v < M) reinterpret_cast<V2*>(c)[v] = V2{acc_r[i][jj][v], acc_i[i][jj][v]};
+              }
+            }
+          }
+          return;
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int64_t row = m0 + wm * TM + i * 16 + Mfma<T>::row(lrow, v);
+          if (row >= M) continue;
+          const int64_t ro = row_off(row);
+#pragma unroll
+          for (int jj = 0; jj < FN; ++jj) {
+            const int64_t col = n0 + wn * TN + jj * 16 + lcol;
+            if (col < N) {
+              V2* c = reinterpret_cast<V2*>(j.C + 2 * (ro + col * cstep));
+              V2 val{acc_r[i][jj][v], acc_i[i][jj][v]};
+              if (j.accumulate) val += *c;
+              *c = val;
+            }
+          }
+        }
+      return;
     }
+    // weighted |c|^2: element index ((((q nk + k) nm + nu) nw + m) nw + n)
+    const int64_t per_q = L.layout == 0 ? (int64_t)L.qb * L.nm : (int64_t)L.qb;
+    const int64_t il = j.batch / per_q;
+    const int64_t iq = L.layout == 0 ? (j.batch / L.nm) % L.qb : j.batch % L.qb;
+    const int64_t nu = L.layout == 0 ? j.batch % L.nm : 0;
+    const uint64_t nw2 = (uint64_t)L.nw * (uint64_t)L.nw;
+    const uint64_t base =
+        (((uint64_t)(L.q0 + iq) * (uint64_t)L.nk + (uint64_t)(L.k0 + il)) * (uint64_t)L.nm + (uint64_t)nu) * nw2;
+    // element index of (row, col) = base + ebase(row) + col * estep
+    const uint64_t estep = L.layout == 0 ? 1 : (uint64_t)L.nw;
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t row = m0 + wm * TM + i * 16 + Mfma<T>::row(lrow, v);
+        if (row >= M) continue;
+        const int64_t ro = L.store ? row_off(row) : 0;
+        uint64_t eb;
+        if (L.layout == 0) {
+          eb = (uint64_t)row * L.nw;
+        } else {
+          const int64_t b = row / L.nw;
+          eb = (uint64_t)b * nw2 + (uint64_t)(row - b * L.nw);
+        }
+        eb += base;
+#pragma unroll
+        for (int jj = 0; jj < FN; ++jj) {
+          const int64_t col = n0 + wn * TN + jj * 16 + lcol;
+          if (col < N) {
+            const T re = acc_r[i][jj][v], im = acc_i[i][jj][v];
+            const double w = splitmix_weight(L.seed, eb + (uint64_t)col * estep);
+            part += w * ((double)re * (double)re + (double)im * (double)im);
+            if (L.store) {
+              T* c = j.C + 2 * (ro + col * cstep);
+              if (L.grad_scale) {
+                c[0] = (T)(2.0 * w) * re;
+                c[1] = (T)(2.0 * w) * im;
+              } else {
+                c[0] = re;
+                c[1] = im;
+              }
+            }
+          }
+        }
+      }
+  }
   // workgroup sum in a fixed order: waves through LDS (free after the K loop)
   for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
   double* red = reinterpret_cast<double*>(smem);
