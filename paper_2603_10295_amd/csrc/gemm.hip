@@ -96,6 +96,11 @@ __device__ __forceinline__ typename Chunk<T>::v4 load_chunk(__amdgpu_buffer_rsrc
   return __builtin_bit_cast(typename Chunk<T>::v4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
+template <int N>
+struct IntC {
+  static constexpr int value = N;
+};
+
 template <typename T, int BM, int BN, int BK, int WM, int WN>
 struct TileShape {
   static constexpr int NT = 64 * WM * WN;
@@ -830,14 +835,20 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
 
   // One BK slab of MFMAs from an LDS stage.  The four real products of every
   // block are issued product by product across all blocks, so consecutive
-  // MFMAs never depend on each other.
-  auto compute = [&](const T* st) {
+  // MFMAs never depend on each other.  NBL (compile time) column blocks of
+  // the wave are multiplied and K steps from kmax on are skipped: the
+  // one-wave-column tiles (WN = 1) leave out a column block that lies wholly
+  // past N and the K steps of the last slab past K (their operands are the
+  // zeros of the padded loads, so skipping them changes nothing).
+  auto compute = [&](const T* st, auto nbl, int kmax) {
+    constexpr int NBL = decltype(nbl)::value;
     const T* As = st;
     const T* Bs = st + 2 * BK * LA;
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
+      if (kk >= kmax) break;
       const int kr = kk + lrow;
-      V2 a[FM], b[FN];
+      V2 a[FM], b[NBL];
       T nai[FM];
 #pragma unroll
       for (int i = 0; i < FM; ++i) {
@@ -845,26 +856,30 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
         nai[i] = -a[i][1];
       }
 #pragma unroll
-      for (int jj = 0; jj < FN; ++jj)
+      for (int jj = 0; jj < NBL; ++jj)
         b[jj] = *reinterpret_cast<const V2*>(Bs + 2 * (kr * LB + wn * TN + jj * 16 + lcol));
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int jj = 0; jj < FN; ++jj) acc_r[i][jj] = Mfma<T>::op(a[i][0], b[jj][0], acc_r[i][jj]);
+        for (int jj = 0; jj < NBL; ++jj) acc_r[i][jj] = Mfma<T>::op(a[i][0], b[jj][0], acc_r[i][jj]);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int jj = 0; jj < FN; ++jj) acc_i[i][jj] = Mfma<T>::op(a[i][0], b[jj][1], acc_i[i][jj]);
+        for (int jj = 0; jj < NBL; ++jj) acc_i[i][jj] = Mfma<T>::op(a[i][0], b[jj][1], acc_i[i][jj]);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int jj = 0; jj < FN; ++jj) acc_r[i][jj] = Mfma<T>::op(nai[i], b[jj][1], acc_r[i][jj]);
+        for (int jj = 0; jj < NBL; ++jj) acc_r[i][jj] = Mfma<T>::op(nai[i], b[jj][1], acc_r[i][jj]);
 #pragma unroll
       for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int jj = 0; jj < FN; ++jj) acc_i[i][jj] = Mfma<T>::op(a[i][1], b[jj][0], acc_i[i][jj]);
+        for (int jj = 0; jj < NBL; ++jj) acc_i[i][jj] = Mfma<T>::op(a[i][1], b[jj][0], acc_i[i][jj]);
     }
   };
+  // the skipping form: FP32 tiles with one wave column (all waves then skip
+  // the same blocks, so no wave waits for another at the slab barrier)
+  constexpr bool SKIP = sizeof(T) == 4 && WN == 1 && FN > 1 && KBLK == 0 && BANDNW == 0;
+  const bool last_col_dead = SKIP && n0 + (FN - 1) * 16 >= N;
 
   // K-blocked accumulation (the compensated FP32 form): the MFMA
   // accumulators start from zero every KBLK slabs and each block's partial
@@ -896,18 +911,44 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
 
   // K loop: one barrier per slab (see the pipeline note above)
   const int64_t nslab = (K + BK - 1) / BK;
-  load(0);
-  stash(smem, 0);
-  __syncthreads();
-  for (int64_t sl = 0; sl < nslab; ++sl) {
-    const bool more = sl + 1 < nslab;
-    if (more) load((sl + 1) * BK);
-    compute(smem + (sl & 1) * S::stage_elems);
-    if constexpr (KBLK > 0) {
-      if ((sl + 1) % KBLK == 0) fold();
-    }
-    if (more) stash(smem + ((sl + 1) & 1) * S::stage_elems, (sl + 1) * BK);
+  // (the skipping tiles run one K loop per column-block count; a branch
+  // between two compute forms inside one loop made the compiler spill)
+  auto kloop = [&](auto nbl) {
+    load(0);
+    stash(smem, 0);
     __syncthreads();
+    for (int64_t sl = 0; sl < nslab; ++sl) {
+      const bool more = sl + 1 < nslab;
+      if (more) load((sl + 1) * BK);
+      // the K steps of the last slab past K are skipped where columns are
+      const int kmax = SKIP ? (int)(K - sl * BK < BK ? K - sl * BK : BK) : BK;
+      compute(smem + (sl & 1) * S::stage_elems, nbl, kmax);
+      if constexpr (KBLK > 0) {
+        if ((sl + 1) % KBLK == 0) fold();
+      }
+      if (more) stash(smem + ((sl + 1) & 1) * S::stage_elems, (sl + 1) * BK);
+      __syncthreads();
+    }
+  };
+  if constexpr (SKIP) {
+    if (last_col_dead)
+      kloop(IntC<(SKIP ? FN - 1 : FN)>{});
+    else
+      kloop(IntC<FN>{});
+  } else {
+    load(0);
+    stash(smem, 0);
+    __syncthreads();
+    for (int64_t sl = 0; sl < nslab; ++sl) {
+      const bool more = sl + 1 < nslab;
+      if (more) load((sl + 1) * BK);
+      compute(smem + (sl & 1) * S::stage_elems, IntC<FN>{}, BK);
+      if constexpr (KBLK > 0) {
+        if ((sl + 1) % KBLK == 0) fold();
+      }
+      if (more) stash(smem + ((sl + 1) & 1) * S::stage_elems, (sl + 1) * BK);
+      __syncthreads();
+    }
   }
   if constexpr (KBLK > 0) {
     // the last (partial) block, then the blocked sum back into the accumulators
@@ -1628,7 +1669,7 @@ ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream) {
   plain_shape(prec, p.M, p.N, &bm, &bn);
   // the 64x224 tile addresses a whole slab from one base; very long rows
   // (e.g. g(Re,Rp) as the B operand) take the default tile instead
-  bool wide = bn == 224 && (prec == 0 ? fits_any<double, 64, 224, 16, 2, 2>(p) : fits_any<float, 64, 224, 16, 2, 2>(p));
+  bool wide = bn == 224 && (prec == 0 ? fits_any<double, 64, 224, 16, 2, 2>(p) : fits_any<float, 64, 224, 16, 4, 1>(p));
   const bool small = prec != 0 && bm == 64 && bn == 64 && fits_any<float, 64, 64, 16, 2, 2>(p);
   if (prec != 0 && bm == 64 && bn == 64 && !small && p.loss.on) {
     set_error("cgemm: leading dimension too large for the 64x64 tile's 32-bit lane offsets");
@@ -1643,7 +1684,7 @@ ephw_status cgemm(int prec, const GemmParams& p, hipStream_t stream) {
     if (wide) return dispatch_trans<double, 64, 224, 16, 2, 2, false, 1>(p, stream);
     return dispatch_trans<double, 64, 64, 8, 2, 2, false, 2>(p, stream);
   }
-  if (wide) return dispatch_trans<float, 64, 224, 16, 2, 2, false, 2>(p, stream);
+  if (wide) return dispatch_trans<float, 64, 224, 16, 4, 1, false, 2>(p, stream);
   if (small) return dispatch_trans<float, 64, 64, 16, 2, 2, false, 4>(p, stream);
   return dispatch_trans<float, 128, 128, 16, 2, 2, false, 2>(p, stream);
 }
