@@ -270,7 +270,8 @@ def bench_batch(args):
     torch.cuda.synchronize()
     t_tune = time.perf_counter()
     b = ephw.Batch(ctx, items, tune=True, tune_cache=args.tune_cache or None)
-    log(f"planned in {time.perf_counter() - t_tune:.1f}s: {b.stats()}")
+    log(f"planned in {time.perf_counter() - t_tune:.1f}s: {b.stats()}, "
+        f"{sum(b.solo(i) for i in range(len(items)))} of {len(items)} systems in rounds of their own")
     for _ in range(max(1, args.warmup)):
         b.run()
     ctx.check()
@@ -281,7 +282,7 @@ def bench_batch(args):
     torch.cuda.synchronize()
     tb = (time.perf_counter() - t0) / args.steps
     ctx.check()
-    stats, shapes = b.stats(), [b.shape(i) for i in range(len(items))]
+    stats, shapes = b.stats(), [dict(b.shape(i), solo=b.solo(i)) for i in range(len(items))]
     b.close()   # release the batch's sweep buffers before the one-at-a-time runs allocate theirs
     # the same items, one system at a time (no grouping, no graph): each
     # system warmed up and timed on its own, its workspace then released

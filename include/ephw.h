@@ -488,8 +488,16 @@ typedef struct ephw_batch_options {
   int32_t use_graph;         /* 1: capture the pass into a HIP graph */
   int64_t item_workspace_bytes; /* per-item cap of the sweep buffers; 0: what the
                                    item's largest unit (128 q, every k) needs, between
-                                   1 GiB and 8 GiB, scaled down together when the items
-                                   would take more than half of the free device memory */
+                                   1 GiB and 8 GiB, within workspace_budget_bytes (below) */
+  int64_t workspace_budget_bytes; /* with item_workspace_bytes = 0: device memory the
+                                   sweep buffers may take together; 0: half of the free
+                                   device memory.  When the items' caps add up to more,
+                                   the largest items run solo (their rounds after the
+                                   grouped ones, one item at a time, sharing one sweep
+                                   region) until the rest fit beside that region; the
+                                   remaining caps are scaled down only if even that
+                                   does not fit.  Results do not depend on which items
+                                   run solo. */
 } ephw_batch_options;
 /* Plan a batch: validates items, tunes shapes, allocates the workspace.
    All items must share one precision; nw <= 32 and nm <= 24 per system. */
@@ -502,6 +510,9 @@ ephw_status ephw_batch_shape(const ephw_batch* b, int32_t i, int32_t* q_batch, i
                              int32_t* cfg_rp, int32_t* cfg_re);
 /* number of rounds and of kernel launches in one pass */
 ephw_status ephw_batch_stats(const ephw_batch* b, int32_t* rounds, int32_t* launches);
+/* *solo = 1 if item i runs its rounds on its own (see workspace_budget_bytes), else 0;
+   EPHW_EINVAL for a NULL batch or output, or no such item */
+ephw_status ephw_batch_solo(const ephw_batch* b, int32_t i, int32_t* solo);
 ephw_status ephw_batch_free(ephw_batch* b);
 
 const char* ephw_status_string(ephw_status s);

@@ -42,14 +42,20 @@ struct ItemPlan {
   void* Gnu = nullptr;     // T [ne][qb*E]
   void* W = nullptr;       // T [kt][qb*E]
   double* lossp = nullptr; // [qb*kt]
-  size_t bytes() const;
+  // runs its units in rounds of its own, after the grouped rounds, with the
+  // sweep buffers (G, Gnu, W, lossp) in a region shared by all such items
+  bool solo = false;
+  size_t q_bytes() const;      // per-q buffers, computed once per pass
+  size_t sweep_bytes() const;  // buffers of one unit
+  size_t bytes() const { return q_bytes() + sweep_bytes(); }
   int64_t units() const { return nqb * nkt; }
 };
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct Launch {
-  enum Kind { PHASE, GEMM, EIGH, MODEVEC, MODE, BAND, SUM } kind;
+  enum Kind { PHASE, GEMM, PGEMM, EIGH, MODEVEC, MODE, BAND, SUM } kind;
+  GemmParams gp;               // PGEMM: one plain GEMM (a solo item's phase sum)
   int prec = 0;
   int cfg = 0;                 // GEMM: tile configuration of every problem in the launch
   int grid = 0;                // GEMM: persistent workgroups
@@ -87,7 +93,7 @@ struct ephw_batch {
 
 namespace {
 
-size_t ItemPlan::bytes() const {
+size_t ItemPlan::q_bytes() const {
   const size_t cs = csize(sys->g_kind);
   size_t b = 0;
   b += align256((size_t)nq * np * cs);
@@ -96,6 +102,12 @@ size_t ItemPlan::bytes() const {
   b += align256((size_t)nq * nm * 8);
   b += align256((size_t)nq * nm * nm * 16);
   b += align256((size_t)nq * nm * nm * cs);
+  return b;
+}
+
+size_t ItemPlan::sweep_bytes() const {
+  const size_t cs = csize(sys->g_kind);
+  size_t b = 0;
   b += align256((size_t)qb * ne * E * cs);
   b += align256((size_t)qb * ne * E * cs);
   b += align256((size_t)kt * qb * E * cs);
@@ -103,8 +115,10 @@ size_t ItemPlan::bytes() const {
   return b;
 }
 
-void carve(ItemPlan& it, char* base) {
+// per-q buffers at qbase (q_bytes), sweep buffers at sbase (sweep_bytes)
+void carve(ItemPlan& it, char* qbase, char* sbase) {
   const size_t cs = csize(it.sys->g_kind);
+  char* base = qbase;
   size_t off = 0;
   auto take = [&](size_t b) {
     char* p = base + off;
@@ -117,6 +131,8 @@ void carve(ItemPlan& it, char* base) {
   it.lam = reinterpret_cast<double*>(take((size_t)it.nq * it.nm * 8));
   it.ev = reinterpret_cast<double*>(take((size_t)it.nq * it.nm * it.nm * 16));
   it.u = take((size_t)it.nq * it.nm * it.nm * cs);
+  base = sbase;
+  off = 0;
   it.G = take((size_t)it.qb * it.ne * it.E * cs);
   it.Gnu = take((size_t)it.qb * it.ne * it.E * cs);
   it.W = take((size_t)it.kt * it.qb * it.E * cs);
@@ -264,7 +280,7 @@ ephw_status tune_item(ItemPlan& it, int kind, int64_t cap, bool measure, hipStre
   for (size_t ci = 0; ci < cands.size() && rc == EPHW_OK; ++ci) {
     const int32_t q = cands[ci];
     set_shape(it, q, k_tile_for(it, q, cap));
-    carve(it, static_cast<char*>(tmp));
+    carve(it, static_cast<char*>(tmp), static_cast<char*>(tmp) + it.q_bytes());
     // phases and mode vectors of the first q batch (values only matter for timing)
     rc = phase_matrix(kind, it.in.q, std::min<int64_t>(q, it.nq), it.sys->r_p, it.sys->w_p, it.np, it.pq, st);
     if (rc == EPHW_OK) rc = hipMemsetAsync(it.u, 0, (size_t)q * it.nm * it.nm * csize(kind), st) == hipSuccess
@@ -335,6 +351,9 @@ ephw_status issue(ephw_batch* bt, hipStream_t st) {
         EPHW_TRY(cgemm_grouped(l.prec, l.cfg, static_cast<const GroupProblem*>(l.jobs), l.n, l.count,
                                (int)std::min<int64_t>(l.grid, l.count), bt->queues + l.qidx * kGroupQueues, st));
         break;
+      case Launch::PGEMM:
+        EPHW_TRY(cgemm(l.prec, l.gp, st));
+        break;
       case Launch::EIGH:
         EPHW_TRY(jacobi_eigh_grouped(static_cast<const EighJob*>(l.jobs), l.n, l.count, l.order, status, st));
         break;
@@ -378,6 +397,25 @@ void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, 
       l.count = cgemm_grouped_layout(prec, probs.data(), l.n);
       l.qidx = bt->nqueue++;
       push(l, hd.add(probs));
+    }
+  };
+  // a solo item's phase sums as plain GEMMs: the tile (or, for at most 16
+  // rows, the streaming kernel) chosen for its own shape, as one at a time
+  auto push_plain = [&](int prec, const std::vector<GroupProblem>& all) {
+    for (const GroupProblem& p : all) {
+      Launch l;
+      l.kind = Launch::PGEMM;
+      l.prec = prec;
+      l.gp.M = p.M;
+      l.gp.N = p.N;
+      l.gp.K = p.K;
+      l.gp.A = p.A;
+      l.gp.lda = p.lda;
+      l.gp.B = p.B;
+      l.gp.ldb = p.ldb;
+      l.gp.C = p.C;
+      l.gp.ldc = p.ldc;
+      bt->launches.push_back(l);
     }
   };
   // q side: phases per item, D(q) GEMMs (one grouped launch), eigensolves (one
@@ -435,143 +473,160 @@ void build_launches(ephw_batch* bt, HostDesc& hd, std::vector<std::pair<size_t, 
     l.item = (int)i;
     bt->launches.push_back(l);
   }
-  // rounds
-  int64_t rounds = 0;
-  for (auto& it : bt->items) rounds = std::max(rounds, it.units());
-  bt->rounds = (int)rounds;
-  for (int64_t r = 0; r < rounds; ++r) {
-    std::vector<GroupProblem> rp, re;
-    std::vector<ModeRotateJob> mj;
-    std::vector<BandRotateJob> bj;
-    std::vector<int> bj_cls;
-    std::vector<size_t> bj_lds;
-    std::vector<SumJob> sj;
-    int64_t mblocks = 0;
-    size_t mlds = 0;
-    for (auto& it : bt->items) {
-      if (r >= it.units()) continue;
-      const int64_t j = r / it.nkt, t = r % it.nkt;
-      const int64_t q0 = j * it.qb, nb = std::min<int64_t>(it.qb, it.nq - q0);
-      const int64_t k0 = t * it.kt, kl = std::min<int64_t>(it.kt, it.nk - k0);
-      const int64_t nw2 = (int64_t)it.nw * it.nw;
-      if (t == 0) {
-        GroupProblem p;
-        p.M = nb;
-        p.N = it.ne * it.E;
-        p.K = it.np;
-        p.A = static_cast<const char*>(it.pq) + (size_t)q0 * it.np * cs;
-        p.lda = it.np;
-        p.B = it.sys->g;
-        p.ldb = p.N;
-        p.C = it.G;
-        p.ldc = p.N;
-        p.cfg = it.cfg_rp;
-        rp.push_back(p);
-        ModeRotateJob m;
-        m.G = it.G;
-        m.u = static_cast<const char*>(it.u) + (size_t)q0 * it.nm * it.nm * cs;
-        m.Gnu = it.Gnu;
-        m.ne = it.ne;
-        m.nw2 = nw2;
-        m.qb = (int)nb;
-        m.nm = it.nm;
-        m.block_base = mblocks;
-        mblocks += nb * ceil_div(it.ne * nw2, 256);
-        mlds = std::max(mlds, (size_t)it.nm * it.nm * cs);
-        mj.push_back(m);
-      }
-      GroupProblem p;
-      p.M = kl;
-      p.N = nb * it.E;
-      p.K = it.ne;
-      p.A = static_cast<const char*>(it.ks->pk) + (size_t)k0 * it.ne * cs;
-      p.lda = it.ne;
-      p.B = it.Gnu;
-      p.ldb = p.N;
-      p.C = it.W;
-      p.ldc = p.N;
-      p.cfg = it.cfg_re;
-      re.push_back(p);
-      BandRotateJob b;
-      BandRotateArgs& br = b.args;
-      br.W = it.W;
-      br.Vk = it.ks->vt;
-      br.Vkq = nullptr;
-      br.kq_index = it.in.kq_index + q0 * it.nk;
-      br.nk = it.nk;
-      br.k0 = k0;
-      br.nk_tile = kl;
-      br.qb = (int)nb;
-      br.nm = it.nm;
-      br.nw = it.nw;
-      br.flags = it.in.flags;
-      br.g_out = (it.in.flags & EPHW_OUT_G) ? static_cast<char*>(it.in.g_out) + (size_t)q0 * it.nk * it.E * cs
-                                            : nullptr;
-      br.band_sum = (it.in.flags & EPHW_OUT_BAND_SUM) ? it.in.band_sum + q0 * it.nk * it.nm : nullptr;
-      br.loss_partial = (it.in.flags & EPHW_OUT_LOSS) ? it.lossp : nullptr;
-      br.loss_seed = it.in.loss_seed;
-      br.q_global0 = q0;
-      br.status = bt->ctx->status;
-      b.P = it.band.P;
-      b.nuc = it.band.nuc;
-      b.block_base = 0;
-      bj.push_back(b);
-      bj_cls.push_back(it.nwb);
-      bj_lds.push_back(it.band.lds);
-      if (it.in.flags & EPHW_OUT_LOSS) sj.push_back(SumJob{it.lossp, nb * kl, it.in.loss});
-    }
-    if (!rp.empty()) {
-      push_gemm(kind, rp);
-      Launch m;
-      m.kind = Launch::MODE;
-      m.n = (int)mj.size();
-      m.count = mblocks;
-      m.lds = mlds;
-      push(m, hd.add(mj));
-    }
-    {
-      push_gemm(kind, re);
-      // one band-rotation launch per kernel instance (band count rounded up
-      // to a multiple of 4) and LDS size (in 8 KB steps): a launch runs at the
-      // occupancy its largest LDS request allows
-      std::vector<std::pair<int, size_t>> keys;
-      for (size_t i = 0; i < bj.size(); ++i) {
-        const std::pair<int, size_t> key{bj_cls[i], ceil_div((int64_t)bj_lds[i], 8192)};
-        if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
-      }
-      std::sort(keys.begin(), keys.end());
-      for (const auto& key : keys) {
-        const int cls = key.first;
-        std::vector<BandRotateJob> part;
-        int64_t blocks = 0;
-        size_t lds = 0;
-        for (size_t i = 0; i < bj.size(); ++i) {
-          if (bj_cls[i] != cls || (size_t)ceil_div((int64_t)bj_lds[i], 8192) != key.second) continue;
-          BandRotateJob jb = bj[i];
-          const int64_t nblk = (int64_t)jb.args.qb * ceil_div(jb.args.nk_tile, (int64_t)jb.P);
-          jb.block_base = blocks;
-          blocks += nblk;
-          lds = std::max(lds, bj_lds[i]);
-          part.push_back(jb);
+  // rounds: the grouped items together, then each solo item on its own
+  bt->rounds = 0;
+  auto emit_rounds = [&](const std::vector<ItemPlan*>& members) {
+    int64_t rounds = 0;
+    for (ItemPlan* m : members) rounds = std::max(rounds, m->units());
+    const bool plain = members.size() == 1 && members[0]->solo;
+    bt->rounds += (int)rounds;
+    for (int64_t r = 0; r < rounds; ++r) {
+      std::vector<GroupProblem> rp, re;
+      std::vector<ModeRotateJob> mj;
+      std::vector<BandRotateJob> bj;
+      std::vector<int> bj_cls;
+      std::vector<size_t> bj_lds;
+      std::vector<SumJob> sj;
+      int64_t mblocks = 0;
+      size_t mlds = 0;
+      for (ItemPlan* mp : members) {
+        ItemPlan& it = *mp;
+        if (r >= it.units()) continue;
+        const int64_t j = r / it.nkt, t = r % it.nkt;
+        const int64_t q0 = j * it.qb, nb = std::min<int64_t>(it.qb, it.nq - q0);
+        const int64_t k0 = t * it.kt, kl = std::min<int64_t>(it.kt, it.nk - k0);
+        const int64_t nw2 = (int64_t)it.nw * it.nw;
+        if (t == 0) {
+          GroupProblem p;
+          p.M = nb;
+          p.N = it.ne * it.E;
+          p.K = it.np;
+          p.A = static_cast<const char*>(it.pq) + (size_t)q0 * it.np * cs;
+          p.lda = it.np;
+          p.B = it.sys->g;
+          p.ldb = p.N;
+          p.C = it.G;
+          p.ldc = p.N;
+          p.cfg = it.cfg_rp;
+          rp.push_back(p);
+          ModeRotateJob m;
+          m.G = it.G;
+          m.u = static_cast<const char*>(it.u) + (size_t)q0 * it.nm * it.nm * cs;
+          m.Gnu = it.Gnu;
+          m.ne = it.ne;
+          m.nw2 = nw2;
+          m.qb = (int)nb;
+          m.nm = it.nm;
+          m.block_base = mblocks;
+          mblocks += nb * ceil_div(it.ne * nw2, 256);
+          mlds = std::max(mlds, (size_t)it.nm * it.nm * cs);
+          mj.push_back(m);
         }
-        if (part.empty()) continue;
-        Launch b;
-        b.kind = Launch::BAND;
-        b.cfg = cls;
-        b.n = (int)part.size();
-        b.count = blocks;
-        b.lds = lds;
-        push(b, hd.add(part));
+        GroupProblem p;
+        p.M = kl;
+        p.N = nb * it.E;
+        p.K = it.ne;
+        p.A = static_cast<const char*>(it.ks->pk) + (size_t)k0 * it.ne * cs;
+        p.lda = it.ne;
+        p.B = it.Gnu;
+        p.ldb = p.N;
+        p.C = it.W;
+        p.ldc = p.N;
+        p.cfg = it.cfg_re;
+        re.push_back(p);
+        BandRotateJob b;
+        BandRotateArgs& br = b.args;
+        br.W = it.W;
+        br.Vk = it.ks->vt;
+        br.Vkq = nullptr;
+        br.kq_index = it.in.kq_index + q0 * it.nk;
+        br.nk = it.nk;
+        br.k0 = k0;
+        br.nk_tile = kl;
+        br.qb = (int)nb;
+        br.nm = it.nm;
+        br.nw = it.nw;
+        br.flags = it.in.flags;
+        br.g_out = (it.in.flags & EPHW_OUT_G) ? static_cast<char*>(it.in.g_out) + (size_t)q0 * it.nk * it.E * cs
+                                              : nullptr;
+        br.band_sum = (it.in.flags & EPHW_OUT_BAND_SUM) ? it.in.band_sum + q0 * it.nk * it.nm : nullptr;
+        br.loss_partial = (it.in.flags & EPHW_OUT_LOSS) ? it.lossp : nullptr;
+        br.loss_seed = it.in.loss_seed;
+        br.q_global0 = q0;
+        br.status = bt->ctx->status;
+        b.P = it.band.P;
+        b.nuc = it.band.nuc;
+        b.block_base = 0;
+        bj.push_back(b);
+        bj_cls.push_back(it.nwb);
+        bj_lds.push_back(it.band.lds);
+        if (it.in.flags & EPHW_OUT_LOSS) sj.push_back(SumJob{it.lossp, nb * kl, it.in.loss});
+      }
+      if (!rp.empty()) {
+        if (plain)
+          push_plain(kind, rp);
+        else
+          push_gemm(kind, rp);
+        Launch m;
+        m.kind = Launch::MODE;
+        m.n = (int)mj.size();
+        m.count = mblocks;
+        m.lds = mlds;
+        push(m, hd.add(mj));
+      }
+      {
+        if (plain)
+          push_plain(kind, re);
+        else
+          push_gemm(kind, re);
+        // one band-rotation launch per kernel instance (band count rounded up
+        // to a multiple of 4) and LDS size (in 8 KB steps): a launch runs at the
+        // occupancy its largest LDS request allows
+        std::vector<std::pair<int, size_t>> keys;
+        for (size_t i = 0; i < bj.size(); ++i) {
+          const std::pair<int, size_t> key{bj_cls[i], ceil_div((int64_t)bj_lds[i], 8192)};
+          if (std::find(keys.begin(), keys.end(), key) == keys.end()) keys.push_back(key);
+        }
+        std::sort(keys.begin(), keys.end());
+        for (const auto& key : keys) {
+          const int cls = key.first;
+          std::vector<BandRotateJob> part;
+          int64_t blocks = 0;
+          size_t lds = 0;
+          for (size_t i = 0; i < bj.size(); ++i) {
+            if (bj_cls[i] != cls || (size_t)ceil_div((int64_t)bj_lds[i], 8192) != key.second) continue;
+            BandRotateJob jb = bj[i];
+            const int64_t nblk = (int64_t)jb.args.qb * ceil_div(jb.args.nk_tile, (int64_t)jb.P);
+            jb.block_base = blocks;
+            blocks += nblk;
+            lds = std::max(lds, bj_lds[i]);
+            part.push_back(jb);
+          }
+          if (part.empty()) continue;
+          Launch b;
+          b.kind = Launch::BAND;
+          b.cfg = cls;
+          b.n = (int)part.size();
+          b.count = blocks;
+          b.lds = lds;
+          push(b, hd.add(part));
+        }
+      }
+      if (!sj.empty()) {
+        Launch l;
+        l.kind = Launch::SUM;
+        l.n = (int)sj.size();
+        l.count = (int64_t)sj.size();
+        push(l, hd.add(sj));
       }
     }
-    if (!sj.empty()) {
-      Launch l;
-      l.kind = Launch::SUM;
-      l.n = (int)sj.size();
-      l.count = (int64_t)sj.size();
-      push(l, hd.add(sj));
-    }
-  }
+  };
+  std::vector<ItemPlan*> grouped;
+  for (auto& it : bt->items)
+    if (!it.solo) grouped.push_back(&it);
+  emit_rounds(grouped);
+  for (auto& it : bt->items)
+    if (it.solo) emit_rounds({&it});
 }
 
 }  // namespace
@@ -665,8 +720,11 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) == hipSuccess && cus > 0)
     bt->cus = cus;
   // Sweep-buffer cap per item: the given per-item cap, else what the item's
-  // largest unit (128 q, every k) needs, at most 8 GiB; if the items together
-  // want more than half of the free HBM, every cap is scaled down to fit (not
+  // largest unit (128 q, every k) needs, at most 8 GiB.  If the items
+  // together want more than half of the free HBM, the largest items run solo
+  // (their rounds after the grouped ones, one item at a time, in one shared
+  // sweep region) until the rest fit beside that region; only if even the
+  // smallest items do not fit are the grouped items' caps scaled down (not
   // below 1 GiB).
   std::vector<int64_t> caps(bt->items.size(), o.item_workspace_bytes);
   if (o.item_workspace_bytes <= 0) {
@@ -676,17 +734,29 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
       return fail(EPHW_EDEVICE);
     }
     const double gib = (double)(1 << 30);
-    const double budget = 0.5 * (double)fr;
-    double want = 0.0;
+    const double budget = o.workspace_budget_bytes > 0 ? (double)o.workspace_budget_bytes : 0.5 * (double)fr;
     for (size_t i = 0; i < bt->items.size(); ++i) {
       const ItemPlan& it = bt->items[i];
       const double cs = (double)csize(bt->kind), qb = (double)std::min<int64_t>(128, std::max<int64_t>(1, it.nq));
       const double full = 2.0 * qb * it.ne * it.E * cs + (double)it.nk * qb * (it.E * cs + 8.0) + 64.0 * (1 << 20);
       caps[i] = (int64_t)std::max(gib, std::min(8.0 * gib, full));
-      want += (double)caps[i];
     }
-    if (want > budget)
-      for (auto& c : caps) c = (int64_t)std::max(gib, (double)c * budget / want);
+    std::vector<size_t> order(bt->items.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return caps[a] > caps[b]; });
+    double want = 0.0, solo_region = 0.0;
+    for (int64_t c : caps) want += (double)c;
+    for (size_t r = 0; r < order.size() && want + solo_region > budget; ++r) {
+      ItemPlan& it = bt->items[order[r]];
+      if (it.nq == 0) continue;
+      it.solo = true;
+      want -= (double)caps[order[r]];
+      solo_region = std::max(solo_region, (double)caps[order[r]]);
+    }
+    const double room = budget - solo_region;
+    if (want > room)
+      for (size_t i = 0; i < caps.size(); ++i)
+        if (!bt->items[i].solo) caps[i] = (int64_t)std::max(gib, (double)caps[i] * std::max(room, 0.0) / want);
     // never below what one q with a 16-point k tile needs
     for (size_t i = 0; i < bt->items.size(); ++i) {
       const ItemPlan& it = bt->items[i];
@@ -720,17 +790,33 @@ ephw_status ephw_batch_create(ephw_ctx* ctx, const ephw_batch_item* items, int32
       cache[key] = {it.qb, it.kt};
     }
   }
-  // workspace
-  size_t total = 0;
-  for (auto& it : bt->items) total += it.bytes();
-  ephw_status e = dev_alloc(&bt->ws, total, bt->mem.get());
+  // workspace: every item's per-q buffers and the grouped items' sweep
+  // buffers side by side, then one sweep region that the solo items share
+  // (their rounds run one item after another in stream order)
+  size_t total = 0, solo_bytes = 0;
+  for (auto& it : bt->items) {
+    total += it.q_bytes();
+    if (it.solo)
+      solo_bytes = std::max(solo_bytes, it.sweep_bytes());
+    else
+      total += it.sweep_bytes();
+  }
+  ephw_status e = dev_alloc(&bt->ws, total + solo_bytes, bt->mem.get());
   if (e != EPHW_OK) return fail(e);
-  bt->ws_bytes = total;
+  bt->ws_bytes = total + solo_bytes;
   {
+    char* base = static_cast<char*>(bt->ws);
+    char* shared = base + total;
     size_t off = 0;
     for (auto& it : bt->items) {
-      carve(it, static_cast<char*>(bt->ws) + off);
-      off += it.bytes();
+      char* q = base + off;
+      off += it.q_bytes();
+      if (it.solo) {
+        carve(it, q, shared);
+      } else {
+        carve(it, q, base + off);
+        off += it.sweep_bytes();
+      }
     }
   }
   // launch list + descriptors
@@ -809,6 +895,15 @@ ephw_status ephw_batch_shape(const ephw_batch* b, int32_t i, int32_t* q_batch, i
   if (k_tile) *k_tile = it.kt;
   if (cfg_rp) *cfg_rp = it.cfg_rp;
   if (cfg_re) *cfg_re = it.cfg_re;
+  return EPHW_OK;
+}
+
+ephw_status ephw_batch_solo(const ephw_batch* b, int32_t i, int32_t* solo) {
+  if (!b || !solo || i < 0 || i >= (int32_t)b->items.size()) {
+    set_error("ephw_batch_solo: no such item or NULL output");
+    return EPHW_EINVAL;
+  }
+  *solo = b->items[i].solo ? 1 : 0;
   return EPHW_OK;
 }
 

@@ -30,7 +30,7 @@ EXPORTS = [
     "ephw_kset_create", "ephw_kset_free", "ephw_kset_bands", "ephw_interpolate", "ephw_interpolate_noalloc", "ephw_interpolate_linewidth", "ephw_degenerate_sums", "ephw_wannier_transform",
     "ephw_window_screen", "ephw_window_pairs", "ephw_interpolate_pairs", "ephw_linewidth",
     "ephw_loss_backward", "ephw_set_q_batch", "ephw_set_k_tile", "ephw_profile_enable", "ephw_profile_read", "ephw_batch_create",
-    "ephw_batch_run", "ephw_batch_shape", "ephw_batch_stats", "ephw_batch_free", "ephw_status_string",
+    "ephw_batch_run", "ephw_batch_shape", "ephw_batch_stats", "ephw_batch_solo", "ephw_batch_free", "ephw_status_string",
     "ephw_last_error", "ephw_version",
 ]
 
@@ -70,7 +70,7 @@ class BatchItem(ctypes.Structure):
 
 class BatchOptions(ctypes.Structure):
     _fields_ = [("tune", ctypes.c_int32), ("tune_cache", ctypes.c_char_p), ("use_graph", ctypes.c_int32),
-                ("item_workspace_bytes", ctypes.c_int64)]
+                ("item_workspace_bytes", ctypes.c_int64), ("workspace_budget_bytes", ctypes.c_int64)]
 
 
 _lib = None
@@ -127,6 +127,7 @@ def lib() -> ctypes.CDLL:
         "ephw_batch_run": [vp, vp],
         "ephw_batch_shape": [vp, i32, vp, vp, vp, vp],
         "ephw_batch_stats": [vp, vp, vp],
+        "ephw_batch_solo": [vp, i32, vp],
         "ephw_batch_free": [vp],
     }
     for name, args in sig.items():
@@ -500,7 +501,8 @@ class Batch:
     """
 
     def __init__(self, ctx: Context, items, *, tune: bool = False, tune_cache: Optional[str] = None,
-                 use_graph: bool = True, item_workspace_bytes: int = 0, stream=None):
+                 use_graph: bool = True, item_workspace_bytes: int = 0, workspace_budget_bytes: int = 0,
+                 stream=None):
         arr = (BatchItem * len(items))()
         self._keep = []
         for i, it in enumerate(items):
@@ -515,7 +517,7 @@ class Batch:
             arr[i].loss_seed = int(it.get("loss_seed", 0))
             self._keep.append(it)
         opt = BatchOptions(1 if tune else 0, tune_cache.encode() if tune_cache else None, 1 if use_graph else 0,
-                           int(item_workspace_bytes))
+                           int(item_workspace_bytes), int(workspace_budget_bytes))
         h = ctypes.c_void_p()
         _check(lib().ephw_batch_create(ctx.handle, arr, len(items), ctypes.byref(opt), _stream(stream),
                                        ctypes.byref(h)), "ephw_batch_create")
@@ -529,6 +531,11 @@ class Batch:
         v = [ctypes.c_int32() for _ in range(4)]
         _check(lib().ephw_batch_shape(self.handle, i, *[ctypes.byref(x) for x in v]), "ephw_batch_shape")
         return dict(q_batch=v[0].value, k_tile=v[1].value, cfg_rp=v[2].value, cfg_re=v[3].value)
+
+    def solo(self, i: int) -> bool:
+        v = ctypes.c_int32()
+        _check(lib().ephw_batch_solo(self.handle, i, ctypes.byref(v)), "ephw_batch_solo")
+        return bool(v.value)
 
     def stats(self):
         r, l = ctypes.c_int32(), ctypes.c_int32()

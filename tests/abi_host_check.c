@@ -65,6 +65,7 @@ int main(void) {
   expect("batch_run NULL", ephw_batch_run(NULL, NULL), EPHW_EINVAL);
   expect("batch_shape NULL", ephw_batch_shape(NULL, 0, NULL, NULL, NULL, NULL), EPHW_EINVAL);
   expect("batch_stats NULL", ephw_batch_stats(NULL, NULL, NULL), EPHW_EINVAL);
+  expect("batch_solo NULL", ephw_batch_solo(NULL, 0, NULL), EPHW_EINVAL);
 
   /* compute calls with NULL handles or buffers */
   expect("bands NULL", ephw_bands(NULL, NULL, 3, NULL, NULL, NULL), EPHW_EINVAL);

@@ -109,6 +109,40 @@ def test_batch_matches_oracle_and_replays(run, tmp_path, seed, max_grid):
     b.close()
 
 
+def test_batch_solo_items_equal_grouped(run):
+    """A workspace budget below what the items' sweep buffers want sends the
+    largest items to rounds of their own, sharing one sweep region, with their
+    phase sums as plain GEMMs (the tile or streaming kernel of their own
+    shape): with every item solo (a 1-byte budget), with some solo (3 GiB: the
+    1 GiB floor caps of six items leave the last two grouped) and with none,
+    the shapes are the same and the outputs agree to FP32 rounding (the plain
+    and grouped GEMMs tile the same sums differently), the sweep region shared
+    by items run one after another included."""
+    from paper_2603_10295_amd import ephw
+    works = small_batch()
+    flags = ephw.OUT_G | ephw.OUT_BAND_SUM | ephw.OUT_LOSS
+    outs, solos = [], []
+    for budget in (0, 3 << 30, 1):
+        items, keep = make_items(run, works, flags)
+        b = ephw.Batch(run.ctx, items, workspace_budget_bytes=budget)
+        b.run()
+        b.run()
+        run.ctx.check()
+        solos.append([b.solo(i) for i in range(len(items))])
+        shapes = [b.shape(i) for i in range(len(items))]
+        outs.append((shapes, [(it["g_out"].cpu().numpy(), it["band_sum"].cpu().numpy(),
+                               float(it["loss"].cpu()[0])) for it in items]))
+        b.close()
+    print("solo items per budget", solos)
+    assert not any(solos[0]) and all(solos[2]) and 0 < sum(solos[1]) < len(works)
+    for shapes, res in outs[1:]:
+        assert shapes == outs[0][0]
+        for (g, t, l), (g0, t0, l0) in zip(res, outs[0][1]):
+            assert np.abs(g - g0).max() <= FP32_TOL * np.abs(g0).max()
+            assert np.abs(t - t0).max() <= FP32_TOL * np.abs(t0).max()
+            assert abs(l - l0) <= FP32_TOL * abs(l0)
+
+
 def test_batch_without_graph_equals_graph(run):
     from paper_2603_10295_amd import ephw
     works = small_batch(count=4, seed=9)
