@@ -757,7 +757,11 @@ ephw_status interpolate_small(ephw_kset* ks, const double* q, const int32_t* kq_
       h.strideC = nk * nw2;
       EPHW_TRY(cgemm(0, h, st));
       double* ekq = eps_kq ? eps_kq + q0 * nk * nw : w.ekq;
-      EPHW_TRY(jacobi_eigh(w.hkq, (int64_t)nb * nk, nw, ekq, w.vkq64, w.jwork, s->ctx->status, st));
+      // FP32 outputs stop the k+q sweeps at an off-diagonal norm of 1e-10 of the
+      // total (eigenvalues then exact to ~1e-20 relative, eigenvectors to ~1e-10,
+      // far below the complex64 rounding they are cast to); FP64 at 1e-14
+      EPHW_TRY(jacobi_eigh(w.hkq, (int64_t)nb * nk, nw, ekq, w.vkq64, w.jwork, s->ctx->status, st,
+                           kind == 0 ? 1e-28 : 1e-20));
       EPHW_TRY(cast_complex(kind, w.vkq64, w.vkq, (int64_t)nb * nk * nw2, st));
       ekq_b = ekq;
     } else if ((eps_kq || r.lw) && kq_index) {

@@ -13,7 +13,7 @@
 // Small matrices (n <= 32) live in LDS, one 64-lane wavefront per matrix, with
 // the LDS sized to the order (8 KB at n = 11) so that a CU holds as many
 // solves as its registers allow; each lane owns one 2x2 block of the round
-// (below).  Large matrices (n > 32) live in a global workspace, one 256-thread
+// (below).  Large matrices (n > 32) live in a global workspace, one 1024-thread
 // workgroup per matrix (the rotation parameters stay in LDS).
 #include "kernels.h"
 
@@ -318,7 +318,7 @@ __device__ __forceinline__ void st_entry(double2* X, uint32_t d, double2 v) {
 
 template <int NP>
 __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, int n, double* __restrict__ eps,
-                                                  double* __restrict__ Vout, uint32_t* status, int64_t b,
+                                                  double* __restrict__ Vout, uint32_t* status, double tol2, int64_t b,
                                                   double2* slice, int lane, const uint2* ent, const int* pqt) {
   using L = SmallLayout<NP>;
   constexpr int N2 = L::N2;
@@ -358,7 +358,7 @@ __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, 
   off = wave_sum(off);
   tot = wave_sum(tot);
   wave_sync();
-  bool converged = n <= 1 || off <= kOffTol2 * tot;
+  bool converged = n <= 1 || off <= tol2 * tot;
   off = 0.0;
   tot = 0.0;
   const int max_sweeps = sweep_limit(status);
@@ -434,7 +434,7 @@ __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, 
     }
     off = wave_sum(off);
     tot = wave_sum(tot);
-    converged = off <= kOffTol2 * tot;
+    converged = off <= tol2 * tot;
     off = 0.0;
     tot = 0.0;
   }
@@ -480,7 +480,7 @@ __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, 
 template <int NP>
 __global__ void __launch_bounds__(64 * kSmallPerBlock)
     jacobi_small_kernel(const double* __restrict__ H, int64_t batch, int n, double* __restrict__ eps,
-                        double* __restrict__ V, uint32_t* status) {
+                        double* __restrict__ V, uint32_t* status, double tol2) {
   extern __shared__ double2 jlds[];
   using L = SmallLayout<NP>;
   const int wave = threadIdx.x >> 6, per = blockDim.x >> 6;
@@ -492,7 +492,7 @@ __global__ void __launch_bounds__(64 * kSmallPerBlock)
   }
   const int64_t m = (int64_t)blockIdx.x * per + wave;
   if (m >= batch) return;
-  jacobi_small_body<NP>(H, n, eps, V, status, m, jlds + wave * L::slice_elems, threadIdx.x & 63, ent, pqt);
+  jacobi_small_body<NP>(H, n, eps, V, status, tol2, m, jlds + wave * L::slice_elems, threadIdx.x & 63, ent, pqt);
 }
 
 // NP covers the largest order among the jobs; smaller orders run padded
@@ -516,11 +516,11 @@ __global__ void __launch_bounds__(64 * kSmallPerBlock)
     if (jobs[mid].block_base <= m) lo = mid; else hi = mid - 1;
   }
   const EighJob& j = jobs[lo];
-  jacobi_small_body<NP>(j.H, j.n, j.eps, j.V, status, m - j.block_base, jlds + wave * L::slice_elems,
+  jacobi_small_body<NP>(j.H, j.n, j.eps, j.V, status, kOffTol2, m - j.block_base, jlds + wave * L::slice_elems,
                         threadIdx.x & 63, ent, pqt);
 }
 
-using SmallKernel = void (*)(const double*, int64_t, int, double*, double*, uint32_t*);
+using SmallKernel = void (*)(const double*, int64_t, int, double*, double*, uint32_t*, double);
 using GroupedKernel = void (*)(const EighJob*, int, int64_t, uint32_t*);
 
 template <int... NPs>
@@ -550,10 +550,15 @@ struct SmallTable {
 };
 using Small = SmallTable<1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16>;
 
-__global__ void __launch_bounds__(256)
+// one workgroup of 16 waves per large matrix: the rounds stream A and V
+// through the caches (640 KB each at n = 200), so the more loads in flight
+// the better; the rotation parameters stay in LDS
+constexpr int kLargeThreads = 1024;
+
+__global__ void __launch_bounds__(kLargeThreads)
     jacobi_large_kernel(const double* __restrict__ H, int n, double* __restrict__ eps,
                         double* __restrict__ V, double* __restrict__ work, uint32_t* status) {
-  __shared__ double rc[128], rs[128], rer[128], rei[128], phr[256], phi[256], red[4];
+  __shared__ double rc[128], rs[128], rer[128], rei[128], phr[256], phi[256], red[kLargeThreads / 64];
   __shared__ int rp[128], rq[128], perm[256];
   const int64_t b = blockIdx.x;
   const int64_t nn = (int64_t)n * n;
@@ -562,14 +567,14 @@ __global__ void __launch_bounds__(256)
   double* Vr = Ai + nn;
   double* Vi = Vr + nn;
   const double* h = H + 2 * b * nn;
-  for (int64_t e = threadIdx.x; e < nn; e += 256) {
+  for (int64_t e = threadIdx.x; e < nn; e += kLargeThreads) {
     Ar[e] = h[2 * e];
     Ai[e] = h[2 * e + 1];
   }
   __syncthreads();
-  const bool ok = jacobi_core<256>(Ar, Ai, Vr, Vi, n, rc, rs, rer, rei, rp, rq, red, sweep_limit(status));
+  const bool ok = jacobi_core<kLargeThreads>(Ar, Ai, Vr, Vi, n, rc, rs, rer, rei, rp, rq, red, sweep_limit(status));
   if (!ok && threadIdx.x == 0) atomicOr(status, kStatusNoConv);
-  jacobi_finish<256>(Ar, Vr, Vi, n, perm, phr, phi, eps + b * n, V + 2 * b * nn);
+  jacobi_finish<kLargeThreads>(Ar, Vr, Vi, n, perm, phr, phi, eps + b * n, V + 2 * b * nn);
 }
 
 constexpr int64_t kLargeChunk = 1024;  // matrices per large-n launch (bounds the workspace)
@@ -602,8 +607,9 @@ ephw_status jacobi_eigh_grouped(const EighJob* d_jobs, int njobs, int64_t total,
 }
 
 ephw_status jacobi_eigh(const double* H, int64_t batch, int n, double* eps, double* V, double* work,
-                        uint32_t* status, hipStream_t s) {
+                        uint32_t* status, hipStream_t s, double off_tol2) {
   if (batch <= 0) return EPHW_OK;
+  if (!(off_tol2 > 0.0) || off_tol2 < kOffTol2) off_tol2 = kOffTol2;
   if ((reinterpret_cast<uintptr_t>(H) | reinterpret_cast<uintptr_t>(V)) & 15) {
     set_error("jacobi_eigh: matrices and eigenvectors must be 16-byte aligned complex128 arrays");
     return EPHW_EINVAL;
@@ -619,7 +625,7 @@ ephw_status jacobi_eigh(const double* H, int64_t batch, int n, double* eps, doub
       const int64_t nb = (batch - b0) < max_per_launch ? (batch - b0) : max_per_launch;
       const int64_t grid = (nb + per - 1) / per;
       hipLaunchKernelGGL(Small::small(np), dim3((unsigned)grid), dim3(64 * per), Small::bytes(np), s,
-                         H + 2 * b0 * n * n, nb, n, eps + b0 * n, V + 2 * b0 * n * n, status);
+                         H + 2 * b0 * n * n, nb, n, eps + b0 * n, V + 2 * b0 * n * n, status, off_tol2);
       EPHW_CHECK_LAUNCH();
     }
     return EPHW_OK;
@@ -630,7 +636,7 @@ ephw_status jacobi_eigh(const double* H, int64_t batch, int n, double* eps, doub
   }
   for (int64_t b0 = 0; b0 < batch; b0 += kLargeChunk) {
     const int64_t nb = (batch - b0) < kLargeChunk ? (batch - b0) : kLargeChunk;
-    hipLaunchKernelGGL(jacobi_large_kernel, dim3((unsigned)nb), dim3(256), 0, s,
+    hipLaunchKernelGGL(jacobi_large_kernel, dim3((unsigned)nb), dim3(kLargeThreads), 0, s,
                        H + 2 * b0 * (int64_t)n * n, n, eps + b0 * n, V + 2 * b0 * (int64_t)n * n,
                        work, status);
     EPHW_CHECK_LAUNCH();

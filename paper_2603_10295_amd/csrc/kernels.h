@@ -15,8 +15,10 @@ ephw_status phase_matrix(int prec, const double* pts, int64_t n, const int32_t* 
 // scaled so its largest-magnitude entry is real positive.  `work` must hold
 // jacobi_work_doubles(n, batch) doubles (0 for n <= 32).
 int64_t jacobi_work_doubles(int n, int64_t batch);
+// off_tol2: convergence when (off-diagonal norm / total norm)^2 <= off_tol2
+// (not below 1e-28, the FP64 default; n <= 32 only, larger orders keep 1e-28)
 ephw_status jacobi_eigh(const double* H, int64_t batch, int n, double* eps, double* V, double* work,
-                        uint32_t* status, hipStream_t s);
+                        uint32_t* status, hipStream_t s, double off_tol2 = 1e-28);
 
 // many small (n <= 32) eigensolves of different orders in one launch;
 // matrix m of the launch belongs to the job with the largest block_base <= m
