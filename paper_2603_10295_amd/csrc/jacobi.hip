@@ -219,7 +219,7 @@ struct SmallLayout {
   // per-round task descriptors and plane pairs, shared by the workgroup's
   // solves (which all have this padded order), when they fit
   static constexpr size_t table_bytes = (size_t)(N2 - 1) * NT * 8 + (size_t)(N2 - 1) * NP * 4;
-  static constexpr bool kTable = table_bytes <= 32768;
+  static constexpr bool kTable = TPL > 1 && table_bytes <= 32768;
   static constexpr size_t table_elems = kTable ? (table_bytes + 15) / 16 : 0;
 };
 
@@ -277,6 +277,28 @@ __device__ void build_tables(uint2* ent, int* pq) {
   constexpr int N2 = L::N2;
   for (int e = threadIdx.x; e < (N2 - 1) * L::NT; e += blockDim.x) ent[e] = task_entries<NP>(e % L::NT, e / L::NT);
   for (int e = threadIdx.x; e < (N2 - 1) * NP; e += blockDim.x) pq[e] = pair_pq(e % NP, e / NP, N2);
+}
+
+// Position order.  A and V are held with their rows and columns (V: columns)
+// in tournament-position order: pair k of every round is positions k and
+// N2 - 1 - k, and after each round the indices move to the positions they take
+// in the next one.  The move is the same every round (the index at position 1
+// goes to the last position, those above 1 move down by one, position 0
+// stays), so a lane's block has fixed load addresses and fixed store
+// addresses (the moved positions) in every round; after a whole sweep of
+// N2 - 1 rounds every index is back at its own position.
+__device__ __forceinline__ int next_pos(int pos, int n2) {
+  return pos == 0 ? 0 : (pos == 1 ? n2 - 1 : pos - 1);
+}
+
+// offset of entry (r, c) of A (upper triangle: an entry below the diagonal is
+// the conjugate of its transpose, flagged by bit 15) or of V (after A)
+template <int NP>
+__device__ __forceinline__ uint32_t entry_offset(bool is_v, int r, int c) {
+  using L = SmallLayout<NP>;
+  constexpr int N2 = L::N2;
+  if (is_v) return (uint32_t)(L::a_elems + r * N2 + c);
+  return r <= c ? (uint32_t)(r * N2 + c) : ((uint32_t)(c * N2 + r) | 0x8000u);
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -475,6 +497,190 @@ __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, 
   }
 }
 
+// The solve for orders with one task per lane (n <= 12): A and V in position
+// order, so every round loads and stores at the same per-lane offsets with
+// no per-round descriptors (about a fifth fewer instructions per round).
+// Larger orders keep the per-round descriptor tables: holding all of a
+// lane's tasks in registers across the round would cost their occupancy.
+template <int NP>
+__device__ __forceinline__ void jacobi_small_body_pos(const double* __restrict__ H, int n, double* __restrict__ eps,
+                                                  double* __restrict__ Vout, uint32_t* status, double tol2, int64_t b,
+                                                  double2* slice, int lane) {
+  using L = SmallLayout<NP>;
+  constexpr int N2 = L::N2, TPL = L::TPL;
+  double2* A = slice;
+  double2* V = A + L::a_elems;
+  double2* prm = V + L::a_elems;
+  double2* fix = prm + L::prm_elems;
+  int* perm = reinterpret_cast<int*>(fix + L::fix_elems);
+  const double2* h = reinterpret_cast<const double2*>(H) + b * n * n;
+  const double2 zero = make_double2(0.0, 0.0);
+
+  // this lane's tasks: block (i, j) of A (i <= j) or of V, i.e. rows
+  // {i, N2-1-i} x columns {j, N2-1-j} in position order (V: rows are the
+  // basis, paired the same way), with the four entries' load offsets and the
+  // offsets they are stored to (their positions in the next round)
+  int task[TPL];
+  uint2 ldo[TPL], sto[TPL];
+#pragma unroll
+  for (int k = 0; k < TPL; ++k) {
+    const int t = lane + 64 * k;
+    int code = -1;
+    uint32_t l[4] = {0, 0, 0, 0}, w[4] = {0, 0, 0, 0};
+    if (t < L::NT) {
+      bool is_v;
+      int i, j;
+      decode_task<NP>(t, is_v, i, j);
+      code = (is_v ? 1 << 16 : 0) | (i << 8) | j;
+      const int rr[2] = {i, N2 - 1 - i}, cc[2] = {j, N2 - 1 - j};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = rr[e >> 1], c = cc[e & 1];
+        l[e] = entry_offset<NP>(is_v, r, c);
+        w[e] = entry_offset<NP>(is_v, is_v ? r : next_pos(r, N2), next_pos(c, N2));
+      }
+    }
+    task[k] = code;
+    ldo[k] = make_uint2(l[0] | l[1] << 16, l[2] | l[3] << 16);
+    sto[k] = make_uint2(w[0] | w[1] << 16, w[2] | w[3] << 16);
+  }
+
+  double off = 0.0, tot = 0.0;
+  for (int e = lane; e < N2 * N2; e += 64) {
+    const int r = e / N2, c = e % N2;
+    const double2 v = (r < n && c < n) ? h[r * n + c] : zero;
+    A[e] = v;
+    V[e] = (r == c && r < n) ? make_double2(1.0, 0.0) : zero;
+    const double m = norm2(v);
+    tot += m;
+    off += r != c ? m : 0.0;
+  }
+  off = wave_sum(off);
+  tot = wave_sum(tot);
+  wave_sync();
+  bool converged = n <= 1 || off <= tol2 * tot;
+  off = 0.0;
+  tot = 0.0;
+  const int max_sweeps = sweep_limit(status);
+  for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+#pragma unroll 1
+    for (int round = 0; round < N2 - 1; ++round) {
+      if (lane < NP) {
+        // pair `lane`: positions p = lane, q = N2-1-lane (a zero padding
+        // row and column give b = 0, the identity)
+        const int p = lane, q = N2 - 1 - lane;
+        double c = 1.0;
+        double2 sg = zero;
+        const double2 bpq = A[p * N2 + q];
+        const double bm2 = norm2(bpq);
+        if (bm2 > 0.0) {
+          const double x = A[q * N2 + q].x - A[p * N2 + p].x;
+          const double ib = rsqrt(bm2);
+          const double y2 = 4.0 * bm2;
+          const double w = fabs(x) + sqrt(fma(x, x, y2));
+          const double z = rsqrt(fma(w, w, y2));
+          c = w * z;
+          const double s = (x >= 0.0 ? 2.0 : -2.0) * (bm2 * ib) * z;  // sign(x) y z
+          sg = make_double2(s * (bpq.x * ib), s * (bpq.y * ib));
+        }
+        prm[2 * lane] = make_double2(c, 0.0);
+        prm[2 * lane + 1] = sg;
+      }
+      wave_sync();
+      const bool last = round == N2 - 2;
+      // every entry is read before any is written (the stores go to the
+      // moved positions, which other tasks read in this round)
+      double2 x[TPL][4];
+#pragma unroll
+      for (int k = 0; k < TPL; ++k) {
+        if (task[k] < 0) continue;
+        x[k][0] = ld_entry(slice, ldo[k].x & 0xffff);
+        x[k][1] = ld_entry(slice, ldo[k].x >> 16);
+        x[k][2] = ld_entry(slice, ldo[k].y & 0xffff);
+        x[k][3] = ld_entry(slice, ldo[k].y >> 16);
+      }
+#pragma unroll
+      for (int k = 0; k < TPL; ++k) {
+        const int code = task[k];
+        if (code < 0) continue;
+        const bool is_v = code >= (1 << 16);
+        const int i = (code >> 8) & 0xff, j = code & 0xff;
+        const double cj = prm[2 * j].x;
+        const double2 sj = prm[2 * j + 1];
+        const double ci = is_v ? 1.0 : prm[2 * i].x;
+        const double2 si = is_v ? zero : prm[2 * i + 1];
+        double2 x00 = x[k][0], x01 = x[k][1], x10 = x[k][2], x11 = x[k][3];
+        rot_right(x00, x01, cj, sj);
+        rot_right(x10, x11, cj, sj);
+        rot_left(x00, x10, ci, si);
+        rot_left(x01, x11, ci, si);
+        const bool diag = !is_v && i == j;
+        if (diag) {
+          // a Hermitian 2x2 block: real diagonal; the plane's pair is annihilated exactly
+          x00.y = 0.0;
+          x11.y = 0.0;
+          if (norm2(si) > 0.0) {
+            x01 = zero;
+            x10 = zero;
+          } else {
+            x10 = make_double2(x01.x, -x01.y);
+          }
+        }
+        st_entry(slice, sto[k].x & 0xffff, x00);
+        st_entry(slice, sto[k].x >> 16, x01);
+        st_entry(slice, sto[k].y & 0xffff, x10);
+        st_entry(slice, sto[k].y >> 16, x11);
+        if (last && !is_v) {
+          const double d = norm2(x00) + norm2(x11), o = norm2(x01) + norm2(x10);
+          tot += diag ? d + o : 2.0 * (d + o);
+          off += diag ? o : 2.0 * (d + o);
+        }
+      }
+      wave_sync();
+    }
+    off = wave_sum(off);
+    tot = wave_sum(tot);
+    converged = off <= tol2 * tot;
+    off = 0.0;
+    tot = 0.0;
+  }
+  if (!converged && lane == 0) atomicOr(status, kStatusNoConv);
+  // ascending order (ties by index), then each column's largest entry made real positive
+  if (lane < n) {
+    const double li = A[lane * N2 + lane].x;
+    int rank = 0;
+    for (int j = 0; j < n; ++j) {
+      const double lj = A[j * N2 + j].x;
+      rank += (lj < li) || (lj == li && j < lane);
+    }
+    perm[rank] = lane;
+  }
+  wave_sync();
+  if (lane < n) {
+    const int src = perm[lane];
+    eps[b * n + lane] = A[src * N2 + src].x;
+    double best = -1.0;
+    double2 bv = make_double2(1.0, 0.0);
+    for (int r = 0; r < n; ++r) {
+      const double2 v = V[r * N2 + src];
+      const double m = norm2(v);
+      if (m > best) {
+        best = m;
+        bv = v;
+      }
+    }
+    const double mag = sqrt(best);
+    fix[lane] = mag > 0.0 ? make_double2(bv.x / mag, -bv.y / mag) : make_double2(1.0, 0.0);
+  }
+  wave_sync();
+  double2* out = reinterpret_cast<double2*>(Vout) + b * n * n;
+  for (int e = lane; e < n * n; e += 64) {
+    const int r = e / n, c = e % n;
+    const double2 v = V[r * N2 + perm[c]], f = fix[c];
+    out[e] = make_double2(v.x * f.x - v.y * f.y, v.x * f.y + v.y * f.x);
+  }
+}
+
 // blockDim.x / 64 matrices per workgroup, one wavefront each: a CU's
 // workgroup slots would otherwise cap it at one single-wave solve per slot
 template <int NP>
@@ -492,7 +698,10 @@ __global__ void __launch_bounds__(64 * kSmallPerBlock)
   }
   const int64_t m = (int64_t)blockIdx.x * per + wave;
   if (m >= batch) return;
-  jacobi_small_body<NP>(H, n, eps, V, status, tol2, m, jlds + wave * L::slice_elems, threadIdx.x & 63, ent, pqt);
+  if constexpr (L::TPL == 1)
+    jacobi_small_body_pos<NP>(H, n, eps, V, status, tol2, m, jlds + wave * L::slice_elems, threadIdx.x & 63);
+  else
+    jacobi_small_body<NP>(H, n, eps, V, status, tol2, m, jlds + wave * L::slice_elems, threadIdx.x & 63, ent, pqt);
 }
 
 // NP covers the largest order among the jobs; smaller orders run padded
@@ -516,8 +725,12 @@ __global__ void __launch_bounds__(64 * kSmallPerBlock)
     if (jobs[mid].block_base <= m) lo = mid; else hi = mid - 1;
   }
   const EighJob& j = jobs[lo];
-  jacobi_small_body<NP>(j.H, j.n, j.eps, j.V, status, kOffTol2, m - j.block_base, jlds + wave * L::slice_elems,
-                        threadIdx.x & 63, ent, pqt);
+  if constexpr (L::TPL == 1)
+    jacobi_small_body_pos<NP>(j.H, j.n, j.eps, j.V, status, kOffTol2, m - j.block_base,
+                              jlds + wave * L::slice_elems, threadIdx.x & 63);
+  else
+    jacobi_small_body<NP>(j.H, j.n, j.eps, j.V, status, kOffTol2, m - j.block_base, jlds + wave * L::slice_elems,
+                          threadIdx.x & 63, ent, pqt);
 }
 
 using SmallKernel = void (*)(const double*, int64_t, int, double*, double*, uint32_t*, double);
