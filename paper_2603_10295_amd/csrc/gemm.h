@@ -119,6 +119,7 @@ struct GroupProblem {
   int64_t ldc = 0;
   int32_t cfg = 0;
   int64_t tiles_m = 0, tiles_n = 0, tile_base = 0;  // set by cgemm_grouped_layout
+  int32_t flat = 0;   // set by cgemm_grouped_layout: both operands' extents fit 32-bit byte offsets
 };
 void cgemm_tile_shape(int prec, int cfg, int* bm, int* bn);
 // workgroups of the grouped kernel one CU holds at once (its persistent grid

@@ -935,6 +935,24 @@ __device__ __forceinline__ void gemm_tile(const TileJob<T>& j, int64_t m0, int64
       kloop(IntC<(SKIP ? FN - 1 : FN)>{});
     else
       kloop(IntC<FN>{});
+  } else if constexpr (sizeof(T) == 4 && KBLK == 0 && BANDNW == 0) {
+    // FP32 without a fused epilogue: the last slab peeled off, so that its K
+    // steps past K are skipped without a test in the main loop (with the
+    // fused band epilogues the peeled copy made the compiler spill more)
+    load(0);
+    stash(smem, 0);
+    __syncthreads();
+    for (int64_t sl = 0; sl + 1 < nslab; ++sl) {
+      load((sl + 1) * BK);
+      compute(smem + (sl & 1) * S::stage_elems, IntC<FN>{}, BK);
+      stash(smem + ((sl + 1) & 1) * S::stage_elems, (sl + 1) * BK);
+      __syncthreads();
+    }
+    if (nslab > 0) {
+      const int64_t sl = nslab - 1;
+      compute(smem + (sl & 1) * S::stage_elems, IntC<FN>{}, (int)(K - sl * BK));
+      __syncthreads();
+    }
   } else {
     load(0);
     stash(smem, 0);
@@ -1301,7 +1319,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
     j.batch = 0;
     j.tile = 0;
     j.ntiles = 1;
-    gemm_tile<T, BM, BN, BK, 2, 2, false, false, 0>(j, tm * BM, tn * BN, smem);
+    // the flat loader where the problem's operand extents allow it (the same
+    // condition as for a plain launch); the per-row-group buffer resources else
+    constexpr int kCpc = Chunk<T>::CPC;
+    constexpr bool kFlatTile = 256 % (BK / kCpc) == 0 && 256 % (BN / kCpc) == 0;
+    if (kFlatTile && P.flat)
+      gemm_tile<T, BM, BN, BK, 2, 2, false, false, 0, 0, kFlatTile>(j, tm * BM, tn * BN, smem);
+    else
+      gemm_tile<T, BM, BN, BK, 2, 2, false, false, 0>(j, tm * BM, tn * BN, smem);
     if (threadIdx.x == 0) {
       int64_t nt = -1;
       if (tried < kXcds) {
@@ -1565,6 +1590,10 @@ int64_t cgemm_grouped_layout(int prec, GroupProblem* probs, int n) {
     probs[i].tiles_n = (probs[i].N > 0 && probs[i].K > 0) ? ceil_div(probs[i].N, bn) : 0;
     probs[i].tile_base = base;
     base += probs[i].tiles_m * probs[i].tiles_n;
+    const int64_t cs = prec == 0 ? 16 : 8, lim = ((int64_t)1 << 32) - 4096, bk = 16;
+    const int64_t a_ext = (probs[i].M - 1) * probs[i].lda + probs[i].K;
+    const int64_t b_ext = (probs[i].K - 1) * probs[i].ldb + probs[i].N;
+    probs[i].flat = (a_ext + bm + bk) * cs < lim && (b_ext + bn + bk) * cs < lim;
   }
   return base;
 }
