@@ -23,9 +23,9 @@ def run():
     return Runner()
 
 
-def small_batch(count=6, seed=3, max_grid=5):
+def small_batch(count=6, seed=3, max_grid=5, cap_mib=24):
     # heterogeneous shapes from the batch generator, capped small for the oracle
-    return synth.batch_systems(seed=seed, count=count, max_grid=max_grid, g_cap_bytes=24 * 2 ** 20)
+    return synth.batch_systems(seed=seed, count=count, max_grid=max_grid, g_cap_bytes=cap_mib * 2 ** 20)
 
 
 def make_items(run, works, flags):
@@ -49,8 +49,8 @@ def make_items(run, works, flags):
     return items, keep
 
 
-@pytest.mark.parametrize("seed,max_grid", [(3, 5), (25, 4)])
-def test_batch_matches_oracle_and_replays(run, tmp_path, seed, max_grid):
+@pytest.mark.parametrize("seed,max_grid,count,cap_mib", [(3, 5, 6, 24), (25, 4, 6, 24), (50, 4, 4, 96)])
+def test_batch_matches_oracle_and_replays(run, tmp_path, seed, max_grid, count, cap_mib):
     """Every item of a heterogeneous batch against the oracle on ALL of its
     pairs, through quantities that depend on the eigenvectors V(k), V(k+q):
     the gauge-invariant block sums of the batch's own stored g (a wrong V,
@@ -58,12 +58,15 @@ def test_batch_matches_oracle_and_replays(run, tmp_path, seed, max_grid):
     weighted loss (the weights differ per (nu, m, n) element).  The band sums
     T_nu, which any unitary V leaves unchanged, are checked beside them.
     Seed 3 draws band counts 4..7 (row kernel), seed 25 also Nw = 9 and 13
-    (the matrix-core rotations, one grouped launch for both)."""
+    (the one-wave matrix-core rotations, one grouped launch for both), seed 50
+    Nw = 22 (the rotations split over a workgroup's four waves) beside Nw = 9."""
     import torch
     from paper_2603_10295_amd import ephw
-    works = small_batch(seed=seed, max_grid=max_grid)
+    works = small_batch(seed=seed, max_grid=max_grid, count=count, cap_mib=cap_mib)
     if seed == 25:
         assert sorted(w.system.nw for w in works if w.system.nw > 8) == [9, 13]
+    if seed == 50:
+        assert sorted(w.system.nw for w in works if w.system.nw > 8) == [9, 22]
     assert len({(w.system.nw, w.system.nm, w.system.ne) for w in works}) > 3   # heterogeneous
     items, keep = make_items(run, works, ephw.OUT_G | ephw.OUT_BAND_SUM | ephw.OUT_LOSS)
     cache = str(tmp_path / "tune.jsonl")
