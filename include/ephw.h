@@ -496,8 +496,10 @@ typedef struct ephw_batch_options {
                                    grouped ones, one item at a time, sharing one sweep
                                    region) until the rest fit beside that region; the
                                    remaining caps are scaled down only if even that
-                                   does not fit.  Results do not depend on which items
-                                   run solo. */
+                                   does not fit.  A solo item's phase sums run as plain
+                                   GEMMs of its own shape, so its results can differ from
+                                   the grouped form's by rounding only.  (Field added in
+                                   version 0.2.0.) */
 } ephw_batch_options;
 /* Plan a batch: validates items, tunes shapes, allocates the workspace.
    All items must share one precision; nw <= 32 and nm <= 24 per system. */
@@ -511,7 +513,7 @@ ephw_status ephw_batch_shape(const ephw_batch* b, int32_t i, int32_t* q_batch, i
 /* number of rounds and of kernel launches in one pass */
 ephw_status ephw_batch_stats(const ephw_batch* b, int32_t* rounds, int32_t* launches);
 /* *solo = 1 if item i runs its rounds on its own (see workspace_budget_bytes), else 0;
-   EPHW_EINVAL for a NULL batch or output, or no such item */
+   EPHW_EINVAL for a NULL batch or output, or no such item.  (Since version 0.2.0.) */
 ephw_status ephw_batch_solo(const ephw_batch* b, int32_t i, int32_t* solo);
 ephw_status ephw_batch_free(ephw_batch* b);
 

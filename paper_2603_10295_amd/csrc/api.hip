@@ -83,7 +83,7 @@ const char* ephw_status_string(ephw_status s) {
 
 const char* ephw_last_error(void) { return g_last_error.c_str(); }
 
-int32_t ephw_version(void) { return 100; }
+int32_t ephw_version(void) { return 200; }
 
 ephw_status ephw_ctx_create(int device, ephw_ctx** out) {
   if (!out) {

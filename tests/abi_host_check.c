@@ -34,7 +34,7 @@ int main(void) {
       ++failures;
     }
   }
-  if (ephw_version() != 100) {
+  if (ephw_version() != 200) {
     fprintf(stderr, "FAIL version %d\n", (int)ephw_version());
     ++failures;
   }

@@ -31,7 +31,7 @@ def test_status_strings_and_version():
     for s in range(7):
         assert L.ephw_status_string(s)
     assert L.ephw_status_string(99) == b"unknown status"
-    assert ephw.version() == 100
+    assert ephw.version() == 200
 
 
 def test_null_arguments_rejected_before_any_device_call():
