@@ -10,11 +10,11 @@
 // plane once; sweeps repeat until the off-diagonal Frobenius norm is below
 // 1e-14 of the total norm.
 //
-// Small matrices (n <= 32) live in LDS, one 64-lane wavefront per matrix, with
-// the LDS sized to the order (8 KB at n = 11) so that a CU holds as many
-// solves as its registers allow; each lane owns one 2x2 block of the round
-// (below).  Large matrices (n > 32) live in a global workspace, one 1024-thread
-// workgroup per matrix (the rotation parameters stay in LDS).
+// Small matrices (n <= 32) live in LDS sized to the order (4 KB per solve at
+// n = 11) so that a CU holds as many solves as its registers allow; each lane
+// owns one 2x2 block of the round (below), a wavefront runs one solve, or
+// several up to n = 12.  Large matrices (n > 32) live in a global workspace,
+// one 1024-thread workgroup per matrix (the rotation parameters stay in LDS).
 #include "kernels.h"
 
 namespace ephw {
@@ -184,7 +184,8 @@ constexpr int kSmallN = 32;
 constexpr int kSmallPerBlock = 4;  // small solves (wavefronts) per workgroup
 
 // ---------------------------------------------------------------------------
-// Small solves (n <= 32): one 64-lane wavefront per matrix, A and V in LDS as
+// Small solves (n <= 32): a 64-lane wavefront per matrix (several matrices
+// up to n = 12, below), A and V in LDS as
 // interleaved complex with the order padded to N2 = 2 NP (a zero row and
 // column for odd n, whose pair is then the identity).  In each round of the
 // tournament the NP disjoint planes cut A and V into NP^2 2x2 blocks, rows
@@ -201,7 +202,7 @@ constexpr int kSmallPerBlock = 4;  // small solves (wavefronts) per workgroup
 //
 // Rotation parameters without divisions, for x = d - a, y = 2|b|:
 //   r = sqrt(x^2 + y^2), w = |x| + r, z = 1/sqrt(w^2 + y^2),
-//   c = w z, s = sign(x) y z, sigma = s b/|b|,
+//   c = w z, s = sign(x) y z, sigma = s b/|b| = sign(x) 2 z b,
 // which are the t = sign(tau)/(|tau| + sqrt(1 + tau^2)) formulas above with
 // the common factors cleared; J = [[c, sigma], [-conj(sigma), c]].
 // ---------------------------------------------------------------------------
@@ -212,9 +213,13 @@ struct SmallLayout {
   static constexpr int NT = NA + NP * NP;                         // tasks: A blocks, then V blocks
   static constexpr int TPL = (NT + 63) / 64;                      // tasks per lane
   static constexpr size_t a_elems = (size_t)N2 * N2;            // complex
+  // A and V: the full squares, or, where the solve keeps per-lane offsets
+  // (one task per lane), task-major: entry e of task t's block at e NT + t
+  static constexpr bool kTaskMajor = TPL == 1;
+  static constexpr size_t data_elems = kTaskMajor ? 4 * (size_t)NT : 2 * a_elems;
   static constexpr size_t prm_elems = 2 * (size_t)NP;            // (c, 0), sigma per pair
   static constexpr size_t fix_elems = (size_t)N2;                // phase fix per column
-  static constexpr size_t bytes = (2 * a_elems + prm_elems + fix_elems) * 16 + (size_t)N2 * 4;
+  static constexpr size_t bytes = (data_elems + prm_elems + fix_elems) * 16 + (size_t)N2 * 4;
   static constexpr size_t slice_elems = (bytes + 15) / 16;       // one wavefront's share, 16-byte units
   // per-round task descriptors and plane pairs, shared by the workgroup's
   // solves (which all have this padded order), when they fit
@@ -224,7 +229,7 @@ struct SmallLayout {
 };
 
 template <int NP>
-__device__ __forceinline__ void decode_task(int t, bool& is_v, int& i, int& j) {
+__host__ __device__ __forceinline__ void decode_task(int t, bool& is_v, int& i, int& j) {
   constexpr int NA = SmallLayout<NP>::NA;
   if (t < NA) {
     int r = 0, rest = t;
@@ -287,18 +292,51 @@ __device__ void build_tables(uint2* ent, int* pq) {
 // stays), so a lane's block has fixed load addresses and fixed store
 // addresses (the moved positions) in every round; after a whole sweep of
 // N2 - 1 rounds every index is back at its own position.
-__device__ __forceinline__ int next_pos(int pos, int n2) {
+__host__ __device__ __forceinline__ int next_pos(int pos, int n2) {
   return pos == 0 ? 0 : (pos == 1 ? n2 - 1 : pos - 1);
 }
 
-// offset of entry (r, c) of A (upper triangle: an entry below the diagonal is
-// the conjugate of its transpose, flagged by bit 15) or of V (after A)
+// Where entries live in the one-task-per-lane solves: entry e (0..3, row
+// bit then column bit) of task t's block at e NT + t, so that each of a
+// round's four loads reads consecutive lanes' entries from consecutive
+// addresses (no LDS bank conflicts).  In position order the entry (r, c)
+// belongs to the planes pr(r), pr(c) of its row and column (pr(x) = x below
+// NP, else N2 - 1 - x), at row bit r >= NP and column bit c >= NP.  A keeps
+// one slot per entry of its upper triangle: an entry below the diagonal is
+// read and written as the conjugate of its transpose (bit 15 of the offset).
+// V: task NA + pr(r) NP + pr(c).  A, (r, c) with r <= c, a = pr(r), b = pr(c):
+// a < b: block (a, b); a > b: block (b, a), whose entry (c, r) lies below
+// the diagonal and so holds this one; a = b: the diagonal block (a, a), whose
+// entries (a, N2-1-a) and (N2-1-a, a) share slot 1.
 template <int NP>
-__device__ __forceinline__ uint32_t entry_offset(bool is_v, int r, int c) {
+__host__ __device__ __forceinline__ uint32_t entry_offset(bool is_v, int r, int c) {
   using L = SmallLayout<NP>;
-  constexpr int N2 = L::N2;
-  if (is_v) return (uint32_t)(L::a_elems + r * N2 + c);
-  return r <= c ? (uint32_t)(r * N2 + c) : ((uint32_t)(c * N2 + r) | 0x8000u);
+  constexpr int N2 = L::N2, NT = L::NT, NA = L::NA;
+  const auto pr = [](int x) { return x < NP ? x : N2 - 1 - x; };
+  const auto hi = [](int x) { return x >= NP ? 1 : 0; };
+  // task of A block (a, b), a <= b: the blocks are numbered row by row
+  const auto task_a = [](int a, int b) { return a * NP - a * (a - 1) / 2 + (b - a); };
+  if (is_v) return (uint32_t)((2 * hi(r) + hi(c)) * NT + NA + pr(r) * NP + pr(c));
+  uint32_t flag = 0;
+  if (r > c) {
+    const int t = r;
+    r = c;
+    c = t;
+    flag = 0x8000u;
+  }
+  const int a = pr(r), b = pr(c);
+  int e, t;
+  if (a < b) {
+    e = 2 * hi(r) + hi(c);
+    t = task_a(a, b);
+  } else if (a > b) {
+    e = 2 * hi(c) + hi(r);
+    t = task_a(b, a);
+  } else {
+    e = r == c ? 3 * hi(r) : 1;
+    t = task_a(a, a);
+  }
+  return (uint32_t)(e * NT + t) | flag;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -397,13 +435,12 @@ __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, 
           const double bm2 = norm2(bpq);
           if (bm2 > 0.0) {
             const double x = A[q * N2 + q].x - A[p * N2 + p].x;
-            const double ib = rsqrt(bm2);
             const double y2 = 4.0 * bm2;
             const double w = fabs(x) + sqrt(fma(x, x, y2));
             const double z = rsqrt(fma(w, w, y2));
             c = w * z;
-            const double s = (x >= 0.0 ? 2.0 : -2.0) * (bm2 * ib) * z;  // sign(x) y z
-            sg = make_double2(s * (bpq.x * ib), s * (bpq.y * ib));
+            const double f = (x >= 0.0 ? 2.0 : -2.0) * z;  // sigma = sign(x) y z b/|b| = sign(x) 2 z b
+            sg = make_double2(f * bpq.x, f * bpq.y);
           }
         }
         prm[2 * lane] = make_double2(c, 0.0);
@@ -502,206 +539,310 @@ __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, 
 // no per-round descriptors (about a fifth fewer instructions per round).
 // Larger orders keep the per-round descriptor tables: holding all of a
 // lane's tasks in registers across the round would cost their occupancy.
+//
+// A wavefront runs several such solves: G lane groups of LPM lanes (the
+// tasks of one solve, rounded up to a power of two) and S solves per group,
+// whose blocks a lane updates one after the other with the same offsets.
+// The plane parameters of the group's S solves come from S NP lanes at once,
+// so the rotation parameters (about a third of a round's instructions at one
+// solve per lane) are shared.  The wavefront sweeps until all its solves have
+// converged; a converged solve takes identity rotations (c = 1, sigma = 0,
+// which leave every entry unchanged) and only moves its entries through the
+// positions, so its results do not depend on the solves beside it.
 template <int NP>
-__device__ __forceinline__ void jacobi_small_body_pos(const double* __restrict__ H, int n, double* __restrict__ eps,
-                                                  double* __restrict__ Vout, uint32_t* status, double tol2, int64_t b,
-                                                  double2* slice, int lane) {
+struct PosShape {
+  static constexpr int NT = SmallLayout<NP>::NT;
+  static constexpr int LPM = NT <= 2 ? 2 : NT <= 4 ? 4 : NT <= 8 ? 8 : NT <= 16 ? 16 : NT <= 32 ? 32 : 64;
+  static constexpr int G = 64 / LPM;
+  static constexpr int S = 2;
+  static constexpr int M = G * S;  // solves per wavefront
+  static_assert(S * NP <= LPM && 2 * NP <= LPM, "a group's lanes must cover its plane parameters and its order");
+};
+
+template <int NP>
+constexpr int solves_per_wave() {
+  if constexpr (SmallLayout<NP>::TPL == 1) return PosShape<NP>::M;
+  else return 1;
+}
+
+// one solve of a wavefront: matrix b of H (n x n), its outputs; n = 0: none
+struct PosJob {
+  const double* H;
+  double* eps;
+  double* V;
+  int64_t b;
+  int n;
+};
+
+template <int LPM>
+__device__ __forceinline__ double group_sum(double v) {
+  for (int m = LPM / 2; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
+// job_at(s): the group's solve s (called before the sweeps and again for the
+// outputs, so that no job is held in registers across them); slices: the
+// group's S solve slices, one after the other; lg: lane in group
+template <int NP, class JobAt>
+__device__ __forceinline__ void jacobi_small_body_pos(JobAt job_at, uint32_t* status, double tol2, double2* slices,
+                                                      int lg) {
   using L = SmallLayout<NP>;
-  constexpr int N2 = L::N2, TPL = L::TPL;
-  double2* A = slice;
-  double2* V = A + L::a_elems;
-  double2* prm = V + L::a_elems;
-  double2* fix = prm + L::prm_elems;
-  int* perm = reinterpret_cast<int*>(fix + L::fix_elems);
-  const double2* h = reinterpret_cast<const double2*>(H) + b * n * n;
+  using P = PosShape<NP>;
+  constexpr int N2 = L::N2, S = P::S, LPM = P::LPM;
+  constexpr size_t SL = L::slice_elems, PO = L::data_elems;
+  static_assert(L::kTaskMajor, "the one-task-per-lane solve keeps A and V task-major");
+  // entry (r, c) of A (r <= c, no conjugate flag) or of V
+  const auto at_a = [](int r, int c) { return entry_offset<NP>(false, r, c); };
+  const auto at_v = [](int r, int c) { return entry_offset<NP>(true, r, c); };
   const double2 zero = make_double2(0.0, 0.0);
 
-  // this lane's tasks: block (i, j) of A (i <= j) or of V, i.e. rows
+  // this lane's task: block (i, j) of A (i <= j) or of V, i.e. rows
   // {i, N2-1-i} x columns {j, N2-1-j} in position order (V: rows are the
   // basis, paired the same way), with the four entries' load offsets and the
-  // offsets they are stored to (their positions in the next round)
-  int task[TPL];
-  uint2 ldo[TPL], sto[TPL];
+  // offsets they are stored to (their positions in the next round); the
+  // same in each of the group's solves
+  int code = -1;
+  uint2 ldo = make_uint2(0, 0), sto = make_uint2(0, 0);
+  if (lg < L::NT) {
+    bool is_v;
+    int i, j;
+    decode_task<NP>(lg, is_v, i, j);
+    code = (is_v ? 1 << 16 : 0) | (i << 8) | j;
+    const int rr[2] = {i, N2 - 1 - i}, cc[2] = {j, N2 - 1 - j};
+    uint32_t l[4], w[4];
 #pragma unroll
-  for (int k = 0; k < TPL; ++k) {
-    const int t = lane + 64 * k;
-    int code = -1;
-    uint32_t l[4] = {0, 0, 0, 0}, w[4] = {0, 0, 0, 0};
-    if (t < L::NT) {
-      bool is_v;
-      int i, j;
-      decode_task<NP>(t, is_v, i, j);
-      code = (is_v ? 1 << 16 : 0) | (i << 8) | j;
-      const int rr[2] = {i, N2 - 1 - i}, cc[2] = {j, N2 - 1 - j};
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = rr[e >> 1], c = cc[e & 1];
-        l[e] = entry_offset<NP>(is_v, r, c);
-        w[e] = entry_offset<NP>(is_v, is_v ? r : next_pos(r, N2), next_pos(c, N2));
-      }
+    for (int e = 0; e < 4; ++e) {
+      const int r = rr[e >> 1], c = cc[e & 1];
+      l[e] = entry_offset<NP>(is_v, r, c);
+      w[e] = entry_offset<NP>(is_v, is_v ? r : next_pos(r, N2), next_pos(c, N2));
     }
-    task[k] = code;
-    ldo[k] = make_uint2(l[0] | l[1] << 16, l[2] | l[3] << 16);
-    sto[k] = make_uint2(w[0] | w[1] << 16, w[2] | w[3] << 16);
+    ldo = make_uint2(l[0] | l[1] << 16, l[2] | l[3] << 16);
+    sto = make_uint2(w[0] | w[1] << 16, w[2] | w[3] << 16);
   }
+  const bool is_v = code >= (1 << 16);
+  const int ti = (code >> 8) & 0xff, tj = code & 0xff;
+  const bool diag = code >= 0 && !is_v && ti == tj;
 
-  double off = 0.0, tot = 0.0;
-  for (int e = lane; e < N2 * N2; e += 64) {
-    const int r = e / N2, c = e % N2;
-    const double2 v = (r < n && c < n) ? h[r * n + c] : zero;
-    A[e] = v;
-    V[e] = (r == c && r < n) ? make_double2(1.0, 0.0) : zero;
-    const double m = norm2(v);
-    tot += m;
-    off += r != c ? m : 0.0;
+  bool conv[S];
+  double off[S], tot[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    double2* X = slices + s * SL;
+    const PosJob job = job_at(s);
+    const int n = job.n;
+    const double2* h = reinterpret_cast<const double2*>(job.H) + job.b * n * n;
+    double o = 0.0, t = 0.0;
+    for (int e = lg; e < N2 * N2; e += LPM) {
+      const int r = e / N2, c = e % N2;
+      const double2 v = (r < n && c < n) ? h[r * n + c] : zero;
+      if (r <= c) X[at_a(r, c)] = v;
+      X[at_v(r, c)] = (r == c && r < n) ? make_double2(1.0, 0.0) : zero;
+      const double m = norm2(v);
+      t += m;
+      o += r != c ? m : 0.0;
+    }
+    o = group_sum<LPM>(o);
+    t = group_sum<LPM>(t);
+    conv[s] = n <= 1 || o <= tol2 * t;
+    off[s] = 0.0;
+    tot[s] = 0.0;
   }
-  off = wave_sum(off);
-  tot = wave_sum(tot);
   wave_sync();
-  bool converged = n <= 1 || off <= tol2 * tot;
-  off = 0.0;
-  tot = 0.0;
   const int max_sweeps = sweep_limit(status);
-  for (int sweep = 0; sweep < max_sweeps && !converged; ++sweep) {
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    bool all = true;
+#pragma unroll
+    for (int s = 0; s < S; ++s) all = all && conv[s];
+    if (__all(all)) break;
 #pragma unroll 1
     for (int round = 0; round < N2 - 1; ++round) {
-      if (lane < NP) {
-        // pair `lane`: positions p = lane, q = N2-1-lane (a zero padding
-        // row and column give b = 0, the identity)
-        const int p = lane, q = N2 - 1 - lane;
+      if (lg < S * NP) {
+        // pair k of solve s: positions p = k, q = N2-1-k (a zero padding row
+        // and column give b = 0, the identity)
+        const int s = lg / NP, k = lg - s * NP;
+        double2* A = slices + s * SL;
+        double2* prm = A + PO;
+        bool done = conv[0];
+#pragma unroll
+        for (int u = 1; u < S; ++u) done = s == u ? conv[u] : done;
+        const int p = k, q = N2 - 1 - k;
         double c = 1.0;
         double2 sg = zero;
-        const double2 bpq = A[p * N2 + q];
+        const double2 bpq = A[at_a(p, q)];
         const double bm2 = norm2(bpq);
-        if (bm2 > 0.0) {
-          const double x = A[q * N2 + q].x - A[p * N2 + p].x;
-          const double ib = rsqrt(bm2);
+        if (!done && bm2 > 0.0) {
+          const double x = A[at_a(q, q)].x - A[at_a(p, p)].x;
           const double y2 = 4.0 * bm2;
           const double w = fabs(x) + sqrt(fma(x, x, y2));
           const double z = rsqrt(fma(w, w, y2));
           c = w * z;
-          const double s = (x >= 0.0 ? 2.0 : -2.0) * (bm2 * ib) * z;  // sign(x) y z
-          sg = make_double2(s * (bpq.x * ib), s * (bpq.y * ib));
+          const double f = (x >= 0.0 ? 2.0 : -2.0) * z;  // sigma = sign(x) y z b/|b| = sign(x) 2 z b
+          sg = make_double2(f * bpq.x, f * bpq.y);
         }
-        prm[2 * lane] = make_double2(c, 0.0);
-        prm[2 * lane + 1] = sg;
+        prm[2 * k] = make_double2(c, 0.0);
+        prm[2 * k + 1] = sg;
       }
       wave_sync();
       const bool last = round == N2 - 2;
       // every entry is read before any is written (the stores go to the
       // moved positions, which other tasks read in this round)
-      double2 x[TPL][4];
+      double2 x[S][4];
+      if (code >= 0) {
 #pragma unroll
-      for (int k = 0; k < TPL; ++k) {
-        if (task[k] < 0) continue;
-        x[k][0] = ld_entry(slice, ldo[k].x & 0xffff);
-        x[k][1] = ld_entry(slice, ldo[k].x >> 16);
-        x[k][2] = ld_entry(slice, ldo[k].y & 0xffff);
-        x[k][3] = ld_entry(slice, ldo[k].y >> 16);
-      }
-#pragma unroll
-      for (int k = 0; k < TPL; ++k) {
-        const int code = task[k];
-        if (code < 0) continue;
-        const bool is_v = code >= (1 << 16);
-        const int i = (code >> 8) & 0xff, j = code & 0xff;
-        const double cj = prm[2 * j].x;
-        const double2 sj = prm[2 * j + 1];
-        const double ci = is_v ? 1.0 : prm[2 * i].x;
-        const double2 si = is_v ? zero : prm[2 * i + 1];
-        double2 x00 = x[k][0], x01 = x[k][1], x10 = x[k][2], x11 = x[k][3];
-        rot_right(x00, x01, cj, sj);
-        rot_right(x10, x11, cj, sj);
-        rot_left(x00, x10, ci, si);
-        rot_left(x01, x11, ci, si);
-        const bool diag = !is_v && i == j;
-        if (diag) {
-          // a Hermitian 2x2 block: real diagonal; the plane's pair is annihilated exactly
-          x00.y = 0.0;
-          x11.y = 0.0;
-          if (norm2(si) > 0.0) {
-            x01 = zero;
-            x10 = zero;
-          } else {
-            x10 = make_double2(x01.x, -x01.y);
-          }
+        for (int s = 0; s < S; ++s) {
+          const double2* X = slices + s * SL;
+          x[s][0] = ld_entry(X, ldo.x & 0xffff);
+          x[s][1] = ld_entry(X, ldo.x >> 16);
+          x[s][2] = ld_entry(X, ldo.y & 0xffff);
+          x[s][3] = ld_entry(X, ldo.y >> 16);
         }
-        st_entry(slice, sto[k].x & 0xffff, x00);
-        st_entry(slice, sto[k].x >> 16, x01);
-        st_entry(slice, sto[k].y & 0xffff, x10);
-        st_entry(slice, sto[k].y >> 16, x11);
-        if (last && !is_v) {
-          const double d = norm2(x00) + norm2(x11), o = norm2(x01) + norm2(x10);
-          tot += diag ? d + o : 2.0 * (d + o);
-          off += diag ? o : 2.0 * (d + o);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+          double2* X = slices + s * SL;
+          const double2* prm = X + PO;
+          const double cj = prm[2 * tj].x;
+          const double2 sj = prm[2 * tj + 1];
+          const double ci = is_v ? 1.0 : prm[2 * ti].x;
+          const double2 si = is_v ? zero : prm[2 * ti + 1];
+          double2 x00 = x[s][0], x01 = x[s][1], x10 = x[s][2], x11 = x[s][3];
+          rot_right(x00, x01, cj, sj);
+          rot_right(x10, x11, cj, sj);
+          rot_left(x00, x10, ci, si);
+          rot_left(x01, x11, ci, si);
+          if (diag) {
+            // a Hermitian 2x2 block: real diagonal; the plane's pair is annihilated exactly
+            x00.y = 0.0;
+            x11.y = 0.0;
+            if (norm2(si) > 0.0) {
+              x01 = zero;
+              x10 = zero;
+            } else {
+              x10 = make_double2(x01.x, -x01.y);
+            }
+          }
+          st_entry(X, sto.x & 0xffff, x00);
+          st_entry(X, sto.x >> 16, x01);
+          st_entry(X, sto.y & 0xffff, x10);
+          st_entry(X, sto.y >> 16, x11);
+          if (last && !is_v) {
+            const double d = norm2(x00) + norm2(x11), o = norm2(x01) + norm2(x10);
+            tot[s] += diag ? d + o : 2.0 * (d + o);
+            off[s] += diag ? o : 2.0 * (d + o);
+          }
         }
       }
       wave_sync();
     }
-    off = wave_sum(off);
-    tot = wave_sum(tot);
-    converged = off <= tol2 * tot;
-    off = 0.0;
-    tot = 0.0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const double o = group_sum<LPM>(off[s]), t = group_sum<LPM>(tot[s]);
+      conv[s] = conv[s] || o <= tol2 * t;
+      off[s] = 0.0;
+      tot[s] = 0.0;
+    }
   }
-  if (!converged && lane == 0) atomicOr(status, kStatusNoConv);
+#pragma unroll
+  for (int s = 0; s < S; ++s)
+    if (!conv[s] && lg == 0) atomicOr(status, kStatusNoConv);
   // ascending order (ties by index), then each column's largest entry made real positive
-  if (lane < n) {
-    const double li = A[lane * N2 + lane].x;
-    int rank = 0;
-    for (int j = 0; j < n; ++j) {
-      const double lj = A[j * N2 + j].x;
-      rank += (lj < li) || (lj == li && j < lane);
-    }
-    perm[rank] = lane;
-  }
-  wave_sync();
-  if (lane < n) {
-    const int src = perm[lane];
-    eps[b * n + lane] = A[src * N2 + src].x;
-    double best = -1.0;
-    double2 bv = make_double2(1.0, 0.0);
-    for (int r = 0; r < n; ++r) {
-      const double2 v = V[r * N2 + src];
-      const double m = norm2(v);
-      if (m > best) {
-        best = m;
-        bv = v;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    double2* A = slices + s * SL;
+    int* perm = reinterpret_cast<int*>(A + PO + L::prm_elems + L::fix_elems);
+    const int n = job_at(s).n;
+    if (lg < n) {
+      const double li = A[at_a(lg, lg)].x;
+      int rank = 0;
+      for (int j = 0; j < n; ++j) {
+        const double lj = A[at_a(j, j)].x;
+        rank += (lj < li) || (lj == li && j < lg);
       }
+      perm[rank] = lg;
     }
-    const double mag = sqrt(best);
-    fix[lane] = mag > 0.0 ? make_double2(bv.x / mag, -bv.y / mag) : make_double2(1.0, 0.0);
   }
   wave_sync();
-  double2* out = reinterpret_cast<double2*>(Vout) + b * n * n;
-  for (int e = lane; e < n * n; e += 64) {
-    const int r = e / n, c = e % n;
-    const double2 v = V[r * N2 + perm[c]], f = fix[c];
-    out[e] = make_double2(v.x * f.x - v.y * f.y, v.x * f.y + v.y * f.x);
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    double2* A = slices + s * SL;
+    double2* fix = A + PO + L::prm_elems;
+    const int* perm = reinterpret_cast<const int*>(fix + L::fix_elems);
+    const PosJob job = job_at(s);
+    const int n = job.n;
+    if (lg < n) {
+      const int src = perm[lg];
+      job.eps[job.b * n + lg] = A[at_a(src, src)].x;
+      double best = -1.0;
+      double2 bv = make_double2(1.0, 0.0);
+      for (int r = 0; r < n; ++r) {
+        const double2 v = A[at_v(r, src)];
+        const double m = norm2(v);
+        if (m > best) {
+          best = m;
+          bv = v;
+        }
+      }
+      const double mag = sqrt(best);
+      fix[lg] = mag > 0.0 ? make_double2(bv.x / mag, -bv.y / mag) : make_double2(1.0, 0.0);
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const double2* A = slices + s * SL;
+    const double2* fix = A + PO + L::prm_elems;
+    const int* perm = reinterpret_cast<const int*>(fix + L::fix_elems);
+    const PosJob job = job_at(s);
+    const int n = job.n;
+    double2* out = reinterpret_cast<double2*>(job.V) + job.b * n * n;
+    for (int e = lg; e < n * n; e += LPM) {
+      const int r = e / n, c = e % n;
+      const double2 v = A[at_v(r, perm[c])], f = fix[c];
+      out[e] = make_double2(v.x * f.x - v.y * f.y, v.x * f.y + v.y * f.x);
+    }
   }
 }
 
-// blockDim.x / 64 matrices per workgroup, one wavefront each: a CU's
-// workgroup slots would otherwise cap it at one single-wave solve per slot
+// blockDim.x / 64 wavefronts per workgroup, each with solves_per_wave<NP>()
+// solves: a CU's workgroup slots would otherwise cap it at one single-wave
+// solve per slot
 template <int NP>
 __global__ void __launch_bounds__(64 * kSmallPerBlock)
     jacobi_small_kernel(const double* __restrict__ H, int64_t batch, int n, double* __restrict__ eps,
                         double* __restrict__ V, uint32_t* status, double tol2) {
   extern __shared__ double2 jlds[];
   using L = SmallLayout<NP>;
+  constexpr int M = solves_per_wave<NP>();
   const int wave = threadIdx.x >> 6, per = blockDim.x >> 6;
-  uint2* ent = reinterpret_cast<uint2*>(jlds + per * L::slice_elems);
+  uint2* ent = reinterpret_cast<uint2*>(jlds + per * M * L::slice_elems);
   int* pqt = reinterpret_cast<int*>(ent + (L::N2 - 1) * L::NT);
   if (L::kTable) {
     build_tables<NP>(ent, pqt);
     __syncthreads();
   }
-  const int64_t m = (int64_t)blockIdx.x * per + wave;
-  if (m >= batch) return;
-  if constexpr (L::TPL == 1)
-    jacobi_small_body_pos<NP>(H, n, eps, V, status, tol2, m, jlds + wave * L::slice_elems, threadIdx.x & 63);
-  else
-    jacobi_small_body<NP>(H, n, eps, V, status, tol2, m, jlds + wave * L::slice_elems, threadIdx.x & 63, ent, pqt);
+  const int64_t m0 = ((int64_t)blockIdx.x * per + wave) * M;
+  if (m0 >= batch) return;
+  const int lane = threadIdx.x & 63;
+  if constexpr (L::TPL == 1) {
+    using P = PosShape<NP>;
+    const int g = lane / P::LPM;
+    const int64_t mg = m0 + g * P::S;
+    auto job_at = [=](int s) {
+      const int64_t m = mg + s;
+      return PosJob{H, eps, V, m < batch ? m : 0, m < batch ? n : 0};
+    };
+    jacobi_small_body_pos<NP>(job_at, status, tol2, jlds + (wave * M + g * P::S) * L::slice_elems, lane % P::LPM);
+  } else {
+    jacobi_small_body<NP>(H, n, eps, V, status, tol2, m0, jlds + wave * L::slice_elems, lane, ent, pqt);
+  }
+}
+
+__device__ __forceinline__ int find_job(const EighJob* __restrict__ jobs, int njobs, int64_t m) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].block_base <= m) lo = mid; else hi = mid - 1;
+  }
+  return lo;
 }
 
 // NP covers the largest order among the jobs; smaller orders run padded
@@ -710,27 +851,34 @@ __global__ void __launch_bounds__(64 * kSmallPerBlock)
     jacobi_grouped_kernel(const EighJob* __restrict__ jobs, int njobs, int64_t total, uint32_t* status) {
   extern __shared__ double2 jlds[];
   using L = SmallLayout<NP>;
+  constexpr int M = solves_per_wave<NP>();
   const int wave = threadIdx.x >> 6, per = blockDim.x >> 6;
-  uint2* ent = reinterpret_cast<uint2*>(jlds + per * L::slice_elems);
+  uint2* ent = reinterpret_cast<uint2*>(jlds + per * M * L::slice_elems);
   int* pqt = reinterpret_cast<int*>(ent + (L::N2 - 1) * L::NT);
   if (L::kTable) {
     build_tables<NP>(ent, pqt);
     __syncthreads();
   }
-  const int64_t m = (int64_t)blockIdx.x * per + wave;
-  if (m >= total) return;
-  int lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].block_base <= m) lo = mid; else hi = mid - 1;
+  const int64_t m0 = ((int64_t)blockIdx.x * per + wave) * M;
+  if (m0 >= total) return;
+  const int lane = threadIdx.x & 63;
+  if constexpr (L::TPL == 1) {
+    using P = PosShape<NP>;
+    const int g = lane / P::LPM;
+    const int64_t mg = m0 + g * P::S;
+    auto job_at = [=](int s) {
+      const int64_t m = mg + s;
+      if (m >= total) return PosJob{nullptr, nullptr, nullptr, 0, 0};
+      const EighJob& j = jobs[find_job(jobs, njobs, m)];
+      return PosJob{j.H, j.eps, j.V, m - j.block_base, j.n};
+    };
+    jacobi_small_body_pos<NP>(job_at, status, kOffTol2, jlds + (wave * M + g * P::S) * L::slice_elems,
+                              lane % P::LPM);
+  } else {
+    const EighJob& j = jobs[find_job(jobs, njobs, m0)];
+    jacobi_small_body<NP>(j.H, j.n, j.eps, j.V, status, kOffTol2, m0 - j.block_base, jlds + wave * L::slice_elems,
+                          lane, ent, pqt);
   }
-  const EighJob& j = jobs[lo];
-  if constexpr (L::TPL == 1)
-    jacobi_small_body_pos<NP>(j.H, j.n, j.eps, j.V, status, kOffTol2, m - j.block_base,
-                              jlds + wave * L::slice_elems, threadIdx.x & 63);
-  else
-    jacobi_small_body<NP>(j.H, j.n, j.eps, j.V, status, kOffTol2, m - j.block_base, jlds + wave * L::slice_elems,
-                          threadIdx.x & 63, ent, pqt);
 }
 
 using SmallKernel = void (*)(const double*, int64_t, int, double*, double*, uint32_t*, double);
@@ -748,16 +896,28 @@ struct SmallTable {
     ((np == NPs ? (k = jacobi_grouped_kernel<NPs>, 0) : 0), ...);
     return k;
   }
-  // solves per workgroup: up to kSmallPerBlock within the 64 KB of dynamic LDS
+  static int per_wave(int np) {
+    int m = 1;
+    ((np == NPs ? (m = solves_per_wave<NPs>(), 0) : 0), ...);
+    return m;
+  }
+  // wavefronts per workgroup: up to kSmallPerBlock, their solves within the
+  // 64 KB of dynamic LDS
   static int per_block(int np) {
     size_t v = 0, t = 0;
-    ((np == NPs ? (v = SmallLayout<NPs>::slice_elems * 16, t = SmallLayout<NPs>::table_elems * 16, 0) : 0), ...);
+    ((np == NPs ? (v = SmallLayout<NPs>::slice_elems * 16 * solves_per_wave<NPs>(),
+                   t = SmallLayout<NPs>::table_elems * 16, 0)
+                : 0),
+     ...);
     const size_t fit = v ? (65536 - t) / v : 1;
     return (int)(fit < (size_t)kSmallPerBlock ? (fit ? fit : 1) : kSmallPerBlock);
   }
   static size_t bytes(int np) {
     size_t v = 0, t = 0;
-    ((np == NPs ? (v = SmallLayout<NPs>::slice_elems * 16, t = SmallLayout<NPs>::table_elems * 16, 0) : 0), ...);
+    ((np == NPs ? (v = SmallLayout<NPs>::slice_elems * 16 * solves_per_wave<NPs>(),
+                   t = SmallLayout<NPs>::table_elems * 16, 0)
+                : 0),
+     ...);
     return v * per_block(np) + t;
   }
 };
@@ -807,13 +967,13 @@ ephw_status jacobi_eigh_grouped(const EighJob* d_jobs, int njobs, int64_t total,
     set_error("jacobi_eigh_grouped: matrix orders must be in [1, 32]");
     return EPHW_EUNSUPPORTED;
   }
-  const int np = (max_n + 1) / 2, per = Small::per_block(np);
+  const int np = (max_n + 1) / 2, waves = Small::per_block(np), per = waves * Small::per_wave(np);
   const int64_t grid = (total + per - 1) / per;
   if (grid > 0x7fffffff) {
     set_error("jacobi_eigh_grouped: too many matrices for one launch");
     return EPHW_EUNSUPPORTED;
   }
-  hipLaunchKernelGGL(Small::grouped(np), dim3((unsigned)grid), dim3(64 * per), Small::bytes(np), s, d_jobs, njobs,
+  hipLaunchKernelGGL(Small::grouped(np), dim3((unsigned)grid), dim3(64 * waves), Small::bytes(np), s, d_jobs, njobs,
                      total, status);
   EPHW_CHECK_LAUNCH();
   return EPHW_OK;
@@ -832,12 +992,12 @@ ephw_status jacobi_eigh(const double* H, int64_t batch, int n, double* eps, doub
     return EPHW_EUNSUPPORTED;
   }
   if (n <= kSmallN) {
-    const int np = (n + 1) / 2, per = Small::per_block(np);
+    const int np = (n + 1) / 2, waves = Small::per_block(np), per = waves * Small::per_wave(np);
     const int64_t max_per_launch = (int64_t)0x7fffffff * per;
     for (int64_t b0 = 0; b0 < batch; b0 += max_per_launch) {
       const int64_t nb = (batch - b0) < max_per_launch ? (batch - b0) : max_per_launch;
       const int64_t grid = (nb + per - 1) / per;
-      hipLaunchKernelGGL(Small::small(np), dim3((unsigned)grid), dim3(64 * per), Small::bytes(np), s,
+      hipLaunchKernelGGL(Small::small(np), dim3((unsigned)grid), dim3(64 * waves), Small::bytes(np), s,
                          H + 2 * b0 * n * n, nb, n, eps + b0 * n, V + 2 * b0 * n * n, status, off_tol2);
       EPHW_CHECK_LAUNCH();
     }

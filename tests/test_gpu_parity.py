@@ -259,17 +259,36 @@ def test_interpolate_fp32_gauge_invariant(run, toy32, toy32_ref, prec):
 
 @pytest.mark.parametrize("nw,na", [(1, 1), (11, 3), (32, 10), (64, 1), (200, 50)])
 def test_jacobi_matches_lapack(run, nw, na):
-    """Eigensolves of both Jacobi forms: LDS-resident, one wavefront each, with
-    the LDS sized to the order (n <= 32: 1, 3, 9, 11, 30, 32), and global-memory
-    (n > 32: 64 and the ribbon's H(k) at 200 and D(q) at 150)."""
+    """Eigensolves of both Jacobi forms: LDS-resident, with the LDS sized to
+    the order (n <= 32: 1, 3, 9, 11, 30, 32), and global-memory (n > 32: 64
+    and the ribbon's H(k) at 200 and D(q) at 150)."""
+    check_jacobi(run, nw, na, np.array([0.0, 0.1, 0.25, 0.5, 0.77]))
+
+
+@pytest.mark.parametrize("nw,na", [(2, 2), (4, 1), (5, 2), (7, 4), (8, 1), (12, 1)])
+def test_jacobi_several_solves_per_wavefront(run, nw, na):
+    """Orders up to 12 run several solves per wavefront: lane groups of 2 to 64
+    lanes, two solves per group.  37 points (and D(q) of orders 3, 6 and 12)
+    leave the last wavefront partly empty.  A solve's results must not depend
+    on the solves beside it (a converged one only takes identity rotations
+    while its neighbours finish): the same points shifted by one give
+    bit-identical eigenpairs."""
+    kx = np.linspace(-0.5, 0.5, 37)
+    sysh, k, eps, vec = check_jacobi(run, nw, na, kx)
+    shift = np.roll(np.arange(len(kx)), 1)
+    eps2, vec2 = run.bands(sysh, k[shift])
+    assert np.array_equal(eps2, eps[shift]) and np.array_equal(vec2, vec[shift])
+
+
+def check_jacobi(run, nw, na, kx):
     r = synth.axis_box(-2, 2, axis=1)
     h_r = synth.hermitian_paired(r, nw, synth.rng([nw, 77], synth.STREAM_H), complex_=True)
     c_r = synth.hermitian_paired(r, 3 * na, synth.rng([nw, 77], synth.STREAM_C), complex_=False)
     # g plays no part in the eigensolves: a minimal one
     s = synth.System(nw=nw, na=na, r_e=r[:1], r_p=r[:1], r_h=r, r_c=r, h_r=h_r, c_r=c_r, mass=np.ones(na),
                      g=np.zeros((1, 1, 3 * na, nw, nw), dtype=np.complex64))
-    k = np.zeros((5, 3))
-    k[:, 1] = np.array([0.0, 0.1, 0.25, 0.5, 0.77])
+    k = np.zeros((len(kx), 3))
+    k[:, 1] = kx
     sysh = run.system(s)
     eps, vec = run.bands(sysh, k)
     ref_eps, _ = oracle.bands(s, k)
@@ -282,6 +301,7 @@ def test_jacobi_matches_lapack(run, nw, na):
     lam, om, ev = run.phonons(sysh, k)
     ref_lam, _, _ = oracle.phonons(s, k)
     assert np.abs(lam - ref_lam).max() <= 1e-11 * np.abs(ref_lam).max()
+    return sysh, k, eps, vec
 
 
 @pytest.mark.parametrize("prec,nw,na", [(0, 4, 1), (0, 5, 2), (1, 9, 3), (0, 16, 4), (1, 17, 5), (0, 20, 6),
