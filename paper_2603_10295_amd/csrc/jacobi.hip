@@ -214,10 +214,13 @@ struct SmallLayout {
   static constexpr int TPL = (NT + 63) / 64;                      // tasks per lane
   static constexpr size_t a_elems = (size_t)N2 * N2;            // complex
   // A and V: the full squares, or, where the solve keeps per-lane offsets
-  // (one task per lane), task-major: entry e of task t's block at e NT + t
+  // (one task per lane), task-major: entry e of task t's block at e RS + t,
+  // the regions RS apart (an odd stride above 32 tasks, which spreads the
+  // scattered stores to the moved positions over more LDS banks)
   static constexpr bool kTaskMajor = TPL == 1;
-  static constexpr size_t data_elems = kTaskMajor ? 4 * (size_t)NT : 2 * a_elems;
-  static constexpr size_t prm_elems = 2 * (size_t)NP;            // (c, 0), sigma per pair
+  static constexpr int RS = NT > 32 ? 63 : NT;
+  static constexpr size_t data_elems = kTaskMajor ? 3 * (size_t)RS + NT : 2 * a_elems;
+  static constexpr size_t prm_elems = 2 * (size_t)NP;            // per pair (c, 0), sigma; task-major: sigma[NP], c[NP]
   static constexpr size_t fix_elems = (size_t)N2;                // phase fix per column
   static constexpr size_t bytes = (data_elems + prm_elems + fix_elems) * 16 + (size_t)N2 * 4;
   static constexpr size_t slice_elems = (bytes + 15) / 16;       // one wavefront's share, 16-byte units
@@ -297,7 +300,7 @@ __host__ __device__ __forceinline__ int next_pos(int pos, int n2) {
 }
 
 // Where entries live in the one-task-per-lane solves: entry e (0..3, row
-// bit then column bit) of task t's block at e NT + t, so that each of a
+// bit then column bit) of task t's block at e RS + t, so that each of a
 // round's four loads reads consecutive lanes' entries from consecutive
 // addresses (no LDS bank conflicts).  In position order the entry (r, c)
 // belongs to the planes pr(r), pr(c) of its row and column (pr(x) = x below
@@ -311,12 +314,12 @@ __host__ __device__ __forceinline__ int next_pos(int pos, int n2) {
 template <int NP>
 __host__ __device__ __forceinline__ uint32_t entry_offset(bool is_v, int r, int c) {
   using L = SmallLayout<NP>;
-  constexpr int N2 = L::N2, NT = L::NT, NA = L::NA;
+  constexpr int N2 = L::N2, RS = L::RS, NA = L::NA;
   const auto pr = [](int x) { return x < NP ? x : N2 - 1 - x; };
   const auto hi = [](int x) { return x >= NP ? 1 : 0; };
   // task of A block (a, b), a <= b: the blocks are numbered row by row
   const auto task_a = [](int a, int b) { return a * NP - a * (a - 1) / 2 + (b - a); };
-  if (is_v) return (uint32_t)((2 * hi(r) + hi(c)) * NT + NA + pr(r) * NP + pr(c));
+  if (is_v) return (uint32_t)((2 * hi(r) + hi(c)) * RS + NA + pr(r) * NP + pr(c));
   uint32_t flag = 0;
   if (r > c) {
     const int t = r;
@@ -336,7 +339,7 @@ __host__ __device__ __forceinline__ uint32_t entry_offset(bool is_v, int r, int 
     e = r == c ? 3 * hi(r) : 1;
     t = task_a(a, a);
   }
-  return (uint32_t)(e * NT + t) | flag;
+  return (uint32_t)(e * RS + t) | flag;
 }
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -679,8 +682,8 @@ __device__ __forceinline__ void jacobi_small_body_pos(JobAt job_at, uint32_t* st
           const double f = (x >= 0.0 ? 2.0 : -2.0) * z;  // sigma = sign(x) y z b/|b| = sign(x) 2 z b
           sg = make_double2(f * bpq.x, f * bpq.y);
         }
-        prm[2 * k] = make_double2(c, 0.0);
-        prm[2 * k + 1] = sg;
+        prm[k] = sg;
+        reinterpret_cast<double*>(prm + NP)[k] = c;
       }
       wave_sync();
       const bool last = round == N2 - 2;
@@ -699,11 +702,14 @@ __device__ __forceinline__ void jacobi_small_body_pos(JobAt job_at, uint32_t* st
 #pragma unroll
         for (int s = 0; s < S; ++s) {
           double2* X = slices + s * SL;
+          // sigma of the NP planes, then their c: consecutive planes' parameters
+          // in consecutive LDS banks
           const double2* prm = X + PO;
-          const double cj = prm[2 * tj].x;
-          const double2 sj = prm[2 * tj + 1];
-          const double ci = is_v ? 1.0 : prm[2 * ti].x;
-          const double2 si = is_v ? zero : prm[2 * ti + 1];
+          const double* pc = reinterpret_cast<const double*>(prm + NP);
+          const double cj = pc[tj];
+          const double2 sj = prm[tj];
+          const double ci = is_v ? 1.0 : pc[ti];
+          const double2 si = is_v ? zero : prm[ti];
           double2 x00 = x[s][0], x01 = x[s][1], x10 = x[s][2], x11 = x[s][3];
           rot_right(x00, x01, cj, sj);
           rot_right(x10, x11, cj, sj);
