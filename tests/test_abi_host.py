@@ -182,3 +182,28 @@ def test_host_validation_under_address_and_ub_sanitizers(tmp_path):
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=120)
     assert r.returncode == 0, (r.returncode, r.stdout[-2000:], r.stderr[-4000:])
     assert "abi_host_check: ok" in r.stdout
+
+
+def test_jacobi_lds_layout(tmp_path):
+    """The LDS map of the one-task-per-lane Jacobi solves (n <= 12), checked on
+    the host from the kernel source (tests/jacobi_layout_check.hip): every
+    entry of A (upper triangle, transposes sharing a slot) and of V in its own
+    slot inside the data region, task t's loads at e RS + t (what keeps a
+    round's loads free of LDS bank conflicts), the stores to the moved
+    positions covering every slot the next round reads, and every position
+    back in place after a sweep."""
+    import subprocess
+    from paper_2603_10295_amd import build as b
+
+    host_only = [b.hipcc(), f"--offload-arch={b.ARCH}", "--offload-host-only", "-fgpu-rdc"]
+    obj, exe = str(tmp_path / "jacobi_layout_check.o"), str(tmp_path / "jacobi_layout_check")
+    r = subprocess.run([*host_only, "-x", "hip", "-std=c++17", "-O1", "-I", os.path.join(ROOT, "include"),
+                        "-I", os.path.join(ROOT, "paper_2603_10295_amd", "csrc"),
+                        os.path.join(ROOT, "tests", "jacobi_layout_check.hip"), "-c", "-o", obj],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    r = subprocess.run([*host_only, obj, "-o", exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr[-3000:]
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0, r.stdout[-3000:]
+    assert "jacobi_layout_check: ok" in r.stdout
