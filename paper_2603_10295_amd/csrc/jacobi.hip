@@ -547,8 +547,8 @@ __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, 
 // tasks of one solve, rounded up to a power of two) and S solves per group,
 // whose blocks a lane updates one after the other with the same offsets.
 // The plane parameters of the group's S solves come from S NP lanes at once,
-// so the rotation parameters (about a third of a round's instructions at one
-// solve per lane) are shared.  The wavefront sweeps until all its solves have
+// so the instructions of that step (about a third of a round's with one solve
+// per wavefront) serve S solves.  The wavefront sweeps until all its solves have
 // converged; a converged solve takes identity rotations (c = 1, sigma = 0,
 // which leave every entry unchanged) and only moves its entries through the
 // positions, so its results do not depend on the solves beside it.
