@@ -4,6 +4,7 @@
     python -m paper_2603_10295_amd.rocprof_summary traffic FETCH.db WRITE.db \
         --copy-bytes BYTES [--command CMD]
     python -m paper_2603_10295_amd.rocprof_summary util COUNTERS.db [--command CMD]
+    python -m paper_2603_10295_amd.rocprof_summary lds COUNTERS.db [--match NAME] [--command CMD]
 
 `stats` groups kernel dispatches by (kernel, grid) - the phase GEMMs of
 Eqs. (9) and (10) share one kernel but differ in grid - and prints calls,
@@ -11,6 +12,12 @@ total/average/min/max duration.  `traffic` reads FETCH_SIZE and WRITE_SIZE
 (KiB per dispatch) from two counter runs, scales each by the factor that
 makes a plain device copy of `--copy-bytes` bytes read and write exactly that
 many bytes, and prints HBM bytes per dispatch per (kernel, grid) group.
+`lds` prints, per (kernel, grid) group, VALU and LDS instructions per
+wavefront (SQ_INSTS_VALU, SQ_INSTS_LDS over SQ_WAVES), the VALU issue time
+they imply (4 cycles per wave64 instruction over the SIMDs) as a share of the
+kernel's cycles, and the LDS-active and bank-conflict cycles
+(SQ_ACTIVE_INST_LDS, SQ_LDS_BANK_CONFLICT) per CU cycle and per LDS-active
+cycle.
 """
 from __future__ import annotations
 
@@ -139,6 +146,44 @@ def utilisation(db: str, simds: int = 1024, xcds: int = 8, command: str = "") ->
     return "\n".join(out) + "\n"
 
 
+def lds(db: str, match: str = "", simds: int = 1024, cus: int = 256, xcds: int = 8, command: str = "") -> str:
+    """VALU and LDS figures per (kernel, grid) group from SQ_WAVES, SQ_INSTS_VALU,
+    SQ_INSTS_LDS, SQ_ACTIVE_INST_LDS, SQ_LDS_BANK_CONFLICT and GRBM_GUI_ACTIVE
+    (each summed over the chip)."""
+    c = sqlite3.connect(db)
+    rows = c.execute("select dispatch_id, kernel_name, grid_size_x, grid_size_y, workgroup_size_x, counter_name, "
+                     "value, start, end from counters_collection").fetchall()
+    per = collections.defaultdict(dict)
+    meta = {}
+    for d, name, gx, gy, wx, cname, val, t0, t1 in rows:
+        if match and match not in name:
+            continue
+        per[d][cname] = per[d].get(cname, 0.0) + val
+        meta[d] = (short_name(name), gx // max(1, wx), gy, (t1 - t0) * 1e-9)
+    groups = collections.defaultdict(list)
+    for d, v in per.items():
+        groups[meta[d][:3]].append((v, meta[d][3]))
+    out = [f"# VALU and LDS counters per dispatch: {os.path.basename(db)}",
+           f"# command: {command}" if command else "# command: (not recorded)",
+           f"# valu_issue = SQ_INSTS_VALU x 4 cycles / {simds} SIMDs / (GRBM_GUI_ACTIVE / {xcds} XCDs); "
+           f"lds_active, conflict = SQ_ACTIVE_INST_LDS, SQ_LDS_BANK_CONFLICT / {cus} CUs / (GRBM_GUI_ACTIVE / {xcds})",
+           f"{'disp':>5} {'avg_ms':>8} {'valu/wave':>10} {'lds/wave':>9} {'valu_issue':>10} {'lds_active':>10} "
+           f"{'conflict':>9} {'conf/lds':>9}  kernel [workgroups x grid_y]"]
+    def avg(xs):
+        return sum(xs) / len(xs) if xs else float("nan")
+    for k in sorted(groups, key=lambda k: -sum(t for _, t in groups[k])):
+        vs = groups[k]
+        def field(n):
+            return avg([v.get(n, float("nan")) for v, _ in vs])
+        waves, gui = field("SQ_WAVES"), field("GRBM_GUI_ACTIVE") / xcds
+        valu, ldsi = field("SQ_INSTS_VALU"), field("SQ_INSTS_LDS")
+        act, conf = field("SQ_ACTIVE_INST_LDS"), field("SQ_LDS_BANK_CONFLICT")
+        out.append(f"{len(vs):5d} {avg([t for _, t in vs]) * 1e3:8.3f} {valu / waves:10.0f} {ldsi / waves:9.0f} "
+                   f"{valu * 4 / simds / gui:10.3f} {act / cus / gui:10.3f} {conf / cus / gui:9.3f} "
+                   f"{conf / act if act else float('nan'):9.3f}  {k[0]} [{k[1]} x {k[2]}]")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -153,11 +198,17 @@ def main(argv=None) -> int:
     u = sub.add_parser("util")
     u.add_argument("db")
     u.add_argument("--command", default="")
+    lp = sub.add_parser("lds")
+    lp.add_argument("db")
+    lp.add_argument("--match", default="")
+    lp.add_argument("--command", default="")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         sys.stdout.write(stats(a.db, a.command))
     elif a.cmd == "util":
         sys.stdout.write(utilisation(a.db, command=a.command))
+    elif a.cmd == "lds":
+        sys.stdout.write(lds(a.db, match=a.match, command=a.command))
     else:
         sys.stdout.write(traffic(a.fetch_db, a.write_db, a.copy_bytes, a.command))
     return 0
