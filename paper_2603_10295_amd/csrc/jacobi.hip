@@ -411,7 +411,8 @@ __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, 
   double off = 0.0, tot = 0.0;
   for (int e = lane; e < N2 * N2; e += 64) {
     const int r = e / N2, c = e % N2;
-    const double2 v = (r < n && c < n) ? h[r * n + c] : zero;
+    double2 v = (r < n && c < n) ? h[r * n + c] : zero;
+    if (r == c) v.y = 0.0;  // Hermitian: a real diagonal
     A[e] = v;
     V[e] = (r == c && r < n) ? make_double2(1.0, 0.0) : zero;
     const double m = norm2(v);
@@ -472,14 +473,13 @@ __device__ __forceinline__ void jacobi_small_body(const double* __restrict__ H, 
         rot_left(x01, x11, ci, si);
         const bool diag = !is_v && i == j;
         if (diag) {
-          // a Hermitian 2x2 block: real diagonal; the plane's pair is annihilated exactly
-          x00.y = 0.0;
-          x11.y = 0.0;
+          // a rotated Hermitian 2x2 block: real diagonal, the plane's pair
+          // annihilated exactly (an unrotated one keeps its entries bit for bit)
           if (norm2(si) > 0.0) {
+            x00.y = 0.0;
+            x11.y = 0.0;
             x01 = zero;
             x10 = zero;
-          } else {
-            x10 = make_double2(x01.x, -x01.y);
           }
         }
         st_entry(slice, d.x & 0xffff, x00);
@@ -637,7 +637,8 @@ __device__ __forceinline__ void jacobi_small_body_pos(JobAt job_at, uint32_t* st
     double o = 0.0, t = 0.0;
     for (int e = lg; e < N2 * N2; e += LPM) {
       const int r = e / N2, c = e % N2;
-      const double2 v = (r < n && c < n) ? h[r * n + c] : zero;
+      double2 v = (r < n && c < n) ? h[r * n + c] : zero;
+      if (r == c) v.y = 0.0;  // Hermitian: a real diagonal
       if (r <= c) X[at_a(r, c)] = v;
       X[at_v(r, c)] = (r == c && r < n) ? make_double2(1.0, 0.0) : zero;
       const double m = norm2(v);
@@ -716,14 +717,13 @@ __device__ __forceinline__ void jacobi_small_body_pos(JobAt job_at, uint32_t* st
           rot_left(x00, x10, ci, si);
           rot_left(x01, x11, ci, si);
           if (diag) {
-            // a Hermitian 2x2 block: real diagonal; the plane's pair is annihilated exactly
-            x00.y = 0.0;
-            x11.y = 0.0;
+            // a rotated Hermitian 2x2 block: real diagonal, the plane's pair
+            // annihilated exactly (an unrotated one keeps its entries bit for bit)
             if (norm2(si) > 0.0) {
+              x00.y = 0.0;
+              x11.y = 0.0;
               x01 = zero;
               x10 = zero;
-            } else {
-              x10 = make_double2(x01.x, -x01.y);
             }
           }
           st_entry(X, sto.x & 0xffff, x00);
